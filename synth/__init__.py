@@ -1,0 +1,21 @@
+"""Seeded synthetic workloads shared by the oracle tests, the GPU tests and the benchmark.
+
+This package only draws random inputs: images, point clouds, neighbour lists
+and initial embeddings.  It contains none of the embedding method's arithmetic
+(no edge weights, degrees, system matrices, solves or orthonormalisation); those
+live separately in ``oracle/`` (CPU, FP64) and in the HIP library.
+
+All generators use ``numpy.random.default_rng(seed)`` (PCG64) and return
+float32 feature arrays, which both sides read as the same exact values.
+"""
+from .voronoi import voronoi_image, image_features, batch_image_shapes
+from .points import gaussian_mixture, knn_edge_list
+from .embed import smooth_y0, gaussian_y0
+from .workloads import (WORKLOADS, Workload, make_workload, grid_workload,
+                        edges_workload)
+
+__all__ = [
+    "voronoi_image", "image_features", "batch_image_shapes",
+    "gaussian_mixture", "knn_edge_list", "smooth_y0", "gaussian_y0",
+    "WORKLOADS", "Workload", "make_workload", "grid_workload", "edges_workload",
+]

@@ -1,0 +1,98 @@
+"""Named synthetic workloads (sizes, value distributions and iteration counts).
+
+Every workload is fully determined by its name and seed.  ``lam``/``r`` set to
+None means the shrink-active choice lambda = r = c, where c is derived from the
+initial embedding by the method itself (1 / 0.99-quantile of |M Y0|).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from .voronoi import voronoi_image, image_features, batch_image_shapes
+from .points import gaussian_mixture, knn_edge_list
+from .embed import smooth_y0, gaussian_y0
+
+
+@dataclass
+class Workload:
+    name: str
+    kind: str                      # "grid" or "edges"
+    n: int
+    d: int
+    sigma: float
+    n_outer: int
+    n_inner: int
+    tol: float
+    lam: Optional[float]
+    r: Optional[float]
+    n_clusters: int
+    y0: np.ndarray                 # float32 n x d, not orthonormalised
+    labels: np.ndarray             # ground-truth cell / component of each vertex
+    H: int = 0
+    W: int = 0
+    stencil: int = 0               # 4, 8, or -R for a Chebyshev window of radius R
+    feat: Optional[np.ndarray] = None   # float32 n x m (grid)
+    src: Optional[np.ndarray] = None    # int32 (edges)
+    dst: Optional[np.ndarray] = None
+    dist2: Optional[np.ndarray] = None  # float64 (edges)
+    fp64: bool = False
+    meta: dict = field(default_factory=dict)
+
+
+def grid_workload(name, H, W, K, noise, seed, *, gradient=0.0, with_xy=False,
+                  stencil=4, sigma=0.1, d=4, lam=None, r=None, n_outer=10,
+                  n_inner=5, tol=1e-6, fp64=False, y0_seed=None):
+    rgb, labels = voronoi_image(H, W, K, noise, seed, gradient=gradient)
+    feat = image_features(rgb, with_xy)
+    y0 = smooth_y0(H, W, d, seed + 7919 if y0_seed is None else y0_seed)
+    return Workload(name=name, kind="grid", n=H * W, d=d, sigma=sigma,
+                    n_outer=n_outer, n_inner=n_inner, tol=tol, lam=lam, r=r,
+                    n_clusters=K, y0=y0, labels=labels.reshape(-1), H=H, W=W,
+                    stencil=stencil, feat=feat, fp64=fp64,
+                    meta=dict(seed=seed, noise=noise, gradient=gradient, K=K))
+
+
+def edges_workload(name, n, m, components, k, seed, *, d=20, n_outer=20,
+                   n_inner=10, tol=1e-6, lam=None, r=None):
+    pts, labels = gaussian_mixture(n, m, components, seed)
+    src, dst, dist2, knn_dist = knn_edge_list(pts, k)
+    sigma = float(np.median(knn_dist))
+    y0 = gaussian_y0(n, d, seed + 7919)
+    return Workload(name=name, kind="edges", n=n, d=d, sigma=sigma,
+                    n_outer=n_outer, n_inner=n_inner, tol=tol, lam=lam, r=r,
+                    n_clusters=components, y0=y0, labels=labels, src=src,
+                    dst=dst, dist2=dist2, meta=dict(seed=seed, k=k, m=m))
+
+
+WORKLOADS = {
+    # 64x64, 5 cells, noise 0.05, RGB, 4-neighbour, sigma 0.1, d=4, lambda=r=1,
+    # 10 outer x 5 inner, solver tolerance 1e-8 in FP64.
+    "voronoi64_4nbr": dict(H=64, W=64, K=5, noise=0.05, stencil=4, d=4,
+                           lam=1.0, r=1.0, n_outer=10, n_inner=5, tol=1e-8,
+                           fp64=True),
+    # 481x321 (BSDS image shape), 40 cells with smooth colour gradients, noise
+    # 0.03, RGB + scaled xy, 8-neighbour, sigma 0.1, d=10, 20 outer x 10 inner,
+    # solver tolerance 1e-6 in FP32.
+    "voronoi481x321_8nbr": dict(H=321, W=481, K=40, noise=0.03, gradient=0.3,
+                                with_xy=True, stencil=8, d=10, n_outer=20,
+                                n_inner=10, tol=1e-6),
+    # 1024x1024, 200 cells, noise 0.05, RGB, 5x5 window (radius 2), d=16.
+    "voronoi1024_r2": dict(H=1024, W=1024, K=200, noise=0.05, stencil=-2, d=16,
+                           n_outer=20, n_inner=10, tol=1e-6),
+    # Small stand-ins with the same structure, sized for tests.
+    "voronoi96x80_8nbr": dict(H=80, W=96, K=8, noise=0.03, gradient=0.3,
+                              with_xy=True, stencil=8, d=10, n_outer=4,
+                              n_inner=4, tol=1e-6),
+    "voronoi48x40_r2": dict(H=40, W=48, K=6, noise=0.05, stencil=-2, d=16,
+                            n_outer=3, n_inner=3, tol=1e-6),
+}
+
+
+def make_workload(name: str, seed: int = 0) -> Workload:
+    if name not in WORKLOADS:
+        raise KeyError(f"unknown workload {name!r}; known: {sorted(WORKLOADS)}")
+    cfg = dict(WORKLOADS[name])
+    return grid_workload(name, seed=seed, **cfg)
