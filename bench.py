@@ -1,0 +1,143 @@
+#!/usr/bin/env python3
+"""Benchmark: PFE outer (SOC) iterations per second on one MI355X.
+
+Workload: 481x321 synthetic Voronoi image (40 cells, smooth colour gradients,
+noise 0.03), RGB + scaled xy features, 8-neighbour heat-kernel graph
+(sigma 0.1), d = 10, 10 Split-Bregman iterations per SOC iteration, Jacobi-PCG
+to relative residual 1e-6, FP32 vectors with FP64 reductions; lambda = r = c
+with the shrink threshold 1/c at the 0.99-quantile of |M Y0|.
+
+One timed step = one SOC iteration (10 inner solves + shrink/Bregman + P/B
+update), launched as one persistent kernel; inputs are resident in HBM.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "voronoi481x321_8nbr"
+PEAK_HBM_GBS = 8000.0
+
+
+def algorithmic_bytes(n, E, d, esz, cg_iters, solves, n_inner, n_outer):
+    """Bytes the method has to move per the model stated in the design doc
+    (FP32 values, int32 indices), summed over n_outer SOC iterations."""
+    rowptr = 4 * (n + 1)
+    csr = 8 * 2 * E + rowptr                  # column index + weight per directed slot
+    nd = n * d * esz
+    cg_iter = csr + 2 * n * esz + 10 * nd       # A: r,p_old -> p_new,q ; B: x,p,q,r -> x,r
+    first_res = csr + 3 * n * esz + 4 * nd      # P, B, x -> r
+    edge_res = csr + 3 * n * esz + 4 * nd + 2 * E * d * esz + 4 * E  # + b read/write per edge
+    ortho = 2 * n * esz + 6 * nd                # Gram (Y, B) + apply (Y, B -> P, B)
+    per_outer_fixed = first_res + (n_inner - 1) * edge_res + ortho
+    return cg_iters * cg_iter + n_outer * per_outer_fixed
+
+
+def cpu_baseline(wl, lam, r, n_steps=2):
+    """The FP64 oracle on the host, on a bounded sample: n_steps SOC iterations
+    of the same workload (sparse LU factorisation reported separately)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+    with threadpool_limits(limits=1):
+        g = O.build_grid_graph(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
+        Y = O.orthonormalize_init(g, wl.y0)
+        t0 = time.perf_counter()
+        solve = O.DirectSolver(O.system_matrix(g, lam, r))
+        t_fact = time.perf_counter() - t0
+        P = np.sqrt(g.D)[:, None] * Y
+        B = np.zeros_like(Y)
+        t0 = time.perf_counter()
+        for _ in range(n_steps):
+            Y, P, B = O.soc_outer_step(g, solve, Y, P, B, lam, r, wl.n_inner)
+        dt = time.perf_counter() - t0
+    return {"value": n_steps / dt, "unit": "outer iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_steps} SOC iterations x {wl.n_inner} inner, sparse LU solves "
+                      f"(factorisation {t_fact:.2f} s once, not in the rate), 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--multi-launch", action="store_true", help="one launch per phase instead of one per SOC iteration")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a "
+              "single MI355X; see DESIGN.md for how the path would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1612_06496_amd import Graph, Solver
+
+    torch.cuda.set_device(0)
+    wl = synth.make_workload(WORKLOAD, 0)
+    G = Graph.grid(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
+    S = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=1000,
+               persistent=not args.multi_launch)
+    # shrink-active penalties: threshold 1/c at the 0.99-quantile of |M Y0|
+    c = 1.0 / S.edge_quantile(0.99)
+    S.set_penalties(c, c)
+
+    S.solve(args.warmup)
+    S.stats(reset=True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    S.solve(args.steps)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop)
+    info = S.stats(reset=True)          # CG iterations of the timed steps
+    mon = S.monitor()
+    ms_per_step = ms / args.steps
+    value = args.steps / (ms / 1e3)
+
+    n, E, d = G.n, G.n_edges, wl.d
+    byt = algorithmic_bytes(n, E, d, 4, info["cg_iters_total"], info["solves"], wl.n_inner, args.steps)
+    achieved = byt / (ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "kernel": "k_soc (one SOC iteration per launch)",
+            "bytes_per_launch": int(byt / args.steps)}
+    line = {
+        "metric": "PFE outer iters/sec at 481x321 d=10 (Jacobi-PCG to 1e-6)",
+        "value": round(value, 2),
+        "unit": "outer iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": n, "edges": E, "d": d, "n_inner": wl.n_inner,
+                   "tol": wl.tol, "lambda": c, "r": c, "precond": "jacobi",
+                   "launch": "multi" if args.multi_launch else "persistent"},
+        "pcg_iters_per_solve": round(info["cg_iters_total"] / max(1, info["solves"]), 2),
+        "pcg_iters_learned": None,
+        "monitor": {k: float(f"{v:.6g}") for k, v in mon.items()},
+        "wall_s_timed": round(wall, 4),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl, c, c)
+        line["cpu_baseline"]["value"] = round(line["cpu_baseline"]["value"], 4)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

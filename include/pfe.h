@@ -1,0 +1,250 @@
+/*
+ * pfe.h — C ABI of libpfe, the MI355X (gfx950) implementation of the
+ * piecewise-flat-embedding (PFE) hot path of Meinhold, Hayes and Cahill,
+ * "Efficiently Computing Piecewise Flat Embeddings for Data Clustering and
+ * Image Segmentation".
+ *
+ * The library runs the nested Bregman iteration of the paper on the GPU:
+ *   - the SOC outer loop (Algorithm 1): Y-update, P-update, B-update;
+ *   - the Y-update by Split Bregman (Algorithm 2) in the compact n x d form of
+ *     Sec. III: the least-squares step as the d systems of Eq. (13),
+ *         [lambda/2 M^T M + r/2 D] Y = lambda/2 M^T (d - b) + r/2 D^{1/2} (P - B),
+ *     solved together by preconditioned conjugate gradient (Sec. III, last
+ *     paragraph), then the shrink of Eq. (9) and the Bregman update of Eq. (10);
+ *   - the P-update, argmin ||P - (D^{1/2} Y + B)|| s.t. P^T P = I, from an FP64
+ *     d x d Gram matrix and its Cholesky factor.
+ *
+ * Sign convention: Eq. (13) prints Q2 = B - P; the library uses P - B, which
+ * is the stationarity condition of Algorithm 2's least-squares objective.
+ *
+ * Conventions for every entry point
+ *   - All functions return a pfe_status; on failure a message is available from
+ *     pfe_last_error() (thread-local, valid until the next call on the thread).
+ *     No C++ exception crosses this boundary.
+ *   - Matrices are row-major.  n x d blocks (Y, P, B, right-hand sides) hold d
+ *     consecutive values per vertex.  Per-edge blocks (the split variables b and
+ *     d) hold d values per undirected edge, edges ordered by (i, j), i < j,
+ *     lexicographically — the row order of M in Sec. II.
+ *   - Element type of n x d and per-edge blocks is float for PFE_FP32 contexts
+ *     and double for PFE_FP64 contexts.
+ *   - "device" pointers are HIP device allocations on the current device; the
+ *     caller keeps ownership of every buffer it passes, and the library never
+ *     keeps a caller pointer after the call returns.  Library objects
+ *     (pfe_graph, pfe_ctx) own their device memory until destroyed.
+ *   - Work is enqueued on the stream given at creation; functions that return
+ *     host-side results (info structs, scalars) synchronise that stream.
+ */
+#ifndef PFE_H
+#define PFE_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PFE_OK = 0,
+    PFE_E_ARG = -1,      /* invalid argument (null pointer, size, parameter range) */
+    PFE_E_GRAPH = -2,    /* invalid graph: isolated vertex, bad/duplicate edge, non-finite weight */
+    PFE_E_HIP = -3,      /* a HIP runtime call failed */
+    PFE_E_NOMEM = -4,    /* device allocation failed */
+    PFE_E_NOT_SPD = -5,  /* CG breakdown: p^T A p <= 0 or non-finite scalar */
+    PFE_E_RANK = -6,     /* Gram matrix not positive definite (rank-deficient embedding) */
+    PFE_E_NOCONV = -7,   /* CG reached maxit; the state was still updated */
+    PFE_E_STATE = -8     /* request not valid in the context's current state */
+} pfe_status;
+
+/* graph kinds */
+enum { PFE_GRID = 0, PFE_EDGES = 1 };
+/* preconditioners */
+enum { PFE_JACOBI = 0, PFE_LEARNED = 1 };
+/* P-update */
+enum { PFE_POLAR = 0, PFE_CHOL = 1 };
+/* element type of the vector state */
+enum { PFE_FP32 = 0, PFE_FP64 = 1 };
+/* pfe_step granularity */
+enum { PFE_INNER = 0, PFE_OUTER = 1 };
+/* state blocks for pfe_get / pfe_set */
+enum {
+    PFE_Y = 0,      /* n x d, the current Y */
+    PFE_P = 1,      /* n x d */
+    PFE_B = 2,      /* n x d, SOC Bregman variable */
+    PFE_YHAT = 3,   /* n x d, D^{-1/2} P (feasible embedding, Yhat^T D Yhat = I); get only */
+    PFE_BSPLIT = 4, /* |E| x d, Split-Bregman variable b */
+    PFE_DSPLIT = 5, /* |E| x d, Split-Bregman variable d (needs keep_split on get) */
+    PFE_RHS = 6     /* n x d, right-hand side of the next least-squares solve; get only */
+};
+
+typedef struct pfe_graph pfe_graph;
+typedef struct pfe_ctx pfe_ctx;
+
+/*
+ * Graph description (Sec. II).  Edge weights are the heat kernel
+ * w_ij = exp(-||x_i - x_j||^2 / (2 sigma^2)), evaluated in FP64.
+ *
+ * PFE_GRID: one vertex per pixel, index y*W + x; feat is H*W x m (row-major,
+ *   float); stencil 4 or 8 selects the 4-/8-neighbourhood, a negative value -R
+ *   the (2R+1)^2 window minus its centre.
+ * PFE_EDGES: n vertices and n_edges undirected edges (src[e], dst[e]) with
+ *   squared feature distances dist2[e]; each unordered pair at most once, no
+ *   self loops.
+ * on_device: 1 if feat/src/dst/dist2 are device pointers, 0 if host pointers.
+ */
+typedef struct {
+    int kind;
+    int H, W, m;
+    const float* feat;
+    int stencil;
+    int64_t n;
+    int64_t n_edges;
+    const int32_t* src;
+    const int32_t* dst;
+    const double* dist2;
+    double sigma;
+    int on_device;
+} pfe_graph_desc;
+
+/*
+ * Solver parameters.
+ *   d          embedding dimension, 1 <= d <= 32, d < n
+ *   lambda     Split-Bregman penalty (Algorithm 2), >= 0; shrink threshold 1/lambda
+ *   r          SOC penalty (Algorithm 1), > 0
+ *   n_inner    Split-Bregman iterations per SOC iteration, >= 1
+ *   tol        PCG stop: ||r_c|| <= tol ||rhs_c|| for every column c
+ *   maxit      PCG iteration cap per solve
+ *   precond    PFE_JACOBI or PFE_LEARNED (needs pfe_set_learned first)
+ *   ortho      PFE_POLAR (exact argmin, default) or PFE_CHOL (Cholesky QR)
+ *   dtype      PFE_FP32 (vectors, SpMM, shrink in float; CG scalars and Gram
+ *              in double) or PFE_FP64 (everything in double)
+ *   init_ortho 1: D-orthonormalise Y0 (Y0 <- Y0 R^{-1}, R^T R = Y0^T D Y0); 0: use Y0 as is
+ *   keep_split 1: also store the split variable d (needed by pfe_get(PFE_DSPLIT))
+ *   persistent 1: run each SOC iteration as one cooperative launch with grid
+ *              barriers; 0: one launch per phase with stream-ordered phases
+ */
+typedef struct {
+    int d;
+    double lambda;
+    double r;
+    int n_inner;
+    double tol;
+    int maxit;
+    int precond;
+    int ortho;
+    int dtype;
+    int init_ortho;
+    int keep_split;
+    int persistent;
+} pfe_params;
+
+/* Per-call solver statistics (filled when a non-null pointer is passed). */
+typedef struct {
+    int64_t solves;          /* PCG solves performed by the call */
+    int64_t cg_iters_total;  /* sum over solves of the iterations of the slowest column */
+    int32_t cg_iters_max;    /* largest iteration count of a single solve */
+    int32_t cg_iters_last;   /* iteration count of the last solve */
+    double rel_res_max;      /* largest final ||r_c||/||rhs_c|| (recursive residual) */
+    int32_t status;          /* worst pfe_status met (PFE_E_NOCONV, PFE_E_NOT_SPD, ...) */
+    int32_t fallbacks;       /* learned-preconditioner solves redone with Jacobi */
+} pfe_step_info;
+
+/* Monitors of the current state (Eq. 1, Eq. 2). */
+typedef struct {
+    double objective;        /* ||M Yhat||_1, each undirected edge once */
+    double constraint;       /* max |Yhat^T D Yhat - I| */
+    double split;            /* ||D^{1/2} Y - P||_F / ||P||_F */
+    double orthogonality;    /* max |P^T P - I| */
+} pfe_monitors;
+
+/* ---- graph ------------------------------------------------------------ */
+
+/* Build the graph of Sec. II on the device: CSR adjacency with both directions
+ * of every edge (columns ascending per row), FP64 heat-kernel weights stored in
+ * FP32 and FP64, degrees d_i = sum_j w_ij (Algorithm 1, D = diag(W 1)).
+ * Errors: PFE_E_ARG for bad sizes/pointers, PFE_E_GRAPH for an isolated vertex
+ * (degree below FLT_MIN), a self loop, a duplicate or out-of-range edge, or a
+ * non-finite weight. */
+pfe_status pfe_build_graph(const pfe_graph_desc* desc, hipStream_t stream, pfe_graph** out);
+
+/* Sizes: vertices, undirected edges, CSR nonzeros of A (n + 2|E|). */
+pfe_status pfe_graph_info(const pfe_graph* g, int64_t* n, int64_t* n_edges, int64_t* nnz_A);
+
+/* Copy the CSR adjacency to caller device buffers (any may be null):
+ * rowptr[n+1], col[2|E|], w[2|E|] (float), degree[n] (double). */
+pfe_status pfe_graph_csr(const pfe_graph* g, int32_t* rowptr, int32_t* col, float* w,
+                         double* degree);
+
+void pfe_destroy_graph(pfe_graph* g);
+
+/* ---- solver context ------------------------------------------------------ */
+
+/* Create a solver for graph g (which must outlive the context): builds
+ * A = lambda/2 M^T M + r/2 D (Eq. 13) implicitly (its diagonal and Jacobi
+ * inverse), copies Y0 (device, n x d, dtype of params) and sets
+ * P = D^{1/2} Y, B = 0 (Algorithm 1 initialisation), after D-orthonormalising
+ * Y0 when init_ortho is set.  PFE_E_RANK if Y0 is rank deficient. */
+pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream_t stream,
+                    pfe_ctx** out);
+
+/* Change lambda and r (recomputes the diagonal of A); the state is kept. */
+pfe_status pfe_set_penalties(pfe_ctx* c, double lambda, double r);
+
+/* Advance the iteration.
+ * PFE_INNER: one Split-Bregman iteration (Algorithm 2): least-squares solve
+ *   of Eq. (13) by PCG warm-started from the current Y, then the shrink of
+ *   Eq. (9) and Bregman update of Eq. (10); b and d start from zero at the first
+ *   inner iteration of each SOC iteration.
+ * PFE_OUTER: complete the current SOC iteration (Algorithm 1): the remaining
+ *   inner iterations (n_inner in total), the P-update and the B-update.
+ * Returns PFE_E_NOCONV if some solve hit maxit (state updated), PFE_E_NOT_SPD
+ * or PFE_E_RANK on breakdown. */
+pfe_status pfe_step(pfe_ctx* c, int granularity, pfe_step_info* info);
+
+/* n_outer calls of pfe_step(PFE_OUTER) (Algorithm 1 for a fixed count). */
+pfe_status pfe_solve(pfe_ctx* c, int n_outer, pfe_step_info* info);
+
+/* Statistics accumulated since the last reset (pfe_step / pfe_solve with a
+ * non-null info reset them first).  reset != 0 clears them after reading.
+ * Synchronises the stream; returns the worst solver status met (as in info). */
+pfe_status pfe_stats(pfe_ctx* c, pfe_step_info* out, int reset);
+
+/* Copy a state block to / from a caller device buffer (layouts above).
+ * pfe_set(PFE_BSPLIT / PFE_DSPLIT) also rebuilds the right-hand side of the
+ * next inner solve.  PFE_E_STATE for PFE_DSPLIT when keep_split is 0. */
+pfe_status pfe_get(pfe_ctx* c, int which, void* dst);
+pfe_status pfe_set(pfe_ctx* c, int which, const void* src);
+
+/* Position inside the current SOC iteration: number of inner iterations done
+ * (0 .. n_inner-1).  Setting it to 0 clears b and d. */
+pfe_status pfe_get_inner_index(pfe_ctx* c, int* inner_index);
+pfe_status pfe_set_inner_index(pfe_ctx* c, int inner_index);
+
+/* Objective, constraint and split residuals of the current state. */
+pfe_status pfe_monitor(pfe_ctx* c, pfe_monitors* out);
+
+/* Q = A X for caller device blocks X, Q (n x d, context dtype): the operator
+ * of Eq. (13). */
+pfe_status pfe_apply_A(pfe_ctx* c, const void* X, void* Q);
+
+/* Solve A X = RHS by the context's PCG, X (device) holds the initial guess on
+ * entry and the solution on return.  iters (host, may be null) receives the
+ * per-column iteration counts (d ints). */
+pfe_status pfe_pcg(pfe_ctx* c, const void* RHS, void* X, int32_t* iters, pfe_step_info* info);
+
+/* q-quantile of |M Y| over all |E| x d entries for the current Y (the order
+ * statistic of rank floor(q (N - 1)) among the N values, computed in the
+ * context dtype).  Used to place the shrink threshold. */
+pfe_status pfe_edge_quantile(pfe_ctx* c, double q, double* out);
+
+void pfe_destroy_ctx(pfe_ctx* c);
+
+/* ---- diagnostics ----------------------------------------------------------- */
+
+const char* pfe_status_string(pfe_status s);
+const char* pfe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFE_H */

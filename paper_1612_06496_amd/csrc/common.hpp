@@ -1,0 +1,71 @@
+// Internal declarations shared by the libpfe translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+
+#include "pfe.h"
+
+namespace pfe {
+
+void set_error(const char* fmt, ...);
+pfe_status hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+constexpr int kMaxD = 32;          // largest embedding dimension
+constexpr int kNumXcd = 8;         // accelerator complex dies on MI355X
+constexpr int kBlock = 512;        // threads per workgroup of the row-parallel phases
+constexpr int kSmemDoubles = 4608; // LDS scratch per workgroup (36 KiB)
+
+// Small solver state kept in device memory: per-column CG scalars, the d x d
+// transform of the P-update, flags and statistics.
+struct alignas(64) Scal {
+    double rho[kMaxD];      // r^T z of the current iteration
+    double alpha[kMaxD];
+    double beta[kMaxD];
+    double bnorm2[kMaxD];   // ||rhs_c||^2
+    double rr[kMaxD];       // ||r_c||^2
+    double T[kMaxD * kMaxD];  // d x d transform, row-major
+    double mon[16];         // monitor results
+    int iters[kMaxD];       // iterations of each column in the current solve
+    int active[kMaxD];      // column still iterating
+    int zero[kMaxD];        // column with a zero right-hand side
+    int it;                 // iteration index of the current solve
+    int done;               // current solve finished
+    int status;             // worst status since the last reset (0 or PFE_E_*)
+    int abort_flag;         // a grid barrier timed out
+    int ortho_ok;           // the last Gram factorisation succeeded
+    int pad_;
+    // statistics since the last reset
+    long long solves;
+    long long iters_total;
+    int iters_max;
+    int iters_last;
+    double relres_max;
+    int fallbacks;
+    int pad2_;
+};
+
+}  // namespace pfe
+
+#define PFE_CHECK_HIP(expr)                                                   \
+    do {                                                                      \
+        hipError_t e__ = (expr);                                              \
+        if (e__ != hipSuccess) return pfe::hip_fail(e__, #expr, __FILE__, __LINE__); \
+    } while (0)
+
+struct pfe_graph {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t n = 0;
+    int64_t n_edges = 0;
+    int64_t slots = 0;        // 2 |E| directed adjacency entries
+    int* rowptr = nullptr;    // n + 1
+    int* col = nullptr;       // slots, ascending within a row
+    int* rev = nullptr;       // slot of the reverse direction
+    int* eid = nullptr;       // undirected edge index (lexicographic (i, j), i < j)
+    float* w32 = nullptr;     // heat-kernel weight per slot, FP32
+    double* w64 = nullptr;    // same in FP64
+    double* degree = nullptr; // d_i = sum_j w_ij (FP64)
+    double* wsq = nullptr;    // sum_j w_ij^2 (FP64): diagonal of M^T M
+};

@@ -1,0 +1,190 @@
+"""Python face of libpfe: the C entry points with torch tensors for device
+memory and streams.  Argument marshalling only — every step of the
+piecewise-flat-embedding iteration runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_WHICH = {"Y": L.PFE_Y, "P": L.PFE_P, "B": L.PFE_B, "Yhat": L.PFE_YHAT,
+          "b": L.PFE_BSPLIT, "d": L.PFE_DSPLIT, "rhs": L.PFE_RHS}
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(x, dtype) -> torch.Tensor:
+    """Contiguous CUDA tensor of the given dtype (copies host arrays in)."""
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x))
+    return x.to(device="cuda", dtype=dtype).contiguous()
+
+
+class Graph:
+    """A graph built by pfe_build_graph (CSR adjacency, heat-kernel weights)."""
+
+    def __init__(self, handle: C.c_void_p, stream):
+        self._h = handle
+        self._stream = stream
+        n, e, nnz = C.c_int64(), C.c_int64(), C.c_int64()
+        L.check(L.lib.pfe_graph_info(self._h, C.byref(n), C.byref(e), C.byref(nnz)), "pfe_graph_info")
+        self.n, self.n_edges, self.nnz_A = n.value, e.value, nnz.value
+
+    @classmethod
+    def grid(cls, feat, H: int, W: int, stencil: int, sigma: float, stream=None) -> "Graph":
+        f = _dev(feat, torch.float32).reshape(H * W, -1)
+        desc = L.pfe_graph_desc(kind=L.PFE_GRID, H=H, W=W, m=f.shape[1], feat=f.data_ptr(),
+                                stencil=stencil, sigma=sigma, on_device=1)
+        h = C.c_void_p()
+        L.check(L.lib.pfe_build_graph(C.byref(desc), _stream_handle(stream), C.byref(h)), "pfe_build_graph")
+        return cls(h, stream)
+
+    @classmethod
+    def edges(cls, n: int, src, dst, dist2, sigma: float, stream=None) -> "Graph":
+        s = _dev(src, torch.int32)
+        t = _dev(dst, torch.int32)
+        q = _dev(dist2, torch.float64)
+        desc = L.pfe_graph_desc(kind=L.PFE_EDGES, n=n, n_edges=s.numel(), src=s.data_ptr(),
+                                dst=t.data_ptr(), dist2=q.data_ptr(), sigma=sigma, on_device=1)
+        h = C.c_void_p()
+        L.check(L.lib.pfe_build_graph(C.byref(desc), _stream_handle(stream), C.byref(h)), "pfe_build_graph")
+        return cls(h, stream)
+
+    def csr(self):
+        rowptr = torch.empty(self.n + 1, dtype=torch.int32, device="cuda")
+        col = torch.empty(2 * self.n_edges, dtype=torch.int32, device="cuda")
+        w = torch.empty(2 * self.n_edges, dtype=torch.float32, device="cuda")
+        deg = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        L.check(L.lib.pfe_graph_csr(self._h, rowptr.data_ptr(), col.data_ptr(), w.data_ptr(),
+                                    deg.data_ptr()), "pfe_graph_csr")
+        return dict(rowptr=rowptr, col=col, w=w, degree=deg)
+
+    def close(self):
+        if self._h:
+            L.lib.pfe_destroy_graph(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver:
+    """A pfe_ctx: the SOC / Split-Bregman iteration on one graph."""
+
+    def __init__(self, graph: Graph, Y0, *, lam: float, r: float, n_inner: int, tol: float = 1e-6,
+                 maxit: int = 1000, ortho: str = "polar", fp64: bool = False, init_ortho: bool = True,
+                 keep_split: bool = False, persistent: bool = True, stream=None):
+        self.graph = graph
+        self.dtype = torch.float64 if fp64 else torch.float32
+        y0 = _dev(Y0, self.dtype)
+        self.n, self.d = y0.shape
+        self.params = L.pfe_params(
+            d=self.d, lambda_=lam, r=r, n_inner=n_inner, tol=tol, maxit=maxit,
+            precond=L.PFE_JACOBI, ortho=L.PFE_POLAR if ortho == "polar" else L.PFE_CHOL,
+            dtype=L.PFE_FP64 if fp64 else L.PFE_FP32, init_ortho=int(init_ortho),
+            keep_split=int(keep_split), persistent=int(persistent))
+        self._stream = stream
+        h = C.c_void_p()
+        L.check(L.lib.pfe_init(graph._h, C.byref(self.params), y0.data_ptr(), _stream_handle(stream),
+                               C.byref(h)), "pfe_init")
+        self._h = h
+
+    # -- iteration -----------------------------------------------------------
+    @staticmethod
+    def _info_dict(info: L.pfe_step_info):
+        return dict(solves=info.solves, cg_iters_total=info.cg_iters_total,
+                    cg_iters_max=info.cg_iters_max, cg_iters_last=info.cg_iters_last,
+                    rel_res_max=info.rel_res_max, status=info.status, fallbacks=info.fallbacks)
+
+    def step(self, granularity: str = "outer", info: bool = False, allow_noconv: bool = False):
+        g = L.PFE_INNER if granularity == "inner" else L.PFE_OUTER
+        inf = L.pfe_step_info() if info else None
+        st = L.lib.pfe_step(self._h, g, C.byref(inf) if info else None)
+        L.check(st, "pfe_step", allow=(L.PFE_E_NOCONV,) if allow_noconv else ())
+        return self._info_dict(inf) if info else None
+
+    def solve(self, n_outer: int, info: bool = False, allow_noconv: bool = False):
+        inf = L.pfe_step_info() if info else None
+        st = L.lib.pfe_solve(self._h, n_outer, C.byref(inf) if info else None)
+        L.check(st, "pfe_solve", allow=(L.PFE_E_NOCONV,) if allow_noconv else ())
+        return self._info_dict(inf) if info else None
+
+    def stats(self, reset: bool = False, allow_noconv: bool = False) -> dict:
+        """Statistics accumulated since the last reset."""
+        inf = L.pfe_step_info()
+        st = L.lib.pfe_stats(self._h, C.byref(inf), int(reset))
+        L.check(st, "pfe_stats", allow=(L.PFE_E_NOCONV,) if allow_noconv else ())
+        return self._info_dict(inf)
+
+    # -- state ---------------------------------------------------------------
+    def get(self, which: str) -> torch.Tensor:
+        rows = self.graph.n_edges if which in ("b", "d") else self.n
+        out = torch.empty(rows, self.d, dtype=self.dtype, device="cuda")
+        L.check(L.lib.pfe_get(self._h, _WHICH[which], out.data_ptr()), f"pfe_get({which})")
+        return out
+
+    def set(self, which: str, value) -> None:
+        v = _dev(value, self.dtype)
+        L.check(L.lib.pfe_set(self._h, _WHICH[which], v.data_ptr()), f"pfe_set({which})")
+
+    @property
+    def inner_index(self) -> int:
+        k = C.c_int()
+        L.check(L.lib.pfe_get_inner_index(self._h, C.byref(k)), "pfe_get_inner_index")
+        return k.value
+
+    @inner_index.setter
+    def inner_index(self, k: int) -> None:
+        L.check(L.lib.pfe_set_inner_index(self._h, int(k)), "pfe_set_inner_index")
+
+    def set_penalties(self, lam: float, r: float) -> None:
+        L.check(L.lib.pfe_set_penalties(self._h, lam, r), "pfe_set_penalties")
+
+    def monitor(self) -> dict:
+        m = L.pfe_monitors()
+        L.check(L.lib.pfe_monitor(self._h, C.byref(m)), "pfe_monitor")
+        return dict(objective=m.objective, constraint=m.constraint, split=m.split,
+                    orthogonality=m.orthogonality)
+
+    # -- operator and solver entry points ------------------------------------
+    def apply_A(self, X) -> torch.Tensor:
+        x = _dev(X, self.dtype)
+        q = torch.empty_like(x)
+        L.check(L.lib.pfe_apply_A(self._h, x.data_ptr(), q.data_ptr()), "pfe_apply_A")
+        return q
+
+    def pcg(self, rhs, x0, allow_noconv: bool = False):
+        b = _dev(rhs, self.dtype)
+        x = _dev(x0, self.dtype).clone()
+        iters = (C.c_int32 * self.d)()
+        inf = L.pfe_step_info()
+        st = L.lib.pfe_pcg(self._h, b.data_ptr(), x.data_ptr(), iters, C.byref(inf))
+        L.check(st, "pfe_pcg", allow=(L.PFE_E_NOCONV,) if allow_noconv else ())
+        return x, np.array(list(iters)), self._info_dict(inf)
+
+    def edge_quantile(self, q: float) -> float:
+        out = C.c_double()
+        L.check(L.lib.pfe_edge_quantile(self._h, q, C.byref(out)), "pfe_edge_quantile")
+        return out.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib.pfe_destroy_ctx(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

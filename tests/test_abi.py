@@ -1,0 +1,73 @@
+"""CPU checks of the C ABI: the library loads and exports every entry point
+declared in include/pfe.h; the ctypes structures match the header's layout."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pfe.h")
+LIB = os.path.join(ROOT, "paper_1612_06496_amd", "libpfe.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pfe_[A-Za-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("pfe_build_graph", "pfe_init", "pfe_step", "pfe_solve"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpfe.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpfe.so not built")
+def test_status_strings_and_binding_signatures():
+    from paper_1612_06496_amd import _lib as L
+    assert set(L.SIGNATURES) == set(declared_functions())
+    assert L.lib.pfe_status_string(L.PFE_E_RANK).decode().startswith("rank")
+    assert L.lib.pfe_status_string(L.PFE_OK).decode() == "ok"
+    # null-argument paths return PFE_E_ARG without touching a GPU
+    assert L.lib.pfe_build_graph(None, None, None) == L.PFE_E_ARG
+    assert L.lib.pfe_step(None, 0, None) == L.PFE_E_ARG
+    assert L.lib.pfe_graph_info(None, None, None, None) == L.PFE_E_ARG
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes field offset equals offsetof() of the C header, compiled with gcc."""
+    import shutil
+    import subprocess
+    from paper_1612_06496_amd import _lib as L
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = [L.pfe_graph_desc, L.pfe_params, L.pfe_step_info, L.pfe_monitors]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pfe.h"', "int main(void){"]
+    for st in structs:
+        cname = st.__name__
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        for fname, _ in st._fields_:
+            cf = "lambda" if fname == "lambda_" else fname
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {cf}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                    "-I", "/opt/rocm/include", str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = []
+    for st in structs:
+        want.append(ctypes.sizeof(st))
+        for fname, _ in st._fields_:
+            want.append(getattr(st, fname).offset)
+    assert got == want
