@@ -40,6 +40,45 @@ def algorithmic_bytes(n, E, d, esz, cg_iters, solves, n_inner, n_outer):
     return cg_iters * cg_iter + n_outer * per_outer_fixed
 
 
+def measured_traffic():
+    """HBM traffic per k_soc launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (scaled by the copy-kernel calibration), or None when the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_soc_voronoi481x321_traffic.json")
+    src = os.path.join(ROOT, "paper_1612_06496_amd", "csrc", "solver.hip")
+    try:
+        rec = json.load(open(path))
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    return rec["traffic_bytes_per_launch"] if rec.get("solver_sha256") == cur else None
+
+
+def copy_bandwidth(gib):
+    """Achievable bandwidth of a plain 16-byte-vector device copy (read + write
+    bytes / time), best of 5."""
+    import ctypes as C
+    import torch
+    from paper_1612_06496_amd import _lib as L
+    nbytes = int(gib * 2**30) // 64 * 64
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    best = 0.0
+    for _ in range(6):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        L.check(L.lib.pfe_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, stream),
+                "pfe_stream_copy")
+        b.record()
+        torch.cuda.synchronize()
+        best = max(best, 2 * nbytes / (a.elapsed_time(b) / 1e3) / 1e9)
+    del src, dst
+    return best
+
+
 def cpu_baseline(wl, lam, r, n_steps=2):
     """The FP64 oracle on the host, on a bounded sample: n_steps SOC iterations
     of the same workload (sparse LU factorisation reported separately)."""
@@ -70,6 +109,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-gib", type=float, default=2.0, help="size of the copy-bandwidth probe")
     ap.add_argument("--multi-launch", action="store_true", help="one launch per phase instead of one per SOC iteration")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -92,14 +132,16 @@ def main():
     c = 1.0 / S.edge_quantile(0.99)
     S.set_penalties(c, c)
 
-    S.solve(args.warmup)
+    for _ in range(args.warmup):
+        S.solve(1)
     S.stats(reset=True)
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record()
-    S.solve(args.steps)
+    for _ in range(args.steps):      # one persistent launch per SOC iteration
+        S.solve(1)
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -113,9 +155,9 @@ def main():
     byt = algorithmic_bytes(n, E, d, 4, info["cg_iters_total"], info["solves"], wl.n_inner, args.steps)
     achieved = byt / (ms / 1e3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
             "kernel": "k_soc (one SOC iteration per launch)",
-            "bytes_per_launch": int(byt / args.steps)}
+            "bytes_per_launch": int(byt / args.steps), "workgroups": info["workgroups"]}
     line = {
         "metric": "PFE outer iters/sec at 481x321 d=10 (Jacobi-PCG to 1e-6)",
         "value": round(value, 2),
@@ -133,6 +175,8 @@ def main():
         "wall_s_timed": round(wall, 4),
         "roofline": roof,
     }
+    if args.copy_gib > 0:
+        line["copy_gbs"] = round(copy_bandwidth(args.copy_gib), 1)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, c, c)
         line["cpu_baseline"]["value"] = round(line["cpu_baseline"]["value"], 4)

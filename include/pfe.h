@@ -147,6 +147,8 @@ typedef struct {
     double rel_res_max;      /* largest final ||r_c||/||rhs_c|| (recursive residual) */
     int32_t status;          /* worst pfe_status met (PFE_E_NOCONV, PFE_E_NOT_SPD, ...) */
     int32_t fallbacks;       /* learned-preconditioner solves redone with Jacobi */
+    int32_t workgroups;      /* workgroups of the persistent launch (0: one launch per phase) */
+    int32_t reserved;
 } pfe_step_info;
 
 /* Monitors of the current state (Eq. 1, Eq. 2). */
@@ -240,6 +242,12 @@ pfe_status pfe_edge_quantile(pfe_ctx* c, double q, double* out);
 void pfe_destroy_ctx(pfe_ctx* c);
 
 /* ---- diagnostics ----------------------------------------------------------- */
+
+/* Plain device copy dst[0..bytes) = src[0..bytes) with 16-byte vector loads and
+ * stores (bytes a multiple of 16, both pointers 16-byte aligned), enqueued on
+ * stream.  Measures the achievable HBM bandwidth and calibrates traffic
+ * counters; it is no part of the embedding method. */
+pfe_status pfe_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 
 const char* pfe_status_string(pfe_status s);
 const char* pfe_last_error(void);

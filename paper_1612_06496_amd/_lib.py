@@ -55,6 +55,7 @@ class pfe_step_info(C.Structure):
         ("solves", C.c_int64), ("cg_iters_total", C.c_int64),
         ("cg_iters_max", C.c_int32), ("cg_iters_last", C.c_int32),
         ("rel_res_max", C.c_double), ("status", C.c_int32), ("fallbacks", C.c_int32),
+        ("workgroups", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -85,6 +86,7 @@ SIGNATURES = {
     "pfe_pcg": (_S, [_P, _P, _P, C.POINTER(C.c_int32), C.POINTER(pfe_step_info)]),
     "pfe_edge_quantile": (_S, [_P, C.c_double, C.POINTER(C.c_double)]),
     "pfe_destroy_ctx": (None, [_P]),
+    "pfe_stream_copy": (_S, [_P, _P, C.c_size_t, _P]),
     "pfe_status_string": (C.c_char_p, [C.c_int]),
     "pfe_last_error": (C.c_char_p, []),
 }

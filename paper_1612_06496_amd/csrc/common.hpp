@@ -60,12 +60,23 @@ struct pfe_graph {
     int64_t n = 0;
     int64_t n_edges = 0;
     int64_t slots = 0;        // 2 |E| directed adjacency entries
+    // CSR adjacency (columns ascending within a row)
     int* rowptr = nullptr;    // n + 1
-    int* col = nullptr;       // slots, ascending within a row
+    int* col = nullptr;       // slots
     int* rev = nullptr;       // slot of the reverse direction
     int* eid = nullptr;       // undirected edge index (lexicographic (i, j), i < j)
     float* w32 = nullptr;     // heat-kernel weight per slot, FP32
     double* w64 = nullptr;    // same in FP64
     double* degree = nullptr; // d_i = sum_j w_ij (FP64)
     double* wsq = nullptr;    // sum_j w_ij^2 (FP64): diagonal of M^T M
+    int max_deg = 0;
+    // Slot layout used by the solver.  ELL (stencil-like graphs): K slots per
+    // row, slot k of row i at index k * n + i, unused slots point at the row
+    // itself with weight 0; otherwise the CSR order above (K = 0).
+    int ell_K = 0;
+    int64_t nslot = 0;        // slots in the solver layout (K n for ELL, 2|E| for CSR)
+    int* s_col = nullptr;
+    float* s_w32 = nullptr;
+    double* s_w64 = nullptr;
+    int* s_eid = nullptr;     // undirected edge of the slot, -1 for padding
 };

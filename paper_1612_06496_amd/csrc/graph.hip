@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstring>
 #include <vector>
+#include <algorithm>
 
 #include "common.hpp"
 
@@ -257,10 +258,49 @@ __global__ void k_rev_eid(int64_t n, const int* __restrict__ rowptr, const int* 
     }
 }
 
+// ELL copy of the CSR slots: slot k of row i at k * n + i.
+__global__ void k_build_ell(int64_t n, int K, const int* __restrict__ rowptr, const int* __restrict__ col,
+                            const float* __restrict__ w32, const double* __restrict__ w64,
+                            const int* __restrict__ eid, int* __restrict__ s_col, float* __restrict__ s_w32,
+                            double* __restrict__ s_w64, int* __restrict__ s_eid) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int s0 = rowptr[i], deg = rowptr[i + 1] - s0;
+    for (int k = 0; k < K; ++k) {
+        int64_t s = (int64_t)k * n + i;
+        if (k < deg) {
+            s_col[s] = col[s0 + k];
+            s_w32[s] = w32[s0 + k];
+            s_w64[s] = w64[s0 + k];
+            s_eid[s] = eid[s0 + k];
+        } else {
+            s_col[s] = (int)i;
+            s_w32[s] = 0.0f;
+            s_w64[s] = 0.0;
+            s_eid[s] = -1;
+        }
+    }
+}
+
+__global__ void k_max_deg(int64_t n, const int* __restrict__ rowptr, int* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    atomicMax(out, rowptr[i + 1] - rowptr[i]);
+}
+
+// grid-stride 16-byte copy
+__global__ void __launch_bounds__(256) k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n16) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 static void free_graph_buffers(pfe_graph* g) {
     if (!g) return;
     (void)hipFree(g->rowptr); (void)hipFree(g->col); (void)hipFree(g->rev); (void)hipFree(g->eid);
     (void)hipFree(g->w32); (void)hipFree(g->w64); (void)hipFree(g->degree); (void)hipFree(g->wsq);
+    if (g->ell_K > 0) {
+        (void)hipFree(g->s_col); (void)hipFree(g->s_w32); (void)hipFree(g->s_w64); (void)hipFree(g->s_eid);
+    }
 }
 
 static const char* graph_err_text(int e) {
@@ -385,6 +425,36 @@ static pfe_status build_impl(const pfe_graph_desc* d, hipStream_t st, pfe_graph*
     if (tmp_in3) PFE_CHECK_HIP(hipFreeAsync(tmp_in3, st));
     PFE_CHECK_HIP(hipStreamSynchronize(st));
     if (herr) { set_error("pfe_build_graph: %s", graph_err_text(herr)); return PFE_E_GRAPH; }
+
+    // slot layout for the solver: ELL when padding to the largest degree costs
+    // at most a quarter more slots (pixel stencils), CSR otherwise.
+    int* dmax = nullptr;
+    PFE_CHECK_HIP(hipMalloc((void**)&dmax, sizeof(int)));
+    PFE_CHECK_HIP(hipMemsetAsync(dmax, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_max_deg, dim3(gridN), dim3(TB), 0, st, n, g->rowptr, dmax);
+    PFE_CHECK_HIP(hipMemcpyAsync(&g->max_deg, dmax, sizeof(int), hipMemcpyDeviceToHost, st));
+    PFE_CHECK_HIP(hipStreamSynchronize(st));
+    PFE_CHECK_HIP(hipFree(dmax));
+    const int64_t ell_slots = (int64_t)g->max_deg * n;
+    if (g->max_deg > 0 && 4 * ell_slots <= 5 * g->slots && ell_slots < (int64_t)INT32_MAX) {
+        g->ell_K = g->max_deg;
+        g->nslot = ell_slots;
+        PFE_CHECK_HIP(hipMalloc((void**)&g->s_col, sizeof(int) * ell_slots));
+        PFE_CHECK_HIP(hipMalloc((void**)&g->s_w32, sizeof(float) * ell_slots));
+        PFE_CHECK_HIP(hipMalloc((void**)&g->s_w64, sizeof(double) * ell_slots));
+        PFE_CHECK_HIP(hipMalloc((void**)&g->s_eid, sizeof(int) * ell_slots));
+        hipLaunchKernelGGL(k_build_ell, dim3(gridN), dim3(TB), 0, st, n, g->ell_K, g->rowptr, g->col, g->w32,
+                           g->w64, g->eid, g->s_col, g->s_w32, g->s_w64, g->s_eid);
+        PFE_CHECK_HIP(hipGetLastError());
+        PFE_CHECK_HIP(hipStreamSynchronize(st));
+    } else {
+        g->ell_K = 0;
+        g->nslot = g->slots;
+        g->s_col = g->col;
+        g->s_w32 = g->w32;
+        g->s_w64 = g->w64;
+        g->s_eid = g->eid;
+    }
     return PFE_OK;
 }
 
@@ -470,6 +540,19 @@ pfe_status pfe_graph_csr(const pfe_graph* g, int32_t* rowptr, int32_t* col, floa
     if (w) PFE_CHECK_HIP(hipMemcpyAsync(w, g->w32, sizeof(float) * g->slots, hipMemcpyDeviceToDevice, st));
     if (degree) PFE_CHECK_HIP(hipMemcpyAsync(degree, g->degree, sizeof(double) * g->n, hipMemcpyDeviceToDevice, st));
     PFE_CHECK_HIP(hipStreamSynchronize(st));
+    return PFE_OK;
+}
+
+pfe_status pfe_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream) {
+    if (!src || !dst || (bytes % 16) != 0 || ((uintptr_t)src % 16) != 0 || ((uintptr_t)dst % 16) != 0) {
+        set_error("pfe_stream_copy: pointers and size must be 16-byte aligned");
+        return PFE_E_ARG;
+    }
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return PFE_OK;
+    const unsigned blocks = (unsigned)std::min<size_t>((n16 + 255) / 256, 256 * 64);
+    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, stream, (const uint4*)src, (uint4*)dst, n16);
+    PFE_CHECK_HIP(hipGetLastError());
     return PFE_OK;
 }
 

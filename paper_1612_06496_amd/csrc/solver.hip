@@ -2,25 +2,34 @@
 // the compact form of Eqs. 9, 10, 13), their PCG least-squares solve
 // (Sec. III), and the SOC P/B-update (Algorithm 1).
 //
-// Layout: every n x d block is row-major (d values per vertex); the
-// Split-Bregman variables are stored per directed CSR slot (i -> j) with the
-// orientation "i minus j", so each vertex owns the slots of its own row and
-// every phase is atomic-free.  The two copies of an undirected edge are exact
-// negatives of each other (the shrink and the clamp are odd functions and
-// w (y_i - y_j) = -(w (y_j - y_i)) exactly), which keeps them consistent.
+// Layout.  Every n x d block is row-major (d values per vertex).  The
+// Split-Bregman variables live per directed slot (i -> j) with the orientation
+// "i minus j", so each vertex owns the slots of its own row and every phase is
+// atomic-free; the two copies of an undirected edge stay exact negatives of each
+// other because the shrink and the clamp are odd and w (y_i - y_j) is exactly
+// -(w (y_j - y_i)).  Slots follow the graph's solver layout (ELL: slot k of row
+// i at k n + i, so lanes on consecutive rows read consecutive slots; or CSR).
 //
-// Work decomposition: a phase is executed by nblk workgroups; workgroup lb
-// owns the contiguous row range [lb n / nblk, (lb+1) n / nblk) and walks it
-// R = blockDim / d rows at a time with thread t on (row t / d, column t % d),
-// so consecutive lanes touch consecutive elements and gathers of neighbour
-// rows stay coalesced on image grids.  Per-column reductions are FP64: each
-// workgroup writes one partial per column, and one workgroup sums the partials
-// in a fixed order (deterministic results).  Workgroup indices are remapped so
-// that each XCD owns one contiguous eighth of the rows.
+// Work decomposition.  A phase runs on nblk workgroups; workgroup lb owns the
+// rows [row0[lb], row0[lb+1]) and walks them R = blockDim / d rows at a time,
+// thread t on (row t / d, column t % d): consecutive lanes touch consecutive
+// elements and gathers of neighbour rows of an image stay coalesced.  Workgroup
+// indices are remapped so that each XCD owns contiguous rows.  Per-column
+// reductions are FP64: one partial per workgroup and column, summed in a fixed
+// order (results are bitwise reproducible).
+//
+// PCG.  The d systems of Eq. 13 are solved together with per-column scalars by
+// the Chronopoulos-Gear form of Jacobi-preconditioned CG, which needs a single
+// global reduction per iteration.  Each iteration is one phase: a row updates
+// its own p, s, x, r and forms w = A u with u = diag(A)^{-1} r, recomputing the
+// neighbours' new u from their previous r, w, s (bit-identical to what their
+// owners store), so an iteration costs one grid-wide synchronisation.
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
 #include <algorithm>
+#include <vector>
 
 #include "common.hpp"
 
@@ -30,37 +39,55 @@ enum Phase : int {
     PH_E0 = 0,      // first inner solve: rhs = r/2 D^{1/2}(P - B), r0 = rhs - A x
     PH_EU = 1,      // shrink + Bregman on the edges, next rhs, optionally r0
     PH_R0 = 2,      // r0 = rhs - A x from a stored rhs
-    PH_A = 3,       // p = z + beta p, q = A p, p^T q
-    PH_B = 4,       // x += alpha p, r -= alpha q, r^T z, r^T r
+    PH_W0 = 3,      // w0 = A u0, gamma0 = r0.u0, delta0 = w0.u0
+    PH_IT = 4,      // one CG iteration (p, s, x, r, w) and its dot products
     PH_GRAM = 5,    // Z = D^{1/2} Y + B, Z^T Z
     PH_APPLY = 6,   // P = Z T, B = Z - P
     PH_RHS = 7,     // rhs from stored b, d (no r0)
     PH_ZERO = 8     // zero the solution columns whose rhs is zero
 };
 
+// per (segment, column) CG state, struct of arrays of length nseg * d
+struct ColState {
+    double* gamma;    // r.u of the current iteration
+    double* alpha;
+    double* beta;
+    double* bnorm2;   // ||rhs||^2
+    double* rr;       // ||r||^2
+    int* iters;
+    int* active;
+    int* zero;
+};
+
 template <typename T>
 struct KA {
-    int n, d, R, nblk;
-    const int* rowptr;
-    const int* col;
-    const T* w;
+    int n, d, R, nblk, nseg, ell_K;
+    const int* row0;       // nblk + 1 row boundaries of the logical workgroups
+    const int* blk_seg;    // segment of each logical workgroup
+    const int* seg_blk0;   // nseg + 1 first logical workgroup of each segment
+    const int* rowptr;     // CSR row pointers (used when ell_K == 0)
+    const int* scol;       // solver slot layout
+    const T* sw;
     const T* diagA;
     const T* invdiag;
     const T* sqrtD;
     const T* isqrtD;
     const double* degree;
-    T* x;              // PCG iterate
+    T* x;              // PCG iterate (Y, or a caller buffer)
     T* Y;
     T* P;
     T* B;
     T* bs;             // Split-Bregman b per slot
     T* ds;             // Split-Bregman d per slot (keep_split)
     T* rhs;
-    T* r;
-    T* pA;
-    T* pB;
-    T* q;
-    double* part;
+    T* rb[2];          // r, double-buffered across iterations
+    T* wb[2];          // w = A u
+    T* sb[2];          // s = A p
+    T* p;
+    double* part;      // workgroup partials
+    double* gpart;     // per-XCD-group partials
+    double* Tm;        // d x d transforms (stride kMaxD), one per segment
+    ColState cs;
     Scal* S;
     unsigned* bar;
     T c_off;           // lambda / 2: A_ij = -c_off w_ij^2, rhs edge factor
@@ -81,11 +108,6 @@ __device__ __forceinline__ int logical_block(int nblk) {
     int b = blockIdx.x;
     if ((nblk % kNumXcd) == 0) return (b % kNumXcd) * (nblk / kNumXcd) + b / kNumXcd;
     return b;
-}
-
-__device__ __forceinline__ void row_range(int lb, int nblk, int n, int& rb, int& re) {
-    rb = (int)(((long long)n * lb) / nblk);
-    re = (int)(((long long)n * (lb + 1)) / nblk);
 }
 
 __device__ __forceinline__ int ld_flag(const int* p) {
@@ -109,10 +131,13 @@ __device__ __forceinline__ T shrink(T y, T g) {
     return fmax(y - g, T(0)) + fmin(y + g, T(0));
 }
 
-// Jacobi-preconditioned residual z = r / diag(A)
-template <typename T>
-__device__ __forceinline__ T zval(const KA<T>& a, int i, size_t e) {
-    return mul_t(a.invdiag[i], a.r[e]);
+// slots of row i: s = s0 + k * stride, k < cnt.  KC > 0 is the ELL width known
+// at compile time (the slot loops of the hot phases then unroll completely).
+template <int KC = 0, typename T>
+__device__ __forceinline__ void row_slots(const KA<T>& a, int i, int& s0, int& cnt, int& stride) {
+    if constexpr (KC > 0) { s0 = i; cnt = KC; stride = a.n; }
+    else if (a.ell_K > 0) { s0 = i; cnt = a.ell_K; stride = a.n; }
+    else { s0 = a.rowptr[i]; cnt = a.rowptr[i + 1] - s0; stride = 1; }
 }
 
 // Z = D^{1/2} Y + B of the P-update
@@ -121,9 +146,17 @@ __device__ __forceinline__ T zrow(const KA<T>& a, int i, size_t e) {
     return fma_t(a.sqrtD[i], a.Y[e], a.B[e]);
 }
 
+// The CG recurrences, written once so that a row and its neighbours evaluate
+// them identically:  s_i = w_i + beta s_{i-1},  r_{i+1} = r_i - alpha s_i,
+// u_{i+1} = r_{i+1} / diag(A).
+template <typename T>
+__device__ __forceinline__ T cg_s(bool first, T beta, T sprev, T w) { return first ? w : fma_t(beta, sprev, w); }
+template <typename T>
+__device__ __forceinline__ T cg_r(T alpha, T s, T r) { return fma_t(-alpha, s, r); }
+
 // per-thread FP64 accumulators -> one partial per (quantity, column) per workgroup
 template <int NQ>
-__device__ void block_partials(const double (&acc)[NQ], double* sh, int d, int R, double* part,
+__device__ __forceinline__ void block_partials(const double (&acc)[NQ], double* sh, int d, int R, double* part,
                                int nblk, int lb) {
     const int t = threadIdx.x;
     const int B = blockDim.x;
@@ -139,19 +172,21 @@ __device__ void block_partials(const double (&acc)[NQ], double* sh, int d, int R
     __syncthreads();
 }
 
-// out[k] = sum over workgroups b (in order) of part[(k / d) * nblk + b) * d + k % d]
-// for k < nq * d; runs on one workgroup; sh needs >= max(blockDim, nq*d) doubles.
-__device__ void reduce_parts(const double* part, int nblk, int d, int nq, double* out, double* sh) {
+// out[q * d + c] = sum over workgroups b in [b0, b1) of src[(q * stride + b) * d + c],
+// in a fixed order; one workgroup; sh needs max(blockDim, nq * d) doubles.
+__device__ __forceinline__ void reduce_range(const double* src, int stride, int b0, int b1, int d, int nq, double* out,
+                             double* sh) {
     const int pairs = nq * d;
     int team = (int)blockDim.x / pairs;
-    if (team > 32) team = 32;
+    if (team > 64) team = 64;
     if (team < 1) team = 1;
     for (int idx = threadIdx.x; idx < pairs * team; idx += blockDim.x) {
-        int pr = idx / team, s = idx - pr * team;
+        int pr = idx / team, sidx = idx - pr * team;
         int q = pr / d, c = pr - q * d;
-        const double* base = part + (size_t)q * nblk * d + c;
+        const double* base = src + (size_t)q * stride * d + c;
         double acc = 0.0;
-        for (int b = s; b < nblk; b += team) acc += base[(size_t)b * d];
+#pragma unroll 4
+        for (int b = b0 + sidx; b < b1; b += team) acc += base[(size_t)b * d];
         sh[idx] = acc;
     }
     __syncthreads();
@@ -163,39 +198,50 @@ __device__ void reduce_parts(const double* part, int nblk, int d, int nq, double
     __syncthreads();
 }
 
+// Reduce the partials of segment sg into out[q * d + c] (nq quantities of d
+// values).  With a single segment the per-XCD-group partials are summed.
+template <typename T>
+__device__ __forceinline__ void seg_sums(const KA<T>& a, int sg, int nq, int d, double* out, double* sh, bool grouped) {
+    if (grouped) reduce_range(a.gpart, kNumXcd, 0, kNumXcd, d, nq, out, sh);
+    else reduce_range(a.part, a.nblk, a.seg_blk0[sg], a.seg_blk0[sg + 1], d, nq, out, sh);
+}
+
 // ---------------------------------------------------------------------------
 // Phases (each called by every workgroup for its rows)
 // ---------------------------------------------------------------------------
 
-// PH_E0 / PH_EU / PH_R0 / PH_RHS.  For every owned element (i, c):
+// Residual phases.  For every owned element (i, c):
 //   EU : t = w (y_i - y_j) + b_s ; d_s = Shrink(t, 1/lambda) ; b_s = t - d_s   (Eqs. 9, 10)
 //        rhs = lambda/2 sum_s w (d_s - b_s) + r/2 D^{1/2} (P - B)               (Eq. 13)
 //   E0 : rhs = r/2 D^{1/2} (P - B)                   (b = d = 0 at the first inner step)
 //   R0 : rhs from the stored rhs
 //   RHS: rhs from the stored b and d
-//   then (unless RHS) r = rhs - A x, with the FP64 partials of r^T z, r^T r, rhs^T rhs.
-template <typename T>
-__device__ void ph_residual(const KA<T>& a, int lb, int mode, int do_r0, double* sh) {
+// then (unless RHS) r0 = rhs - A x, with FP64 partials of rhs^T rhs and r0^T r0.
+template <int KC = 0, typename T>
+__device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, int do_r0, int b_zero, double* sh) {
     const int d = a.d, R = a.R, t = threadIdx.x;
-    int rb, re;
-    row_range(lb, a.nblk, a.n, rb, re);
-    double acc[3] = {0.0, 0.0, 0.0};
+    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    double acc[2] = {0.0, 0.0};
+    T* r0 = a.rb[0];
     if (t < R * d) {
         const int rl = t / d, c = t - rl * d;
         for (int i = rb + rl; i < re; i += R) {
             const size_t e = (size_t)i * d + c;
-            const int s0 = a.rowptr[i], s1 = a.rowptr[i + 1];
+            int s0, cnt, st;
+            row_slots<KC>(a, i, s0, cnt, st);
             const T xi = a.x[e];
             T accR = T(0), accA = T(0);
             if (mode == PH_EU) {
                 const T yi = a.Y[e];
-                for (int s = s0; s < s1; ++s) {
-                    const int j = a.col[s];
-                    const T ww = a.w[s];
+#pragma unroll(KC > 0 ? 4 : 2)
+                for (int k = 0; k < cnt; ++k) {
+                    const int s = s0 + k * st;
+                    const int j = a.scol[s];
+                    const T ww = a.sw[s];
                     const size_t ej = (size_t)j * d + c;
                     const T yj = a.Y[ej];
                     const size_t es = (size_t)s * d + c;
-                    const T bold = a.b_zero ? T(0) : a.bs[es];
+                    const T bold = b_zero ? T(0) : a.bs[es];
                     const T tv = fma_t(ww, yi - yj, bold);
                     const T dv = shrink(tv, a.gamma);
                     const T bn = tv - dv;
@@ -205,15 +251,18 @@ __device__ void ph_residual(const KA<T>& a, int lb, int mode, int do_r0, double*
                     if (do_r0) accA = fma_t(mul_t(ww, ww), a.x[ej], accA);
                 }
             } else if (mode == PH_RHS) {
-                for (int s = s0; s < s1; ++s) {
+#pragma unroll(KC > 0 ? 4 : 2)
+                for (int k = 0; k < cnt; ++k) {
+                    const int s = s0 + k * st;
                     const size_t es = (size_t)s * d + c;
-                    accR = fma_t(a.w[s], a.ds[es] - a.bs[es], accR);
+                    accR = fma_t(a.sw[s], a.ds[es] - a.bs[es], accR);
                 }
             } else if (do_r0) {
-                for (int s = s0; s < s1; ++s) {
-                    const int j = a.col[s];
-                    const T ww = a.w[s];
-                    accA = fma_t(mul_t(ww, ww), a.x[(size_t)j * d + c], accA);
+#pragma unroll(KC > 0 ? 4 : 2)
+                for (int k = 0; k < cnt; ++k) {
+                    const int s = s0 + k * st;
+                    const T ww = a.sw[s];
+                    accA = fma_t(mul_t(ww, ww), a.x[(size_t)a.scol[s] * d + c], accA);
                 }
             }
             T rhs;
@@ -227,114 +276,140 @@ __device__ void ph_residual(const KA<T>& a, int lb, int mode, int do_r0, double*
             if (do_r0) {
                 const T ax = fma_t(a.diagA[i], xi, -mul_t(a.c_off, accA));
                 const T rv = rhs - ax;
-                a.r[e] = rv;
-                const T zv = mul_t(a.invdiag[i], rv);
-                acc[0] += (double)rv * (double)zv;
+                r0[e] = rv;
+                acc[0] += (double)rhs * (double)rhs;
                 acc[1] += (double)rv * (double)rv;
-                acc[2] += (double)rhs * (double)rhs;
             }
         }
     }
-    if (do_r0) block_partials<3>(acc, sh, d, R, a.part, a.nblk, lb);
+    if (do_r0) block_partials<2>(acc, sh, d, R, a.part, a.nblk, lb);
 }
 
-// PH_A: p_new = z + beta p_old (z = r / diag A), q = A p_new, partial p^T q.
-// Neighbour values of p_new are recomputed from r and p_old, bit-identical to
-// what their owner stores, so no separate p-update pass is needed.
-template <typename T>
-__device__ void ph_a(const KA<T>& a, int lb, double* sh) {
+// PH_W0: w0 = A u0 with u0 = r0 / diag(A); partials of r0.u0 and w0.u0.
+template <int KC = 0, typename T>
+__device__ __forceinline__ void ph_w0(const KA<T>& a, int lb, double* sh) {
     const int d = a.d, R = a.R, t = threadIdx.x;
-    int rb, re;
-    row_range(lb, a.nblk, a.n, rb, re);
-    const int it = ld_flag(&a.S->it);
-    const bool first = (it == 0);
-    T* pnew = (it & 1) ? a.pB : a.pA;
-    const T* pold = (it & 1) ? a.pA : a.pB;
-    double acc[1] = {0.0};
-    if (t < R * d) {
-        const int rl = t / d, c = t - rl * d;
-        const T beta = (T)a.S->beta[c];
-        for (int i = rb + rl; i < re; i += R) {
-            const size_t e = (size_t)i * d + c;
-            const T zi = zval(a, i, e);
-            const T pi = first ? zi : fma_t(beta, pold[e], zi);
-            const int s0 = a.rowptr[i], s1 = a.rowptr[i + 1];
-            T accA = T(0);
-            for (int s = s0; s < s1; ++s) {
-                const int j = a.col[s];
-                const T ww = a.w[s];
-                const size_t ej = (size_t)j * d + c;
-                const T zj = zval(a, j, ej);
-                const T pj = first ? zj : fma_t(beta, pold[ej], zj);
-                accA = fma_t(mul_t(ww, ww), pj, accA);
-            }
-            const T qi = fma_t(a.diagA[i], pi, -mul_t(a.c_off, accA));
-            pnew[e] = pi;
-            a.q[e] = qi;
-            acc[0] += (double)pi * (double)qi;
-        }
-    }
-    block_partials<1>(acc, sh, d, R, a.part, a.nblk, lb);
-}
-
-// PH_B: x += alpha p, r -= alpha q, partials of r^T z and r^T r.
-template <typename T>
-__device__ void ph_b(const KA<T>& a, int lb, double* sh) {
-    const int d = a.d, R = a.R, t = threadIdx.x;
-    int rb, re;
-    row_range(lb, a.nblk, a.n, rb, re);
-    const int it = ld_flag(&a.S->it);
-    const T* p = (it & 1) ? a.pB : a.pA;
+    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const T* r = a.rb[0];
+    T* w = a.wb[0];
     double acc[2] = {0.0, 0.0};
     if (t < R * d) {
         const int rl = t / d, c = t - rl * d;
-        const T alpha = (T)a.S->alpha[c];
         for (int i = rb + rl; i < re; i += R) {
             const size_t e = (size_t)i * d + c;
-            const T xv = fma_t(alpha, p[e], a.x[e]);
-            const T rv = fma_t(-alpha, a.q[e], a.r[e]);
-            a.x[e] = xv;
-            a.r[e] = rv;
-            const T zv = mul_t(a.invdiag[i], rv);
-            acc[0] += (double)rv * (double)zv;
-            acc[1] += (double)rv * (double)rv;
+            int s0, cnt, st;
+            row_slots<KC>(a, i, s0, cnt, st);
+            const T ri = r[e];
+            const T ui = mul_t(a.invdiag[i], ri);
+            T accA = T(0);
+#pragma unroll(KC > 0 ? 4 : 2)
+            for (int k = 0; k < cnt; ++k) {
+                const int s = s0 + k * st;
+                const int j = a.scol[s];
+                const T ww = a.sw[s];
+                const T uj = mul_t(a.invdiag[j], r[(size_t)j * d + c]);
+                accA = fma_t(mul_t(ww, ww), uj, accA);
+            }
+            const T wi = fma_t(a.diagA[i], ui, -mul_t(a.c_off, accA));
+            w[e] = wi;
+            acc[0] += (double)ri * (double)ui;
+            acc[1] += (double)wi * (double)ui;
         }
     }
     block_partials<2>(acc, sh, d, R, a.part, a.nblk, lb);
 }
 
-// PH_ZERO: x_c = 0 for columns with a zero right-hand side
-template <typename T>
-__device__ void ph_zero(const KA<T>& a, int lb) {
+// PH_IT: CG iteration i = S->it with alpha_i, beta_i per (segment, column):
+//   p_i = u_i + beta p_{i-1}, s_i = w_i + beta s_{i-1}, x += alpha p_i,
+//   r_{i+1} = r_i - alpha s_i, u_{i+1} = r_{i+1} / diag(A), w_{i+1} = A u_{i+1};
+// partials of r.u, w.u and r.r of iteration i+1.
+template <int KC = 0, typename T>
+__device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh) {
     const int d = a.d, R = a.R, t = threadIdx.x;
-    int rb, re;
-    row_range(lb, a.nblk, a.n, rb, re);
+    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const int it = ld_flag(&a.S->it);
+    const bool first = (it == 0);
+    const int cur = it & 1, nxt = cur ^ 1;
+    const T* r = a.rb[cur];
+    const T* w = a.wb[cur];
+    const T* sp = a.sb[cur];     // s_{i-1}
+    T* rn = a.rb[nxt];
+    T* wn = a.wb[nxt];
+    T* sn = a.sb[nxt];           // s_i
+    const int sg = a.blk_seg[lb];
+    double acc[3] = {0.0, 0.0, 0.0};
     if (t < R * d) {
         const int rl = t / d, c = t - rl * d;
-        if (!a.S->zero[c]) return;
+        const int ci = sg * d + c;
+        const T alpha = (T)a.cs.alpha[ci];
+        const T beta = (T)a.cs.beta[ci];
+        for (int i = rb + rl; i < re; i += R) {
+            const size_t e = (size_t)i * d + c;
+            int s0, cnt, st;
+            row_slots<KC>(a, i, s0, cnt, st);
+            const T inv = a.invdiag[i];
+            const T ri = r[e];
+            const T ui = mul_t(inv, ri);
+            const T pi = first ? ui : fma_t(beta, a.p[e], ui);
+            const T si = cg_s(first, beta, sp[e], w[e]);
+            const T rn_i = cg_r(alpha, si, ri);
+            const T un_i = mul_t(inv, rn_i);
+            T accA = T(0);
+#pragma unroll(KC > 0 ? 4 : 2)
+            for (int k = 0; k < cnt; ++k) {
+                const int s = s0 + k * st;
+                const int j = a.scol[s];
+                const T ww = a.sw[s];
+                const size_t ej = (size_t)j * d + c;
+                const T sj = cg_s(first, beta, sp[ej], w[ej]);
+                const T uj = mul_t(a.invdiag[j], cg_r(alpha, sj, r[ej]));
+                accA = fma_t(mul_t(ww, ww), uj, accA);
+            }
+            const T wn_i = fma_t(a.diagA[i], un_i, -mul_t(a.c_off, accA));
+            a.p[e] = pi;
+            sn[e] = si;
+            a.x[e] = fma_t(alpha, pi, a.x[e]);
+            rn[e] = rn_i;
+            wn[e] = wn_i;
+            acc[0] += (double)rn_i * (double)un_i;
+            acc[1] += (double)wn_i * (double)un_i;
+            acc[2] += (double)rn_i * (double)rn_i;
+        }
+    }
+    block_partials<3>(acc, sh, d, R, a.part, a.nblk, lb);
+}
+
+// PH_ZERO: x_c = 0 for columns with a zero right-hand side
+template <typename T>
+__device__ __forceinline__ void ph_zero(const KA<T>& a, int lb) {
+    const int d = a.d, R = a.R, t = threadIdx.x;
+    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    if (t < R * d) {
+        const int rl = t / d, c = t - rl * d;
+        if (!a.cs.zero[a.blk_seg[lb] * d + c]) return;
         for (int i = rb + rl; i < re; i += R) a.x[(size_t)i * d + c] = T(0);
     }
+}
+
+__device__ __forceinline__ void pair_of(int k, int d, int& pa, int& pb) {
+    int r = 0, off = 0;
+    while (off + (d - r) <= k) { off += d - r; ++r; }
+    pa = r;
+    pb = r + (k - off);
 }
 
 // PH_GRAM: FP64 Gram matrix of Z (mode 0: Z = D^{1/2} Y + B; mode 1: Z = D^{1/2} Y),
 // upper triangle packed, one partial per workgroup.
 template <typename T>
-__device__ void ph_gram(const KA<T>& a, int lb, int mode, double* sh) {
+__device__ __forceinline__ void ph_gram(const KA<T>& a, int lb, int mode, double* sh) {
     const int d = a.d, R = a.R, t = threadIdx.x;
     const int npair = d * (d + 1) / 2;
-    int rb, re;
-    row_range(lb, a.nblk, a.n, rb, re);
+    const int rb = a.row0[lb], re = a.row0[lb + 1];
     double* zt = sh;                  // R x d staged rows
-    // pair decode (row-major upper triangle): k -> (pa, pb), pa <= pb
     int pa[2] = {0, 0}, pb[2] = {0, 0};
     for (int h = 0; h < 2; ++h) {
         int k = t + h * (int)blockDim.x;
-        if (k < npair) {
-            int r = 0, off = 0;
-            while (off + (d - r) <= k) { off += d - r; ++r; }
-            pa[h] = r;
-            pb[h] = r + (k - off);
-        }
+        if (k < npair) pair_of(k, d, pa[h], pb[h]);
     }
     double acc[2] = {0.0, 0.0};
     for (int base = rb; base < re; base += R) {
@@ -366,13 +441,13 @@ __device__ void ph_gram(const KA<T>& a, int lb, int mode, double* sh) {
 // PH_APPLY: mode 0 (P-update): P = Z T, B = Z - P with Z = D^{1/2} Y + B;
 //           mode 1 (initial orthonormalisation): Y <- Y T, P = D^{1/2} Y, B = 0.
 template <typename T>
-__device__ void ph_apply(const KA<T>& a, int lb, int mode, double* sh) {
+__device__ __forceinline__ void ph_apply(const KA<T>& a, int lb, int mode, double* sh) {
     const int d = a.d, R = a.R, t = threadIdx.x;
-    int rb, re;
-    row_range(lb, a.nblk, a.n, rb, re);
+    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const double* Tg = a.Tm + (size_t)a.blk_seg[lb] * kMaxD * kMaxD;
     double* Ts = sh;                  // d x d
     double* zt = sh + kMaxD * kMaxD;  // R x d
-    for (int k = t; k < d * d; k += blockDim.x) Ts[k] = a.S->T[(k / d) * kMaxD + (k % d)];
+    for (int k = t; k < d * d; k += blockDim.x) Ts[k] = Tg[(k / d) * kMaxD + (k % d)];
     for (int base = rb; base < re; base += R) {
         int rows = min(R, re - base);
         __syncthreads();
@@ -405,84 +480,110 @@ __device__ void ph_apply(const KA<T>& a, int lb, int mode, double* sh) {
 }
 
 // ---------------------------------------------------------------------------
-// Finalisers (one workgroup, after every workgroup has written its partials)
+// Finalisers (one workgroup, after every workgroup has written its partials).
+// 'grouped' means the per-XCD-group partials are already summed (one segment).
 // ---------------------------------------------------------------------------
 
-// after PH_E0 / PH_EU / PH_R0: start of a PCG solve
+// after a residual phase: ||rhs||^2, ||r0||^2, convergence at iteration 0
 template <typename T>
-__device__ void fin_init(const KA<T>& a, double* sh) {
+__device__ __forceinline__ void fin_res(const KA<T>& a, double* sh, bool grouped) {
     const int d = a.d;
     double* out = sh + 1024;
-    reduce_parts(a.part, a.nblk, d, 3, out, sh);
-    if (threadIdx.x == 0) {
-        int any = 0;
-        for (int c = 0; c < d; ++c) {
-            double rz = out[c], rr = out[d + c], bb = out[2 * d + c];
-            a.S->rho[c] = rz;
-            a.S->rr[c] = rr;
-            a.S->bnorm2[c] = bb;
-            a.S->beta[c] = 0.0;
-            a.S->alpha[c] = 0.0;
-            a.S->iters[c] = 0;
+    __shared__ int s_any;
+    if (threadIdx.x == 0) s_any = 0;
+    for (int sg = 0; sg < a.nseg; ++sg) {
+        seg_sums(a, sg, 2, d, out, sh, grouped);
+        if (threadIdx.x < d) {
+            const int c = threadIdx.x, ci = sg * d + c;
+            double bb = out[c], rr = out[d + c];
+            a.cs.bnorm2[ci] = bb;
+            a.cs.rr[ci] = rr;
+            a.cs.iters[ci] = 0;
+            a.cs.alpha[ci] = 0.0;
+            a.cs.beta[ci] = 0.0;
             int z = (bb == 0.0);
-            a.S->zero[c] = z;
+            a.cs.zero[ci] = z;
             int act = !z && (rr > a.tol2 * bb);
-            a.S->active[c] = act;
-            any |= act;
+            a.cs.active[ci] = act;
+            if (act) atomicOr(&s_any, 1);
         }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
         a.S->it = 0;
-        a.S->done = !any;
+        a.S->done = !s_any;
     }
 }
 
-// after PH_A: alpha = rho / p^T q per active column; breakdown check
+// after PH_W0: alpha0 = gamma0 / delta0
 template <typename T>
-__device__ void fin_a(const KA<T>& a, double* sh) {
+__device__ __forceinline__ void fin_w0(const KA<T>& a, double* sh, bool grouped) {
     const int d = a.d;
     double* out = sh + 1024;
-    reduce_parts(a.part, a.nblk, d, 1, out, sh);
-    if (threadIdx.x == 0) {
-        int bad = 0;
-        for (int c = 0; c < d; ++c) {
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    for (int sg = 0; sg < a.nseg; ++sg) {
+        seg_sums(a, sg, 2, d, out, sh, grouped);
+        if (threadIdx.x < d) {
+            const int c = threadIdx.x, ci = sg * d + c;
+            double g = out[c], dl = out[d + c];
+            a.cs.gamma[ci] = g;
             double al = 0.0;
-            if (a.S->active[c]) {
-                double pq = out[c];
-                al = a.S->rho[c] / pq;
-                if (!(pq > 0.0) || !isfinite(al)) { bad = 1; al = 0.0; }
+            if (a.cs.active[ci]) {
+                al = g / dl;
+                if (!(dl > 0.0) || !(g > 0.0) || !isfinite(al)) { s_bad = 1; al = 0.0; }
             }
-            a.S->alpha[c] = al;
+            a.cs.alpha[ci] = al;
+            a.cs.beta[ci] = 0.0;
         }
-        if (bad) {
-            a.S->status = PFE_E_NOT_SPD;
-            a.S->done = 1;
-        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && s_bad) {
+        a.S->status = PFE_E_NOT_SPD;
+        a.S->done = 1;
     }
 }
 
-// after PH_B: beta, convergence, iteration count, statistics
+// after PH_IT: convergence, beta, alpha of the next iteration, statistics
 template <typename T>
-__device__ void fin_b(const KA<T>& a, double* sh) {
+__device__ __forceinline__ void fin_it(const KA<T>& a, double* sh, bool grouped) {
     const int d = a.d;
     double* out = sh + 1024;
-    reduce_parts(a.part, a.nblk, d, 2, out, sh);
-    if (threadIdx.x == 0) {
-        int any = 0;
-        for (int c = 0; c < d; ++c) {
-            int act = a.S->active[c];
-            double rz = out[c], rr = out[d + c];
+    __shared__ int s_any, s_bad;
+    if (threadIdx.x == 0) { s_any = 0; s_bad = 0; }
+    for (int sg = 0; sg < a.nseg; ++sg) {
+        seg_sums(a, sg, 3, d, out, sh, grouped);
+        if (threadIdx.x < d) {
+            const int c = threadIdx.x, ci = sg * d + c;
+            int act = a.cs.active[ci];
             if (act) {
-                a.S->beta[c] = rz / a.S->rho[c];
-                a.S->rho[c] = rz;
-                a.S->rr[c] = rr;
-                a.S->iters[c] += 1;
-                act = rr > a.tol2 * a.S->bnorm2[c];
-                if (!isfinite(rr)) { a.S->status = PFE_E_NOT_SPD; act = 0; }
-            } else {
-                a.S->beta[c] = 0.0;
+                double g = out[c], dl = out[d + c], rr = out[2 * d + c];
+                a.cs.iters[ci] += 1;
+                a.cs.rr[ci] = rr;
+                act = rr > a.tol2 * a.cs.bnorm2[ci];
+                if (!isfinite(rr)) { s_bad = 1; act = 0; }
+                if (act) {
+                    double be = g / a.cs.gamma[ci];
+                    double den = dl - be * g / a.cs.alpha[ci];
+                    double al = g / den;
+                    if (!(den > 0.0) || !isfinite(al) || !isfinite(be)) { s_bad = 1; act = 0; al = 0.0; be = 0.0; }
+                    a.cs.beta[ci] = be;
+                    a.cs.alpha[ci] = al;
+                    a.cs.gamma[ci] = g;
+                }
             }
-            a.S->active[c] = act;
-            any |= act;
+            if (!act) {
+                a.cs.alpha[ci] = 0.0;
+                a.cs.beta[ci] = 0.0;
+            }
+            a.cs.active[ci] = act;
+            if (act) atomicOr(&s_any, 1);
         }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int any = s_any;
+        if (s_bad) a.S->status = PFE_E_NOT_SPD;
         int it = a.S->it + 1;
         a.S->it = it;
         if (any && it >= a.maxit) {
@@ -493,15 +594,15 @@ __device__ void fin_b(const KA<T>& a, double* sh) {
     }
 }
 
-// called by thread 0 when a solve ends: accumulate statistics
+// called by one thread when a solve ends: accumulate statistics
 template <typename T>
-__device__ void solve_stats(const KA<T>& a) {
-    int d = a.d, mx = 0;
+__device__ __forceinline__ void solve_stats(const KA<T>& a) {
+    int mx = 0;
     double rel = 0.0;
-    for (int c = 0; c < d; ++c) {
-        mx = max(mx, a.S->iters[c]);
-        double bb = a.S->bnorm2[c];
-        if (bb > 0.0) rel = fmax(rel, sqrt(a.S->rr[c] / bb));
+    for (int ci = 0; ci < a.nseg * a.d; ++ci) {
+        mx = max(mx, a.cs.iters[ci]);
+        double bb = a.cs.bnorm2[ci];
+        if (bb > 0.0) rel = fmax(rel, sqrt(a.cs.rr[ci] / bb));
     }
     a.S->solves += 1;
     a.S->iters_total += mx;
@@ -510,32 +611,29 @@ __device__ void solve_stats(const KA<T>& a) {
     a.S->relres_max = fmax(a.S->relres_max, rel);
 }
 
-// d x d factor of the P-update, FP64, one workgroup.
-//   G = Z^T Z (sum of the packed partials), Cholesky G = L L^T (rank check),
+// d x d factor of the P-update for segment sg, FP64, one workgroup.
+//   G = Z^T Z (packed, in gsum), Cholesky G = L L^T (rank check),
 //   CHOL / init: T = L^{-T}  (Z T = Z R^{-1}, R = L^T);
 //   POLAR: T = G^{-1/2} by the coupled Newton-Schulz iteration on G / s,
 //   s = ||G||_inf, so that Z T is the orthogonal polar factor of Z.
+// LDS use: sh[1024, 4608).
 template <typename T>
-__device__ void fin_gram(const KA<T>& a, int mode, double* sh) {
+__device__ __forceinline__ void factor_gram(const KA<T>& a, int sg, int mode, const double* gsum, double* sh) {
     const int d = a.d, t = threadIdx.x, nb = blockDim.x;
     const int npair = d * (d + 1) / 2;
-    // layout in sh: [0,1024) reduce scratch, G at 1024, L at 2048, M0 at 2048+1024...
     double* G = sh + 1024;
     double* L = sh + 2048;
     double* Ym = sh + 3072;
-    double* Zm = sh + 3072 + 512;   // only for d <= 22 (d*d <= 512); larger d uses Gm
+    double* Zm = sh + 3072 + 512;
     double* red = sh + 4096;
-    // packed partials: part[lb * npair + k], summed in workgroup order
-    reduce_parts(a.part, a.nblk, npair, 1, L, sh);
+    double* Tout = a.Tm + (size_t)sg * kMaxD * kMaxD;
     for (int k = t; k < npair; k += nb) {
-        int r = 0, off = 0;
-        while (off + (d - r) <= k) { off += d - r; ++r; }
-        int cc = r + (k - off);
-        G[r * d + cc] = L[k];
-        G[cc * d + r] = L[k];
+        int r, cc;
+        pair_of(k, d, r, cc);
+        G[r * d + cc] = gsum[k];
+        G[cc * d + r] = gsum[k];
     }
     __syncthreads();
-    // Cholesky (lower), on a copy in L
     for (int k = t; k < d * d; k += nb) L[k] = G[k];
     __shared__ int s_bad;
     if (t == 0) s_bad = 0;
@@ -576,101 +674,108 @@ __device__ void fin_gram(const KA<T>& a, int mode, double* sh) {
         __syncthreads();
         for (int idx = t; idx < d * d; idx += nb) {
             int r = idx / d, c = idx - r * d;
-            a.S->T[r * kMaxD + c] = Ym[c * kMaxD + r];
-        }
-    } else {
-        // coupled Newton-Schulz for (G/s)^{-1/2}
-        __shared__ double s_scale;
-        if (t == 0) {
-            double s = 0.0;
-            for (int i = 0; i < d; ++i) {
-                double rs = 0.0;
-                for (int j = 0; j < d; ++j) rs += fabs(G[i * d + j]);
-                s = fmax(s, rs);
-            }
-            s_scale = s;
+            Tout[r * kMaxD + c] = Ym[c * kMaxD + r];
         }
         __syncthreads();
-        const double s = s_scale;
-        double* Yk = Ym;          // d x d, stride d
-        double* Zk = L;           // reuse L storage (Cholesky no longer needed)
-        double* Mk = G;           // reuse G storage
-        double* Wk = Zm;          // scratch
-        const int dd = d * d;
-        double* big = sh;         // when d*d > 512, scratch lives in the reduce area
-        if (dd > 512) Wk = big;
-        for (int k = t; k < dd; k += nb) {
-            Yk[k] = G[k] / s;
-            Zk[k] = ((k / d) == (k % d)) ? 1.0 : 0.0;
-        }
-        __syncthreads();
-        __shared__ double s_err;
-        double prev = INFINITY;
-        for (int iter = 0; iter < 100; ++iter) {
-            // M = Z Y
-            double emax = 0.0;
-            for (int k = t; k < dd; k += nb) {
-                int i = k / d, j = k - i * d;
-                double acc = 0.0;
-                for (int m = 0; m < d; ++m) acc += Zk[i * d + m] * Yk[m * d + j];
-                Wk[k] = acc;
-                emax = fmax(emax, fabs(acc - ((i == j) ? 1.0 : 0.0)));
-            }
-            red[t] = emax;
-            __syncthreads();
-            if (t == 0) {
-                double e = 0.0;
-                for (int k = 0; k < nb; ++k) e = fmax(e, red[k]);
-                s_err = e;
-            }
-            __syncthreads();
-            // stop at rounding level: tiny, or no longer shrinking quadratically
-            if (s_err < 1e-14 || !isfinite(s_err) || (s_err < 1e-11 && s_err > 0.25 * prev)) break;
-            prev = s_err;
-            // T = (3 I - M) / 2, kept in Mk
-            for (int k = t; k < dd; k += nb) {
-                int i = k / d, j = k - i * d;
-                Mk[k] = 0.5 * (((i == j) ? 3.0 : 0.0) - Wk[k]);
-            }
-            __syncthreads();
-            // Y <- Y T (into Wk), Z <- T Z (into Yk after copy)
-            for (int k = t; k < dd; k += nb) {
-                int i = k / d, j = k - i * d;
-                double acc = 0.0;
-                for (int m = 0; m < d; ++m) acc += Yk[i * d + m] * Mk[m * d + j];
-                Wk[k] = acc;
-            }
-            __syncthreads();
-            for (int k = t; k < dd; k += nb) Yk[k] = Wk[k];
-            __syncthreads();
-            for (int k = t; k < dd; k += nb) {
-                int i = k / d, j = k - i * d;
-                double acc = 0.0;
-                for (int m = 0; m < d; ++m) acc += Mk[i * d + m] * Zk[m * d + j];
-                Wk[k] = acc;
-            }
-            __syncthreads();
-            for (int k = t; k < dd; k += nb) Zk[k] = Wk[k];
-            __syncthreads();
-        }
-        const double is = 1.0 / sqrt(s);
-        for (int k = t; k < dd; k += nb) {
-            int r = k / d, c = k - r * d;
-            a.S->T[r * kMaxD + c] = Zk[k] * is;
-        }
-        if (t == 0 && !(s_err < 1e-10)) {
-            a.S->ortho_ok = 0;
-            a.S->status = PFE_E_RANK;
-            return;
-        }
+        return;
     }
-    if (t == 0) a.S->ortho_ok = 1;
+    // coupled Newton-Schulz for (G/s)^{-1/2}
+    __shared__ double s_scale, s_err;
+    if (t == 0) {
+        double s = 0.0;
+        for (int i = 0; i < d; ++i) {
+            double rs = 0.0;
+            for (int j = 0; j < d; ++j) rs += fabs(G[i * d + j]);
+            s = fmax(s, rs);
+        }
+        s_scale = s;
+    }
+    __syncthreads();
+    const double s = s_scale;
+    const int dd = d * d;
+    double* Yk = Ym;
+    double* Zk = L;           // the Cholesky factor is no longer needed
+    double* Mk = G;
+    double* Wk = (dd > 512) ? sh : Zm;
+    for (int k = t; k < dd; k += nb) {
+        Yk[k] = G[k] / s;
+        Zk[k] = ((k / d) == (k % d)) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    double prev = INFINITY;
+    for (int iter = 0; iter < 100; ++iter) {
+        double emax = 0.0;
+        for (int k = t; k < dd; k += nb) {
+            int i = k / d, j = k - i * d;
+            double acc = 0.0;
+            for (int m = 0; m < d; ++m) acc += Zk[i * d + m] * Yk[m * d + j];
+            Wk[k] = acc;
+            emax = fmax(emax, fabs(acc - ((i == j) ? 1.0 : 0.0)));
+        }
+        red[t] = emax;
+        __syncthreads();
+        if (t == 0) {
+            double e = 0.0;
+            for (int k = 0; k < nb; ++k) e = fmax(e, red[k]);
+            s_err = e;
+        }
+        __syncthreads();
+        const double err = s_err;
+        // stop at rounding level: tiny, or no longer shrinking quadratically
+        if (err < 1e-14 || !isfinite(err) || (err < 1e-11 && err > 0.25 * prev)) break;
+        prev = err;
+        for (int k = t; k < dd; k += nb) {
+            int i = k / d, j = k - i * d;
+            Mk[k] = 0.5 * (((i == j) ? 3.0 : 0.0) - Wk[k]);
+        }
+        __syncthreads();
+        for (int k = t; k < dd; k += nb) {
+            int i = k / d, j = k - i * d;
+            double acc = 0.0;
+            for (int m = 0; m < d; ++m) acc += Yk[i * d + m] * Mk[m * d + j];
+            Wk[k] = acc;
+        }
+        __syncthreads();
+        for (int k = t; k < dd; k += nb) Yk[k] = Wk[k];
+        __syncthreads();
+        for (int k = t; k < dd; k += nb) {
+            int i = k / d, j = k - i * d;
+            double acc = 0.0;
+            for (int m = 0; m < d; ++m) acc += Mk[i * d + m] * Zk[m * d + j];
+            Wk[k] = acc;
+        }
+        __syncthreads();
+        for (int k = t; k < dd; k += nb) Zk[k] = Wk[k];
+        __syncthreads();
+    }
+    const double is = 1.0 / sqrt(s);
+    for (int k = t; k < dd; k += nb) {
+        int r = k / d, c = k - r * d;
+        Tout[r * kMaxD + c] = Zk[k] * is;
+    }
+    if (t == 0 && !(s_err < 1e-10)) {
+        a.S->ortho_ok = 0;
+        a.S->status = PFE_E_RANK;
+    }
+    __syncthreads();
+}
+
+// after PH_GRAM: per-segment Gram sums and their factors
+template <typename T>
+__device__ __forceinline__ void fin_gram(const KA<T>& a, int mode, double* sh, bool grouped) {
+    const int npair = a.d * (a.d + 1) / 2;
+    __shared__ double gsum[kMaxD * (kMaxD + 1) / 2];
+    if (threadIdx.x == 0) a.S->ortho_ok = 1;
+    for (int sg = 0; sg < a.nseg; ++sg) {
+        if (grouped) reduce_range(a.gpart, kNumXcd, 0, kNumXcd, npair, 1, gsum, sh);
+        else reduce_range(a.part, a.nblk, a.seg_blk0[sg], a.seg_blk0[sg + 1], npair, 1, gsum, sh);
+        factor_gram(a, sg, mode, gsum, sh);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Grid-wide synchronisation
 // ---------------------------------------------------------------------------
-
 // Fences: one thread per workgroup publishes and acquires.  __syncthreads()
 // completes the stores of every wave of the workgroup (the vector L1 is
 // write-through), so thread 0's agent-scope release covers them, and its
@@ -690,55 +795,98 @@ __device__ bool last_block(unsigned* counter, unsigned nblk) {
     return s_last;
 }
 
-// Persistent path: barrier over all co-resident workgroups; the last to
-// arrive runs fin() before releasing the others.  Waiters poll with relaxed
-// loads (no cache invalidation per poll) and acquire once.  The wait is
+// Persistent path: two-level barrier over all co-resident workgroups.
+// Workgroups arrive on the counter of their XCD group (blockIdx % 8, one
+// 128-byte line each); the last of a group optionally pre-reduces the group's
+// partials (gfin), then arrives on the top counter; the last group leader runs
+// fin() and bumps the generation word that everybody else polls with relaxed
+// loads (no cache invalidation per poll) before one acquire.  The wait is
 // bounded: after kSpinLimit polls a workgroup raises abort_flag and the kernel
-// unwinds (every later barrier returns at once).
+// unwinds (every later barrier then times out quickly).
 constexpr long long kSpinLimit = 1ll << 25;
+constexpr int kBarGen = 0;          // bar[0]: generation
+constexpr int kBarTop = 32;         // bar[32]: top counter
+constexpr int kBarGroup = 64;       // bar[64 + 32 g]: group counters
+constexpr int kBarLast = 448;       // bar[448]: last-workgroup counter of the multi-launch path
 
-template <class F>
-__device__ bool grid_sync(unsigned* bar, unsigned nblk, Scal* S, F&& fin) {
-    __shared__ int s_last;
+template <class GF, class F>
+__device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned nblk, Scal* S, GF&& gfin, F&& fin) {
+    __shared__ int s_role;     // 0 waiter, 1 group leader, 2 top leader
     __shared__ int s_abort;
+    const unsigned g = blockIdx.x % kNumXcd;
+    const unsigned gsize = nblk / kNumXcd;
     __syncthreads();
+    unsigned gen = 0;
     if (threadIdx.x == 0) {
         s_abort = 0;
-        unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned prev = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == nblk - 1);
-        if (!s_last) {
-            long long spins = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(1);
-                if ((++spins & 1023) == 0) {
-                    if (ld_flag(&S->abort_flag) || spins > kSpinLimit) {
-                        st_flag(&S->abort_flag, 1);
-                        s_abort = 1;
-                        break;
-                    }
-                }
-            }
+        gen = __hip_atomic_load(&bar[kBarGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned prev = __hip_atomic_fetch_add(&bar[kBarGroup + 32 * g], 1u, __ATOMIC_RELEASE,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        s_role = (prev == gsize - 1) ? 1 : 0;
+        if (s_role) {
             fence_acquire_agent();
+            __hip_atomic_store(&bar[kBarGroup + 32 * g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     __syncthreads();
-    if (s_abort) return false;
-    if (s_last) {
-        fin();
+    if (s_role == 1) {
+        gfin(g);
         __syncthreads();
         if (threadIdx.x == 0) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned prev = __hip_atomic_fetch_add(&bar[kBarTop], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (prev == kNumXcd - 1) {
+                s_role = 2;
+                __hip_atomic_store(&bar[kBarTop], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                s_role = 0;
+            }
         }
         __syncthreads();
     }
-    return true;
+    if (s_role == 2) {
+        fin();
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&bar[kBarGen], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        return true;
+    }
+    if (threadIdx.x == 0) {
+        long long spins = 0;
+        while (__hip_atomic_load(&bar[kBarGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            __builtin_amdgcn_s_sleep(1);
+            if ((++spins & 1023) == 0) {
+                if (ld_flag(&S->abort_flag) || spins > kSpinLimit) {
+                    st_flag(&S->abort_flag, 1);
+                    s_abort = 1;
+                    break;
+                }
+            }
+        }
+        fence_acquire_agent();
+    }
+    __syncthreads();
+    return !s_abort;
 }
 
 struct NoFin {
     __device__ void operator()() const {}
+    __device__ void operator()(unsigned) const {}
 };
+
+// group pre-reduction of nq quantities of m values each (single segment):
+// gpart[(q * 8 + g) * m + c] = sum over the group's workgroups
+template <typename T>
+__device__ __forceinline__ void group_reduce(const KA<T>& a, unsigned g, int m, int nq, double* sh) {
+    const int gs = a.nblk / kNumXcd;
+    double* out = sh + 1024;
+    reduce_range(a.part, a.nblk, (int)g * gs, (int)(g + 1) * gs, m, nq, out, sh);
+    for (int k = threadIdx.x; k < nq * m; k += blockDim.x) {
+        int q = k / m, c = k - q * m;
+        a.gpart[((size_t)q * kNumXcd + g) * m + c] = out[k];
+    }
+    __syncthreads();
+}
 
 // ---------------------------------------------------------------------------
 // Kernels
@@ -749,20 +897,20 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_phase(KA<T> a, int ph, int mode, int do_r0) {
     __shared__ double sh[kSmemDoubles];
     const int lb = logical_block(a.nblk);
-    if ((ph == PH_A || ph == PH_B) && ld_flag(&a.S->done)) return;
+    if ((ph == PH_IT || ph == PH_W0) && ld_flag(&a.S->done)) return;
     switch (ph) {
         case PH_E0: case PH_EU: case PH_R0: case PH_RHS:
-            ph_residual(a, lb, ph, do_r0, sh);
-            if (do_r0 && last_block(a.bar, a.nblk)) fin_init(a, sh);
+            ph_residual(a, lb, ph, do_r0, a.b_zero, sh);
+            if (do_r0 && last_block(a.bar + kBarLast, a.nblk)) fin_res(a, sh, false);
             break;
-        case PH_A:
-            ph_a(a, lb, sh);
-            if (last_block(a.bar, a.nblk)) fin_a(a, sh);
+        case PH_W0:
+            ph_w0(a, lb, sh);
+            if (last_block(a.bar + kBarLast, a.nblk)) fin_w0(a, sh, false);
             break;
-        case PH_B:
-            ph_b(a, lb, sh);
-            if (last_block(a.bar, a.nblk)) {
-                fin_b(a, sh);
+        case PH_IT:
+            ph_it(a, lb, sh);
+            if (last_block(a.bar + kBarLast, a.nblk)) {
+                fin_it(a, sh, false);
                 if (threadIdx.x == 0 && a.S->done) solve_stats(a);
             }
             break;
@@ -771,7 +919,7 @@ __global__ void __launch_bounds__(kBlock) k_phase(KA<T> a, int ph, int mode, int
             break;
         case PH_GRAM:
             ph_gram(a, lb, mode, sh);
-            if (last_block(a.bar, a.nblk)) fin_gram(a, mode, sh);
+            if (last_block(a.bar + kBarLast, a.nblk)) fin_gram(a, mode, sh, false);
             break;
         case PH_APPLY:
             if (!ld_flag(&a.S->ortho_ok)) return;
@@ -790,46 +938,49 @@ struct Plan {
     int l_begin;      // first inner index of the first SOC iteration
     int n_inner;      // inner iterations per SOC iteration
     int n_outer;      // SOC iterations to run
-    int skip_last_eu; // the edge update after the last solve is not needed
 };
 
-// Persistent path: whole SOC iterations in one cooperative launch.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_soc(KA<T> a_in, Plan plan) {
-    KA<T> a = a_in;
+// Persistent path: whole SOC iterations in one cooperative launch (single segment).
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_soc(KA<T> a, Plan plan) {
     __shared__ double sh[kSmemDoubles];
     const int lb = logical_block(a.nblk);
     const unsigned nb = (unsigned)a.nblk;
     Scal* S = a.S;
+    const int d = a.d;
+    const int npair = d * (d + 1) / 2;
+    auto g2 = [&](unsigned g) { group_reduce(a, g, d, 2, sh); };
+    auto g3 = [&](unsigned g) { group_reduce(a, g, d, 3, sh); };
+    auto gg = [&](unsigned g) { group_reduce(a, g, npair, 1, sh); };
     int l0 = plan.l_begin;
     for (int outer = 0; outer < plan.n_outer; ++outer) {
         for (int l = l0; l < plan.n_inner; ++l) {
-            a.b_zero = (l == 1);
-            ph_residual(a, lb, (l == 0) ? PH_E0 : PH_EU, 1, sh);
-            if (!grid_sync(a.bar, nb, S, [&] { fin_init(a, sh); })) return;
+            ph_residual<KC>(a, lb, (l == 0) ? PH_E0 : PH_EU, 1, (l == 1) ? 1 : 0, sh);
+            if (!grid_sync(a.bar, nb, S, g2, [&] { fin_res(a, sh, true); })) return;
+            if (!ld_flag(&S->done)) {
+                ph_w0<KC>(a, lb, sh);
+                if (!grid_sync(a.bar, nb, S, g2, [&] { fin_w0(a, sh, true); })) return;
+            }
             while (!ld_flag(&S->done)) {
-                ph_a(a, lb, sh);
-                if (!grid_sync(a.bar, nb, S, [&] { fin_a(a, sh); })) return;
-                if (ld_flag(&S->done)) break;
-                ph_b(a, lb, sh);
-                if (!grid_sync(a.bar, nb, S, [&] { fin_b(a, sh); })) return;
+                ph_it<KC>(a, lb, sh);
+                if (!grid_sync(a.bar, nb, S, g3, [&] { fin_it(a, sh, true); })) return;
             }
             if (lb == 0 && threadIdx.x == 0) solve_stats(a);
             int any_zero = 0;
-            for (int c = 0; c < a.d; ++c) any_zero |= a.S->zero[c];
+            for (int c = 0; c < d; ++c) any_zero |= a.cs.zero[c];
             if (any_zero) {
                 // columns with a zero right-hand side: x_c = 0
                 ph_zero(a, lb);
-                if (!grid_sync(a.bar, nb, S, NoFin{})) return;
+                if (!grid_sync(a.bar, nb, S, NoFin{}, NoFin{})) return;
             }
         }
         l0 = 0;
         ph_gram(a, lb, 0, sh);
-        if (!grid_sync(a.bar, nb, S, [&] { fin_gram(a, 0, sh); })) return;
-        if (ld_flag(&S->ortho_ok)) ph_apply(a, lb, 0, sh);
-        else return;
-        // P, B of each row are written and read by the same workgroup; the
-        // next barrier (after the first residual phase) orders the rest.
+        if (!grid_sync(a.bar, nb, S, gg, [&] { fin_gram(a, 0, sh, true); })) return;
+        if (!ld_flag(&S->ortho_ok)) return;
+        ph_apply(a, lb, 0, sh);
+        // P and B of a row are written and read by the same workgroup; the
+        // barrier after the next residual phase orders everything else.
     }
 }
 
@@ -837,16 +988,18 @@ template <typename T>
 __global__ void k_spmm(KA<T> a, const T* __restrict__ X, T* __restrict__ Q) {
     const int d = a.d, R = a.R, t = threadIdx.x;
     const int lb = blockIdx.x;
-    int rb, re;
-    row_range(lb, gridDim.x, a.n, rb, re);
+    const int rb = a.row0[lb], re = a.row0[lb + 1];
     if (t >= R * d) return;
     const int rl = t / d, c = t - rl * d;
     for (int i = rb + rl; i < re; i += R) {
         const size_t e = (size_t)i * d + c;
+        int s0, cnt, st;
+        row_slots(a, i, s0, cnt, st);
         T acc = T(0);
-        for (int s = a.rowptr[i]; s < a.rowptr[i + 1]; ++s) {
-            const T ww = a.w[s];
-            acc = fma_t(mul_t(ww, ww), X[(size_t)a.col[s] * d + c], acc);
+        for (int k = 0; k < cnt; ++k) {
+            const int s = s0 + k * st;
+            const T ww = a.sw[s];
+            acc = fma_t(mul_t(ww, ww), X[(size_t)a.scol[s] * d + c], acc);
         }
         Q[e] = fma_t(a.diagA[i], X[e], -mul_t(a.c_off, acc));
     }
@@ -867,25 +1020,39 @@ __global__ void k_diag(int n, const double* __restrict__ degree, const double* _
 
 // per-slot state <-> per-undirected-edge blocks (orientation: lower index minus upper)
 template <typename T>
-__global__ void k_slots_to_edges(int n, int d, const int* __restrict__ rowptr, const int* __restrict__ col,
-                                 const int* __restrict__ eid, const T* __restrict__ s, T* __restrict__ e) {
+__global__ void k_slots_to_edges(KA<T> a, const int* __restrict__ seid, const T* __restrict__ s,
+                                 T* __restrict__ e) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-        if (col[k] <= i) continue;
-        size_t eo = (size_t)eid[k] * d, so = (size_t)k * d;
+    if (i >= a.n) return;
+    const int d = a.d;
+    int s0, cnt, st;
+    row_slots(a, i, s0, cnt, st);
+    for (int k = 0; k < cnt; ++k) {
+        int sl = s0 + k * st;
+        int j = a.scol[sl];
+        if (j <= i || seid[sl] < 0) continue;
+        size_t eo = (size_t)seid[sl] * d, so = (size_t)sl * d;
         for (int c = 0; c < d; ++c) e[eo + c] = s[so + c];
     }
 }
 
 template <typename T>
-__global__ void k_edges_to_slots(int n, int d, const int* __restrict__ rowptr, const int* __restrict__ col,
-                                 const int* __restrict__ eid, const T* __restrict__ e, T* __restrict__ s) {
+__global__ void k_edges_to_slots(KA<T> a, const int* __restrict__ seid, const T* __restrict__ e,
+                                 T* __restrict__ s) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-        size_t eo = (size_t)eid[k] * d, so = (size_t)k * d;
-        bool up = col[k] > i;
+    if (i >= a.n) return;
+    const int d = a.d;
+    int s0, cnt, st;
+    row_slots(a, i, s0, cnt, st);
+    for (int k = 0; k < cnt; ++k) {
+        int sl = s0 + k * st;
+        size_t so = (size_t)sl * d;
+        if (seid[sl] < 0) {
+            for (int c = 0; c < d; ++c) s[so + c] = T(0);
+            continue;
+        }
+        size_t eo = (size_t)seid[sl] * d;
+        bool up = a.scol[sl] > i;
         for (int c = 0; c < d; ++c) s[so + c] = up ? e[eo + c] : -e[eo + c];
     }
 }
@@ -905,22 +1072,16 @@ __global__ void __launch_bounds__(kBlock) k_monitor(KA<T> a) {
     const int d = a.d, R = a.R, t = threadIdx.x;
     const int lb = blockIdx.x;
     const int npair = d * (d + 1) / 2;
-    const int nq = 3 + 2 * npair;     // objective, split^2, P^2, PtP pairs, YDY pairs
-    int rb, re;
-    row_range(lb, a.nblk, a.n, rb, re);
-    double* pz = sh;             // R x d P rows
-    double* yz = sh + kBlock;    // R x d Yhat rows
+    const int nq = 3 + 2 * npair;
+    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    double* pz = sh;
+    double* yz = sh + kBlock;
     double obj = 0.0, spl = 0.0, pp = 0.0;
     double g1[2] = {0.0, 0.0}, g2[2] = {0.0, 0.0};
     int pa[2] = {0, 0}, pb[2] = {0, 0};
     for (int h = 0; h < 2; ++h) {
         int k = t + h * (int)blockDim.x;
-        if (k < npair) {
-            int r = 0, off = 0;
-            while (off + (d - r) <= k) { off += d - r; ++r; }
-            pa[h] = r;
-            pb[h] = r + (k - off);
-        }
+        if (k < npair) pair_of(k, d, pa[h], pb[h]);
     }
     for (int base = rb; base < re; base += R) {
         int rows = min(R, re - base);
@@ -929,11 +1090,14 @@ __global__ void __launch_bounds__(kBlock) k_monitor(KA<T> a) {
             int i = base + rl;
             size_t e = (size_t)i * d + c;
             T yh = mul_t(a.isqrtD[i], a.P[e]);
-            for (int s = a.rowptr[i]; s < a.rowptr[i + 1]; ++s) {
-                int j = a.col[s];
+            int s0, cnt, st;
+            row_slots(a, i, s0, cnt, st);
+            for (int k = 0; k < cnt; ++k) {
+                int s = s0 + k * st;
+                int j = a.scol[s];
                 if (j <= i) continue;
                 T yj = mul_t(a.isqrtD[j], a.P[(size_t)j * d + c]);
-                obj += fabs((double)a.w[s] * ((double)yh - (double)yj));
+                obj += fabs((double)a.sw[s] * ((double)yh - (double)yj));
             }
             double dv = (double)mul_t(a.sqrtD[i], a.Y[e]) - (double)a.P[e];
             spl += dv * dv;
@@ -952,7 +1116,6 @@ __global__ void __launch_bounds__(kBlock) k_monitor(KA<T> a) {
         }
         __syncthreads();
     }
-    // block sums of obj, spl, pp
     double* red = sh + 2 * kBlock;
     red[t] = obj;
     red[kBlock + t] = spl;
@@ -971,33 +1134,28 @@ __global__ void __launch_bounds__(kBlock) k_monitor(KA<T> a) {
             out[3 + npair + k] = g2[h];
         }
     }
-    if (last_block(a.bar, a.nblk)) {
-        for (int k = t; k < nq; k += blockDim.x) {
-            double s = 0.0;
-            for (int b = 0; b < a.nblk; ++b) s += a.part[(size_t)b * nq + k];
-            sh[k] = s;
-        }
-        __syncthreads();
+    if (last_block(a.bar + kBarLast, a.nblk)) {
+        double* tot = sh + 2048;
+        reduce_range(a.part, 1, 0, a.nblk, nq, 1, tot, sh);   // layout part[b * nq + k]
         if (t == 0) {
             double cmax = 0.0, omax = 0.0;
             for (int k = 0; k < npair; ++k) {
-                int r = 0, off = 0;
-                while (off + (d - r) <= k) { off += d - r; ++r; }
-                int cc = r + (k - off);
+                int r, cc;
+                pair_of(k, d, r, cc);
                 double id = (r == cc) ? 1.0 : 0.0;
-                omax = fmax(omax, fabs(sh[3 + k] - id));
-                cmax = fmax(cmax, fabs(sh[3 + npair + k] - id));
+                omax = fmax(omax, fabs(tot[3 + k] - id));
+                cmax = fmax(cmax, fabs(tot[3 + npair + k] - id));
             }
-            a.S->mon[0] = sh[0];
+            a.S->mon[0] = tot[0];
             a.S->mon[1] = cmax;
-            a.S->mon[2] = sqrt(sh[1]) / sqrt(sh[2]);
+            a.S->mon[2] = sqrt(tot[1]) / sqrt(tot[2]);
             a.S->mon[3] = omax;
         }
     }
 }
 
 // |M Y| histogram passes for the exact order statistic (radix select on the
-// bit pattern of the non-negative value, 3 passes of 12 + 12 + 8 bits).
+// bit pattern of the non-negative value).
 template <typename T> struct Bits;
 template <> struct Bits<float> { typedef unsigned U; static constexpr int W = 32; };
 template <> struct Bits<double> { typedef unsigned long long U; static constexpr int W = 64; };
@@ -1015,10 +1173,13 @@ __global__ void k_hist(KA<T> a, int shift, int nbits, unsigned long long prefix,
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
         int i = (int)(e / d), c = (int)(e - (size_t)i * d);
         T yi = a.Y[e];
-        for (int s = a.rowptr[i]; s < a.rowptr[i + 1]; ++s) {
-            int j = a.col[s];
+        int s0, cnt, st;
+        row_slots(a, i, s0, cnt, st);
+        for (int k = 0; k < cnt; ++k) {
+            int s = s0 + k * st;
+            int j = a.scol[s];
             if (j <= i) continue;
-            T v = fabs(mul_t(a.w[s], yi - a.Y[(size_t)j * d + c]));
+            T v = fabs(mul_t(a.sw[s], yi - a.Y[(size_t)j * d + c]));
             U u;
             memcpy(&u, &v, sizeof(T));
             if (pshift < Bits<T>::W && (unsigned long long)(u >> pshift) != prefix) continue;
@@ -1037,22 +1198,39 @@ __global__ void k_hist(KA<T> a, int shift, int nbits, unsigned long long prefix,
 // ===========================================================================
 using namespace pfe;
 
+// Row partition of nblk logical workgroups over the segments (contiguous row
+// ranges; every workgroup inside one segment).
+struct Partition {
+    int nblk = 0;
+    int* row0 = nullptr;      // device, nblk + 1
+    int* blk_seg = nullptr;   // device, nblk
+    int* seg_blk0 = nullptr;  // device, nseg + 1
+};
+
 struct pfe_ctx {
     pfe_graph* g = nullptr;
     pfe_params prm{};
     hipStream_t stream = nullptr;
     int device = 0;
     int esz = 4;
-    int64_t n = 0, d = 0, slots = 0;
+    int64_t n = 0, d = 0;
+    int nseg = 1;
     int inner = 0;           // inner iterations done in the current SOC iteration
-    int nblk = 0;            // workgroups of the multi-launch path
-    int nblk_coop = 0;       // workgroups of the persistent path
+    Partition pm;            // multi-launch partition
+    Partition pc;            // persistent partition (pc.nblk == 0: not available)
     void* Y = nullptr; void* P = nullptr; void* B = nullptr;
     void* bs = nullptr; void* ds = nullptr;
-    void* rhs = nullptr; void* r = nullptr; void* pA = nullptr; void* pB = nullptr; void* q = nullptr;
+    void* rhs = nullptr; void* p = nullptr;
+    void* rb[2] = {nullptr, nullptr};
+    void* wb[2] = {nullptr, nullptr};
+    void* sb[2] = {nullptr, nullptr};
     void* diagA = nullptr; void* invdiag = nullptr; void* sqrtD = nullptr; void* isqrtD = nullptr;
     double* part = nullptr;
-    size_t part_doubles = 0;
+    double* gpart = nullptr;
+    double* Tm = nullptr;
+    double* colbuf = nullptr;
+    int* colint = nullptr;
+    ColState cs{};
     Scal* S = nullptr;
     unsigned* bar = nullptr;
     unsigned* hist = nullptr;
@@ -1060,16 +1238,80 @@ struct pfe_ctx {
 
 namespace {
 
+#define PFE_TRY(x) do { pfe_status s__ = (x); if (s__ != PFE_OK) return s__; } while (0)
+
+pfe_status make_partition(const std::vector<int64_t>& seg_rows, int want_blocks, Partition& P) {
+    // workgroups per segment proportional to its rows (at least one each)
+    const int nseg = (int)seg_rows.size();
+    int64_t n = 0;
+    for (auto r : seg_rows) n += r;
+    std::vector<int> nb(nseg, 1);
+    int total = nseg;
+    if (want_blocks > nseg) {
+        int extra = want_blocks - nseg;
+        for (int s = 0; s < nseg; ++s) {
+            int k = (int)((double)extra * (double)seg_rows[s] / (double)n);
+            k = (int)std::min<int64_t>(k, std::max<int64_t>(0, seg_rows[s] - 1));
+            nb[s] += k;
+            total += k;
+        }
+        // top up to the requested count, largest rows-per-workgroup first
+        while (total < want_blocks) {
+            int best = -1;
+            for (int q = 0; q < nseg; ++q)
+                if (nb[q] < seg_rows[q] && (best < 0 || (double)seg_rows[q] / nb[q] > (double)seg_rows[best] / nb[best]))
+                    best = q;
+            if (best < 0) break;
+            nb[best] += 1;
+            ++total;
+        }
+    }
+    std::vector<int> row0(total + 1), bseg(total), sb0(nseg + 1);
+    int b = 0;
+    int64_t base = 0;
+    for (int s = 0; s < nseg; ++s) {
+        sb0[s] = b;
+        for (int k = 0; k < nb[s]; ++k) {
+            row0[b] = (int)(base + seg_rows[s] * k / nb[s]);
+            bseg[b] = s;
+            ++b;
+        }
+        base += seg_rows[s];
+    }
+    row0[total] = (int)base;
+    sb0[nseg] = total;
+    P.nblk = total;
+    PFE_CHECK_HIP(hipMalloc((void**)&P.row0, sizeof(int) * (total + 1)));
+    PFE_CHECK_HIP(hipMalloc((void**)&P.blk_seg, sizeof(int) * total));
+    PFE_CHECK_HIP(hipMalloc((void**)&P.seg_blk0, sizeof(int) * (nseg + 1)));
+    PFE_CHECK_HIP(hipMemcpy(P.row0, row0.data(), sizeof(int) * (total + 1), hipMemcpyHostToDevice));
+    PFE_CHECK_HIP(hipMemcpy(P.blk_seg, bseg.data(), sizeof(int) * total, hipMemcpyHostToDevice));
+    PFE_CHECK_HIP(hipMemcpy(P.seg_blk0, sb0.data(), sizeof(int) * (nseg + 1), hipMemcpyHostToDevice));
+    return PFE_OK;
+}
+
+void free_partition(Partition& P) {
+    if (P.row0) (void)hipFree(P.row0);
+    if (P.blk_seg) (void)hipFree(P.blk_seg);
+    if (P.seg_blk0) (void)hipFree(P.seg_blk0);
+    P = Partition{};
+}
+
 template <typename T>
-KA<T> make_args(pfe_ctx* c, int nblk) {
+KA<T> make_args(pfe_ctx* c, const Partition& pt) {
     KA<T> a{};
     a.n = (int)c->n;
     a.d = (int)c->d;
     a.R = kBlock / (int)c->d;
-    a.nblk = nblk;
+    a.nblk = pt.nblk;
+    a.nseg = c->nseg;
+    a.ell_K = c->g->ell_K;
+    a.row0 = pt.row0;
+    a.blk_seg = pt.blk_seg;
+    a.seg_blk0 = pt.seg_blk0;
     a.rowptr = c->g->rowptr;
-    a.col = c->g->col;
-    if (sizeof(T) == 4) a.w = (const T*)c->g->w32; else a.w = (const T*)c->g->w64;
+    a.scol = c->g->s_col;
+    if (sizeof(T) == 4) a.sw = (const T*)c->g->s_w32; else a.sw = (const T*)c->g->s_w64;
     a.diagA = (const T*)c->diagA;
     a.invdiag = (const T*)c->invdiag;
     a.sqrtD = (const T*)c->sqrtD;
@@ -1082,11 +1324,16 @@ KA<T> make_args(pfe_ctx* c, int nblk) {
     a.bs = (T*)c->bs;
     a.ds = (T*)c->ds;
     a.rhs = (T*)c->rhs;
-    a.r = (T*)c->r;
-    a.pA = (T*)c->pA;
-    a.pB = (T*)c->pB;
-    a.q = (T*)c->q;
+    for (int k = 0; k < 2; ++k) {
+        a.rb[k] = (T*)c->rb[k];
+        a.wb[k] = (T*)c->wb[k];
+        a.sb[k] = (T*)c->sb[k];
+    }
+    a.p = (T*)c->p;
     a.part = c->part;
+    a.gpart = c->gpart;
+    a.Tm = c->Tm;
+    a.cs = c->cs;
     a.S = c->S;
     a.bar = c->bar;
     a.c_off = (T)(0.5 * c->prm.lambda);
@@ -1096,6 +1343,7 @@ KA<T> make_args(pfe_ctx* c, int nblk) {
     a.maxit = c->prm.maxit;
     a.keep_split = c->prm.keep_split;
     a.store_rhs = 0;
+    a.b_zero = 0;
     a.ortho = c->prm.ortho;
     return a;
 }
@@ -1107,21 +1355,17 @@ pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0)
     return PFE_OK;
 }
 
-#define PFE_TRY(x) do { pfe_status s__ = (x); if (s__ != PFE_OK) return s__; } while (0)
-
-// Multi-launch PCG loop after a residual phase; the host polls the done flag
-// every few iterations.
+// Multi-launch PCG after a residual phase (r0 in rb[0]); the host polls the
+// done flag every few iterations; the iterate ends in a.x.
 template <typename T>
 pfe_status pcg_loop_mk(pfe_ctx* c, const KA<T>& a) {
     hipLaunchKernelGGL(k_stats_if_done<T>, dim3(1), dim3(64), 0, c->stream, a);
+    PFE_TRY(launch_phase(c, a, PH_W0, 0, 0));
     int it = 0;
     const int chunk = 4;
     int done = 0;
     while (true) {
-        for (int k = 0; k < chunk; ++k) {
-            PFE_TRY(launch_phase(c, a, PH_A, 0, 0));
-            PFE_TRY(launch_phase(c, a, PH_B, 0, 0));
-        }
+        for (int k = 0; k < chunk; ++k) PFE_TRY(launch_phase(c, a, PH_IT, 0, 0));
         it += chunk;
         PFE_CHECK_HIP(hipMemcpyAsync(&done, &c->S->done, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         PFE_CHECK_HIP(hipStreamSynchronize(c->stream));
@@ -1132,28 +1376,22 @@ pfe_status pcg_loop_mk(pfe_ctx* c, const KA<T>& a) {
 }
 
 template <typename T>
-pfe_status inner_mk(pfe_ctx* c, bool store_next) {
-    KA<T> a = make_args<T>(c, c->nblk);
-    // residual / rhs for this solve
-    if (c->inner == 0) {
-        PFE_TRY(launch_phase(c, a, PH_E0, 0, 1));
-    } else {
-        PFE_TRY(launch_phase(c, a, PH_R0, 0, 1));
-    }
+pfe_status inner_mk(pfe_ctx* c) {
+    KA<T> a = make_args<T>(c, c->pm);
+    PFE_TRY(launch_phase(c, a, (c->inner == 0) ? PH_E0 : PH_R0, 0, 1));
     PFE_TRY(pcg_loop_mk(c, a));
     // edge update of this inner step and rhs of the next one
     KA<T> b = a;
     b.store_rhs = 1;
     b.b_zero = (c->inner == 0);
     PFE_TRY(launch_phase(c, b, PH_EU, 0, 0));
-    (void)store_next;
     c->inner += 1;
     return PFE_OK;
 }
 
 template <typename T>
 pfe_status ortho_mk(pfe_ctx* c, int mode) {
-    KA<T> a = make_args<T>(c, c->nblk);
+    KA<T> a = make_args<T>(c, c->pm);
     PFE_TRY(launch_phase(c, a, PH_GRAM, mode, 0));
     PFE_TRY(launch_phase(c, a, PH_APPLY, mode, 0));
     return PFE_OK;
@@ -1161,38 +1399,36 @@ pfe_status ortho_mk(pfe_ctx* c, int mode) {
 
 template <typename T>
 pfe_status outer_mk(pfe_ctx* c) {
-    while (c->inner < c->prm.n_inner) PFE_TRY(inner_mk<T>(c, true));
+    while (c->inner < c->prm.n_inner) PFE_TRY(inner_mk<T>(c));
     PFE_TRY(ortho_mk<T>(c, 0));
     c->inner = 0;
     return PFE_OK;
 }
 
+// persistent kernel specialised for the graph's ELL width (0: generic loops)
+template <typename T>
+const void* soc_kernel(int ell_K) {
+    switch (ell_K) {
+        case 4: return reinterpret_cast<const void*>(&k_soc<T, 4>);
+        case 8: return reinterpret_cast<const void*>(&k_soc<T, 8>);
+        case 24: return reinterpret_cast<const void*>(&k_soc<T, 24>);
+        default: return reinterpret_cast<const void*>(&k_soc<T, 0>);
+    }
+}
+
 template <typename T>
 pfe_status outer_coop(pfe_ctx* c, int n_outer) {
-    KA<T> a = make_args<T>(c, c->nblk_coop);
-    Plan plan{c->inner, c->prm.n_inner, n_outer, 1};
     if (c->inner > 0) {
-        // resuming mid-iteration: the next solve starts from the stored rhs
-        KA<T> m = make_args<T>(c, c->nblk);
-        PFE_TRY(launch_phase(c, m, PH_R0, 0, 1));
-        PFE_TRY(pcg_loop_mk(c, m));
-        KA<T> b = m;
-        b.store_rhs = 1;
-        c->inner += 1;
-        if (c->inner < c->prm.n_inner) PFE_TRY(launch_phase(c, b, PH_EU, 0, 0));
-        // the remaining inner steps of this SOC iteration use the multi-launch path
-        while (c->inner < c->prm.n_inner) PFE_TRY(inner_mk<T>(c, true));
-        PFE_TRY(ortho_mk<T>(c, 0));
-        c->inner = 0;
-        n_outer -= 1;
-        plan.l_begin = 0;
-        if (n_outer == 0) return PFE_OK;
+        // finish the current SOC iteration one phase per launch
+        PFE_TRY(outer_mk<T>(c));
+        if (--n_outer == 0) return PFE_OK;
     }
-    plan.n_outer = n_outer;
-    PFE_CHECK_HIP(hipMemsetAsync(c->bar, 0, 2 * sizeof(unsigned), c->stream));
+    KA<T> a = make_args<T>(c, c->pc);
+    Plan plan{0, c->prm.n_inner, n_outer};
+    PFE_CHECK_HIP(hipMemsetAsync(c->bar, 0, 512 * sizeof(unsigned), c->stream));
     void* args[] = {(void*)&a, (void*)&plan};
-    PFE_CHECK_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_soc<T>), dim3(a.nblk),
-                                             dim3(kBlock), args, 0, c->stream));
+    PFE_CHECK_HIP(hipLaunchCooperativeKernel(soc_kernel<T>(c->g->ell_K), dim3(a.nblk), dim3(kBlock), args, 0,
+                                             c->stream));
     c->inner = 0;
     return PFE_OK;
 }
@@ -1210,6 +1446,8 @@ pfe_status read_info(pfe_ctx* c, pfe_step_info* info) {
         info->rel_res_max = h.relres_max;
         info->status = h.status;
         info->fallbacks = h.fallbacks;
+        info->workgroups = (c->prm.persistent && c->pc.nblk > 0) ? c->pc.nblk : 0;
+        info->reserved = 0;
     }
     if (h.status != 0) {
         set_error("%s", pfe_status_string((pfe_status)h.status));
@@ -1219,7 +1457,6 @@ pfe_status read_info(pfe_ctx* c, pfe_step_info* info) {
 }
 
 pfe_status reset_stats(pfe_ctx* c) {
-    // statistics and status are the tail of Scal starting at 'status'
     size_t off = offsetof(Scal, status);
     PFE_CHECK_HIP(hipMemsetAsync((char*)c->S + off, 0, sizeof(int), c->stream));
     off = offsetof(Scal, solves);
@@ -1238,10 +1475,13 @@ pfe_status set_diag(pfe_ctx* c) {
 }
 
 void free_ctx(pfe_ctx* c) {
-    void* bufs[] = {c->Y, c->P, c->B, c->bs, c->ds, c->rhs, c->r, c->pA, c->pB, c->q,
-                    c->diagA, c->invdiag, c->sqrtD, c->isqrtD, c->part, c->S, c->bar, c->hist};
+    void* bufs[] = {c->Y, c->P, c->B, c->bs, c->ds, c->rhs, c->p, c->rb[0], c->rb[1], c->wb[0], c->wb[1],
+                    c->sb[0], c->sb[1], c->diagA, c->invdiag, c->sqrtD, c->isqrtD, c->part, c->gpart,
+                    c->Tm, c->colbuf, c->colint, c->S, c->bar, c->hist};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
+    free_partition(c->pm);
+    free_partition(c->pc);
 }
 
 bool params_ok(const pfe_params* p, int64_t n) {
@@ -1258,7 +1498,7 @@ bool params_ok(const pfe_params* p, int64_t n) {
 
 template <typename T>
 pfe_status monitor_impl(pfe_ctx* c, pfe_monitors* out) {
-    KA<T> a = make_args<T>(c, c->nblk);
+    KA<T> a = make_args<T>(c, c->pm);
     hipLaunchKernelGGL(k_monitor<T>, dim3(a.nblk), dim3(kBlock), 0, c->stream, a);
     PFE_CHECK_HIP(hipGetLastError());
     double mon[4];
@@ -1274,9 +1514,8 @@ pfe_status monitor_impl(pfe_ctx* c, pfe_monitors* out) {
 template <typename T>
 pfe_status quantile_impl(pfe_ctx* c, double q, double* out) {
     typedef typename Bits<T>::U U;
-    KA<T> a = make_args<T>(c, c->nblk);
+    KA<T> a = make_args<T>(c, c->pm);
     const int W = Bits<T>::W;
-    // passes over the top bits; float: 12+12+8, double: 16+16+16+16
     int widths[4];
     int np;
     if (W == 32) { widths[0] = 12; widths[1] = 12; widths[2] = 8; np = 3; }
@@ -1306,15 +1545,39 @@ pfe_status quantile_impl(pfe_ctx* c, double q, double* out) {
         k -= cum;
         prefix = (prefix << nb) | (unsigned long long)bin;
         consumed += nb;
-        if (W == 64 && pz == np - 1 && consumed < W) {
-            // remaining low bits are not resolved; the value is the bin's lower edge
-        }
     }
+    // with FP64 the lowest 16 bits stay unresolved: the value is the bin's lower edge
     U u = (U)(prefix << (W - consumed));
     T v;
     memcpy(&v, &u, sizeof(T));
     *out = (double)v;
     return PFE_OK;
+}
+
+template <typename T>
+pfe_status split_to_edges(pfe_ctx* c, const void* src, void* dst) {
+    KA<T> a = make_args<T>(c, c->pm);
+    const int n = (int)c->n;
+    hipLaunchKernelGGL(k_slots_to_edges<T>, dim3((n + 255) / 256), dim3(256), 0, c->stream, a, c->g->s_eid,
+                       (const T*)src, (T*)dst);
+    PFE_CHECK_HIP(hipGetLastError());
+    return PFE_OK;
+}
+
+template <typename T>
+pfe_status edges_to_split(pfe_ctx* c, const void* src, void* dst) {
+    KA<T> a = make_args<T>(c, c->pm);
+    const int n = (int)c->n;
+    hipLaunchKernelGGL(k_edges_to_slots<T>, dim3((n + 255) / 256), dim3(256), 0, c->stream, a, c->g->s_eid,
+                       (const T*)src, (T*)dst);
+    PFE_CHECK_HIP(hipGetLastError());
+    return PFE_OK;
+}
+
+template <typename T>
+pfe_status rebuild_rhs(pfe_ctx* c) {
+    KA<T> a = make_args<T>(c, c->pm);
+    return launch_phase(c, a, PH_RHS, 0, 0);
 }
 
 }  // namespace
@@ -1329,45 +1592,58 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
     c->g = g;
     c->prm = *p;
     c->stream = stream;
-    PFE_CHECK_HIP(hipGetDevice(&c->device));
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; set_error("hipGetDevice failed"); return PFE_E_HIP; }
     c->esz = (p->dtype == PFE_FP64) ? 8 : 4;
     c->n = g->n;
     c->d = p->d;
-    c->slots = g->slots;
+    c->nseg = 1;
     const size_t nd = (size_t)c->n * c->d * c->esz;
-    const size_t sd = (size_t)(c->slots + 1) * c->d * c->esz;
+    const size_t sd = (size_t)(g->nslot + 1) * c->d * c->esz;
     const size_t nv = (size_t)c->n * c->esz;
-    // workgroup counts
-    int ncu = 0;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) { delete c; set_error("hipGetDeviceProperties failed"); return PFE_E_HIP; }
-    ncu = prop.multiProcessorCount;
+    const int ncu = prop.multiProcessorCount;
     const int R = kBlock / (int)c->d;
-    int64_t want = (c->n + R - 1) / R;
-    c->nblk = (int)std::max<int64_t>(1, std::min<int64_t>(want, 2048));
-    if (c->nblk >= kNumXcd) c->nblk -= c->nblk % kNumXcd;
+    const int64_t want = (c->n + R - 1) / R;
     int occ = 0;
-    hipError_t oe = (p->dtype == PFE_FP64)
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_soc<double>, kBlock, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_soc<float>, kBlock, 0);
+    hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &occ, (p->dtype == PFE_FP64) ? soc_kernel<double>(g->ell_K) : soc_kernel<float>(g->ell_K), kBlock, 0);
     if (oe != hipSuccess) occ = 0;
-    int per_cu = std::max(0, std::min(occ, 2));
-    c->nblk_coop = per_cu * ncu;
-    if (c->nblk_coop > want) c->nblk_coop = (int)std::max<int64_t>(kNumXcd, want - want % kNumXcd);
-    if (c->nblk_coop >= kNumXcd) c->nblk_coop -= c->nblk_coop % kNumXcd;
-    int npair = (int)(c->d * (c->d + 1) / 2);
-    int nblk_max = std::max(c->nblk, c->nblk_coop);
-    c->part_doubles = (size_t)nblk_max * std::max<int64_t>(3 * c->d, 3 + 2 * npair) + 64;
+    const int per_cu = std::max(0, std::min(occ, 2));
+    std::vector<int64_t> seg_rows{c->n};
+    pfe_status s = make_partition(seg_rows, (int)std::min<int64_t>(want, 2048), c->pm);
+    if (s == PFE_OK && p->persistent) {
+        int64_t coop = (int64_t)per_cu * ncu;
+        if (const char* ev = getenv("PFE_PERSISTENT_WG")) {
+            // launch-shape experiments: cap the persistent grid (never above co-residency)
+            int64_t cap = atoll(ev);
+            if (cap > 0 && cap < coop) coop = cap;
+        }
+        if (coop > want) coop = want;
+        coop -= coop % kNumXcd;
+        if (coop >= kNumXcd) s = make_partition(seg_rows, (int)coop, c->pc);
+        if (c->pc.nblk % kNumXcd != 0 || c->pc.nblk > per_cu * ncu) free_partition(c->pc);
+    }
+    if (s != PFE_OK) { free_ctx(c); delete c; return s; }
+    const int nblk_max = std::max(c->pm.nblk, c->pc.nblk);
+    const int npair = (int)(c->d * (c->d + 1) / 2);
+    const size_t part_doubles = (size_t)nblk_max * std::max<int64_t>(3 * c->d, 3 + 2 * npair) + 64;
+    const size_t ncol = (size_t)c->nseg * c->d;
     hipError_t e = hipSuccess;
 #define ALLOC(ptr, bytes) do { if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (bytes)); } while (0)
     ALLOC(c->Y, nd); ALLOC(c->P, nd); ALLOC(c->B, nd);
     ALLOC(c->bs, sd);
     if (p->keep_split) ALLOC(c->ds, sd);
-    ALLOC(c->rhs, nd); ALLOC(c->r, nd); ALLOC(c->pA, nd); ALLOC(c->pB, nd); ALLOC(c->q, nd);
+    ALLOC(c->rhs, nd); ALLOC(c->p, nd);
+    for (int k = 0; k < 2; ++k) { ALLOC(c->rb[k], nd); ALLOC(c->wb[k], nd); ALLOC(c->sb[k], nd); }
     ALLOC(c->diagA, nv); ALLOC(c->invdiag, nv); ALLOC(c->sqrtD, nv); ALLOC(c->isqrtD, nv);
-    ALLOC(c->part, sizeof(double) * c->part_doubles);
+    ALLOC(c->part, sizeof(double) * part_doubles);
+    ALLOC(c->gpart, sizeof(double) * kNumXcd * std::max(3 * kMaxD, kMaxD * (kMaxD + 1) / 2));
+    ALLOC(c->Tm, sizeof(double) * c->nseg * kMaxD * kMaxD);
+    ALLOC(c->colbuf, sizeof(double) * ncol * 5);
+    ALLOC(c->colint, sizeof(int) * ncol * 3);
     ALLOC(c->S, sizeof(Scal));
-    ALLOC(c->bar, 64 * sizeof(unsigned));
+    ALLOC(c->bar, 512 * sizeof(unsigned));
     ALLOC(c->hist, 4096 * sizeof(unsigned));
 #undef ALLOC
     if (e != hipSuccess) {
@@ -1375,13 +1651,21 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
         delete c;
         return hip_fail(e, "hipMalloc (context)", __FILE__, __LINE__);
     }
-    pfe_status s = PFE_OK;
+    c->cs.gamma = c->colbuf;
+    c->cs.alpha = c->colbuf + ncol;
+    c->cs.beta = c->colbuf + 2 * ncol;
+    c->cs.bnorm2 = c->colbuf + 3 * ncol;
+    c->cs.rr = c->colbuf + 4 * ncol;
+    c->cs.iters = c->colint;
+    c->cs.active = c->colint + ncol;
+    c->cs.zero = c->colint + 2 * ncol;
     do {
         if (hipMemsetAsync(c->S, 0, sizeof(Scal), stream) != hipSuccess ||
-            hipMemsetAsync(c->bar, 0, 64 * sizeof(unsigned), stream) != hipSuccess ||
+            hipMemsetAsync(c->bar, 0, 512 * sizeof(unsigned), stream) != hipSuccess ||
             hipMemsetAsync(c->bs, 0, sd, stream) != hipSuccess ||
-            hipMemsetAsync(c->pA, 0, nd, stream) != hipSuccess ||
-            hipMemsetAsync(c->pB, 0, nd, stream) != hipSuccess ||
+            hipMemsetAsync(c->p, 0, nd, stream) != hipSuccess ||
+            hipMemsetAsync(c->colbuf, 0, sizeof(double) * ncol * 5, stream) != hipSuccess ||
+            hipMemsetAsync(c->colint, 0, sizeof(int) * ncol * 3, stream) != hipSuccess ||
             (c->ds && hipMemsetAsync(c->ds, 0, sd, stream) != hipSuccess) ||
             hipMemcpyAsync(c->Y, Y0, nd, hipMemcpyDeviceToDevice, stream) != hipSuccess) {
             s = hip_fail(hipGetLastError(), "context initialisation", __FILE__, __LINE__);
@@ -1393,16 +1677,16 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
             s = (p->dtype == PFE_FP64) ? ortho_mk<double>(c, 1) : ortho_mk<float>(c, 1);
         } else {
             // P = D^{1/2} Y, B = 0 through the same apply pass with T = I
-            Scal hS;
-            memset(&hS, 0, sizeof(hS));
-            for (int k = 0; k < c->d; ++k) hS.T[k * kMaxD + k] = 1.0;
-            hS.ortho_ok = 1;
-            if (hipMemcpyAsync(c->S, &hS, sizeof(Scal), hipMemcpyHostToDevice, stream) != hipSuccess) {
+            std::vector<double> I((size_t)c->nseg * kMaxD * kMaxD, 0.0);
+            for (int sg = 0; sg < c->nseg; ++sg)
+                for (int k = 0; k < c->d; ++k) I[(size_t)sg * kMaxD * kMaxD + k * kMaxD + k] = 1.0;
+            int one = 1;
+            if (hipMemcpyAsync(c->Tm, I.data(), sizeof(double) * I.size(), hipMemcpyHostToDevice, stream) != hipSuccess ||
+                hipMemcpyAsync(&c->S->ortho_ok, &one, sizeof(int), hipMemcpyHostToDevice, stream) != hipSuccess) {
                 s = PFE_E_HIP; break;
             }
-            KA<float> af; KA<double> ad;
-            if (p->dtype == PFE_FP64) { ad = make_args<double>(c, c->nblk); s = launch_phase(c, ad, PH_APPLY, 1, 0); }
-            else { af = make_args<float>(c, c->nblk); s = launch_phase(c, af, PH_APPLY, 1, 0); }
+            if (p->dtype == PFE_FP64) { KA<double> ad = make_args<double>(c, c->pm); s = launch_phase(c, ad, PH_APPLY, 1, 0); }
+            else { KA<float> af = make_args<float>(c, c->pm); s = launch_phase(c, af, PH_APPLY, 1, 0); }
             if (hipStreamSynchronize(stream) != hipSuccess) s = PFE_E_HIP;
         }
         if (s != PFE_OK) break;
@@ -1443,9 +1727,9 @@ pfe_status pfe_step(pfe_ctx* c, int granularity, pfe_step_info* info) {
     const bool f64 = c->prm.dtype == PFE_FP64;
     if (granularity == PFE_INNER) {
         if (c->inner >= c->prm.n_inner) { set_error("all inner iterations done; call pfe_step(PFE_OUTER)"); return PFE_E_STATE; }
-        s = f64 ? inner_mk<double>(c, true) : inner_mk<float>(c, true);
+        s = f64 ? inner_mk<double>(c) : inner_mk<float>(c);
     } else if (granularity == PFE_OUTER) {
-        if (c->prm.persistent && c->nblk_coop >= kNumXcd && c->inner < c->prm.n_inner)
+        if (c->prm.persistent && c->pc.nblk > 0 && c->inner == 0)
             s = f64 ? outer_coop<double>(c, 1) : outer_coop<float>(c, 1);
         else
             s = f64 ? outer_mk<double>(c) : outer_mk<float>(c);
@@ -1462,7 +1746,7 @@ pfe_status pfe_solve(pfe_ctx* c, int n_outer, pfe_step_info* info) {
     if (!c || n_outer < 0) { set_error("pfe_solve: bad argument"); return PFE_E_ARG; }
     if (info) PFE_TRY(reset_stats(c));
     const bool f64 = c->prm.dtype == PFE_FP64;
-    if (c->prm.persistent && c->nblk_coop >= kNumXcd && n_outer > 0 && c->inner < c->prm.n_inner) {
+    if (c->prm.persistent && c->pc.nblk > 0 && n_outer > 0) {
         PFE_TRY(f64 ? outer_coop<double>(c, n_outer) : outer_coop<float>(c, n_outer));
     } else {
         for (int k = 0; k < n_outer; ++k) PFE_TRY(f64 ? outer_mk<double>(c) : outer_mk<float>(c));
@@ -1482,7 +1766,7 @@ pfe_status pfe_get(pfe_ctx* c, int which, void* dst) {
     if (!c || !dst) { set_error("pfe_get: null argument"); return PFE_E_ARG; }
     const size_t nd = (size_t)c->n * c->d * c->esz;
     hipStream_t st = c->stream;
-    const int n = (int)c->n, d = (int)c->d;
+    const int d = (int)c->d;
     switch (which) {
         case PFE_Y: PFE_CHECK_HIP(hipMemcpyAsync(dst, c->Y, nd, hipMemcpyDeviceToDevice, st)); break;
         case PFE_P: PFE_CHECK_HIP(hipMemcpyAsync(dst, c->P, nd, hipMemcpyDeviceToDevice, st)); break;
@@ -1508,13 +1792,7 @@ pfe_status pfe_get(pfe_ctx* c, int which, void* dst) {
                 PFE_CHECK_HIP(hipMemsetAsync(dst, 0, (size_t)c->g->n_edges * d * c->esz, st));
                 break;
             }
-            if (c->esz == 8)
-                hipLaunchKernelGGL(k_slots_to_edges<double>, dim3((n + 255) / 256), dim3(256), 0, st, n, d,
-                                   c->g->rowptr, c->g->col, c->g->eid, (const double*)src, (double*)dst);
-            else
-                hipLaunchKernelGGL(k_slots_to_edges<float>, dim3((n + 255) / 256), dim3(256), 0, st, n, d,
-                                   c->g->rowptr, c->g->col, c->g->eid, (const float*)src, (float*)dst);
-            PFE_CHECK_HIP(hipGetLastError());
+            PFE_TRY(c->esz == 8 ? split_to_edges<double>(c, src, dst) : split_to_edges<float>(c, src, dst));
             break;
         }
         default: set_error("pfe_get: unknown block %d", which); return PFE_E_ARG;
@@ -1527,7 +1805,6 @@ pfe_status pfe_set(pfe_ctx* c, int which, const void* src) {
     if (!c || !src) { set_error("pfe_set: null argument"); return PFE_E_ARG; }
     const size_t nd = (size_t)c->n * c->d * c->esz;
     hipStream_t st = c->stream;
-    const int n = (int)c->n, d = (int)c->d;
     switch (which) {
         case PFE_Y: PFE_CHECK_HIP(hipMemcpyAsync(c->Y, src, nd, hipMemcpyDeviceToDevice, st)); break;
         case PFE_P: PFE_CHECK_HIP(hipMemcpyAsync(c->P, src, nd, hipMemcpyDeviceToDevice, st)); break;
@@ -1536,22 +1813,13 @@ pfe_status pfe_set(pfe_ctx* c, int which, const void* src) {
         case PFE_DSPLIT: {
             void* dstp = (which == PFE_BSPLIT) ? c->bs : c->ds;
             if (!dstp) { set_error("pfe_set: split variable d not kept (keep_split = 0)"); return PFE_E_STATE; }
-            if (c->esz == 8)
-                hipLaunchKernelGGL(k_edges_to_slots<double>, dim3((n + 255) / 256), dim3(256), 0, st, n, d,
-                                   c->g->rowptr, c->g->col, c->g->eid, (const double*)src, (double*)dstp);
-            else
-                hipLaunchKernelGGL(k_edges_to_slots<float>, dim3((n + 255) / 256), dim3(256), 0, st, n, d,
-                                   c->g->rowptr, c->g->col, c->g->eid, (const float*)src, (float*)dstp);
-            PFE_CHECK_HIP(hipGetLastError());
+            PFE_TRY(c->esz == 8 ? edges_to_split<double>(c, src, dstp) : edges_to_split<float>(c, src, dstp));
             break;
         }
         default: set_error("pfe_set: block %d cannot be set", which); return PFE_E_ARG;
     }
     // the stored rhs follows the state when mid-way through a SOC iteration
-    if (c->inner > 0 && c->ds) {
-        if (c->esz == 8) { KA<double> a = make_args<double>(c, c->nblk); PFE_TRY(launch_phase(c, a, PH_RHS, 0, 0)); }
-        else { KA<float> a = make_args<float>(c, c->nblk); PFE_TRY(launch_phase(c, a, PH_RHS, 0, 0)); }
-    }
+    if (c->inner > 0 && c->ds) PFE_TRY(c->esz == 8 ? rebuild_rhs<double>(c) : rebuild_rhs<float>(c));
     PFE_CHECK_HIP(hipStreamSynchronize(st));
     return PFE_OK;
 }
@@ -1568,11 +1836,10 @@ pfe_status pfe_set_inner_index(pfe_ctx* c, int inner_index) {
     if (inner_index > 0 && !c->ds) { set_error("resuming inside a SOC iteration needs keep_split = 1"); return PFE_E_STATE; }
     c->inner = inner_index;
     if (inner_index == 0) {
-        PFE_CHECK_HIP(hipMemsetAsync(c->bs, 0, (size_t)(c->slots + 1) * c->d * c->esz, c->stream));
-        if (c->ds) PFE_CHECK_HIP(hipMemsetAsync(c->ds, 0, (size_t)(c->slots + 1) * c->d * c->esz, c->stream));
+        PFE_CHECK_HIP(hipMemsetAsync(c->bs, 0, (size_t)(c->g->nslot + 1) * c->d * c->esz, c->stream));
+        if (c->ds) PFE_CHECK_HIP(hipMemsetAsync(c->ds, 0, (size_t)(c->g->nslot + 1) * c->d * c->esz, c->stream));
     } else {
-        if (c->esz == 8) { KA<double> a = make_args<double>(c, c->nblk); PFE_TRY(launch_phase(c, a, PH_RHS, 0, 0)); }
-        else { KA<float> a = make_args<float>(c, c->nblk); PFE_TRY(launch_phase(c, a, PH_RHS, 0, 0)); }
+        PFE_TRY(c->esz == 8 ? rebuild_rhs<double>(c) : rebuild_rhs<float>(c));
     }
     PFE_CHECK_HIP(hipStreamSynchronize(c->stream));
     return PFE_OK;
@@ -1586,10 +1853,10 @@ pfe_status pfe_monitor(pfe_ctx* c, pfe_monitors* out) {
 pfe_status pfe_apply_A(pfe_ctx* c, const void* X, void* Q) {
     if (!c || !X || !Q) { set_error("pfe_apply_A: null argument"); return PFE_E_ARG; }
     if (c->esz == 8) {
-        KA<double> a = make_args<double>(c, c->nblk);
+        KA<double> a = make_args<double>(c, c->pm);
         hipLaunchKernelGGL(k_spmm<double>, dim3(a.nblk), dim3(kBlock), 0, c->stream, a, (const double*)X, (double*)Q);
     } else {
-        KA<float> a = make_args<float>(c, c->nblk);
+        KA<float> a = make_args<float>(c, c->pm);
         hipLaunchKernelGGL(k_spmm<float>, dim3(a.nblk), dim3(kBlock), 0, c->stream, a, (const float*)X, (float*)Q);
     }
     PFE_CHECK_HIP(hipGetLastError());
@@ -1601,20 +1868,20 @@ pfe_status pfe_pcg(pfe_ctx* c, const void* RHS, void* X, int32_t* iters, pfe_ste
     if (!c || !RHS || !X) { set_error("pfe_pcg: null argument"); return PFE_E_ARG; }
     PFE_TRY(reset_stats(c));
     if (c->esz == 8) {
-        KA<double> a = make_args<double>(c, c->nblk);
+        KA<double> a = make_args<double>(c, c->pm);
         a.x = (double*)X;
         a.rhs = (double*)RHS;
         PFE_TRY(launch_phase(c, a, PH_R0, 0, 1));
         PFE_TRY(pcg_loop_mk(c, a));
     } else {
-        KA<float> a = make_args<float>(c, c->nblk);
+        KA<float> a = make_args<float>(c, c->pm);
         a.x = (float*)X;
         a.rhs = (float*)RHS;
         PFE_TRY(launch_phase(c, a, PH_R0, 0, 1));
         PFE_TRY(pcg_loop_mk(c, a));
     }
     if (iters) {
-        PFE_CHECK_HIP(hipMemcpyAsync(iters, c->S->iters, sizeof(int) * c->d, hipMemcpyDeviceToHost, c->stream));
+        PFE_CHECK_HIP(hipMemcpyAsync(iters, c->cs.iters, sizeof(int) * c->d, hipMemcpyDeviceToHost, c->stream));
     }
     return read_info(c, info);
 }
