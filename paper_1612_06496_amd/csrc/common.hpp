@@ -79,4 +79,7 @@ struct pfe_graph {
     float* s_w32 = nullptr;
     double* s_w64 = nullptr;
     int* s_eid = nullptr;     // undirected edge of the slot, -1 for padding
+    // Pixel grids: ELL slot k of every row is stencil offset k; slots that
+    // leave the image have weight 0 and point at the row itself.
+    int stencil = 0;
 };

@@ -282,6 +282,45 @@ __global__ void k_build_ell(int64_t n, int K, const int* __restrict__ rowptr, co
     }
 }
 
+// Stencil-ordered ELL for pixel grids: slot k of row i is stencil offset k.
+__global__ void k_build_stencil_ell(int H, int W, Stencil st, const int* __restrict__ rowptr,
+                                    const int* __restrict__ col, const float* __restrict__ w32,
+                                    const double* __restrict__ w64, const int* __restrict__ eid,
+                                    int* __restrict__ s_col, float* __restrict__ s_w32,
+                                    double* __restrict__ s_w64, int* __restrict__ s_eid, int* __restrict__ err) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = (int64_t)H * W;
+    if (i >= n) return;
+    int y = (int)(i / W), x = (int)(i - (int64_t)y * W);
+    int s0 = rowptr[i], s1 = rowptr[i + 1];
+    for (int k = 0; k < st.k; ++k) {
+        int64_t s = (int64_t)k * n + i;
+        int yy = y + st.dy[k], xx = x + st.dx[k];
+        int slot = -1;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+            int j = yy * W + xx;
+            int lo = s0, hi = s1 - 1;
+            while (lo <= hi) {
+                int mid = (lo + hi) >> 1;
+                if (col[mid] == j) { slot = mid; break; }
+                if (col[mid] < j) lo = mid + 1; else hi = mid - 1;
+            }
+            if (slot < 0) atomicOr(err, ERR_ASYM);
+        }
+        if (slot >= 0) {
+            s_col[s] = col[slot];
+            s_w32[s] = w32[slot];
+            s_w64[s] = w64[slot];
+            s_eid[s] = eid[slot];
+        } else {
+            s_col[s] = (int)i;
+            s_w32[s] = 0.0f;
+            s_w64[s] = 0.0;
+            s_eid[s] = -1;
+        }
+    }
+}
+
 __global__ void k_max_deg(int64_t n, const int* __restrict__ rowptr, int* __restrict__ out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -436,7 +475,44 @@ static pfe_status build_impl(const pfe_graph_desc* d, hipStream_t st, pfe_graph*
     PFE_CHECK_HIP(hipStreamSynchronize(st));
     PFE_CHECK_HIP(hipFree(dmax));
     const int64_t ell_slots = (int64_t)g->max_deg * n;
-    if (g->max_deg > 0 && 4 * ell_slots <= 5 * g->slots && ell_slots < (int64_t)INT32_MAX) {
+    if (d->kind == PFE_GRID) {
+        // stencil-ordered ELL (every pixel grid qualifies)
+        Stencil sten{};
+        std::vector<std::pair<int, int>> offs;
+        if (d->stencil == 4) offs = {{-1, 0}, {0, -1}, {0, 1}, {1, 0}};
+        else if (d->stencil == 8) offs = {{-1, -1}, {-1, 0}, {-1, 1}, {0, -1}, {0, 1}, {1, -1}, {1, 0}, {1, 1}};
+        else {
+            int R = -d->stencil;
+            for (int dy = -R; dy <= R; ++dy)
+                for (int dx = -R; dx <= R; ++dx)
+                    if (dy || dx) offs.push_back({dy, dx});
+        }
+        sten.k = (int)offs.size();
+        for (int k = 0; k < sten.k; ++k) {
+            sten.dy[k] = offs[k].first;
+            sten.dx[k] = offs[k].second;
+        }
+        const int64_t ns = (int64_t)sten.k * n;
+        if (ns >= (int64_t)INT32_MAX) { set_error("pfe_build_graph: graph too large"); return PFE_E_ARG; }
+        g->ell_K = sten.k;
+        g->stencil = 1;
+        g->nslot = ns;
+        PFE_CHECK_HIP(hipMalloc((void**)&g->s_col, sizeof(int) * ns));
+        PFE_CHECK_HIP(hipMalloc((void**)&g->s_w32, sizeof(float) * ns));
+        PFE_CHECK_HIP(hipMalloc((void**)&g->s_w64, sizeof(double) * ns));
+        PFE_CHECK_HIP(hipMalloc((void**)&g->s_eid, sizeof(int) * ns));
+        int* err2 = nullptr;
+        PFE_CHECK_HIP(hipMalloc((void**)&err2, sizeof(int)));
+        PFE_CHECK_HIP(hipMemsetAsync(err2, 0, sizeof(int), st));
+        hipLaunchKernelGGL(k_build_stencil_ell, dim3(gridN), dim3(TB), 0, st, d->H, d->W, sten, g->rowptr, g->col,
+                           g->w32, g->w64, g->eid, g->s_col, g->s_w32, g->s_w64, g->s_eid, err2);
+        PFE_CHECK_HIP(hipGetLastError());
+        int herr2 = 0;
+        PFE_CHECK_HIP(hipMemcpyAsync(&herr2, err2, sizeof(int), hipMemcpyDeviceToHost, st));
+        PFE_CHECK_HIP(hipStreamSynchronize(st));
+        PFE_CHECK_HIP(hipFree(err2));
+        if (herr2) { set_error("pfe_build_graph: %s", graph_err_text(herr2)); return PFE_E_GRAPH; }
+    } else if (g->max_deg > 0 && 4 * ell_slots <= 5 * g->slots && ell_slots < (int64_t)INT32_MAX) {
         g->ell_K = g->max_deg;
         g->nslot = ell_slots;
         PFE_CHECK_HIP(hipMalloc((void**)&g->s_col, sizeof(int) * ell_slots));

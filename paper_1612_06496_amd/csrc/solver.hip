@@ -984,8 +984,8 @@ __global__ void __launch_bounds__(kBlock) k_soc(KA<T> a, Plan plan) {
     }
 }
 
-template <typename T>
-__global__ void k_spmm(KA<T> a, const T* __restrict__ X, T* __restrict__ Q) {
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_spmm(KA<T> a, const T* __restrict__ X, T* __restrict__ Q) {
     const int d = a.d, R = a.R, t = threadIdx.x;
     const int lb = blockIdx.x;
     const int rb = a.row0[lb], re = a.row0[lb + 1];
@@ -994,8 +994,9 @@ __global__ void k_spmm(KA<T> a, const T* __restrict__ X, T* __restrict__ Q) {
     for (int i = rb + rl; i < re; i += R) {
         const size_t e = (size_t)i * d + c;
         int s0, cnt, st;
-        row_slots(a, i, s0, cnt, st);
+        row_slots<KC>(a, i, s0, cnt, st);
         T acc = T(0);
+#pragma unroll(KC > 0 ? 4 : 2)
         for (int k = 0; k < cnt; ++k) {
             const int s = s0 + k * st;
             const T ww = a.sw[s];
@@ -1575,6 +1576,18 @@ pfe_status edges_to_split(pfe_ctx* c, const void* src, void* dst) {
 }
 
 template <typename T>
+pfe_status launch_spmm(pfe_ctx* c, const KA<T>& a, const T* X, T* Q) {
+    switch (c->g->ell_K) {
+        case 4: hipLaunchKernelGGL((k_spmm<T, 4>), dim3(a.nblk), dim3(kBlock), 0, c->stream, a, X, Q); break;
+        case 8: hipLaunchKernelGGL((k_spmm<T, 8>), dim3(a.nblk), dim3(kBlock), 0, c->stream, a, X, Q); break;
+        case 24: hipLaunchKernelGGL((k_spmm<T, 24>), dim3(a.nblk), dim3(kBlock), 0, c->stream, a, X, Q); break;
+        default: hipLaunchKernelGGL((k_spmm<T, 0>), dim3(a.nblk), dim3(kBlock), 0, c->stream, a, X, Q); break;
+    }
+    PFE_CHECK_HIP(hipGetLastError());
+    return PFE_OK;
+}
+
+template <typename T>
 pfe_status rebuild_rhs(pfe_ctx* c) {
     KA<T> a = make_args<T>(c, c->pm);
     return launch_phase(c, a, PH_RHS, 0, 0);
@@ -1854,10 +1867,10 @@ pfe_status pfe_apply_A(pfe_ctx* c, const void* X, void* Q) {
     if (!c || !X || !Q) { set_error("pfe_apply_A: null argument"); return PFE_E_ARG; }
     if (c->esz == 8) {
         KA<double> a = make_args<double>(c, c->pm);
-        hipLaunchKernelGGL(k_spmm<double>, dim3(a.nblk), dim3(kBlock), 0, c->stream, a, (const double*)X, (double*)Q);
+        PFE_TRY(launch_spmm<double>(c, a, (const double*)X, (double*)Q));
     } else {
         KA<float> a = make_args<float>(c, c->pm);
-        hipLaunchKernelGGL(k_spmm<float>, dim3(a.nblk), dim3(kBlock), 0, c->stream, a, (const float*)X, (float*)Q);
+        PFE_TRY(launch_spmm<float>(c, a, (const float*)X, (float*)Q));
     }
     PFE_CHECK_HIP(hipGetLastError());
     PFE_CHECK_HIP(hipStreamSynchronize(c->stream));
