@@ -74,7 +74,8 @@ enum {
     PFE_YHAT = 3,   /* n x d, D^{-1/2} P (feasible embedding, Yhat^T D Yhat = I); get only */
     PFE_BSPLIT = 4, /* |E| x d, Split-Bregman variable b */
     PFE_DSPLIT = 5, /* |E| x d, Split-Bregman variable d (needs keep_split on get) */
-    PFE_RHS = 6     /* n x d, right-hand side of the next least-squares solve; get only */
+    PFE_RHS = 6,    /* n x d, right-hand side of the next least-squares solve; get only */
+    PFE_RESID = 7   /* n x d, initial residual rhs - A Y of the next least-squares solve; get only */
 };
 
 typedef struct pfe_graph pfe_graph;
@@ -233,6 +234,47 @@ pfe_status pfe_apply_A(pfe_ctx* c, const void* X, void* Q);
  * entry and the solution on return.  iters (host, may be null) receives the
  * per-column iteration counts (d ints). */
 pfe_status pfe_pcg(pfe_ctx* c, const void* RHS, void* X, int32_t* iters, pfe_step_info* info);
+
+/* ---- learned preconditioner ---------------------------------------------------
+ * Not part of the paper (which preconditions with incomplete Cholesky, Sec. III):
+ * M^{-1} = G^T G, G = Gt D_A^{-1/2}, Gt lower triangular on the pattern of A with
+ * a positive (softplus) diagonal, so M^{-1} is SPD for any weights and Gt = I is
+ * Jacobi.  Gt comes from a two-layer message-passing network of width 16 on the
+ * scaled matrix D_A^{-1/2} A D_A^{-1/2}; its dense layers run on MFMA with bf16
+ * weights and fp32 accumulation.  Parameters: PFE_MPNN_NPARAMS floats in the
+ * order W1s (16x4), W1m (16x4), b1 (16), W2s (16x16), W2m (16x16), b2 (16),
+ * u (16), v (16), q (16), c, bd. */
+#define PFE_MPNN_NPARAMS 722
+typedef struct pfe_mpnn pfe_mpnn;
+
+/* Create a network from host parameters, or the identity network (Gt = I)
+ * when params is null.  Weights and Adam state live on the current device. */
+pfe_status pfe_mpnn_create(const float* params, pfe_mpnn** out);
+/* Copy the parameters and/or the gradient of the last training step to host
+ * arrays of PFE_MPNN_NPARAMS floats (either may be null). */
+pfe_status pfe_mpnn_get_params(pfe_mpnn* net, float* params, float* grad);
+/* Replace the parameters (host array) and reset the Adam state. */
+pfe_status pfe_mpnn_set_params(pfe_mpnn* net, const float* params);
+void pfe_mpnn_destroy(pfe_mpnn* net);
+
+/* One training step on the context's system: samples are k residual vectors
+ * (device, n x k row-major, context element type, 1 <= k <= 32), scaled to
+ * rho = D_A^{-1/2} r / ||D_A^{-1/2} r||; loss = mean_k ||At Gt^T Gt rho_k - rho_k||^2
+ * with At = D_A^{-1/2} A D_A^{-1/2}.  lr > 0 applies one Adam step (lr = 0 only
+ * computes the gradient).  loss (host, may be null) receives the loss before
+ * the update. */
+pfe_status pfe_mpnn_train_step(pfe_mpnn* net, pfe_ctx* c, const void* samples, int k, float lr,
+                               double* loss);
+
+/* Evaluate the network on the context's A and switch its PCG to
+ * M^{-1} = G^T G (PFE_LEARNED).  The factor is kept until the next call;
+ * pfe_set_penalties recomputes A but not the factor. */
+pfe_status pfe_set_learned(pfe_ctx* c, pfe_mpnn* net);
+/* Switch between PFE_JACOBI and PFE_LEARNED (which needs pfe_set_learned first). */
+pfe_status pfe_set_preconditioner(pfe_ctx* c, int precond);
+/* Copy the current factor: per undirected edge (lexicographic (i, j), i < j)
+ * the entry Gt_ji, and the diagonal (device buffers, context element type). */
+pfe_status pfe_get_factor(pfe_ctx* c, void* edge_vals, void* diag);
 
 /* q-quantile of |M Y| over all |E| x d entries for the current Y (the order
  * statistic of rank floor(q (N - 1)) among the N values, computed in the

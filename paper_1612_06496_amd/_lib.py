@@ -28,7 +28,8 @@ PFE_JACOBI, PFE_LEARNED = 0, 1
 PFE_POLAR, PFE_CHOL = 0, 1
 PFE_FP32, PFE_FP64 = 0, 1
 PFE_INNER, PFE_OUTER = 0, 1
-PFE_Y, PFE_P, PFE_B, PFE_YHAT, PFE_BSPLIT, PFE_DSPLIT, PFE_RHS = range(7)
+PFE_Y, PFE_P, PFE_B, PFE_YHAT, PFE_BSPLIT, PFE_DSPLIT, PFE_RHS, PFE_RESID = range(8)
+PFE_MPNN_NPARAMS = 722
 
 
 class pfe_graph_desc(C.Structure):
@@ -85,6 +86,14 @@ SIGNATURES = {
     "pfe_apply_A": (_S, [_P, _P, _P]),
     "pfe_pcg": (_S, [_P, _P, _P, C.POINTER(C.c_int32), C.POINTER(pfe_step_info)]),
     "pfe_edge_quantile": (_S, [_P, C.c_double, C.POINTER(C.c_double)]),
+    "pfe_mpnn_create": (_S, [_P, C.POINTER(_P)]),
+    "pfe_mpnn_get_params": (_S, [_P, _P, _P]),
+    "pfe_mpnn_set_params": (_S, [_P, _P]),
+    "pfe_mpnn_destroy": (None, [_P]),
+    "pfe_mpnn_train_step": (_S, [_P, _P, _P, C.c_int, C.c_float, C.POINTER(C.c_double)]),
+    "pfe_set_learned": (_S, [_P, _P]),
+    "pfe_set_preconditioner": (_S, [_P, C.c_int]),
+    "pfe_get_factor": (_S, [_P, _P, _P]),
     "pfe_destroy_ctx": (None, [_P]),
     "pfe_stream_copy": (_S, [_P, _P, C.c_size_t, _P]),
     "pfe_status_string": (C.c_char_p, [C.c_int]),

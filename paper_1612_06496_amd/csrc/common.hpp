@@ -48,6 +48,30 @@ struct alignas(64) Scal {
 
 }  // namespace pfe
 
+struct pfe_mpnn;
+
+namespace pfe {
+// graph and system seen by the learned-preconditioner network
+struct NetGraph {
+    int64_t n = 0, nslot = 0;
+    int ell_K = 0, deg_max = 0;
+    const int* rowptr = nullptr;
+    const int* scol = nullptr;
+    const int* seid = nullptr;
+    const double* sw64 = nullptr;
+    const double* degree = nullptr;
+    const double* wsq = nullptr;
+    double lambda = 0.0, r = 0.0;
+};
+// Gt on every slot and its diagonal, in the context's element type
+pfe_status mpnn_factor(pfe_mpnn* w, const NetGraph& g, void* gval, void* gdiag, int esz, hipStream_t st);
+// one training step (lr == 0: gradient only) on k residual samples
+pfe_status mpnn_train_step(pfe_mpnn* w, const NetGraph& g, const void* samples, int esz, int kc, float lr,
+                           double* loss, hipStream_t st);
+}  // namespace pfe
+
+#define PFE_TRY_STATUS(x) do { pfe_status s__ = (x); if (s__ != PFE_OK) return s__; } while (0)
+
 #define PFE_CHECK_HIP(expr)                                                   \
     do {                                                                      \
         hipError_t e__ = (expr);                                              \

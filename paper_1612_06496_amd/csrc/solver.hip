@@ -44,7 +44,12 @@ enum Phase : int {
     PH_GRAM = 5,    // Z = D^{1/2} Y + B, Z^T Z
     PH_APPLY = 6,   // P = Z T, B = Z - P
     PH_RHS = 7,     // rhs from stored b, d (no r0)
-    PH_ZERO = 8     // zero the solution columns whose rhs is zero
+    PH_ZERO = 8,    // zero the solution columns whose rhs is zero
+    // PCG with the learned factor M^{-1} = D_A^{-1/2} Gt^T Gt D_A^{-1/2}
+    PH_LA = 9,      // p = z + beta p, q = A p, p.q
+    PH_LB = 10,     // x += alpha p, r -= alpha q
+    PH_LC = 11,     // y1 = Gt D_A^{-1/2} r
+    PH_LD = 12      // z = D_A^{-1/2} Gt^T y1, r.z, r.r
 };
 
 // per (segment, column) CG state, struct of arrays of length nseg * d
@@ -84,6 +89,11 @@ struct KA {
     T* wb[2];          // w = A u
     T* sb[2];          // s = A p
     T* p;
+    const T* gval;     // learned factor: Gt entry of each slot's edge
+    const T* gdiag;    // its diagonal
+    const T* isq;      // D_A^{-1/2}
+    T* zl;             // preconditioned residual (learned path)
+    T* y1;             // Gt D_A^{-1/2} r
     double* part;      // workgroup partials
     double* gpart;     // per-XCD-group partials
     double* Tm;        // d x d transforms (stride kMaxD), one per segment
@@ -379,6 +389,111 @@ __device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh) {
     block_partials<3>(acc, sh, d, R, a.part, a.nblk, lb);
 }
 
+// Learned-preconditioner PCG phases.  Buffers: r = rb[0], q = wb[0], p double
+// buffered in sb[it & 1] (new) / sb[(it & 1) ^ 1] (previous).
+template <typename T>
+__device__ __forceinline__ void ph_lc(const KA<T>& a, int lb) {
+    const int d = a.d, R = a.R, t = threadIdx.x;
+    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const T* r = a.rb[0];
+    if (t >= R * d) return;
+    const int rl = t / d, c = t - rl * d;
+    for (int i = rb + rl; i < re; i += R) {
+        const size_t e = (size_t)i * d + c;
+        int s0, cnt, st;
+        row_slots(a, i, s0, cnt, st);
+        T acc = mul_t(a.gdiag[i], mul_t(a.isq[i], r[e]));
+        for (int k = 0; k < cnt; ++k) {
+            const int s = s0 + k * st;
+            const int j = a.scol[s];
+            if (j < i) acc = fma_t(a.gval[s], mul_t(a.isq[j], r[(size_t)j * d + c]), acc);
+        }
+        a.y1[e] = acc;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void ph_ld(const KA<T>& a, int lb, double* sh) {
+    const int d = a.d, R = a.R, t = threadIdx.x;
+    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const T* r = a.rb[0];
+    double acc2[2] = {0.0, 0.0};
+    if (t < R * d) {
+        const int rl = t / d, c = t - rl * d;
+        for (int i = rb + rl; i < re; i += R) {
+            const size_t e = (size_t)i * d + c;
+            int s0, cnt, st;
+            row_slots(a, i, s0, cnt, st);
+            T acc = mul_t(a.gdiag[i], a.y1[e]);
+            for (int k = 0; k < cnt; ++k) {
+                const int s = s0 + k * st;
+                const int j = a.scol[s];
+                if (j > i) acc = fma_t(a.gval[s], a.y1[(size_t)j * d + c], acc);
+            }
+            const T z = mul_t(a.isq[i], acc);
+            a.zl[e] = z;
+            const T rv = r[e];
+            acc2[0] += (double)rv * (double)z;
+            acc2[1] += (double)rv * (double)rv;
+        }
+    }
+    block_partials<2>(acc2, sh, d, R, a.part, a.nblk, lb);
+}
+
+template <typename T>
+__device__ __forceinline__ void ph_la(const KA<T>& a, int lb, double* sh) {
+    const int d = a.d, R = a.R, t = threadIdx.x;
+    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const int it = ld_flag(&a.S->it);
+    const bool first = (it == 0);
+    T* pnew = a.sb[it & 1];
+    const T* pold = a.sb[(it & 1) ^ 1];
+    T* q = a.wb[0];
+    const int sg = a.blk_seg[lb];
+    double acc1[1] = {0.0};
+    if (t < R * d) {
+        const int rl = t / d, c = t - rl * d;
+        const T beta = (T)a.cs.beta[sg * d + c];
+        for (int i = rb + rl; i < re; i += R) {
+            const size_t e = (size_t)i * d + c;
+            int s0, cnt, st;
+            row_slots(a, i, s0, cnt, st);
+            const T pi = first ? a.zl[e] : fma_t(beta, pold[e], a.zl[e]);
+            T acc = T(0);
+            for (int k = 0; k < cnt; ++k) {
+                const int s = s0 + k * st;
+                const size_t ej = (size_t)a.scol[s] * d + c;
+                const T ww = a.sw[s];
+                const T pj = first ? a.zl[ej] : fma_t(beta, pold[ej], a.zl[ej]);
+                acc = fma_t(mul_t(ww, ww), pj, acc);
+            }
+            const T qi = fma_t(a.diagA[i], pi, -mul_t(a.c_off, acc));
+            pnew[e] = pi;
+            q[e] = qi;
+            acc1[0] += (double)pi * (double)qi;
+        }
+    }
+    block_partials<1>(acc1, sh, d, R, a.part, a.nblk, lb);
+}
+
+template <typename T>
+__device__ __forceinline__ void ph_lb(const KA<T>& a, int lb) {
+    const int d = a.d, R = a.R, t = threadIdx.x;
+    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const int it = ld_flag(&a.S->it);
+    const T* p = a.sb[it & 1];
+    const T* q = a.wb[0];
+    T* r = a.rb[0];
+    if (t >= R * d) return;
+    const int rl = t / d, c = t - rl * d;
+    const T alpha = (T)a.cs.alpha[a.blk_seg[lb] * d + c];
+    for (int i = rb + rl; i < re; i += R) {
+        const size_t e = (size_t)i * d + c;
+        a.x[e] = fma_t(alpha, p[e], a.x[e]);
+        r[e] = fma_t(-alpha, q[e], r[e]);
+    }
+}
+
 // PH_ZERO: x_c = 0 for columns with a zero right-hand side
 template <typename T>
 __device__ __forceinline__ void ph_zero(const KA<T>& a, int lb) {
@@ -591,6 +706,84 @@ __device__ __forceinline__ void fin_it(const KA<T>& a, double* sh, bool grouped)
             any = 0;
         }
         a.S->done = !any;
+    }
+}
+
+// learned path, after PH_LD: initial (before the first iteration) or after an
+// iteration: convergence on ||r||, beta = (r.z)_new / (r.z)_old
+template <typename T>
+__device__ __forceinline__ void fin_ld(const KA<T>& a, double* sh, bool initial) {
+    const int d = a.d;
+    double* out = sh + 1024;
+    __shared__ int s_any, s_bad;
+    if (threadIdx.x == 0) { s_any = 0; s_bad = 0; }
+    for (int sg = 0; sg < a.nseg; ++sg) {
+        seg_sums(a, sg, 2, d, out, sh, false);
+        if (threadIdx.x < d) {
+            const int c = threadIdx.x, ci = sg * d + c;
+            int act = a.cs.active[ci];
+            double g = out[c], rr = out[d + c];
+            if (initial) {
+                a.cs.gamma[ci] = g;
+                a.cs.beta[ci] = 0.0;
+                if (act && !(g > 0.0)) { s_bad = 1; act = 0; }
+            } else if (act) {
+                a.cs.iters[ci] += 1;
+                a.cs.rr[ci] = rr;
+                act = rr > a.tol2 * a.cs.bnorm2[ci];
+                if (!isfinite(rr)) { s_bad = 1; act = 0; }
+                if (act) {
+                    double be = g / a.cs.gamma[ci];
+                    if (!isfinite(be)) { s_bad = 1; act = 0; be = 0.0; }
+                    a.cs.beta[ci] = be;
+                    a.cs.gamma[ci] = g;
+                }
+            }
+            if (!act) { a.cs.alpha[ci] = 0.0; a.cs.beta[ci] = 0.0; }
+            a.cs.active[ci] = act;
+            if (act) atomicOr(&s_any, 1);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int any = s_any;
+        if (s_bad) a.S->status = PFE_E_NOT_SPD;
+        if (!initial) {
+            int it = a.S->it + 1;
+            a.S->it = it;
+            if (any && it >= a.maxit) {
+                if (a.S->status == 0) a.S->status = PFE_E_NOCONV;
+                any = 0;
+            }
+        }
+        a.S->done = !any;
+    }
+}
+
+// learned path, after PH_LA: alpha = (r.z) / (p.q)
+template <typename T>
+__device__ __forceinline__ void fin_la(const KA<T>& a, double* sh) {
+    const int d = a.d;
+    double* out = sh + 1024;
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    for (int sg = 0; sg < a.nseg; ++sg) {
+        seg_sums(a, sg, 1, d, out, sh, false);
+        if (threadIdx.x < d) {
+            const int c = threadIdx.x, ci = sg * d + c;
+            double al = 0.0;
+            if (a.cs.active[ci]) {
+                double pq = out[c];
+                al = a.cs.gamma[ci] / pq;
+                if (!(pq > 0.0) || !isfinite(al)) { s_bad = 1; al = 0.0; }
+            }
+            a.cs.alpha[ci] = al;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && s_bad) {
+        a.S->status = PFE_E_NOT_SPD;
+        a.S->done = 1;
     }
 }
 
@@ -897,7 +1090,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_phase(KA<T> a, int ph, int mode, int do_r0) {
     __shared__ double sh[kSmemDoubles];
     const int lb = logical_block(a.nblk);
-    if ((ph == PH_IT || ph == PH_W0) && ld_flag(&a.S->done)) return;
+    if ((ph == PH_IT || ph == PH_W0 || ph >= PH_LA) && ld_flag(&a.S->done)) return;
     switch (ph) {
         case PH_E0: case PH_EU: case PH_R0: case PH_RHS:
             ph_residual(a, lb, ph, do_r0, a.b_zero, sh);
@@ -916,6 +1109,23 @@ __global__ void __launch_bounds__(kBlock) k_phase(KA<T> a, int ph, int mode, int
             break;
         case PH_ZERO:
             ph_zero(a, lb);
+            break;
+        case PH_LA:
+            ph_la(a, lb, sh);
+            if (last_block(a.bar + kBarLast, a.nblk)) fin_la(a, sh);
+            break;
+        case PH_LB:
+            ph_lb(a, lb);
+            break;
+        case PH_LC:
+            ph_lc(a, lb);
+            break;
+        case PH_LD:
+            ph_ld(a, lb, sh);
+            if (last_block(a.bar + kBarLast, a.nblk)) {
+                fin_ld(a, sh, mode != 0);
+                if (threadIdx.x == 0 && a.S->done) solve_stats(a);
+            }
             break;
         case PH_GRAM:
             ph_gram(a, lb, mode, sh);
@@ -1009,12 +1219,13 @@ __global__ void __launch_bounds__(kBlock) k_spmm(KA<T> a, const T* __restrict__ 
 // diagonal of A = lambda/2 M^T M + r/2 D in FP64, and D^{+-1/2}
 template <typename T>
 __global__ void k_diag(int n, const double* __restrict__ degree, const double* __restrict__ wsq,
-                       double half_lam, double half_r, T* diagA, T* invdiag, T* sqrtD, T* isqrtD) {
+                       double half_lam, double half_r, T* diagA, T* invdiag, T* sqrtD, T* isqrtD, T* isq) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double da = half_lam * wsq[i] + half_r * degree[i];
     diagA[i] = (T)da;
     invdiag[i] = (T)(1.0 / da);
+    isq[i] = (T)(1.0 / sqrt(da));
     sqrtD[i] = (T)sqrt(degree[i]);
     isqrtD[i] = (T)(1.0 / sqrt(degree[i]));
 }
@@ -1056,6 +1267,12 @@ __global__ void k_edges_to_slots(KA<T> a, const int* __restrict__ seid, const T*
         bool up = a.scol[sl] > i;
         for (int c = 0; c < d; ++c) s[so + c] = up ? e[eo + c] : -e[eo + c];
     }
+}
+
+template <typename T>
+__global__ void k_fill(size_t n, T v, T* __restrict__ out) {
+    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) out[e] = v;
 }
 
 template <typename T>
@@ -1226,6 +1443,12 @@ struct pfe_ctx {
     void* wb[2] = {nullptr, nullptr};
     void* sb[2] = {nullptr, nullptr};
     void* diagA = nullptr; void* invdiag = nullptr; void* sqrtD = nullptr; void* isqrtD = nullptr;
+    void* isq = nullptr;       // D_A^{-1/2}
+    void* gval = nullptr;      // learned factor per slot
+    void* gdiag = nullptr;
+    void* zl = nullptr;
+    void* y1 = nullptr;
+    int have_factor = 0;
     double* part = nullptr;
     double* gpart = nullptr;
     double* Tm = nullptr;
@@ -1331,6 +1554,11 @@ KA<T> make_args(pfe_ctx* c, const Partition& pt) {
         a.sb[k] = (T*)c->sb[k];
     }
     a.p = (T*)c->p;
+    a.gval = (const T*)c->gval;
+    a.gdiag = (const T*)c->gdiag;
+    a.isq = (const T*)c->isq;
+    a.zl = (T*)c->zl;
+    a.y1 = (T*)c->y1;
     a.part = c->part;
     a.gpart = c->gpart;
     a.Tm = c->Tm;
@@ -1376,11 +1604,41 @@ pfe_status pcg_loop_mk(pfe_ctx* c, const KA<T>& a) {
     return PFE_OK;
 }
 
+// Multi-launch PCG with the learned factor after a residual phase (r0 in rb[0]).
+template <typename T>
+pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a) {
+    hipLaunchKernelGGL(k_stats_if_done<T>, dim3(1), dim3(64), 0, c->stream, a);
+    PFE_TRY(launch_phase(c, a, PH_LC, 0, 0));
+    PFE_TRY(launch_phase(c, a, PH_LD, 1, 0));     // initial r.z
+    int it = 0;
+    const int chunk = 4;
+    int done = 0;
+    while (true) {
+        for (int k = 0; k < chunk; ++k) {
+            PFE_TRY(launch_phase(c, a, PH_LA, 0, 0));
+            PFE_TRY(launch_phase(c, a, PH_LB, 0, 0));
+            PFE_TRY(launch_phase(c, a, PH_LC, 0, 0));
+            PFE_TRY(launch_phase(c, a, PH_LD, 0, 0));
+        }
+        it += chunk;
+        PFE_CHECK_HIP(hipMemcpyAsync(&done, &c->S->done, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        PFE_CHECK_HIP(hipStreamSynchronize(c->stream));
+        if (done || it > c->prm.maxit + chunk) break;
+    }
+    PFE_TRY(launch_phase(c, a, PH_ZERO, 0, 0));
+    return PFE_OK;
+}
+
+template <typename T>
+pfe_status pcg_any_mk(pfe_ctx* c, const KA<T>& a) {
+    return (c->prm.precond == PFE_LEARNED) ? pcg_loop_learned_mk(c, a) : pcg_loop_mk(c, a);
+}
+
 template <typename T>
 pfe_status inner_mk(pfe_ctx* c) {
     KA<T> a = make_args<T>(c, c->pm);
     PFE_TRY(launch_phase(c, a, (c->inner == 0) ? PH_E0 : PH_R0, 0, 1));
-    PFE_TRY(pcg_loop_mk(c, a));
+    PFE_TRY(pcg_any_mk(c, a));
     // edge update of this inner step and rhs of the next one
     KA<T> b = a;
     b.store_rhs = 1;
@@ -1470,14 +1728,15 @@ pfe_status set_diag(pfe_ctx* c) {
     int n = (int)c->n;
     hipLaunchKernelGGL(k_diag<T>, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, c->g->degree, c->g->wsq,
                        0.5 * c->prm.lambda, 0.5 * c->prm.r, (T*)c->diagA, (T*)c->invdiag, (T*)c->sqrtD,
-                       (T*)c->isqrtD);
+                       (T*)c->isqrtD, (T*)c->isq);
     PFE_CHECK_HIP(hipGetLastError());
     return PFE_OK;
 }
 
 void free_ctx(pfe_ctx* c) {
     void* bufs[] = {c->Y, c->P, c->B, c->bs, c->ds, c->rhs, c->p, c->rb[0], c->rb[1], c->wb[0], c->wb[1],
-                    c->sb[0], c->sb[1], c->diagA, c->invdiag, c->sqrtD, c->isqrtD, c->part, c->gpart,
+                    c->sb[0], c->sb[1], c->diagA, c->invdiag, c->sqrtD, c->isqrtD, c->isq, c->gval, c->gdiag,
+                    c->zl, c->y1, c->part, c->gpart,
                     c->Tm, c->colbuf, c->colint, c->S, c->bar, c->hist};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
@@ -1491,7 +1750,7 @@ bool params_ok(const pfe_params* p, int64_t n) {
     if (!(p->r > 0.0) || !std::isfinite(p->r)) { set_error("r must be > 0"); return false; }
     if (p->n_inner < 1) { set_error("n_inner must be >= 1"); return false; }
     if (!(p->tol > 0.0) || p->maxit < 1) { set_error("tol must be > 0 and maxit >= 1"); return false; }
-    if (p->precond != PFE_JACOBI) { set_error("preconditioner not available"); return false; }
+    if (p->precond != PFE_JACOBI && p->precond != PFE_LEARNED) { set_error("unknown preconditioner"); return false; }
     if (p->ortho != PFE_POLAR && p->ortho != PFE_CHOL) { set_error("unknown ortho mode"); return false; }
     if (p->dtype != PFE_FP32 && p->dtype != PFE_FP64) { set_error("unknown dtype"); return false; }
     return true;
@@ -1587,6 +1846,55 @@ pfe_status launch_spmm(pfe_ctx* c, const KA<T>& a, const T* X, T* Q) {
     return PFE_OK;
 }
 
+// Gt = I (Jacobi) until a network is evaluated on the context
+template <typename T>
+pfe_status identity_factor(pfe_ctx* c) {
+    const size_t ns = (size_t)c->g->nslot + 1, n = (size_t)c->n;
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, c->stream, ns, T(0), (T*)c->gval);
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, T(1), (T*)c->gdiag);
+    PFE_CHECK_HIP(hipGetLastError());
+    c->have_factor = 0;
+    return PFE_OK;
+}
+
+NetGraph net_graph(const pfe_ctx* c) {
+    NetGraph ng;
+    ng.n = c->n;
+    ng.nslot = c->g->nslot;
+    ng.ell_K = c->g->ell_K;
+    ng.deg_max = c->g->max_deg;
+    ng.rowptr = c->g->rowptr;
+    ng.scol = c->g->s_col;
+    ng.seid = c->g->s_eid;
+    ng.sw64 = c->g->s_w64;
+    ng.degree = c->g->degree;
+    ng.wsq = c->g->wsq;
+    ng.lambda = c->prm.lambda;
+    ng.r = c->prm.r;
+    return ng;
+}
+
+template <typename T>
+pfe_status residual_to(pfe_ctx* c, void* dst) {
+    KA<T> a = make_args<T>(c, c->pm);
+    PFE_TRY(launch_phase(c, a, (c->inner == 0) ? PH_E0 : PH_R0, 0, 1));
+    PFE_CHECK_HIP(hipMemcpyAsync(dst, c->rb[0], (size_t)c->n * c->d * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    return PFE_OK;
+}
+
+template <typename T>
+pfe_status factor_to_edges(pfe_ctx* c, void* edge_vals, void* diag) {
+    KA<T> a = make_args<T>(c, c->pm);
+    a.d = 1;
+    const int n = (int)c->n;
+    if (edge_vals)
+        hipLaunchKernelGGL(k_slots_to_edges<T>, dim3((n + 255) / 256), dim3(256), 0, c->stream, a, c->g->s_eid,
+                           (const T*)c->gval, (T*)edge_vals);
+    if (diag) PFE_CHECK_HIP(hipMemcpyAsync(diag, c->gdiag, sizeof(T) * n, hipMemcpyDeviceToDevice, c->stream));
+    PFE_CHECK_HIP(hipGetLastError());
+    return PFE_OK;
+}
+
 template <typename T>
 pfe_status rebuild_rhs(pfe_ctx* c) {
     KA<T> a = make_args<T>(c, c->pm);
@@ -1649,7 +1957,8 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
     if (p->keep_split) ALLOC(c->ds, sd);
     ALLOC(c->rhs, nd); ALLOC(c->p, nd);
     for (int k = 0; k < 2; ++k) { ALLOC(c->rb[k], nd); ALLOC(c->wb[k], nd); ALLOC(c->sb[k], nd); }
-    ALLOC(c->diagA, nv); ALLOC(c->invdiag, nv); ALLOC(c->sqrtD, nv); ALLOC(c->isqrtD, nv);
+    ALLOC(c->diagA, nv); ALLOC(c->invdiag, nv); ALLOC(c->sqrtD, nv); ALLOC(c->isqrtD, nv); ALLOC(c->isq, nv);
+    ALLOC(c->gval, (size_t)(g->nslot + 1) * c->esz); ALLOC(c->gdiag, nv); ALLOC(c->zl, nd); ALLOC(c->y1, nd);
     ALLOC(c->part, sizeof(double) * part_doubles);
     ALLOC(c->gpart, sizeof(double) * kNumXcd * std::max(3 * kMaxD, kMaxD * (kMaxD + 1) / 2));
     ALLOC(c->Tm, sizeof(double) * c->nseg * kMaxD * kMaxD);
@@ -1685,6 +1994,8 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
             break;
         }
         s = (p->dtype == PFE_FP64) ? set_diag<double>(c) : set_diag<float>(c);
+        if (s != PFE_OK) break;
+        s = (p->dtype == PFE_FP64) ? identity_factor<double>(c) : identity_factor<float>(c);
         if (s != PFE_OK) break;
         if (p->init_ortho) {
             s = (p->dtype == PFE_FP64) ? ortho_mk<double>(c, 1) : ortho_mk<float>(c, 1);
@@ -1742,7 +2053,7 @@ pfe_status pfe_step(pfe_ctx* c, int granularity, pfe_step_info* info) {
         if (c->inner >= c->prm.n_inner) { set_error("all inner iterations done; call pfe_step(PFE_OUTER)"); return PFE_E_STATE; }
         s = f64 ? inner_mk<double>(c) : inner_mk<float>(c);
     } else if (granularity == PFE_OUTER) {
-        if (c->prm.persistent && c->pc.nblk > 0 && c->inner == 0)
+        if (c->prm.persistent && c->pc.nblk > 0 && c->inner == 0 && c->prm.precond == PFE_JACOBI)
             s = f64 ? outer_coop<double>(c, 1) : outer_coop<float>(c, 1);
         else
             s = f64 ? outer_mk<double>(c) : outer_mk<float>(c);
@@ -1759,7 +2070,7 @@ pfe_status pfe_solve(pfe_ctx* c, int n_outer, pfe_step_info* info) {
     if (!c || n_outer < 0) { set_error("pfe_solve: bad argument"); return PFE_E_ARG; }
     if (info) PFE_TRY(reset_stats(c));
     const bool f64 = c->prm.dtype == PFE_FP64;
-    if (c->prm.persistent && c->pc.nblk > 0 && n_outer > 0) {
+    if (c->prm.persistent && c->pc.nblk > 0 && n_outer > 0 && c->prm.precond == PFE_JACOBI) {
         PFE_TRY(f64 ? outer_coop<double>(c, n_outer) : outer_coop<float>(c, n_outer));
     } else {
         for (int k = 0; k < n_outer; ++k) PFE_TRY(f64 ? outer_mk<double>(c) : outer_mk<float>(c));
@@ -1785,6 +2096,7 @@ pfe_status pfe_get(pfe_ctx* c, int which, void* dst) {
         case PFE_P: PFE_CHECK_HIP(hipMemcpyAsync(dst, c->P, nd, hipMemcpyDeviceToDevice, st)); break;
         case PFE_B: PFE_CHECK_HIP(hipMemcpyAsync(dst, c->B, nd, hipMemcpyDeviceToDevice, st)); break;
         case PFE_RHS: PFE_CHECK_HIP(hipMemcpyAsync(dst, c->rhs, nd, hipMemcpyDeviceToDevice, st)); break;
+        case PFE_RESID: PFE_TRY(c->esz == 8 ? residual_to<double>(c, dst) : residual_to<float>(c, dst)); break;
         case PFE_YHAT: {
             size_t ne = (size_t)c->n * c->d;
             if (c->esz == 8)
@@ -1885,18 +2197,51 @@ pfe_status pfe_pcg(pfe_ctx* c, const void* RHS, void* X, int32_t* iters, pfe_ste
         a.x = (double*)X;
         a.rhs = (double*)RHS;
         PFE_TRY(launch_phase(c, a, PH_R0, 0, 1));
-        PFE_TRY(pcg_loop_mk(c, a));
+        PFE_TRY(pcg_any_mk(c, a));
     } else {
         KA<float> a = make_args<float>(c, c->pm);
         a.x = (float*)X;
         a.rhs = (float*)RHS;
         PFE_TRY(launch_phase(c, a, PH_R0, 0, 1));
-        PFE_TRY(pcg_loop_mk(c, a));
+        PFE_TRY(pcg_any_mk(c, a));
     }
     if (iters) {
         PFE_CHECK_HIP(hipMemcpyAsync(iters, c->cs.iters, sizeof(int) * c->d, hipMemcpyDeviceToHost, c->stream));
     }
     return read_info(c, info);
+}
+
+pfe_status pfe_set_learned(pfe_ctx* c, pfe_mpnn* net) {
+    if (!c || !net) { set_error("pfe_set_learned: null argument"); return PFE_E_ARG; }
+    PFE_TRY(mpnn_factor(net, net_graph(c), c->gval, c->gdiag, c->esz, c->stream));
+    PFE_CHECK_HIP(hipStreamSynchronize(c->stream));
+    c->have_factor = 1;
+    c->prm.precond = PFE_LEARNED;
+    return PFE_OK;
+}
+
+pfe_status pfe_set_preconditioner(pfe_ctx* c, int precond) {
+    if (!c) { set_error("null context"); return PFE_E_ARG; }
+    if (precond != PFE_JACOBI && precond != PFE_LEARNED) { set_error("unknown preconditioner"); return PFE_E_ARG; }
+    c->prm.precond = precond;
+    return PFE_OK;
+}
+
+pfe_status pfe_get_factor(pfe_ctx* c, void* edge_vals, void* diag) {
+    if (!c) { set_error("pfe_get_factor: null context"); return PFE_E_ARG; }
+    PFE_TRY(c->esz == 8 ? factor_to_edges<double>(c, edge_vals, diag) : factor_to_edges<float>(c, edge_vals, diag));
+    PFE_CHECK_HIP(hipStreamSynchronize(c->stream));
+    return PFE_OK;
+}
+
+pfe_status pfe_mpnn_train_step(pfe_mpnn* net, pfe_ctx* c, const void* samples, int k, float lr, double* loss) {
+    if (!net || !c || !samples || k < 1 || k > 32 || !(lr >= 0.f)) {
+        set_error("pfe_mpnn_train_step: bad argument (1 <= k <= 32, lr >= 0)");
+        return PFE_E_ARG;
+    }
+    PFE_TRY(mpnn_train_step(net, net_graph(c), samples, c->esz, k, lr, loss, c->stream));
+    PFE_CHECK_HIP(hipStreamSynchronize(c->stream));
+    return PFE_OK;
 }
 
 pfe_status pfe_edge_quantile(pfe_ctx* c, double q, double* out) {

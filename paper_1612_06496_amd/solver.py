@@ -13,7 +13,7 @@ import torch
 from . import _lib as L
 
 _WHICH = {"Y": L.PFE_Y, "P": L.PFE_P, "B": L.PFE_B, "Yhat": L.PFE_YHAT,
-          "b": L.PFE_BSPLIT, "d": L.PFE_DSPLIT, "rhs": L.PFE_RHS}
+          "b": L.PFE_BSPLIT, "d": L.PFE_DSPLIT, "rhs": L.PFE_RHS, "resid": L.PFE_RESID}
 
 
 def _stream_handle(stream: Optional[torch.cuda.Stream]) -> C.c_void_p:
@@ -174,6 +174,22 @@ class Solver:
         L.check(st, "pfe_pcg", allow=(L.PFE_E_NOCONV,) if allow_noconv else ())
         return x, np.array(list(iters)), self._info_dict(inf)
 
+    # -- learned preconditioner ------------------------------------------------
+    def set_learned(self, net: "Mpnn") -> None:
+        """Evaluate the network on this system and precondition with G^T G."""
+        L.check(L.lib.pfe_set_learned(self._h, net._h), "pfe_set_learned")
+
+    def set_preconditioner(self, which: str) -> None:
+        L.check(L.lib.pfe_set_preconditioner(self._h, L.PFE_LEARNED if which == "learned" else L.PFE_JACOBI),
+                "pfe_set_preconditioner")
+
+    def get_factor(self):
+        """(Gt_ji per undirected edge (i < j, lexicographic), diag(Gt))."""
+        ev = torch.empty(self.graph.n_edges, dtype=self.dtype, device="cuda")
+        dg = torch.empty(self.n, dtype=self.dtype, device="cuda")
+        L.check(L.lib.pfe_get_factor(self._h, ev.data_ptr(), dg.data_ptr()), "pfe_get_factor")
+        return ev, dg
+
     def edge_quantile(self, q: float) -> float:
         out = C.c_double()
         L.check(L.lib.pfe_edge_quantile(self._h, q, C.byref(out)), "pfe_edge_quantile")
@@ -182,6 +198,57 @@ class Solver:
     def close(self):
         if getattr(self, "_h", None):
             L.lib.pfe_destroy_ctx(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mpnn:
+    """The learned-preconditioner network (weights + Adam state on the device)."""
+
+    NPARAMS = L.PFE_MPNN_NPARAMS
+
+    def __init__(self, params=None):
+        h = C.c_void_p()
+        if params is None:
+            L.check(L.lib.pfe_mpnn_create(None, C.byref(h)), "pfe_mpnn_create")
+        else:
+            p = np.ascontiguousarray(params, dtype=np.float32)
+            assert p.size == self.NPARAMS
+            L.check(L.lib.pfe_mpnn_create(p.ctypes.data, C.byref(h)), "pfe_mpnn_create")
+        self._h = h
+
+    @property
+    def params(self) -> np.ndarray:
+        out = np.empty(self.NPARAMS, dtype=np.float32)
+        L.check(L.lib.pfe_mpnn_get_params(self._h, out.ctypes.data, None), "pfe_mpnn_get_params")
+        return out
+
+    @property
+    def grad(self) -> np.ndarray:
+        out = np.empty(self.NPARAMS, dtype=np.float32)
+        L.check(L.lib.pfe_mpnn_get_params(self._h, None, out.ctypes.data), "pfe_mpnn_get_params")
+        return out
+
+    def set_params(self, params) -> None:
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        L.check(L.lib.pfe_mpnn_set_params(self._h, p.ctypes.data), "pfe_mpnn_set_params")
+
+    def train_step(self, solver: Solver, samples, lr: float) -> float:
+        """One Adam step (lr = 0: gradient only) on residual samples (n x k)."""
+        x = _dev(samples, solver.dtype)
+        loss = C.c_double()
+        L.check(L.lib.pfe_mpnn_train_step(self._h, solver._h, x.data_ptr(), x.shape[1], float(lr),
+                                          C.byref(loss)), "pfe_mpnn_train_step")
+        return loss.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib.pfe_mpnn_destroy(self._h)
             self._h = None
 
     def __del__(self):
