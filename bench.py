@@ -79,6 +79,78 @@ def copy_bandwidth(gib):
     return best
 
 
+def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0), captures=8, steps=300,
+                lr=3e-3, workload="voronoi1024_r2"):
+    """PCG iterations to 1e-6 with the learned preconditioner vs Jacobi.
+
+    Training data: initial residuals of PFE inner solves on held-out images
+    (training seeds), at every lambda/r of the sweep.  Evaluation: the
+    initial residual of the first inner solve on the evaluation image (seed 0),
+    solved from zero with each preconditioner (one launch per phase for both)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1612_06496_amd import Graph, Mpnn, Solver
+
+    t_start = time.perf_counter()
+    samples = []
+    keep = []
+    for seed in train_seeds:
+        wl = synth.make_workload(workload, seed)
+        G = Graph.grid(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
+        S = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=2000, persistent=False)
+        c = 1.0 / S.edge_quantile(0.99)
+        for ratio in ratios:
+            S.set_penalties(ratio * c, c)
+            S.inner_index = 0
+            for _ in range(captures):
+                samples.append((S, ratio * c, c, S.get("resid")))
+                S.step("inner", allow_noconv=True)
+        keep.append((G, S))
+    rng = np.random.default_rng(0)
+    init = rng.normal(0.0, 0.1, size=Mpnn.NPARAMS).astype(np.float32)
+    init[672:] = 0.0
+    init[721] = np.log(np.e - 1.0)
+    net = Mpnn(init)
+    losses = []
+    for t in range(steps):
+        S, lam, r, R = samples[rng.integers(len(samples))]
+        S.set_penalties(lam, r)
+        losses.append(net.train_step(S, R, lr))
+    t_train = time.perf_counter() - t_start
+
+    wl = synth.make_workload(workload, 0)
+    G = Graph.grid(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
+    S = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=5000, persistent=False)
+    c = 1.0 / S.edge_quantile(0.99)
+    rows = []
+    for ratio in ratios:
+        S.set_penalties(ratio * c, c)
+        S.inner_index = 0
+        r0 = S.get("resid")
+        x0 = torch.zeros_like(r0)
+        res = {"lambda_over_r": ratio}
+        for pre in ("jacobi", "learned"):
+            if pre == "learned":
+                S.set_learned(net)
+            else:
+                S.set_preconditioner("jacobi")
+            S.pcg(r0, x0)                      # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, it, info = S.pcg(r0, x0)
+            torch.cuda.synchronize()
+            res[pre] = {"iters_max": int(it.max()), "iters_mean": round(float(it.mean()), 2),
+                        "ms": round((time.perf_counter() - t0) * 1e3, 2),
+                        "rel_res": float(f"{info['rel_res_max']:.3g}")}
+        rows.append(res)
+    return {"workload": workload, "d": wl.d, "train_images": list(train_seeds), "train_steps": steps,
+            "train_samples": len(samples), "loss_first": round(losses[0], 4),
+            "loss_last10": round(float(np.mean(losses[-10:])), 4), "train_s": round(t_train, 1),
+            "launch": "one launch per phase (both preconditioners)", "sweep": rows}
+
+
 def cpu_baseline(wl, lam, r, n_steps=2):
     """The FP64 oracle on the host, on a bounded sample: n_steps SOC iterations
     of the same workload (sparse LU factorisation reported separately)."""
@@ -110,6 +182,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-gib", type=float, default=2.0, help="size of the copy-bandwidth probe")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-Jacobi PCG comparison")
     ap.add_argument("--multi-launch", action="store_true", help="one launch per phase instead of one per SOC iteration")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -170,11 +243,16 @@ def main():
                    "tol": wl.tol, "lambda": c, "r": c, "precond": "jacobi",
                    "launch": "multi" if args.multi_launch else "persistent"},
         "pcg_iters_per_solve": round(info["cg_iters_total"] / max(1, info["solves"]), 2),
-        "pcg_iters_learned": None,
+        "pcg_iters_learned": None,     # filled by the learned-vs-Jacobi leg below
         "monitor": {k: float(f"{v:.6g}") for k, v in mon.items()},
         "wall_s_timed": round(wall, 4),
         "roofline": roof,
     }
+    if not args.no_learned:
+        leg = learned_leg()
+        line["learned_vs_jacobi"] = leg
+        line["pcg_iters_learned"] = {str(r["lambda_over_r"]): [r["jacobi"]["iters_max"], r["learned"]["iters_max"]]
+                                     for r in leg["sweep"]}
     if args.copy_gib > 0:
         line["copy_gbs"] = round(copy_bandwidth(args.copy_gib), 1)
     if not args.no_cpu_baseline:
