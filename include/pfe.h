@@ -178,6 +178,25 @@ pfe_status pfe_graph_info(const pfe_graph* g, int64_t* n, int64_t* n_edges, int6
 pfe_status pfe_graph_csr(const pfe_graph* g, int32_t* rowptr, int32_t* col, float* w,
                          double* degree);
 
+/* Block-diagonal union of count graphs, for running a batch of independent
+ * problems (one PFE per part, Algorithms 1 and 2 applied to each) as one
+ * graph.  Vertex v of part p becomes vertex off_p + v with off_p the number of
+ * vertices in parts 0..p-1; its edges are renumbered the same way, so the
+ * per-edge blocks of the union are the parts' blocks one after another.  Each
+ * part becomes one segment (a part that is itself a union contributes its
+ * segments); a solver on the union keeps separate CG scalars, convergence and
+ * P-update (Gram matrix, constraint Yhat^T D Yhat = I) per segment.  The parts
+ * are only read (they may be destroyed afterwards) and must live on the
+ * current device.  The pixel-stencil slot layout is kept when every part has
+ * the same stencil.  Errors: PFE_E_ARG for a null part, count < 1, another
+ * device, or a union above 2^30 vertices / 2^31 slots. */
+pfe_status pfe_graph_union(const pfe_graph* const* parts, int count, hipStream_t stream, pfe_graph** out);
+
+/* Segments of a graph: *count (1 for a graph built by pfe_build_graph), and
+ * if non-null the host arrays row0[count + 1] (first vertex of each segment,
+ * then n) and edge0[count + 1] (first undirected edge, then |E|). */
+pfe_status pfe_graph_segments(const pfe_graph* g, int* count, int64_t* row0, int64_t* edge0);
+
 void pfe_destroy_graph(pfe_graph* g);
 
 /* ---- solver context ------------------------------------------------------ */
@@ -232,7 +251,8 @@ pfe_status pfe_apply_A(pfe_ctx* c, const void* X, void* Q);
 
 /* Solve A X = RHS by the context's PCG, X (device) holds the initial guess on
  * entry and the solution on return.  iters (host, may be null) receives the
- * per-column iteration counts (d ints). */
+ * per-column iteration counts (d ints; for a batch, the largest over its
+ * segments). */
 pfe_status pfe_pcg(pfe_ctx* c, const void* RHS, void* X, int32_t* iters, pfe_step_info* info);
 
 /* ---- learned preconditioner ---------------------------------------------------

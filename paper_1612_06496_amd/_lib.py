@@ -72,6 +72,8 @@ SIGNATURES = {
     "pfe_build_graph": (_S, [C.POINTER(pfe_graph_desc), _P, C.POINTER(_P)]),
     "pfe_graph_info": (_S, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "pfe_graph_csr": (_S, [_P, _P, _P, _P, _P]),
+    "pfe_graph_union": (_S, [_P, C.c_int, _P, C.POINTER(_P)]),
+    "pfe_graph_segments": (_S, [_P, C.POINTER(C.c_int), _P, _P]),
     "pfe_destroy_graph": (None, [_P]),
     "pfe_init": (_S, [_P, C.POINTER(pfe_params), _P, _P, C.POINTER(_P)]),
     "pfe_set_penalties": (_S, [_P, C.c_double, C.c_double]),

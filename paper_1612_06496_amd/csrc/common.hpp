@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstdio>
+#include <vector>
 
 #include "pfe.h"
 
@@ -106,4 +107,9 @@ struct pfe_graph {
     // Pixel grids: ELL slot k of every row is stencil offset k; slots that
     // leave the image have weight 0 and point at the row itself.
     int stencil = 0;
+    // Block-diagonal batches: segment s owns the vertices [seg_row0[s],
+    // seg_row0[s+1]) and the undirected edges [seg_edge0[s], seg_edge0[s+1]);
+    // a graph built from one description is a single segment.
+    std::vector<int64_t> seg_row0;
+    std::vector<int64_t> seg_edge0;
 };

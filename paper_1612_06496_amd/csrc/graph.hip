@@ -321,6 +321,14 @@ __global__ void k_build_stencil_ell(int H, int W, Stencil st, const int* __restr
     }
 }
 
+// dst[i] = src[i] + add (negative entries kept as they are when keep_neg)
+__global__ void k_add_int(int64_t n, const int* __restrict__ src, int add, int keep_neg, int* __restrict__ dst) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int v = src[i];
+    dst[i] = (keep_neg && v < 0) ? v : v + add;
+}
+
 __global__ void k_max_deg(int64_t n, const int* __restrict__ rowptr, int* __restrict__ out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -596,7 +604,139 @@ pfe_status pfe_build_graph(const pfe_graph_desc* d, hipStream_t stream, pfe_grap
         delete g;
         return s;
     }
+    g->seg_row0 = {0, g->n};
+    g->seg_edge0 = {0, g->n_edges};
     *out = g;
+    return PFE_OK;
+}
+
+pfe_status pfe_graph_union(const pfe_graph* const* parts, int count, hipStream_t stream, pfe_graph** out) {
+    g_err[0] = 0;
+    if (!parts || !out || count < 1) { set_error("pfe_graph_union: null argument or count < 1"); return PFE_E_ARG; }
+    *out = nullptr;
+    int dev = 0;
+    PFE_CHECK_HIP(hipGetDevice(&dev));
+    int64_t N = 0, SL = 0, E = 0, NS = 0;
+    int K = -1, max_deg = 0;
+    bool ell = true, sten = true;
+    for (int p = 0; p < count; ++p) {
+        const pfe_graph* q = parts[p];
+        if (!q) { set_error("pfe_graph_union: part %d is null", p); return PFE_E_ARG; }
+        if (q->device != dev) { set_error("pfe_graph_union: part %d lives on another device", p); return PFE_E_ARG; }
+        N += q->n;
+        SL += q->slots;
+        E += q->n_edges;
+        max_deg = std::max(max_deg, q->max_deg);
+        if (K < 0) K = q->ell_K;
+        ell = ell && q->ell_K > 0 && q->ell_K == K;
+        sten = sten && q->stencil;
+    }
+    if (N >= (int64_t)INT32_MAX / 2 || SL >= (int64_t)INT32_MAX) { set_error("pfe_graph_union: union too large"); return PFE_E_ARG; }
+    if (ell) {
+        NS = (int64_t)K * N;
+        if (NS >= (int64_t)INT32_MAX) ell = false;
+    }
+    pfe_graph* g = new pfe_graph();
+    g->device = dev;
+    g->stream = stream;
+    g->n = N;
+    g->slots = SL;
+    g->n_edges = E;
+    g->max_deg = max_deg;
+    auto fail = [&](pfe_status s) {
+        (void)hipStreamSynchronize(stream);
+        free_graph_buffers(g);
+        delete g;
+        return s;
+    };
+    hipError_t e = hipSuccess;
+#define UALLOC(ptr, bytes) do { if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (bytes)); } while (0)
+    UALLOC(g->rowptr, sizeof(int) * (N + 1));
+    UALLOC(g->col, sizeof(int) * (SL + 1));
+    UALLOC(g->rev, sizeof(int) * (SL + 1));
+    UALLOC(g->eid, sizeof(int) * (SL + 1));
+    UALLOC(g->w32, sizeof(float) * (SL + 1));
+    UALLOC(g->w64, sizeof(double) * (SL + 1));
+    UALLOC(g->degree, sizeof(double) * N);
+    UALLOC(g->wsq, sizeof(double) * N);
+    if (ell) {
+        UALLOC(g->s_col, sizeof(int) * NS);
+        UALLOC(g->s_w32, sizeof(float) * NS);
+        UALLOC(g->s_w64, sizeof(double) * NS);
+        UALLOC(g->s_eid, sizeof(int) * NS);
+    }
+#undef UALLOC
+    if (e != hipSuccess) {
+        if (!ell) g->ell_K = 0;   // nothing ELL-specific allocated
+        else g->ell_K = K;
+        return fail(hip_fail(e, "hipMalloc (graph union)", __FILE__, __LINE__));
+    }
+    g->ell_K = ell ? K : 0;
+    const int TB = 256;
+    int64_t V = 0, S = 0, Eo = 0;
+    g->seg_row0.assign(1, 0);
+    g->seg_edge0.assign(1, 0);
+    for (int p = 0; p < count; ++p) {
+        const pfe_graph* q = parts[p];
+        const int64_t n = q->n, sl = q->slots;
+        const unsigned gn = (unsigned)((n + TB - 1) / TB), gs = (unsigned)((sl + TB - 1) / TB);
+        hipLaunchKernelGGL(k_add_int, dim3(gn), dim3(TB), 0, stream, n, q->rowptr, (int)S, 0, g->rowptr + V);
+        if (sl > 0) {
+            hipLaunchKernelGGL(k_add_int, dim3(gs), dim3(TB), 0, stream, sl, q->col, (int)V, 0, g->col + S);
+            hipLaunchKernelGGL(k_add_int, dim3(gs), dim3(TB), 0, stream, sl, q->rev, (int)S, 0, g->rev + S);
+            hipLaunchKernelGGL(k_add_int, dim3(gs), dim3(TB), 0, stream, sl, q->eid, (int)Eo, 0, g->eid + S);
+            if (hipMemcpyAsync(g->w32 + S, q->w32, sizeof(float) * sl, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+                hipMemcpyAsync(g->w64 + S, q->w64, sizeof(double) * sl, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+                return fail(hip_fail(hipGetLastError(), "hipMemcpyAsync (graph union)", __FILE__, __LINE__));
+        }
+        if (hipMemcpyAsync(g->degree + V, q->degree, sizeof(double) * n, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(g->wsq + V, q->wsq, sizeof(double) * n, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+            return fail(hip_fail(hipGetLastError(), "hipMemcpyAsync (graph union)", __FILE__, __LINE__));
+        if (ell) {
+            for (int k = 0; k < K; ++k) {
+                const int64_t so = (int64_t)k * n, dO = (int64_t)k * N + V;
+                hipLaunchKernelGGL(k_add_int, dim3(gn), dim3(TB), 0, stream, n, q->s_col + so, (int)V, 0, g->s_col + dO);
+                hipLaunchKernelGGL(k_add_int, dim3(gn), dim3(TB), 0, stream, n, q->s_eid + so, (int)Eo, 1, g->s_eid + dO);
+                if (hipMemcpyAsync(g->s_w32 + dO, q->s_w32 + so, sizeof(float) * n, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+                    hipMemcpyAsync(g->s_w64 + dO, q->s_w64 + so, sizeof(double) * n, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+                    return fail(hip_fail(hipGetLastError(), "hipMemcpyAsync (graph union)", __FILE__, __LINE__));
+            }
+        }
+        hipError_t le = hipGetLastError();
+        if (le != hipSuccess) return fail(hip_fail(le, "graph union kernels", __FILE__, __LINE__));
+        V += n;
+        S += sl;
+        Eo += q->n_edges;
+        for (size_t k = 1; k < q->seg_row0.size(); ++k) {
+            g->seg_row0.push_back(g->seg_row0.back() + (q->seg_row0[k] - q->seg_row0[k - 1]));
+            g->seg_edge0.push_back(g->seg_edge0.back() + (q->seg_edge0[k] - q->seg_edge0[k - 1]));
+        }
+    }
+    const int last = (int)SL;
+    if (hipMemcpyAsync(g->rowptr + N, &last, sizeof(int), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return fail(hip_fail(hipGetLastError(), "graph union", __FILE__, __LINE__));
+    if (ell) {
+        g->nslot = NS;
+        g->stencil = sten ? 1 : 0;
+    } else {
+        g->nslot = SL;
+        g->s_col = g->col;
+        g->s_w32 = g->w32;
+        g->s_w64 = g->w64;
+        g->s_eid = g->eid;
+    }
+    *out = g;
+    return PFE_OK;
+}
+
+pfe_status pfe_graph_segments(const pfe_graph* g, int* count, int64_t* row0, int64_t* edge0) {
+    if (!g || !count) { set_error("pfe_graph_segments: null argument"); return PFE_E_ARG; }
+    *count = (int)g->seg_row0.size() - 1;
+    for (size_t k = 0; k < g->seg_row0.size(); ++k) {
+        if (row0) row0[k] = g->seg_row0[k];
+        if (edge0) edge0[k] = g->seg_edge0[k];
+    }
     return PFE_OK;
 }
 

@@ -216,6 +216,33 @@ __device__ __forceinline__ void seg_sums(const KA<T>& a, int sg, int nq, int d, 
     else reduce_range(a.part, a.nblk, a.seg_blk0[sg], a.seg_blk0[sg + 1], d, nq, out, sh);
 }
 
+// Sums for the segments [sg0, sg0 + ns) at once: out[(k * nq + q) * d + c] for
+// segment sg0 + k.  One segment: the team reduction above (or the per-XCD-group
+// partials when grouped); several: one thread per (segment, quantity, column),
+// summing the segment's workgroups in order.
+template <typename T>
+__device__ __forceinline__ void seg_sums_all(const KA<T>& a, int sg0, int ns, int nq, double* out, double* sh,
+                                             bool grouped) {
+    const int d = a.d;
+    if (a.nseg == 1) { seg_sums(a, 0, nq, d, out, sh, grouped); return; }
+    const int per = nq * d;
+    for (int idx = threadIdx.x; idx < ns * per; idx += blockDim.x) {
+        const int k = idx / per, rem = idx - k * per, q = rem / d, c = rem - q * d;
+        const int sg = sg0 + k;
+        const double* base = a.part + (size_t)q * a.nblk * d + c;
+        double acc = 0.0;
+        for (int b = a.seg_blk0[sg]; b < a.seg_blk0[sg + 1]; ++b) acc += base[(size_t)b * d];
+        out[idx] = acc;
+    }
+    __syncthreads();
+}
+
+// segments per pass of a finaliser (their sums share sh[1024, 4608))
+__device__ __forceinline__ int seg_chunk(int nq, int d) {
+    const int c = (kSmemDoubles - 1024) / (nq * d);
+    return c < 1 ? 1 : c;
+}
+
 // ---------------------------------------------------------------------------
 // Phases (each called by every workgroup for its rows)
 // ---------------------------------------------------------------------------
@@ -527,6 +554,8 @@ __device__ __forceinline__ void ph_gram(const KA<T>& a, int lb, int mode, double
         if (k < npair) pair_of(k, d, pa[h], pb[h]);
     }
     double acc[2] = {0.0, 0.0};
+    // the factorisations that follow only ever clear this flag
+    if (lb == 0 && t == 0) a.S->ortho_ok = 1;
     for (int base = rb; base < re; base += R) {
         int rows = min(R, re - base);
         if (t < rows * d) {
@@ -555,11 +584,11 @@ __device__ __forceinline__ void ph_gram(const KA<T>& a, int lb, int mode, double
 
 // PH_APPLY: mode 0 (P-update): P = Z T, B = Z - P with Z = D^{1/2} Y + B;
 //           mode 1 (initial orthonormalisation): Y <- Y T, P = D^{1/2} Y, B = 0.
+//           Tg: the segment's d x d transform (row stride kMaxD), global or LDS.
 template <typename T>
-__device__ __forceinline__ void ph_apply(const KA<T>& a, int lb, int mode, double* sh) {
+__device__ __forceinline__ void ph_apply(const KA<T>& a, int lb, int mode, double* sh, const double* Tg) {
     const int d = a.d, R = a.R, t = threadIdx.x;
     const int rb = a.row0[lb], re = a.row0[lb + 1];
-    const double* Tg = a.Tm + (size_t)a.blk_seg[lb] * kMaxD * kMaxD;
     double* Ts = sh;                  // d x d
     double* zt = sh + kMaxD * kMaxD;  // R x d
     for (int k = t; k < d * d; k += blockDim.x) Ts[k] = Tg[(k / d) * kMaxD + (k % d)];
@@ -606,11 +635,14 @@ __device__ __forceinline__ void fin_res(const KA<T>& a, double* sh, bool grouped
     double* out = sh + 1024;
     __shared__ int s_any;
     if (threadIdx.x == 0) s_any = 0;
-    for (int sg = 0; sg < a.nseg; ++sg) {
-        seg_sums(a, sg, 2, d, out, sh, grouped);
-        if (threadIdx.x < d) {
-            const int c = threadIdx.x, ci = sg * d + c;
-            double bb = out[c], rr = out[d + c];
+    const int chunk = seg_chunk(2, d);
+    for (int sg0 = 0; sg0 < a.nseg; sg0 += chunk) {
+        const int ns = min(chunk, a.nseg - sg0);
+        seg_sums_all(a, sg0, ns, 2, out, sh, grouped);
+        for (int idx = threadIdx.x; idx < ns * d; idx += blockDim.x) {
+            const int k = idx / d, c = idx - k * d, ci = (sg0 + k) * d + c;
+            const double* o = out + k * 2 * d;
+            double bb = o[c], rr = o[d + c];
             a.cs.bnorm2[ci] = bb;
             a.cs.rr[ci] = rr;
             a.cs.iters[ci] = 0;
@@ -637,11 +669,14 @@ __device__ __forceinline__ void fin_w0(const KA<T>& a, double* sh, bool grouped)
     double* out = sh + 1024;
     __shared__ int s_bad;
     if (threadIdx.x == 0) s_bad = 0;
-    for (int sg = 0; sg < a.nseg; ++sg) {
-        seg_sums(a, sg, 2, d, out, sh, grouped);
-        if (threadIdx.x < d) {
-            const int c = threadIdx.x, ci = sg * d + c;
-            double g = out[c], dl = out[d + c];
+    const int chunk = seg_chunk(2, d);
+    for (int sg0 = 0; sg0 < a.nseg; sg0 += chunk) {
+        const int ns = min(chunk, a.nseg - sg0);
+        seg_sums_all(a, sg0, ns, 2, out, sh, grouped);
+        for (int idx = threadIdx.x; idx < ns * d; idx += blockDim.x) {
+            const int k = idx / d, c = idx - k * d, ci = (sg0 + k) * d + c;
+            const double* o = out + k * 2 * d;
+            double g = o[c], dl = o[d + c];
             a.cs.gamma[ci] = g;
             double al = 0.0;
             if (a.cs.active[ci]) {
@@ -666,13 +701,16 @@ __device__ __forceinline__ void fin_it(const KA<T>& a, double* sh, bool grouped)
     double* out = sh + 1024;
     __shared__ int s_any, s_bad;
     if (threadIdx.x == 0) { s_any = 0; s_bad = 0; }
-    for (int sg = 0; sg < a.nseg; ++sg) {
-        seg_sums(a, sg, 3, d, out, sh, grouped);
-        if (threadIdx.x < d) {
-            const int c = threadIdx.x, ci = sg * d + c;
+    const int chunk = seg_chunk(3, d);
+    for (int sg0 = 0; sg0 < a.nseg; sg0 += chunk) {
+        const int ns = min(chunk, a.nseg - sg0);
+        seg_sums_all(a, sg0, ns, 3, out, sh, grouped);
+        for (int idx = threadIdx.x; idx < ns * d; idx += blockDim.x) {
+            const int k = idx / d, c = idx - k * d, ci = (sg0 + k) * d + c;
+            const double* o = out + k * 3 * d;
             int act = a.cs.active[ci];
             if (act) {
-                double g = out[c], dl = out[d + c], rr = out[2 * d + c];
+                double g = o[c], dl = o[d + c], rr = o[2 * d + c];
                 a.cs.iters[ci] += 1;
                 a.cs.rr[ci] = rr;
                 act = rr > a.tol2 * a.cs.bnorm2[ci];
@@ -717,12 +755,15 @@ __device__ __forceinline__ void fin_ld(const KA<T>& a, double* sh, bool initial)
     double* out = sh + 1024;
     __shared__ int s_any, s_bad;
     if (threadIdx.x == 0) { s_any = 0; s_bad = 0; }
-    for (int sg = 0; sg < a.nseg; ++sg) {
-        seg_sums(a, sg, 2, d, out, sh, false);
-        if (threadIdx.x < d) {
-            const int c = threadIdx.x, ci = sg * d + c;
+    const int chunk = seg_chunk(2, d);
+    for (int sg0 = 0; sg0 < a.nseg; sg0 += chunk) {
+        const int ns = min(chunk, a.nseg - sg0);
+        seg_sums_all(a, sg0, ns, 2, out, sh, false);
+        for (int idx = threadIdx.x; idx < ns * d; idx += blockDim.x) {
+            const int k = idx / d, c = idx - k * d, ci = (sg0 + k) * d + c;
+            const double* o = out + k * 2 * d;
             int act = a.cs.active[ci];
-            double g = out[c], rr = out[d + c];
+            double g = o[c], rr = o[d + c];
             if (initial) {
                 a.cs.gamma[ci] = g;
                 a.cs.beta[ci] = 0.0;
@@ -767,13 +808,15 @@ __device__ __forceinline__ void fin_la(const KA<T>& a, double* sh) {
     double* out = sh + 1024;
     __shared__ int s_bad;
     if (threadIdx.x == 0) s_bad = 0;
-    for (int sg = 0; sg < a.nseg; ++sg) {
-        seg_sums(a, sg, 1, d, out, sh, false);
-        if (threadIdx.x < d) {
-            const int c = threadIdx.x, ci = sg * d + c;
+    const int chunk = seg_chunk(1, d);
+    for (int sg0 = 0; sg0 < a.nseg; sg0 += chunk) {
+        const int ns = min(chunk, a.nseg - sg0);
+        seg_sums_all(a, sg0, ns, 1, out, sh, false);
+        for (int idx = threadIdx.x; idx < ns * d; idx += blockDim.x) {
+            const int k = idx / d, c = idx - k * d, ci = (sg0 + k) * d + c;
             double al = 0.0;
             if (a.cs.active[ci]) {
-                double pq = out[c];
+                double pq = out[k * d + c];
                 al = a.cs.gamma[ci] / pq;
                 if (!(pq > 0.0) || !isfinite(al)) { s_bad = 1; al = 0.0; }
             }
@@ -809,9 +852,12 @@ __device__ __forceinline__ void solve_stats(const KA<T>& a) {
 //   CHOL / init: T = L^{-T}  (Z T = Z R^{-1}, R = L^T);
 //   POLAR: T = G^{-1/2} by the coupled Newton-Schulz iteration on G / s,
 //   s = ||G||_inf, so that Z T is the orthogonal polar factor of Z.
-// LDS use: sh[1024, 4608).
+// The transform goes to Tout (row stride kMaxD); report: record a failure in
+// the solver flags.  Returns false when G is not (numerically) positive
+// definite.  LDS use: sh[1024, 4608).
 template <typename T>
-__device__ __forceinline__ void factor_gram(const KA<T>& a, int sg, int mode, const double* gsum, double* sh) {
+__device__ __forceinline__ bool factor_gram(const KA<T>& a, int mode, const double* gsum, double* sh, double* Tout,
+                                            bool report) {
     const int d = a.d, t = threadIdx.x, nb = blockDim.x;
     const int npair = d * (d + 1) / 2;
     double* G = sh + 1024;
@@ -819,7 +865,6 @@ __device__ __forceinline__ void factor_gram(const KA<T>& a, int sg, int mode, co
     double* Ym = sh + 3072;
     double* Zm = sh + 3072 + 512;
     double* red = sh + 4096;
-    double* Tout = a.Tm + (size_t)sg * kMaxD * kMaxD;
     for (int k = t; k < npair; k += nb) {
         int r, cc;
         pair_of(k, d, r, cc);
@@ -848,12 +893,12 @@ __device__ __forceinline__ void factor_gram(const KA<T>& a, int sg, int mode, co
         __syncthreads();
     }
     if (s_bad) {
-        if (t == 0) {
+        if (t == 0 && report) {
             a.S->ortho_ok = 0;
             a.S->status = PFE_E_RANK;
         }
         __syncthreads();
-        return;
+        return false;
     }
     if (mode == 1 || a.ortho == PFE_CHOL) {
         // T = L^{-T}: column c of L^{-1} by forward substitution, T[a][c] = Linv[c][a]
@@ -870,7 +915,7 @@ __device__ __forceinline__ void factor_gram(const KA<T>& a, int sg, int mode, co
             Tout[r * kMaxD + c] = Ym[c * kMaxD + r];
         }
         __syncthreads();
-        return;
+        return true;
     }
     // coupled Newton-Schulz for (G/s)^{-1/2}
     __shared__ double s_scale, s_err;
@@ -946,24 +991,25 @@ __device__ __forceinline__ void factor_gram(const KA<T>& a, int sg, int mode, co
         int r = k / d, c = k - r * d;
         Tout[r * kMaxD + c] = Zk[k] * is;
     }
-    if (t == 0 && !(s_err < 1e-10)) {
+    const bool ok = s_err < 1e-10;
+    if (t == 0 && !ok && report) {
         a.S->ortho_ok = 0;
         a.S->status = PFE_E_RANK;
     }
     __syncthreads();
+    return ok;
 }
 
-// after PH_GRAM: per-segment Gram sums and their factors
+// Gram sum of segment sg (grouped: the per-XCD-group partials of the single
+// segment) and its factor, written to Tout.
 template <typename T>
-__device__ __forceinline__ void fin_gram(const KA<T>& a, int mode, double* sh, bool grouped) {
+__device__ __forceinline__ bool seg_factor(const KA<T>& a, int sg, int mode, double* sh, bool grouped, double* Tout,
+                                           bool report) {
     const int npair = a.d * (a.d + 1) / 2;
     __shared__ double gsum[kMaxD * (kMaxD + 1) / 2];
-    if (threadIdx.x == 0) a.S->ortho_ok = 1;
-    for (int sg = 0; sg < a.nseg; ++sg) {
-        if (grouped) reduce_range(a.gpart, kNumXcd, 0, kNumXcd, npair, 1, gsum, sh);
-        else reduce_range(a.part, a.nblk, a.seg_blk0[sg], a.seg_blk0[sg + 1], npair, 1, gsum, sh);
-        factor_gram(a, sg, mode, gsum, sh);
-    }
+    if (grouped) reduce_range(a.gpart, kNumXcd, 0, kNumXcd, npair, 1, gsum, sh);
+    else reduce_range(a.part, a.nblk, a.seg_blk0[sg], a.seg_blk0[sg + 1], npair, 1, gsum, sh);
+    return factor_gram(a, mode, gsum, sh, Tout, report);
 }
 
 // ---------------------------------------------------------------------------
@@ -1129,13 +1175,22 @@ __global__ void __launch_bounds__(kBlock) k_phase(KA<T> a, int ph, int mode, int
             break;
         case PH_GRAM:
             ph_gram(a, lb, mode, sh);
-            if (last_block(a.bar + kBarLast, a.nblk)) fin_gram(a, mode, sh, false);
+            // several segments: one workgroup per segment factors in k_factor
+            if (a.nseg == 1 && last_block(a.bar + kBarLast, a.nblk)) seg_factor(a, 0, mode, sh, false, a.Tm, true);
             break;
         case PH_APPLY:
             if (!ld_flag(&a.S->ortho_ok)) return;
-            ph_apply(a, lb, mode, sh);
+            ph_apply(a, lb, mode, sh, a.Tm + (size_t)a.blk_seg[lb] * kMaxD * kMaxD);
             break;
     }
+}
+
+// P-update factors of a batch: workgroup sg reduces and factors segment sg
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_factor(KA<T> a, int mode) {
+    __shared__ double sh[kSmemDoubles];
+    const int sg = blockIdx.x;
+    seg_factor(a, sg, mode, sh, false, a.Tm + (size_t)sg * kMaxD * kMaxD, true);
 }
 
 // statistics when a solve finished before its first iteration
@@ -1150,34 +1205,42 @@ struct Plan {
     int n_outer;      // SOC iterations to run
 };
 
-// Persistent path: whole SOC iterations in one cooperative launch (single segment).
+// Persistent path: whole SOC iterations in one cooperative launch.  One
+// segment: the group leaders pre-reduce the partials of their XCD group.
+// Several segments (a batch): the finalisers reduce every segment at once, and
+// after the Gram phase every workgroup factors its own segment's Gram matrix
+// (the same FP64 operations in the same order in each of them), so the
+// P-update needs no further barrier.
 template <typename T, int KC>
 __global__ void __launch_bounds__(kBlock) k_soc(KA<T> a, Plan plan) {
     __shared__ double sh[kSmemDoubles];
+    __shared__ double Tsh[kMaxD * kMaxD];
     const int lb = logical_block(a.nblk);
     const unsigned nb = (unsigned)a.nblk;
     Scal* S = a.S;
     const int d = a.d;
     const int npair = d * (d + 1) / 2;
-    auto g2 = [&](unsigned g) { group_reduce(a, g, d, 2, sh); };
-    auto g3 = [&](unsigned g) { group_reduce(a, g, d, 3, sh); };
-    auto gg = [&](unsigned g) { group_reduce(a, g, npair, 1, sh); };
+    const bool one = (a.nseg == 1);
+    auto g2 = [&](unsigned g) { if (one) group_reduce(a, g, d, 2, sh); };
+    auto g3 = [&](unsigned g) { if (one) group_reduce(a, g, d, 3, sh); };
+    auto gg = [&](unsigned g) { if (one) group_reduce(a, g, npair, 1, sh); };
+    const int ncol = a.nseg * d;
     int l0 = plan.l_begin;
     for (int outer = 0; outer < plan.n_outer; ++outer) {
         for (int l = l0; l < plan.n_inner; ++l) {
             ph_residual<KC>(a, lb, (l == 0) ? PH_E0 : PH_EU, 1, (l == 1) ? 1 : 0, sh);
-            if (!grid_sync(a.bar, nb, S, g2, [&] { fin_res(a, sh, true); })) return;
+            if (!grid_sync(a.bar, nb, S, g2, [&] { fin_res(a, sh, one); })) return;
             if (!ld_flag(&S->done)) {
                 ph_w0<KC>(a, lb, sh);
-                if (!grid_sync(a.bar, nb, S, g2, [&] { fin_w0(a, sh, true); })) return;
+                if (!grid_sync(a.bar, nb, S, g2, [&] { fin_w0(a, sh, one); })) return;
             }
             while (!ld_flag(&S->done)) {
                 ph_it<KC>(a, lb, sh);
-                if (!grid_sync(a.bar, nb, S, g3, [&] { fin_it(a, sh, true); })) return;
+                if (!grid_sync(a.bar, nb, S, g3, [&] { fin_it(a, sh, one); })) return;
             }
             if (lb == 0 && threadIdx.x == 0) solve_stats(a);
             int any_zero = 0;
-            for (int c = 0; c < d; ++c) any_zero |= a.cs.zero[c];
+            for (int c = 0; c < ncol; ++c) any_zero |= a.cs.zero[c];
             if (any_zero) {
                 // columns with a zero right-hand side: x_c = 0
                 ph_zero(a, lb);
@@ -1186,9 +1249,17 @@ __global__ void __launch_bounds__(kBlock) k_soc(KA<T> a, Plan plan) {
         }
         l0 = 0;
         ph_gram(a, lb, 0, sh);
-        if (!grid_sync(a.bar, nb, S, gg, [&] { fin_gram(a, 0, sh, true); })) return;
-        if (!ld_flag(&S->ortho_ok)) return;
-        ph_apply(a, lb, 0, sh);
+        if (one) {
+            if (!grid_sync(a.bar, nb, S, gg, [&] { seg_factor(a, 0, 0, sh, true, a.Tm, true); })) return;
+            if (!ld_flag(&S->ortho_ok)) return;
+            ph_apply(a, lb, 0, sh, a.Tm);
+        } else {
+            if (!grid_sync(a.bar, nb, S, NoFin{}, NoFin{})) return;
+            const int sg = a.blk_seg[lb];
+            // a segment whose Gram matrix is singular keeps its P and B; the
+            // first workgroup of the segment records the failure
+            if (seg_factor(a, sg, 0, sh, false, Tsh, lb == a.seg_blk0[sg])) ph_apply(a, lb, 0, sh, Tsh);
+        }
         // P and B of a row are written and read by the same workgroup; the
         // barrier after the next residual phase orders everything else.
     }
@@ -1353,20 +1424,29 @@ __global__ void __launch_bounds__(kBlock) k_monitor(KA<T> a) {
         }
     }
     if (last_block(a.bar + kBarLast, a.nblk)) {
+        // per segment: its Gram matrices against I; sums over all segments
         double* tot = sh + 2048;
-        reduce_range(a.part, 1, 0, a.nblk, nq, 1, tot, sh);   // layout part[b * nq + k]
-        if (t == 0) {
-            double cmax = 0.0, omax = 0.0;
-            for (int k = 0; k < npair; ++k) {
-                int r, cc;
-                pair_of(k, d, r, cc);
-                double id = (r == cc) ? 1.0 : 0.0;
-                omax = fmax(omax, fabs(tot[3 + k] - id));
-                cmax = fmax(cmax, fabs(tot[3 + npair + k] - id));
+        double s_obj = 0.0, s_spl = 0.0, s_pp = 0.0, cmax = 0.0, omax = 0.0;
+        for (int sg = 0; sg < a.nseg; ++sg) {
+            reduce_range(a.part, 1, a.seg_blk0[sg], a.seg_blk0[sg + 1], nq, 1, tot, sh);  // part[b * nq + k]
+            if (t == 0) {
+                s_obj += tot[0];
+                s_spl += tot[1];
+                s_pp += tot[2];
+                for (int k = 0; k < npair; ++k) {
+                    int r, cc;
+                    pair_of(k, d, r, cc);
+                    double id = (r == cc) ? 1.0 : 0.0;
+                    omax = fmax(omax, fabs(tot[3 + k] - id));
+                    cmax = fmax(cmax, fabs(tot[3 + npair + k] - id));
+                }
             }
-            a.S->mon[0] = tot[0];
+            __syncthreads();
+        }
+        if (t == 0) {
+            a.S->mon[0] = s_obj;
             a.S->mon[1] = cmax;
-            a.S->mon[2] = sqrt(tot[1]) / sqrt(tot[2]);
+            a.S->mon[2] = sqrt(s_spl) / sqrt(s_pp);
             a.S->mon[3] = omax;
         }
     }
@@ -1652,6 +1732,10 @@ template <typename T>
 pfe_status ortho_mk(pfe_ctx* c, int mode) {
     KA<T> a = make_args<T>(c, c->pm);
     PFE_TRY(launch_phase(c, a, PH_GRAM, mode, 0));
+    if (a.nseg > 1) {
+        hipLaunchKernelGGL(k_factor<T>, dim3(a.nseg), dim3(kBlock), 0, c->stream, a, mode);
+        PFE_CHECK_HIP(hipGetLastError());
+    }
     PFE_TRY(launch_phase(c, a, PH_APPLY, mode, 0));
     return PFE_OK;
 }
@@ -1917,7 +2001,17 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
     c->esz = (p->dtype == PFE_FP64) ? 8 : 4;
     c->n = g->n;
     c->d = p->d;
-    c->nseg = 1;
+    c->nseg = (int)g->seg_row0.size() - 1;
+    std::vector<int64_t> seg_rows(c->nseg);
+    for (int sg = 0; sg < c->nseg; ++sg) {
+        seg_rows[sg] = g->seg_row0[sg + 1] - g->seg_row0[sg];
+        if (seg_rows[sg] <= p->d) {
+            delete c;
+            set_error("pfe_init: graph %d of the batch has %lld vertices, not more than d = %d", sg,
+                      (long long)seg_rows[sg], p->d);
+            return PFE_E_ARG;
+        }
+    }
     const size_t nd = (size_t)c->n * c->d * c->esz;
     const size_t sd = (size_t)(g->nslot + 1) * c->d * c->esz;
     const size_t nv = (size_t)c->n * c->esz;
@@ -1931,7 +2025,6 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
         &occ, (p->dtype == PFE_FP64) ? soc_kernel<double>(g->ell_K) : soc_kernel<float>(g->ell_K), kBlock, 0);
     if (oe != hipSuccess) occ = 0;
     const int per_cu = std::max(0, std::min(occ, 2));
-    std::vector<int64_t> seg_rows{c->n};
     pfe_status s = make_partition(seg_rows, (int)std::min<int64_t>(want, 2048), c->pm);
     if (s == PFE_OK && p->persistent) {
         int64_t coop = (int64_t)per_cu * ncu;
@@ -2206,7 +2299,16 @@ pfe_status pfe_pcg(pfe_ctx* c, const void* RHS, void* X, int32_t* iters, pfe_ste
         PFE_TRY(pcg_any_mk(c, a));
     }
     if (iters) {
-        PFE_CHECK_HIP(hipMemcpyAsync(iters, c->cs.iters, sizeof(int) * c->d, hipMemcpyDeviceToHost, c->stream));
+        // per column, the largest count over the segments of a batch
+        std::vector<int> all((size_t)c->nseg * c->d);
+        PFE_CHECK_HIP(hipMemcpyAsync(all.data(), c->cs.iters, sizeof(int) * all.size(), hipMemcpyDeviceToHost,
+                                     c->stream));
+        PFE_CHECK_HIP(hipStreamSynchronize(c->stream));
+        for (int col = 0; col < c->d; ++col) {
+            int m = 0;
+            for (int sg = 0; sg < c->nseg; ++sg) m = std::max(m, all[(size_t)sg * c->d + col]);
+            iters[col] = m;
+        }
     }
     return read_info(c, info);
 }

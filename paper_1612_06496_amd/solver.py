@@ -58,6 +58,26 @@ class Graph:
         L.check(L.lib.pfe_build_graph(C.byref(desc), _stream_handle(stream), C.byref(h)), "pfe_build_graph")
         return cls(h, stream)
 
+    @classmethod
+    def union(cls, parts, stream=None) -> "Graph":
+        """Block-diagonal union (one segment per part) of already built graphs."""
+        arr = (C.c_void_p * len(parts))(*[g._h for g in parts])
+        h = C.c_void_p()
+        L.check(L.lib.pfe_graph_union(arr, len(parts), _stream_handle(stream), C.byref(h)), "pfe_graph_union")
+        return cls(h, stream)
+
+    @property
+    def segments(self):
+        """(row0, edge0): first vertex and first edge of each segment, with the
+        totals appended."""
+        k = C.c_int()
+        L.check(L.lib.pfe_graph_segments(self._h, C.byref(k), None, None), "pfe_graph_segments")
+        row0 = np.empty(k.value + 1, dtype=np.int64)
+        edge0 = np.empty(k.value + 1, dtype=np.int64)
+        L.check(L.lib.pfe_graph_segments(self._h, C.byref(k), row0.ctypes.data, edge0.ctypes.data),
+                "pfe_graph_segments")
+        return row0, edge0
+
     def csr(self):
         rowptr = torch.empty(self.n + 1, dtype=torch.int32, device="cuda")
         col = torch.empty(2 * self.n_edges, dtype=torch.int32, device="cuda")

@@ -11,11 +11,12 @@ float32 feature arrays, which both sides read as the same exact values.
 from .voronoi import voronoi_image, image_features, batch_image_shapes
 from .points import gaussian_mixture, knn_edge_list
 from .embed import smooth_y0, gaussian_y0
-from .workloads import (WORKLOADS, Workload, make_workload, grid_workload,
-                        edges_workload)
+from .workloads import (WORKLOADS, BATCHES, Workload, make_workload, make_batch,
+                        grid_workload, edges_workload)
 
 __all__ = [
     "voronoi_image", "image_features", "batch_image_shapes",
     "gaussian_mixture", "knn_edge_list", "smooth_y0", "gaussian_y0",
-    "WORKLOADS", "Workload", "make_workload", "grid_workload", "edges_workload",
+    "WORKLOADS", "BATCHES", "Workload", "make_workload", "make_batch", "grid_workload",
+    "edges_workload",
 ]

@@ -91,6 +91,32 @@ WORKLOADS = {
 }
 
 
+# Batches of uneven images (one problem per image, solved side by side):
+# W ~ U{wmin..wmax}, H ~ U{hmin..hmax}, one child seed per image; every image
+# otherwise as its single-image counterpart.
+BATCHES = {
+    # 64 images of 128..512 x 128..384 pixels, each as the 481x321 workload.
+    "voronoi_batch64_8nbr": dict(count=64, K=40, noise=0.03, gradient=0.3,
+                                 with_xy=True, stencil=8, d=10, n_outer=20,
+                                 n_inner=10, tol=1e-6),
+    # Small stand-in for tests: 5 images of 24..64 x 20..48 pixels.
+    "voronoi_batch5_8nbr": dict(count=5, wmin=24, wmax=64, hmin=20, hmax=48,
+                                K=6, noise=0.03, gradient=0.3, with_xy=True,
+                                stencil=8, d=6, n_outer=3, n_inner=3, tol=1e-6),
+}
+
+
+def make_batch(name: str, seed: int = 0) -> list:
+    """The images of a named batch as single-image workloads, in batch order."""
+    if name not in BATCHES:
+        raise KeyError(f"unknown batch {name!r}; known: {sorted(BATCHES)}")
+    cfg = dict(BATCHES[name])
+    count = cfg.pop("count")
+    lim = {k: cfg.pop(k) for k in ("wmin", "wmax", "hmin", "hmax") if k in cfg}
+    shapes = batch_image_shapes(count, seed, **lim)
+    return [grid_workload(f"{name}[{k}]", H, W, seed=s, **cfg) for k, (H, W, s) in enumerate(shapes)]
+
+
 def make_workload(name: str, seed: int = 0) -> Workload:
     if name not in WORKLOADS:
         raise KeyError(f"unknown workload {name!r}; known: {sorted(WORKLOADS)}")
