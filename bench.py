@@ -40,12 +40,20 @@ def algorithmic_bytes(n, E, d, esz, cg_iters, solves, n_inner, n_outer):
     return cg_iters * cg_iter + n_outer * per_outer_fixed
 
 
-def measured_traffic():
+# committed rocprofv3 traffic summaries of the persistent kernel, per workload
+TRAFFIC_FILES = {"voronoi481x321_8nbr": "k_soc_voronoi481x321_traffic.json",
+                 "voronoi_batch64_8nbr": "k_soc_voronoi_batch64_traffic.json"}
+
+
+def measured_traffic(workload):
     """HBM traffic per k_soc launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs (scaled by the copy-kernel calibration), or None when the
-    kernel source changed since the counters were taken."""
+    WRITE_SIZE runs (scaled by the copy-kernel calibration), or None when there
+    is none for the workload or the kernel source changed since the counters
+    were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_soc_voronoi481x321_traffic.json")
+    if workload not in TRAFFIC_FILES:
+        return None
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES[workload])
     src = os.path.join(ROOT, "paper_1612_06496_amd", "csrc", "solver.hip")
     try:
         rec = json.load(open(path))
@@ -151,27 +159,37 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0), captu
             "launch": "one launch per phase (both preconditioners)", "sweep": rows}
 
 
-def cpu_baseline(wl, lam, r, n_steps=2):
+def cpu_baseline(wls, lam, r, n_steps=2, max_images=2):
     """The FP64 oracle on the host, on a bounded sample: n_steps SOC iterations
-    of the same workload (sparse LU factorisation reported separately)."""
+    of the workload's first max_images images (sparse LU factorisation reported
+    separately); for a batch the rate is scaled to the whole batch by its
+    vertex count."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import oracle as O
+    sample = wls[:max_images]
+    n_all = sum(w.n for w in wls)
+    n_sample = sum(w.n for w in sample)
+    dt = t_fact = 0.0
     with threadpool_limits(limits=1):
-        g = O.build_grid_graph(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
-        Y = O.orthonormalize_init(g, wl.y0)
-        t0 = time.perf_counter()
-        solve = O.DirectSolver(O.system_matrix(g, lam, r))
-        t_fact = time.perf_counter() - t0
-        P = np.sqrt(g.D)[:, None] * Y
-        B = np.zeros_like(Y)
-        t0 = time.perf_counter()
-        for _ in range(n_steps):
-            Y, P, B = O.soc_outer_step(g, solve, Y, P, B, lam, r, wl.n_inner)
-        dt = time.perf_counter() - t0
-    return {"value": n_steps / dt, "unit": "outer iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_steps} SOC iterations x {wl.n_inner} inner, sparse LU solves "
+        for wl in sample:
+            g = O.build_grid_graph(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
+            Y = O.orthonormalize_init(g, wl.y0)
+            t0 = time.perf_counter()
+            solve = O.DirectSolver(O.system_matrix(g, lam, r))
+            t_fact += time.perf_counter() - t0
+            P = np.sqrt(g.D)[:, None] * Y
+            B = np.zeros_like(Y)
+            t0 = time.perf_counter()
+            for _ in range(n_steps):
+                Y, P, B = O.soc_outer_step(g, solve, Y, P, B, lam, r, wl.n_inner)
+            dt += time.perf_counter() - t0
+    scale = n_all / n_sample
+    what = (f"{len(sample)} of {len(wls)} images ({n_sample} of {n_all} vertices, rate scaled by vertex count)"
+            if len(wls) > 1 else "the whole image")
+    return {"value": n_steps / (dt * scale), "unit": "outer iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_steps} SOC iterations x {sample[0].n_inner} inner on {what}; sparse LU solves "
                       f"(factorisation {t_fact:.2f} s once, not in the rate), 1 thread"}
 
 
@@ -184,6 +202,8 @@ def main():
     ap.add_argument("--copy-gib", type=float, default=2.0, help="size of the copy-bandwidth probe")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-Jacobi PCG comparison")
     ap.add_argument("--multi-launch", action="store_true", help="one launch per phase instead of one per SOC iteration")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="a single-image workload or an image batch (block-diagonal union) from synth")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a "
@@ -197,9 +217,18 @@ def main():
     from paper_1612_06496_amd import Graph, Solver
 
     torch.cuda.set_device(0)
-    wl = synth.make_workload(WORKLOAD, 0)
-    G = Graph.grid(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
-    S = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=1000,
+    if args.workload in synth.BATCHES:
+        wls = synth.make_batch(args.workload, 0)
+        parts = [Graph.grid(w.feat, w.H, w.W, w.stencil, w.sigma) for w in wls]
+        G = Graph.union(parts)
+        del parts
+        Y0 = np.concatenate([w.y0 for w in wls])
+    else:
+        wls = [synth.make_workload(args.workload, 0)]
+        G = Graph.grid(wls[0].feat, wls[0].H, wls[0].W, wls[0].stencil, wls[0].sigma)
+        Y0 = wls[0].y0
+    wl = wls[0]
+    S = Solver(G, Y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=1000,
                persistent=not args.multi_launch)
     # shrink-active penalties: threshold 1/c at the 0.99-quantile of |M Y0|
     c = 1.0 / S.edge_quantile(0.99)
@@ -228,18 +257,21 @@ def main():
     byt = algorithmic_bytes(n, E, d, 4, info["cg_iters_total"], info["solves"], wl.n_inner, args.steps)
     achieved = byt / (ms / 1e3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
-            "kernel": "k_soc (one SOC iteration per launch)",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None if args.multi_launch else measured_traffic(args.workload),
+            "kernel": "one kernel per phase" if args.multi_launch else "k_soc (one SOC iteration per launch)",
             "bytes_per_launch": int(byt / args.steps), "workgroups": info["workgroups"]}
+    default = args.workload == WORKLOAD
     line = {
-        "metric": "PFE outer iters/sec at 481x321 d=10 (Jacobi-PCG to 1e-6)",
+        "metric": "PFE outer iters/sec at 481x321 d=10 (Jacobi-PCG to 1e-6)" if default else
+                  f"PFE outer iters/sec on {args.workload} (Jacobi-PCG to {wl.tol:g})",
         "value": round(value, 2),
         "unit": "outer iters/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": n, "edges": E, "d": d, "n_inner": wl.n_inner,
+        "config": {"workload": args.workload, "graphs": len(wls), "n": n, "edges": E, "d": d,
+                   "n_inner": wl.n_inner,
                    "tol": wl.tol, "lambda": c, "r": c, "precond": "jacobi",
                    "launch": "multi" if args.multi_launch else "persistent"},
         "pcg_iters_per_solve": round(info["cg_iters_total"] / max(1, info["solves"]), 2),
@@ -248,7 +280,7 @@ def main():
         "wall_s_timed": round(wall, 4),
         "roofline": roof,
     }
-    if not args.no_learned:
+    if not args.no_learned and default:
         leg = learned_leg()
         line["learned_vs_jacobi"] = leg
         line["pcg_iters_learned"] = {str(r["lambda_over_r"]): [r["jacobi"]["iters_max"], r["learned"]["iters_max"]]
@@ -256,7 +288,7 @@ def main():
     if args.copy_gib > 0:
         line["copy_gbs"] = round(copy_bandwidth(args.copy_gib), 1)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl, c, c)
+        line["cpu_baseline"] = cpu_baseline(wls, c, c)
         line["cpu_baseline"]["value"] = round(line["cpu_baseline"]["value"], 4)
     print(json.dumps(line), flush=True)
 

@@ -10,13 +10,17 @@
 // -(w (y_j - y_i)).  Slots follow the graph's solver layout (ELL: slot k of row
 // i at k n + i, so lanes on consecutive rows read consecutive slots; or CSR).
 //
-// Work decomposition.  A phase runs on nblk workgroups; workgroup lb owns the
-// rows [row0[lb], row0[lb+1]) and walks them R = blockDim / d rows at a time,
-// thread t on (row t / d, column t % d): consecutive lanes touch consecutive
-// elements and gathers of neighbour rows of an image stay coalesced.  Workgroup
-// indices are remapped so that each XCD owns contiguous rows.  Per-column
-// reductions are FP64: one partial per workgroup and column, summed in a fixed
-// order (results are bitwise reproducible).
+// Work decomposition.  A phase runs on nblk workgroups, each walking its rows
+// R = blockDim / d at a time, thread t on (row t / d, column t % d):
+// consecutive lanes touch consecutive elements and gathers of neighbour rows of
+// an image stay coalesced.  Workgroup indices are remapped so that each XCD owns
+// a contiguous band of rows.  Inside a band, a team of up to 64 workgroups of
+// the same segment deals the band's R-row chunks out cyclically, so the team
+// sweeps the band together and the rows a chunk gathers from (an image row
+// above and below) are still in that XCD's L2 when they are read again; with
+// teams of one workgroup each owns a contiguous range.  Per-column reductions
+// are FP64: one partial per workgroup and column, summed in a fixed order
+// (results are bitwise reproducible).
 //
 // PCG.  The d systems of Eq. 13 are solved together with per-column scalars by
 // the Chronopoulos-Gear form of Jacobi-preconditioned CG, which needs a single
@@ -68,6 +72,8 @@ template <typename T>
 struct KA {
     int n, d, R, nblk, nseg, ell_K;
     const int* row0;       // nblk + 1 row boundaries of the logical workgroups
+    const int* bit;        // per logical workgroup: first row, end row, stride (rows
+                           // first + k stride + [0, R) below end are its own)
     const int* blk_seg;    // segment of each logical workgroup
     const int* seg_blk0;   // nseg + 1 first logical workgroup of each segment
     const int* rowptr;     // CSR row pointers (used when ell_K == 0)
@@ -230,8 +236,10 @@ __device__ __forceinline__ void seg_sums_all(const KA<T>& a, int sg0, int ns, in
         const int k = idx / per, rem = idx - k * per, q = rem / d, c = rem - q * d;
         const int sg = sg0 + k;
         const double* base = a.part + (size_t)q * a.nblk * d + c;
+        const int b0 = a.seg_blk0[sg], b1 = a.seg_blk0[sg + 1];
         double acc = 0.0;
-        for (int b = a.seg_blk0[sg]; b < a.seg_blk0[sg + 1]; ++b) acc += base[(size_t)b * d];
+#pragma unroll 8
+        for (int b = b0; b < b1; ++b) acc += base[(size_t)b * d];
         out[idx] = acc;
     }
     __syncthreads();
@@ -246,6 +254,15 @@ __device__ __forceinline__ int seg_chunk(int nq, int d) {
 // ---------------------------------------------------------------------------
 // Phases (each called by every workgroup for its rows)
 // ---------------------------------------------------------------------------
+// With the ELL width KC known at compile time the slot loops run in groups of
+// up to 8 slots: the group's slot indices and weights are loaded together, then
+// all of its neighbour gathers, then the arithmetic in slot order (the same
+// operations in the same order as the generic loop), so one wave keeps many
+// independent loads in flight instead of waiting on each slot.
+// (GM: largest group, 8 in the one-phase kernels, 4 in the persistent kernel
+// whose registers are shared by every phase)
+template <int KC, int GM>
+constexpr int slot_group() { return KC <= 0 ? 1 : (KC <= GM ? KC : GM); }
 
 // Residual phases.  For every owned element (i, c):
 //   EU : t = w (y_i - y_j) + b_s ; d_s = Shrink(t, 1/lambda) ; b_s = t - d_s   (Eqs. 9, 10)
@@ -254,21 +271,52 @@ __device__ __forceinline__ int seg_chunk(int nq, int d) {
 //   R0 : rhs from the stored rhs
 //   RHS: rhs from the stored b and d
 // then (unless RHS) r0 = rhs - A x, with FP64 partials of rhs^T rhs and r0^T r0.
-template <int KC = 0, typename T>
+template <int KC = 0, int GM = 8, typename T>
 __device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, int do_r0, int b_zero, double* sh) {
     const int d = a.d, R = a.R, t = threadIdx.x;
-    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     double acc[2] = {0.0, 0.0};
     T* r0 = a.rb[0];
     if (t < R * d) {
         const int rl = t / d, c = t - rl * d;
-        for (int i = rb + rl; i < re; i += R) {
+        for (int i = rb + rl; i < re; i += rs) {
             const size_t e = (size_t)i * d + c;
             int s0, cnt, st;
             row_slots<KC>(a, i, s0, cnt, st);
             const T xi = a.x[e];
             T accR = T(0), accA = T(0);
-            if (mode == PH_EU) {
+            if (mode == PH_EU && KC > 0) {
+                const T yi = a.Y[e];
+                constexpr int G = slot_group<KC, GM>();
+                for (int k0 = 0; k0 < cnt; k0 += G) {
+                    int jj[G];
+                    T ww[G], yj[G], bo[G], xj[G];
+#pragma unroll
+                    for (int k = 0; k < G; ++k) {
+                        const int sl = s0 + (k0 + k) * st;
+                        jj[k] = a.scol[sl];
+                        ww[k] = a.sw[sl];
+                        bo[k] = b_zero ? T(0) : a.bs[(size_t)sl * d + c];
+                    }
+#pragma unroll
+                    for (int k = 0; k < G; ++k) {
+                        const size_t ej = (size_t)jj[k] * d + c;
+                        yj[k] = a.Y[ej];
+                        xj[k] = do_r0 ? a.x[ej] : T(0);
+                    }
+#pragma unroll
+                    for (int k = 0; k < G; ++k) {
+                        const size_t es = (size_t)(s0 + (k0 + k) * st) * d + c;
+                        const T tv = fma_t(ww[k], yi - yj[k], bo[k]);
+                        const T dv = shrink(tv, a.gamma);
+                        const T bn = tv - dv;
+                        a.bs[es] = bn;
+                        if (a.keep_split) a.ds[es] = dv;
+                        accR = fma_t(ww[k], dv - bn, accR);
+                        if (do_r0) accA = fma_t(mul_t(ww[k], ww[k]), xj[k], accA);
+                    }
+                }
+            } else if (mode == PH_EU) {
                 const T yi = a.Y[e];
 #pragma unroll(KC > 0 ? 4 : 2)
                 for (int k = 0; k < cnt; ++k) {
@@ -293,6 +341,22 @@ __device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, in
                     const int s = s0 + k * st;
                     const size_t es = (size_t)s * d + c;
                     accR = fma_t(a.sw[s], a.ds[es] - a.bs[es], accR);
+                }
+            } else if (do_r0 && KC > 0) {
+                constexpr int G = slot_group<KC, GM>();
+                for (int k0 = 0; k0 < cnt; k0 += G) {
+                    int jj[G];
+                    T ww[G], xj[G];
+#pragma unroll
+                    for (int k = 0; k < G; ++k) {
+                        const int sl = s0 + (k0 + k) * st;
+                        jj[k] = a.scol[sl];
+                        ww[k] = a.sw[sl];
+                    }
+#pragma unroll
+                    for (int k = 0; k < G; ++k) xj[k] = a.x[(size_t)jj[k] * d + c];
+#pragma unroll
+                    for (int k = 0; k < G; ++k) accA = fma_t(mul_t(ww[k], ww[k]), xj[k], accA);
                 }
             } else if (do_r0) {
 #pragma unroll(KC > 0 ? 4 : 2)
@@ -323,29 +387,50 @@ __device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, in
 }
 
 // PH_W0: w0 = A u0 with u0 = r0 / diag(A); partials of r0.u0 and w0.u0.
-template <int KC = 0, typename T>
+template <int KC = 0, int GM = 8, typename T>
 __device__ __forceinline__ void ph_w0(const KA<T>& a, int lb, double* sh) {
     const int d = a.d, R = a.R, t = threadIdx.x;
-    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     const T* r = a.rb[0];
     T* w = a.wb[0];
     double acc[2] = {0.0, 0.0};
     if (t < R * d) {
         const int rl = t / d, c = t - rl * d;
-        for (int i = rb + rl; i < re; i += R) {
+        for (int i = rb + rl; i < re; i += rs) {
             const size_t e = (size_t)i * d + c;
             int s0, cnt, st;
             row_slots<KC>(a, i, s0, cnt, st);
             const T ri = r[e];
             const T ui = mul_t(a.invdiag[i], ri);
             T accA = T(0);
-#pragma unroll(KC > 0 ? 4 : 2)
-            for (int k = 0; k < cnt; ++k) {
-                const int s = s0 + k * st;
-                const int j = a.scol[s];
-                const T ww = a.sw[s];
-                const T uj = mul_t(a.invdiag[j], r[(size_t)j * d + c]);
-                accA = fma_t(mul_t(ww, ww), uj, accA);
+            if constexpr (KC > 0) {
+                constexpr int G = slot_group<KC, GM>();
+                for (int k0 = 0; k0 < cnt; k0 += G) {
+                    int jj[G];
+                    T ww[G], rj[G], ij[G];
+#pragma unroll
+                    for (int k = 0; k < G; ++k) {
+                        const int sl = s0 + (k0 + k) * st;
+                        jj[k] = a.scol[sl];
+                        ww[k] = a.sw[sl];
+                    }
+#pragma unroll
+                    for (int k = 0; k < G; ++k) {
+                        rj[k] = r[(size_t)jj[k] * d + c];
+                        ij[k] = a.invdiag[jj[k]];
+                    }
+#pragma unroll
+                    for (int k = 0; k < G; ++k) accA = fma_t(mul_t(ww[k], ww[k]), mul_t(ij[k], rj[k]), accA);
+                }
+            } else {
+#pragma unroll 2
+                for (int k = 0; k < cnt; ++k) {
+                    const int s = s0 + k * st;
+                    const int j = a.scol[s];
+                    const T ww = a.sw[s];
+                    const T uj = mul_t(a.invdiag[j], r[(size_t)j * d + c]);
+                    accA = fma_t(mul_t(ww, ww), uj, accA);
+                }
             }
             const T wi = fma_t(a.diagA[i], ui, -mul_t(a.c_off, accA));
             w[e] = wi;
@@ -360,10 +445,10 @@ __device__ __forceinline__ void ph_w0(const KA<T>& a, int lb, double* sh) {
 //   p_i = u_i + beta p_{i-1}, s_i = w_i + beta s_{i-1}, x += alpha p_i,
 //   r_{i+1} = r_i - alpha s_i, u_{i+1} = r_{i+1} / diag(A), w_{i+1} = A u_{i+1};
 // partials of r.u, w.u and r.r of iteration i+1.
-template <int KC = 0, typename T>
+template <int KC = 0, int GM = 8, typename T>
 __device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh) {
     const int d = a.d, R = a.R, t = threadIdx.x;
-    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     const int it = ld_flag(&a.S->it);
     const bool first = (it == 0);
     const int cur = it & 1, nxt = cur ^ 1;
@@ -380,27 +465,59 @@ __device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh) {
         const int ci = sg * d + c;
         const T alpha = (T)a.cs.alpha[ci];
         const T beta = (T)a.cs.beta[ci];
-        for (int i = rb + rl; i < re; i += R) {
+        for (int i = rb + rl; i < re; i += rs) {
             const size_t e = (size_t)i * d + c;
             int s0, cnt, st;
             row_slots<KC>(a, i, s0, cnt, st);
+            // own-row loads are unconditional (selected below) so they issue together
             const T inv = a.invdiag[i];
             const T ri = r[e];
+            const T pold = a.p[e];
+            const T spi = sp[e];
+            const T wi = w[e];
             const T ui = mul_t(inv, ri);
-            const T pi = first ? ui : fma_t(beta, a.p[e], ui);
-            const T si = cg_s(first, beta, sp[e], w[e]);
+            const T pi = first ? ui : fma_t(beta, pold, ui);
+            const T si = cg_s(first, beta, spi, wi);
             const T rn_i = cg_r(alpha, si, ri);
             const T un_i = mul_t(inv, rn_i);
             T accA = T(0);
-#pragma unroll(KC > 0 ? 4 : 2)
-            for (int k = 0; k < cnt; ++k) {
-                const int s = s0 + k * st;
-                const int j = a.scol[s];
-                const T ww = a.sw[s];
-                const size_t ej = (size_t)j * d + c;
-                const T sj = cg_s(first, beta, sp[ej], w[ej]);
-                const T uj = mul_t(a.invdiag[j], cg_r(alpha, sj, r[ej]));
-                accA = fma_t(mul_t(ww, ww), uj, accA);
+            if constexpr (KC > 0) {
+                constexpr int G = slot_group<KC, GM>();
+                for (int k0 = 0; k0 < cnt; k0 += G) {
+                    int jj[G];
+                    T ww[G], spj[G], wj[G], rj[G], ij[G];
+#pragma unroll
+                    for (int k = 0; k < G; ++k) {
+                        const int sl = s0 + (k0 + k) * st;
+                        jj[k] = a.scol[sl];
+                        ww[k] = a.sw[sl];
+                    }
+#pragma unroll
+                    for (int k = 0; k < G; ++k) {
+                        const size_t ej = (size_t)jj[k] * d + c;
+                        spj[k] = sp[ej];
+                        wj[k] = w[ej];
+                        rj[k] = r[ej];
+                        ij[k] = a.invdiag[jj[k]];
+                    }
+#pragma unroll
+                    for (int k = 0; k < G; ++k) {
+                        const T sj = cg_s(first, beta, spj[k], wj[k]);
+                        const T uj = mul_t(ij[k], cg_r(alpha, sj, rj[k]));
+                        accA = fma_t(mul_t(ww[k], ww[k]), uj, accA);
+                    }
+                }
+            } else {
+#pragma unroll 2
+                for (int k = 0; k < cnt; ++k) {
+                    const int s = s0 + k * st;
+                    const int j = a.scol[s];
+                    const T ww = a.sw[s];
+                    const size_t ej = (size_t)j * d + c;
+                    const T sj = cg_s(first, beta, sp[ej], w[ej]);
+                    const T uj = mul_t(a.invdiag[j], cg_r(alpha, sj, r[ej]));
+                    accA = fma_t(mul_t(ww, ww), uj, accA);
+                }
             }
             const T wn_i = fma_t(a.diagA[i], un_i, -mul_t(a.c_off, accA));
             a.p[e] = pi;
@@ -418,18 +535,19 @@ __device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh) {
 
 // Learned-preconditioner PCG phases.  Buffers: r = rb[0], q = wb[0], p double
 // buffered in sb[it & 1] (new) / sb[(it & 1) ^ 1] (previous).
-template <typename T>
+template <int KC = 0, typename T>
 __device__ __forceinline__ void ph_lc(const KA<T>& a, int lb) {
     const int d = a.d, R = a.R, t = threadIdx.x;
-    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     const T* r = a.rb[0];
     if (t >= R * d) return;
     const int rl = t / d, c = t - rl * d;
-    for (int i = rb + rl; i < re; i += R) {
+    for (int i = rb + rl; i < re; i += rs) {
         const size_t e = (size_t)i * d + c;
         int s0, cnt, st;
-        row_slots(a, i, s0, cnt, st);
+        row_slots<KC>(a, i, s0, cnt, st);
         T acc = mul_t(a.gdiag[i], mul_t(a.isq[i], r[e]));
+#pragma unroll(KC > 0 ? 4 : 2)
         for (int k = 0; k < cnt; ++k) {
             const int s = s0 + k * st;
             const int j = a.scol[s];
@@ -439,19 +557,20 @@ __device__ __forceinline__ void ph_lc(const KA<T>& a, int lb) {
     }
 }
 
-template <typename T>
+template <int KC = 0, typename T>
 __device__ __forceinline__ void ph_ld(const KA<T>& a, int lb, double* sh) {
     const int d = a.d, R = a.R, t = threadIdx.x;
-    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     const T* r = a.rb[0];
     double acc2[2] = {0.0, 0.0};
     if (t < R * d) {
         const int rl = t / d, c = t - rl * d;
-        for (int i = rb + rl; i < re; i += R) {
+        for (int i = rb + rl; i < re; i += rs) {
             const size_t e = (size_t)i * d + c;
             int s0, cnt, st;
-            row_slots(a, i, s0, cnt, st);
+            row_slots<KC>(a, i, s0, cnt, st);
             T acc = mul_t(a.gdiag[i], a.y1[e]);
+#pragma unroll(KC > 0 ? 4 : 2)
             for (int k = 0; k < cnt; ++k) {
                 const int s = s0 + k * st;
                 const int j = a.scol[s];
@@ -467,10 +586,10 @@ __device__ __forceinline__ void ph_ld(const KA<T>& a, int lb, double* sh) {
     block_partials<2>(acc2, sh, d, R, a.part, a.nblk, lb);
 }
 
-template <typename T>
+template <int KC = 0, typename T>
 __device__ __forceinline__ void ph_la(const KA<T>& a, int lb, double* sh) {
     const int d = a.d, R = a.R, t = threadIdx.x;
-    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     const int it = ld_flag(&a.S->it);
     const bool first = (it == 0);
     T* pnew = a.sb[it & 1];
@@ -481,12 +600,13 @@ __device__ __forceinline__ void ph_la(const KA<T>& a, int lb, double* sh) {
     if (t < R * d) {
         const int rl = t / d, c = t - rl * d;
         const T beta = (T)a.cs.beta[sg * d + c];
-        for (int i = rb + rl; i < re; i += R) {
+        for (int i = rb + rl; i < re; i += rs) {
             const size_t e = (size_t)i * d + c;
             int s0, cnt, st;
-            row_slots(a, i, s0, cnt, st);
+            row_slots<KC>(a, i, s0, cnt, st);
             const T pi = first ? a.zl[e] : fma_t(beta, pold[e], a.zl[e]);
             T acc = T(0);
+#pragma unroll(KC > 0 ? 4 : 2)
             for (int k = 0; k < cnt; ++k) {
                 const int s = s0 + k * st;
                 const size_t ej = (size_t)a.scol[s] * d + c;
@@ -506,7 +626,7 @@ __device__ __forceinline__ void ph_la(const KA<T>& a, int lb, double* sh) {
 template <typename T>
 __device__ __forceinline__ void ph_lb(const KA<T>& a, int lb) {
     const int d = a.d, R = a.R, t = threadIdx.x;
-    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     const int it = ld_flag(&a.S->it);
     const T* p = a.sb[it & 1];
     const T* q = a.wb[0];
@@ -514,7 +634,7 @@ __device__ __forceinline__ void ph_lb(const KA<T>& a, int lb) {
     if (t >= R * d) return;
     const int rl = t / d, c = t - rl * d;
     const T alpha = (T)a.cs.alpha[a.blk_seg[lb] * d + c];
-    for (int i = rb + rl; i < re; i += R) {
+    for (int i = rb + rl; i < re; i += rs) {
         const size_t e = (size_t)i * d + c;
         a.x[e] = fma_t(alpha, p[e], a.x[e]);
         r[e] = fma_t(-alpha, q[e], r[e]);
@@ -525,11 +645,11 @@ __device__ __forceinline__ void ph_lb(const KA<T>& a, int lb) {
 template <typename T>
 __device__ __forceinline__ void ph_zero(const KA<T>& a, int lb) {
     const int d = a.d, R = a.R, t = threadIdx.x;
-    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     if (t < R * d) {
         const int rl = t / d, c = t - rl * d;
         if (!a.cs.zero[a.blk_seg[lb] * d + c]) return;
-        for (int i = rb + rl; i < re; i += R) a.x[(size_t)i * d + c] = T(0);
+        for (int i = rb + rl; i < re; i += rs) a.x[(size_t)i * d + c] = T(0);
     }
 }
 
@@ -546,7 +666,7 @@ template <typename T>
 __device__ __forceinline__ void ph_gram(const KA<T>& a, int lb, int mode, double* sh) {
     const int d = a.d, R = a.R, t = threadIdx.x;
     const int npair = d * (d + 1) / 2;
-    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     double* zt = sh;                  // R x d staged rows
     int pa[2] = {0, 0}, pb[2] = {0, 0};
     for (int h = 0; h < 2; ++h) {
@@ -556,7 +676,7 @@ __device__ __forceinline__ void ph_gram(const KA<T>& a, int lb, int mode, double
     double acc[2] = {0.0, 0.0};
     // the factorisations that follow only ever clear this flag
     if (lb == 0 && t == 0) a.S->ortho_ok = 1;
-    for (int base = rb; base < re; base += R) {
+    for (int base = rb; base < re; base += rs) {
         int rows = min(R, re - base);
         if (t < rows * d) {
             int rl = t / d, c = t - rl * d;
@@ -588,11 +708,11 @@ __device__ __forceinline__ void ph_gram(const KA<T>& a, int lb, int mode, double
 template <typename T>
 __device__ __forceinline__ void ph_apply(const KA<T>& a, int lb, int mode, double* sh, const double* Tg) {
     const int d = a.d, R = a.R, t = threadIdx.x;
-    const int rb = a.row0[lb], re = a.row0[lb + 1];
+    const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     double* Ts = sh;                  // d x d
     double* zt = sh + kMaxD * kMaxD;  // R x d
     for (int k = t; k < d * d; k += blockDim.x) Ts[k] = Tg[(k / d) * kMaxD + (k % d)];
-    for (int base = rb; base < re; base += R) {
+    for (int base = rb; base < re; base += rs) {
         int rows = min(R, re - base);
         __syncthreads();
         if (t < rows * d) {
@@ -1131,58 +1251,93 @@ __device__ __forceinline__ void group_reduce(const KA<T>& a, unsigned g, int m, 
 // Kernels
 // ---------------------------------------------------------------------------
 
-// One phase per launch; the last workgroup finalises.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_phase(KA<T> a, int ph, int mode, int do_r0) {
+// One phase per launch (the one-launch-per-phase path): a kernel per phase, the
+// row-gathering ones specialised on the ELL width KC; the last workgroup to
+// finish runs the finaliser.
+
+// residual family (PH_E0, PH_EU, PH_R0, PH_RHS in ph)
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_residual(KA<T> a, int ph, int do_r0) {
     __shared__ double sh[kSmemDoubles];
     const int lb = logical_block(a.nblk);
-    if ((ph == PH_IT || ph == PH_W0 || ph >= PH_LA) && ld_flag(&a.S->done)) return;
-    switch (ph) {
-        case PH_E0: case PH_EU: case PH_R0: case PH_RHS:
-            ph_residual(a, lb, ph, do_r0, a.b_zero, sh);
-            if (do_r0 && last_block(a.bar + kBarLast, a.nblk)) fin_res(a, sh, false);
-            break;
-        case PH_W0:
-            ph_w0(a, lb, sh);
-            if (last_block(a.bar + kBarLast, a.nblk)) fin_w0(a, sh, false);
-            break;
-        case PH_IT:
-            ph_it(a, lb, sh);
-            if (last_block(a.bar + kBarLast, a.nblk)) {
-                fin_it(a, sh, false);
-                if (threadIdx.x == 0 && a.S->done) solve_stats(a);
-            }
-            break;
-        case PH_ZERO:
-            ph_zero(a, lb);
-            break;
-        case PH_LA:
-            ph_la(a, lb, sh);
-            if (last_block(a.bar + kBarLast, a.nblk)) fin_la(a, sh);
-            break;
-        case PH_LB:
-            ph_lb(a, lb);
-            break;
-        case PH_LC:
-            ph_lc(a, lb);
-            break;
-        case PH_LD:
-            ph_ld(a, lb, sh);
-            if (last_block(a.bar + kBarLast, a.nblk)) {
-                fin_ld(a, sh, mode != 0);
-                if (threadIdx.x == 0 && a.S->done) solve_stats(a);
-            }
-            break;
-        case PH_GRAM:
-            ph_gram(a, lb, mode, sh);
-            // several segments: one workgroup per segment factors in k_factor
-            if (a.nseg == 1 && last_block(a.bar + kBarLast, a.nblk)) seg_factor(a, 0, mode, sh, false, a.Tm, true);
-            break;
-        case PH_APPLY:
-            if (!ld_flag(&a.S->ortho_ok)) return;
-            ph_apply(a, lb, mode, sh, a.Tm + (size_t)a.blk_seg[lb] * kMaxD * kMaxD);
-            break;
+    ph_residual<KC>(a, lb, ph, do_r0, a.b_zero, sh);
+    if (do_r0 && last_block(a.bar + kBarLast, a.nblk)) fin_res(a, sh, false);
+}
+
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_cg_w0(KA<T> a) {
+    __shared__ double sh[kSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    const int lb = logical_block(a.nblk);
+    ph_w0<KC>(a, lb, sh);
+    if (last_block(a.bar + kBarLast, a.nblk)) fin_w0(a, sh, false);
+}
+
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_cg_it(KA<T> a) {
+    __shared__ double sh[kSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    const int lb = logical_block(a.nblk);
+    ph_it<KC>(a, lb, sh);
+    if (last_block(a.bar + kBarLast, a.nblk)) {
+        fin_it(a, sh, false);
+        if (threadIdx.x == 0 && a.S->done) solve_stats(a);
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cg_zero(KA<T> a) {
+    ph_zero(a, logical_block(a.nblk));
+}
+
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_lpcg_aq(KA<T> a) {
+    __shared__ double sh[kSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    const int lb = logical_block(a.nblk);
+    ph_la<KC>(a, lb, sh);
+    if (last_block(a.bar + kBarLast, a.nblk)) fin_la(a, sh);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_lpcg_xr(KA<T> a) {
+    if (ld_flag(&a.S->done)) return;
+    ph_lb(a, logical_block(a.nblk));
+}
+
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_lpcg_g(KA<T> a) {
+    if (ld_flag(&a.S->done)) return;
+    ph_lc<KC>(a, logical_block(a.nblk));
+}
+
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_lpcg_gt(KA<T> a, int initial) {
+    __shared__ double sh[kSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    const int lb = logical_block(a.nblk);
+    ph_ld<KC>(a, lb, sh);
+    if (last_block(a.bar + kBarLast, a.nblk)) {
+        fin_ld(a, sh, initial != 0);
+        if (threadIdx.x == 0 && a.S->done) solve_stats(a);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gram(KA<T> a, int mode) {
+    __shared__ double sh[kSmemDoubles];
+    const int lb = logical_block(a.nblk);
+    ph_gram(a, lb, mode, sh);
+    // several segments: one workgroup per segment factors in k_factor
+    if (a.nseg == 1 && last_block(a.bar + kBarLast, a.nblk)) seg_factor(a, 0, mode, sh, false, a.Tm, true);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_apply(KA<T> a, int mode) {
+    __shared__ double sh[kSmemDoubles];
+    if (!ld_flag(&a.S->ortho_ok)) return;
+    const int lb = logical_block(a.nblk);
+    ph_apply(a, lb, mode, sh, a.Tm + (size_t)a.blk_seg[lb] * kMaxD * kMaxD);
 }
 
 // P-update factors of a batch: workgroup sg reduces and factors segment sg
@@ -1212,7 +1367,7 @@ struct Plan {
 // (the same FP64 operations in the same order in each of them), so the
 // P-update needs no further barrier.
 template <typename T, int KC>
-__global__ void __launch_bounds__(kBlock) k_soc(KA<T> a, Plan plan) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_soc(KA<T> a, Plan plan) {
     __shared__ double sh[kSmemDoubles];
     __shared__ double Tsh[kMaxD * kMaxD];
     const int lb = logical_block(a.nblk);
@@ -1228,14 +1383,14 @@ __global__ void __launch_bounds__(kBlock) k_soc(KA<T> a, Plan plan) {
     int l0 = plan.l_begin;
     for (int outer = 0; outer < plan.n_outer; ++outer) {
         for (int l = l0; l < plan.n_inner; ++l) {
-            ph_residual<KC>(a, lb, (l == 0) ? PH_E0 : PH_EU, 1, (l == 1) ? 1 : 0, sh);
+            ph_residual<KC, 4>(a, lb, (l == 0) ? PH_E0 : PH_EU, 1, (l == 1) ? 1 : 0, sh);
             if (!grid_sync(a.bar, nb, S, g2, [&] { fin_res(a, sh, one); })) return;
             if (!ld_flag(&S->done)) {
-                ph_w0<KC>(a, lb, sh);
+                ph_w0<KC, 4>(a, lb, sh);
                 if (!grid_sync(a.bar, nb, S, g2, [&] { fin_w0(a, sh, one); })) return;
             }
             while (!ld_flag(&S->done)) {
-                ph_it<KC>(a, lb, sh);
+                ph_it<KC, 4>(a, lb, sh);
                 if (!grid_sync(a.bar, nb, S, g3, [&] { fin_it(a, sh, one); })) return;
             }
             if (lb == 0 && threadIdx.x == 0) solve_stats(a);
@@ -1500,7 +1655,9 @@ using namespace pfe;
 // ranges; every workgroup inside one segment).
 struct Partition {
     int nblk = 0;
+    int team = 1;             // workgroups per team (cyclic chunk ownership)
     int* row0 = nullptr;      // device, nblk + 1
+    int* bit = nullptr;       // device, 3 nblk: first row, end row, stride
     int* blk_seg = nullptr;   // device, nblk
     int* seg_blk0 = nullptr;  // device, nseg + 1
 };
@@ -1544,7 +1701,31 @@ namespace {
 
 #define PFE_TRY(x) do { pfe_status s__ = (x); if (s__ != PFE_OK) return s__; } while (0)
 
-pfe_status make_partition(const std::vector<int64_t>& seg_rows, int want_blocks, Partition& P) {
+// Teams: runs of at most team_max consecutive logical workgroups of the same
+// segment and the same XCD band (logical index / (nblk / 8) when nblk is a
+// multiple of 8).  Member j of a team of m owning rows [b, e) takes the R-row
+// chunks b + (j + k m) R.
+static void team_iteration(const std::vector<int>& row0, const std::vector<int>& bseg, int R, int team_max,
+                           std::vector<int>& bit) {
+    const int nblk = (int)bseg.size();
+    const int band = (nblk % kNumXcd == 0) ? nblk / kNumXcd : nblk;
+    bit.assign(3 * (size_t)nblk, 0);
+    int t0 = 0;
+    while (t0 < nblk) {
+        int t1 = t0 + 1;
+        while (t1 < nblk && t1 - t0 < team_max && bseg[t1] == bseg[t0] && t1 / band == t0 / band) ++t1;
+        const int m = t1 - t0;
+        for (int j = 0; j < m; ++j) {
+            bit[3 * (t0 + j)] = row0[t0] + j * R;
+            bit[3 * (t0 + j) + 1] = row0[t1];
+            bit[3 * (t0 + j) + 2] = m * R;
+        }
+        t0 = t1;
+    }
+}
+
+pfe_status make_partition(const std::vector<int64_t>& seg_rows, int want_blocks, int R, int team_max,
+                          Partition& P) {
     // workgroups per segment proportional to its rows (at least one each)
     const int nseg = (int)seg_rows.size();
     int64_t n = 0;
@@ -1585,6 +1766,11 @@ pfe_status make_partition(const std::vector<int64_t>& seg_rows, int want_blocks,
     row0[total] = (int)base;
     sb0[nseg] = total;
     P.nblk = total;
+    P.team = std::max(1, team_max);
+    std::vector<int> bit;
+    team_iteration(row0, bseg, R, P.team, bit);
+    PFE_CHECK_HIP(hipMalloc((void**)&P.bit, sizeof(int) * bit.size()));
+    PFE_CHECK_HIP(hipMemcpy(P.bit, bit.data(), sizeof(int) * bit.size(), hipMemcpyHostToDevice));
     PFE_CHECK_HIP(hipMalloc((void**)&P.row0, sizeof(int) * (total + 1)));
     PFE_CHECK_HIP(hipMalloc((void**)&P.blk_seg, sizeof(int) * total));
     PFE_CHECK_HIP(hipMalloc((void**)&P.seg_blk0, sizeof(int) * (nseg + 1)));
@@ -1596,6 +1782,7 @@ pfe_status make_partition(const std::vector<int64_t>& seg_rows, int want_blocks,
 
 void free_partition(Partition& P) {
     if (P.row0) (void)hipFree(P.row0);
+    if (P.bit) (void)hipFree(P.bit);
     if (P.blk_seg) (void)hipFree(P.blk_seg);
     if (P.seg_blk0) (void)hipFree(P.seg_blk0);
     P = Partition{};
@@ -1611,6 +1798,7 @@ KA<T> make_args(pfe_ctx* c, const Partition& pt) {
     a.nseg = c->nseg;
     a.ell_K = c->g->ell_K;
     a.row0 = pt.row0;
+    a.bit = pt.bit;
     a.blk_seg = pt.blk_seg;
     a.seg_blk0 = pt.seg_blk0;
     a.rowptr = c->g->rowptr;
@@ -1657,9 +1845,36 @@ KA<T> make_args(pfe_ctx* c, const Partition& pt) {
     return a;
 }
 
+// launch kernel template K<T, KC> with KC the graph's ELL width when it has a
+// specialisation (4, 8, 24), else the generic loops (KC = 0)
+#define PFE_LAUNCH_KC(K, ellK, grid, stream, ...)                                                   \
+    do {                                                                                           \
+        switch (ellK) {                                                                            \
+            case 4: hipLaunchKernelGGL((K<T, 4>), grid, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+            case 8: hipLaunchKernelGGL((K<T, 8>), grid, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+            case 24: hipLaunchKernelGGL((K<T, 24>), grid, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+            default: hipLaunchKernelGGL((K<T, 0>), grid, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+        }                                                                                          \
+    } while (0)
+
 template <typename T>
 pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0) {
-    hipLaunchKernelGGL(k_phase<T>, dim3(a.nblk), dim3(kBlock), 0, c->stream, a, ph, mode, do_r0);
+    const dim3 grid(a.nblk);
+    hipStream_t st = c->stream;
+    const int K = a.ell_K;
+    switch (ph) {
+        case PH_E0: case PH_EU: case PH_R0: case PH_RHS: PFE_LAUNCH_KC(k_residual, K, grid, st, a, ph, do_r0); break;
+        case PH_W0: PFE_LAUNCH_KC(k_cg_w0, K, grid, st, a); break;
+        case PH_IT: PFE_LAUNCH_KC(k_cg_it, K, grid, st, a); break;
+        case PH_ZERO: hipLaunchKernelGGL(k_cg_zero<T>, grid, dim3(kBlock), 0, st, a); break;
+        case PH_LA: PFE_LAUNCH_KC(k_lpcg_aq, K, grid, st, a); break;
+        case PH_LB: hipLaunchKernelGGL(k_lpcg_xr<T>, grid, dim3(kBlock), 0, st, a); break;
+        case PH_LC: PFE_LAUNCH_KC(k_lpcg_g, K, grid, st, a); break;
+        case PH_LD: PFE_LAUNCH_KC(k_lpcg_gt, K, grid, st, a, mode); break;
+        case PH_GRAM: hipLaunchKernelGGL(k_gram<T>, grid, dim3(kBlock), 0, st, a, mode); break;
+        case PH_APPLY: hipLaunchKernelGGL(k_apply<T>, grid, dim3(kBlock), 0, st, a, mode); break;
+        default: set_error("unknown phase %d", ph); return PFE_E_ARG;
+    }
     PFE_CHECK_HIP(hipGetLastError());
     return PFE_OK;
 }
@@ -2025,7 +2240,9 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
         &occ, (p->dtype == PFE_FP64) ? soc_kernel<double>(g->ell_K) : soc_kernel<float>(g->ell_K), kBlock, 0);
     if (oe != hipSuccess) occ = 0;
     const int per_cu = std::max(0, std::min(occ, 2));
-    pfe_status s = make_partition(seg_rows, (int)std::min<int64_t>(want, 2048), c->pm);
+    int team = 64;
+    if (const char* ev = getenv("PFE_TEAM")) team = std::max(1, atoi(ev));   // launch-shape experiments
+    pfe_status s = make_partition(seg_rows, (int)std::min<int64_t>(want, 2048), R, team, c->pm);
     if (s == PFE_OK && p->persistent) {
         int64_t coop = (int64_t)per_cu * ncu;
         if (const char* ev = getenv("PFE_PERSISTENT_WG")) {
@@ -2035,7 +2252,7 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
         }
         if (coop > want) coop = want;
         coop -= coop % kNumXcd;
-        if (coop >= kNumXcd) s = make_partition(seg_rows, (int)coop, c->pc);
+        if (coop >= kNumXcd) s = make_partition(seg_rows, (int)coop, R, team, c->pc);
         if (c->pc.nblk % kNumXcd != 0 || c->pc.nblk > per_cu * ncu) free_partition(c->pc);
     }
     if (s != PFE_OK) { free_ctx(c); delete c; return s; }
