@@ -264,6 +264,60 @@ __device__ __forceinline__ int seg_chunk(int nq, int d) {
 template <int KC, int GM>
 constexpr int slot_group() { return KC <= 0 ? 1 : (KC <= GM ? KC : GM); }
 
+// LDS copy of the constant per-row data a workgroup of the persistent kernel
+// reads in every phase (ELL slot columns and weights, diag(A), its inverse,
+// D^{1/2}), filled once per launch when the workgroup's rows fit: the slot
+// lookups of the gathers then cost an LDS access instead of a global one.
+// Layout: chunk p of the workgroup (its p-th R-row chunk), row rl of the chunk:
+// col/w at (p KC + k) R + rl, per-row values at p R + rl.
+template <typename T>
+struct RowCache {
+    const int* col = nullptr;
+    const T* w = nullptr;
+    const T* inv = nullptr;
+    const T* dA = nullptr;
+    const T* sq = nullptr;
+};
+
+template <typename T>
+__host__ __device__ constexpr size_t row_cache_bytes(int np, int R, int K) {
+    return (size_t)np * R * ((size_t)K * (sizeof(int) + sizeof(T)) + 3 * sizeof(T));
+}
+
+template <typename T, int KC>
+__device__ __forceinline__ RowCache<T> fill_row_cache(const KA<T>& a, int lb, unsigned char* lds, int np) {
+    const int R = a.R;
+    const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
+    int* col = reinterpret_cast<int*>(lds);
+    T* w = reinterpret_cast<T*>(col + (size_t)np * KC * R);
+    T* inv = w + (size_t)np * KC * R;
+    T* dA = inv + (size_t)np * R;
+    T* sq = dA + (size_t)np * R;
+    for (int idx = threadIdx.x; idx < np * R; idx += blockDim.x) {
+        const int p = idx / R, rl = idx - p * R;
+        const int i = rb + p * rs + rl;
+        if (i < re) {
+            inv[idx] = a.invdiag[i];
+            dA[idx] = a.diagA[i];
+            sq[idx] = a.sqrtD[i];
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                const int sl = i + k * a.n;
+                col[(p * KC + k) * R + rl] = a.scol[sl];
+                w[(p * KC + k) * R + rl] = a.sw[sl];
+            }
+        }
+    }
+    __syncthreads();
+    RowCache<T> rc;
+    rc.col = col;
+    rc.w = w;
+    rc.inv = inv;
+    rc.dA = dA;
+    rc.sq = sq;
+    return rc;
+}
+
 // Residual phases.  For every owned element (i, c):
 //   EU : t = w (y_i - y_j) + b_s ; d_s = Shrink(t, 1/lambda) ; b_s = t - d_s   (Eqs. 9, 10)
 //        rhs = lambda/2 sum_s w (d_s - b_s) + r/2 D^{1/2} (P - B)               (Eq. 13)
@@ -271,15 +325,17 @@ constexpr int slot_group() { return KC <= 0 ? 1 : (KC <= GM ? KC : GM); }
 //   R0 : rhs from the stored rhs
 //   RHS: rhs from the stored b and d
 // then (unless RHS) r0 = rhs - A x, with FP64 partials of rhs^T rhs and r0^T r0.
-template <int KC = 0, int GM = 8, typename T>
-__device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, int do_r0, int b_zero, double* sh) {
+template <int KC = 0, int GM = 8, bool LC = false, typename T>
+__device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, int do_r0, int b_zero, double* sh,
+                                            const RowCache<T>& rc = RowCache<T>()) {
     const int d = a.d, R = a.R, t = threadIdx.x;
     const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     double acc[2] = {0.0, 0.0};
     T* r0 = a.rb[0];
     if (t < R * d) {
         const int rl = t / d, c = t - rl * d;
-        for (int i = rb + rl; i < re; i += rs) {
+        int p = 0;
+        for (int i = rb + rl; i < re; i += rs, ++p) {
             const size_t e = (size_t)i * d + c;
             int s0, cnt, st;
             row_slots<KC>(a, i, s0, cnt, st);
@@ -294,8 +350,9 @@ __device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, in
 #pragma unroll
                     for (int k = 0; k < G; ++k) {
                         const int sl = s0 + (k0 + k) * st;
-                        jj[k] = a.scol[sl];
-                        ww[k] = a.sw[sl];
+                        const int cix = (p * KC + k0 + k) * R + rl;
+                        jj[k] = LC ? rc.col[cix] : a.scol[sl];
+                        ww[k] = LC ? rc.w[cix] : a.sw[sl];
                         bo[k] = b_zero ? T(0) : a.bs[(size_t)sl * d + c];
                     }
 #pragma unroll
@@ -350,8 +407,9 @@ __device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, in
 #pragma unroll
                     for (int k = 0; k < G; ++k) {
                         const int sl = s0 + (k0 + k) * st;
-                        jj[k] = a.scol[sl];
-                        ww[k] = a.sw[sl];
+                        const int cix = (p * KC + k0 + k) * R + rl;
+                        jj[k] = LC ? rc.col[cix] : a.scol[sl];
+                        ww[k] = LC ? rc.w[cix] : a.sw[sl];
                     }
 #pragma unroll
                     for (int k = 0; k < G; ++k) xj[k] = a.x[(size_t)jj[k] * d + c];
@@ -370,12 +428,12 @@ __device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, in
             if (mode == PH_R0) {
                 rhs = a.rhs[e];
             } else {
-                const T split = mul_t(a.half_r, mul_t(a.sqrtD[i], a.P[e] - a.B[e]));
+                const T split = mul_t(a.half_r, mul_t(LC ? rc.sq[p * R + rl] : a.sqrtD[i], a.P[e] - a.B[e]));
                 rhs = (mode == PH_E0) ? split : fma_t(a.c_off, accR, split);
                 if (a.store_rhs || mode == PH_RHS) a.rhs[e] = rhs;
             }
             if (do_r0) {
-                const T ax = fma_t(a.diagA[i], xi, -mul_t(a.c_off, accA));
+                const T ax = fma_t(LC ? rc.dA[p * R + rl] : a.diagA[i], xi, -mul_t(a.c_off, accA));
                 const T rv = rhs - ax;
                 r0[e] = rv;
                 acc[0] += (double)rhs * (double)rhs;
@@ -387,8 +445,8 @@ __device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, in
 }
 
 // PH_W0: w0 = A u0 with u0 = r0 / diag(A); partials of r0.u0 and w0.u0.
-template <int KC = 0, int GM = 8, typename T>
-__device__ __forceinline__ void ph_w0(const KA<T>& a, int lb, double* sh) {
+template <int KC = 0, int GM = 8, bool LC = false, typename T>
+__device__ __forceinline__ void ph_w0(const KA<T>& a, int lb, double* sh, const RowCache<T>& rc = RowCache<T>()) {
     const int d = a.d, R = a.R, t = threadIdx.x;
     const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     const T* r = a.rb[0];
@@ -396,12 +454,13 @@ __device__ __forceinline__ void ph_w0(const KA<T>& a, int lb, double* sh) {
     double acc[2] = {0.0, 0.0};
     if (t < R * d) {
         const int rl = t / d, c = t - rl * d;
-        for (int i = rb + rl; i < re; i += rs) {
+        int p = 0;
+        for (int i = rb + rl; i < re; i += rs, ++p) {
             const size_t e = (size_t)i * d + c;
             int s0, cnt, st;
             row_slots<KC>(a, i, s0, cnt, st);
             const T ri = r[e];
-            const T ui = mul_t(a.invdiag[i], ri);
+            const T ui = mul_t(LC ? rc.inv[p * R + rl] : a.invdiag[i], ri);
             T accA = T(0);
             if constexpr (KC > 0) {
                 constexpr int G = slot_group<KC, GM>();
@@ -411,8 +470,9 @@ __device__ __forceinline__ void ph_w0(const KA<T>& a, int lb, double* sh) {
 #pragma unroll
                     for (int k = 0; k < G; ++k) {
                         const int sl = s0 + (k0 + k) * st;
-                        jj[k] = a.scol[sl];
-                        ww[k] = a.sw[sl];
+                        const int cix = (p * KC + k0 + k) * R + rl;
+                        jj[k] = LC ? rc.col[cix] : a.scol[sl];
+                        ww[k] = LC ? rc.w[cix] : a.sw[sl];
                     }
 #pragma unroll
                     for (int k = 0; k < G; ++k) {
@@ -432,7 +492,7 @@ __device__ __forceinline__ void ph_w0(const KA<T>& a, int lb, double* sh) {
                     accA = fma_t(mul_t(ww, ww), uj, accA);
                 }
             }
-            const T wi = fma_t(a.diagA[i], ui, -mul_t(a.c_off, accA));
+            const T wi = fma_t(LC ? rc.dA[p * R + rl] : a.diagA[i], ui, -mul_t(a.c_off, accA));
             w[e] = wi;
             acc[0] += (double)ri * (double)ui;
             acc[1] += (double)wi * (double)ui;
@@ -445,8 +505,8 @@ __device__ __forceinline__ void ph_w0(const KA<T>& a, int lb, double* sh) {
 //   p_i = u_i + beta p_{i-1}, s_i = w_i + beta s_{i-1}, x += alpha p_i,
 //   r_{i+1} = r_i - alpha s_i, u_{i+1} = r_{i+1} / diag(A), w_{i+1} = A u_{i+1};
 // partials of r.u, w.u and r.r of iteration i+1.
-template <int KC = 0, int GM = 8, typename T>
-__device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh) {
+template <int KC = 0, int GM = 8, bool LC = false, typename T>
+__device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh, const RowCache<T>& rc = RowCache<T>()) {
     const int d = a.d, R = a.R, t = threadIdx.x;
     const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     const int it = ld_flag(&a.S->it);
@@ -465,12 +525,13 @@ __device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh) {
         const int ci = sg * d + c;
         const T alpha = (T)a.cs.alpha[ci];
         const T beta = (T)a.cs.beta[ci];
-        for (int i = rb + rl; i < re; i += rs) {
+        int p = 0;
+        for (int i = rb + rl; i < re; i += rs, ++p) {
             const size_t e = (size_t)i * d + c;
             int s0, cnt, st;
             row_slots<KC>(a, i, s0, cnt, st);
             // own-row loads are unconditional (selected below) so they issue together
-            const T inv = a.invdiag[i];
+            const T inv = LC ? rc.inv[p * R + rl] : a.invdiag[i];
             const T ri = r[e];
             const T pold = a.p[e];
             const T spi = sp[e];
@@ -489,8 +550,9 @@ __device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh) {
 #pragma unroll
                     for (int k = 0; k < G; ++k) {
                         const int sl = s0 + (k0 + k) * st;
-                        jj[k] = a.scol[sl];
-                        ww[k] = a.sw[sl];
+                        const int cix = (p * KC + k0 + k) * R + rl;
+                        jj[k] = LC ? rc.col[cix] : a.scol[sl];
+                        ww[k] = LC ? rc.w[cix] : a.sw[sl];
                     }
 #pragma unroll
                     for (int k = 0; k < G; ++k) {
@@ -519,7 +581,7 @@ __device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh) {
                     accA = fma_t(mul_t(ww, ww), uj, accA);
                 }
             }
-            const T wn_i = fma_t(a.diagA[i], un_i, -mul_t(a.c_off, accA));
+            const T wn_i = fma_t(LC ? rc.dA[p * R + rl] : a.diagA[i], un_i, -mul_t(a.c_off, accA));
             a.p[e] = pi;
             sn[e] = si;
             a.x[e] = fma_t(alpha, pi, a.x[e]);
@@ -1358,6 +1420,7 @@ struct Plan {
     int l_begin;      // first inner index of the first SOC iteration
     int n_inner;      // inner iterations per SOC iteration
     int n_outer;      // SOC iterations to run
+    int cache_np;     // chunks per workgroup held in the LDS row cache (LC kernels)
 };
 
 // Persistent path: whole SOC iterations in one cooperative launch.  One
@@ -1366,11 +1429,14 @@ struct Plan {
 // after the Gram phase every workgroup factors its own segment's Gram matrix
 // (the same FP64 operations in the same order in each of them), so the
 // P-update needs no further barrier.
-template <typename T, int KC>
+template <typename T, int KC, bool LC>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_soc(KA<T> a, Plan plan) {
     __shared__ double sh[kSmemDoubles];
     __shared__ double Tsh[kMaxD * kMaxD];
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
     const int lb = logical_block(a.nblk);
+    RowCache<T> rc;
+    if constexpr (LC) rc = fill_row_cache<T, KC>(a, lb, dyn_lds, plan.cache_np);
     const unsigned nb = (unsigned)a.nblk;
     Scal* S = a.S;
     const int d = a.d;
@@ -1383,14 +1449,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
     int l0 = plan.l_begin;
     for (int outer = 0; outer < plan.n_outer; ++outer) {
         for (int l = l0; l < plan.n_inner; ++l) {
-            ph_residual<KC, 4>(a, lb, (l == 0) ? PH_E0 : PH_EU, 1, (l == 1) ? 1 : 0, sh);
+            ph_residual<KC, 4, LC>(a, lb, (l == 0) ? PH_E0 : PH_EU, 1, (l == 1) ? 1 : 0, sh, rc);
             if (!grid_sync(a.bar, nb, S, g2, [&] { fin_res(a, sh, one); })) return;
             if (!ld_flag(&S->done)) {
-                ph_w0<KC, 4>(a, lb, sh);
+                ph_w0<KC, 4, LC>(a, lb, sh, rc);
                 if (!grid_sync(a.bar, nb, S, g2, [&] { fin_w0(a, sh, one); })) return;
             }
             while (!ld_flag(&S->done)) {
-                ph_it<KC, 4>(a, lb, sh);
+                ph_it<KC, 4, LC>(a, lb, sh, rc);
                 if (!grid_sync(a.bar, nb, S, g3, [&] { fin_it(a, sh, one); })) return;
             }
             if (lb == 0 && threadIdx.x == 0) solve_stats(a);
@@ -1656,6 +1722,7 @@ using namespace pfe;
 struct Partition {
     int nblk = 0;
     int team = 1;             // workgroups per team (cyclic chunk ownership)
+    int max_np = 0;           // largest number of R-row chunks of one workgroup
     int* row0 = nullptr;      // device, nblk + 1
     int* bit = nullptr;       // device, 3 nblk: first row, end row, stride
     int* blk_seg = nullptr;   // device, nblk
@@ -1691,6 +1758,7 @@ struct pfe_ctx {
     double* Tm = nullptr;
     double* colbuf = nullptr;
     int* colint = nullptr;
+    int cache_np = 0;        // persistent kernel: LDS row cache chunks (0: no cache)
     ColState cs{};
     Scal* S = nullptr;
     unsigned* bar = nullptr;
@@ -1769,6 +1837,11 @@ pfe_status make_partition(const std::vector<int64_t>& seg_rows, int want_blocks,
     P.team = std::max(1, team_max);
     std::vector<int> bit;
     team_iteration(row0, bseg, R, P.team, bit);
+    P.max_np = 0;
+    for (int b = 0; b < total; ++b) {
+        const int rb = bit[3 * b], re = bit[3 * b + 1], rs = bit[3 * b + 2];
+        if (re > rb) P.max_np = std::max(P.max_np, (re - rb + rs - 1) / rs);
+    }
     PFE_CHECK_HIP(hipMalloc((void**)&P.bit, sizeof(int) * bit.size()));
     PFE_CHECK_HIP(hipMemcpy(P.bit, bit.data(), sizeof(int) * bit.size(), hipMemcpyHostToDevice));
     PFE_CHECK_HIP(hipMalloc((void**)&P.row0, sizeof(int) * (total + 1)));
@@ -1963,14 +2036,15 @@ pfe_status outer_mk(pfe_ctx* c) {
     return PFE_OK;
 }
 
-// persistent kernel specialised for the graph's ELL width (0: generic loops)
+// persistent kernel specialised for the graph's ELL width (0: generic loops),
+// with or without the LDS row cache
 template <typename T>
-const void* soc_kernel(int ell_K) {
+const void* soc_kernel(int ell_K, bool lc) {
     switch (ell_K) {
-        case 4: return reinterpret_cast<const void*>(&k_soc<T, 4>);
-        case 8: return reinterpret_cast<const void*>(&k_soc<T, 8>);
-        case 24: return reinterpret_cast<const void*>(&k_soc<T, 24>);
-        default: return reinterpret_cast<const void*>(&k_soc<T, 0>);
+        case 4: return lc ? reinterpret_cast<const void*>(&k_soc<T, 4, true>) : reinterpret_cast<const void*>(&k_soc<T, 4, false>);
+        case 8: return lc ? reinterpret_cast<const void*>(&k_soc<T, 8, true>) : reinterpret_cast<const void*>(&k_soc<T, 8, false>);
+        case 24: return lc ? reinterpret_cast<const void*>(&k_soc<T, 24, true>) : reinterpret_cast<const void*>(&k_soc<T, 24, false>);
+        default: return reinterpret_cast<const void*>(&k_soc<T, 0, false>);
     }
 }
 
@@ -1982,10 +2056,12 @@ pfe_status outer_coop(pfe_ctx* c, int n_outer) {
         if (--n_outer == 0) return PFE_OK;
     }
     KA<T> a = make_args<T>(c, c->pc);
-    Plan plan{0, c->prm.n_inner, n_outer};
+    const bool lc = c->cache_np > 0;
+    Plan plan{0, c->prm.n_inner, n_outer, lc ? c->cache_np : 0};
+    const size_t dyn = lc ? row_cache_bytes<T>(c->cache_np, a.R, c->g->ell_K) : 0;
     PFE_CHECK_HIP(hipMemsetAsync(c->bar, 0, 512 * sizeof(unsigned), c->stream));
     void* args[] = {(void*)&a, (void*)&plan};
-    PFE_CHECK_HIP(hipLaunchCooperativeKernel(soc_kernel<T>(c->g->ell_K), dim3(a.nblk), dim3(kBlock), args, 0,
+    PFE_CHECK_HIP(hipLaunchCooperativeKernel(soc_kernel<T>(c->g->ell_K, lc), dim3(a.nblk), dim3(kBlock), args, dyn,
                                              c->stream));
     c->inner = 0;
     return PFE_OK;
@@ -2237,7 +2313,7 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
     const int64_t want = (c->n + R - 1) / R;
     int occ = 0;
     hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &occ, (p->dtype == PFE_FP64) ? soc_kernel<double>(g->ell_K) : soc_kernel<float>(g->ell_K), kBlock, 0);
+        &occ, (p->dtype == PFE_FP64) ? soc_kernel<double>(g->ell_K, false) : soc_kernel<float>(g->ell_K, false), kBlock, 0);
     if (oe != hipSuccess) occ = 0;
     const int per_cu = std::max(0, std::min(occ, 2));
     int team = 64;
@@ -2254,6 +2330,20 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
         coop -= coop % kNumXcd;
         if (coop >= kNumXcd) s = make_partition(seg_rows, (int)coop, R, team, c->pc);
         if (c->pc.nblk % kNumXcd != 0 || c->pc.nblk > per_cu * ncu) free_partition(c->pc);
+    }
+    if (s == PFE_OK && c->pc.nblk > 0 && g->ell_K > 0 && (g->ell_K == 4 || g->ell_K == 8 || g->ell_K == 24)) {
+        // LDS row cache when the persistent workgroups' rows fit without
+        // lowering their co-residency
+        const size_t bytes = (p->dtype == PFE_FP64) ? row_cache_bytes<double>(c->pc.max_np, R, g->ell_K)
+                                                    : row_cache_bytes<float>(c->pc.max_np, R, g->ell_K);
+        int occ_lc = 0;
+        bool want_lc = bytes <= 48 * 1024;
+        if (const char* ev = getenv("PFE_ROWCACHE")) want_lc = want_lc && atoi(ev) != 0;   // experiments
+        if (want_lc && hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                           &occ_lc, (p->dtype == PFE_FP64) ? soc_kernel<double>(g->ell_K, true) : soc_kernel<float>(g->ell_K, true),
+                           kBlock, bytes) == hipSuccess &&
+            occ_lc >= per_cu)
+            c->cache_np = c->pc.max_np;
     }
     if (s != PFE_OK) { free_ctx(c); delete c; return s; }
     const int nblk_max = std::max(c->pm.nblk, c->pc.nblk);

@@ -362,3 +362,22 @@ def test_edge_quantile_matches_order_statistic():
     S32 = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=2)
     got = S32.edge_quantile(0.99)
     assert abs(got - v[int(np.floor(0.99 * (v.size - 1)))]) <= 1e-5 * got
+
+
+@pytest.mark.parametrize("name", ["voronoi96x80_8nbr", "voronoi48x40_r2", "voronoi64_4nbr"])
+def test_lds_row_cache_is_bitwise_neutral(name, monkeypatch):
+    """The persistent kernel's LDS copy of the rows' slot data gives bitwise the
+    same iteration as reading it from global memory."""
+    from paper_1612_06496_amd import Solver
+    banner(f"LDS row cache {name}")
+    wl = load(name)
+    G = gpu_graph(wl)
+    out = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("PFE_ROWCACHE", flag)
+        S = Solver(G, wl.y0, lam=30.0, r=30.0, n_inner=3, tol=1e-6, maxit=1000, persistent=True)
+        info = S.solve(2, info=True)
+        assert info["workgroups"] > 0
+        out.append((to_np(S.get("Y")), to_np(S.get("P")), to_np(S.get("B"))))
+    for k in range(3):
+        assert np.array_equal(out[0][k], out[1][k])
