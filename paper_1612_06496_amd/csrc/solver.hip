@@ -505,11 +505,12 @@ __device__ __forceinline__ void ph_w0(const KA<T>& a, int lb, double* sh, const 
 //   p_i = u_i + beta p_{i-1}, s_i = w_i + beta s_{i-1}, x += alpha p_i,
 //   r_{i+1} = r_i - alpha s_i, u_{i+1} = r_{i+1} / diag(A), w_{i+1} = A u_{i+1};
 // partials of r.u, w.u and r.r of iteration i+1.
+//   it: iteration index; alphas, betas: the scalars per (segment, column).
 template <int KC = 0, int GM = 8, bool LC = false, typename T>
-__device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh, const RowCache<T>& rc = RowCache<T>()) {
+__device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh, int it, const double* alphas,
+                                      const double* betas, const RowCache<T>& rc = RowCache<T>()) {
     const int d = a.d, R = a.R, t = threadIdx.x;
     const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
-    const int it = ld_flag(&a.S->it);
     const bool first = (it == 0);
     const int cur = it & 1, nxt = cur ^ 1;
     const T* r = a.rb[cur];
@@ -523,8 +524,8 @@ __device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh, const 
     if (t < R * d) {
         const int rl = t / d, c = t - rl * d;
         const int ci = sg * d + c;
-        const T alpha = (T)a.cs.alpha[ci];
-        const T beta = (T)a.cs.beta[ci];
+        const T alpha = (T)alphas[ci];
+        const T beta = (T)betas[ci];
         int p = 0;
         for (int i = rb + rl; i < re; i += rs, ++p) {
             const size_t e = (size_t)i * d + c;
@@ -705,12 +706,12 @@ __device__ __forceinline__ void ph_lb(const KA<T>& a, int lb) {
 
 // PH_ZERO: x_c = 0 for columns with a zero right-hand side
 template <typename T>
-__device__ __forceinline__ void ph_zero(const KA<T>& a, int lb) {
+__device__ __forceinline__ void ph_zero(const KA<T>& a, int lb, const int* zero) {
     const int d = a.d, R = a.R, t = threadIdx.x;
     const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     if (t < R * d) {
         const int rl = t / d, c = t - rl * d;
-        if (!a.cs.zero[a.blk_seg[lb] * d + c]) return;
+        if (!zero[a.blk_seg[lb] * d + c]) return;
         for (int i = rb + rl; i < re; i += rs) a.x[(size_t)i * d + c] = T(0);
     }
 }
@@ -1184,12 +1185,13 @@ __device__ __forceinline__ bool factor_gram(const KA<T>& a, int mode, const doub
 
 // Gram sum of segment sg (grouped: the per-XCD-group partials of the single
 // segment) and its factor, written to Tout.
+// (gp: the per-XCD-group partial buffer when grouped)
 template <typename T>
 __device__ __forceinline__ bool seg_factor(const KA<T>& a, int sg, int mode, double* sh, bool grouped, double* Tout,
-                                           bool report) {
+                                           bool report, const double* gp = nullptr) {
     const int npair = a.d * (a.d + 1) / 2;
     __shared__ double gsum[kMaxD * (kMaxD + 1) / 2];
-    if (grouped) reduce_range(a.gpart, kNumXcd, 0, kNumXcd, npair, 1, gsum, sh);
+    if (grouped) reduce_range(gp, kNumXcd, 0, kNumXcd, npair, 1, gsum, sh);
     else reduce_range(a.part, a.nblk, a.seg_blk0[sg], a.seg_blk0[sg + 1], npair, 1, gsum, sh);
     return factor_gram(a, mode, gsum, sh, Tout, report);
 }
@@ -1298,15 +1300,151 @@ struct NoFin {
 // group pre-reduction of nq quantities of m values each (single segment):
 // gpart[(q * 8 + g) * m + c] = sum over the group's workgroups
 template <typename T>
-__device__ __forceinline__ void group_reduce(const KA<T>& a, unsigned g, int m, int nq, double* sh) {
+__device__ __forceinline__ void group_reduce(const KA<T>& a, unsigned g, int m, int nq, double* sh, double* gp) {
     const int gs = a.nblk / kNumXcd;
     double* out = sh + 1024;
     reduce_range(a.part, a.nblk, (int)g * gs, (int)(g + 1) * gs, m, nq, out, sh);
     for (int k = threadIdx.x; k < nq * m; k += blockDim.x) {
         int q = k / m, c = k - q * m;
-        a.gpart[((size_t)q * kNumXcd + g) * m + c] = out[k];
+        gp[((size_t)q * kNumXcd + g) * m + c] = out[k];
     }
     __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Per-workgroup CG state (persistent kernel, single segment).  After each grid
+// barrier every workgroup sums the eight per-XCD-group partials itself, in the
+// same order, and advances its own LDS copy of the column scalars and
+// convergence flags (the copies stay bitwise identical), so the barrier only
+// counts arrivals and no finaliser runs between the last arrival and the
+// release.  Workgroup 0 records the statistics.
+// ---------------------------------------------------------------------------
+struct LocState {
+    double gamma[kMaxD], alpha[kMaxD], beta[kMaxD], bnorm2[kMaxD], rr[kMaxD];
+    int iters[kMaxD], active[kMaxD], zero[kMaxD];
+    int it, done, status, any_zero;
+};
+
+// per-XCD-group partial buffer of the k-th barrier of a launch (two buffers:
+// a workgroup may still read one while the next barrier's leaders write the other)
+constexpr int kGroupStride = kNumXcd * (kMaxD * (kMaxD + 1) / 2 > 3 * kMaxD ? kMaxD * (kMaxD + 1) / 2 : 3 * kMaxD);
+
+template <typename T>
+__device__ __forceinline__ void lfin_res(const KA<T>& a, LocState& L, const double* gp, double* sh) {
+    const int d = a.d, t = threadIdx.x;
+    double* out = sh + 1024;
+    reduce_range(gp, kNumXcd, 0, kNumXcd, d, 2, out, sh);
+    if (t < d) {
+        const double bb = out[t], rr = out[d + t];
+        L.bnorm2[t] = bb;
+        L.rr[t] = rr;
+        L.iters[t] = 0;
+        L.alpha[t] = 0.0;
+        L.beta[t] = 0.0;
+        L.zero[t] = (bb == 0.0);
+        L.active[t] = !L.zero[t] && (rr > a.tol2 * bb);
+    }
+    __syncthreads();
+    if (t == 0) {
+        int any = 0, anyz = 0;
+        for (int c = 0; c < d; ++c) { any |= L.active[c]; anyz |= L.zero[c]; }
+        L.it = 0;
+        L.done = !any;
+        L.any_zero = anyz;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void lfin_w0(const KA<T>& a, LocState& L, const double* gp, double* sh) {
+    const int d = a.d, t = threadIdx.x;
+    double* out = sh + 1024;
+    reduce_range(gp, kNumXcd, 0, kNumXcd, d, 2, out, sh);
+    __shared__ int s_bad;
+    if (t == 0) s_bad = 0;
+    __syncthreads();
+    if (t < d) {
+        const double g = out[t], dl = out[d + t];
+        L.gamma[t] = g;
+        double al = 0.0;
+        if (L.active[t]) {
+            al = g / dl;
+            if (!(dl > 0.0) || !(g > 0.0) || !isfinite(al)) { s_bad = 1; al = 0.0; }
+        }
+        L.alpha[t] = al;
+        L.beta[t] = 0.0;
+    }
+    __syncthreads();
+    if (t == 0 && s_bad) {
+        L.status = PFE_E_NOT_SPD;
+        L.done = 1;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void lfin_it(const KA<T>& a, LocState& L, const double* gp, double* sh) {
+    const int d = a.d, t = threadIdx.x;
+    double* out = sh + 1024;
+    reduce_range(gp, kNumXcd, 0, kNumXcd, d, 3, out, sh);
+    __shared__ int s_bad;
+    if (t == 0) s_bad = 0;
+    __syncthreads();
+    if (t < d) {
+        int act = L.active[t];
+        if (act) {
+            const double g = out[t], dl = out[d + t], rr = out[2 * d + t];
+            L.iters[t] += 1;
+            L.rr[t] = rr;
+            act = rr > a.tol2 * L.bnorm2[t];
+            if (!isfinite(rr)) { s_bad = 1; act = 0; }
+            if (act) {
+                double be = g / L.gamma[t];
+                double den = dl - be * g / L.alpha[t];
+                double al = g / den;
+                if (!(den > 0.0) || !isfinite(al) || !isfinite(be)) { s_bad = 1; act = 0; al = 0.0; be = 0.0; }
+                L.beta[t] = be;
+                L.alpha[t] = al;
+                L.gamma[t] = g;
+            }
+        }
+        if (!act) {
+            L.alpha[t] = 0.0;
+            L.beta[t] = 0.0;
+        }
+        L.active[t] = act;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int any = 0;
+        for (int c = 0; c < d; ++c) any |= L.active[c];
+        if (s_bad) L.status = PFE_E_NOT_SPD;
+        const int it = L.it + 1;
+        L.it = it;
+        if (any && it >= a.maxit) {
+            if (L.status == 0) L.status = PFE_E_NOCONV;
+            any = 0;
+        }
+        L.done = !any;
+    }
+    __syncthreads();
+}
+
+// statistics of a finished solve from the local state (one thread)
+template <typename T>
+__device__ __forceinline__ void solve_stats_loc(const KA<T>& a, const LocState& L) {
+    int mx = 0;
+    double rel = 0.0;
+    for (int c = 0; c < a.d; ++c) {
+        mx = max(mx, L.iters[c]);
+        if (L.bnorm2[c] > 0.0) rel = fmax(rel, sqrt(L.rr[c] / L.bnorm2[c]));
+    }
+    a.S->solves += 1;
+    a.S->iters_total += mx;
+    a.S->iters_max = max(a.S->iters_max, mx);
+    a.S->iters_last = mx;
+    a.S->relres_max = fmax(a.S->relres_max, rel);
+    if (L.status != 0 && (a.S->status == 0 || L.status == PFE_E_NOT_SPD)) a.S->status = L.status;
 }
 
 // ---------------------------------------------------------------------------
@@ -1340,7 +1478,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_it(KA<T> a) {
     __shared__ double sh[kSmemDoubles];
     if (ld_flag(&a.S->done)) return;
     const int lb = logical_block(a.nblk);
-    ph_it<KC>(a, lb, sh);
+    ph_it<KC>(a, lb, sh, ld_flag(&a.S->it), a.cs.alpha, a.cs.beta);
     if (last_block(a.bar + kBarLast, a.nblk)) {
         fin_it(a, sh, false);
         if (threadIdx.x == 0 && a.S->done) solve_stats(a);
@@ -1349,7 +1487,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_it(KA<T> a) {
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_cg_zero(KA<T> a) {
-    ph_zero(a, logical_block(a.nblk));
+    ph_zero(a, logical_block(a.nblk), a.cs.zero);
 }
 
 template <typename T, int KC>
@@ -1442,45 +1580,79 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
     const int d = a.d;
     const int npair = d * (d + 1) / 2;
     const bool one = (a.nseg == 1);
-    auto g2 = [&](unsigned g) { if (one) group_reduce(a, g, d, 2, sh); };
-    auto g3 = [&](unsigned g) { if (one) group_reduce(a, g, d, 3, sh); };
-    auto gg = [&](unsigned g) { if (one) group_reduce(a, g, npair, 1, sh); };
     const int ncol = a.nseg * d;
     int l0 = plan.l_begin;
+    if (one) {
+        __shared__ LocState L;
+        if (threadIdx.x == 0) L.status = 0;
+        int par = 0;
+        // the group partial buffer of the next barrier
+        auto gbuf = [&]() { double* gp = a.gpart + (size_t)par * kGroupStride; par ^= 1; return gp; };
+        for (int outer = 0; outer < plan.n_outer; ++outer) {
+            for (int l = l0; l < plan.n_inner; ++l) {
+                ph_residual<KC, 4, LC>(a, lb, (l == 0) ? PH_E0 : PH_EU, 1, (l == 1) ? 1 : 0, sh, rc);
+                double* gp = gbuf();
+                if (!grid_sync(a.bar, nb, S, [&](unsigned g) { group_reduce(a, g, d, 2, sh, gp); }, NoFin{})) return;
+                lfin_res(a, L, gp, sh);
+                if (!L.done) {
+                    ph_w0<KC, 4, LC>(a, lb, sh, rc);
+                    gp = gbuf();
+                    if (!grid_sync(a.bar, nb, S, [&](unsigned g) { group_reduce(a, g, d, 2, sh, gp); }, NoFin{})) return;
+                    lfin_w0(a, L, gp, sh);
+                }
+                while (!L.done) {
+                    ph_it<KC, 4, LC>(a, lb, sh, L.it, L.alpha, L.beta, rc);
+                    gp = gbuf();
+                    if (!grid_sync(a.bar, nb, S, [&](unsigned g) { group_reduce(a, g, d, 3, sh, gp); }, NoFin{})) return;
+                    lfin_it(a, L, gp, sh);
+                }
+                if (lb == 0 && threadIdx.x == 0) solve_stats_loc(a, L);
+                if (L.any_zero) {
+                    // columns with a zero right-hand side: x_c = 0
+                    ph_zero(a, lb, L.zero);
+                    gbuf();
+                    if (!grid_sync(a.bar, nb, S, NoFin{}, NoFin{})) return;
+                }
+            }
+            l0 = 0;
+            ph_gram(a, lb, 0, sh);
+            double* gp = gbuf();
+            if (!grid_sync(a.bar, nb, S, [&](unsigned g) { group_reduce(a, g, npair, 1, sh, gp); },
+                           [&] { seg_factor(a, 0, 0, sh, true, a.Tm, true, gp); }))
+                return;
+            if (!ld_flag(&S->ortho_ok)) return;
+            ph_apply(a, lb, 0, sh, a.Tm);
+        }
+        return;
+    }
     for (int outer = 0; outer < plan.n_outer; ++outer) {
         for (int l = l0; l < plan.n_inner; ++l) {
             ph_residual<KC, 4, LC>(a, lb, (l == 0) ? PH_E0 : PH_EU, 1, (l == 1) ? 1 : 0, sh, rc);
-            if (!grid_sync(a.bar, nb, S, g2, [&] { fin_res(a, sh, one); })) return;
+            if (!grid_sync(a.bar, nb, S, NoFin{}, [&] { fin_res(a, sh, false); })) return;
             if (!ld_flag(&S->done)) {
                 ph_w0<KC, 4, LC>(a, lb, sh, rc);
-                if (!grid_sync(a.bar, nb, S, g2, [&] { fin_w0(a, sh, one); })) return;
+                if (!grid_sync(a.bar, nb, S, NoFin{}, [&] { fin_w0(a, sh, false); })) return;
             }
             while (!ld_flag(&S->done)) {
-                ph_it<KC, 4, LC>(a, lb, sh, rc);
-                if (!grid_sync(a.bar, nb, S, g3, [&] { fin_it(a, sh, one); })) return;
+                ph_it<KC, 4, LC>(a, lb, sh, ld_flag(&S->it), a.cs.alpha, a.cs.beta, rc);
+                if (!grid_sync(a.bar, nb, S, NoFin{}, [&] { fin_it(a, sh, false); })) return;
             }
             if (lb == 0 && threadIdx.x == 0) solve_stats(a);
             int any_zero = 0;
             for (int c = 0; c < ncol; ++c) any_zero |= a.cs.zero[c];
             if (any_zero) {
                 // columns with a zero right-hand side: x_c = 0
-                ph_zero(a, lb);
+                ph_zero(a, lb, a.cs.zero);
                 if (!grid_sync(a.bar, nb, S, NoFin{}, NoFin{})) return;
             }
         }
         l0 = 0;
         ph_gram(a, lb, 0, sh);
-        if (one) {
-            if (!grid_sync(a.bar, nb, S, gg, [&] { seg_factor(a, 0, 0, sh, true, a.Tm, true); })) return;
-            if (!ld_flag(&S->ortho_ok)) return;
-            ph_apply(a, lb, 0, sh, a.Tm);
-        } else {
-            if (!grid_sync(a.bar, nb, S, NoFin{}, NoFin{})) return;
-            const int sg = a.blk_seg[lb];
-            // a segment whose Gram matrix is singular keeps its P and B; the
-            // first workgroup of the segment records the failure
-            if (seg_factor(a, sg, 0, sh, false, Tsh, lb == a.seg_blk0[sg])) ph_apply(a, lb, 0, sh, Tsh);
-        }
+        if (!grid_sync(a.bar, nb, S, NoFin{}, NoFin{})) return;
+        const int sg = a.blk_seg[lb];
+        // a segment whose Gram matrix is singular keeps its P and B; the
+        // first workgroup of the segment records the failure
+        if (seg_factor(a, sg, 0, sh, false, Tsh, lb == a.seg_blk0[sg])) ph_apply(a, lb, 0, sh, Tsh);
         // P and B of a row are written and read by the same workgroup; the
         // barrier after the next residual phase orders everything else.
     }
@@ -2360,7 +2532,7 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
     ALLOC(c->diagA, nv); ALLOC(c->invdiag, nv); ALLOC(c->sqrtD, nv); ALLOC(c->isqrtD, nv); ALLOC(c->isq, nv);
     ALLOC(c->gval, (size_t)(g->nslot + 1) * c->esz); ALLOC(c->gdiag, nv); ALLOC(c->zl, nd); ALLOC(c->y1, nd);
     ALLOC(c->part, sizeof(double) * part_doubles);
-    ALLOC(c->gpart, sizeof(double) * kNumXcd * std::max(3 * kMaxD, kMaxD * (kMaxD + 1) / 2));
+    ALLOC(c->gpart, sizeof(double) * 2 * kGroupStride);
     ALLOC(c->Tm, sizeof(double) * c->nseg * kMaxD * kMaxD);
     ALLOC(c->colbuf, sizeof(double) * ncol * 5);
     ALLOC(c->colint, sizeof(int) * ncol * 3);
