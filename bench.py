@@ -259,7 +259,8 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None if args.multi_launch else measured_traffic(args.workload),
             "kernel": "one kernel per phase" if args.multi_launch else "k_soc (one SOC iteration per launch)",
-            "bytes_per_launch": int(byt / args.steps), "workgroups": info["workgroups"]}
+            "bytes_per_launch": int(byt / args.steps), "workgroups": info["workgroups"],
+            "launch_flags": info["flags"]}
     default = args.workload == WORKLOAD
     line = {
         "metric": "PFE outer iters/sec at 481x321 d=10 (Jacobi-PCG to 1e-6)" if default else

@@ -149,7 +149,7 @@ typedef struct {
     int32_t status;          /* worst pfe_status met (PFE_E_NOCONV, PFE_E_NOT_SPD, ...) */
     int32_t fallbacks;       /* learned-preconditioner solves redone with Jacobi */
     int32_t workgroups;      /* workgroups of the persistent launch (0: one launch per phase) */
-    int32_t reserved;
+    int32_t flags;           /* persistent launch: bit 0 the rows' slot data were held in LDS */
 } pfe_step_info;
 
 /* Monitors of the current state (Eq. 1, Eq. 2). */

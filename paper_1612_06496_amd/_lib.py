@@ -56,7 +56,7 @@ class pfe_step_info(C.Structure):
         ("solves", C.c_int64), ("cg_iters_total", C.c_int64),
         ("cg_iters_max", C.c_int32), ("cg_iters_last", C.c_int32),
         ("rel_res_max", C.c_double), ("status", C.c_int32), ("fallbacks", C.c_int32),
-        ("workgroups", C.c_int32), ("reserved", C.c_int32),
+        ("workgroups", C.c_int32), ("flags", C.c_int32),
     ]
 
 

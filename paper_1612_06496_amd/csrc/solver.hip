@@ -1931,6 +1931,7 @@ struct pfe_ctx {
     double* colbuf = nullptr;
     int* colint = nullptr;
     int cache_np = 0;        // persistent kernel: LDS row cache chunks (0: no cache)
+    int launched_coop = 0;   // the last advance ran the persistent kernel
     ColState cs{};
     Scal* S = nullptr;
     unsigned* bar = nullptr;
@@ -2235,6 +2236,7 @@ pfe_status outer_coop(pfe_ctx* c, int n_outer) {
     void* args[] = {(void*)&a, (void*)&plan};
     PFE_CHECK_HIP(hipLaunchCooperativeKernel(soc_kernel<T>(c->g->ell_K, lc), dim3(a.nblk), dim3(kBlock), args, dyn,
                                              c->stream));
+    c->launched_coop = 1;
     c->inner = 0;
     return PFE_OK;
 }
@@ -2253,7 +2255,7 @@ pfe_status read_info(pfe_ctx* c, pfe_step_info* info) {
         info->status = h.status;
         info->fallbacks = h.fallbacks;
         info->workgroups = (c->prm.persistent && c->pc.nblk > 0) ? c->pc.nblk : 0;
-        info->reserved = 0;
+        info->flags = (c->launched_coop && c->cache_np > 0) ? 1 : 0;
     }
     if (h.status != 0) {
         set_error("%s", pfe_status_string((pfe_status)h.status));
@@ -2618,6 +2620,7 @@ pfe_status pfe_set_penalties(pfe_ctx* c, double lambda, double r) {
 
 pfe_status pfe_step(pfe_ctx* c, int granularity, pfe_step_info* info) {
     if (!c) { set_error("null context"); return PFE_E_ARG; }
+    c->launched_coop = 0;
     if (info) PFE_TRY(reset_stats(c));
     pfe_status s;
     const bool f64 = c->prm.dtype == PFE_FP64;
@@ -2640,6 +2643,7 @@ pfe_status pfe_step(pfe_ctx* c, int granularity, pfe_step_info* info) {
 
 pfe_status pfe_solve(pfe_ctx* c, int n_outer, pfe_step_info* info) {
     if (!c || n_outer < 0) { set_error("pfe_solve: bad argument"); return PFE_E_ARG; }
+    c->launched_coop = 0;
     if (info) PFE_TRY(reset_stats(c));
     const bool f64 = c->prm.dtype == PFE_FP64;
     if (c->prm.persistent && c->pc.nblk > 0 && n_outer > 0 && c->prm.precond == PFE_JACOBI) {

@@ -126,7 +126,7 @@ class Solver:
         return dict(solves=info.solves, cg_iters_total=info.cg_iters_total,
                     cg_iters_max=info.cg_iters_max, cg_iters_last=info.cg_iters_last,
                     rel_res_max=info.rel_res_max, status=info.status, fallbacks=info.fallbacks,
-                    workgroups=info.workgroups)
+                    workgroups=info.workgroups, flags=info.flags)
 
     def step(self, granularity: str = "outer", info: bool = False, allow_noconv: bool = False):
         g = L.PFE_INNER if granularity == "inner" else L.PFE_OUTER
