@@ -123,6 +123,9 @@ typedef struct {
  *   keep_split 1: also store the split variable d (needed by pfe_get(PFE_DSPLIT))
  *   persistent 1: run each SOC iteration as one cooperative launch with grid
  *              barriers; 0: one launch per phase with stream-ordered phases
+ *   graphs     1: in the one-launch-per-phase mode (and for the learned
+ *              preconditioner), replay the PCG iterations from a HIP graph of 8
+ *              iterations instead of launching each kernel from the host
  */
 typedef struct {
     int d;
@@ -137,6 +140,7 @@ typedef struct {
     int init_ortho;
     int keep_split;
     int persistent;
+    int graphs;
 } pfe_params;
 
 /* Per-call solver statistics (filled when a non-null pointer is passed). */
@@ -225,6 +229,32 @@ pfe_status pfe_step(pfe_ctx* c, int granularity, pfe_step_info* info);
 
 /* n_outer calls of pfe_step(PFE_OUTER) (Algorithm 1 for a fixed count). */
 pfe_status pfe_solve(pfe_ctx* c, int n_outer, pfe_step_info* info);
+
+/* Launch shape of the solver (how the same arithmetic is mapped on the GPU):
+ * persistent (one cooperative launch per SOC iteration) or one launch per
+ * phase; team = workgroups that deal an XCD band's row chunks out cyclically
+ * (1: contiguous row ranges); row_cache = slot data of the workgroups' rows
+ * held in LDS.  The results are identical up to the summation order of the
+ * FP64 reductions. */
+typedef struct {
+    int32_t persistent;
+    int32_t team;
+    int32_t row_cache;
+    int32_t workgroups;      /* persistent launch: its workgroups */
+    double ms;               /* measured milliseconds per SOC iteration */
+    int32_t chosen;          /* 1 for the shape kept */
+    int32_t reserved;
+} pfe_tune_result;
+
+/* Autotune the launch shape on this context's graph: from the current state
+ * (between SOC iterations) run one untimed and `trials` timed SOC iterations
+ * per candidate shape, restore the state after each, and keep the fastest for
+ * later pfe_step / pfe_solve calls.  Candidates: persistent with teams of 64
+ * or 1, each with and without the LDS row cache (when the rows fit), and one
+ * launch per phase.  results (host, may be null when max_results is 0)
+ * receives up to max_results measured shapes, *n_results their number.
+ * Allocates a temporary copy of Y, P, B.  PFE_E_STATE inside a SOC iteration. */
+pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int max_results, int* n_results);
 
 /* Statistics accumulated since the last reset (pfe_step / pfe_solve with a
  * non-null info reset them first).  reset != 0 clears them after reading.

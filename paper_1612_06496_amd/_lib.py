@@ -48,6 +48,7 @@ class pfe_params(C.Structure):
         ("n_inner", C.c_int), ("tol", C.c_double), ("maxit", C.c_int),
         ("precond", C.c_int), ("ortho", C.c_int), ("dtype", C.c_int),
         ("init_ortho", C.c_int), ("keep_split", C.c_int), ("persistent", C.c_int),
+        ("graphs", C.c_int),
     ]
 
 
@@ -65,6 +66,12 @@ class pfe_monitors(C.Structure):
                 ("split", C.c_double), ("orthogonality", C.c_double)]
 
 
+class pfe_tune_result(C.Structure):
+    _fields_ = [("persistent", C.c_int32), ("team", C.c_int32), ("row_cache", C.c_int32),
+                ("workgroups", C.c_int32), ("ms", C.c_double), ("chosen", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 _P = C.c_void_p
 _S = C.c_int  # pfe_status
 
@@ -80,6 +87,7 @@ SIGNATURES = {
     "pfe_step": (_S, [_P, C.c_int, C.POINTER(pfe_step_info)]),
     "pfe_solve": (_S, [_P, C.c_int, C.POINTER(pfe_step_info)]),
     "pfe_stats": (_S, [_P, C.POINTER(pfe_step_info), C.c_int]),
+    "pfe_autotune": (_S, [_P, C.c_int, C.POINTER(pfe_tune_result), C.c_int, C.POINTER(C.c_int)]),
     "pfe_get": (_S, [_P, C.c_int, _P]),
     "pfe_set": (_S, [_P, C.c_int, _P]),
     "pfe_get_inner_index": (_S, [_P, C.POINTER(C.c_int)]),

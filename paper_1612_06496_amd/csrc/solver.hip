@@ -1932,6 +1932,15 @@ struct pfe_ctx {
     int* colint = nullptr;
     int cache_np = 0;        // persistent kernel: LDS row cache chunks (0: no cache)
     int launched_coop = 0;   // the last advance ran the persistent kernel
+    // persistent launch shape
+    std::vector<int64_t> seg_rows;
+    int per_cu = 0;          // co-resident workgroups per CU
+    int64_t coop = 0;        // persistent grid size (0: none)
+    int team = 64;           // workgroups per team (cyclic chunk ownership)
+    int want_cache = 1;      // use the LDS row cache when the rows fit
+    // one-launch-per-phase PCG replayed from a HIP graph of kCgChunk iterations
+    hipGraphExec_t cg_exec = nullptr;
+    std::vector<unsigned char> cg_key;   // kernel arguments the graph was built with
     ColState cs{};
     Scal* S = nullptr;
     unsigned* bar = nullptr;
@@ -2125,12 +2134,107 @@ pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0)
     return PFE_OK;
 }
 
+// One-launch-per-phase PCG from a HIP graph: kCgChunk iterations (Jacobi: one
+// kernel each; learned: the four phases each) as kernel nodes in sequence,
+// replayed until the done flag is set (later nodes of a finished solve return
+// at once).  Built with the graph API (no stream capture, so any stream works),
+// cached per context and rebuilt when the kernel arguments change.
+constexpr int kCgChunk = 8;
+
+template <typename T>
+const void* kernel_for(int which, int ellK) {
+#define PFE_KSEL(K) switch (ellK) { \
+        case 4: return reinterpret_cast<const void*>(&K<T, 4>); \
+        case 8: return reinterpret_cast<const void*>(&K<T, 8>); \
+        case 24: return reinterpret_cast<const void*>(&K<T, 24>); \
+        default: return reinterpret_cast<const void*>(&K<T, 0>); }
+    switch (which) {
+        case PH_IT: PFE_KSEL(k_cg_it)
+        case PH_LA: PFE_KSEL(k_lpcg_aq)
+        case PH_LC: PFE_KSEL(k_lpcg_g)
+        case PH_LD: PFE_KSEL(k_lpcg_gt)
+        case PH_LB: return reinterpret_cast<const void*>(&k_lpcg_xr<T>);
+    }
+#undef PFE_KSEL
+    return nullptr;
+}
+
+template <typename T>
+pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, hipGraphExec_t* out) {
+    std::vector<unsigned char> key(sizeof(KA<T>) + 2);
+    std::memcpy(key.data(), &a, sizeof(KA<T>));
+    key[sizeof(KA<T>)] = learned ? 1 : 0;
+    key[sizeof(KA<T>) + 1] = (unsigned char)sizeof(T);
+    if (c->cg_exec && key == c->cg_key) { *out = c->cg_exec; return PFE_OK; }
+    if (c->cg_exec) { (void)hipGraphExecDestroy(c->cg_exec); c->cg_exec = nullptr; }
+    hipGraph_t g = nullptr;
+    PFE_CHECK_HIP(hipGraphCreate(&g, 0));
+    KA<T> args = a;
+    int initial = 0;
+    void* p1[] = {(void*)&args};
+    void* p2[] = {(void*)&args, (void*)&initial};
+    hipGraphNode_t prev = nullptr;
+    hipError_t e = hipSuccess;
+    auto add = [&](const void* fn, void** kp) {
+        if (e != hipSuccess) return;
+        hipKernelNodeParams np{};
+        np.func = const_cast<void*>(fn);
+        np.gridDim = dim3(a.nblk);
+        np.blockDim = dim3(kBlock);
+        np.sharedMemBytes = 0;
+        np.kernelParams = kp;
+        np.extra = nullptr;
+        hipGraphNode_t node = nullptr;
+        e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &np);
+        prev = node;
+    };
+    const int K = a.ell_K;
+    for (int k = 0; k < kCgChunk; ++k) {
+        if (learned) {
+            add(kernel_for<T>(PH_LA, K), p1);
+            add(kernel_for<T>(PH_LB, K), p1);
+            add(kernel_for<T>(PH_LC, K), p1);
+            add(kernel_for<T>(PH_LD, K), p2);
+        } else {
+            add(kernel_for<T>(PH_IT, K), p1);
+        }
+    }
+    hipGraphExec_t ex = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "PCG chunk graph", __FILE__, __LINE__);
+    c->cg_exec = ex;
+    c->cg_key = key;
+    *out = ex;
+    return PFE_OK;
+}
+
+// replay the chunk graph until the solve is done
+template <typename T>
+pfe_status pcg_replay(pfe_ctx* c, const KA<T>& a, bool learned) {
+    hipGraphExec_t ex = nullptr;
+    PFE_TRY(cg_chunk_graph(c, a, learned, &ex));
+    int it = 0, done = 0;
+    while (true) {
+        PFE_CHECK_HIP(hipGraphLaunch(ex, c->stream));
+        it += kCgChunk;
+        PFE_CHECK_HIP(hipMemcpyAsync(&done, &c->S->done, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        PFE_CHECK_HIP(hipStreamSynchronize(c->stream));
+        if (done || it > c->prm.maxit + kCgChunk) break;
+    }
+    return PFE_OK;
+}
+
 // Multi-launch PCG after a residual phase (r0 in rb[0]); the host polls the
 // done flag every few iterations; the iterate ends in a.x.
 template <typename T>
 pfe_status pcg_loop_mk(pfe_ctx* c, const KA<T>& a) {
     hipLaunchKernelGGL(k_stats_if_done<T>, dim3(1), dim3(64), 0, c->stream, a);
     PFE_TRY(launch_phase(c, a, PH_W0, 0, 0));
+    if (c->prm.graphs) {
+        PFE_TRY(pcg_replay(c, a, false));
+        return launch_phase(c, a, PH_ZERO, 0, 0);
+    }
     int it = 0;
     const int chunk = 4;
     int done = 0;
@@ -2151,6 +2255,10 @@ pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a) {
     hipLaunchKernelGGL(k_stats_if_done<T>, dim3(1), dim3(64), 0, c->stream, a);
     PFE_TRY(launch_phase(c, a, PH_LC, 0, 0));
     PFE_TRY(launch_phase(c, a, PH_LD, 1, 0));     // initial r.z
+    if (c->prm.graphs) {
+        PFE_TRY(pcg_replay(c, a, true));
+        return launch_phase(c, a, PH_ZERO, 0, 0);
+    }
     int it = 0;
     const int chunk = 4;
     int done = 0;
@@ -2291,6 +2399,8 @@ void free_ctx(pfe_ctx* c) {
         if (p) (void)hipFree(p);
     free_partition(c->pm);
     free_partition(c->pc);
+    if (c->cg_exec) (void)hipGraphExecDestroy(c->cg_exec);
+    c->cg_exec = nullptr;
 }
 
 bool params_ok(const pfe_params* p, int64_t n) {
@@ -2450,6 +2560,44 @@ pfe_status rebuild_rhs(pfe_ctx* c) {
     return launch_phase(c, a, PH_RHS, 0, 0);
 }
 
+// n_outer SOC iterations in the context's current launch shape
+template <typename T>
+pfe_status run_outer(pfe_ctx* c, int n_outer) {
+    if (c->prm.persistent && c->pc.nblk > 0 && c->prm.precond == PFE_JACOBI) return outer_coop<T>(c, n_outer);
+    for (int k = 0; k < n_outer; ++k) PFE_TRY(outer_mk<T>(c));
+    return PFE_OK;
+}
+
+// (Re)build the persistent partition for the context's launch shape (team
+// size, row cache) and decide whether the LDS row cache fits.
+pfe_status setup_persistent(pfe_ctx* c) {
+    free_partition(c->pc);
+    c->cache_np = 0;
+    if (c->coop < kNumXcd) return PFE_OK;
+    const int R = kBlock / (int)c->d;
+    const int K = c->g->ell_K;
+    PFE_TRY(make_partition(c->seg_rows, (int)c->coop, R, c->team, c->pc));
+    hipDeviceProp_t prop;
+    PFE_CHECK_HIP(hipGetDeviceProperties(&prop, c->device));
+    if (c->pc.nblk % kNumXcd != 0 || c->pc.nblk > c->per_cu * prop.multiProcessorCount) {
+        free_partition(c->pc);
+        return PFE_OK;
+    }
+    if (c->want_cache && (K == 4 || K == 8 || K == 24)) {
+        // LDS row cache when the persistent workgroups' rows fit without
+        // lowering their co-residency
+        const bool f64 = c->prm.dtype == PFE_FP64;
+        const size_t bytes = f64 ? row_cache_bytes<double>(c->pc.max_np, R, K) : row_cache_bytes<float>(c->pc.max_np, R, K);
+        int occ_lc = 0;
+        if (bytes <= 48 * 1024 &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_lc, f64 ? soc_kernel<double>(K, true) : soc_kernel<float>(K, true),
+                                                         kBlock, bytes) == hipSuccess &&
+            occ_lc >= c->per_cu)
+            c->cache_np = c->pc.max_np;
+    }
+    return PFE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2489,36 +2637,23 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
     hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &occ, (p->dtype == PFE_FP64) ? soc_kernel<double>(g->ell_K, false) : soc_kernel<float>(g->ell_K, false), kBlock, 0);
     if (oe != hipSuccess) occ = 0;
-    const int per_cu = std::max(0, std::min(occ, 2));
-    int team = 64;
-    if (const char* ev = getenv("PFE_TEAM")) team = std::max(1, atoi(ev));   // launch-shape experiments
-    pfe_status s = make_partition(seg_rows, (int)std::min<int64_t>(want, 2048), R, team, c->pm);
-    if (s == PFE_OK && p->persistent) {
-        int64_t coop = (int64_t)per_cu * ncu;
-        if (const char* ev = getenv("PFE_PERSISTENT_WG")) {
-            // launch-shape experiments: cap the persistent grid (never above co-residency)
-            int64_t cap = atoll(ev);
-            if (cap > 0 && cap < coop) coop = cap;
-        }
-        if (coop > want) coop = want;
-        coop -= coop % kNumXcd;
-        if (coop >= kNumXcd) s = make_partition(seg_rows, (int)coop, R, team, c->pc);
-        if (c->pc.nblk % kNumXcd != 0 || c->pc.nblk > per_cu * ncu) free_partition(c->pc);
+    c->per_cu = std::max(0, std::min(occ, 2));
+    c->seg_rows = seg_rows;
+    if (const char* ev = getenv("PFE_TEAM")) c->team = std::max(1, atoi(ev));   // launch-shape experiments
+    if (const char* ev = getenv("PFE_ROWCACHE")) c->want_cache = atoi(ev) != 0;
+    pfe_status s = make_partition(seg_rows, (int)std::min<int64_t>(want, 2048), R, c->team, c->pm);
+    // persistent grid: every co-resident workgroup (at most one per R rows), a
+    // multiple of the XCD count; built even when the context starts in the
+    // one-launch-per-phase mode, so that the autotuner can try it
+    c->coop = (int64_t)c->per_cu * ncu;
+    if (const char* ev = getenv("PFE_PERSISTENT_WG")) {
+        // launch-shape experiments: cap the persistent grid (never above co-residency)
+        int64_t cap = atoll(ev);
+        if (cap > 0 && cap < c->coop) c->coop = cap;
     }
-    if (s == PFE_OK && c->pc.nblk > 0 && g->ell_K > 0 && (g->ell_K == 4 || g->ell_K == 8 || g->ell_K == 24)) {
-        // LDS row cache when the persistent workgroups' rows fit without
-        // lowering their co-residency
-        const size_t bytes = (p->dtype == PFE_FP64) ? row_cache_bytes<double>(c->pc.max_np, R, g->ell_K)
-                                                    : row_cache_bytes<float>(c->pc.max_np, R, g->ell_K);
-        int occ_lc = 0;
-        bool want_lc = bytes <= 48 * 1024;
-        if (const char* ev = getenv("PFE_ROWCACHE")) want_lc = want_lc && atoi(ev) != 0;   // experiments
-        if (want_lc && hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                           &occ_lc, (p->dtype == PFE_FP64) ? soc_kernel<double>(g->ell_K, true) : soc_kernel<float>(g->ell_K, true),
-                           kBlock, bytes) == hipSuccess &&
-            occ_lc >= per_cu)
-            c->cache_np = c->pc.max_np;
-    }
+    if (c->coop > want) c->coop = want;
+    c->coop -= c->coop % kNumXcd;
+    if (s == PFE_OK) s = setup_persistent(c);
     if (s != PFE_OK) { free_ctx(c); delete c; return s; }
     const int nblk_max = std::max(c->pm.nblk, c->pc.nblk);
     const int npair = (int)(c->d * (c->d + 1) / 2);
@@ -2653,6 +2788,101 @@ pfe_status pfe_solve(pfe_ctx* c, int n_outer, pfe_step_info* info) {
     }
     if (info) return read_info(c, info);
     return PFE_OK;
+}
+
+pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int max_results, int* n_results) {
+    if (!c || trials < 1 || max_results < 0 || (max_results > 0 && !results)) {
+        set_error("pfe_autotune: bad argument");
+        return PFE_E_ARG;
+    }
+    if (c->inner != 0) { set_error("pfe_autotune: call between SOC iterations (inner index 0)"); return PFE_E_STATE; }
+    if (n_results) *n_results = 0;
+    const bool f64 = c->prm.dtype == PFE_FP64;
+    const size_t nd = (size_t)c->n * c->d * c->esz;
+    struct Shape { int persistent, team, cache; };
+    const Shape shapes[] = {{1, 64, 1}, {1, 64, 0}, {1, 1, 1}, {1, 1, 0}, {0, c->team, 0}};
+    const Shape orig{c->prm.persistent, c->team, c->want_cache};
+    char* save = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    pfe_status st = PFE_OK;
+    auto restore = [&]() -> pfe_status {
+        PFE_CHECK_HIP(hipMemcpyAsync(c->Y, save, nd, hipMemcpyDeviceToDevice, c->stream));
+        PFE_CHECK_HIP(hipMemcpyAsync(c->P, save + nd, nd, hipMemcpyDeviceToDevice, c->stream));
+        PFE_CHECK_HIP(hipMemcpyAsync(c->B, save + 2 * nd, nd, hipMemcpyDeviceToDevice, c->stream));
+        c->inner = 0;
+        return PFE_OK;
+    };
+    int best = -1, count = 0;
+    double best_ms = 0.0;
+    std::vector<pfe_tune_result> found;
+    do {
+        if (hipMalloc((void**)&save, 3 * nd) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+            hipEventCreate(&e1) != hipSuccess) {
+            st = hip_fail(hipGetLastError(), "pfe_autotune set-up", __FILE__, __LINE__);
+            break;
+        }
+        if (hipMemcpyAsync(save, c->Y, nd, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(save + nd, c->P, nd, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(save + 2 * nd, c->B, nd, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+            st = hip_fail(hipGetLastError(), "pfe_autotune save", __FILE__, __LINE__);
+            break;
+        }
+        for (int k = 0; k < (int)(sizeof(shapes) / sizeof(shapes[0])) && st == PFE_OK; ++k) {
+            const Shape& sh = shapes[k];
+            if (sh.persistent && (c->coop < kNumXcd || c->prm.precond != PFE_JACOBI)) continue;
+            c->prm.persistent = sh.persistent;
+            c->team = sh.team;
+            c->want_cache = sh.cache;
+            if (sh.persistent) {
+                if ((st = setup_persistent(c)) != PFE_OK) break;
+                if (c->pc.nblk == 0 || (sh.cache && c->cache_np == 0)) continue;
+            }
+            // one untimed SOC iteration (code loading, caches), then the timed ones
+            st = f64 ? run_outer<double>(c, 1) : run_outer<float>(c, 1);
+            if (st == PFE_OK) st = restore();
+            if (st == PFE_OK && hipEventRecord(e0, c->stream) != hipSuccess) st = PFE_E_HIP;
+            if (st == PFE_OK) st = f64 ? run_outer<double>(c, trials) : run_outer<float>(c, trials);
+            if (st == PFE_OK && hipEventRecord(e1, c->stream) != hipSuccess) st = PFE_E_HIP;
+            if (st == PFE_OK && hipEventSynchronize(e1) != hipSuccess) st = PFE_E_HIP;
+            float ms = 0.f;
+            if (st == PFE_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = PFE_E_HIP;
+            if (st == PFE_OK) st = restore();
+            if (st != PFE_OK) break;
+            Scal h;
+            if (hipMemcpy(&h, c->S, sizeof(Scal), hipMemcpyDeviceToHost) != hipSuccess) { st = PFE_E_HIP; break; }
+            if (h.abort_flag || (h.status != 0 && h.status != PFE_E_NOCONV)) continue;
+            pfe_tune_result r{};
+            r.persistent = sh.persistent;
+            r.team = sh.team;
+            r.row_cache = sh.persistent ? (c->cache_np > 0) : 0;
+            r.workgroups = sh.persistent ? c->pc.nblk : 0;
+            r.ms = ms / trials;
+            found.push_back(r);
+            if (best < 0 || r.ms < best_ms) { best = (int)found.size() - 1; best_ms = r.ms; }
+        }
+    } while (0);
+    // keep the fastest shape (the original one if nothing was measured)
+    if (best >= 0) {
+        c->prm.persistent = found[best].persistent;
+        c->team = found[best].persistent ? found[best].team : orig.team;
+        c->want_cache = found[best].persistent ? found[best].row_cache : orig.cache;
+        found[best].chosen = 1;
+    } else {
+        c->prm.persistent = orig.persistent;
+        c->team = orig.team;
+        c->want_cache = orig.cache;
+    }
+    pfe_status s2 = setup_persistent(c);
+    if (st == PFE_OK) st = s2;
+    if (save && st == PFE_OK) st = restore();
+    (void)hipStreamSynchronize(c->stream);
+    if (save) (void)hipFree(save);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st == PFE_OK) st = reset_stats(c);
+    for (size_t k = 0; k < found.size() && (int)k < max_results; ++k) results[k] = found[k];
+    if (n_results) *n_results = (int)std::min<size_t>(found.size(), (size_t)max_results);
+    return st;
 }
 
 pfe_status pfe_stats(pfe_ctx* c, pfe_step_info* out, int reset) {

@@ -104,7 +104,7 @@ class Solver:
 
     def __init__(self, graph: Graph, Y0, *, lam: float, r: float, n_inner: int, tol: float = 1e-6,
                  maxit: int = 1000, ortho: str = "polar", fp64: bool = False, init_ortho: bool = True,
-                 keep_split: bool = False, persistent: bool = True, stream=None):
+                 keep_split: bool = False, persistent: bool = True, graphs: bool = False, stream=None):
         self.graph = graph
         self.dtype = torch.float64 if fp64 else torch.float32
         y0 = _dev(Y0, self.dtype)
@@ -113,7 +113,7 @@ class Solver:
             d=self.d, lambda_=lam, r=r, n_inner=n_inner, tol=tol, maxit=maxit,
             precond=L.PFE_JACOBI, ortho=L.PFE_POLAR if ortho == "polar" else L.PFE_CHOL,
             dtype=L.PFE_FP64 if fp64 else L.PFE_FP32, init_ortho=int(init_ortho),
-            keep_split=int(keep_split), persistent=int(persistent))
+            keep_split=int(keep_split), persistent=int(persistent), graphs=int(graphs))
         self._stream = stream
         h = C.c_void_p()
         L.check(L.lib.pfe_init(graph._h, C.byref(self.params), y0.data_ptr(), _stream_handle(stream),
@@ -147,6 +147,15 @@ class Solver:
         st = L.lib.pfe_stats(self._h, C.byref(inf), int(reset))
         L.check(st, "pfe_stats", allow=(L.PFE_E_NOCONV,) if allow_noconv else ())
         return self._info_dict(inf)
+
+    def autotune(self, trials: int = 2) -> list:
+        """Time the candidate launch shapes on this graph and keep the fastest."""
+        res = (L.pfe_tune_result * 8)()
+        n = C.c_int()
+        L.check(L.lib.pfe_autotune(self._h, int(trials), res, 8, C.byref(n)), "pfe_autotune",
+                allow=(L.PFE_E_NOCONV,))
+        return [dict(persistent=r.persistent, team=r.team, row_cache=r.row_cache, workgroups=r.workgroups,
+                     ms=r.ms, chosen=r.chosen) for r in res[:n.value]]
 
     # -- state ---------------------------------------------------------------
     def get(self, which: str) -> torch.Tensor:

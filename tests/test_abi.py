@@ -49,7 +49,7 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_1612_06496_amd import _lib as L
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
-    structs = [L.pfe_graph_desc, L.pfe_params, L.pfe_step_info, L.pfe_monitors]
+    structs = [L.pfe_graph_desc, L.pfe_params, L.pfe_step_info, L.pfe_monitors, L.pfe_tune_result]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pfe.h"', "int main(void){"]
     for st in structs:
         cname = st.__name__

@@ -248,3 +248,31 @@ def test_batch64_full_size_sampled():
     eY, eP = rel(Yg[sl], Y1), rel(Pg[sl], P1)
     print(f"smallest image vs oracle: Y {eY:.2e} P {eP:.2e}; info {info}")
     assert eY <= 1e-5 and eP <= 1e-5
+
+
+def test_autotune_restores_state_and_keeps_results():
+    """The launch-shape autotuner restores the state it measured from, keeps
+    one shape, and the tuned solver follows the default one (only the FP64
+    summation order differs between shapes)."""
+    from paper_1612_06496_amd import Solver
+    banner("autotune")
+    wls = synth.make_batch(BATCH)
+    parts, U = build(wls)
+    lam, r = fixed_penalties(wls)
+    kw = dict(lam=lam, r=r, n_inner=wls[0].n_inner, tol=1e-6, maxit=3000)
+    Y0 = np.concatenate([w.y0 for w in wls])
+    S = Solver(U, Y0, **kw)
+    before = [to_np(S.get(k)) for k in ("Y", "P", "B")]
+    res = S.autotune(trials=1)
+    print("autotune:", res)
+    assert len(res) >= 2 and sum(x["chosen"] for x in res) == 1
+    assert all(x["ms"] > 0 for x in res)
+    after = [to_np(S.get(k)) for k in ("Y", "P", "B")]
+    for b0, a0 in zip(before, after):
+        assert np.array_equal(b0, a0)
+    S.solve(2)
+    R = Solver(U, Y0, **kw)
+    R.solve(2)
+    e = max(rel(to_np(S.get(k)), to_np(R.get(k))) for k in ("Y", "P"))
+    print(f"tuned vs default rel err {e:.2e}")
+    assert e <= 1e-5

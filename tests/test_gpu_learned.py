@@ -153,3 +153,21 @@ def test_training_on_gpu_gains_on_held_out_image(ratio):
     assert np.mean(losses[-10:]) < 0.8 * losses[0]
     assert it_l.max() < it_j.max()
     assert info["rel_res_max"] <= 1e-6
+
+
+def test_learned_pcg_graph_replay_is_bitwise_neutral():
+    from paper_1612_06496_amd import Mpnn, Solver
+    banner("graph replay (learned PCG)")
+    wl = synth.grid_workload("t", 40, 48, 6, 0.05, 3, stencil=8, d=4)
+    G = __import__("gpu_helpers").gpu_graph(wl)
+    net = Mpnn(random_params(4, scale=0.2))
+    rhs = np.random.default_rng(5).normal(size=(wl.n, 4))
+    out = []
+    for graphs in (True, False):
+        S = Solver(G, wl.y0, lam=20.0, r=1.0, n_inner=2, tol=1e-6, maxit=5000, persistent=False, graphs=graphs)
+        S.set_learned(net)
+        res = [S.pcg(rhs, np.zeros_like(rhs)) for _ in range(3)]     # three solves, the graph reused
+        out.append(res)
+    for (xa, ia, _), (xb, ib, _) in zip(out[0], out[1]):
+        assert np.array_equal(ia, ib)
+        assert np.array_equal(xa.cpu().numpy(), xb.cpu().numpy())

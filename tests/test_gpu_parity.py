@@ -381,3 +381,20 @@ def test_lds_row_cache_is_bitwise_neutral(name, monkeypatch):
         out.append((to_np(S.get("Y")), to_np(S.get("P")), to_np(S.get("B"))))
     for k in range(3):
         assert np.array_equal(out[0][k], out[1][k])
+
+
+def test_graph_replay_is_bitwise_neutral():
+    """One-launch-per-phase PCG replayed from HIP graphs (many replays across
+    inner solves, with host synchronisation between them) gives bitwise the
+    iteration of host-launched kernels."""
+    from paper_1612_06496_amd import Solver
+    banner("graph replay (Jacobi)")
+    wl = load("voronoi96x80_8nbr")
+    G = gpu_graph(wl)
+    out = []
+    for graphs in (True, False):
+        S = Solver(G, wl.y0, lam=30.0, r=30.0, n_inner=3, tol=1e-6, maxit=1000, persistent=False, graphs=graphs)
+        info = S.solve(2, info=True)
+        out.append((to_np(S.get("Y")), to_np(S.get("P")), info["cg_iters_total"]))
+    assert out[0][2] == out[1][2]
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
