@@ -107,7 +107,8 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0), captu
     for seed in train_seeds:
         wl = synth.make_workload(workload, seed)
         G = Graph.grid(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
-        S = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=2000, persistent=False)
+        S = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=2000, persistent=False,
+                   graphs=True)
         c = 1.0 / S.edge_quantile(0.99)
         for ratio in ratios:
             S.set_penalties(ratio * c, c)
@@ -130,7 +131,7 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0), captu
 
     wl = synth.make_workload(workload, 0)
     G = Graph.grid(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
-    S = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=5000, persistent=False)
+    S = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=5000, persistent=False, graphs=True)
     c = 1.0 / S.edge_quantile(0.99)
     rows = []
     for ratio in ratios:
@@ -156,7 +157,7 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0), captu
     return {"workload": workload, "d": wl.d, "train_images": list(train_seeds), "train_steps": steps,
             "train_samples": len(samples), "loss_first": round(losses[0], 4),
             "loss_last10": round(float(np.mean(losses[-10:])), 4), "train_s": round(t_train, 1),
-            "launch": "one launch per phase (both preconditioners)", "sweep": rows}
+            "launch": "one launch per phase, PCG replayed from HIP graphs (both preconditioners)", "sweep": rows}
 
 
 def cpu_baseline(wls, lam, r, n_steps=2, max_images=2):
@@ -202,6 +203,8 @@ def main():
     ap.add_argument("--copy-gib", type=float, default=2.0, help="size of the copy-bandwidth probe")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-Jacobi PCG comparison")
     ap.add_argument("--multi-launch", action="store_true", help="one launch per phase instead of one per SOC iteration")
+    ap.add_argument("--graphs", action="store_true", help="replay one-launch-per-phase PCG from HIP graphs")
+    ap.add_argument("--autotune", action="store_true", help="autotune the launch shape before timing")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="a single-image workload or an image batch (block-diagonal union) from synth")
     args = ap.parse_args()
@@ -229,10 +232,11 @@ def main():
         Y0 = wls[0].y0
     wl = wls[0]
     S = Solver(G, Y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=1000,
-               persistent=not args.multi_launch)
+               persistent=not args.multi_launch, graphs=args.graphs)
     # shrink-active penalties: threshold 1/c at the 0.99-quantile of |M Y0|
     c = 1.0 / S.edge_quantile(0.99)
     S.set_penalties(c, c)
+    tuned = S.autotune(trials=2) if args.autotune else None
 
     for _ in range(args.warmup):
         S.solve(1)
@@ -242,7 +246,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record()
-    for _ in range(args.steps):      # one persistent launch per SOC iteration
+    for _ in range(args.steps):      # one SOC iteration per step
         S.solve(1)
     stop.record()
     torch.cuda.synchronize()
@@ -257,8 +261,8 @@ def main():
     byt = algorithmic_bytes(n, E, d, 4, info["cg_iters_total"], info["solves"], wl.n_inner, args.steps)
     achieved = byt / (ms / 1e3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None if args.multi_launch else measured_traffic(args.workload),
-            "kernel": "one kernel per phase" if args.multi_launch else "k_soc (one SOC iteration per launch)",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.workload) if info["workgroups"] else None,
+            "kernel": "k_soc (one SOC iteration per launch)" if info["workgroups"] else "one kernel per phase",
             "bytes_per_launch": int(byt / args.steps), "workgroups": info["workgroups"],
             "launch_flags": info["flags"]}
     default = args.workload == WORKLOAD
@@ -274,7 +278,9 @@ def main():
         "config": {"workload": args.workload, "graphs": len(wls), "n": n, "edges": E, "d": d,
                    "n_inner": wl.n_inner,
                    "tol": wl.tol, "lambda": c, "r": c, "precond": "jacobi",
-                   "launch": "multi" if args.multi_launch else "persistent"},
+                   "launch": "persistent" if info["workgroups"] else "multi",
+                   "graphs": bool(args.graphs),
+                   "autotuned": ([t for t in tuned if t["chosen"]] or [None])[0] if tuned else None},
         "pcg_iters_per_solve": round(info["cg_iters_total"] / max(1, info["solves"]), 2),
         "pcg_iters_learned": None,     # filled by the learned-vs-Jacobi leg below
         "monitor": {k: float(f"{v:.6g}") for k, v in mon.items()},

@@ -51,8 +51,7 @@ enum Phase : int {
     PH_ZERO = 8,    // zero the solution columns whose rhs is zero
     // PCG with the learned factor M^{-1} = D_A^{-1/2} Gt^T Gt D_A^{-1/2}
     PH_LA = 9,      // p = z + beta p, q = A p, p.q
-    PH_LB = 10,     // x += alpha p, r -= alpha q
-    PH_LC = 11,     // y1 = Gt D_A^{-1/2} r
+    PH_LC = 11,     // x += alpha p, r -= alpha q, y1 = Gt D_A^{-1/2} r
     PH_LD = 12      // z = D_A^{-1/2} Gt^T y1, r.z, r.r
 };
 
@@ -115,6 +114,7 @@ struct KA {
     int store_rhs;
     int b_zero;        // first edge update of a SOC iteration: b starts from 0
     int ortho;         // PFE_POLAR / PFE_CHOL
+    int sten;          // ELL slots in pixel-stencil order (lower neighbours first)
 };
 
 // ---------------------------------------------------------------------------
@@ -596,35 +596,91 @@ __device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh, int it
     block_partials<3>(acc, sh, d, R, a.part, a.nblk, lb);
 }
 
-// Learned-preconditioner PCG phases.  Buffers: r = rb[0], q = wb[0], p double
-// buffered in sb[it & 1] (new) / sb[(it & 1) ^ 1] (previous).
+// Learned-preconditioner PCG phases (standard PCG with M^{-1} = G^T G, one
+// kernel per phase, three per iteration).  Buffers: q = wb[0]; p double
+// buffered in sb[it & 1] (new) / sb[(it & 1) ^ 1] (previous); r double
+// buffered in rb[it & 1] (before the update of iteration it) / rb[(it & 1) ^ 1]
+// (after it), the initial residual in rb[0].
+//   LA : p = z + beta p, q = A p, partials of p.q
+//   LC : x += alpha p, r' = r - alpha q (own rows), y1 = Gt D_A^{-1/2} r' with
+//        the neighbours' r' recomputed from their r and q (upd = 0: y1 from
+//        the initial residual, no update)
+//   LD : z = D_A^{-1/2} Gt^T y1, partials of r'.z and r'.r'
+// On pixel-grid stencils the ELL slots [0, K/2) of a row are exactly its
+// lower neighbours (raster order), [K/2, K) the upper ones; otherwise the
+// column decides.
+template <int H>
+constexpr int half_group() { return H <= 0 ? 1 : (H % 8 == 0 ? 8 : (H % 6 == 0 ? 6 : (H % 4 == 0 ? 4 : H))); }
+
 template <int KC = 0, typename T>
-__device__ __forceinline__ void ph_lc(const KA<T>& a, int lb) {
+__device__ __forceinline__ void ph_lc(const KA<T>& a, int lb, int upd) {
     const int d = a.d, R = a.R, t = threadIdx.x;
     const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
-    const T* r = a.rb[0];
+    const int it = upd ? ld_flag(&a.S->it) : 0;
+    const T* r = a.rb[it & 1];
+    T* rn = a.rb[(it & 1) ^ 1];
+    const T* p = a.sb[it & 1];
+    const T* q = a.wb[0];
     if (t >= R * d) return;
     const int rl = t / d, c = t - rl * d;
+    const T alpha = upd ? (T)a.cs.alpha[a.blk_seg[lb] * d + c] : T(0);
     for (int i = rb + rl; i < re; i += rs) {
         const size_t e = (size_t)i * d + c;
         int s0, cnt, st;
         row_slots<KC>(a, i, s0, cnt, st);
-        T acc = mul_t(a.gdiag[i], mul_t(a.isq[i], r[e]));
-#pragma unroll(KC > 0 ? 4 : 2)
-        for (int k = 0; k < cnt; ++k) {
-            const int s = s0 + k * st;
-            const int j = a.scol[s];
-            if (j < i) acc = fma_t(a.gval[s], mul_t(a.isq[j], r[(size_t)j * d + c]), acc);
+        T ri = r[e];
+        if (upd) {
+            a.x[e] = fma_t(alpha, p[e], a.x[e]);
+            ri = fma_t(-alpha, q[e], ri);
+            rn[e] = ri;
+        }
+        T acc = mul_t(a.gdiag[i], mul_t(a.isq[i], ri));
+        if (KC > 0 && a.sten) {
+            constexpr int H = KC / 2, G = half_group<H>();
+#pragma unroll
+            for (int k0 = 0; k0 < H; k0 += G) {
+                int jj[G];
+                T gv[G], rj[G], qj[G], ij[G];
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const int sl = s0 + (k0 + k) * st;
+                    jj[k] = a.scol[sl];
+                    gv[k] = a.gval[sl];
+                }
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const size_t ej = (size_t)jj[k] * d + c;
+                    rj[k] = r[ej];
+                    qj[k] = upd ? q[ej] : T(0);
+                    ij[k] = a.isq[jj[k]];
+                }
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const T rv = upd ? fma_t(-alpha, qj[k], rj[k]) : rj[k];
+                    acc = fma_t(gv[k], mul_t(ij[k], rv), acc);
+                }
+            }
+        } else {
+#pragma unroll 2
+            for (int k = 0; k < cnt; ++k) {
+                const int s = s0 + k * st;
+                const int j = a.scol[s];
+                if (j < i) {
+                    const size_t ej = (size_t)j * d + c;
+                    const T rv = upd ? fma_t(-alpha, q[ej], r[ej]) : r[ej];
+                    acc = fma_t(a.gval[s], mul_t(a.isq[j], rv), acc);
+                }
+            }
         }
         a.y1[e] = acc;
     }
 }
 
 template <int KC = 0, typename T>
-__device__ __forceinline__ void ph_ld(const KA<T>& a, int lb, double* sh) {
+__device__ __forceinline__ void ph_ld(const KA<T>& a, int lb, double* sh, int initial) {
     const int d = a.d, R = a.R, t = threadIdx.x;
     const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
-    const T* r = a.rb[0];
+    const T* r = initial ? a.rb[0] : a.rb[(ld_flag(&a.S->it) & 1) ^ 1];
     double acc2[2] = {0.0, 0.0};
     if (t < R * d) {
         const int rl = t / d, c = t - rl * d;
@@ -633,11 +689,30 @@ __device__ __forceinline__ void ph_ld(const KA<T>& a, int lb, double* sh) {
             int s0, cnt, st;
             row_slots<KC>(a, i, s0, cnt, st);
             T acc = mul_t(a.gdiag[i], a.y1[e]);
-#pragma unroll(KC > 0 ? 4 : 2)
-            for (int k = 0; k < cnt; ++k) {
-                const int s = s0 + k * st;
-                const int j = a.scol[s];
-                if (j > i) acc = fma_t(a.gval[s], a.y1[(size_t)j * d + c], acc);
+            if (KC > 0 && a.sten) {
+                constexpr int H = KC / 2, G = half_group<H>();
+#pragma unroll
+                for (int k0 = H; k0 < KC; k0 += G) {
+                    int jj[G];
+                    T gv[G], yj[G];
+#pragma unroll
+                    for (int k = 0; k < G; ++k) {
+                        const int sl = s0 + (k0 + k) * st;
+                        jj[k] = a.scol[sl];
+                        gv[k] = a.gval[sl];
+                    }
+#pragma unroll
+                    for (int k = 0; k < G; ++k) yj[k] = a.y1[(size_t)jj[k] * d + c];
+#pragma unroll
+                    for (int k = 0; k < G; ++k) acc = fma_t(gv[k], yj[k], acc);
+                }
+            } else {
+#pragma unroll 2
+                for (int k = 0; k < cnt; ++k) {
+                    const int s = s0 + k * st;
+                    const int j = a.scol[s];
+                    if (j > i) acc = fma_t(a.gval[s], a.y1[(size_t)j * d + c], acc);
+                }
             }
             const T z = mul_t(a.isq[i], acc);
             a.zl[e] = z;
@@ -667,15 +742,43 @@ __device__ __forceinline__ void ph_la(const KA<T>& a, int lb, double* sh) {
             const size_t e = (size_t)i * d + c;
             int s0, cnt, st;
             row_slots<KC>(a, i, s0, cnt, st);
-            const T pi = first ? a.zl[e] : fma_t(beta, pold[e], a.zl[e]);
+            const T zi = a.zl[e];
+            const T po = pold[e];
+            const T pi = first ? zi : fma_t(beta, po, zi);
             T acc = T(0);
-#pragma unroll(KC > 0 ? 4 : 2)
-            for (int k = 0; k < cnt; ++k) {
-                const int s = s0 + k * st;
-                const size_t ej = (size_t)a.scol[s] * d + c;
-                const T ww = a.sw[s];
-                const T pj = first ? a.zl[ej] : fma_t(beta, pold[ej], a.zl[ej]);
-                acc = fma_t(mul_t(ww, ww), pj, acc);
+            if constexpr (KC > 0) {
+                constexpr int G = slot_group<KC, 8>();
+#pragma unroll
+                for (int k0 = 0; k0 < KC; k0 += G) {
+                    int jj[G];
+                    T ww[G], zj[G], pj[G];
+#pragma unroll
+                    for (int k = 0; k < G; ++k) {
+                        const int sl = s0 + (k0 + k) * st;
+                        jj[k] = a.scol[sl];
+                        ww[k] = a.sw[sl];
+                    }
+#pragma unroll
+                    for (int k = 0; k < G; ++k) {
+                        const size_t ej = (size_t)jj[k] * d + c;
+                        zj[k] = a.zl[ej];
+                        pj[k] = pold[ej];
+                    }
+#pragma unroll
+                    for (int k = 0; k < G; ++k) {
+                        const T pv = first ? zj[k] : fma_t(beta, pj[k], zj[k]);
+                        acc = fma_t(mul_t(ww[k], ww[k]), pv, acc);
+                    }
+                }
+            } else {
+#pragma unroll 2
+                for (int k = 0; k < cnt; ++k) {
+                    const int s = s0 + k * st;
+                    const size_t ej = (size_t)a.scol[s] * d + c;
+                    const T ww = a.sw[s];
+                    const T pj = first ? a.zl[ej] : fma_t(beta, pold[ej], a.zl[ej]);
+                    acc = fma_t(mul_t(ww, ww), pj, acc);
+                }
             }
             const T qi = fma_t(a.diagA[i], pi, -mul_t(a.c_off, acc));
             pnew[e] = pi;
@@ -684,24 +787,6 @@ __device__ __forceinline__ void ph_la(const KA<T>& a, int lb, double* sh) {
         }
     }
     block_partials<1>(acc1, sh, d, R, a.part, a.nblk, lb);
-}
-
-template <typename T>
-__device__ __forceinline__ void ph_lb(const KA<T>& a, int lb) {
-    const int d = a.d, R = a.R, t = threadIdx.x;
-    const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
-    const int it = ld_flag(&a.S->it);
-    const T* p = a.sb[it & 1];
-    const T* q = a.wb[0];
-    T* r = a.rb[0];
-    if (t >= R * d) return;
-    const int rl = t / d, c = t - rl * d;
-    const T alpha = (T)a.cs.alpha[a.blk_seg[lb] * d + c];
-    for (int i = rb + rl; i < re; i += rs) {
-        const size_t e = (size_t)i * d + c;
-        a.x[e] = fma_t(alpha, p[e], a.x[e]);
-        r[e] = fma_t(-alpha, q[e], r[e]);
-    }
 }
 
 // PH_ZERO: x_c = 0 for columns with a zero right-hand side
@@ -1499,16 +1584,10 @@ __global__ void __launch_bounds__(kBlock) k_lpcg_aq(KA<T> a) {
     if (last_block(a.bar + kBarLast, a.nblk)) fin_la(a, sh);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_lpcg_xr(KA<T> a) {
-    if (ld_flag(&a.S->done)) return;
-    ph_lb(a, logical_block(a.nblk));
-}
-
 template <typename T, int KC>
-__global__ void __launch_bounds__(kBlock) k_lpcg_g(KA<T> a) {
+__global__ void __launch_bounds__(kBlock) k_lpcg_g(KA<T> a, int upd) {
     if (ld_flag(&a.S->done)) return;
-    ph_lc<KC>(a, logical_block(a.nblk));
+    ph_lc<KC>(a, logical_block(a.nblk), upd);
 }
 
 template <typename T, int KC>
@@ -1516,7 +1595,7 @@ __global__ void __launch_bounds__(kBlock) k_lpcg_gt(KA<T> a, int initial) {
     __shared__ double sh[kSmemDoubles];
     if (ld_flag(&a.S->done)) return;
     const int lb = logical_block(a.nblk);
-    ph_ld<KC>(a, lb, sh);
+    ph_ld<KC>(a, lb, sh, initial);
     if (last_block(a.bar + kBarLast, a.nblk)) {
         fin_ld(a, sh, initial != 0);
         if (threadIdx.x == 0 && a.S->done) solve_stats(a);
@@ -2097,6 +2176,7 @@ KA<T> make_args(pfe_ctx* c, const Partition& pt) {
     a.store_rhs = 0;
     a.b_zero = 0;
     a.ortho = c->prm.ortho;
+    a.sten = c->g->stencil;
     return a;
 }
 
@@ -2123,8 +2203,7 @@ pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0)
         case PH_IT: PFE_LAUNCH_KC(k_cg_it, K, grid, st, a); break;
         case PH_ZERO: hipLaunchKernelGGL(k_cg_zero<T>, grid, dim3(kBlock), 0, st, a); break;
         case PH_LA: PFE_LAUNCH_KC(k_lpcg_aq, K, grid, st, a); break;
-        case PH_LB: hipLaunchKernelGGL(k_lpcg_xr<T>, grid, dim3(kBlock), 0, st, a); break;
-        case PH_LC: PFE_LAUNCH_KC(k_lpcg_g, K, grid, st, a); break;
+        case PH_LC: PFE_LAUNCH_KC(k_lpcg_g, K, grid, st, a, mode); break;
         case PH_LD: PFE_LAUNCH_KC(k_lpcg_gt, K, grid, st, a, mode); break;
         case PH_GRAM: hipLaunchKernelGGL(k_gram<T>, grid, dim3(kBlock), 0, st, a, mode); break;
         case PH_APPLY: hipLaunchKernelGGL(k_apply<T>, grid, dim3(kBlock), 0, st, a, mode); break;
@@ -2153,7 +2232,6 @@ const void* kernel_for(int which, int ellK) {
         case PH_LA: PFE_KSEL(k_lpcg_aq)
         case PH_LC: PFE_KSEL(k_lpcg_g)
         case PH_LD: PFE_KSEL(k_lpcg_gt)
-        case PH_LB: return reinterpret_cast<const void*>(&k_lpcg_xr<T>);
     }
 #undef PFE_KSEL
     return nullptr;
@@ -2170,9 +2248,10 @@ pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, hipGraphExec
     hipGraph_t g = nullptr;
     PFE_CHECK_HIP(hipGraphCreate(&g, 0));
     KA<T> args = a;
-    int initial = 0;
+    int initial = 0, upd = 1;
     void* p1[] = {(void*)&args};
     void* p2[] = {(void*)&args, (void*)&initial};
+    void* p3[] = {(void*)&args, (void*)&upd};
     hipGraphNode_t prev = nullptr;
     hipError_t e = hipSuccess;
     auto add = [&](const void* fn, void** kp) {
@@ -2192,8 +2271,7 @@ pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, hipGraphExec
     for (int k = 0; k < kCgChunk; ++k) {
         if (learned) {
             add(kernel_for<T>(PH_LA, K), p1);
-            add(kernel_for<T>(PH_LB, K), p1);
-            add(kernel_for<T>(PH_LC, K), p1);
+            add(kernel_for<T>(PH_LC, K), p3);
             add(kernel_for<T>(PH_LD, K), p2);
         } else {
             add(kernel_for<T>(PH_IT, K), p1);
@@ -2253,7 +2331,7 @@ pfe_status pcg_loop_mk(pfe_ctx* c, const KA<T>& a) {
 template <typename T>
 pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a) {
     hipLaunchKernelGGL(k_stats_if_done<T>, dim3(1), dim3(64), 0, c->stream, a);
-    PFE_TRY(launch_phase(c, a, PH_LC, 0, 0));
+    PFE_TRY(launch_phase(c, a, PH_LC, 0, 0));     // y1 from the initial residual
     PFE_TRY(launch_phase(c, a, PH_LD, 1, 0));     // initial r.z
     if (c->prm.graphs) {
         PFE_TRY(pcg_replay(c, a, true));
@@ -2265,8 +2343,7 @@ pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a) {
     while (true) {
         for (int k = 0; k < chunk; ++k) {
             PFE_TRY(launch_phase(c, a, PH_LA, 0, 0));
-            PFE_TRY(launch_phase(c, a, PH_LB, 0, 0));
-            PFE_TRY(launch_phase(c, a, PH_LC, 0, 0));
+            PFE_TRY(launch_phase(c, a, PH_LC, 1, 0));
             PFE_TRY(launch_phase(c, a, PH_LD, 0, 0));
         }
         it += chunk;

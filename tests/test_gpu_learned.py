@@ -171,3 +171,26 @@ def test_learned_pcg_graph_replay_is_bitwise_neutral():
     for (xa, ia, _), (xb, ib, _) in zip(out[0], out[1]):
         assert np.array_equal(ia, ib)
         assert np.array_equal(xa.cpu().numpy(), xb.cpu().numpy())
+
+
+def test_learned_pcg_on_edge_list_graph_matches_oracle():
+    """General (non-stencil) slot layout: lower/upper neighbours chosen by column."""
+    from paper_1612_06496_amd import Graph, Mpnn, Solver
+    banner("learned PCG on a k-NN graph")
+    wl = synth.edges_workload("gmm", 700, 8, 4, 6, 2, d=3)
+    g = O.build_edge_graph(wl.n, wl.src, wl.dst, wl.dist2, wl.sigma)
+    G = Graph.edges(wl.n, wl.src, wl.dst, wl.dist2, wl.sigma)
+    S = Solver(G, wl.y0, lam=20.0, r=1.0, n_inner=2, tol=1e-6, maxit=5000, persistent=False)
+    SS = LN.ScaledSystem(g, 20.0, 1.0)
+    th = random_params(9, scale=0.2)
+    S.set_learned(Mpnn(th))
+    rhs = np.random.default_rng(10).normal(size=(g.n, 3))
+    x, it, info = S.pcg(rhs, np.zeros_like(rhs))
+    gv, dg = LN.factor(th, SS)
+    _, it_o = LN.pcg_preconditioned(SS.A, rhs, np.zeros_like(rhs),
+                                    lambda q: LN.apply_preconditioner(gv, dg, SS, q), 1e-6, 5000)
+    exact = O.DirectSolver(SS.A)(rhs)
+    e = rel(x.cpu().numpy(), exact)
+    print(f"iterations gpu {it} oracle {it_o}; solution rel err {e:.2e}")
+    assert info["rel_res_max"] <= 1e-6 and e <= 1e-4
+    assert np.all(np.abs(it - it_o) <= 2)
