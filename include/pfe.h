@@ -153,7 +153,8 @@ typedef struct {
     int32_t status;          /* worst pfe_status met (PFE_E_NOCONV, PFE_E_NOT_SPD, ...) */
     int32_t fallbacks;       /* learned-preconditioner solves redone with Jacobi */
     int32_t workgroups;      /* workgroups of the persistent launch (0: one launch per phase) */
-    int32_t flags;           /* persistent launch: bit 0 the rows' slot data were held in LDS */
+    int32_t flags;           /* bit 0: persistent launch with the rows' slot data held in LDS;
+                                bit 1: one launch per phase on image strips */
 } pfe_step_info;
 
 /* Monitors of the current state (Eq. 1, Eq. 2). */
@@ -234,16 +235,18 @@ pfe_status pfe_solve(pfe_ctx* c, int n_outer, pfe_step_info* info);
  * persistent (one cooperative launch per SOC iteration) or one launch per
  * phase; team = workgroups that deal an XCD band's row chunks out cyclically
  * (1: contiguous row ranges); row_cache = slot data of the workgroups' rows
- * held in LDS.  The results are identical up to the summation order of the
- * FP64 reductions. */
+ * held in LDS; strips = one launch per phase with the residual, w0 and CG
+ * kernels of a pixel-grid graph on image strips (each workgroup walks a strip
+ * row by row, neighbour values from an LDS ring).  The results are identical
+ * up to the summation order of the FP64 reductions. */
 typedef struct {
     int32_t persistent;
     int32_t team;
     int32_t row_cache;
-    int32_t workgroups;      /* persistent launch: its workgroups */
+    int32_t workgroups;      /* persistent launch: its workgroups; one launch per phase: the CG kernels' */
     double ms;               /* measured milliseconds per SOC iteration */
     int32_t chosen;          /* 1 for the shape kept */
-    int32_t reserved;
+    int32_t strips;          /* one launch per phase on image strips */
 } pfe_tune_result;
 
 /* Autotune the launch shape on this context's graph: from the current state
@@ -251,7 +254,7 @@ typedef struct {
  * per candidate shape, restore the state after each, and keep the fastest for
  * later pfe_step / pfe_solve calls.  Candidates: persistent with teams of 64
  * or 1, each with and without the LDS row cache (when the rows fit), and one
- * launch per phase.  results (host, may be null when max_results is 0)
+ * launch per phase on row chunks and (pixel grids) on image strips.  results (host, may be null when max_results is 0)
  * receives up to max_results measured shapes, *n_results their number.
  * Allocates a temporary copy of Y, P, B.  PFE_E_STATE inside a SOC iteration. */
 pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int max_results, int* n_results);

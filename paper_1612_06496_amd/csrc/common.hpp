@@ -112,4 +112,8 @@ struct pfe_graph {
     // a graph built from one description is a single segment.
     std::vector<int64_t> seg_row0;
     std::vector<int64_t> seg_edge0;
+    // image height and width of each segment (0 for edge-list graphs); a
+    // segment's pixel (y, x) is vertex seg_row0 + y W + x
+    std::vector<int> seg_H;
+    std::vector<int> seg_W;
 };

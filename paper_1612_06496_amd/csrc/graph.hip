@@ -606,6 +606,8 @@ pfe_status pfe_build_graph(const pfe_graph_desc* d, hipStream_t stream, pfe_grap
     }
     g->seg_row0 = {0, g->n};
     g->seg_edge0 = {0, g->n_edges};
+    g->seg_H = {d->kind == PFE_GRID ? d->H : 0};
+    g->seg_W = {d->kind == PFE_GRID ? d->W : 0};
     *out = g;
     return PFE_OK;
 }
@@ -676,6 +678,8 @@ pfe_status pfe_graph_union(const pfe_graph* const* parts, int count, hipStream_t
     int64_t V = 0, S = 0, Eo = 0;
     g->seg_row0.assign(1, 0);
     g->seg_edge0.assign(1, 0);
+    g->seg_H.clear();
+    g->seg_W.clear();
     for (int p = 0; p < count; ++p) {
         const pfe_graph* q = parts[p];
         const int64_t n = q->n, sl = q->slots;
@@ -710,6 +714,8 @@ pfe_status pfe_graph_union(const pfe_graph* const* parts, int count, hipStream_t
         for (size_t k = 1; k < q->seg_row0.size(); ++k) {
             g->seg_row0.push_back(g->seg_row0.back() + (q->seg_row0[k] - q->seg_row0[k - 1]));
             g->seg_edge0.push_back(g->seg_edge0.back() + (q->seg_edge0[k] - q->seg_edge0[k - 1]));
+            g->seg_H.push_back(q->seg_H[k - 1]);
+            g->seg_W.push_back(q->seg_W[k - 1]);
         }
     }
     const int last = (int)SL;

@@ -75,6 +75,8 @@ struct KA {
                            // first + k stride + [0, R) below end are its own)
     const int* blk_seg;    // segment of each logical workgroup
     const int* seg_blk0;   // nseg + 1 first logical workgroup of each segment
+    const int* geo;        // strip partitions: per logical workgroup {row0, W, H, x0, len, y0, y1, 0}
+                           // (image pixels (y, x), y in [y0, y1), x in [x0, x0 + len)); else null
     const int* rowptr;     // CSR row pointers (used when ell_K == 0)
     const int* scol;       // solver slot layout
     const T* sw;
@@ -892,6 +894,295 @@ __device__ __forceinline__ void ph_apply(const KA<T>& a, int lb, int mode, doubl
 }
 
 // ---------------------------------------------------------------------------
+// Strip phases (pixel grids with a compiled stencil width, one launch per
+// phase).  A workgroup owns the pixels x in [x0, x0 + len), y in [y0, y1) of
+// one image and walks them one image row at a time.  Thread t holds element t
+// of a ring row: pixel x0 - rho + t / d, column t % d, over the row segment
+// [x0 - rho, x0 + len + rho).  The value each neighbour contributes (u_j of
+// the CG iteration, x_j of A x) is formed once per pixel, by the thread that
+// loaded it, into an LDS ring of 2 rho + 2 image rows, and the stencil sums
+// read the ring; the loads of the next image row are issued before the
+// arithmetic of the current one.  A thread's own pixel is the pixel it loads
+// into the ring, so its own r, w, s come from the same loads.  The per-element
+// arithmetic and the slot order are those of the row-chunk phases, so both
+// give the same values element by element; only the per-workgroup partial
+// sums group the rows differently.
+// ---------------------------------------------------------------------------
+
+// ELL slot k of a pixel grid is the stencil offset (dy, dx) of the (2 rho + 1)^2
+// window in raster order without its centre (8 and 24 slots), or of the
+// 4-neighbour cross in raster order.
+template <int KC>
+struct Sten {
+    static constexpr int rho = (KC == 24) ? 2 : 1;
+    static constexpr int side = 2 * rho + 1;
+    static constexpr int ring = 2 * rho + 2;   // ring rows in LDS
+    __device__ static constexpr int dy(int k) {
+        return KC == 4 ? (k == 0 ? -1 : (k == 3 ? 1 : 0)) : ((k < KC / 2 ? k : k + 1) / side - rho);
+    }
+    __device__ static constexpr int dx(int k) {
+        return KC == 4 ? (k == 1 ? -1 : (k == 2 ? 1 : 0)) : ((k < KC / 2 ? k : k + 1) % side - rho);
+    }
+    __device__ static constexpr int slot(int y) { return (y + 4 * ring) % ring; }   // y >= -2 rho
+};
+
+struct StripGeo {
+    int row0, W, H, x0, len, y0, y1;
+};
+
+__device__ __forceinline__ StripGeo strip_geo(const int* geo, int lb) {
+    const int* g = geo + 8 * lb;
+    return StripGeo{g[0], g[1], g[2], g[3], g[4], g[5], g[6]};
+}
+
+// lane roles of a strip workgroup
+struct StripLane {
+    int c, px, span;
+    bool loader, in_image, owner;
+    __device__ StripLane(const StripGeo& g, int d, int rho) {
+        const int t = threadIdx.x, q = t / d;
+        c = t - q * d;
+        span = g.len + 2 * rho;
+        px = g.x0 - rho + q;
+        loader = q < span;
+        in_image = loader && px >= 0 && px < g.W;
+        owner = q >= rho && q < rho + g.len;
+    }
+};
+
+// CG iteration (the PH_IT arithmetic) over a strip
+template <int KC, typename T>
+__device__ __forceinline__ void st_it(const KA<T>& a, int lb, double* sh, int it, const double* alphas,
+                                      const double* betas) {
+    using S = Sten<KC>;
+    constexpr int rho = S::rho;
+    constexpr bool PW = KC <= 8;   // slot weights loaded one image row ahead with the rest
+    const StripGeo g = strip_geo(a.geo, lb);
+    const int d = a.d, t = threadIdx.x;
+    const StripLane ln(g, d, rho);
+    const bool first = (it == 0);
+    const int cur = it & 1, nxt = cur ^ 1;
+    const T* r = a.rb[cur];
+    const T* w = a.wb[cur];
+    const T* sp = a.sb[cur];
+    T* rn = a.rb[nxt];
+    T* wn = a.wb[nxt];
+    T* sn = a.sb[nxt];
+    const int ci = a.blk_seg[lb] * d + ln.c;
+    const T alpha = (T)alphas[ci];
+    const T beta = (T)betas[ci];
+    T* ring = reinterpret_cast<T*>(sh);
+    const int ylo = max(0, g.y0 - rho), yhi = min(g.H, g.y1 + rho);
+    struct Raw { T r, w, sp, inv; };
+    struct Own { T p, x, dA, ww[PW ? KC : 1]; };
+    auto ld = [&](int y) {
+        Raw v{T(0), T(0), T(0), T(0)};
+        if (ln.in_image && y >= ylo && y < yhi) {
+            const int j = g.row0 + y * g.W + ln.px;
+            const size_t e = (size_t)j * d + ln.c;
+            v.r = r[e];
+            v.w = w[e];
+            v.sp = sp[e];
+            v.inv = a.invdiag[j];
+        }
+        return v;
+    };
+    auto ldo = [&](int y) {
+        Own o{};
+        if (ln.owner && y < g.y1) {
+            const int i = g.row0 + y * g.W + ln.px;
+            const size_t e = (size_t)i * d + ln.c;
+            o.p = a.p[e];
+            o.x = a.x[e];
+            o.dA = a.diagA[i];
+            if constexpr (PW) {
+#pragma unroll
+                for (int k = 0; k < KC; ++k) o.ww[k] = a.sw[(size_t)k * a.n + i];
+            }
+        }
+        return o;
+    };
+    // u_j = diag(A)^{-1} r_{j, i+1}: the neighbours' new u, as their owners form it
+    auto u_of = [&](const Raw& v) { return mul_t(v.inv, cg_r(alpha, cg_s(first, beta, v.sp, v.w), v.r)); };
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (g.len > 0 && g.y1 > g.y0) {
+        Raw raw[rho + 1];   // image rows y .. y + rho of this lane
+#pragma unroll
+        for (int k = 1; k <= rho; ++k)
+            if (ln.loader) ring[S::slot(g.y0 - k) * kBlock + t] = u_of(ld(g.y0 - k));
+#pragma unroll
+        for (int k = 0; k <= rho; ++k) raw[k] = ld(g.y0 + k);
+#pragma unroll
+        for (int k = 0; k < rho; ++k)
+            if (ln.loader) ring[S::slot(g.y0 + k) * kBlock + t] = u_of(raw[k]);
+        Own own = ldo(g.y0);
+        for (int y = g.y0; y < g.y1; ++y) {
+            if (ln.loader) ring[S::slot(y + rho) * kBlock + t] = u_of(raw[rho]);
+            const Raw rnext = ld(y + rho + 1);
+            const Own onext = ldo(y + 1);
+            __syncthreads();
+            if (ln.owner) {
+                const int i = g.row0 + y * g.W + ln.px;
+                const size_t e = (size_t)i * d + ln.c;
+                const Raw& v = raw[0];
+                const T ui = mul_t(v.inv, v.r);
+                const T pi = first ? ui : fma_t(beta, own.p, ui);
+                const T si = cg_s(first, beta, v.sp, v.w);
+                const T rn_i = cg_r(alpha, si, v.r);
+                const T un_i = mul_t(v.inv, rn_i);
+                T accA = T(0);
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    const T wk = PW ? own.ww[PW ? k : 0] : a.sw[(size_t)k * a.n + i];
+                    accA = fma_t(mul_t(wk, wk), ring[S::slot(y + S::dy(k)) * kBlock + t + S::dx(k) * d], accA);
+                }
+                const T wn_i = fma_t(own.dA, un_i, -mul_t(a.c_off, accA));
+                a.p[e] = pi;
+                sn[e] = si;
+                a.x[e] = fma_t(alpha, pi, own.x);
+                rn[e] = rn_i;
+                wn[e] = wn_i;
+                acc[0] += (double)rn_i * (double)un_i;
+                acc[1] += (double)wn_i * (double)un_i;
+                acc[2] += (double)rn_i * (double)rn_i;
+            }
+#pragma unroll
+            for (int k = 0; k < rho; ++k) raw[k] = raw[k + 1];
+            raw[rho] = rnext;
+            own = onext;
+        }
+    }
+    __syncthreads();   // the ring shares sh with the partial sums
+    block_partials<3>(acc, sh, d, kBlock / d, a.part, a.nblk, lb);
+}
+
+// w0 = A u0 with u0 = r0 / diag(A) (the PH_W0 arithmetic) over a strip
+template <int KC, typename T>
+__device__ __forceinline__ void st_w0(const KA<T>& a, int lb, double* sh) {
+    using S = Sten<KC>;
+    constexpr int rho = S::rho;
+    const StripGeo g = strip_geo(a.geo, lb);
+    const int d = a.d, t = threadIdx.x;
+    const StripLane ln(g, d, rho);
+    const T* r = a.rb[0];
+    T* w = a.wb[0];
+    T* ring = reinterpret_cast<T*>(sh);
+    const int ylo = max(0, g.y0 - rho), yhi = min(g.H, g.y1 + rho);
+    struct Raw { T r, inv; };
+    auto ld = [&](int y) {
+        Raw v{T(0), T(0)};
+        if (ln.in_image && y >= ylo && y < yhi) {
+            const int j = g.row0 + y * g.W + ln.px;
+            v.r = r[(size_t)j * d + ln.c];
+            v.inv = a.invdiag[j];
+        }
+        return v;
+    };
+    double acc[2] = {0.0, 0.0};
+    if (g.len > 0 && g.y1 > g.y0) {
+        Raw raw[rho + 1];
+#pragma unroll
+        for (int k = 1; k <= rho; ++k)
+            if (ln.loader) { const Raw v = ld(g.y0 - k); ring[S::slot(g.y0 - k) * kBlock + t] = mul_t(v.inv, v.r); }
+#pragma unroll
+        for (int k = 0; k <= rho; ++k) raw[k] = ld(g.y0 + k);
+#pragma unroll
+        for (int k = 0; k < rho; ++k)
+            if (ln.loader) ring[S::slot(g.y0 + k) * kBlock + t] = mul_t(raw[k].inv, raw[k].r);
+        for (int y = g.y0; y < g.y1; ++y) {
+            if (ln.loader) ring[S::slot(y + rho) * kBlock + t] = mul_t(raw[rho].inv, raw[rho].r);
+            const Raw rnext = ld(y + rho + 1);
+            __syncthreads();
+            if (ln.owner) {
+                const int i = g.row0 + y * g.W + ln.px;
+                const size_t e = (size_t)i * d + ln.c;
+                const T ri = raw[0].r;
+                const T ui = mul_t(raw[0].inv, ri);
+                T accA = T(0);
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    const T wk = a.sw[(size_t)k * a.n + i];
+                    accA = fma_t(mul_t(wk, wk), ring[S::slot(y + S::dy(k)) * kBlock + t + S::dx(k) * d], accA);
+                }
+                const T wi = fma_t(a.diagA[i], ui, -mul_t(a.c_off, accA));
+                w[e] = wi;
+                acc[0] += (double)ri * (double)ui;
+                acc[1] += (double)wi * (double)ui;
+            }
+#pragma unroll
+            for (int k = 0; k < rho; ++k) raw[k] = raw[k + 1];
+            raw[rho] = rnext;
+        }
+    }
+    __syncthreads();
+    block_partials<2>(acc, sh, d, kBlock / d, a.part, a.nblk, lb);
+}
+
+// r0 = rhs - A x (PH_E0: rhs = r/2 D^{1/2}(P - B); PH_R0: the stored rhs) over
+// a strip, with the partials of rhs.rhs and r0.r0 (the ph_residual arithmetic)
+template <int KC, typename T>
+__device__ __forceinline__ void st_res(const KA<T>& a, int lb, int mode, double* sh) {
+    using S = Sten<KC>;
+    constexpr int rho = S::rho;
+    const StripGeo g = strip_geo(a.geo, lb);
+    const int d = a.d, t = threadIdx.x;
+    const StripLane ln(g, d, rho);
+    T* r0 = a.rb[0];
+    T* ring = reinterpret_cast<T*>(sh);
+    const int ylo = max(0, g.y0 - rho), yhi = min(g.H, g.y1 + rho);
+    auto ld = [&](int y) {
+        T v = T(0);
+        if (ln.in_image && y >= ylo && y < yhi) v = a.x[(size_t)(g.row0 + y * g.W + ln.px) * d + ln.c];
+        return v;
+    };
+    double acc[2] = {0.0, 0.0};
+    if (g.len > 0 && g.y1 > g.y0) {
+        T raw[rho + 1];
+#pragma unroll
+        for (int k = 1; k <= rho; ++k)
+            if (ln.loader) ring[S::slot(g.y0 - k) * kBlock + t] = ld(g.y0 - k);
+#pragma unroll
+        for (int k = 0; k <= rho; ++k) raw[k] = ld(g.y0 + k);
+#pragma unroll
+        for (int k = 0; k < rho; ++k)
+            if (ln.loader) ring[S::slot(g.y0 + k) * kBlock + t] = raw[k];
+        for (int y = g.y0; y < g.y1; ++y) {
+            if (ln.loader) ring[S::slot(y + rho) * kBlock + t] = raw[rho];
+            const T rnext = ld(y + rho + 1);
+            __syncthreads();
+            if (ln.owner) {
+                const int i = g.row0 + y * g.W + ln.px;
+                const size_t e = (size_t)i * d + ln.c;
+                const T xi = raw[0];
+                T accA = T(0);
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    const T wk = a.sw[(size_t)k * a.n + i];
+                    accA = fma_t(mul_t(wk, wk), ring[S::slot(y + S::dy(k)) * kBlock + t + S::dx(k) * d], accA);
+                }
+                T rhs;
+                if (mode == PH_R0) {
+                    rhs = a.rhs[e];
+                } else {
+                    rhs = mul_t(a.half_r, mul_t(a.sqrtD[i], a.P[e] - a.B[e]));
+                    if (a.store_rhs) a.rhs[e] = rhs;
+                }
+                const T ax = fma_t(a.diagA[i], xi, -mul_t(a.c_off, accA));
+                const T rv = rhs - ax;
+                r0[e] = rv;
+                acc[0] += (double)rhs * (double)rhs;
+                acc[1] += (double)rv * (double)rv;
+            }
+#pragma unroll
+            for (int k = 0; k < rho; ++k) raw[k] = raw[k + 1];
+            raw[rho] = rnext;
+        }
+    }
+    __syncthreads();
+    block_partials<2>(acc, sh, d, kBlock / d, a.part, a.nblk, lb);
+}
+
+// ---------------------------------------------------------------------------
 // Finalisers (one workgroup, after every workgroup has written its partials).
 // 'grouped' means the per-XCD-group partials are already summed (one segment).
 // ---------------------------------------------------------------------------
@@ -1570,6 +1861,36 @@ __global__ void __launch_bounds__(kBlock) k_cg_it(KA<T> a) {
     }
 }
 
+// strip kernels (pixel grids): the residual with r0, w0 and the CG iteration
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_st_res(KA<T> a, int ph) {
+    __shared__ double sh[kSmemDoubles];
+    const int lb = logical_block(a.nblk);
+    st_res<KC>(a, lb, ph, sh);
+    if (last_block(a.bar + kBarLast, a.nblk)) fin_res(a, sh, false);
+}
+
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_st_w0(KA<T> a) {
+    __shared__ double sh[kSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    const int lb = logical_block(a.nblk);
+    st_w0<KC>(a, lb, sh);
+    if (last_block(a.bar + kBarLast, a.nblk)) fin_w0(a, sh, false);
+}
+
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_st_it(KA<T> a) {
+    __shared__ double sh[kSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    const int lb = logical_block(a.nblk);
+    st_it<KC>(a, lb, sh, ld_flag(&a.S->it), a.cs.alpha, a.cs.beta);
+    if (last_block(a.bar + kBarLast, a.nblk)) {
+        fin_it(a, sh, false);
+        if (threadIdx.x == 0 && a.S->done) solve_stats(a);
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_cg_zero(KA<T> a) {
     ph_zero(a, logical_block(a.nblk), a.cs.zero);
@@ -1978,6 +2299,7 @@ struct Partition {
     int* bit = nullptr;       // device, 3 nblk: first row, end row, stride
     int* blk_seg = nullptr;   // device, nblk
     int* seg_blk0 = nullptr;  // device, nseg + 1
+    int* geo = nullptr;       // device, 8 nblk: strip geometry (strip partitions only)
 };
 
 struct pfe_ctx {
@@ -1991,6 +2313,8 @@ struct pfe_ctx {
     int inner = 0;           // inner iterations done in the current SOC iteration
     Partition pm;            // multi-launch partition
     Partition pc;            // persistent partition (pc.nblk == 0: not available)
+    Partition ps;            // strip partition of pixel grids (ps.nblk == 0: not available)
+    int want_strips = 1;     // one-launch-per-phase: residual, w0 and CG kernels on strips
     void* Y = nullptr; void* P = nullptr; void* B = nullptr;
     void* bs = nullptr; void* ds = nullptr;
     void* rhs = nullptr; void* p = nullptr;
@@ -2115,11 +2439,77 @@ pfe_status make_partition(const std::vector<int64_t>& seg_rows, int want_blocks,
 }
 
 void free_partition(Partition& P) {
+    if (P.geo) (void)hipFree(P.geo);
     if (P.row0) (void)hipFree(P.row0);
     if (P.bit) (void)hipFree(P.bit);
     if (P.blk_seg) (void)hipFree(P.blk_seg);
     if (P.seg_blk0) (void)hipFree(P.seg_blk0);
     P = Partition{};
+}
+
+// Strip partition of a graph whose segments are pixel grids with a compiled
+// stencil width (4, 8, 24 slots): image s is cut into nsx column strips of at
+// most kBlock / d - 2 rho pixels (equal widths up to one pixel) and nsy bands
+// of image rows (at least kStripMinRows rows each), the number of workgroups
+// of each image proportional to its pixels.  Logical workgroups run in the
+// order (image, band, strip), so the consecutive workgroups that one XCD holds
+// are horizontally adjacent strips and share the cache lines at their borders.
+// The count is padded to a multiple of the XCD count with empty workgroups.
+constexpr int kStripMinRows = 16;
+
+pfe_status make_strip_partition(const pfe_graph* g, int d, int want_blocks, Partition& P) {
+    free_partition(P);
+    const int K = g->ell_K;
+    const int nseg = (int)g->seg_row0.size() - 1;
+    if (!g->stencil || !(K == 4 || K == 8 || K == 24) || (int)g->seg_W.size() != nseg) return PFE_OK;
+    for (int s = 0; s < nseg; ++s)
+        if (g->seg_W[s] < 1 || g->seg_H[s] < 1) return PFE_OK;
+    const int rho = (K == 24) ? 2 : 1;
+    const int L = kBlock / d - 2 * rho;
+    if (L < 1) return PFE_OK;
+    const double n = (double)g->n;
+    std::vector<int> geo, bseg, sb0(nseg + 1);
+    for (int s = 0; s < nseg; ++s) {
+        const int W = g->seg_W[s], H = g->seg_H[s], row0 = (int)g->seg_row0[s];
+        const int nsx = (W + L - 1) / L;
+        const double ns = (double)W * H;
+        int nsy = (int)std::llround((double)want_blocks * ns / (n * nsx));
+        nsy = std::min(nsy, std::max(1, H / kStripMinRows));
+        nsy = std::max(1, std::min(nsy, H));
+        sb0[s] = (int)bseg.size();
+        for (int sy = 0; sy < nsy; ++sy) {
+            const int y0 = (int)((int64_t)H * sy / nsy), y1 = (int)((int64_t)H * (sy + 1) / nsy);
+            for (int sx = 0; sx < nsx; ++sx) {
+                const int x0 = (int)((int64_t)W * sx / nsx), x1 = (int)((int64_t)W * (sx + 1) / nsx);
+                const int gv[8] = {row0, W, H, x0, x1 - x0, y0, y1, 0};
+                geo.insert(geo.end(), gv, gv + 8);
+                bseg.push_back(s);
+            }
+        }
+    }
+    while (bseg.size() % kNumXcd) {
+        const int s = nseg - 1;
+        const int gv[8] = {(int)g->seg_row0[s], g->seg_W[s], g->seg_H[s], 0, 0, 0, 0, 0};
+        geo.insert(geo.end(), gv, gv + 8);
+        bseg.push_back(s);
+    }
+    const int total = (int)bseg.size();
+    sb0[nseg] = total;
+    std::vector<int> zeros(3 * (size_t)total + 1, 0);
+    P.nblk = total;
+    P.team = 1;
+    P.max_np = 0;
+    PFE_CHECK_HIP(hipMalloc((void**)&P.geo, sizeof(int) * geo.size()));
+    PFE_CHECK_HIP(hipMalloc((void**)&P.bit, sizeof(int) * 3 * total));
+    PFE_CHECK_HIP(hipMalloc((void**)&P.row0, sizeof(int) * (total + 1)));
+    PFE_CHECK_HIP(hipMalloc((void**)&P.blk_seg, sizeof(int) * total));
+    PFE_CHECK_HIP(hipMalloc((void**)&P.seg_blk0, sizeof(int) * (nseg + 1)));
+    PFE_CHECK_HIP(hipMemcpy(P.geo, geo.data(), sizeof(int) * geo.size(), hipMemcpyHostToDevice));
+    PFE_CHECK_HIP(hipMemcpy(P.bit, zeros.data(), sizeof(int) * 3 * total, hipMemcpyHostToDevice));
+    PFE_CHECK_HIP(hipMemcpy(P.row0, zeros.data(), sizeof(int) * (total + 1), hipMemcpyHostToDevice));
+    PFE_CHECK_HIP(hipMemcpy(P.blk_seg, bseg.data(), sizeof(int) * total, hipMemcpyHostToDevice));
+    PFE_CHECK_HIP(hipMemcpy(P.seg_blk0, sb0.data(), sizeof(int) * (nseg + 1), hipMemcpyHostToDevice));
+    return PFE_OK;
 }
 
 template <typename T>
@@ -2135,6 +2525,7 @@ KA<T> make_args(pfe_ctx* c, const Partition& pt) {
     a.bit = pt.bit;
     a.blk_seg = pt.blk_seg;
     a.seg_blk0 = pt.seg_blk0;
+    a.geo = pt.geo;
     a.rowptr = c->g->rowptr;
     a.scol = c->g->s_col;
     if (sizeof(T) == 4) a.sw = (const T*)c->g->s_w32; else a.sw = (const T*)c->g->s_w64;
@@ -2192,11 +2583,37 @@ KA<T> make_args(pfe_ctx* c, const Partition& pt) {
         }                                                                                          \
     } while (0)
 
+// strip kernel K<T, KC> for the stencil width (strip partitions exist only for 4, 8, 24)
+#define PFE_LAUNCH_ST(K, ellK, grid, stream, ...)                                                   \
+    do {                                                                                           \
+        switch (ellK) {                                                                            \
+            case 4: hipLaunchKernelGGL((K<T, 4>), grid, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+            case 8: hipLaunchKernelGGL((K<T, 8>), grid, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+            case 24: hipLaunchKernelGGL((K<T, 24>), grid, dim3(kBlock), 0, stream, __VA_ARGS__); break; \
+            default: set_error("strip kernels need a stencil of 4, 8 or 24 slots"); return PFE_E_STATE; \
+        }                                                                                          \
+    } while (0)
+
 template <typename T>
 pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0) {
     const dim3 grid(a.nblk);
     hipStream_t st = c->stream;
     const int K = a.ell_K;
+    if (a.geo) {
+        // strip partition: only the phases with a strip kernel
+        switch (ph) {
+            case PH_E0: case PH_R0:
+                if (!do_r0) break;
+                PFE_LAUNCH_ST(k_st_res, K, grid, st, a, ph);
+                PFE_CHECK_HIP(hipGetLastError());
+                return PFE_OK;
+            case PH_W0: PFE_LAUNCH_ST(k_st_w0, K, grid, st, a); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
+            case PH_IT: PFE_LAUNCH_ST(k_st_it, K, grid, st, a); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
+            default: break;
+        }
+        set_error("phase %d has no strip kernel", ph);
+        return PFE_E_STATE;
+    }
     switch (ph) {
         case PH_E0: case PH_EU: case PH_R0: case PH_RHS: PFE_LAUNCH_KC(k_residual, K, grid, st, a, ph, do_r0); break;
         case PH_W0: PFE_LAUNCH_KC(k_cg_w0, K, grid, st, a); break;
@@ -2221,7 +2638,15 @@ pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0)
 constexpr int kCgChunk = 8;
 
 template <typename T>
-const void* kernel_for(int which, int ellK) {
+const void* kernel_for(int which, int ellK, bool strip) {
+    if (strip && which == PH_IT) {
+        switch (ellK) {
+            case 4: return reinterpret_cast<const void*>(&k_st_it<T, 4>);
+            case 8: return reinterpret_cast<const void*>(&k_st_it<T, 8>);
+            case 24: return reinterpret_cast<const void*>(&k_st_it<T, 24>);
+            default: return nullptr;
+        }
+    }
 #define PFE_KSEL(K) switch (ellK) { \
         case 4: return reinterpret_cast<const void*>(&K<T, 4>); \
         case 8: return reinterpret_cast<const void*>(&K<T, 8>); \
@@ -2256,6 +2681,7 @@ pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, hipGraphExec
     hipError_t e = hipSuccess;
     auto add = [&](const void* fn, void** kp) {
         if (e != hipSuccess) return;
+        if (!fn) { e = hipErrorInvalidDeviceFunction; return; }
         hipKernelNodeParams np{};
         np.func = const_cast<void*>(fn);
         np.gridDim = dim3(a.nblk);
@@ -2270,11 +2696,11 @@ pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, hipGraphExec
     const int K = a.ell_K;
     for (int k = 0; k < kCgChunk; ++k) {
         if (learned) {
-            add(kernel_for<T>(PH_LA, K), p1);
-            add(kernel_for<T>(PH_LC, K), p3);
-            add(kernel_for<T>(PH_LD, K), p2);
+            add(kernel_for<T>(PH_LA, K, false), p1);
+            add(kernel_for<T>(PH_LC, K, false), p3);
+            add(kernel_for<T>(PH_LD, K, false), p2);
         } else {
-            add(kernel_for<T>(PH_IT, K), p1);
+            add(kernel_for<T>(PH_IT, K, a.geo != nullptr), p1);
         }
     }
     hipGraphExec_t ex = nullptr;
@@ -2304,20 +2730,22 @@ pfe_status pcg_replay(pfe_ctx* c, const KA<T>& a, bool learned) {
 }
 
 // Multi-launch PCG after a residual phase (r0 in rb[0]); the host polls the
-// done flag every few iterations; the iterate ends in a.x.
+// done flag every few iterations; the iterate ends in a.x.  w0 and the
+// iterations run on the arguments 'as' (the strip partition of a pixel grid,
+// or 'a' itself).
 template <typename T>
-pfe_status pcg_loop_mk(pfe_ctx* c, const KA<T>& a) {
+pfe_status pcg_loop_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
     hipLaunchKernelGGL(k_stats_if_done<T>, dim3(1), dim3(64), 0, c->stream, a);
-    PFE_TRY(launch_phase(c, a, PH_W0, 0, 0));
+    PFE_TRY(launch_phase(c, as, PH_W0, 0, 0));
     if (c->prm.graphs) {
-        PFE_TRY(pcg_replay(c, a, false));
+        PFE_TRY(pcg_replay(c, as, false));
         return launch_phase(c, a, PH_ZERO, 0, 0);
     }
     int it = 0;
     const int chunk = 4;
     int done = 0;
     while (true) {
-        for (int k = 0; k < chunk; ++k) PFE_TRY(launch_phase(c, a, PH_IT, 0, 0));
+        for (int k = 0; k < chunk; ++k) PFE_TRY(launch_phase(c, as, PH_IT, 0, 0));
         it += chunk;
         PFE_CHECK_HIP(hipMemcpyAsync(&done, &c->S->done, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         PFE_CHECK_HIP(hipStreamSynchronize(c->stream));
@@ -2356,15 +2784,20 @@ pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a) {
 }
 
 template <typename T>
-pfe_status pcg_any_mk(pfe_ctx* c, const KA<T>& a) {
-    return (c->prm.precond == PFE_LEARNED) ? pcg_loop_learned_mk(c, a) : pcg_loop_mk(c, a);
+pfe_status pcg_any_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
+    return (c->prm.precond == PFE_LEARNED) ? pcg_loop_learned_mk(c, a) : pcg_loop_mk(c, a, as);
 }
+
+// the strip partition is used in the one-launch-per-phase path when the graph
+// has one and the context wants it
+inline bool use_strips(const pfe_ctx* c) { return c->want_strips && c->ps.nblk > 0; }
 
 template <typename T>
 pfe_status inner_mk(pfe_ctx* c) {
     KA<T> a = make_args<T>(c, c->pm);
-    PFE_TRY(launch_phase(c, a, (c->inner == 0) ? PH_E0 : PH_R0, 0, 1));
-    PFE_TRY(pcg_any_mk(c, a));
+    const KA<T> as = use_strips(c) ? make_args<T>(c, c->ps) : a;
+    PFE_TRY(launch_phase(c, as, (c->inner == 0) ? PH_E0 : PH_R0, 0, 1));
+    PFE_TRY(pcg_any_mk(c, a, as));
     // edge update of this inner step and rhs of the next one
     KA<T> b = a;
     b.store_rhs = 1;
@@ -2440,7 +2873,7 @@ pfe_status read_info(pfe_ctx* c, pfe_step_info* info) {
         info->status = h.status;
         info->fallbacks = h.fallbacks;
         info->workgroups = (c->prm.persistent && c->pc.nblk > 0) ? c->pc.nblk : 0;
-        info->flags = (c->launched_coop && c->cache_np > 0) ? 1 : 0;
+        info->flags = ((c->launched_coop && c->cache_np > 0) ? 1 : 0) | ((!c->launched_coop && use_strips(c)) ? 2 : 0);
     }
     if (h.status != 0) {
         set_error("%s", pfe_status_string((pfe_status)h.status));
@@ -2476,6 +2909,7 @@ void free_ctx(pfe_ctx* c) {
         if (p) (void)hipFree(p);
     free_partition(c->pm);
     free_partition(c->pc);
+    free_partition(c->ps);
     if (c->cg_exec) (void)hipGraphExecDestroy(c->cg_exec);
     c->cg_exec = nullptr;
 }
@@ -2731,8 +3165,24 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
     if (c->coop > want) c->coop = want;
     c->coop -= c->coop % kNumXcd;
     if (s == PFE_OK) s = setup_persistent(c);
+    if (const char* ev = getenv("PFE_STRIPS")) c->want_strips = atoi(ev) != 0;   // launch-shape experiments
+    if (s == PFE_OK) {
+        // strip partition: two waves of the co-resident strip workgroups
+        int occ_st = 0;
+        const void* kst = nullptr;
+        switch (g->ell_K) {
+            case 4: kst = (p->dtype == PFE_FP64) ? (const void*)&k_st_it<double, 4> : (const void*)&k_st_it<float, 4>; break;
+            case 8: kst = (p->dtype == PFE_FP64) ? (const void*)&k_st_it<double, 8> : (const void*)&k_st_it<float, 8>; break;
+            case 24: kst = (p->dtype == PFE_FP64) ? (const void*)&k_st_it<double, 24> : (const void*)&k_st_it<float, 24>; break;
+            default: break;
+        }
+        if (kst && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_st, kst, kBlock, 0) != hipSuccess) occ_st = 0;
+        int want_st = 2 * std::max(1, occ_st) * ncu;
+        if (const char* ev = getenv("PFE_STRIP_WG")) want_st = std::max(1, atoi(ev));   // launch-shape experiments
+        if (kst) s = make_strip_partition(g, (int)c->d, want_st, c->ps);
+    }
     if (s != PFE_OK) { free_ctx(c); delete c; return s; }
-    const int nblk_max = std::max(c->pm.nblk, c->pc.nblk);
+    const int nblk_max = std::max(std::max(c->pm.nblk, c->pc.nblk), c->ps.nblk);
     const int npair = (int)(c->d * (c->d + 1) / 2);
     const size_t part_doubles = (size_t)nblk_max * std::max<int64_t>(3 * c->d, 3 + 2 * npair) + 64;
     const size_t ncol = (size_t)c->nseg * c->d;
@@ -2876,9 +3326,9 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
     if (n_results) *n_results = 0;
     const bool f64 = c->prm.dtype == PFE_FP64;
     const size_t nd = (size_t)c->n * c->d * c->esz;
-    struct Shape { int persistent, team, cache; };
-    const Shape shapes[] = {{1, 64, 1}, {1, 64, 0}, {1, 1, 1}, {1, 1, 0}, {0, c->team, 0}};
-    const Shape orig{c->prm.persistent, c->team, c->want_cache};
+    struct Shape { int persistent, team, cache, strips; };
+    const Shape shapes[] = {{1, 64, 1, 0}, {1, 64, 0, 0}, {1, 1, 1, 0}, {1, 1, 0, 0}, {0, c->team, 0, 0}, {0, c->team, 0, 1}};
+    const Shape orig{c->prm.persistent, c->team, c->want_cache, c->want_strips};
     char* save = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     pfe_status st = PFE_OK;
@@ -2907,9 +3357,11 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
         for (int k = 0; k < (int)(sizeof(shapes) / sizeof(shapes[0])) && st == PFE_OK; ++k) {
             const Shape& sh = shapes[k];
             if (sh.persistent && (c->coop < kNumXcd || c->prm.precond != PFE_JACOBI)) continue;
+            if (sh.strips && c->ps.nblk == 0) continue;
             c->prm.persistent = sh.persistent;
             c->team = sh.team;
             c->want_cache = sh.cache;
+            c->want_strips = sh.strips;
             if (sh.persistent) {
                 if ((st = setup_persistent(c)) != PFE_OK) break;
                 if (c->pc.nblk == 0 || (sh.cache && c->cache_np == 0)) continue;
@@ -2932,7 +3384,8 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
             r.persistent = sh.persistent;
             r.team = sh.team;
             r.row_cache = sh.persistent ? (c->cache_np > 0) : 0;
-            r.workgroups = sh.persistent ? c->pc.nblk : 0;
+            r.strips = sh.strips;
+            r.workgroups = sh.persistent ? c->pc.nblk : (sh.strips ? c->ps.nblk : c->pm.nblk);
             r.ms = ms / trials;
             found.push_back(r);
             if (best < 0 || r.ms < best_ms) { best = (int)found.size() - 1; best_ms = r.ms; }
@@ -2943,11 +3396,13 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
         c->prm.persistent = found[best].persistent;
         c->team = found[best].persistent ? found[best].team : orig.team;
         c->want_cache = found[best].persistent ? found[best].row_cache : orig.cache;
+        c->want_strips = found[best].persistent ? orig.strips : found[best].strips;
         found[best].chosen = 1;
     } else {
         c->prm.persistent = orig.persistent;
         c->team = orig.team;
         c->want_cache = orig.cache;
+        c->want_strips = orig.strips;
     }
     pfe_status s2 = setup_persistent(c);
     if (st == PFE_OK) st = s2;
@@ -3079,14 +3534,20 @@ pfe_status pfe_pcg(pfe_ctx* c, const void* RHS, void* X, int32_t* iters, pfe_ste
         KA<double> a = make_args<double>(c, c->pm);
         a.x = (double*)X;
         a.rhs = (double*)RHS;
-        PFE_TRY(launch_phase(c, a, PH_R0, 0, 1));
-        PFE_TRY(pcg_any_mk(c, a));
+        KA<double> as = use_strips(c) ? make_args<double>(c, c->ps) : a;
+        as.x = a.x;
+        as.rhs = a.rhs;
+        PFE_TRY(launch_phase(c, as, PH_R0, 0, 1));
+        PFE_TRY(pcg_any_mk(c, a, as));
     } else {
         KA<float> a = make_args<float>(c, c->pm);
         a.x = (float*)X;
         a.rhs = (float*)RHS;
-        PFE_TRY(launch_phase(c, a, PH_R0, 0, 1));
-        PFE_TRY(pcg_any_mk(c, a));
+        KA<float> as = use_strips(c) ? make_args<float>(c, c->ps) : a;
+        as.x = a.x;
+        as.rhs = a.rhs;
+        PFE_TRY(launch_phase(c, as, PH_R0, 0, 1));
+        PFE_TRY(pcg_any_mk(c, a, as));
     }
     if (iters) {
         // per column, the largest count over the segments of a batch

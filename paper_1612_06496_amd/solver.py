@@ -154,8 +154,8 @@ class Solver:
         n = C.c_int()
         L.check(L.lib.pfe_autotune(self._h, int(trials), res, 8, C.byref(n)), "pfe_autotune",
                 allow=(L.PFE_E_NOCONV,))
-        return [dict(persistent=r.persistent, team=r.team, row_cache=r.row_cache, workgroups=r.workgroups,
-                     ms=r.ms, chosen=r.chosen) for r in res[:n.value]]
+        return [dict(persistent=r.persistent, team=r.team, row_cache=r.row_cache, strips=r.strips,
+                     workgroups=r.workgroups, ms=r.ms, chosen=r.chosen) for r in res[:n.value]]
 
     # -- state ---------------------------------------------------------------
     def get(self, which: str) -> torch.Tensor:
