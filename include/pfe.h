@@ -246,7 +246,8 @@ typedef struct {
     int32_t workgroups;      /* persistent launch: its workgroups; one launch per phase: the CG kernels' */
     double ms;               /* measured milliseconds per SOC iteration */
     int32_t chosen;          /* 1 for the shape kept */
-    int32_t strips;          /* one launch per phase on image strips */
+    int32_t strips;          /* one launch per phase on image strips sized for this many waves of
+                                co-resident workgroups (0: row chunks) */
 } pfe_tune_result;
 
 /* Autotune the launch shape on this context's graph: from the current state
@@ -254,7 +255,8 @@ typedef struct {
  * per candidate shape, restore the state after each, and keep the fastest for
  * later pfe_step / pfe_solve calls.  Candidates: persistent with teams of 64
  * or 1, each with and without the LDS row cache (when the rows fit), and one
- * launch per phase on row chunks and (pixel grids) on image strips.  results (host, may be null when max_results is 0)
+ * launch per phase on row chunks and (pixel grids) on image strips sized for
+ * one or two waves of co-resident workgroups.  results (host, may be null when max_results is 0)
  * receives up to max_results measured shapes, *n_results their number.
  * Allocates a temporary copy of Y, P, B.  PFE_E_STATE inside a SOC iteration. */
 pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int max_results, int* n_results);

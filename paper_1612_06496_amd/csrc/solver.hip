@@ -2314,7 +2314,11 @@ struct pfe_ctx {
     Partition pm;            // multi-launch partition
     Partition pc;            // persistent partition (pc.nblk == 0: not available)
     Partition ps;            // strip partition of pixel grids (ps.nblk == 0: not available)
-    int want_strips = 1;     // one-launch-per-phase: residual, w0 and CG kernels on strips
+    int want_strips = 2;     // one launch per phase: residual, w0 and CG kernels on image strips sized
+                             // for this many waves of co-resident strip workgroups (0: row chunks)
+    int strip_slots = 0;     // co-resident strip workgroups on the device (0: no strip kernel)
+    int ps_waves = 0;        // waves the strip partition was built for
+    int part_blocks = 0;     // workgroups the partial-sum buffer holds
     void* Y = nullptr; void* P = nullptr; void* B = nullptr;
     void* bs = nullptr; void* ds = nullptr;
     void* rhs = nullptr; void* p = nullptr;
@@ -2459,6 +2463,8 @@ constexpr int kStripMinRows = 16;
 
 pfe_status make_strip_partition(const pfe_graph* g, int d, int want_blocks, Partition& P) {
     free_partition(P);
+    int min_rows = kStripMinRows;
+    if (const char* ev = getenv("PFE_STRIP_MINROWS")) min_rows = std::max(1, atoi(ev));   // launch-shape experiments
     const int K = g->ell_K;
     const int nseg = (int)g->seg_row0.size() - 1;
     if (!g->stencil || !(K == 4 || K == 8 || K == 24) || (int)g->seg_W.size() != nseg) return PFE_OK;
@@ -2474,7 +2480,7 @@ pfe_status make_strip_partition(const pfe_graph* g, int d, int want_blocks, Part
         const int nsx = (W + L - 1) / L;
         const double ns = (double)W * H;
         int nsy = (int)std::llround((double)want_blocks * ns / (n * nsx));
-        nsy = std::min(nsy, std::max(1, H / kStripMinRows));
+        nsy = std::min(nsy, std::max(1, H / min_rows));
         nsy = std::max(1, std::min(nsy, H));
         sb0[s] = (int)bseg.size();
         for (int sy = 0; sy < nsy; ++sy) {
@@ -2790,7 +2796,23 @@ pfe_status pcg_any_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
 
 // the strip partition is used in the one-launch-per-phase path when the graph
 // has one and the context wants it
-inline bool use_strips(const pfe_ctx* c) { return c->want_strips && c->ps.nblk > 0; }
+inline bool use_strips(const pfe_ctx* c) { return c->want_strips > 0 && c->ps.nblk > 0; }
+
+// (re)build the strip partition for the wanted number of waves
+pfe_status setup_strips(pfe_ctx* c) {
+    if (c->want_strips <= 0 || c->strip_slots <= 0 || c->ps_waves == c->want_strips) return PFE_OK;
+    int want = c->want_strips * c->strip_slots;
+    if (const char* ev = getenv("PFE_STRIP_WG")) want = std::max(1, atoi(ev));   // launch-shape experiments
+    PFE_TRY(make_strip_partition(c->g, (int)c->d, want, c->ps));
+    c->ps_waves = c->want_strips;
+    if (c->part_blocks > 0 && c->ps.nblk > c->part_blocks) {
+        free_partition(c->ps);
+        c->ps_waves = 0;
+        set_error("strip partition of %d workgroups exceeds the partial-sum buffer", c->ps.nblk);
+        return PFE_E_STATE;
+    }
+    return PFE_OK;
+}
 
 template <typename T>
 pfe_status inner_mk(pfe_ctx* c) {
@@ -3165,9 +3187,10 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
     if (c->coop > want) c->coop = want;
     c->coop -= c->coop % kNumXcd;
     if (s == PFE_OK) s = setup_persistent(c);
-    if (const char* ev = getenv("PFE_STRIPS")) c->want_strips = atoi(ev) != 0;   // launch-shape experiments
+    if (const char* ev = getenv("PFE_STRIPS")) c->want_strips = std::max(0, atoi(ev));   // launch-shape experiments
     if (s == PFE_OK) {
-        // strip partition: two waves of the co-resident strip workgroups
+        // strip partition: built first for the most waves any later shape asks
+        // for (it has the most workgroups), then for the wanted count
         int occ_st = 0;
         const void* kst = nullptr;
         switch (g->ell_K) {
@@ -3177,12 +3200,17 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
             default: break;
         }
         if (kst && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_st, kst, kBlock, 0) != hipSuccess) occ_st = 0;
-        int want_st = 2 * std::max(1, occ_st) * ncu;
-        if (const char* ev = getenv("PFE_STRIP_WG")) want_st = std::max(1, atoi(ev));   // launch-shape experiments
-        if (kst) s = make_strip_partition(g, (int)c->d, want_st, c->ps);
+        c->strip_slots = kst ? std::max(1, occ_st) * ncu : 0;
+        const int want = c->want_strips;
+        c->want_strips = std::max(want, 2);
+        s = setup_strips(c);
+        c->want_strips = want;
     }
     if (s != PFE_OK) { free_ctx(c); delete c; return s; }
     const int nblk_max = std::max(std::max(c->pm.nblk, c->pc.nblk), c->ps.nblk);
+    c->part_blocks = nblk_max;
+    if (s == PFE_OK) s = setup_strips(c);
+    if (s != PFE_OK) { free_ctx(c); delete c; return s; }
     const int npair = (int)(c->d * (c->d + 1) / 2);
     const size_t part_doubles = (size_t)nblk_max * std::max<int64_t>(3 * c->d, 3 + 2 * npair) + 64;
     const size_t ncol = (size_t)c->nseg * c->d;
@@ -3327,7 +3355,8 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
     const bool f64 = c->prm.dtype == PFE_FP64;
     const size_t nd = (size_t)c->n * c->d * c->esz;
     struct Shape { int persistent, team, cache, strips; };
-    const Shape shapes[] = {{1, 64, 1, 0}, {1, 64, 0, 0}, {1, 1, 1, 0}, {1, 1, 0, 0}, {0, c->team, 0, 0}, {0, c->team, 0, 1}};
+    const Shape shapes[] = {{1, 64, 1, 0}, {1, 64, 0, 0}, {1, 1, 1, 0}, {1, 1, 0, 0}, {0, c->team, 0, 0},
+                            {0, c->team, 0, 1}, {0, c->team, 0, 2}};
     const Shape orig{c->prm.persistent, c->team, c->want_cache, c->want_strips};
     char* save = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -3357,11 +3386,13 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
         for (int k = 0; k < (int)(sizeof(shapes) / sizeof(shapes[0])) && st == PFE_OK; ++k) {
             const Shape& sh = shapes[k];
             if (sh.persistent && (c->coop < kNumXcd || c->prm.precond != PFE_JACOBI)) continue;
-            if (sh.strips && c->ps.nblk == 0) continue;
+            if (sh.strips && c->strip_slots == 0) continue;
             c->prm.persistent = sh.persistent;
             c->team = sh.team;
             c->want_cache = sh.cache;
             c->want_strips = sh.strips;
+            if ((st = setup_strips(c)) != PFE_OK) break;
+            if (sh.strips && c->ps.nblk == 0) continue;
             if (sh.persistent) {
                 if ((st = setup_persistent(c)) != PFE_OK) break;
                 if (c->pc.nblk == 0 || (sh.cache && c->cache_np == 0)) continue;
@@ -3405,6 +3436,7 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
         c->want_strips = orig.strips;
     }
     pfe_status s2 = setup_persistent(c);
+    if (s2 == PFE_OK) s2 = setup_strips(c);
     if (st == PFE_OK) st = s2;
     if (save && st == PFE_OK) st = restore();
     (void)hipStreamSynchronize(c->stream);
