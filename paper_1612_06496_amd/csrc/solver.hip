@@ -1182,6 +1182,87 @@ __device__ __forceinline__ void st_res(const KA<T>& a, int lb, int mode, double*
     block_partials<2>(acc, sh, d, kBlock / d, a.part, a.nblk, lb);
 }
 
+// Edge update (the PH_EU arithmetic without r0) over a strip: per slot
+// t = w (y_i - y_j) + b, d = Shrink(t, 1/lambda), b = t - d (Eqs. 9, 10), and
+// rhs = lambda/2 sum w (d - b) + r/2 D^{1/2} (P - B) (Eq. 13), stored.
+template <int KC, typename T>
+__device__ __forceinline__ void st_eu(const KA<T>& a, int lb, double* sh) {
+    using S = Sten<KC>;
+    constexpr int rho = S::rho;
+    constexpr bool PW = KC <= 8;   // slot weights and b loaded one image row ahead
+    const StripGeo g = strip_geo(a.geo, lb);
+    const int d = a.d, t = threadIdx.x;
+    const StripLane ln(g, d, rho);
+    T* ring = reinterpret_cast<T*>(sh);
+    const int ylo = max(0, g.y0 - rho), yhi = min(g.H, g.y1 + rho);
+    const int b_zero = a.b_zero;
+    auto ld = [&](int y) {
+        T v = T(0);
+        if (ln.in_image && y >= ylo && y < yhi) v = a.Y[(size_t)(g.row0 + y * g.W + ln.px) * d + ln.c];
+        return v;
+    };
+    struct Own { T split, ww[PW ? KC : 1], bo[PW ? KC : 1]; };
+    auto ldo = [&](int y) {
+        Own o{};
+        if (ln.owner && y < g.y1) {
+            const int i = g.row0 + y * g.W + ln.px;
+            const size_t e = (size_t)i * d + ln.c;
+            o.split = mul_t(a.half_r, mul_t(a.sqrtD[i], a.P[e] - a.B[e]));
+            if constexpr (PW) {
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    const size_t sl = (size_t)k * a.n + i;
+                    o.ww[k] = a.sw[sl];
+                    o.bo[k] = b_zero ? T(0) : a.bs[sl * d + ln.c];
+                }
+            }
+        }
+        return o;
+    };
+    if (g.len > 0 && g.y1 > g.y0) {
+        T raw[rho + 1];
+#pragma unroll
+        for (int k = 1; k <= rho; ++k)
+            if (ln.loader) ring[S::slot(g.y0 - k) * kBlock + t] = ld(g.y0 - k);
+#pragma unroll
+        for (int k = 0; k <= rho; ++k) raw[k] = ld(g.y0 + k);
+#pragma unroll
+        for (int k = 0; k < rho; ++k)
+            if (ln.loader) ring[S::slot(g.y0 + k) * kBlock + t] = raw[k];
+        Own own = ldo(g.y0);
+        for (int y = g.y0; y < g.y1; ++y) {
+            if (ln.loader) ring[S::slot(y + rho) * kBlock + t] = raw[rho];
+            const T rnext = ld(y + rho + 1);
+            const Own onext = ldo(y + 1);
+            __syncthreads();
+            if (ln.owner) {
+                const int i = g.row0 + y * g.W + ln.px;
+                const size_t e = (size_t)i * d + ln.c;
+                const T yi = raw[0];
+                T accR = T(0);
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    const size_t sl = (size_t)k * a.n + i;
+                    const T wk = PW ? own.ww[PW ? k : 0] : a.sw[sl];
+                    const T bo = PW ? own.bo[PW ? k : 0] : (b_zero ? T(0) : a.bs[sl * d + ln.c]);
+                    const T yj = ring[S::slot(y + S::dy(k)) * kBlock + t + S::dx(k) * d];
+                    const T tv = fma_t(wk, yi - yj, bo);
+                    const T dv = shrink(tv, a.gamma);
+                    const T bn = tv - dv;
+                    a.bs[sl * d + ln.c] = bn;
+                    if (a.keep_split) a.ds[sl * d + ln.c] = dv;
+                    accR = fma_t(wk, dv - bn, accR);
+                }
+                a.rhs[e] = fma_t(a.c_off, accR, own.split);
+            }
+#pragma unroll
+            for (int k = 0; k < rho; ++k) raw[k] = raw[k + 1];
+            raw[rho] = rnext;
+            own = onext;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Finalisers (one workgroup, after every workgroup has written its partials).
 // 'grouped' means the per-XCD-group partials are already summed (one segment).
@@ -1889,6 +1970,12 @@ __global__ void __launch_bounds__(kBlock) k_st_it(KA<T> a) {
         fin_it(a, sh, false);
         if (threadIdx.x == 0 && a.S->done) solve_stats(a);
     }
+}
+
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_st_eu(KA<T> a) {
+    __shared__ double sh[kSmemDoubles];
+    st_eu<KC>(a, logical_block(a.nblk), sh);
 }
 
 template <typename T>
@@ -2613,6 +2700,11 @@ pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0)
                 PFE_LAUNCH_ST(k_st_res, K, grid, st, a, ph);
                 PFE_CHECK_HIP(hipGetLastError());
                 return PFE_OK;
+            case PH_EU:
+                if (do_r0 || !a.store_rhs) break;
+                PFE_LAUNCH_ST(k_st_eu, K, grid, st, a);
+                PFE_CHECK_HIP(hipGetLastError());
+                return PFE_OK;
             case PH_W0: PFE_LAUNCH_ST(k_st_w0, K, grid, st, a); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
             case PH_IT: PFE_LAUNCH_ST(k_st_it, K, grid, st, a); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
             default: break;
@@ -2820,8 +2912,9 @@ pfe_status inner_mk(pfe_ctx* c) {
     const KA<T> as = use_strips(c) ? make_args<T>(c, c->ps) : a;
     PFE_TRY(launch_phase(c, as, (c->inner == 0) ? PH_E0 : PH_R0, 0, 1));
     PFE_TRY(pcg_any_mk(c, a, as));
-    // edge update of this inner step and rhs of the next one
-    KA<T> b = a;
+    // edge update of this inner step and rhs of the next one (on strips when
+    // the slot data are loaded one image row ahead, widths up to 8)
+    KA<T> b = (as.geo && c->g->ell_K <= 8) ? as : a;
     b.store_rhs = 1;
     b.b_zero = (c->inner == 0);
     PFE_TRY(launch_phase(c, b, PH_EU, 0, 0));
