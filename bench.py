@@ -41,26 +41,32 @@ def algorithmic_bytes(n, E, d, esz, cg_iters, solves, n_inner, n_outer):
 
 
 # committed rocprofv3 traffic summaries of the persistent kernel, per workload
-TRAFFIC_FILES = {"voronoi481x321_8nbr": "k_soc_voronoi481x321_traffic.json",
-                 "voronoi_batch64_8nbr": "k_soc_voronoi_batch64_traffic.json"}
+# committed rocprofv3 FETCH_SIZE / WRITE_SIZE records: (workload, launch) ->
+# file; persistent records count one k_soc launch, strip records one SOC
+# iteration of the one-launch-per-phase path on image strips
+TRAFFIC_FILES = {("voronoi481x321_8nbr", "persistent"): "k_soc_voronoi481x321_traffic.json",
+                 ("voronoi_batch64_8nbr", "strips"): "strips_voronoi_batch64_traffic.json",
+                 ("voronoi1024_r2", "strips"): "strips_voronoi1024_r2_traffic.json"}
 
 
-def measured_traffic(workload):
-    """HBM traffic per k_soc launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs (scaled by the copy-kernel calibration), or None when there
-    is none for the workload or the kernel source changed since the counters
-    were taken."""
+def measured_traffic(workload, launch):
+    """HBM traffic per SOC iteration from the committed counter runs (scaled by
+    the copy-kernel calibration), or None when there is none for the workload
+    and launch shape or the kernel source changed since the counters were
+    taken."""
     import hashlib
-    if workload not in TRAFFIC_FILES:
+    if (workload, launch) not in TRAFFIC_FILES:
         return None
-    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES[workload])
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES[(workload, launch)])
     src = os.path.join(ROOT, "paper_1612_06496_amd", "csrc", "solver.hip")
     try:
         rec = json.load(open(path))
         cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
-    return rec["traffic_bytes_per_launch"] if rec.get("solver_sha256") == cur else None
+    if rec.get("solver_sha256") != cur:
+        return None
+    return rec.get("traffic_bytes_per_launch", rec.get("traffic_bytes_per_soc"))
 
 
 def copy_bandwidth(gib):
@@ -93,10 +99,11 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
 
     Training data: residuals of PFE inner solves on held-out images (training
     seeds) at every lambda/r of the sweep.  Evaluation on the evaluation image
-    (seed 0): n_outer SOC iterations (n_outer x n_inner solves) from the same
-    start with each preconditioner, each in its fastest launch mode (Jacobi:
-    one persistent launch per SOC iteration; learned: one launch per phase with
-    the PCG replayed from HIP graphs); the network's factor inference is timed
+    (seed 0): from the same start, one untimed SOC iteration, then n_outer
+    timed ones (n_outer x n_inner solves) with each preconditioner in its
+    fastest launch mode (Jacobi: the autotuned shape, persistent or one launch
+    per phase on image strips; learned: one launch per phase with the PCG
+    replayed from HIP graphs); the network's factor inference is timed
     separately (once per graph and penalties)."""
     import numpy as np
     import torch
@@ -143,12 +150,17 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
             S = Solver(G, wl.y0, lam=ratio * c, r=c, n_inner=wl.n_inner, tol=wl.tol, maxit=5000,
                        persistent=(pre == "jacobi"), graphs=True)
             factor_ms = None
+            shape = None
             if pre == "learned":
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 S.set_learned(net)
                 torch.cuda.synchronize()
                 factor_ms = round((time.perf_counter() - t0) * 1e3, 2)
+            else:
+                shape = [t for t in S.autotune(trials=1) if t["chosen"]][0]
+            S.solve(1, allow_noconv=True)
+            S.stats(reset=True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             info = S.solve(n_outer, info=True, allow_noconv=True)
@@ -158,6 +170,9 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
                         "iters_max": info["cg_iters_max"], "solves": info["solves"],
                         "ms_per_solve": round(dt * 1e3 / max(1, info["solves"]), 3),
                         "rel_res_max": float(f"{info['rel_res_max']:.3g}"), "status": info["status"]}
+            if shape is not None:
+                res[pre]["launch"] = ("persistent" if shape["persistent"] else
+                                      "strips" if shape["strips"] else "one launch per phase")
             if factor_ms is not None:
                 res[pre]["factor_ms"] = factor_ms
                 res[pre]["ms_per_solve_amortised"] = round(res[pre]["ms_per_solve"] + factor_ms / max(1, info["solves"]), 3)
@@ -213,8 +228,10 @@ def main():
     ap.add_argument("--copy-gib", type=float, default=2.0, help="size of the copy-bandwidth probe")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-Jacobi PCG comparison")
     ap.add_argument("--multi-launch", action="store_true", help="one launch per phase instead of one per SOC iteration")
-    ap.add_argument("--graphs", action="store_true", help="replay one-launch-per-phase PCG from HIP graphs")
-    ap.add_argument("--autotune", action="store_true", help="autotune the launch shape before timing")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="one-launch-per-phase PCG launched from the host instead of replayed from HIP graphs")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shape instead of autotuning it before timing")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="a single-image workload or an image batch (block-diagonal union) from synth")
     args = ap.parse_args()
@@ -242,11 +259,13 @@ def main():
         Y0 = wls[0].y0
     wl = wls[0]
     S = Solver(G, Y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=1000,
-               persistent=not args.multi_launch, graphs=args.graphs)
+               persistent=not args.multi_launch, graphs=not args.no_graphs)
     # shrink-active penalties: threshold 1/c at the 0.99-quantile of |M Y0|
     c = 1.0 / S.edge_quantile(0.99)
     S.set_penalties(c, c)
-    tuned = S.autotune(trials=2) if args.autotune else None
+    # the launch shape (persistent or one launch per phase, teams, LDS row
+    # cache, image strips) is picked by timing each on this graph; untimed
+    tuned = None if args.no_autotune else S.autotune(trials=2)
 
     for _ in range(args.warmup):
         S.solve(1)
@@ -270,9 +289,11 @@ def main():
     n, E, d = G.n, G.n_edges, wl.d
     byt = algorithmic_bytes(n, E, d, 4, info["cg_iters_total"], info["solves"], wl.n_inner, args.steps)
     achieved = byt / (ms / 1e3) / 1e9
+    launch = "persistent" if info["workgroups"] else ("strips" if info["flags"] & 2 else "multi")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.workload) if info["workgroups"] else None,
-            "kernel": "k_soc (one SOC iteration per launch)" if info["workgroups"] else "one kernel per phase",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.workload, launch),
+            "kernel": "k_soc (one SOC iteration per launch)" if info["workgroups"] else
+                      "one kernel per phase (bytes and time per SOC iteration)",
             "bytes_per_launch": int(byt / args.steps), "workgroups": info["workgroups"],
             "launch_flags": info["flags"]}
     default = args.workload == WORKLOAD
@@ -285,11 +306,11 @@ def main():
         "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": args.workload, "graphs": len(wls), "n": n, "edges": E, "d": d,
+        "config": {"workload": args.workload, "images": len(wls), "n": n, "edges": E, "d": d,
                    "n_inner": wl.n_inner,
                    "tol": wl.tol, "lambda": c, "r": c, "precond": "jacobi",
-                   "launch": "persistent" if info["workgroups"] else "multi",
-                   "graphs": bool(args.graphs),
+                   "launch": launch,
+                   "graphs": not args.no_graphs,
                    "autotuned": ([t for t in tuned if t["chosen"]] or [None])[0] if tuned else None},
         "pcg_iters_per_solve": round(info["cg_iters_total"] / max(1, info["solves"]), 2),
         "pcg_iters_learned": None,     # filled by the learned-vs-Jacobi leg below
