@@ -950,16 +950,78 @@ struct StripLane {
     }
 };
 
+// Walk the strip of workgroup lb one image row at a time.
+//   ld(j, e)    this lane's raw values of pixel j (element e = j d + c), loaded
+//               one image row ahead; value-initialised (zero) outside the image
+//               and outside the rows the strip reads
+//   val(raw)    the value the lane publishes into the ring for its pixel
+//   ldo(i, e)   an owner's further values of its pixel i, loaded one row ahead
+//   body(i, e, raw, own, nb)  the arithmetic of owned pixel i, with nb(k) the
+//               ring value of ELL slot k (zero outside the image)
+// Ends with a workgroup barrier (the ring shares sh with the partial sums).
+template <int KC, typename T, class LD, class VAL, class LDO, class BODY>
+__device__ __forceinline__ void strip_walk(const KA<T>& a, const StripGeo& g, const StripLane& ln, T* ring, LD&& ld,
+                                           VAL&& val, LDO&& ldo, BODY&& body) {
+    using S = Sten<KC>;
+    constexpr int rho = S::rho;
+    const int d = a.d, t = threadIdx.x;
+    using Raw = decltype(ld(0, size_t(0)));
+    using Own = decltype(ldo(0, size_t(0)));
+    const int ylo = max(0, g.y0 - rho), yhi = min(g.H, g.y1 + rho);
+    auto ldr = [&](int y) {
+        Raw v{};
+        if (ln.in_image && y >= ylo && y < yhi) {
+            const int j = g.row0 + y * g.W + ln.px;
+            v = ld(j, (size_t)j * d + ln.c);
+        }
+        return v;
+    };
+    auto ldw = [&](int y) {
+        Own o{};
+        if (ln.owner && y < g.y1) {
+            const int i = g.row0 + y * g.W + ln.px;
+            o = ldo(i, (size_t)i * d + ln.c);
+        }
+        return o;
+    };
+    if (g.len > 0 && g.y1 > g.y0) {
+        Raw raw[rho + 1];   // image rows y .. y + rho of this lane
+#pragma unroll
+        for (int k = 1; k <= rho; ++k)
+            if (ln.loader) ring[S::slot(g.y0 - k) * kBlock + t] = val(ldr(g.y0 - k));
+#pragma unroll
+        for (int k = 0; k <= rho; ++k) raw[k] = ldr(g.y0 + k);
+#pragma unroll
+        for (int k = 0; k < rho; ++k)
+            if (ln.loader) ring[S::slot(g.y0 + k) * kBlock + t] = val(raw[k]);
+        Own own = ldw(g.y0);
+        for (int y = g.y0; y < g.y1; ++y) {
+            if (ln.loader) ring[S::slot(y + rho) * kBlock + t] = val(raw[rho]);
+            const Raw rnext = ldr(y + rho + 1);
+            const Own onext = ldw(y + 1);
+            __syncthreads();
+            if (ln.owner) {
+                const int i = g.row0 + y * g.W + ln.px;
+                auto nb = [&](int k) { return ring[S::slot(y + S::dy(k)) * kBlock + t + S::dx(k) * d]; };
+                body(i, (size_t)i * d + ln.c, raw[0], own, nb);
+            }
+#pragma unroll
+            for (int k = 0; k < rho; ++k) raw[k] = raw[k + 1];
+            raw[rho] = rnext;
+            own = onext;
+        }
+    }
+    __syncthreads();
+}
+
 // CG iteration (the PH_IT arithmetic) over a strip
 template <int KC, typename T>
 __device__ __forceinline__ void st_it(const KA<T>& a, int lb, double* sh, int it, const double* alphas,
                                       const double* betas) {
-    using S = Sten<KC>;
-    constexpr int rho = S::rho;
     constexpr bool PW = KC <= 8;   // slot weights loaded one image row ahead with the rest
     const StripGeo g = strip_geo(a.geo, lb);
-    const int d = a.d, t = threadIdx.x;
-    const StripLane ln(g, d, rho);
+    const int d = a.d;
+    const StripLane ln(g, d, Sten<KC>::rho);
     const bool first = (it == 0);
     const int cur = it & 1, nxt = cur ^ 1;
     const T* r = a.rb[cur];
@@ -971,27 +1033,15 @@ __device__ __forceinline__ void st_it(const KA<T>& a, int lb, double* sh, int it
     const int ci = a.blk_seg[lb] * d + ln.c;
     const T alpha = (T)alphas[ci];
     const T beta = (T)betas[ci];
-    T* ring = reinterpret_cast<T*>(sh);
-    const int ylo = max(0, g.y0 - rho), yhi = min(g.H, g.y1 + rho);
     struct Raw { T r, w, sp, inv; };
     struct Own { T p, x, dA, ww[PW ? KC : 1]; };
-    auto ld = [&](int y) {
-        Raw v{T(0), T(0), T(0), T(0)};
-        if (ln.in_image && y >= ylo && y < yhi) {
-            const int j = g.row0 + y * g.W + ln.px;
-            const size_t e = (size_t)j * d + ln.c;
-            v.r = r[e];
-            v.w = w[e];
-            v.sp = sp[e];
-            v.inv = a.invdiag[j];
-        }
-        return v;
-    };
-    auto ldo = [&](int y) {
-        Own o{};
-        if (ln.owner && y < g.y1) {
-            const int i = g.row0 + y * g.W + ln.px;
-            const size_t e = (size_t)i * d + ln.c;
+    double acc[3] = {0.0, 0.0, 0.0};
+    strip_walk<KC>(a, g, ln, reinterpret_cast<T*>(sh),
+        [&](int j, size_t e) { return Raw{r[e], w[e], sp[e], a.invdiag[j]}; },
+        // u_j = diag(A)^{-1} r_{j, i+1}: the neighbours' new u, as their owners form it
+        [&](const Raw& v) { return mul_t(v.inv, cg_r(alpha, cg_s(first, beta, v.sp, v.w), v.r)); },
+        [&](int i, size_t e) {
+            Own o{};
             o.p = a.p[e];
             o.x = a.x[e];
             o.dA = a.diagA[i];
@@ -999,122 +1049,61 @@ __device__ __forceinline__ void st_it(const KA<T>& a, int lb, double* sh, int it
 #pragma unroll
                 for (int k = 0; k < KC; ++k) o.ww[k] = a.sw[(size_t)k * a.n + i];
             }
-        }
-        return o;
-    };
-    // u_j = diag(A)^{-1} r_{j, i+1}: the neighbours' new u, as their owners form it
-    auto u_of = [&](const Raw& v) { return mul_t(v.inv, cg_r(alpha, cg_s(first, beta, v.sp, v.w), v.r)); };
-    double acc[3] = {0.0, 0.0, 0.0};
-    if (g.len > 0 && g.y1 > g.y0) {
-        Raw raw[rho + 1];   // image rows y .. y + rho of this lane
+            return o;
+        },
+        [&](int i, size_t e, const Raw& v, const Own& own, auto&& nb) {
+            const T ui = mul_t(v.inv, v.r);
+            const T pi = first ? ui : fma_t(beta, own.p, ui);
+            const T si = cg_s(first, beta, v.sp, v.w);
+            const T rn_i = cg_r(alpha, si, v.r);
+            const T un_i = mul_t(v.inv, rn_i);
+            T accA = T(0);
 #pragma unroll
-        for (int k = 1; k <= rho; ++k)
-            if (ln.loader) ring[S::slot(g.y0 - k) * kBlock + t] = u_of(ld(g.y0 - k));
-#pragma unroll
-        for (int k = 0; k <= rho; ++k) raw[k] = ld(g.y0 + k);
-#pragma unroll
-        for (int k = 0; k < rho; ++k)
-            if (ln.loader) ring[S::slot(g.y0 + k) * kBlock + t] = u_of(raw[k]);
-        Own own = ldo(g.y0);
-        for (int y = g.y0; y < g.y1; ++y) {
-            if (ln.loader) ring[S::slot(y + rho) * kBlock + t] = u_of(raw[rho]);
-            const Raw rnext = ld(y + rho + 1);
-            const Own onext = ldo(y + 1);
-            __syncthreads();
-            if (ln.owner) {
-                const int i = g.row0 + y * g.W + ln.px;
-                const size_t e = (size_t)i * d + ln.c;
-                const Raw& v = raw[0];
-                const T ui = mul_t(v.inv, v.r);
-                const T pi = first ? ui : fma_t(beta, own.p, ui);
-                const T si = cg_s(first, beta, v.sp, v.w);
-                const T rn_i = cg_r(alpha, si, v.r);
-                const T un_i = mul_t(v.inv, rn_i);
-                T accA = T(0);
-#pragma unroll
-                for (int k = 0; k < KC; ++k) {
-                    const T wk = PW ? own.ww[PW ? k : 0] : a.sw[(size_t)k * a.n + i];
-                    accA = fma_t(mul_t(wk, wk), ring[S::slot(y + S::dy(k)) * kBlock + t + S::dx(k) * d], accA);
-                }
-                const T wn_i = fma_t(own.dA, un_i, -mul_t(a.c_off, accA));
-                a.p[e] = pi;
-                sn[e] = si;
-                a.x[e] = fma_t(alpha, pi, own.x);
-                rn[e] = rn_i;
-                wn[e] = wn_i;
-                acc[0] += (double)rn_i * (double)un_i;
-                acc[1] += (double)wn_i * (double)un_i;
-                acc[2] += (double)rn_i * (double)rn_i;
+            for (int k = 0; k < KC; ++k) {
+                const T wk = PW ? own.ww[PW ? k : 0] : a.sw[(size_t)k * a.n + i];
+                accA = fma_t(mul_t(wk, wk), nb(k), accA);
             }
-#pragma unroll
-            for (int k = 0; k < rho; ++k) raw[k] = raw[k + 1];
-            raw[rho] = rnext;
-            own = onext;
-        }
-    }
-    __syncthreads();   // the ring shares sh with the partial sums
+            const T wn_i = fma_t(own.dA, un_i, -mul_t(a.c_off, accA));
+            a.p[e] = pi;
+            sn[e] = si;
+            a.x[e] = fma_t(alpha, pi, own.x);
+            rn[e] = rn_i;
+            wn[e] = wn_i;
+            acc[0] += (double)rn_i * (double)un_i;
+            acc[1] += (double)wn_i * (double)un_i;
+            acc[2] += (double)rn_i * (double)rn_i;
+        });
     block_partials<3>(acc, sh, d, kBlock / d, a.part, a.nblk, lb);
 }
 
 // w0 = A u0 with u0 = r0 / diag(A) (the PH_W0 arithmetic) over a strip
 template <int KC, typename T>
 __device__ __forceinline__ void st_w0(const KA<T>& a, int lb, double* sh) {
-    using S = Sten<KC>;
-    constexpr int rho = S::rho;
     const StripGeo g = strip_geo(a.geo, lb);
-    const int d = a.d, t = threadIdx.x;
-    const StripLane ln(g, d, rho);
+    const int d = a.d;
+    const StripLane ln(g, d, Sten<KC>::rho);
     const T* r = a.rb[0];
     T* w = a.wb[0];
-    T* ring = reinterpret_cast<T*>(sh);
-    const int ylo = max(0, g.y0 - rho), yhi = min(g.H, g.y1 + rho);
     struct Raw { T r, inv; };
-    auto ld = [&](int y) {
-        Raw v{T(0), T(0)};
-        if (ln.in_image && y >= ylo && y < yhi) {
-            const int j = g.row0 + y * g.W + ln.px;
-            v.r = r[(size_t)j * d + ln.c];
-            v.inv = a.invdiag[j];
-        }
-        return v;
-    };
+    struct Own { T dA; };
     double acc[2] = {0.0, 0.0};
-    if (g.len > 0 && g.y1 > g.y0) {
-        Raw raw[rho + 1];
+    strip_walk<KC>(a, g, ln, reinterpret_cast<T*>(sh),
+        [&](int j, size_t e) { return Raw{r[e], a.invdiag[j]}; },
+        [&](const Raw& v) { return mul_t(v.inv, v.r); },
+        [&](int i, size_t) { return Own{a.diagA[i]}; },
+        [&](int i, size_t e, const Raw& v, const Own& own, auto&& nb) {
+            const T ui = mul_t(v.inv, v.r);
+            T accA = T(0);
 #pragma unroll
-        for (int k = 1; k <= rho; ++k)
-            if (ln.loader) { const Raw v = ld(g.y0 - k); ring[S::slot(g.y0 - k) * kBlock + t] = mul_t(v.inv, v.r); }
-#pragma unroll
-        for (int k = 0; k <= rho; ++k) raw[k] = ld(g.y0 + k);
-#pragma unroll
-        for (int k = 0; k < rho; ++k)
-            if (ln.loader) ring[S::slot(g.y0 + k) * kBlock + t] = mul_t(raw[k].inv, raw[k].r);
-        for (int y = g.y0; y < g.y1; ++y) {
-            if (ln.loader) ring[S::slot(y + rho) * kBlock + t] = mul_t(raw[rho].inv, raw[rho].r);
-            const Raw rnext = ld(y + rho + 1);
-            __syncthreads();
-            if (ln.owner) {
-                const int i = g.row0 + y * g.W + ln.px;
-                const size_t e = (size_t)i * d + ln.c;
-                const T ri = raw[0].r;
-                const T ui = mul_t(raw[0].inv, ri);
-                T accA = T(0);
-#pragma unroll
-                for (int k = 0; k < KC; ++k) {
-                    const T wk = a.sw[(size_t)k * a.n + i];
-                    accA = fma_t(mul_t(wk, wk), ring[S::slot(y + S::dy(k)) * kBlock + t + S::dx(k) * d], accA);
-                }
-                const T wi = fma_t(a.diagA[i], ui, -mul_t(a.c_off, accA));
-                w[e] = wi;
-                acc[0] += (double)ri * (double)ui;
-                acc[1] += (double)wi * (double)ui;
+            for (int k = 0; k < KC; ++k) {
+                const T wk = a.sw[(size_t)k * a.n + i];
+                accA = fma_t(mul_t(wk, wk), nb(k), accA);
             }
-#pragma unroll
-            for (int k = 0; k < rho; ++k) raw[k] = raw[k + 1];
-            raw[rho] = rnext;
-        }
-    }
-    __syncthreads();
+            const T wi = fma_t(own.dA, ui, -mul_t(a.c_off, accA));
+            w[e] = wi;
+            acc[0] += (double)v.r * (double)ui;
+            acc[1] += (double)wi * (double)ui;
+        });
     block_partials<2>(acc, sh, d, kBlock / d, a.part, a.nblk, lb);
 }
 
@@ -1122,63 +1111,36 @@ __device__ __forceinline__ void st_w0(const KA<T>& a, int lb, double* sh) {
 // a strip, with the partials of rhs.rhs and r0.r0 (the ph_residual arithmetic)
 template <int KC, typename T>
 __device__ __forceinline__ void st_res(const KA<T>& a, int lb, int mode, double* sh) {
-    using S = Sten<KC>;
-    constexpr int rho = S::rho;
     const StripGeo g = strip_geo(a.geo, lb);
-    const int d = a.d, t = threadIdx.x;
-    const StripLane ln(g, d, rho);
+    const int d = a.d;
+    const StripLane ln(g, d, Sten<KC>::rho);
     T* r0 = a.rb[0];
-    T* ring = reinterpret_cast<T*>(sh);
-    const int ylo = max(0, g.y0 - rho), yhi = min(g.H, g.y1 + rho);
-    auto ld = [&](int y) {
-        T v = T(0);
-        if (ln.in_image && y >= ylo && y < yhi) v = a.x[(size_t)(g.row0 + y * g.W + ln.px) * d + ln.c];
-        return v;
-    };
+    struct Raw { T x; };
+    struct Own { T rhs, dA; };
     double acc[2] = {0.0, 0.0};
-    if (g.len > 0 && g.y1 > g.y0) {
-        T raw[rho + 1];
+    strip_walk<KC>(a, g, ln, reinterpret_cast<T*>(sh),
+        [&](int, size_t e) { return Raw{a.x[e]}; },
+        [&](const Raw& v) { return v.x; },
+        [&](int i, size_t e) {
+            Own o{};
+            o.rhs = (mode == PH_R0) ? a.rhs[e] : mul_t(a.half_r, mul_t(a.sqrtD[i], a.P[e] - a.B[e]));
+            o.dA = a.diagA[i];
+            return o;
+        },
+        [&](int i, size_t e, const Raw& v, const Own& own, auto&& nb) {
+            T accA = T(0);
 #pragma unroll
-        for (int k = 1; k <= rho; ++k)
-            if (ln.loader) ring[S::slot(g.y0 - k) * kBlock + t] = ld(g.y0 - k);
-#pragma unroll
-        for (int k = 0; k <= rho; ++k) raw[k] = ld(g.y0 + k);
-#pragma unroll
-        for (int k = 0; k < rho; ++k)
-            if (ln.loader) ring[S::slot(g.y0 + k) * kBlock + t] = raw[k];
-        for (int y = g.y0; y < g.y1; ++y) {
-            if (ln.loader) ring[S::slot(y + rho) * kBlock + t] = raw[rho];
-            const T rnext = ld(y + rho + 1);
-            __syncthreads();
-            if (ln.owner) {
-                const int i = g.row0 + y * g.W + ln.px;
-                const size_t e = (size_t)i * d + ln.c;
-                const T xi = raw[0];
-                T accA = T(0);
-#pragma unroll
-                for (int k = 0; k < KC; ++k) {
-                    const T wk = a.sw[(size_t)k * a.n + i];
-                    accA = fma_t(mul_t(wk, wk), ring[S::slot(y + S::dy(k)) * kBlock + t + S::dx(k) * d], accA);
-                }
-                T rhs;
-                if (mode == PH_R0) {
-                    rhs = a.rhs[e];
-                } else {
-                    rhs = mul_t(a.half_r, mul_t(a.sqrtD[i], a.P[e] - a.B[e]));
-                    if (a.store_rhs) a.rhs[e] = rhs;
-                }
-                const T ax = fma_t(a.diagA[i], xi, -mul_t(a.c_off, accA));
-                const T rv = rhs - ax;
-                r0[e] = rv;
-                acc[0] += (double)rhs * (double)rhs;
-                acc[1] += (double)rv * (double)rv;
+            for (int k = 0; k < KC; ++k) {
+                const T wk = a.sw[(size_t)k * a.n + i];
+                accA = fma_t(mul_t(wk, wk), nb(k), accA);
             }
-#pragma unroll
-            for (int k = 0; k < rho; ++k) raw[k] = raw[k + 1];
-            raw[rho] = rnext;
-        }
-    }
-    __syncthreads();
+            if (mode != PH_R0 && a.store_rhs) a.rhs[e] = own.rhs;
+            const T ax = fma_t(own.dA, v.x, -mul_t(a.c_off, accA));
+            const T rv = own.rhs - ax;
+            r0[e] = rv;
+            acc[0] += (double)own.rhs * (double)own.rhs;
+            acc[1] += (double)rv * (double)rv;
+        });
     block_partials<2>(acc, sh, d, kBlock / d, a.part, a.nblk, lb);
 }
 
@@ -1187,26 +1149,18 @@ __device__ __forceinline__ void st_res(const KA<T>& a, int lb, int mode, double*
 // rhs = lambda/2 sum w (d - b) + r/2 D^{1/2} (P - B) (Eq. 13), stored.
 template <int KC, typename T>
 __device__ __forceinline__ void st_eu(const KA<T>& a, int lb, double* sh) {
-    using S = Sten<KC>;
-    constexpr int rho = S::rho;
     constexpr bool PW = KC <= 8;   // slot weights and b loaded one image row ahead
     const StripGeo g = strip_geo(a.geo, lb);
-    const int d = a.d, t = threadIdx.x;
-    const StripLane ln(g, d, rho);
-    T* ring = reinterpret_cast<T*>(sh);
-    const int ylo = max(0, g.y0 - rho), yhi = min(g.H, g.y1 + rho);
+    const int d = a.d;
+    const StripLane ln(g, d, Sten<KC>::rho);
     const int b_zero = a.b_zero;
-    auto ld = [&](int y) {
-        T v = T(0);
-        if (ln.in_image && y >= ylo && y < yhi) v = a.Y[(size_t)(g.row0 + y * g.W + ln.px) * d + ln.c];
-        return v;
-    };
+    struct Raw { T y; };
     struct Own { T split, ww[PW ? KC : 1], bo[PW ? KC : 1]; };
-    auto ldo = [&](int y) {
-        Own o{};
-        if (ln.owner && y < g.y1) {
-            const int i = g.row0 + y * g.W + ln.px;
-            const size_t e = (size_t)i * d + ln.c;
+    strip_walk<KC>(a, g, ln, reinterpret_cast<T*>(sh),
+        [&](int, size_t e) { return Raw{a.Y[e]}; },
+        [&](const Raw& v) { return v.y; },
+        [&](int i, size_t e) {
+            Own o{};
             o.split = mul_t(a.half_r, mul_t(a.sqrtD[i], a.P[e] - a.B[e]));
             if constexpr (PW) {
 #pragma unroll
@@ -1216,51 +1170,150 @@ __device__ __forceinline__ void st_eu(const KA<T>& a, int lb, double* sh) {
                     o.bo[k] = b_zero ? T(0) : a.bs[sl * d + ln.c];
                 }
             }
-        }
-        return o;
-    };
-    if (g.len > 0 && g.y1 > g.y0) {
-        T raw[rho + 1];
+            return o;
+        },
+        [&](int i, size_t e, const Raw& v, const Own& own, auto&& nb) {
+            T accR = T(0);
 #pragma unroll
-        for (int k = 1; k <= rho; ++k)
-            if (ln.loader) ring[S::slot(g.y0 - k) * kBlock + t] = ld(g.y0 - k);
-#pragma unroll
-        for (int k = 0; k <= rho; ++k) raw[k] = ld(g.y0 + k);
-#pragma unroll
-        for (int k = 0; k < rho; ++k)
-            if (ln.loader) ring[S::slot(g.y0 + k) * kBlock + t] = raw[k];
-        Own own = ldo(g.y0);
-        for (int y = g.y0; y < g.y1; ++y) {
-            if (ln.loader) ring[S::slot(y + rho) * kBlock + t] = raw[rho];
-            const T rnext = ld(y + rho + 1);
-            const Own onext = ldo(y + 1);
-            __syncthreads();
-            if (ln.owner) {
-                const int i = g.row0 + y * g.W + ln.px;
-                const size_t e = (size_t)i * d + ln.c;
-                const T yi = raw[0];
-                T accR = T(0);
-#pragma unroll
-                for (int k = 0; k < KC; ++k) {
-                    const size_t sl = (size_t)k * a.n + i;
-                    const T wk = PW ? own.ww[PW ? k : 0] : a.sw[sl];
-                    const T bo = PW ? own.bo[PW ? k : 0] : (b_zero ? T(0) : a.bs[sl * d + ln.c]);
-                    const T yj = ring[S::slot(y + S::dy(k)) * kBlock + t + S::dx(k) * d];
-                    const T tv = fma_t(wk, yi - yj, bo);
-                    const T dv = shrink(tv, a.gamma);
-                    const T bn = tv - dv;
-                    a.bs[sl * d + ln.c] = bn;
-                    if (a.keep_split) a.ds[sl * d + ln.c] = dv;
-                    accR = fma_t(wk, dv - bn, accR);
-                }
-                a.rhs[e] = fma_t(a.c_off, accR, own.split);
+            for (int k = 0; k < KC; ++k) {
+                const size_t sl = (size_t)k * a.n + i;
+                const T wk = PW ? own.ww[PW ? k : 0] : a.sw[sl];
+                const T bo = PW ? own.bo[PW ? k : 0] : (b_zero ? T(0) : a.bs[sl * d + ln.c]);
+                const T tv = fma_t(wk, v.y - nb(k), bo);
+                const T dv = shrink(tv, a.gamma);
+                const T bn = tv - dv;
+                a.bs[sl * d + ln.c] = bn;
+                if (a.keep_split) a.ds[sl * d + ln.c] = dv;
+                accR = fma_t(wk, dv - bn, accR);
             }
+            a.rhs[e] = fma_t(a.c_off, accR, own.split);
+        });
+}
+
+// Learned-preconditioner PCG phases over a strip (the ph_la, ph_lc, ph_ld
+// arithmetic; the stencil's slots [0, K/2) are a pixel's lower neighbours).
+// LA: p = z + beta p, q = A p, partials of p.q
+template <int KC, typename T>
+__device__ __forceinline__ void st_la(const KA<T>& a, int lb, double* sh) {
+    constexpr bool PW = KC <= 8;
+    const StripGeo g = strip_geo(a.geo, lb);
+    const int d = a.d;
+    const StripLane ln(g, d, Sten<KC>::rho);
+    const int it = ld_flag(&a.S->it);
+    const bool first = (it == 0);
+    T* pnew = a.sb[it & 1];
+    const T* pold = a.sb[(it & 1) ^ 1];
+    T* q = a.wb[0];
+    const T beta = (T)a.cs.beta[a.blk_seg[lb] * d + ln.c];
+    struct Raw { T z, po; };
+    struct Own { T dA, ww[PW ? KC : 1]; };
+    auto p_of = [&](const Raw& v) { return first ? v.z : fma_t(beta, v.po, v.z); };
+    double acc1[1] = {0.0};
+    strip_walk<KC>(a, g, ln, reinterpret_cast<T*>(sh),
+        [&](int, size_t e) { return Raw{a.zl[e], pold[e]}; },
+        p_of,
+        [&](int i, size_t) {
+            Own o{};
+            o.dA = a.diagA[i];
+            if constexpr (PW) {
 #pragma unroll
-            for (int k = 0; k < rho; ++k) raw[k] = raw[k + 1];
-            raw[rho] = rnext;
-            own = onext;
-        }
-    }
+                for (int k = 0; k < KC; ++k) o.ww[k] = a.sw[(size_t)k * a.n + i];
+            }
+            return o;
+        },
+        [&](int i, size_t e, const Raw& v, const Own& own, auto&& nb) {
+            const T pi = p_of(v);
+            T acc = T(0);
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                const T wk = PW ? own.ww[PW ? k : 0] : a.sw[(size_t)k * a.n + i];
+                acc = fma_t(mul_t(wk, wk), nb(k), acc);
+            }
+            const T qi = fma_t(own.dA, pi, -mul_t(a.c_off, acc));
+            pnew[e] = pi;
+            q[e] = qi;
+            acc1[0] += (double)pi * (double)qi;
+        });
+    block_partials<1>(acc1, sh, d, kBlock / d, a.part, a.nblk, lb);
+}
+
+// LC: x += alpha p, r' = r - alpha q (own pixels), y1 = Gt D_A^{-1/2} r' over
+// the lower neighbours (upd = 0: y1 from the initial residual, no update)
+template <int KC, typename T>
+__device__ __forceinline__ void st_lc(const KA<T>& a, int lb, double* sh, int upd) {
+    constexpr int H = KC / 2;
+    const StripGeo g = strip_geo(a.geo, lb);
+    const int d = a.d;
+    const StripLane ln(g, d, Sten<KC>::rho);
+    const int it = upd ? ld_flag(&a.S->it) : 0;
+    const T* r = a.rb[it & 1];
+    T* rn = a.rb[(it & 1) ^ 1];
+    const T* p = a.sb[it & 1];
+    const T* q = a.wb[0];
+    const T alpha = upd ? (T)a.cs.alpha[a.blk_seg[lb] * d + ln.c] : T(0);
+    struct Raw { T r, q, isq; };
+    struct Own { T x, p, gd, gv[H]; };
+    auto rv_of = [&](const Raw& v) { return upd ? fma_t(-alpha, v.q, v.r) : v.r; };
+    strip_walk<KC>(a, g, ln, reinterpret_cast<T*>(sh),
+        [&](int j, size_t e) { return Raw{r[e], upd ? q[e] : T(0), a.isq[j]}; },
+        [&](const Raw& v) { return mul_t(v.isq, rv_of(v)); },
+        [&](int i, size_t e) {
+            Own o{};
+            if (upd) {
+                o.x = a.x[e];
+                o.p = p[e];
+            }
+            o.gd = a.gdiag[i];
+#pragma unroll
+            for (int k = 0; k < H; ++k) o.gv[k] = a.gval[(size_t)k * a.n + i];
+            return o;
+        },
+        [&](int, size_t e, const Raw& v, const Own& own, auto&& nb) {
+            const T ri = rv_of(v);
+            if (upd) {
+                a.x[e] = fma_t(alpha, own.p, own.x);
+                rn[e] = ri;
+            }
+            T acc = mul_t(own.gd, mul_t(v.isq, ri));
+#pragma unroll
+            for (int k = 0; k < H; ++k) acc = fma_t(own.gv[k], nb(k), acc);
+            a.y1[e] = acc;
+        });
+}
+
+// LD: z = D_A^{-1/2} Gt^T y1 over the upper neighbours, partials of r'.z, r'.r'
+template <int KC, typename T>
+__device__ __forceinline__ void st_ld(const KA<T>& a, int lb, double* sh, int initial) {
+    constexpr int H = KC / 2;
+    const StripGeo g = strip_geo(a.geo, lb);
+    const int d = a.d;
+    const StripLane ln(g, d, Sten<KC>::rho);
+    const T* r = initial ? a.rb[0] : a.rb[(ld_flag(&a.S->it) & 1) ^ 1];
+    struct Raw { T y1; };
+    struct Own { T r, isq, gd, gv[KC - H]; };
+    double acc2[2] = {0.0, 0.0};
+    strip_walk<KC>(a, g, ln, reinterpret_cast<T*>(sh),
+        [&](int, size_t e) { return Raw{a.y1[e]}; },
+        [&](const Raw& v) { return v.y1; },
+        [&](int i, size_t e) {
+            Own o{};
+            o.r = r[e];
+            o.isq = a.isq[i];
+            o.gd = a.gdiag[i];
+#pragma unroll
+            for (int k = H; k < KC; ++k) o.gv[k - H] = a.gval[(size_t)k * a.n + i];
+            return o;
+        },
+        [&](int, size_t e, const Raw& v, const Own& own, auto&& nb) {
+            T acc = mul_t(own.gd, v.y1);
+#pragma unroll
+            for (int k = H; k < KC; ++k) acc = fma_t(own.gv[k - H], nb(k), acc);
+            const T z = mul_t(own.isq, acc);
+            a.zl[e] = z;
+            acc2[0] += (double)own.r * (double)z;
+            acc2[1] += (double)own.r * (double)own.r;
+        });
+    block_partials<2>(acc2, sh, d, kBlock / d, a.part, a.nblk, lb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1976,6 +2029,33 @@ template <typename T, int KC>
 __global__ void __launch_bounds__(kBlock) k_st_eu(KA<T> a) {
     __shared__ double sh[kSmemDoubles];
     st_eu<KC>(a, logical_block(a.nblk), sh);
+}
+
+// learned-preconditioner PCG phases on strips
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_st_la(KA<T> a) {
+    __shared__ double sh[kSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    st_la<KC>(a, logical_block(a.nblk), sh);
+    if (last_block(a.bar + kBarLast, a.nblk)) fin_la(a, sh);
+}
+
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_st_lc(KA<T> a, int upd) {
+    __shared__ double sh[kSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    st_lc<KC>(a, logical_block(a.nblk), sh, upd);
+}
+
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_st_ld(KA<T> a, int initial) {
+    __shared__ double sh[kSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    st_ld<KC>(a, logical_block(a.nblk), sh, initial);
+    if (last_block(a.bar + kBarLast, a.nblk)) {
+        fin_ld(a, sh, initial != 0);
+        if (threadIdx.x == 0 && a.S->done) solve_stats(a);
+    }
 }
 
 template <typename T>
@@ -2706,6 +2786,9 @@ pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0)
                 PFE_CHECK_HIP(hipGetLastError());
                 return PFE_OK;
             case PH_W0: PFE_LAUNCH_ST(k_st_w0, K, grid, st, a); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
+            case PH_LA: PFE_LAUNCH_ST(k_st_la, K, grid, st, a); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
+            case PH_LC: PFE_LAUNCH_ST(k_st_lc, K, grid, st, a, mode); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
+            case PH_LD: PFE_LAUNCH_ST(k_st_ld, K, grid, st, a, mode); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
             case PH_IT: PFE_LAUNCH_ST(k_st_it, K, grid, st, a); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
             default: break;
         }
@@ -2737,14 +2820,21 @@ constexpr int kCgChunk = 8;
 
 template <typename T>
 const void* kernel_for(int which, int ellK, bool strip) {
-    if (strip && which == PH_IT) {
-        switch (ellK) {
-            case 4: return reinterpret_cast<const void*>(&k_st_it<T, 4>);
-            case 8: return reinterpret_cast<const void*>(&k_st_it<T, 8>);
-            case 24: return reinterpret_cast<const void*>(&k_st_it<T, 24>);
-            default: return nullptr;
+#define PFE_SSEL(K) switch (ellK) { \
+        case 4: return reinterpret_cast<const void*>(&K<T, 4>); \
+        case 8: return reinterpret_cast<const void*>(&K<T, 8>); \
+        case 24: return reinterpret_cast<const void*>(&K<T, 24>); \
+        default: return nullptr; }
+    if (strip) {
+        switch (which) {
+            case PH_IT: PFE_SSEL(k_st_it)
+            case PH_LA: PFE_SSEL(k_st_la)
+            case PH_LC: PFE_SSEL(k_st_lc)
+            case PH_LD: PFE_SSEL(k_st_ld)
         }
+        return nullptr;
     }
+#undef PFE_SSEL
 #define PFE_KSEL(K) switch (ellK) { \
         case 4: return reinterpret_cast<const void*>(&K<T, 4>); \
         case 8: return reinterpret_cast<const void*>(&K<T, 8>); \
@@ -2794,9 +2884,9 @@ pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, hipGraphExec
     const int K = a.ell_K;
     for (int k = 0; k < kCgChunk; ++k) {
         if (learned) {
-            add(kernel_for<T>(PH_LA, K, false), p1);
-            add(kernel_for<T>(PH_LC, K, false), p3);
-            add(kernel_for<T>(PH_LD, K, false), p2);
+            add(kernel_for<T>(PH_LA, K, a.geo != nullptr), p1);
+            add(kernel_for<T>(PH_LC, K, a.geo != nullptr), p3);
+            add(kernel_for<T>(PH_LD, K, a.geo != nullptr), p2);
         } else {
             add(kernel_for<T>(PH_IT, K, a.geo != nullptr), p1);
         }
@@ -2853,14 +2943,15 @@ pfe_status pcg_loop_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
     return PFE_OK;
 }
 
-// Multi-launch PCG with the learned factor after a residual phase (r0 in rb[0]).
+// Multi-launch PCG with the learned factor after a residual phase (r0 in rb[0]);
+// the PCG phases run on the arguments 'as' (strips of a pixel grid, or 'a').
 template <typename T>
-pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a) {
+pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
     hipLaunchKernelGGL(k_stats_if_done<T>, dim3(1), dim3(64), 0, c->stream, a);
-    PFE_TRY(launch_phase(c, a, PH_LC, 0, 0));     // y1 from the initial residual
-    PFE_TRY(launch_phase(c, a, PH_LD, 1, 0));     // initial r.z
+    PFE_TRY(launch_phase(c, as, PH_LC, 0, 0));     // y1 from the initial residual
+    PFE_TRY(launch_phase(c, as, PH_LD, 1, 0));     // initial r.z
     if (c->prm.graphs) {
-        PFE_TRY(pcg_replay(c, a, true));
+        PFE_TRY(pcg_replay(c, as, true));
         return launch_phase(c, a, PH_ZERO, 0, 0);
     }
     int it = 0;
@@ -2868,9 +2959,9 @@ pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a) {
     int done = 0;
     while (true) {
         for (int k = 0; k < chunk; ++k) {
-            PFE_TRY(launch_phase(c, a, PH_LA, 0, 0));
-            PFE_TRY(launch_phase(c, a, PH_LC, 1, 0));
-            PFE_TRY(launch_phase(c, a, PH_LD, 0, 0));
+            PFE_TRY(launch_phase(c, as, PH_LA, 0, 0));
+            PFE_TRY(launch_phase(c, as, PH_LC, 1, 0));
+            PFE_TRY(launch_phase(c, as, PH_LD, 0, 0));
         }
         it += chunk;
         PFE_CHECK_HIP(hipMemcpyAsync(&done, &c->S->done, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -2883,7 +2974,7 @@ pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a) {
 
 template <typename T>
 pfe_status pcg_any_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
-    return (c->prm.precond == PFE_LEARNED) ? pcg_loop_learned_mk(c, a) : pcg_loop_mk(c, a, as);
+    return (c->prm.precond == PFE_LEARNED) ? pcg_loop_learned_mk(c, a, as) : pcg_loop_mk(c, a, as);
 }
 
 // the strip partition is used in the one-launch-per-phase path when the graph

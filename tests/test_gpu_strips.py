@@ -169,3 +169,28 @@ def test_autotune_offers_strips(monkeypatch):
     res = S.autotune(1)
     assert any(r["strips"] == 1 and r["persistent"] == 0 for r in res), res
     assert sum(r["chosen"] for r in res) == 1
+
+
+@pytest.mark.parametrize("stencil,d", [(8, 4), (-2, 5), (4, 3)])
+def test_learned_pcg_strips_match_row_chunks(stencil, d, monkeypatch):
+    """PCG with a (non-identity) learned factor: the three strip phases per
+    iteration give the row-chunk phases' iterate and iteration counts."""
+    from paper_1612_06496_amd import Mpnn, Solver
+    banner(f"learned PCG strips vs row chunks stencil={stencil}")
+    wl = synth.grid_workload("t", 45, 101, 6, 0.05, 3, stencil=stencil, d=d)
+    th = np.random.default_rng(1).normal(0.0, 0.3, size=Mpnn.NPARAMS)
+    th[Mpnn.NPARAMS - 1] = np.log(np.e - 1.0)
+    rhs = np.random.default_rng(2).normal(size=(wl.n, d))
+    out = []
+    for strips in ("1", "0"):
+        monkeypatch.setenv("PFE_STRIPS", strips)
+        S = Solver(gpu_graph(wl), wl.y0, lam=20.0, r=1.0, n_inner=2, tol=1e-10, maxit=5000, fp64=True,
+                   persistent=False)
+        S.set_learned(Mpnn(th.astype(np.float32)))
+        x, iters, info = S.pcg(rhs, np.zeros_like(rhs))
+        out.append((to_np(x), np.asarray(iters), info))
+    e = rel(out[0][0], out[1][0])
+    print(f"rel diff {e:.2e}; iterations {out[0][1].tolist()} vs {out[1][1].tolist()}")
+    assert np.all(np.abs(out[0][1] - out[1][1]) <= 1)
+    assert e <= 1e-9
+    assert out[0][2]["rel_res_max"] <= 1e-10
