@@ -52,7 +52,8 @@ enum Phase : int {
     // PCG with the learned factor M^{-1} = D_A^{-1/2} Gt^T Gt D_A^{-1/2}
     PH_LA = 9,      // p = z + beta p, q = A p, p.q
     PH_LC = 11,     // x += alpha p, r -= alpha q, y1 = Gt D_A^{-1/2} r
-    PH_LD = 12      // z = D_A^{-1/2} Gt^T y1, r.z, r.r
+    PH_LD = 12,     // z = D_A^{-1/2} Gt^T y1, r.z, r.r
+    PH_LCD = 13     // LC and LD fused (strips with a two-radius halo)
 };
 
 // per (segment, column) CG state, struct of arrays of length nseg * d
@@ -1316,6 +1317,141 @@ __device__ __forceinline__ void st_ld(const KA<T>& a, int lb, double* sh, int in
     block_partials<2>(acc2, sh, d, kBlock / d, a.part, a.nblk, lb);
 }
 
+// LC and LD fused (the ph_lc + ph_ld arithmetic) over a strip whose ring rows
+// span two stencil radii on each side: x += alpha p and r' = r - alpha q on the
+// owned pixels; y1 = Gt D_A^{-1/2} r' over the lower neighbours for every pixel
+// within one radius of the strip, formed into a second LDS ring (not stored);
+// z = D_A^{-1/2} Gt^T y1 over the upper neighbours on the owned pixels, with
+// the partials of r'.z and r'.r' (upd = 0: from the initial residual).  Per
+// image row y: publish isq r' of row y + rho, barrier, y1 of row y + rho,
+// barrier, z of row y.
+template <int KC, typename T>
+__device__ __forceinline__ void st_lcd(const KA<T>& a, int lb, double* sh, int upd) {
+    using S = Sten<KC>;
+    constexpr int rho = S::rho, H = KC / 2, NS = rho + 2;
+    const StripGeo g = strip_geo(a.geo, lb);
+    const int d = a.d, t = threadIdx.x;
+    const int qx = t / d, c = t - qx * d;
+    const int span = g.len + 4 * rho;
+    const int px = g.x0 - 2 * rho + qx;
+    const bool loader = qx < span;
+    const bool in_image = loader && px >= 0 && px < g.W;
+    const bool mid = in_image && qx >= rho && qx < g.len + 3 * rho;   // forms y1 of its pixel
+    const bool owner = qx >= 2 * rho && qx < g.len + 2 * rho;
+    const int it = upd ? ld_flag(&a.S->it) : 0;
+    const T* r = a.rb[it & 1];
+    T* rn = a.rb[(it & 1) ^ 1];
+    const T* p = a.sb[it & 1];
+    const T* q = a.wb[0];
+    const T alpha = upd ? (T)a.cs.alpha[a.blk_seg[lb] * d + c] : T(0);
+    T* ringA = reinterpret_cast<T*>(sh);   // isq r'
+    T* ringB = ringA + NS * kBlock;        // y1
+    auto slot = [](int y) { return (y + 4 * NS) % NS; };
+    const int ylo = max(0, g.y0 - rho), yhi = min(g.H, g.y1 + rho);    // rows of r' the strip reads
+    struct Raw { T r, q, isq; };
+    struct Mid { T gd, gv[H]; };
+    struct Own { T x, p, gd, gv[KC - H]; };
+    auto ldr = [&](int y) {
+        Raw v{};
+        if (in_image && y >= ylo && y < yhi) {
+            const int j = g.row0 + y * g.W + px;
+            const size_t e = (size_t)j * d + c;
+            v.r = r[e];
+            v.q = upd ? q[e] : T(0);
+            v.isq = a.isq[j];
+        }
+        return v;
+    };
+    auto ldm = [&](int y) {
+        Mid m{};
+        if (mid && y < min(g.H, g.y1 + rho)) {
+            const int j = g.row0 + y * g.W + px;
+            m.gd = a.gdiag[j];
+#pragma unroll
+            for (int k = 0; k < H; ++k) m.gv[k] = a.gval[(size_t)k * a.n + j];
+        }
+        return m;
+    };
+    auto ldo = [&](int y) {
+        Own o{};
+        if (owner && y < g.y1) {
+            const int i = g.row0 + y * g.W + px;
+            const size_t e = (size_t)i * d + c;
+            if (upd) {
+                o.x = a.x[e];
+                o.p = p[e];
+            }
+            o.gd = a.gdiag[i];
+#pragma unroll
+            for (int k = H; k < KC; ++k) o.gv[k - H] = a.gval[(size_t)k * a.n + i];
+        }
+        return o;
+    };
+    auto rv_of = [&](const Raw& v) { return upd ? fma_t(-alpha, v.q, v.r) : v.r; };
+    // y1 of this lane's pixel at image row y (ring A holds rows y - rho .. y)
+    auto y1_of = [&](int y, const Mid& m) {
+        T acc = mul_t(m.gd, ringA[slot(y) * kBlock + t]);
+#pragma unroll
+        for (int k = 0; k < H; ++k) acc = fma_t(m.gv[k], ringA[slot(y + S::dy(k)) * kBlock + t + S::dx(k) * d], acc);
+        return acc;
+    };
+    double acc2[2] = {0.0, 0.0};
+    if (g.len > 0 && g.y1 > g.y0) {
+        Raw raw[rho + 1];   // rows y .. y + rho of this lane
+        // prime ring A with rows y0 - rho .. y0 + rho - 1 and ring B with rows y0 .. y0 + rho - 1
+#pragma unroll
+        for (int k = 1; k <= rho; ++k)
+            if (loader) { const Raw v = ldr(g.y0 - k); ringA[slot(g.y0 - k) * kBlock + t] = mul_t(v.isq, rv_of(v)); }
+#pragma unroll
+        for (int k = 0; k <= rho; ++k) raw[k] = ldr(g.y0 + k);
+#pragma unroll
+        for (int k = 0; k < rho; ++k)
+            if (loader) ringA[slot(g.y0 + k) * kBlock + t] = mul_t(raw[k].isq, rv_of(raw[k]));
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < rho; ++k) {
+            const Mid m = ldm(g.y0 + k);
+            if (loader) ringB[slot(g.y0 + k) * kBlock + t] = (mid && g.y0 + k < g.H) ? y1_of(g.y0 + k, m) : T(0);
+        }
+        __syncthreads();   // the first row overwrites a ring-A row the priming read
+        Mid mcur = ldm(g.y0 + rho);
+        Own own = ldo(g.y0);
+        for (int y = g.y0; y < g.y1; ++y) {
+            if (loader) ringA[slot(y + rho) * kBlock + t] = mul_t(raw[rho].isq, rv_of(raw[rho]));
+            const Raw rnext = ldr(y + rho + 1);
+            const Mid mnext = ldm(y + rho + 1);
+            const Own onext = ldo(y + 1);
+            __syncthreads();
+            if (loader) ringB[slot(y + rho) * kBlock + t] = (mid && y + rho < g.H) ? y1_of(y + rho, mcur) : T(0);
+            __syncthreads();
+            if (owner) {
+                const int i = g.row0 + y * g.W + px;
+                const size_t e = (size_t)i * d + c;
+                const T ri = rv_of(raw[0]);
+                if (upd) {
+                    a.x[e] = fma_t(alpha, own.p, own.x);
+                    rn[e] = ri;
+                }
+                T acc = mul_t(own.gd, ringB[slot(y) * kBlock + t]);
+#pragma unroll
+                for (int k = H; k < KC; ++k)
+                    acc = fma_t(own.gv[k - H], ringB[slot(y + S::dy(k)) * kBlock + t + S::dx(k) * d], acc);
+                const T z = mul_t(raw[0].isq, acc);
+                a.zl[e] = z;
+                acc2[0] += (double)ri * (double)z;
+                acc2[1] += (double)ri * (double)ri;
+            }
+#pragma unroll
+            for (int k = 0; k < rho; ++k) raw[k] = raw[k + 1];
+            raw[rho] = rnext;
+            mcur = mnext;
+            own = onext;
+        }
+    }
+    __syncthreads();
+    block_partials<2>(acc2, sh, d, kBlock / d, a.part, a.nblk, lb);
+}
+
 // ---------------------------------------------------------------------------
 // Finalisers (one workgroup, after every workgroup has written its partials).
 // 'grouped' means the per-XCD-group partials are already summed (one segment).
@@ -2058,6 +2194,18 @@ __global__ void __launch_bounds__(kBlock) k_st_ld(KA<T> a, int initial) {
     }
 }
 
+// LC and LD fused on strips with a two-radius halo
+template <typename T, int KC>
+__global__ void __launch_bounds__(kBlock) k_st_lcd(KA<T> a, int upd) {
+    __shared__ double sh[kSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    st_lcd<KC>(a, logical_block(a.nblk), sh, upd);
+    if (last_block(a.bar + kBarLast, a.nblk)) {
+        fin_ld(a, sh, upd == 0);
+        if (threadIdx.x == 0 && a.S->done) solve_stats(a);
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_cg_zero(KA<T> a) {
     ph_zero(a, logical_block(a.nblk), a.cs.zero);
@@ -2481,6 +2629,7 @@ struct pfe_ctx {
     Partition pm;            // multi-launch partition
     Partition pc;            // persistent partition (pc.nblk == 0: not available)
     Partition ps;            // strip partition of pixel grids (ps.nblk == 0: not available)
+    Partition pl;            // strips with a two-radius halo (fused learned apply)
     int want_strips = 2;     // one launch per phase: residual, w0 and CG kernels on image strips sized
                              // for this many waves of co-resident strip workgroups (0: row chunks)
     int strip_slots = 0;     // co-resident strip workgroups on the device (0: no strip kernel)
@@ -2620,7 +2769,8 @@ void free_partition(Partition& P) {
 
 // Strip partition of a graph whose segments are pixel grids with a compiled
 // stencil width (4, 8, 24 slots): image s is cut into nsx column strips of at
-// most kBlock / d - 2 rho pixels (equal widths up to one pixel) and nsy bands
+// most kBlock / d - 2 halos rho pixels (equal widths up to one pixel; halos = 1
+// for the one-hop phases, 2 for the fused learned apply) and nsy bands
 // of image rows (at least kStripMinRows rows each), the number of workgroups
 // of each image proportional to its pixels.  Logical workgroups run in the
 // order (image, band, strip), so the consecutive workgroups that one XCD holds
@@ -2628,7 +2778,7 @@ void free_partition(Partition& P) {
 // The count is padded to a multiple of the XCD count with empty workgroups.
 constexpr int kStripMinRows = 16;
 
-pfe_status make_strip_partition(const pfe_graph* g, int d, int want_blocks, Partition& P) {
+pfe_status make_strip_partition(const pfe_graph* g, int d, int want_blocks, int halos, Partition& P) {
     free_partition(P);
     int min_rows = kStripMinRows;
     if (const char* ev = getenv("PFE_STRIP_MINROWS")) min_rows = std::max(1, atoi(ev));   // launch-shape experiments
@@ -2638,7 +2788,7 @@ pfe_status make_strip_partition(const pfe_graph* g, int d, int want_blocks, Part
     for (int s = 0; s < nseg; ++s)
         if (g->seg_W[s] < 1 || g->seg_H[s] < 1) return PFE_OK;
     const int rho = (K == 24) ? 2 : 1;
-    const int L = kBlock / d - 2 * rho;
+    const int L = kBlock / d - 2 * halos * rho;   // a ring row spans halos stencil radii on each side
     if (L < 1) return PFE_OK;
     const double n = (double)g->n;
     std::vector<int> geo, bseg, sb0(nseg + 1);
@@ -2789,6 +2939,7 @@ pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0)
             case PH_LA: PFE_LAUNCH_ST(k_st_la, K, grid, st, a); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
             case PH_LC: PFE_LAUNCH_ST(k_st_lc, K, grid, st, a, mode); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
             case PH_LD: PFE_LAUNCH_ST(k_st_ld, K, grid, st, a, mode); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
+            case PH_LCD: PFE_LAUNCH_ST(k_st_lcd, K, grid, st, a, mode); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
             case PH_IT: PFE_LAUNCH_ST(k_st_it, K, grid, st, a); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
             default: break;
         }
@@ -2831,6 +2982,7 @@ const void* kernel_for(int which, int ellK, bool strip) {
             case PH_LA: PFE_SSEL(k_st_la)
             case PH_LC: PFE_SSEL(k_st_lc)
             case PH_LD: PFE_SSEL(k_st_ld)
+            case PH_LCD: PFE_SSEL(k_st_lcd)
         }
         return nullptr;
     }
@@ -2851,28 +3003,32 @@ const void* kernel_for(int which, int ellK, bool strip) {
 }
 
 template <typename T>
-pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, hipGraphExec_t* out) {
-    std::vector<unsigned char> key(sizeof(KA<T>) + 2);
+pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, const KA<T>* al, hipGraphExec_t* out) {
+    // al: arguments of the fused learned apply (strips with a two-radius halo), or null
+    std::vector<unsigned char> key(2 * sizeof(KA<T>) + 2, 0);
     std::memcpy(key.data(), &a, sizeof(KA<T>));
-    key[sizeof(KA<T>)] = learned ? 1 : 0;
-    key[sizeof(KA<T>) + 1] = (unsigned char)sizeof(T);
+    if (al) std::memcpy(key.data() + sizeof(KA<T>), al, sizeof(KA<T>));
+    key[2 * sizeof(KA<T>)] = learned ? 1 : 0;
+    key[2 * sizeof(KA<T>) + 1] = (unsigned char)sizeof(T);
     if (c->cg_exec && key == c->cg_key) { *out = c->cg_exec; return PFE_OK; }
     if (c->cg_exec) { (void)hipGraphExecDestroy(c->cg_exec); c->cg_exec = nullptr; }
     hipGraph_t g = nullptr;
     PFE_CHECK_HIP(hipGraphCreate(&g, 0));
     KA<T> args = a;
+    KA<T> largs = al ? *al : a;
     int initial = 0, upd = 1;
     void* p1[] = {(void*)&args};
     void* p2[] = {(void*)&args, (void*)&initial};
     void* p3[] = {(void*)&args, (void*)&upd};
+    void* p4[] = {(void*)&largs, (void*)&upd};
     hipGraphNode_t prev = nullptr;
     hipError_t e = hipSuccess;
-    auto add = [&](const void* fn, void** kp) {
+    auto add = [&](const void* fn, void** kp, int nblk) {
         if (e != hipSuccess) return;
         if (!fn) { e = hipErrorInvalidDeviceFunction; return; }
         hipKernelNodeParams np{};
         np.func = const_cast<void*>(fn);
-        np.gridDim = dim3(a.nblk);
+        np.gridDim = dim3(nblk);
         np.blockDim = dim3(kBlock);
         np.sharedMemBytes = 0;
         np.kernelParams = kp;
@@ -2882,13 +3038,18 @@ pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, hipGraphExec
         prev = node;
     };
     const int K = a.ell_K;
+    const bool st = a.geo != nullptr;
     for (int k = 0; k < kCgChunk; ++k) {
         if (learned) {
-            add(kernel_for<T>(PH_LA, K, a.geo != nullptr), p1);
-            add(kernel_for<T>(PH_LC, K, a.geo != nullptr), p3);
-            add(kernel_for<T>(PH_LD, K, a.geo != nullptr), p2);
+            add(kernel_for<T>(PH_LA, K, st), p1, a.nblk);
+            if (al) {
+                add(kernel_for<T>(PH_LCD, K, true), p4, al->nblk);
+            } else {
+                add(kernel_for<T>(PH_LC, K, st), p3, a.nblk);
+                add(kernel_for<T>(PH_LD, K, st), p2, a.nblk);
+            }
         } else {
-            add(kernel_for<T>(PH_IT, K, a.geo != nullptr), p1);
+            add(kernel_for<T>(PH_IT, K, st), p1, a.nblk);
         }
     }
     hipGraphExec_t ex = nullptr;
@@ -2903,9 +3064,9 @@ pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, hipGraphExec
 
 // replay the chunk graph until the solve is done
 template <typename T>
-pfe_status pcg_replay(pfe_ctx* c, const KA<T>& a, bool learned) {
+pfe_status pcg_replay(pfe_ctx* c, const KA<T>& a, bool learned, const KA<T>* al = nullptr) {
     hipGraphExec_t ex = nullptr;
-    PFE_TRY(cg_chunk_graph(c, a, learned, &ex));
+    PFE_TRY(cg_chunk_graph(c, a, learned, al, &ex));
     int it = 0, done = 0;
     while (true) {
         PFE_CHECK_HIP(hipGraphLaunch(ex, c->stream));
@@ -2947,11 +3108,24 @@ pfe_status pcg_loop_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
 // the PCG phases run on the arguments 'as' (strips of a pixel grid, or 'a').
 template <typename T>
 pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
+    // on strips the two factor products run as one kernel on strips with a
+    // two-radius halo
+    const bool fused = as.geo && c->pl.nblk > 0;
+    KA<T> al = as;
+    if (fused) {
+        al = make_args<T>(c, c->pl);
+        al.x = as.x;       // the iterate and rhs of this solve (a caller's buffers in pfe_pcg)
+        al.rhs = as.rhs;
+    }
     hipLaunchKernelGGL(k_stats_if_done<T>, dim3(1), dim3(64), 0, c->stream, a);
-    PFE_TRY(launch_phase(c, as, PH_LC, 0, 0));     // y1 from the initial residual
-    PFE_TRY(launch_phase(c, as, PH_LD, 1, 0));     // initial r.z
+    if (fused) {
+        PFE_TRY(launch_phase(c, al, PH_LCD, 0, 0));    // z and r.z from the initial residual
+    } else {
+        PFE_TRY(launch_phase(c, as, PH_LC, 0, 0));     // y1 from the initial residual
+        PFE_TRY(launch_phase(c, as, PH_LD, 1, 0));     // initial r.z
+    }
     if (c->prm.graphs) {
-        PFE_TRY(pcg_replay(c, as, true));
+        PFE_TRY(pcg_replay(c, as, true, fused ? &al : nullptr));
         return launch_phase(c, a, PH_ZERO, 0, 0);
     }
     int it = 0;
@@ -2960,8 +3134,12 @@ pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
     while (true) {
         for (int k = 0; k < chunk; ++k) {
             PFE_TRY(launch_phase(c, as, PH_LA, 0, 0));
-            PFE_TRY(launch_phase(c, as, PH_LC, 1, 0));
-            PFE_TRY(launch_phase(c, as, PH_LD, 0, 0));
+            if (fused) {
+                PFE_TRY(launch_phase(c, al, PH_LCD, 1, 0));
+            } else {
+                PFE_TRY(launch_phase(c, as, PH_LC, 1, 0));
+                PFE_TRY(launch_phase(c, as, PH_LD, 0, 0));
+            }
         }
         it += chunk;
         PFE_CHECK_HIP(hipMemcpyAsync(&done, &c->S->done, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -2986,10 +3164,12 @@ pfe_status setup_strips(pfe_ctx* c) {
     if (c->want_strips <= 0 || c->strip_slots <= 0 || c->ps_waves == c->want_strips) return PFE_OK;
     int want = c->want_strips * c->strip_slots;
     if (const char* ev = getenv("PFE_STRIP_WG")) want = std::max(1, atoi(ev));   // launch-shape experiments
-    PFE_TRY(make_strip_partition(c->g, (int)c->d, want, c->ps));
+    PFE_TRY(make_strip_partition(c->g, (int)c->d, want, 1, c->ps));
+    PFE_TRY(make_strip_partition(c->g, (int)c->d, want, 2, c->pl));
     c->ps_waves = c->want_strips;
-    if (c->part_blocks > 0 && c->ps.nblk > c->part_blocks) {
+    if (c->part_blocks > 0 && std::max(c->ps.nblk, c->pl.nblk) > c->part_blocks) {
         free_partition(c->ps);
+        free_partition(c->pl);
         c->ps_waves = 0;
         set_error("strip partition of %d workgroups exceeds the partial-sum buffer", c->ps.nblk);
         return PFE_E_STATE;
@@ -3116,6 +3296,7 @@ void free_ctx(pfe_ctx* c) {
     free_partition(c->pm);
     free_partition(c->pc);
     free_partition(c->ps);
+    free_partition(c->pl);
     if (c->cg_exec) (void)hipGraphExecDestroy(c->cg_exec);
     c->cg_exec = nullptr;
 }
@@ -3391,7 +3572,7 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
         c->want_strips = want;
     }
     if (s != PFE_OK) { free_ctx(c); delete c; return s; }
-    const int nblk_max = std::max(std::max(c->pm.nblk, c->pc.nblk), c->ps.nblk);
+    const int nblk_max = std::max(std::max(c->pm.nblk, c->pc.nblk), std::max(c->ps.nblk, c->pl.nblk));
     c->part_blocks = nblk_max;
     if (s == PFE_OK) s = setup_strips(c);
     if (s != PFE_OK) { free_ctx(c); delete c; return s; }
