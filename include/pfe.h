@@ -235,7 +235,9 @@ pfe_status pfe_solve(pfe_ctx* c, int n_outer, pfe_step_info* info);
  * persistent (one cooperative launch per SOC iteration) or one launch per
  * phase; team = workgroups that deal an XCD band's row chunks out cyclically
  * (1: contiguous row ranges); row_cache = slot data of the workgroups' rows
- * held in LDS; strips = one launch per phase with the residual, w0 and CG
+ * held in LDS; second_weight = share of rows of the workgroup dispatched second
+ * onto each CU (its waves are issued after the first's, so it may be given
+ * fewer rows); strips = one launch per phase with the residual, w0 and CG
  * kernels of a pixel-grid graph on image strips (each workgroup walks a strip
  * row by row, neighbour values from an LDS ring).  The results are identical
  * up to the summation order of the FP64 reductions. */
@@ -248,13 +250,16 @@ typedef struct {
     int32_t chosen;          /* 1 for the shape kept */
     int32_t strips;          /* one launch per phase on image strips sized for this many waves of
                                 co-resident workgroups (0: row chunks) */
+    double second_weight;    /* persistent, teams of 1: rows of the second workgroup placed on each CU
+                                relative to the first (1: equal) */
 } pfe_tune_result;
 
 /* Autotune the launch shape on this context's graph: from the current state
  * (between SOC iterations) run one untimed and `trials` timed SOC iterations
  * per candidate shape, restore the state after each, and keep the fastest for
  * later pfe_step / pfe_solve calls.  Candidates: persistent with teams of 64
- * or 1, each with and without the LDS row cache (when the rows fit), and one
+ * or 1, each with and without the LDS row cache (when the rows fit), teams of 1
+ * also with second_weight 0.9, 0.85 and 0.8, and one
  * launch per phase on row chunks and (pixel grids) on image strips sized for
  * one or two waves of co-resident workgroups.  results (host, may be null when max_results is 0)
  * receives up to max_results measured shapes, *n_results their number.

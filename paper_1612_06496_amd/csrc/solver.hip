@@ -33,6 +33,7 @@
 #include <cstring>
 #include <cstdlib>
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -1867,35 +1868,42 @@ __device__ bool last_block(unsigned* counter, unsigned nblk) {
 // Persistent path: two-level barrier over all co-resident workgroups.
 // Workgroups arrive on the counter of their XCD group (blockIdx % 8, one
 // 128-byte line each); the last of a group optionally pre-reduces the group's
-// partials (gfin), then arrives on the top counter; the last group leader runs
-// fin() and bumps the generation word that everybody else polls with relaxed
-// loads (no cache invalidation per poll) before one acquire.  The wait is
-// bounded: after kSpinLimit polls a workgroup raises abort_flag and the kernel
-// unwinds (every later barrier then times out quickly).
+// partials (gfin), then arrives on the top counter.  The counters only grow
+// during a launch (the host clears them before it), so the k-th barrier of a
+// launch is complete when a group counter reaches k times the group size and
+// the top counter k times the group count.  Without a finaliser the top counter
+// is the release: everybody polls it with relaxed loads (no cache
+// invalidation per poll) and then acquires.  With a finaliser the last group
+// leader runs fin() and then bumps the generation word the others poll.  The
+// wait is bounded: after kSpinLimit polls a workgroup raises abort_flag and the
+// kernel unwinds (every later barrier then times out quickly).
 constexpr long long kSpinLimit = 1ll << 25;
 constexpr int kBarGen = 0;          // bar[0]: generation
 constexpr int kBarTop = 32;         // bar[32]: top counter
 constexpr int kBarGroup = 64;       // bar[64 + 32 g]: group counters
 constexpr int kBarLast = 448;       // bar[448]: last-workgroup counter of the multi-launch path
 
+struct NoFin;
+
+// nbar: barriers this workgroup has passed in the current launch (every
+// workgroup passes the same sequence)
 template <class GF, class F>
-__device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned nblk, Scal* S, GF&& gfin, F&& fin) {
-    __shared__ int s_role;     // 0 waiter, 1 group leader, 2 top leader
+__device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned nblk, Scal* S, unsigned& nbar, GF&& gfin, F&& fin) {
+    constexpr bool kFin = !std::is_same<typename std::decay<F>::type, NoFin>::value;
+    __shared__ int s_role;     // 0 waiter, 1 group leader, 2 finalising leader
     __shared__ int s_abort;
     const unsigned g = blockIdx.x % kNumXcd;
     const unsigned gsize = nblk / kNumXcd;
+    const unsigned k1 = ++nbar;
     __syncthreads();
     unsigned gen = 0;
     if (threadIdx.x == 0) {
         s_abort = 0;
-        gen = __hip_atomic_load(&bar[kBarGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (kFin) gen = __hip_atomic_load(&bar[kBarGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned prev = __hip_atomic_fetch_add(&bar[kBarGroup + 32 * g], 1u, __ATOMIC_RELEASE,
                                                __HIP_MEMORY_SCOPE_AGENT);
-        s_role = (prev == gsize - 1) ? 1 : 0;
-        if (s_role) {
-            fence_acquire_agent();
-            __hip_atomic_store(&bar[kBarGroup + 32 * g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        s_role = (prev == gsize * k1 - 1) ? 1 : 0;
+        if (s_role) fence_acquire_agent();
     }
     __syncthreads();
     if (s_role == 1) {
@@ -1903,16 +1911,11 @@ __device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned nblk, Scal* S,
         __syncthreads();
         if (threadIdx.x == 0) {
             unsigned prev = __hip_atomic_fetch_add(&bar[kBarTop], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            if (prev == kNumXcd - 1) {
-                s_role = 2;
-                __hip_atomic_store(&bar[kBarTop], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                s_role = 0;
-            }
+            s_role = (kFin && prev == kNumXcd * k1 - 1) ? 2 : 0;
         }
         __syncthreads();
     }
-    if (s_role == 2) {
+    if (kFin && s_role == 2) {
         fin();
         __syncthreads();
         if (threadIdx.x == 0)
@@ -1922,7 +1925,8 @@ __device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned nblk, Scal* S,
     }
     if (threadIdx.x == 0) {
         long long spins = 0;
-        while (__hip_atomic_load(&bar[kBarGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        while (kFin ? (__hip_atomic_load(&bar[kBarGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen)
+                    : (__hip_atomic_load(&bar[kBarTop], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < kNumXcd * k1)) {
             __builtin_amdgcn_s_sleep(1);
             if ((++spins & 1023) == 0) {
                 if (ld_flag(&S->abort_flag) || spins > kSpinLimit) {
@@ -2297,6 +2301,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
     const bool one = (a.nseg == 1);
     const int ncol = a.nseg * d;
     int l0 = plan.l_begin;
+    unsigned nbar = 0;   // grid barriers passed in this launch
     if (one) {
         __shared__ LocState L;
         if (threadIdx.x == 0) L.status = 0;
@@ -2307,18 +2312,18 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
             for (int l = l0; l < plan.n_inner; ++l) {
                 ph_residual<KC, 4, LC>(a, lb, (l == 0) ? PH_E0 : PH_EU, 1, (l == 1) ? 1 : 0, sh, rc);
                 double* gp = gbuf();
-                if (!grid_sync(a.bar, nb, S, [&](unsigned g) { group_reduce(a, g, d, 2, sh, gp); }, NoFin{})) return;
+                if (!grid_sync(a.bar, nb, S, nbar, [&](unsigned g) { group_reduce(a, g, d, 2, sh, gp); }, NoFin{})) return;
                 lfin_res(a, L, gp, sh);
                 if (!L.done) {
                     ph_w0<KC, 4, LC>(a, lb, sh, rc);
                     gp = gbuf();
-                    if (!grid_sync(a.bar, nb, S, [&](unsigned g) { group_reduce(a, g, d, 2, sh, gp); }, NoFin{})) return;
+                    if (!grid_sync(a.bar, nb, S, nbar, [&](unsigned g) { group_reduce(a, g, d, 2, sh, gp); }, NoFin{})) return;
                     lfin_w0(a, L, gp, sh);
                 }
                 while (!L.done) {
                     ph_it<KC, 4, LC>(a, lb, sh, L.it, L.alpha, L.beta, rc);
                     gp = gbuf();
-                    if (!grid_sync(a.bar, nb, S, [&](unsigned g) { group_reduce(a, g, d, 3, sh, gp); }, NoFin{})) return;
+                    if (!grid_sync(a.bar, nb, S, nbar, [&](unsigned g) { group_reduce(a, g, d, 3, sh, gp); }, NoFin{})) return;
                     lfin_it(a, L, gp, sh);
                 }
                 if (lb == 0 && threadIdx.x == 0) solve_stats_loc(a, L);
@@ -2326,13 +2331,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                     // columns with a zero right-hand side: x_c = 0
                     ph_zero(a, lb, L.zero);
                     gbuf();
-                    if (!grid_sync(a.bar, nb, S, NoFin{}, NoFin{})) return;
+                    if (!grid_sync(a.bar, nb, S, nbar, NoFin{}, NoFin{})) return;
                 }
             }
             l0 = 0;
             ph_gram(a, lb, 0, sh);
             double* gp = gbuf();
-            if (!grid_sync(a.bar, nb, S, [&](unsigned g) { group_reduce(a, g, npair, 1, sh, gp); },
+            if (!grid_sync(a.bar, nb, S, nbar, [&](unsigned g) { group_reduce(a, g, npair, 1, sh, gp); },
                            [&] { seg_factor(a, 0, 0, sh, true, a.Tm, true, gp); }))
                 return;
             if (!ld_flag(&S->ortho_ok)) return;
@@ -2343,14 +2348,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
     for (int outer = 0; outer < plan.n_outer; ++outer) {
         for (int l = l0; l < plan.n_inner; ++l) {
             ph_residual<KC, 4, LC>(a, lb, (l == 0) ? PH_E0 : PH_EU, 1, (l == 1) ? 1 : 0, sh, rc);
-            if (!grid_sync(a.bar, nb, S, NoFin{}, [&] { fin_res(a, sh, false); })) return;
+            if (!grid_sync(a.bar, nb, S, nbar, NoFin{}, [&] { fin_res(a, sh, false); })) return;
             if (!ld_flag(&S->done)) {
                 ph_w0<KC, 4, LC>(a, lb, sh, rc);
-                if (!grid_sync(a.bar, nb, S, NoFin{}, [&] { fin_w0(a, sh, false); })) return;
+                if (!grid_sync(a.bar, nb, S, nbar, NoFin{}, [&] { fin_w0(a, sh, false); })) return;
             }
             while (!ld_flag(&S->done)) {
                 ph_it<KC, 4, LC>(a, lb, sh, ld_flag(&S->it), a.cs.alpha, a.cs.beta, rc);
-                if (!grid_sync(a.bar, nb, S, NoFin{}, [&] { fin_it(a, sh, false); })) return;
+                if (!grid_sync(a.bar, nb, S, nbar, NoFin{}, [&] { fin_it(a, sh, false); })) return;
             }
             if (lb == 0 && threadIdx.x == 0) solve_stats(a);
             int any_zero = 0;
@@ -2358,12 +2363,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
             if (any_zero) {
                 // columns with a zero right-hand side: x_c = 0
                 ph_zero(a, lb, a.cs.zero);
-                if (!grid_sync(a.bar, nb, S, NoFin{}, NoFin{})) return;
+                if (!grid_sync(a.bar, nb, S, nbar, NoFin{}, NoFin{})) return;
             }
         }
         l0 = 0;
         ph_gram(a, lb, 0, sh);
-        if (!grid_sync(a.bar, nb, S, NoFin{}, NoFin{})) return;
+        if (!grid_sync(a.bar, nb, S, nbar, NoFin{}, NoFin{})) return;
         const int sg = a.blk_seg[lb];
         // a segment whose Gram matrix is singular keeps its P and B; the
         // first workgroup of the segment records the failure
@@ -2660,6 +2665,7 @@ struct pfe_ctx {
     int per_cu = 0;          // co-resident workgroups per CU
     int64_t coop = 0;        // persistent grid size (0: none)
     int team = 64;           // workgroups per team (cyclic chunk ownership)
+    double second_weight = 1.0;   // persistent: rows of the second workgroup on each CU, relative
     int want_cache = 1;      // use the LDS row cache when the rows fit
     // one-launch-per-phase PCG replayed from a HIP graph of kCgChunk iterations
     hipGraphExec_t cg_exec = nullptr;
@@ -2697,8 +2703,12 @@ static void team_iteration(const std::vector<int>& row0, const std::vector<int>&
     }
 }
 
+// second_weight: share of rows, relative to the others, of the logical
+// workgroups in the upper half of each XCD band (with two co-resident
+// workgroups per CU and nblk a multiple of 16 these are the physical blocks
+// nblk / 2 .. nblk - 1, the second workgroup placed on each CU); 1: equal rows
 pfe_status make_partition(const std::vector<int64_t>& seg_rows, int want_blocks, int R, int team_max,
-                          Partition& P) {
+                          Partition& P, double second_weight = 1.0) {
     // workgroups per segment proportional to its rows (at least one each)
     const int nseg = (int)seg_rows.size();
     int64_t n = 0;
@@ -2725,12 +2735,18 @@ pfe_status make_partition(const std::vector<int64_t>& seg_rows, int want_blocks,
         }
     }
     std::vector<int> row0(total + 1), bseg(total), sb0(nseg + 1);
+    const int band = (total % (2 * kNumXcd) == 0) ? total / kNumXcd : 0;
+    auto weight = [&](int blk) { return (band > 0 && blk % band >= band / 2) ? second_weight : 1.0; };
     int b = 0;
     int64_t base = 0;
     for (int s = 0; s < nseg; ++s) {
         sb0[s] = b;
+        double wsum = 0.0;
+        for (int k = 0; k < nb[s]; ++k) wsum += weight(b + k);
+        double acc = 0.0;
         for (int k = 0; k < nb[s]; ++k) {
-            row0[b] = (int)(base + seg_rows[s] * k / nb[s]);
+            row0[b] = (int)(base + (int64_t)std::llround((double)seg_rows[s] * acc / wsum));
+            acc += weight(b);
             bseg[b] = s;
             ++b;
         }
@@ -3474,7 +3490,7 @@ pfe_status setup_persistent(pfe_ctx* c) {
     if (c->coop < kNumXcd) return PFE_OK;
     const int R = kBlock / (int)c->d;
     const int K = c->g->ell_K;
-    PFE_TRY(make_partition(c->seg_rows, (int)c->coop, R, c->team, c->pc));
+    PFE_TRY(make_partition(c->seg_rows, (int)c->coop, R, c->team, c->pc, c->per_cu == 2 ? c->second_weight : 1.0));
     hipDeviceProp_t prop;
     PFE_CHECK_HIP(hipGetDeviceProperties(&prop, c->device));
     if (c->pc.nblk % kNumXcd != 0 || c->pc.nblk > c->per_cu * prop.multiProcessorCount) {
@@ -3539,6 +3555,7 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
     c->seg_rows = seg_rows;
     if (const char* ev = getenv("PFE_TEAM")) c->team = std::max(1, atoi(ev));   // launch-shape experiments
     if (const char* ev = getenv("PFE_ROWCACHE")) c->want_cache = atoi(ev) != 0;
+    if (const char* ev = getenv("PFE_SECOND_WEIGHT")) c->second_weight = std::min(1.0, std::max(0.25, atof(ev)));
     pfe_status s = make_partition(seg_rows, (int)std::min<int64_t>(want, 2048), R, c->team, c->pm);
     // persistent grid: every co-resident workgroup (at most one per R rows), a
     // multiple of the XCD count; built even when the context starts in the
@@ -3719,10 +3736,12 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
     if (n_results) *n_results = 0;
     const bool f64 = c->prm.dtype == PFE_FP64;
     const size_t nd = (size_t)c->n * c->d * c->esz;
-    struct Shape { int persistent, team, cache, strips; };
-    const Shape shapes[] = {{1, 64, 1, 0}, {1, 64, 0, 0}, {1, 1, 1, 0}, {1, 1, 0, 0}, {0, c->team, 0, 0},
-                            {0, c->team, 0, 1}, {0, c->team, 0, 2}};
-    const Shape orig{c->prm.persistent, c->team, c->want_cache, c->want_strips};
+    struct Shape { int persistent, team, cache, strips; double w2; };
+    const Shape shapes[] = {{1, 64, 1, 0, 1.0}, {1, 64, 0, 0, 1.0}, {1, 1, 1, 0, 1.0}, {1, 1, 0, 0, 1.0},
+                            {1, 1, 1, 0, 0.9}, {1, 1, 0, 0, 0.9}, {1, 1, 1, 0, 0.85}, {1, 1, 0, 0, 0.85},
+                            {1, 1, 1, 0, 0.8}, {1, 1, 0, 0, 0.8},
+                            {0, c->team, 0, 0, 1.0}, {0, c->team, 0, 1, 1.0}, {0, c->team, 0, 2, 1.0}};
+    const Shape orig{c->prm.persistent, c->team, c->want_cache, c->want_strips, c->second_weight};
     char* save = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     pfe_status st = PFE_OK;
@@ -3752,10 +3771,12 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
             const Shape& sh = shapes[k];
             if (sh.persistent && (c->coop < kNumXcd || c->prm.precond != PFE_JACOBI)) continue;
             if (sh.strips && c->strip_slots == 0) continue;
+            if (sh.w2 != 1.0 && c->per_cu != 2) continue;
             c->prm.persistent = sh.persistent;
             c->team = sh.team;
             c->want_cache = sh.cache;
             c->want_strips = sh.strips;
+            c->second_weight = sh.w2;
             if ((st = setup_strips(c)) != PFE_OK) break;
             if (sh.strips && c->ps.nblk == 0) continue;
             if (sh.persistent) {
@@ -3781,6 +3802,7 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
             r.team = sh.team;
             r.row_cache = sh.persistent ? (c->cache_np > 0) : 0;
             r.strips = sh.strips;
+            r.second_weight = sh.persistent ? sh.w2 : 1.0;
             r.workgroups = sh.persistent ? c->pc.nblk : (sh.strips ? c->ps.nblk : c->pm.nblk);
             r.ms = ms / trials;
             found.push_back(r);
@@ -3793,12 +3815,14 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
         c->team = found[best].persistent ? found[best].team : orig.team;
         c->want_cache = found[best].persistent ? found[best].row_cache : orig.cache;
         c->want_strips = found[best].persistent ? orig.strips : found[best].strips;
+        c->second_weight = found[best].persistent ? found[best].second_weight : orig.w2;
         found[best].chosen = 1;
     } else {
         c->prm.persistent = orig.persistent;
         c->team = orig.team;
         c->want_cache = orig.cache;
         c->want_strips = orig.strips;
+        c->second_weight = orig.w2;
     }
     pfe_status s2 = setup_persistent(c);
     if (s2 == PFE_OK) s2 = setup_strips(c);

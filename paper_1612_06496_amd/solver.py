@@ -150,12 +150,13 @@ class Solver:
 
     def autotune(self, trials: int = 2) -> list:
         """Time the candidate launch shapes on this graph and keep the fastest."""
-        res = (L.pfe_tune_result * 8)()
+        res = (L.pfe_tune_result * 16)()
         n = C.c_int()
-        L.check(L.lib.pfe_autotune(self._h, int(trials), res, 8, C.byref(n)), "pfe_autotune",
+        L.check(L.lib.pfe_autotune(self._h, int(trials), res, 16, C.byref(n)), "pfe_autotune",
                 allow=(L.PFE_E_NOCONV,))
         return [dict(persistent=r.persistent, team=r.team, row_cache=r.row_cache, strips=r.strips,
-                     workgroups=r.workgroups, ms=r.ms, chosen=r.chosen) for r in res[:n.value]]
+                     second_weight=r.second_weight, workgroups=r.workgroups, ms=r.ms, chosen=r.chosen)
+                for r in res[:n.value]]
 
     # -- state ---------------------------------------------------------------
     def get(self, which: str) -> torch.Tensor:
