@@ -398,3 +398,26 @@ def test_graph_replay_is_bitwise_neutral():
         out.append((to_np(S.get("Y")), to_np(S.get("P")), info["cg_iters_total"]))
     assert out[0][2] == out[1][2]
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_second_workgroup_weight_partition(monkeypatch):
+    """Persistent, teams of one workgroup: giving the second workgroup placed
+    on each CU a smaller share of the rows changes only which rows each
+    workgroup owns, so one SOC iteration agrees with the equal split up to the
+    summation order of the FP64 partials, and stays bitwise reproducible."""
+    from paper_1612_06496_amd import Solver
+    banner("second-workgroup row weight (481x321)")
+    wl = load("voronoi481x321_8nbr")
+    G = gpu_graph(wl)
+    monkeypatch.setenv("PFE_TEAM", "1")
+    out = []
+    for w in ("1.0", "0.8", "0.8"):
+        monkeypatch.setenv("PFE_SECOND_WEIGHT", w)
+        S = Solver(G, wl.y0, lam=2000.0, r=2000.0, n_inner=3, tol=1e-6, maxit=1000, persistent=True)
+        info = S.solve(1, info=True)
+        assert info["workgroups"] == 512
+        out.append((to_np(S.get("Y")), to_np(S.get("P"))))
+    e = max(rel(out[1][k], out[0][k]) for k in range(2))
+    print(f"weighted vs equal rows: rel {e:.2e}")
+    assert e <= 1e-5
+    assert all(np.array_equal(out[1][k], out[2][k]) for k in range(2))
