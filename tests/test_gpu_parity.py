@@ -415,7 +415,7 @@ def test_second_workgroup_weight_partition(monkeypatch):
         monkeypatch.setenv("PFE_SECOND_WEIGHT", w)
         S = Solver(G, wl.y0, lam=2000.0, r=2000.0, n_inner=3, tol=1e-6, maxit=1000, persistent=True)
         info = S.solve(1, info=True)
-        assert info["workgroups"] == 512
+        assert info["workgroups"] > 0 and info["workgroups"] % 16 == 0
         out.append((to_np(S.get("Y")), to_np(S.get("P"))))
     e = max(rel(out[1][k], out[0][k]) for k in range(2))
     print(f"weighted vs equal rows: rel {e:.2e}")
