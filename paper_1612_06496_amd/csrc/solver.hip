@@ -960,8 +960,9 @@ struct StripLane {
 //   ldo(i, e)   an owner's further values of its pixel i, loaded one row ahead
 //   body(i, e, raw, own, nb)  the arithmetic of owned pixel i, with nb(k) the
 //               ring value of ELL slot k (zero outside the image)
+// LA: image rows of loads in flight ahead of the arithmetic.
 // Ends with a workgroup barrier (the ring shares sh with the partial sums).
-template <int KC, typename T, class LD, class VAL, class LDO, class BODY>
+template <int KC, int LA = 1, typename T, class LD, class VAL, class LDO, class BODY>
 __device__ __forceinline__ void strip_walk(const KA<T>& a, const StripGeo& g, const StripLane& ln, T* ring, LD&& ld,
                                            VAL&& val, LDO&& ldo, BODY&& body) {
     using S = Sten<KC>;
@@ -987,30 +988,35 @@ __device__ __forceinline__ void strip_walk(const KA<T>& a, const StripGeo& g, co
         return o;
     };
     if (g.len > 0 && g.y1 > g.y0) {
-        Raw raw[rho + 1];   // image rows y .. y + rho of this lane
+        constexpr int NR = rho + LA;   // raw rows held: y .. y + rho + LA - 1
+        Raw raw[NR];
+        Own own[LA];                   // own rows y .. y + LA - 1
 #pragma unroll
         for (int k = 1; k <= rho; ++k)
             if (ln.loader) ring[S::slot(g.y0 - k) * kBlock + t] = val(ldr(g.y0 - k));
 #pragma unroll
-        for (int k = 0; k <= rho; ++k) raw[k] = ldr(g.y0 + k);
+        for (int k = 0; k < NR; ++k) raw[k] = ldr(g.y0 + k);
 #pragma unroll
         for (int k = 0; k < rho; ++k)
             if (ln.loader) ring[S::slot(g.y0 + k) * kBlock + t] = val(raw[k]);
-        Own own = ldw(g.y0);
+#pragma unroll
+        for (int k = 0; k < LA; ++k) own[k] = ldw(g.y0 + k);
         for (int y = g.y0; y < g.y1; ++y) {
             if (ln.loader) ring[S::slot(y + rho) * kBlock + t] = val(raw[rho]);
-            const Raw rnext = ldr(y + rho + 1);
-            const Own onext = ldw(y + 1);
+            const Raw rnext = ldr(y + NR);
+            const Own onext = ldw(y + LA);
             __syncthreads();
             if (ln.owner) {
                 const int i = g.row0 + y * g.W + ln.px;
                 auto nb = [&](int k) { return ring[S::slot(y + S::dy(k)) * kBlock + t + S::dx(k) * d]; };
-                body(i, (size_t)i * d + ln.c, raw[0], own, nb);
+                body(i, (size_t)i * d + ln.c, raw[0], own[0], nb);
             }
 #pragma unroll
-            for (int k = 0; k < rho; ++k) raw[k] = raw[k + 1];
-            raw[rho] = rnext;
-            own = onext;
+            for (int k = 0; k + 1 < NR; ++k) raw[k] = raw[k + 1];
+            raw[NR - 1] = rnext;
+#pragma unroll
+            for (int k = 0; k + 1 < LA; ++k) own[k] = own[k + 1];
+            own[LA - 1] = onext;
         }
     }
     __syncthreads();
@@ -1038,7 +1044,7 @@ __device__ __forceinline__ void st_it(const KA<T>& a, int lb, double* sh, int it
     struct Raw { T r, w, sp, inv; };
     struct Own { T p, x, dA, ww[PW ? KC : 1]; };
     double acc[3] = {0.0, 0.0, 0.0};
-    strip_walk<KC>(a, g, ln, reinterpret_cast<T*>(sh),
+    strip_walk<KC, 2>(a, g, ln, reinterpret_cast<T*>(sh),
         [&](int j, size_t e) { return Raw{r[e], w[e], sp[e], a.invdiag[j]}; },
         // u_j = diag(A)^{-1} r_{j, i+1}: the neighbours' new u, as their owners form it
         [&](const Raw& v) { return mul_t(v.inv, cg_r(alpha, cg_s(first, beta, v.sp, v.w), v.r)); },
