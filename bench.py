@@ -93,18 +93,31 @@ def copy_bandwidth(gib):
     return best
 
 
+def load_graph(name, seed):
+    """(workload, Graph) of a named image or point-cloud workload."""
+    import synth
+    from paper_1612_06496_amd import Graph
+    if name in synth.EDGE_WORKLOADS:
+        wl = synth.make_edges_workload(name, seed)
+        return wl, Graph.edges(wl.n, wl.src, wl.dst, wl.dist2, wl.sigma)
+    wl = synth.make_workload(name, seed)
+    return wl, Graph.grid(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
+
+
 def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0), captures=6, steps=300,
-                lr=3e-3, workload="voronoi1024_r2", n_outer=2):
+                lr=3e-3, workload="voronoi1024_r2", train_workload=None, n_outer=2):
     """PCG iterations to 1e-6 with the learned preconditioner vs Jacobi.
 
     Training data: residuals of PFE inner solves on held-out images (training
     seeds) at every lambda/r of the sweep.  Evaluation on the evaluation image
     (seed 0): from the same start, one untimed SOC iteration, then n_outer
     timed ones (n_outer x n_inner solves) with each preconditioner in its
-    fastest launch mode (Jacobi: the autotuned shape, persistent or one launch
-    per phase on image strips; learned: one launch per phase with the PCG
-    replayed from HIP graphs); the network's factor inference is timed
-    separately (once per graph and penalties)."""
+    fastest launch mode (Jacobi: the shape autotuned at the first ratio,
+    persistent or one launch per phase, on image strips for pixel grids;
+    learned: one launch per phase with the PCG replayed from HIP graphs); the
+    network's factor inference is timed separately (once per graph and
+    penalties).  train_workload: the workload of the training images (default:
+    the evaluation workload; the network is size-independent)."""
     import numpy as np
     import torch
 
@@ -115,8 +128,7 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
     samples = []
     keep = []
     for seed in train_seeds:
-        wl = synth.make_workload(workload, seed)
-        G = Graph.grid(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
+        wl, G = load_graph(train_workload or workload, seed)
         S = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=3000, persistent=False,
                    graphs=True)
         c = 1.0 / S.edge_quantile(0.99)
@@ -140,15 +152,15 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
     t_train = time.perf_counter() - t_start
     del keep, samples
 
-    wl = synth.make_workload(workload, 0)
-    G = Graph.grid(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
+    wl, G = load_graph(workload, 0)
     c = 1.0 / Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=1, persistent=False).edge_quantile(0.99)
     rows = []
+    jshape = None
     for ratio in ratios:
         res = {"lambda_over_r": ratio}
         for pre in ("jacobi", "learned"):
             S = Solver(G, wl.y0, lam=ratio * c, r=c, n_inner=wl.n_inner, tol=wl.tol, maxit=5000,
-                       persistent=(pre == "jacobi"), graphs=True)
+                       persistent=(pre == "jacobi" and (jshape is None or jshape["persistent"] == 1)), graphs=True)
             factor_ms = None
             shape = None
             if pre == "learned":
@@ -157,8 +169,10 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
                 S.set_learned(net)
                 torch.cuda.synchronize()
                 factor_ms = round((time.perf_counter() - t0) * 1e3, 2)
+            elif jshape is None:
+                shape = jshape = [t for t in S.autotune(trials=1) if t["chosen"]][0]
             else:
-                shape = [t for t in S.autotune(trials=1) if t["chosen"]][0]
+                shape = jshape   # persistent or not as autotuned at the first ratio (other knobs default)
             S.solve(1, allow_noconv=True)
             S.stats(reset=True)
             torch.cuda.synchronize()
@@ -178,7 +192,8 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
                 res[pre]["ms_per_solve_amortised"] = round(res[pre]["ms_per_solve"] + factor_ms / max(1, info["solves"]), 3)
             del S
         rows.append(res)
-    return {"workload": workload, "d": wl.d, "train_images": list(train_seeds), "train_steps": steps,
+    return {"workload": workload, "train_workload": train_workload or workload, "n": wl.n, "d": wl.d,
+            "train_images": list(train_seeds), "train_steps": steps,
             "train_samples": len(train_seeds) * len(ratios) * captures, "loss_first": round(losses[0], 4),
             "loss_last10": round(float(np.mean(losses[-10:])), 4), "train_s": round(t_train, 1),
             "run": f"{n_outer} SOC iterations x {wl.n_inner} inner solves per preconditioner and lambda/r",
@@ -232,6 +247,11 @@ def main():
                     help="one-launch-per-phase PCG launched from the host instead of replayed from HIP graphs")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shape instead of autotuning it before timing")
+    ap.add_argument("--learned-workload", default="voronoi1024_r2",
+                    help="evaluation graph of the learned-vs-Jacobi leg (an image or a point-cloud workload)")
+    ap.add_argument("--learned-train-workload", default=None,
+                    help="training graphs of the learned leg (default: the evaluation workload)")
+    ap.add_argument("--learned-outer", type=int, default=2, help="timed SOC iterations per preconditioner and ratio")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="a single-image workload or an image batch (block-diagonal union) from synth")
     args = ap.parse_args()
@@ -319,7 +339,8 @@ def main():
         "roofline": roof,
     }
     if not args.no_learned and default:
-        leg = learned_leg()
+        leg = learned_leg(workload=args.learned_workload, train_workload=args.learned_train_workload,
+                          n_outer=args.learned_outer)
         line["learned_vs_jacobi"] = leg
         line["pcg_iters_learned"] = {str(r["lambda_over_r"]): {"jacobi_mean": r["jacobi"]["iters_mean"],
                                                                "learned_mean": r["learned"]["iters_mean"],

@@ -12,7 +12,7 @@ from typing import Optional
 import numpy as np
 
 from .voronoi import voronoi_image, image_features, batch_image_shapes
-from .points import gaussian_mixture, knn_edge_list
+from .points import gaussian_mixture, knn_edge_list, knn_edge_list_torch
 from .embed import smooth_y0, gaussian_y0
 
 
@@ -89,6 +89,36 @@ WORKLOADS = {
     "voronoi48x40_r2": dict(H=40, W=48, K=6, noise=0.05, stencil=-2, d=16,
                             n_outer=3, n_inner=3, tol=1e-6),
 }
+
+
+# Gaussian-mixture point clouds with symmetrised exact k-NN graphs (edge
+# lists), generated on a torch device (2 M points: about 4e12 candidate
+# distances): 20 components in R^32, means N(0, 4 I), unit covariance,
+# Dirichlet(1) weights, k = 16, sigma = median k-NN distance, d = 20.
+EDGE_WORKLOADS = {
+    "gmm2m_knn16": dict(n=2_000_000, m=32, components=20, k=16, d=20, n_outer=20, n_inner=10, tol=1e-6),
+    # same distribution at a tenth of the size (training graphs for the learned
+    # preconditioner of the 2 M-point graph)
+    "gmm200k_knn16": dict(n=200_000, m=32, components=20, k=16, d=20, n_outer=20, n_inner=10, tol=1e-6),
+}
+
+
+def make_edges_workload(name: str, seed: int = 0, device="cuda") -> Workload:
+    """A named point-cloud workload; src, dst, dist2 are torch tensors on
+    `device` (the k-NN search runs there)."""
+    import torch
+    if name not in EDGE_WORKLOADS:
+        raise KeyError(f"unknown edge workload {name!r}; known: {sorted(EDGE_WORKLOADS)}")
+    cfg = dict(EDGE_WORKLOADS[name])
+    n, m, comps, k = cfg.pop("n"), cfg.pop("m"), cfg.pop("components"), cfg.pop("k")
+    pts, labels = gaussian_mixture(n, m, comps, seed)
+    src, dst, dist2, knn_dist = knn_edge_list_torch(pts, k, device=device)
+    sigma = float(torch.median(knn_dist))
+    y0 = gaussian_y0(n, cfg["d"], seed + 7919)
+    return Workload(name=name, kind="edges", n=n, d=cfg["d"], sigma=sigma,
+                    n_outer=cfg["n_outer"], n_inner=cfg["n_inner"], tol=cfg["tol"], lam=None, r=None,
+                    n_clusters=comps, y0=y0, labels=labels, src=src, dst=dst, dist2=dist2,
+                    meta=dict(seed=seed, k=k, m=m))
 
 
 # Batches of uneven images (one problem per image, solved side by side):
