@@ -954,13 +954,12 @@ struct StripLane {
 
 // Walk the strip of workgroup lb one image row at a time.
 //   ld(j, e)    this lane's raw values of pixel j (element e = j d + c), loaded
-//               one image row ahead; value-initialised (zero) outside the image
-//               and outside the rows the strip reads
+//               LA image rows ahead of their publication; value-initialised
+//               (zero) outside the image and outside the rows the strip reads
 //   val(raw)    the value the lane publishes into the ring for its pixel
-//   ldo(i, e)   an owner's further values of its pixel i, loaded one row ahead
+//   ldo(i, e)   an owner's further values of its pixel i, loaded LA rows ahead
 //   body(i, e, raw, own, nb)  the arithmetic of owned pixel i, with nb(k) the
 //               ring value of ELL slot k (zero outside the image)
-// LA: image rows of loads in flight ahead of the arithmetic.
 // Ends with a workgroup barrier (the ring shares sh with the partial sums).
 template <int KC, int LA = 1, typename T, class LD, class VAL, class LDO, class BODY>
 __device__ __forceinline__ void strip_walk(const KA<T>& a, const StripGeo& g, const StripLane& ln, T* ring, LD&& ld,
