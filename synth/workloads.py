@@ -100,7 +100,34 @@ EDGE_WORKLOADS = {
     # same distribution at a tenth of the size (training graphs for the learned
     # preconditioner of the 2 M-point graph)
     "gmm200k_knn16": dict(n=200_000, m=32, components=20, k=16, d=20, n_outer=20, n_inner=10, tol=1e-6),
+    # the same graphs with the vertices relabelled in reverse Cuthill-McKee
+    # order (input preparation that gives neighbour gathers locality; the
+    # sampled points are i.i.d., so their order is arbitrary)
+    "gmm2m_knn16_rcm": dict(n=2_000_000, m=32, components=20, k=16, d=20, n_outer=20, n_inner=10, tol=1e-6,
+                            order="rcm"),
+    "gmm200k_knn16_rcm": dict(n=200_000, m=32, components=20, k=16, d=20, n_outer=20, n_inner=10, tol=1e-6,
+                              order="rcm"),
 }
+
+
+def rcm_relabel(n: int, src, dst, dist2, *arrays):
+    """Relabel the vertices of an edge list (src < dst unique pairs) in reverse
+    Cuthill-McKee order.  Returns (src', dst', dist2', perm, relabelled arrays):
+    new vertex k is old vertex perm[k]; pairs re-sorted lexicographically;
+    per-vertex arrays reordered."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    A = sp.coo_matrix((np.ones(src.size, np.int8), (src, dst)), shape=(n, n)).tocsr()
+    perm = reverse_cuthill_mckee((A + A.T).tocsr(), symmetric_mode=True).astype(np.int64)
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n, dtype=np.int64)
+    a, b = inv[src], inv[dst]
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    order = np.argsort(lo * n + hi, kind="stable")
+    out = [lo[order].astype(np.int32), hi[order].astype(np.int32), np.asarray(dist2)[order], perm]
+    return tuple(out) + tuple(np.asarray(x)[perm] for x in arrays)
 
 
 def make_edges_workload(name: str, seed: int = 0, device="cuda") -> Workload:
@@ -111,9 +138,15 @@ def make_edges_workload(name: str, seed: int = 0, device="cuda") -> Workload:
         raise KeyError(f"unknown edge workload {name!r}; known: {sorted(EDGE_WORKLOADS)}")
     cfg = dict(EDGE_WORKLOADS[name])
     n, m, comps, k = cfg.pop("n"), cfg.pop("m"), cfg.pop("components"), cfg.pop("k")
+    order = cfg.pop("order", None)
     pts, labels = gaussian_mixture(n, m, comps, seed)
     src, dst, dist2, knn_dist = knn_edge_list_torch(pts, k, device=device)
     sigma = float(torch.median(knn_dist))
+    if order == "rcm":
+        s2, d2, w2, perm, labels = rcm_relabel(n, src.cpu().numpy(), dst.cpu().numpy(), dist2.cpu().numpy(), labels)
+        src = torch.as_tensor(s2, device=device)
+        dst = torch.as_tensor(d2, device=device)
+        dist2 = torch.as_tensor(w2, device=device)
     y0 = gaussian_y0(n, cfg["d"], seed + 7919)
     return Workload(name=name, kind="edges", n=n, d=cfg["d"], sigma=sigma,
                     n_outer=cfg["n_outer"], n_inner=cfg["n_inner"], tol=cfg["tol"], lam=None, r=None,

@@ -37,3 +37,20 @@ def test_knn_neighbour_property_tiny():
             assert (min(i, j), max(i, j)) in pairs
     deg = np.bincount(np.concatenate([src, dst]), minlength=len(x))
     assert deg.min() >= k
+
+
+def test_rcm_relabel_is_a_graph_isomorphism():
+    """Relabelling keeps the edge set (up to the permutation) and its weights,
+    and yields sorted unique pairs src < dst."""
+    from synth.workloads import rcm_relabel
+    pts, labels = synth.gaussian_mixture(400, 5, 4, 3)
+    src, dst, d2, _ = synth.knn_edge_list(pts, 6)
+    s2, t2, w2, perm, lab2 = rcm_relabel(len(pts), src, dst, d2, labels)
+    assert np.all(s2 < t2)
+    key = s2.astype(np.int64) * len(pts) + t2
+    assert np.all(np.diff(key) > 0)
+    assert np.array_equal(lab2, labels[perm])
+    back = {(min(perm[a], perm[b]), max(perm[a], perm[b])): w for a, b, w in zip(s2, t2, w2)}
+    orig = {(a, b): w for a, b, w in zip(src.tolist(), dst.tolist(), d2)}
+    assert back.keys() == orig.keys()
+    assert all(back[k] == orig[k] for k in orig)
