@@ -16,6 +16,9 @@ What it computes, with the passage each piece follows:
   Reading of the right-hand side: Eq. (6)/(13) print Q2 = B - P; the
   stationarity condition of the least-squares objective in Algorithm 2 gives
   P - B, which is used here (pinned by tests: argmin check and lambda = 0 case).
+* Stage II (Sec. IV, experiments): after the SOC iterations, Split-Bregman
+  iterations alone with the orthogonality constraint relaxed; read as
+  Algorithm 2 run with P and B frozen at their final values.
 * SOC outer loop (Algorithm 1): b and d start at zero for every outer step;
   Z = D^{1/2} Y + B; P = argmin ||P - Z|| s.t. P^T P = I, i.e. the polar factor
   of Z (default), or the Cholesky-QR factor Z R^{-1} (option); B = Z - P.
@@ -44,7 +47,7 @@ import scipy.sparse.linalg as spla
 __all__ = [
     "grid_edges", "heat_kernel", "Graph", "build_grid_graph", "build_edge_graph",
     "system_matrix", "shrink", "sb_rhs", "DirectSolver", "CGSolver", "pcg",
-    "sb_inner_step", "p_update", "soc_outer_step", "orthonormalize_init",
+    "sb_inner_step", "split_bregman", "p_update", "soc_outer_step", "orthonormalize_init",
     "PFEState", "pfe_run", "objective", "constraint_residual", "split_residual",
     "le_init", "shrink_active_scale", "kron_L", "kron_Dt", "vec", "unvec",
     "kronecker_memory", "kmeans_agreement", "jacobi_condition_number",
@@ -267,16 +270,29 @@ def p_update(Z, mode: str = "polar"):
     raise ValueError(mode)
 
 
+def split_bregman(g: Graph, solve, Y, P, B, lam: float, r: float, n_iter: int):
+    """SplitBregman(M, D, P, B) of Algorithm 2 for a fixed number of
+    iterations: b = d = 0 at the start, then n_iter inner steps with P and B
+    held fixed.  Returns (Y, b, dd) after the last step.
+
+    This is both the Y-update inside a SOC iteration and, run on its own with
+    the final P and B, Stage II of the two-stage procedure of the experiments
+    (Sec. IV: orthogonality no longer enforced, only Split-Bregman iterations;
+    reading: P and B frozen at the values Stage I ends with)."""
+    d = Y.shape[1]
+    b = np.zeros((g.n_edges, d))
+    dd = np.zeros((g.n_edges, d))
+    for _ in range(n_iter):
+        Y, b, dd = sb_inner_step(g, solve, Y, P, B, b, dd, lam, r)
+    return Y, b, dd
+
+
 def soc_outer_step(g: Graph, solve, Y, P, B, lam, r, n_inner, mode="polar",
                    return_split=False):
     """One SOC iteration (Algorithm 1): the Y-update by n_inner Split-Bregman
     iterations started from b = d = 0 (Algorithm 2 initialisation), then the
     P-update and the B-update."""
-    d = Y.shape[1]
-    b = np.zeros((g.n_edges, d))
-    dd = np.zeros((g.n_edges, d))
-    for _ in range(n_inner):
-        Y, b, dd = sb_inner_step(g, solve, Y, P, B, b, dd, lam, r)
+    Y, b, dd = split_bregman(g, solve, Y, P, B, lam, r, n_inner)
     Z = np.sqrt(g.D)[:, None] * Y + B
     P = p_update(Z, mode)
     B = Z - P

@@ -229,6 +229,45 @@ def test_split_bregman_converges_to_eq5_minimiser():
     assert np.abs(stat).max() < 1e-8
 
 
+def test_stage2_split_bregman_reaches_dual_certified_minimiser():
+    """Stage II (Algorithm 2 alone, P and B frozen) converges, for any split
+    penalty lambda, to the minimiser of ||M Y||_1 + r/2 ||D^{1/2} Y - P + B||^2,
+    column by column.  The minimiser comes from the dual problem, a box-constrained
+    QP over |z| <= 1 (||M y||_1 = max z^T M y) solved by L-BFGS-B, with
+    y = D^{-1/2} (q - D^{-1/2} M^T z / r); the primal-dual gap certifies it."""
+    g = tiny_graph(12, seed=21, extra=6)
+    d, r = 3, 1.2
+    rng = np.random.default_rng(22)
+    P = rng.normal(size=(g.n, d))
+    B = 0.3 * rng.normal(size=(g.n, d))
+    M = g.M.toarray()
+    sD = np.sqrt(g.D)
+    K = M / sD[None, :]
+    H = K @ K.T / r
+    Ystar = np.zeros((g.n, d))
+    for k in range(d):
+        q = (P - B)[:, k]
+        c = K @ q
+        res = sopt.minimize(lambda z: (0.5 * z @ H @ z - z @ c, H @ z - c), np.zeros(g.n_edges), jac=True,
+                            method="L-BFGS-B", bounds=[(-1.0, 1.0)] * g.n_edges,
+                            options=dict(ftol=1e-16, gtol=1e-13, maxiter=20000, maxcor=50))
+        z = res.x
+        y = (q - K.T @ z / r) / sD
+        primal = np.abs(M @ y).sum() + r / 2 * np.sum((sD * y - q) ** 2)
+        dual = c @ z - 0.5 * z @ H @ z
+        print(f"column {k}: primal {primal:.12f}, duality gap {primal - dual:.2e}")
+        assert primal - dual <= 1e-7 * primal
+        Ystar[:, k] = y
+    for lam in (0.7, 2.0, 5.0):
+        solve = O.DirectSolver(O.system_matrix(g, lam, r))
+        Y, b, dd = O.split_bregman(g, solve, np.zeros((g.n, d)), P, B, lam, r, 1000)
+        err = np.abs(Y - Ystar).max()
+        print(f"lambda {lam}: Stage II after 1000 iterations vs dual minimiser {err:.2e}")
+        assert err <= 1e-7
+        # the split variables are consistent with the edge differences at the limit
+        assert np.abs(dd - g.M @ Y).max() <= 1e-6
+
+
 # --- P7/P8: P-update ---------------------------------------------------------------
 
 def test_p7_polar_update_properties():
