@@ -26,9 +26,15 @@ WORKLOAD = "voronoi481x321_8nbr"
 PEAK_HBM_GBS = 8000.0
 
 
-def algorithmic_bytes(n, E, d, esz, cg_iters, solves, n_inner, n_outer):
+def progress(msg):
+    """A line on stderr when a leg of the benchmark ends (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(n, E, d, esz, cg_iters, solves, n_inner, n_outer, pupdate=True):
     """Bytes the method has to move per the model stated in the design doc
-    (FP32 values, int32 indices), summed over n_outer SOC iterations."""
+    (FP32 values, int32 indices), summed over n_outer SOC iterations (without
+    the P- and B-update when pupdate is False: Split Bregman alone)."""
     rowptr = 4 * (n + 1)
     csr = 8 * 2 * E + rowptr                  # column index + weight per directed slot
     nd = n * d * esz
@@ -36,7 +42,7 @@ def algorithmic_bytes(n, E, d, esz, cg_iters, solves, n_inner, n_outer):
     first_res = csr + 3 * n * esz + 4 * nd      # P, B, x -> r
     edge_res = csr + 3 * n * esz + 4 * nd + 2 * E * d * esz + 4 * E  # + b read/write per edge
     ortho = 2 * n * esz + 6 * nd                # Gram (Y, B) + apply (Y, B -> P, B)
-    per_outer_fixed = first_res + (n_inner - 1) * edge_res + ortho
+    per_outer_fixed = first_res + (n_inner - 1) * edge_res + (ortho if pupdate else 0)
     return cg_iters * cg_iter + n_outer * per_outer_fixed
 
 
@@ -151,6 +157,7 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
         losses.append(net.train_step(S, R, lr))
     t_train = time.perf_counter() - t_start
     del keep, samples
+    progress(f"learned leg: {steps} training steps in {t_train:.1f} s")
 
     wl, G = load_graph(workload, 0)
     c = 1.0 / Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=1, persistent=False).edge_quantile(0.99)
@@ -192,6 +199,7 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
                 res[pre]["ms_per_solve_amortised"] = round(res[pre]["ms_per_solve"] + factor_ms / max(1, info["solves"]), 3)
             del S
         rows.append(res)
+        progress(f"learned leg: lambda/r = {ratio} done")
     return {"workload": workload, "train_workload": train_workload or workload, "n": wl.n, "d": wl.d,
             "train_images": list(train_seeds), "train_steps": steps,
             "train_samples": len(train_seeds) * len(ratios) * captures, "loss_first": round(losses[0], 4),
@@ -252,6 +260,8 @@ def main():
     ap.add_argument("--learned-train-workload", default=None,
                     help="training graphs of the learned leg (default: the evaluation workload)")
     ap.add_argument("--learned-outer", type=int, default=2, help="timed SOC iterations per preconditioner and ratio")
+    ap.add_argument("--stage2-iters", type=int, default=100,
+                    help="Split-Bregman iterations of the timed Stage II run after the SOC iterations (0: skip)")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="a single-image workload or an image batch (block-diagonal union) from synth")
     args = ap.parse_args()
@@ -286,6 +296,7 @@ def main():
     # the launch shape (persistent or one launch per phase, teams, LDS row
     # cache, image strips) is picked by timing each on this graph; untimed
     tuned = None if args.no_autotune else S.autotune(trials=2)
+    progress("launch shape picked" if tuned else "launch shape kept")
 
     for _ in range(args.warmup):
         S.solve(1)
@@ -302,6 +313,7 @@ def main():
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop)
     info = S.stats(reset=True)          # CG iterations of the timed steps
+    progress(f"{args.steps} timed SOC iterations: {ms:.1f} ms")
     mon = S.monitor()
     ms_per_step = ms / args.steps
     value = args.steps / (ms / 1e3)
@@ -338,6 +350,24 @@ def main():
         "wall_s_timed": round(wall, 4),
         "roofline": roof,
     }
+    if args.stage2_iters > 0:
+        # Stage II of the two-stage procedure: Split Bregman alone with P and B
+        # frozen at the values the timed SOC iterations ended with
+        torch.cuda.synchronize()
+        start.record()
+        S.split_bregman(args.stage2_iters)
+        stop.record()
+        torch.cuda.synchronize()
+        ms2 = start.elapsed_time(stop)
+        i2 = S.stats(reset=True)
+        progress(f"Stage II, {args.stage2_iters} Split-Bregman iterations: {ms2:.1f} ms")
+        b2 = algorithmic_bytes(n, E, d, 4, i2["cg_iters_total"], i2["solves"], args.stage2_iters, 1, pupdate=False)
+        line["stage2"] = {"iterations": args.stage2_iters, "ms": round(ms2, 3),
+                          "sb_iters_per_s": round(args.stage2_iters / (ms2 / 1e3), 1),
+                          "pcg_iters_per_solve": round(i2["cg_iters_total"] / max(1, i2["solves"]), 2),
+                          "launch": "persistent" if i2["workgroups"] else ("strips" if i2["flags"] & 2 else "multi"),
+                          "algorithmic_gbs": round(b2 / (ms2 / 1e3) / 1e9, 1),
+                          "frac": round(b2 / (ms2 / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
     if not args.no_learned and default:
         leg = learned_leg(workload=args.learned_workload, train_workload=args.learned_train_workload,
                           n_outer=args.learned_outer)
@@ -352,6 +382,7 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wls, c, c)
         line["cpu_baseline"]["value"] = round(line["cpu_baseline"]["value"], 4)
+        progress("CPU baseline (oracle) done")
     print(json.dumps(line), flush=True)
 
 

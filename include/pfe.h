@@ -231,6 +231,18 @@ pfe_status pfe_step(pfe_ctx* c, int granularity, pfe_step_info* info);
 /* n_outer calls of pfe_step(PFE_OUTER) (Algorithm 1 for a fixed count). */
 pfe_status pfe_solve(pfe_ctx* c, int n_outer, pfe_step_info* info);
 
+/* Stage II of the paper's two-stage procedure (Sec. IV, experiments): after
+ * the SOC iterations, the orthogonality constraint is relaxed and only
+ * Split-Bregman iterations run.  Here: n_iter >= 0 iterations of Algorithm 2
+ * from b = d = 0 with P and B held at their current values (each a PCG solve
+ * of Eq. (13) warm-started from the current Y, then Eqs. (9) and (10)), in the
+ * context's launch shape.  On return Y (device state) holds the iterate of the
+ * last solve; P and B are unchanged; b and d are not part of the result (the
+ * context stays between SOC iterations, so a later SOC iteration starts them
+ * from zero).  PFE_E_STATE inside a SOC iteration (inner index > 0); solver
+ * statuses as for pfe_step. */
+pfe_status pfe_split_bregman(pfe_ctx* c, int n_iter, pfe_step_info* info);
+
 /* Launch shape of the solver (how the same arithmetic is mapped on the GPU):
  * persistent (one cooperative launch per SOC iteration) or one launch per
  * phase; team = workgroups that deal an XCD band's row chunks out cyclically

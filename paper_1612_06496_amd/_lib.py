@@ -86,6 +86,7 @@ SIGNATURES = {
     "pfe_set_penalties": (_S, [_P, C.c_double, C.c_double]),
     "pfe_step": (_S, [_P, C.c_int, C.POINTER(pfe_step_info)]),
     "pfe_solve": (_S, [_P, C.c_int, C.POINTER(pfe_step_info)]),
+    "pfe_split_bregman": (_S, [_P, C.c_int, C.POINTER(pfe_step_info)]),
     "pfe_stats": (_S, [_P, C.POINTER(pfe_step_info), C.c_int]),
     "pfe_autotune": (_S, [_P, C.c_int, C.POINTER(pfe_tune_result), C.c_int, C.POINTER(C.c_int)]),
     "pfe_get": (_S, [_P, C.c_int, _P]),

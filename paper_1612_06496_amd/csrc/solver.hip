@@ -2283,6 +2283,7 @@ struct Plan {
     int n_inner;      // inner iterations per SOC iteration
     int n_outer;      // SOC iterations to run
     int cache_np;     // chunks per workgroup held in the LDS row cache (LC kernels)
+    int pupdate;      // 1: P- and B-update after the inner iterations; 0: Split Bregman alone
 };
 
 // Persistent path: whole SOC iterations in one cooperative launch.  One
@@ -2340,6 +2341,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                 }
             }
             l0 = 0;
+            if (!plan.pupdate) continue;
             ph_gram(a, lb, 0, sh);
             double* gp = gbuf();
             if (!grid_sync(a.bar, nb, S, nbar, [&](unsigned g) { group_reduce(a, g, npair, 1, sh, gp); },
@@ -2372,6 +2374,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
             }
         }
         l0 = 0;
+        if (!plan.pupdate) continue;
         ph_gram(a, lb, 0, sh);
         if (!grid_sync(a.bar, nb, S, nbar, NoFin{}, NoFin{})) return;
         const int sg = a.blk_seg[lb];
@@ -3198,18 +3201,25 @@ pfe_status setup_strips(pfe_ctx* c) {
     return PFE_OK;
 }
 
+// inner iteration l of a Split-Bregman run (l = 0: b = d = 0), one launch per phase
 template <typename T>
-pfe_status inner_mk(pfe_ctx* c) {
+pfe_status inner_at(pfe_ctx* c, int l) {
     KA<T> a = make_args<T>(c, c->pm);
     const KA<T> as = use_strips(c) ? make_args<T>(c, c->ps) : a;
-    PFE_TRY(launch_phase(c, as, (c->inner == 0) ? PH_E0 : PH_R0, 0, 1));
+    PFE_TRY(launch_phase(c, as, (l == 0) ? PH_E0 : PH_R0, 0, 1));
     PFE_TRY(pcg_any_mk(c, a, as));
     // edge update of this inner step and rhs of the next one (on strips when
     // the slot data are loaded one image row ahead, widths up to 8)
     KA<T> b = (as.geo && c->g->ell_K <= 8) ? as : a;
     b.store_rhs = 1;
-    b.b_zero = (c->inner == 0);
+    b.b_zero = (l == 0);
     PFE_TRY(launch_phase(c, b, PH_EU, 0, 0));
+    return PFE_OK;
+}
+
+template <typename T>
+pfe_status inner_mk(pfe_ctx* c) {
+    PFE_TRY(inner_at<T>(c, c->inner));
     c->inner += 1;
     return PFE_OK;
 }
@@ -3246,6 +3256,22 @@ const void* soc_kernel(int ell_K, bool lc) {
     }
 }
 
+// one cooperative launch of the persistent kernel: n_outer runs of n_inner
+// Split-Bregman iterations, each followed by the P- and B-update when pupdate
+template <typename T>
+pfe_status launch_soc(pfe_ctx* c, int n_inner, int n_outer, int pupdate) {
+    KA<T> a = make_args<T>(c, c->pc);
+    const bool lc = c->cache_np > 0;
+    Plan plan{0, n_inner, n_outer, lc ? c->cache_np : 0, pupdate};
+    const size_t dyn = lc ? row_cache_bytes<T>(c->cache_np, a.R, c->g->ell_K) : 0;
+    PFE_CHECK_HIP(hipMemsetAsync(c->bar, 0, 512 * sizeof(unsigned), c->stream));
+    void* args[] = {(void*)&a, (void*)&plan};
+    PFE_CHECK_HIP(hipLaunchCooperativeKernel(soc_kernel<T>(c->g->ell_K, lc), dim3(a.nblk), dim3(kBlock), args, dyn,
+                                             c->stream));
+    c->launched_coop = 1;
+    return PFE_OK;
+}
+
 template <typename T>
 pfe_status outer_coop(pfe_ctx* c, int n_outer) {
     if (c->inner > 0) {
@@ -3253,16 +3279,18 @@ pfe_status outer_coop(pfe_ctx* c, int n_outer) {
         PFE_TRY(outer_mk<T>(c));
         if (--n_outer == 0) return PFE_OK;
     }
-    KA<T> a = make_args<T>(c, c->pc);
-    const bool lc = c->cache_np > 0;
-    Plan plan{0, c->prm.n_inner, n_outer, lc ? c->cache_np : 0};
-    const size_t dyn = lc ? row_cache_bytes<T>(c->cache_np, a.R, c->g->ell_K) : 0;
-    PFE_CHECK_HIP(hipMemsetAsync(c->bar, 0, 512 * sizeof(unsigned), c->stream));
-    void* args[] = {(void*)&a, (void*)&plan};
-    PFE_CHECK_HIP(hipLaunchCooperativeKernel(soc_kernel<T>(c->g->ell_K, lc), dim3(a.nblk), dim3(kBlock), args, dyn,
-                                             c->stream));
-    c->launched_coop = 1;
+    PFE_TRY(launch_soc<T>(c, c->prm.n_inner, n_outer, 1));
     c->inner = 0;
+    return PFE_OK;
+}
+
+// Stage II: n_iter Split-Bregman iterations from b = d = 0 with P and B fixed,
+// in one persistent launch when the context runs that way, else one launch per
+// phase; the context stays between SOC iterations (inner index 0)
+template <typename T>
+pfe_status split_bregman_run(pfe_ctx* c, int n_iter) {
+    if (c->prm.persistent && c->pc.nblk > 0 && c->prm.precond == PFE_JACOBI) return launch_soc<T>(c, n_iter, 1, 0);
+    for (int l = 0; l < n_iter; ++l) PFE_TRY(inner_at<T>(c, l));
     return PFE_OK;
 }
 
@@ -3728,6 +3756,16 @@ pfe_status pfe_solve(pfe_ctx* c, int n_outer, pfe_step_info* info) {
     } else {
         for (int k = 0; k < n_outer; ++k) PFE_TRY(f64 ? outer_mk<double>(c) : outer_mk<float>(c));
     }
+    if (info) return read_info(c, info);
+    return PFE_OK;
+}
+
+pfe_status pfe_split_bregman(pfe_ctx* c, int n_iter, pfe_step_info* info) {
+    if (!c || n_iter < 0) { set_error("pfe_split_bregman: bad argument"); return PFE_E_ARG; }
+    if (c->inner != 0) { set_error("pfe_split_bregman: call between SOC iterations (inner index 0)"); return PFE_E_STATE; }
+    c->launched_coop = 0;
+    if (info) PFE_TRY(reset_stats(c));
+    if (n_iter > 0) PFE_TRY(c->prm.dtype == PFE_FP64 ? split_bregman_run<double>(c, n_iter) : split_bregman_run<float>(c, n_iter));
     if (info) return read_info(c, info);
     return PFE_OK;
 }

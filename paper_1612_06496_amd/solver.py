@@ -141,6 +141,13 @@ class Solver:
         L.check(st, "pfe_solve", allow=(L.PFE_E_NOCONV,) if allow_noconv else ())
         return self._info_dict(inf) if info else None
 
+    def split_bregman(self, n_iter: int, info: bool = False, allow_noconv: bool = False):
+        """Stage II: n_iter Split-Bregman iterations with P and B held fixed (pfe_split_bregman)."""
+        inf = L.pfe_step_info() if info else None
+        st = L.lib.pfe_split_bregman(self._h, int(n_iter), C.byref(inf) if info else None)
+        L.check(st, "pfe_split_bregman", allow=(L.PFE_E_NOCONV,) if allow_noconv else ())
+        return self._info_dict(inf) if info else None
+
     def stats(self, reset: bool = False, allow_noconv: bool = False) -> dict:
         """Statistics accumulated since the last reset."""
         inf = L.pfe_step_info()

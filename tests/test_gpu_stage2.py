@@ -1,0 +1,164 @@
+"""GPU Stage II: Split-Bregman iterations alone with P and B held fixed (the
+second stage of the paper's experimental procedure, Sec. IV), through the C ABI
+call pfe_split_bregman, against the oracle's split_bregman on the same seeded
+state, in the persistent and the one-launch-per-phase shapes.
+
+Bounds: the FP64 instantiation with PCG to 1e-12 follows the oracle's direct
+solves to ~1e-10 per iteration; FP32 with PCG to 1e-6 carries a per-iteration
+error of ~1e-6 that the Split-Bregman map does not amplify (the shrink and the
+Bregman update are 1-Lipschitz and the solve is a contraction in the A-norm),
+so after n iterations the error stays below n times the one-step bar of 1e-5
+and is checked against that."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_helpers import banner, gpu_graph, oracle_graph, penalties, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def to_np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def load(name, seed=0):
+    if name == "edges":
+        return synth.edges_workload("gmm_small", 900, 8, 4, 6, 3, d=5, n_outer=3, n_inner=3)
+    return synth.make_workload(name, seed)
+
+
+def oracle_state(g, wl, lam, r, n_outer_before):
+    """(solve, Y, P, B) after some SOC iterations of the oracle."""
+    Y = O.orthonormalize_init(g, wl.y0)
+    P = np.sqrt(g.D)[:, None] * Y
+    B = np.zeros_like(Y)
+    solve = O.DirectSolver(O.system_matrix(g, lam, r))
+    for _ in range(n_outer_before):
+        Y, P, B = O.soc_outer_step(g, solve, Y, P, B, lam, r, wl.n_inner)
+    return solve, Y, P, B
+
+
+def solver_at(wl, G, Y, P, B, lam, r, fp64, persistent, monkeypatch, strips="1"):
+    from paper_1612_06496_amd import Solver
+    monkeypatch.setenv("PFE_STRIPS", strips)
+    S = Solver(G, Y, lam=lam, r=r, n_inner=wl.n_inner, tol=1e-12 if fp64 else 1e-6, maxit=3000, fp64=fp64,
+               init_ortho=False, persistent=persistent)
+    S.set("Y", Y); S.set("P", P); S.set("B", B)
+    return S
+
+
+CASES = [("voronoi96x80_8nbr", False, True), ("voronoi96x80_8nbr", False, False),
+         ("voronoi64_4nbr", True, True), ("voronoi48x40_r2", True, False),
+         ("edges", False, True), ("edges", True, False)]
+
+
+@pytest.mark.parametrize("name,fp64,persistent", CASES)
+def test_stage2_matches_oracle(name, fp64, persistent, monkeypatch):
+    n_iter = 12
+    banner(f"stage II {name} fp64={fp64} persistent={persistent} n_iter={n_iter}")
+    wl = load(name)
+    g = oracle_graph(wl)
+    lam, r = penalties(wl, g, O.orthonormalize_init(g, wl.y0))
+    solve, Y, P, B = oracle_state(g, wl, lam, r, 2)
+    S = solver_at(wl, gpu_graph(wl), Y, P, B, lam, r, fp64, persistent, monkeypatch)
+    P_in, B_in = to_np(S.get("P")), to_np(S.get("B"))
+    info = S.split_bregman(n_iter, info=True)
+    Y_ref, b_ref, dd_ref = O.split_bregman(g, solve, Y, P, B, lam, r, n_iter)
+    eY = rel(to_np(S.get("Y")), Y_ref)
+    bound = 1e-9 if fp64 else n_iter * 1e-5
+    frac = np.mean(dd_ref != 0)
+    print(f"Y rel err {eY:.2e} (bound {bound:.1e}); solves {info['solves']}, CG iterations "
+          f"{info['cg_iters_total']}; launched persistent: {info['workgroups'] > 0 and persistent}; "
+          f"nonzero d fraction {frac:.4f}")
+    assert info["solves"] == n_iter
+    assert eY <= bound
+    # P and B are held fixed, bit for bit
+    assert np.array_equal(to_np(S.get("P")), P_in) and np.array_equal(to_np(S.get("B")), B_in)
+    assert S.inner_index == 0
+    if wl.lam is None:
+        assert frac > 0.0
+
+
+def test_stage2_then_soc_iteration_starts_from_zero_split(monkeypatch):
+    """After Stage II the context is between SOC iterations: the next SOC
+    iteration starts from b = d = 0 (Algorithm 2 initialisation)."""
+    wl = load("voronoi96x80_8nbr")
+    banner("stage II then SOC iteration")
+    g = oracle_graph(wl)
+    lam, r = penalties(wl, g, O.orthonormalize_init(g, wl.y0))
+    solve, Y, P, B = oracle_state(g, wl, lam, r, 1)
+    S = solver_at(wl, gpu_graph(wl), Y, P, B, lam, r, True, False, monkeypatch)
+    S.split_bregman(5)
+    S.step("outer")
+    Y1, _, _ = O.split_bregman(g, solve, Y, P, B, lam, r, 5)
+    Y2, P2, B2 = O.soc_outer_step(g, solve, Y1, P, B, lam, r, wl.n_inner)
+    eY, eP = rel(to_np(S.get("Y")), Y2), rel(to_np(S.get("P")), P2)
+    print(f"Y {eY:.2e} P {eP:.2e}")
+    assert eY <= 1e-9 and eP <= 1e-9
+
+
+def test_stage2_persistent_equals_multi_launch(monkeypatch):
+    wl = load("voronoi96x80_8nbr")
+    banner("stage II persistent vs one launch per phase (fp64)")
+    g = oracle_graph(wl)
+    lam, r = penalties(wl, g, O.orthonormalize_init(g, wl.y0))
+    _, Y, P, B = oracle_state(g, wl, lam, r, 1)
+    out = []
+    for persistent in (True, False):
+        S = solver_at(wl, gpu_graph(wl), Y, P, B, lam, r, True, persistent, monkeypatch)
+        info = S.split_bregman(8, info=True)
+        out.append((to_np(S.get("Y")), info["cg_iters_total"]))
+    e = rel(out[0][0], out[1][0])
+    print(f"rel diff {e:.2e}; CG iterations {out[0][1]} vs {out[1][1]}")
+    assert e <= 1e-10 and out[0][1] == out[1][1]
+
+
+def test_stage2_zero_iterations_and_inside_soc_iteration(monkeypatch):
+    from paper_1612_06496_amd._lib import PFEError
+    wl = load("voronoi64_4nbr")
+    banner("stage II argument and state checks")
+    g = oracle_graph(wl)
+    _, Y, P, B = oracle_state(g, wl, wl.lam, wl.r, 0)
+    S = solver_at(wl, gpu_graph(wl), Y, P, B, wl.lam, wl.r, True, True, monkeypatch)
+    Y_in = to_np(S.get("Y"))
+    assert S.split_bregman(0, info=True)["solves"] == 0
+    assert np.array_equal(to_np(S.get("Y")), Y_in)
+    with pytest.raises(PFEError):
+        S.split_bregman(-1)
+    S.step("inner")
+    with pytest.raises(PFEError):
+        S.split_bregman(3)
+
+
+def test_stage2_headline_image_in_bench_shape(monkeypatch):
+    """481x321, d = 10, 100 Split-Bregman iterations (the paper's Stage II
+    count) from the initial state, in the autotuned shape the benchmark uses,
+    against the oracle's direct solves."""
+    from paper_1612_06496_amd import Solver
+    n_iter = 100
+    wl = synth.make_workload("voronoi481x321_8nbr", 0)
+    banner(f"stage II 481x321 n_iter={n_iter} (autotuned shape)")
+    g = oracle_graph(wl)
+    Y0 = O.orthonormalize_init(g, wl.y0)
+    lam, r = penalties(wl, g, Y0)
+    P = np.sqrt(g.D)[:, None] * Y0
+    B = np.zeros_like(Y0)
+    S = Solver(gpu_graph(wl), Y0, lam=lam, r=r, n_inner=wl.n_inner, tol=1e-6, maxit=3000, init_ortho=False)
+    shapes = S.autotune(1)
+    S.set("Y", Y0); S.set("P", P); S.set("B", B)
+    P_in = to_np(S.get("P"))
+    info = S.split_bregman(n_iter, info=True)
+    Y_ref, _, dd_ref = O.split_bregman(g, O.DirectSolver(O.system_matrix(g, lam, r)), Y0, P, B, lam, r, n_iter)
+    eY = rel(to_np(S.get("Y")), Y_ref)
+    chosen = [s for s in shapes if s["chosen"]][0]
+    print(f"Y rel err {eY:.2e}; shape {chosen}; CG iterations per solve "
+          f"{info['cg_iters_total'] / max(1, info['solves']):.2f}; nonzero d fraction {np.mean(dd_ref != 0):.4f}")
+    assert info["solves"] == n_iter
+    assert eY <= 1e-4
+    assert np.array_equal(to_np(S.get("P")), P_in)
