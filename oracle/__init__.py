@@ -11,3 +11,4 @@ Parity status per function is listed in the module docstrings; every function
 here is pinned by a ``-m "not gpu"`` test in ``tests/test_oracle_*.py``.
 """
 from .pfe import *  # noqa: F401,F403
+from . import classical  # noqa: F401,E402
