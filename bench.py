@@ -112,7 +112,8 @@ def load_graph(name, seed):
 
 def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0), captures=6, steps=300,
                 lr=3e-3, workload="voronoi1024_r2", train_workload=None, n_outer=2):
-    """PCG iterations to 1e-6 with the learned preconditioner vs Jacobi.
+    """PCG iterations to 1e-6 with the learned preconditioner vs Jacobi, and
+    vs FSAI (a classical sparse approximate inverse factor of the same form).
 
     Training data: residuals of PFE inner solves on held-out images (training
     seeds) at every lambda/r of the sweep.  Evaluation on the evaluation image
@@ -120,9 +121,9 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
     timed ones (n_outer x n_inner solves) with each preconditioner in its
     fastest launch mode (Jacobi: the shape autotuned at the first ratio,
     persistent or one launch per phase, on image strips for pixel grids;
-    learned: one launch per phase with the PCG replayed from HIP graphs); the
-    network's factor inference is timed separately (once per graph and
-    penalties).  train_workload: the workload of the training images (default:
+    learned and FSAI: one launch per phase with the PCG replayed from HIP
+    graphs); the network's factor inference and the FSAI factor are timed
+    separately (once per graph and penalties).  train_workload: the workload of the training images (default:
     the evaluation workload; the network is size-independent)."""
     import numpy as np
     import torch
@@ -165,15 +166,18 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
     jshape = None
     for ratio in ratios:
         res = {"lambda_over_r": ratio}
-        for pre in ("jacobi", "learned"):
+        for pre in ("jacobi", "fsai", "learned"):
             S = Solver(G, wl.y0, lam=ratio * c, r=c, n_inner=wl.n_inner, tol=wl.tol, maxit=5000,
                        persistent=(pre == "jacobi" and (jshape is None or jshape["persistent"] == 1)), graphs=True)
             factor_ms = None
             shape = None
-            if pre == "learned":
+            if pre != "jacobi":
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                S.set_learned(net)
+                if pre == "learned":
+                    S.set_learned(net)
+                else:
+                    S.set_fsai()
                 torch.cuda.synchronize()
                 factor_ms = round((time.perf_counter() - t0) * 1e3, 2)
             elif jshape is None:
@@ -375,7 +379,9 @@ def main():
         line["pcg_iters_learned"] = {str(r["lambda_over_r"]): {"jacobi_mean": r["jacobi"]["iters_mean"],
                                                                "learned_mean": r["learned"]["iters_mean"],
                                                                "jacobi_max": r["jacobi"]["iters_max"],
-                                                               "learned_max": r["learned"]["iters_max"]}
+                                                               "learned_max": r["learned"]["iters_max"],
+                                                               "fsai_mean": r["fsai"]["iters_mean"],
+                                                               "fsai_max": r["fsai"]["iters_max"]}
                                      for r in leg["sweep"]}
     if args.copy_gib > 0:
         line["copy_gbs"] = round(copy_bandwidth(args.copy_gib), 1)

@@ -59,7 +59,7 @@ typedef enum {
 /* graph kinds */
 enum { PFE_GRID = 0, PFE_EDGES = 1 };
 /* preconditioners */
-enum { PFE_JACOBI = 0, PFE_LEARNED = 1 };
+enum { PFE_JACOBI = 0, PFE_LEARNED = 1, PFE_FSAI = 2 };
 /* P-update */
 enum { PFE_POLAR = 0, PFE_CHOL = 1 };
 /* element type of the vector state */
@@ -115,7 +115,8 @@ typedef struct {
  *   n_inner    Split-Bregman iterations per SOC iteration, >= 1
  *   tol        PCG stop: ||r_c|| <= tol ||rhs_c|| for every column c
  *   maxit      PCG iteration cap per solve
- *   precond    PFE_JACOBI or PFE_LEARNED (needs pfe_set_learned first)
+ *   precond    PFE_JACOBI, or PFE_LEARNED / PFE_FSAI (both apply the context's sparse
+ *              factor, set by pfe_set_learned or pfe_set_fsai; Gt = I until then)
  *   ortho      PFE_POLAR (exact argmin, default) or PFE_CHOL (Cholesky QR)
  *   dtype      PFE_FP32 (vectors, SpMM, shrink in float; CG scalars and Gram
  *              in double) or PFE_FP64 (everything in double)
@@ -342,7 +343,19 @@ pfe_status pfe_mpnn_train_step(pfe_mpnn* net, pfe_ctx* c, const void* samples, i
  * M^{-1} = G^T G (PFE_LEARNED).  The factor is kept until the next call;
  * pfe_set_penalties recomputes A but not the factor. */
 pfe_status pfe_set_learned(pfe_ctx* c, pfe_mpnn* net);
-/* Switch between PFE_JACOBI and PFE_LEARNED (which needs pfe_set_learned first). */
+/* Non-learned factor of the same form, for comparison: the factorized sparse
+ * approximate inverse (FSAI, Kolotilina and Yeremin; not in the paper, which
+ * uses incomplete Cholesky, Sec. III) on the lower pattern of A: row i of G
+ * solves A[S_i, S_i] g = e_i over S_i = {i} and the lower neighbours of i,
+ * scaled so that (G A G^T)_ii = 1; M^{-1} = G^T G, stored as Gt = G D_A^{1/2}
+ * like the learned factor (pfe_get_factor reads it back).  Computed on the
+ * device in FP64 from the context's A (one thread per row, a Cholesky
+ * factorisation of the local system) and switches the PCG to PFE_FSAI.
+ * Pixel-grid graphs only (4, 8 or 24 stencil slots): PFE_E_ARG otherwise.
+ * pfe_set_penalties recomputes A but not the factor. */
+pfe_status pfe_set_fsai(pfe_ctx* c);
+/* Switch between PFE_JACOBI and the factor preconditioners PFE_LEARNED and
+ * PFE_FSAI (the latter two apply whatever factor was set last). */
 pfe_status pfe_set_preconditioner(pfe_ctx* c, int precond);
 /* Copy the current factor: per undirected edge (lexicographic (i, j), i < j)
  * the entry Gt_ji, and the diagonal (device buffers, context element type). */

@@ -24,7 +24,7 @@ PFE_E_NOCONV = -7
 PFE_E_STATE = -8
 # enums
 PFE_GRID, PFE_EDGES = 0, 1
-PFE_JACOBI, PFE_LEARNED = 0, 1
+PFE_JACOBI, PFE_LEARNED, PFE_FSAI = 0, 1, 2
 PFE_POLAR, PFE_CHOL = 0, 1
 PFE_FP32, PFE_FP64 = 0, 1
 PFE_INNER, PFE_OUTER = 0, 1
@@ -104,6 +104,7 @@ SIGNATURES = {
     "pfe_mpnn_train_step": (_S, [_P, _P, _P, C.c_int, C.c_float, C.POINTER(C.c_double)]),
     "pfe_set_learned": (_S, [_P, _P]),
     "pfe_set_preconditioner": (_S, [_P, C.c_int]),
+    "pfe_set_fsai": (_S, [_P]),
     "pfe_get_factor": (_S, [_P, _P, _P]),
     "pfe_destroy_ctx": (None, [_P]),
     "pfe_stream_copy": (_S, [_P, _P, C.c_size_t, _P]),

@@ -2610,6 +2610,122 @@ __global__ void k_hist(KA<T> a, int shift, int nbits, unsigned long long prefix,
         if (sh[k]) atomicAdd(&hist[k], sh[k]);
 }
 
+// ---------------------------------------------------------------------------
+// FSAI factor (factorized sparse approximate inverse, Kolotilina and Yeremin):
+// a non-learned factor of the learned one's form.  Row i of G lives on S_i =
+// (the lower neighbours of i) + i and solves A[S_i, S_i] g = e_i, scaled so
+// that (G A G^T)_ii = 1.  With A[S_i, S_i] = R R^T (Cholesky, R lower, i last)
+// that row is the solution x of R^T x = e_last.  Pixel grids only: the
+// stencil-ordered slots [0, K/2) of a row are its lower neighbours, and slot
+// K-1-k of the neighbour behind slot k points back (symmetric stencil listed
+// in lexicographic order).  A lower slot that leaves the image becomes an
+// identity row and column of the local system (it decouples, its x is 0).
+// One thread per row, FP64 throughout, A from the FP64 weights
+// (A_jj = lambda/2 sum w^2 + r/2 deg_j, A_jk = -lambda/2 w_jk^2).  Stored
+// like the learned factor: Gt = G D_A^{1/2} on both slots of every edge (the
+// edge's lower-triangular entry) and on the diagonal.
+// ---------------------------------------------------------------------------
+struct FsaiArgs {
+    int64_t n;
+    const int* scol;
+    const double* sw;
+    const double* degree;
+    const double* wsq;
+    double hl, hr;       // lambda / 2, r / 2
+    int* err;
+};
+
+template <int KC>
+__device__ __forceinline__ double fsai_pair(const FsaiArgs& f, int j, int k) {
+    // A_jk, j != k, from row j's slots
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+        const size_t s = (size_t)q * f.n + j;
+        if (f.scol[s] == k) { const double w = f.sw[s]; v = -f.hl * w * w; }
+    }
+    return v;
+}
+
+template <typename T, int KC>
+__global__ void __launch_bounds__(64) k_fsai(FsaiArgs f, T* __restrict__ gval, T* __restrict__ gdiag) {
+    constexpr int H = KC / 2, MM = H + 1;
+    const int64_t n = f.n;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int jj[MM];
+    bool act[MM];
+    double dA[MM];
+#pragma unroll
+    for (int a = 0; a < H; ++a) {
+        const int j = f.scol[(size_t)a * n + i];
+        jj[a] = j;
+        act[a] = j < i;
+        dA[a] = act[a] ? f.hl * f.wsq[j] + f.hr * f.degree[j] : 1.0;
+    }
+    jj[H] = (int)i;
+    act[H] = true;
+    dA[H] = f.hl * f.wsq[i] + f.hr * f.degree[i];
+    double R[MM][MM];
+#pragma unroll
+    for (int a = 0; a < MM; ++a) {
+#pragma unroll
+        for (int b = 0; b < a; ++b) {
+            double v = 0.0;
+            if (act[a] && act[b]) {
+                if (a == H) {
+                    const double w = f.sw[(size_t)b * n + i];
+                    v = -f.hl * w * w;
+                } else {
+                    v = fsai_pair<KC>(f, jj[a], jj[b]);
+                }
+            }
+            R[a][b] = v;
+        }
+        R[a][a] = dA[a];
+    }
+    // Cholesky, lower, in place
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < MM; ++c) {
+        double p = R[c][c];
+#pragma unroll
+        for (int k = 0; k < c; ++k) p -= R[c][k] * R[c][k];
+        if (!(p > 0.0)) { ok = false; p = 1.0; }
+        const double rc = sqrt(p), inv = 1.0 / rc;
+        R[c][c] = rc;
+#pragma unroll
+        for (int a = c + 1; a < MM; ++a) {
+            double v = R[a][c];
+#pragma unroll
+            for (int k = 0; k < c; ++k) v -= R[a][k] * R[c][k];
+            R[a][c] = v * inv;
+        }
+    }
+    if (!ok) atomicOr(f.err, 1);
+    // R^T x = e_last
+    double x[MM];
+    x[H] = 1.0 / R[H][H];
+#pragma unroll
+    for (int k = H - 1; k >= 0; --k) {
+        double v = 0.0;
+#pragma unroll
+        for (int l = k + 1; l < MM; ++l) v -= R[l][k] * x[l];
+        x[k] = v / R[k][k];
+    }
+    gdiag[i] = (T)(x[H] * sqrt(dA[H]));
+#pragma unroll
+    for (int a = 0; a < H; ++a) {
+        const T gv = act[a] ? (T)(x[a] * sqrt(dA[a])) : T(0);
+        gval[(size_t)a * n + i] = gv;
+        if (act[a]) {
+            const size_t mirror = (size_t)(KC - 1 - a) * n + jj[a];
+            if (f.scol[mirror] == (int)i) gval[mirror] = gv;
+            else atomicOr(f.err, 2);
+        }
+    }
+}
+
 }  // namespace pfe
 
 // ===========================================================================
@@ -3176,7 +3292,7 @@ pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
 
 template <typename T>
 pfe_status pcg_any_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
-    return (c->prm.precond == PFE_LEARNED) ? pcg_loop_learned_mk(c, a, as) : pcg_loop_mk(c, a, as);
+    return (c->prm.precond != PFE_JACOBI) ? pcg_loop_learned_mk(c, a, as) : pcg_loop_mk(c, a, as);
 }
 
 // the strip partition is used in the one-launch-per-phase path when the graph
@@ -3356,7 +3472,7 @@ bool params_ok(const pfe_params* p, int64_t n) {
     if (!(p->r > 0.0) || !std::isfinite(p->r)) { set_error("r must be > 0"); return false; }
     if (p->n_inner < 1) { set_error("n_inner must be >= 1"); return false; }
     if (!(p->tol > 0.0) || p->maxit < 1) { set_error("tol must be > 0 and maxit >= 1"); return false; }
-    if (p->precond != PFE_JACOBI && p->precond != PFE_LEARNED) { set_error("unknown preconditioner"); return false; }
+    if (p->precond != PFE_JACOBI && p->precond != PFE_LEARNED && p->precond != PFE_FSAI) { set_error("unknown preconditioner"); return false; }
     if (p->ortho != PFE_POLAR && p->ortho != PFE_CHOL) { set_error("unknown ortho mode"); return false; }
     if (p->dtype != PFE_FP32 && p->dtype != PFE_FP64) { set_error("unknown dtype"); return false; }
     return true;
@@ -3460,6 +3576,35 @@ pfe_status identity_factor(pfe_ctx* c) {
     hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, T(1), (T*)c->gdiag);
     PFE_CHECK_HIP(hipGetLastError());
     c->have_factor = 0;
+    return PFE_OK;
+}
+
+template <typename T>
+pfe_status fsai_factor(pfe_ctx* c) {
+    const pfe_graph* g = c->g;
+    const int64_t n = c->n;
+    int* err = nullptr;
+    PFE_CHECK_HIP(hipMalloc((void**)&err, sizeof(int)));
+    PFE_CHECK_HIP(hipMemsetAsync(err, 0, sizeof(int), c->stream));
+    const size_t ns = (size_t)g->nslot + 1;
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, c->stream, ns, T(0), (T*)c->gval);
+    FsaiArgs f{n, g->s_col, g->s_w64, g->degree, g->wsq, 0.5 * c->prm.lambda, 0.5 * c->prm.r, err};
+    const dim3 grid((unsigned)((n + 63) / 64));
+    switch (g->ell_K) {
+        case 4: hipLaunchKernelGGL((k_fsai<T, 4>), grid, dim3(64), 0, c->stream, f, (T*)c->gval, (T*)c->gdiag); break;
+        case 8: hipLaunchKernelGGL((k_fsai<T, 8>), grid, dim3(64), 0, c->stream, f, (T*)c->gval, (T*)c->gdiag); break;
+        default: hipLaunchKernelGGL((k_fsai<T, 24>), grid, dim3(64), 0, c->stream, f, (T*)c->gval, (T*)c->gdiag); break;
+    }
+    hipError_t e = hipGetLastError();
+    int h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(err);
+    if (e != hipSuccess) return hip_fail(e, "FSAI factor", __FILE__, __LINE__);
+    if (h) {
+        set_error("pfe_set_fsai: %s", (h & 2) ? "slot layout is not a symmetric stencil" : "local system not positive definite");
+        return PFE_E_STATE;
+    }
     return PFE_OK;
 }
 
@@ -4037,9 +4182,23 @@ pfe_status pfe_set_learned(pfe_ctx* c, pfe_mpnn* net) {
     return PFE_OK;
 }
 
+
+pfe_status pfe_set_fsai(pfe_ctx* c) {
+    if (!c) { set_error("pfe_set_fsai: null context"); return PFE_E_ARG; }
+    const int K = c->g->ell_K;
+    if (!c->g->stencil || (K != 4 && K != 8 && K != 24)) {
+        set_error("pfe_set_fsai: needs a pixel-grid graph (stencil slot layout with 4, 8 or 24 slots)");
+        return PFE_E_ARG;
+    }
+    PFE_TRY(c->esz == 8 ? fsai_factor<double>(c) : fsai_factor<float>(c));
+    c->have_factor = 1;
+    c->prm.precond = PFE_FSAI;
+    return PFE_OK;
+}
+
 pfe_status pfe_set_preconditioner(pfe_ctx* c, int precond) {
     if (!c) { set_error("null context"); return PFE_E_ARG; }
-    if (precond != PFE_JACOBI && precond != PFE_LEARNED) { set_error("unknown preconditioner"); return PFE_E_ARG; }
+    if (precond != PFE_JACOBI && precond != PFE_LEARNED && precond != PFE_FSAI) { set_error("unknown preconditioner"); return PFE_E_ARG; }
     c->prm.precond = precond;
     return PFE_OK;
 }

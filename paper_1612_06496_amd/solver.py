@@ -216,9 +216,13 @@ class Solver:
         """Evaluate the network on this system and precondition with G^T G."""
         L.check(L.lib.pfe_set_learned(self._h, net._h), "pfe_set_learned")
 
+    def set_fsai(self) -> None:
+        """Compute the FSAI factor of this system on the device and precondition with it."""
+        L.check(L.lib.pfe_set_fsai(self._h), "pfe_set_fsai")
+
     def set_preconditioner(self, which: str) -> None:
-        L.check(L.lib.pfe_set_preconditioner(self._h, L.PFE_LEARNED if which == "learned" else L.PFE_JACOBI),
-                "pfe_set_preconditioner")
+        code = {"jacobi": L.PFE_JACOBI, "learned": L.PFE_LEARNED, "fsai": L.PFE_FSAI}[which]
+        L.check(L.lib.pfe_set_preconditioner(self._h, code), "pfe_set_preconditioner")
 
     def get_factor(self):
         """(Gt_ji per undirected edge (i < j, lexicographic), diag(Gt))."""
