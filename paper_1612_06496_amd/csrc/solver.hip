@@ -2635,16 +2635,65 @@ struct FsaiArgs {
     int* err;
 };
 
+// stencil offset of slot k (lexicographic (dy, dx) order of the 4-neighbour
+// cross, the 3x3 window or the 5x5 window without its centre) and the slot of
+// an offset (-1 outside the stencil)
 template <int KC>
-__device__ __forceinline__ double fsai_pair(const FsaiArgs& f, int j, int k) {
-    // A_jk, j != k, from row j's slots
-    double v = 0.0;
-#pragma unroll
-    for (int q = 0; q < KC; ++q) {
-        const size_t s = (size_t)q * f.n + j;
-        if (f.scol[s] == k) { const double w = f.sw[s]; v = -f.hl * w * w; }
+__host__ __device__ constexpr int sten_off(int k, bool want_dy) {
+    if (KC == 4) {
+        const int dy[4] = {-1, 0, 0, 1}, dx[4] = {0, -1, 1, 0};
+        return want_dy ? dy[k] : dx[k];
     }
-    return v;
+    const int R = (KC == 8) ? 1 : 2, w = 2 * R + 1, c = R * w + R;
+    const int idx = (k < c) ? k : k + 1;
+    return want_dy ? idx / w - R : idx % w - R;
+}
+
+template <int KC>
+__host__ __device__ constexpr int sten_slot(int dy, int dx) {
+    if (KC == 4) {
+        if (dy == -1 && dx == 0) return 0;
+        if (dy == 0 && dx == -1) return 1;
+        if (dy == 0 && dx == 1) return 2;
+        if (dy == 1 && dx == 0) return 3;
+        return -1;
+    }
+    const int R = (KC == 8) ? 1 : 2, w = 2 * R + 1, c = R * w + R;
+    if (dy < -R || dy > R || dx < -R || dx > R || (dy == 0 && dx == 0)) return -1;
+    const int idx = (dy + R) * w + (dx + R);
+    return idx < c ? idx : idx - 1;
+}
+
+// every slot maps back to itself, offsets ascend lexicographically, and slot
+// K-1-k holds the negated offset of slot k
+template <int KC>
+constexpr bool sten_table_ok() {
+    for (int k = 0; k < KC; ++k) {
+        const int dy = sten_off<KC>(k, true), dx = sten_off<KC>(k, false);
+        if (sten_slot<KC>(dy, dx) != k) return false;
+        if (sten_off<KC>(KC - 1 - k, true) != -dy || sten_off<KC>(KC - 1 - k, false) != -dx) return false;
+        if (k > 0) {
+            const int py = sten_off<KC>(k - 1, true), px = sten_off<KC>(k - 1, false);
+            if (!(py < dy || (py == dy && px < dx))) return false;
+        }
+    }
+    return true;
+}
+static_assert(sten_table_ok<4>() && sten_table_ok<8>() && sten_table_ok<24>(), "stencil table");
+
+// A_jk for the lower neighbours j (slot a of row i) and k (slot b): the slot of
+// row j at offset off_b - off_a, if that offset is in the stencil and the slot
+// points at k (both pixels are inside the image, so it does when they are
+// neighbours)
+template <int KC>
+__device__ __forceinline__ double fsai_pair(const FsaiArgs& f, int a, int b, int j, int k) {
+    const int q = sten_slot<KC>(sten_off<KC>(b, true) - sten_off<KC>(a, true),
+                                sten_off<KC>(b, false) - sten_off<KC>(a, false));
+    if (q < 0) return 0.0;
+    const size_t s = (size_t)q * f.n + j;
+    if (f.scol[s] != k) return 0.0;
+    const double w = f.sw[s];
+    return -f.hl * w * w;
 }
 
 template <typename T, int KC>
@@ -2677,7 +2726,7 @@ __global__ void __launch_bounds__(64) k_fsai(FsaiArgs f, T* __restrict__ gval, T
                     const double w = f.sw[(size_t)b * n + i];
                     v = -f.hl * w * w;
                 } else {
-                    v = fsai_pair<KC>(f, jj[a], jj[b]);
+                    v = fsai_pair<KC>(f, a, b, jj[a], jj[b]);
                 }
             }
             R[a][b] = v;

@@ -5,6 +5,9 @@ and PCG with it against the oracle's preconditioned PCG.
 The device computes the factor in FP64 from the FP64 weights, so an FP64
 context matches the oracle to rounding (<= 1e-11 relative); an FP32 context
 stores the same values rounded to float (<= 1e-6)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -19,6 +22,9 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
+
+
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def to_np(t):
@@ -151,3 +157,34 @@ def test_fsai_window_graph_full_size_sampled_rows():
         worst = max(worst, np.abs(got - want).max() / np.abs(want).max())
     print(f"worst sampled-row rel err {worst:.2e}")
     assert worst <= 1e-6
+
+
+def test_full_size_counts_match_stored_oracle_counts():
+    """1024x1024 window graph, first inner solve of a run (rhs = r/2 D Y0,
+    x0 = Y0), FP32 PCG to 1e-6 with Jacobi and with FSAI at lambda/r = 1, 10,
+    100, 1000: per-column iteration counts against the oracle's FP64 counts
+    stored by tests/golden/make_preconditioner_counts.py, within 2 or 3 %
+    (FP32 rounding can move the last iterations)."""
+    from paper_1612_06496_amd import Solver
+    with open(os.path.join(HERE, "golden", "preconditioner_counts_voronoi1024_r2.json")) as f:
+        ref = json.load(f)
+    wl = synth.make_workload(ref["workload"], ref["seed"])
+    banner("Jacobi and FSAI iteration counts at 1024x1024 vs stored oracle counts")
+    g = oracle_graph(wl)
+    Y = O.orthonormalize_init(g, wl.y0)
+    G = gpu_graph(wl)
+    c = ref["c"]
+    for ratio, cnt in ref["ratios"].items():
+        lam, r = float(ratio) * c, c
+        S = Solver(G, Y, lam=lam, r=r, n_inner=wl.n_inner, tol=ref["tol"], maxit=5000, init_ortho=False,
+                   persistent=False)
+        rhs = 0.5 * r * g.D[:, None] * Y
+        _, it_j, _ = S.pcg(rhs, Y)
+        S.set_fsai()
+        _, it_f, _ = S.pcg(rhs, Y)
+        print(f"lambda/r {ratio}: Jacobi max {it_j.max()} (oracle {max(cnt['jacobi'])}), FSAI max {it_f.max()} "
+              f"(oracle {max(cnt['fsai'])}), IC(0) oracle {max(cnt['ic0'])}")
+        for got, want in ((it_j, cnt["jacobi"]), (it_f, cnt["fsai"])):
+            want = np.asarray(want)
+            assert np.all(np.abs(got - want) <= np.maximum(2, 0.03 * want)), (ratio, got, want)
+        del S
