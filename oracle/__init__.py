@@ -12,3 +12,4 @@ here is pinned by a ``-m "not gpu"`` test in ``tests/test_oracle_*.py``.
 """
 from .pfe import *  # noqa: F401,F403
 from . import classical  # noqa: F401,E402
+from . import kmeans  # noqa: F401,E402
