@@ -266,6 +266,8 @@ def main():
     ap.add_argument("--learned-outer", type=int, default=2, help="timed SOC iterations per preconditioner and ratio")
     ap.add_argument("--stage2-iters", type=int, default=100,
                     help="Split-Bregman iterations of the timed Stage II run after the SOC iterations (0: skip)")
+    ap.add_argument("--kmeans-iters", type=int, default=100,
+                    help="cap of the timed k-means (Lloyd) run on the final embedding, single images (0: skip)")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="a single-image workload or an image batch (block-diagonal union) from synth")
     args = ap.parse_args()
@@ -372,6 +374,23 @@ def main():
                           "launch": "persistent" if i2["workgroups"] else ("strips" if i2["flags"] & 2 else "multi"),
                           "algorithmic_gbs": round(b2 / (ms2 / 1e3) / 1e9, 1),
                           "frac": round(b2 / (ms2 / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+    if args.kmeans_iters > 0 and len(wls) == 1:
+        # the segmentation step: k-means on the embedding, initial centroids at
+        # seeded rows (the caller's random draw)
+        from paper_1612_06496_amd import kmeans
+        yh = S.get("Yhat")
+        K = wl.n_clusters
+        rows = np.random.default_rng(0).choice(n, K, replace=False)
+        C0 = yh[torch.as_tensor(rows, device="cuda")].double()
+        torch.cuda.synchronize()
+        start.record()
+        _, _, kit = kmeans(yh, C0, args.kmeans_iters)
+        stop.record()
+        torch.cuda.synchronize()
+        ms3 = start.elapsed_time(stop)
+        line["kmeans"] = {"clusters": K, "iterations": kit, "ms": round(ms3, 3),
+                          "ms_per_iteration": round(ms3 / max(1, kit), 4)}
+        progress(f"k-means, {kit} Lloyd iterations: {ms3:.1f} ms")
     if not args.no_learned and default:
         leg = learned_leg(workload=args.learned_workload, train_workload=args.learned_train_workload,
                           n_outer=args.learned_outer)

@@ -368,6 +368,23 @@ pfe_status pfe_edge_quantile(pfe_ctx* c, double q, double* out);
 
 void pfe_destroy_ctx(pfe_ctx* c);
 
+/* ---- k-means on an embedding ----------------------------------------------------
+ * The segmentation experiment (Sec. IV) clusters the embedding by k-means.
+ * Lloyd iterations on the n rows of Y (device, n x d row-major, dtype
+ * PFE_FP32 or PFE_FP64; for the embedding, pfe_get(PFE_YHAT)) from the
+ * initial centroids C0 (device, K x d doubles; choosing them is the caller's
+ * random draw).  One iteration assigns each row to its nearest centroid (the
+ * squared Euclidean distance summed over the coordinates in order in FP64,
+ * each product and sum rounded on its own; ties to the lowest index) and then
+ * moves each centroid to the mean of its rows (a centroid without rows stays).
+ * Stops after max_iter iterations or after one in which no label changed.
+ * labels (device, n int32) and centroids (device, K x d doubles; may be C0)
+ * receive the result, iters (host, may be null) the iterations run.
+ * 1 <= d <= 32, 1 <= K <= 256, K d <= 8000, n < 2^31.  Synchronises the
+ * stream (the stopping test reads a count back after every iteration). */
+pfe_status pfe_kmeans(const void* Y, int64_t n, int d, int dtype, const double* C0, int K, int max_iter,
+                      int32_t* labels, double* centroids, int32_t* iters, hipStream_t stream);
+
 /* ---- diagnostics ----------------------------------------------------------- */
 
 /* Plain device copy dst[0..bytes) = src[0..bytes) with 16-byte vector loads and

@@ -108,6 +108,7 @@ SIGNATURES = {
     "pfe_get_factor": (_S, [_P, _P, _P]),
     "pfe_destroy_ctx": (None, [_P]),
     "pfe_stream_copy": (_S, [_P, _P, C.c_size_t, _P]),
+    "pfe_kmeans": (_S, [_P, C.c_int64, C.c_int, C.c_int, _P, C.c_int, C.c_int, _P, _P, C.POINTER(C.c_int32), _P]),
     "pfe_status_string": (C.c_char_p, [C.c_int]),
     "pfe_last_error": (C.c_char_p, []),
 }

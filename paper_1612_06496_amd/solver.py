@@ -28,6 +28,27 @@ def _dev(x, dtype) -> torch.Tensor:
     return x.to(device="cuda", dtype=dtype).contiguous()
 
 
+def kmeans(Y, C0, max_iter: int = 100, stream: Optional[torch.cuda.Stream] = None):
+    """Lloyd k-means on the rows of Y (n x d, float32 or float64; host arrays
+    are copied in as float64) from the initial centroids C0 (K x d) through
+    pfe_kmeans.  Returns (labels int32 tensor, centroids float64 tensor,
+    iterations run)."""
+    if isinstance(Y, torch.Tensor) and Y.is_cuda and Y.dtype in (torch.float32, torch.float64):
+        Yd = Y.contiguous()
+    else:
+        Yd = _dev(Y, torch.float64)
+    n, d = Yd.shape
+    cen0 = _dev(C0, torch.float64)
+    K = cen0.shape[0]
+    labels = torch.empty(n, dtype=torch.int32, device="cuda")
+    cen = torch.empty((K, d), dtype=torch.float64, device="cuda")
+    iters = C.c_int32()
+    dt = L.PFE_FP64 if Yd.dtype == torch.float64 else L.PFE_FP32
+    L.check(L.lib.pfe_kmeans(Yd.data_ptr(), n, d, dt, cen0.data_ptr(), K, int(max_iter), labels.data_ptr(),
+                             cen.data_ptr(), C.byref(iters), _stream_handle(stream)), "pfe_kmeans")
+    return labels, cen, iters.value
+
+
 class Graph:
     """A graph built by pfe_build_graph (CSR adjacency, heat-kernel weights)."""
 
