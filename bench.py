@@ -212,6 +212,41 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
             "sweep": rows}
 
 
+def d_sweep_leg(G, wl, dims=(5, 10, 15, 20, 25), steps=10):
+    """SOC iterations/s of one image at several embedding dimensions d (one
+    context per d, its launch shape autotuned, shrink-active penalties from its
+    own initial embedding; one untimed and `steps` timed SOC iterations)."""
+    import torch
+
+    import synth
+    from paper_1612_06496_amd import Solver
+    rows = []
+    for d in dims:
+        y0 = synth.smooth_y0(wl.H, wl.W, d, 7919)
+        S = Solver(G, y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=1000)
+        c = 1.0 / S.edge_quantile(0.99)
+        S.set_penalties(c, c)
+        S.autotune(trials=1)
+        S.solve(1)
+        S.stats(reset=True)
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(steps):
+            S.solve(1)
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop)
+        info = S.stats(reset=True)
+        rows.append({"d": d, "outer_iters_per_s": round(steps / (ms / 1e3), 1), "ms_per_step": round(ms / steps, 4),
+                     "pcg_iters_per_solve": round(info["cg_iters_total"] / max(1, info["solves"]), 2),
+                     "launch": "persistent" if info["workgroups"] else ("strips" if info["flags"] & 2 else "multi")})
+        del S
+        progress(f"d-sweep: d = {d} done")
+    return rows
+
+
 def cpu_baseline(wls, lam, r, n_steps=2, max_images=2):
     """The FP64 oracle on the host, on a bounded sample: n_steps SOC iterations
     of the workload's first max_images images (sparse LU factorisation reported
@@ -268,6 +303,8 @@ def main():
                     help="Split-Bregman iterations of the timed Stage II run after the SOC iterations (0: skip)")
     ap.add_argument("--kmeans-iters", type=int, default=100,
                     help="cap of the timed k-means (Lloyd) run on the final embedding, single images (0: skip)")
+    ap.add_argument("--no-d-sweep", action="store_true",
+                    help="skip the SOC-iteration rate at d = 5, 10, 15, 20, 25 on the headline image")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="a single-image workload or an image batch (block-diagonal union) from synth")
     args = ap.parse_args()
@@ -391,6 +428,8 @@ def main():
         line["kmeans"] = {"clusters": K, "iterations": kit, "ms": round(ms3, 3),
                           "ms_per_iteration": round(ms3 / max(1, kit), 4)}
         progress(f"k-means, {kit} Lloyd iterations: {ms3:.1f} ms")
+    if not args.no_d_sweep and default:
+        line["d_sweep"] = d_sweep_leg(G, wl)
     if not args.no_learned and default:
         leg = learned_leg(workload=args.learned_workload, train_workload=args.learned_train_workload,
                           n_outer=args.learned_outer)

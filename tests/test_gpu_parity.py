@@ -328,7 +328,7 @@ def test_rank_deficient_init_is_rejected():
     assert e.value.status == PFE_E_RANK
 
 
-@pytest.mark.parametrize("d", [1, 3, 32])
+@pytest.mark.parametrize("d", [1, 3, 5, 25, 32])
 def test_dimensions_and_ragged_sizes(d):
     """d = 1 and d = 32, and an image whose pixel count is not a multiple of
     the rows handled per pass, against the oracle."""
