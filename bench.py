@@ -32,9 +32,12 @@ def progress(msg):
 
 
 def algorithmic_bytes(n, E, d, esz, cg_iters, solves, n_inner, n_outer, pupdate=True):
-    """Bytes the method has to move per the model stated in the design doc
-    (FP32 values, int32 indices), summed over n_outer SOC iterations (without
-    the P- and B-update when pupdate is False: Split Bregman alone)."""
+    """Bytes the method has to move (FP32 values, int32 indices): per CG
+    iteration the slot columns and weights, row pointers, diagonal and ten n x d
+    vector streams; per inner step the residual or edge update with its split
+    state; per SOC iteration the Gram and apply passes.  Summed over n_outer
+    SOC iterations (without the P- and B-update when pupdate is False: Split
+    Bregman alone)."""
     rowptr = 4 * (n + 1)
     csr = 8 * 2 * E + rowptr                  # column index + weight per directed slot
     nd = n * d * esz
@@ -309,8 +312,9 @@ def main():
                     help="a single-image workload or an image batch (block-diagonal union) from synth")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a "
-              "single MI355X; see DESIGN.md for how the path would shard).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the solver runs on a "
+              "single MI355X (a batch would shard by whole images, one large graph by row bands with a halo "
+              "exchange per CG iteration; neither is built).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
