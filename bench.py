@@ -169,7 +169,8 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
     jshape = None
     for ratio in ratios:
         res = {"lambda_over_r": ratio}
-        for pre in ("jacobi", "fsai", "learned"):
+        # FSAI is built for pixel grids (stencil slot layout) only
+        for pre in (("jacobi", "fsai", "learned") if wl.kind == "grid" else ("jacobi", "learned")):
             S = Solver(G, wl.y0, lam=ratio * c, r=c, n_inner=wl.n_inner, tol=wl.tol, maxit=5000,
                        persistent=(pre == "jacobi" and (jshape is None or jshape["persistent"] == 1)), graphs=True)
             factor_ms = None
@@ -442,8 +443,8 @@ def main():
                                                                "learned_mean": r["learned"]["iters_mean"],
                                                                "jacobi_max": r["jacobi"]["iters_max"],
                                                                "learned_max": r["learned"]["iters_max"],
-                                                               "fsai_mean": r["fsai"]["iters_mean"],
-                                                               "fsai_max": r["fsai"]["iters_max"]}
+                                                               "fsai_mean": r.get("fsai", {}).get("iters_mean"),
+                                                               "fsai_max": r.get("fsai", {}).get("iters_max")}
                                      for r in leg["sweep"]}
     if args.copy_gib > 0:
         line["copy_gbs"] = round(copy_bandwidth(args.copy_gib), 1)
