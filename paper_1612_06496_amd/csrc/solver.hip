@@ -1984,103 +1984,116 @@ struct LocState {
 // a workgroup may still read one while the next barrier's leaders write the other)
 constexpr int kGroupStride = kNumXcd * (kMaxD * (kMaxD + 1) / 2 > 3 * kMaxD ? kMaxD * (kMaxD + 1) / 2 : 3 * kMaxD);
 
-template <typename T>
-__device__ __forceinline__ void lfin_res(const KA<T>& a, LocState& L, const double* gp, double* sh) {
-    const int d = a.d, t = threadIdx.x;
-    double* out = sh + 1024;
-    reduce_range(gp, kNumXcd, 0, kNumXcd, d, 2, out, sh);
-    if (t < d) {
-        const double bb = out[t], rr = out[d + t];
-        L.bnorm2[t] = bb;
-        L.rr[t] = rr;
-        L.iters[t] = 0;
-        L.alpha[t] = 0.0;
-        L.beta[t] = 0.0;
-        L.zero[t] = (bb == 0.0);
-        L.active[t] = !L.zero[t] && (rr > a.tol2 * bb);
-    }
-    __syncthreads();
-    if (t == 0) {
-        int any = 0, anyz = 0;
-        for (int c = 0; c < d; ++c) { any |= L.active[c]; anyz |= L.zero[c]; }
-        L.it = 0;
-        L.done = !any;
-        L.any_zero = anyz;
-    }
-    __syncthreads();
+// sum of the eight per-XCD-group partials of quantity q, column c, in group
+// order (the loads are independent, so one memory round trip)
+__device__ __forceinline__ double group_total(const double* gp, int d, int q, int c) {
+    const double* p = gp + (size_t)q * kNumXcd * d + c;
+    double v[kNumXcd];
+#pragma unroll
+    for (int g = 0; g < kNumXcd; ++g) v[g] = p[(size_t)g * d];
+    double acc = 0.0;
+#pragma unroll
+    for (int g = 0; g < kNumXcd; ++g) acc += v[g];
+    return acc;
 }
 
+// The local finalisations run on the first wave only (lane c owns column c,
+// d <= 32 < 64): its lanes load the group partials, advance the column
+// scalars and vote on the flags; one workgroup barrier publishes the result.
 template <typename T>
-__device__ __forceinline__ void lfin_w0(const KA<T>& a, LocState& L, const double* gp, double* sh) {
+__device__ __forceinline__ void lfin_res(const KA<T>& a, LocState& L, const double* gp, double*) {
     const int d = a.d, t = threadIdx.x;
-    double* out = sh + 1024;
-    reduce_range(gp, kNumXcd, 0, kNumXcd, d, 2, out, sh);
-    __shared__ int s_bad;
-    if (t == 0) s_bad = 0;
-    __syncthreads();
-    if (t < d) {
-        const double g = out[t], dl = out[d + t];
-        L.gamma[t] = g;
-        double al = 0.0;
-        if (L.active[t]) {
-            al = g / dl;
-            if (!(dl > 0.0) || !(g > 0.0) || !isfinite(al)) { s_bad = 1; al = 0.0; }
-        }
-        L.alpha[t] = al;
-        L.beta[t] = 0.0;
-    }
-    __syncthreads();
-    if (t == 0 && s_bad) {
-        L.status = PFE_E_NOT_SPD;
-        L.done = 1;
-    }
-    __syncthreads();
-}
-
-template <typename T>
-__device__ __forceinline__ void lfin_it(const KA<T>& a, LocState& L, const double* gp, double* sh) {
-    const int d = a.d, t = threadIdx.x;
-    double* out = sh + 1024;
-    reduce_range(gp, kNumXcd, 0, kNumXcd, d, 3, out, sh);
-    __shared__ int s_bad;
-    if (t == 0) s_bad = 0;
-    __syncthreads();
-    if (t < d) {
-        int act = L.active[t];
-        if (act) {
-            const double g = out[t], dl = out[d + t], rr = out[2 * d + t];
-            L.iters[t] += 1;
+    if (t < 64) {
+        int act = 0, zr = 0;
+        if (t < d) {
+            const double bb = group_total(gp, d, 0, t), rr = group_total(gp, d, 1, t);
+            L.bnorm2[t] = bb;
             L.rr[t] = rr;
-            act = rr > a.tol2 * L.bnorm2[t];
-            if (!isfinite(rr)) { s_bad = 1; act = 0; }
-            if (act) {
-                double be = g / L.gamma[t];
-                double den = dl - be * g / L.alpha[t];
-                double al = g / den;
-                if (!(den > 0.0) || !isfinite(al) || !isfinite(be)) { s_bad = 1; act = 0; al = 0.0; be = 0.0; }
-                L.beta[t] = be;
-                L.alpha[t] = al;
-                L.gamma[t] = g;
-            }
-        }
-        if (!act) {
+            L.iters[t] = 0;
             L.alpha[t] = 0.0;
             L.beta[t] = 0.0;
+            zr = (bb == 0.0);
+            act = !zr && (rr > a.tol2 * bb);
+            L.zero[t] = zr;
+            L.active[t] = act;
         }
-        L.active[t] = act;
+        const bool any = __any(act), anyz = __any(zr);
+        if (t == 0) {
+            L.it = 0;
+            L.done = !any;
+            L.any_zero = anyz;
+        }
     }
     __syncthreads();
-    if (t == 0) {
-        int any = 0;
-        for (int c = 0; c < d; ++c) any |= L.active[c];
-        if (s_bad) L.status = PFE_E_NOT_SPD;
-        const int it = L.it + 1;
-        L.it = it;
-        if (any && it >= a.maxit) {
-            if (L.status == 0) L.status = PFE_E_NOCONV;
-            any = 0;
+}
+
+template <typename T>
+__device__ __forceinline__ void lfin_w0(const KA<T>& a, LocState& L, const double* gp, double*) {
+    const int d = a.d, t = threadIdx.x;
+    if (t < 64) {
+        int bad = 0;
+        if (t < d) {
+            const double g = group_total(gp, d, 0, t), dl = group_total(gp, d, 1, t);
+            L.gamma[t] = g;
+            double al = 0.0;
+            if (L.active[t]) {
+                al = g / dl;
+                if (!(dl > 0.0) || !(g > 0.0) || !isfinite(al)) { bad = 1; al = 0.0; }
+            }
+            L.alpha[t] = al;
+            L.beta[t] = 0.0;
         }
-        L.done = !any;
+        const bool anybad = __any(bad);
+        if (t == 0 && anybad) {
+            L.status = PFE_E_NOT_SPD;
+            L.done = 1;
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void lfin_it(const KA<T>& a, LocState& L, const double* gp, double*) {
+    const int d = a.d, t = threadIdx.x;
+    if (t < 64) {
+        int act = 0, bad = 0;
+        if (t < d) {
+            act = L.active[t];
+            if (act) {
+                const double g = group_total(gp, d, 0, t), dl = group_total(gp, d, 1, t),
+                             rr = group_total(gp, d, 2, t);
+                L.iters[t] += 1;
+                L.rr[t] = rr;
+                act = rr > a.tol2 * L.bnorm2[t];
+                if (!isfinite(rr)) { bad = 1; act = 0; }
+                if (act) {
+                    double be = g / L.gamma[t];
+                    double den = dl - be * g / L.alpha[t];
+                    double al = g / den;
+                    if (!(den > 0.0) || !isfinite(al) || !isfinite(be)) { bad = 1; act = 0; al = 0.0; be = 0.0; }
+                    L.beta[t] = be;
+                    L.alpha[t] = al;
+                    L.gamma[t] = g;
+                }
+            }
+            if (!act) {
+                L.alpha[t] = 0.0;
+                L.beta[t] = 0.0;
+            }
+            L.active[t] = act;
+        }
+        const bool any = __any(act), anybad = __any(bad);
+        if (t == 0) {
+            bool more = any;
+            if (anybad) L.status = PFE_E_NOT_SPD;
+            const int it = L.it + 1;
+            L.it = it;
+            if (more && it >= a.maxit) {
+                if (L.status == 0) L.status = PFE_E_NOCONV;
+                more = false;
+            }
+            L.done = !more;
+        }
     }
     __syncthreads();
 }
