@@ -127,6 +127,8 @@ typedef struct {
  *   graphs     1: in the one-launch-per-phase mode (and for the learned
  *              preconditioner), replay the PCG iterations from a HIP graph of 8
  *              iterations instead of launching each kernel from the host
+ *   cold_start 0 (default): every PCG solve of Eq. (13) starts from the current
+ *              Y (warm start); 1: from zero (runs one launch per phase)
  */
 typedef struct {
     int d;
@@ -142,6 +144,7 @@ typedef struct {
     int keep_split;
     int persistent;
     int graphs;
+    int cold_start;
 } pfe_params;
 
 /* Per-call solver statistics (filled when a non-null pointer is passed). */
@@ -384,6 +387,22 @@ void pfe_destroy_ctx(pfe_ctx* c);
  * stream (the stopping test reads a count back after every iteration). */
 pfe_status pfe_kmeans(const void* Y, int64_t n, int d, int dtype, const double* C0, int K, int max_iter,
                       int32_t* labels, double* centroids, int32_t* iters, hipStream_t stream);
+
+/* ---- device memory ------------------------------------------------------------
+ * Graphs, contexts, networks and the temporaries of a call take device memory
+ * from hipMalloc / hipFree unless the caller routes it through its own
+ * allocator (for example a caching allocator that owns the process's device
+ * memory): alloc(bytes, device, user) returns at least `bytes` bytes of device
+ * memory on `device` (256-byte aligned) or null on failure (the library call
+ * then returns PFE_E_HIP); release(ptr, device, user) takes it back, called
+ * after the device has finished with it.  Both functions or neither (null,
+ * null: back to hipMalloc).  Only while no library allocation is live
+ * (PFE_E_STATE otherwise); not thread-safe against concurrent library calls. */
+typedef void* (*pfe_alloc_fn)(size_t bytes, int device, void* user);
+typedef void (*pfe_free_fn)(void* ptr, int device, void* user);
+pfe_status pfe_set_allocator(pfe_alloc_fn alloc, pfe_free_fn release, void* user);
+/* Device allocations of the library currently live (from either allocator). */
+int64_t pfe_live_allocations(void);
 
 /* ---- diagnostics ----------------------------------------------------------- */
 

@@ -48,7 +48,7 @@ class pfe_params(C.Structure):
         ("n_inner", C.c_int), ("tol", C.c_double), ("maxit", C.c_int),
         ("precond", C.c_int), ("ortho", C.c_int), ("dtype", C.c_int),
         ("init_ortho", C.c_int), ("keep_split", C.c_int), ("persistent", C.c_int),
-        ("graphs", C.c_int),
+        ("graphs", C.c_int), ("cold_start", C.c_int),
     ]
 
 
@@ -108,6 +108,8 @@ SIGNATURES = {
     "pfe_get_factor": (_S, [_P, _P, _P]),
     "pfe_destroy_ctx": (None, [_P]),
     "pfe_stream_copy": (_S, [_P, _P, C.c_size_t, _P]),
+    "pfe_set_allocator": (_S, [_P, _P, _P]),
+    "pfe_live_allocations": (C.c_int64, []),
     "pfe_kmeans": (_S, [_P, C.c_int64, C.c_int, C.c_int, _P, C.c_int, C.c_int, _P, _P, C.POINTER(C.c_int32), _P]),
     "pfe_status_string": (C.c_char_p, [C.c_int]),
     "pfe_last_error": (C.c_char_p, []),

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpfe.so")
 
-SOURCES = ["graph.hip", "solver.hip", "learned.hip", "kmeans.hip"]
+SOURCES = ["alloc.hip", "graph.hip", "solver.hip", "learned.hip", "kmeans.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

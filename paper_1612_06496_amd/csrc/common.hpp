@@ -13,6 +13,18 @@ namespace pfe {
 void set_error(const char* fmt, ...);
 pfe_status hip_fail(hipError_t e, const char* what, const char* file, int line);
 
+// device memory of the library (the caller's allocator when one is installed)
+hipError_t dev_alloc(void** p, size_t bytes);
+hipError_t dev_free(void* p);
+hipError_t dev_alloc_async(void** p, size_t bytes, hipStream_t st);
+hipError_t dev_free_async(void* p, hipStream_t st);
+template <typename T>
+inline hipError_t dev_alloc(T** p, size_t bytes) { return dev_alloc(reinterpret_cast<void**>(p), bytes); }
+template <typename T>
+inline hipError_t dev_alloc_async(T** p, size_t bytes, hipStream_t st) {
+    return dev_alloc_async(reinterpret_cast<void**>(p), bytes, st);
+}
+
 constexpr int kMaxD = 32;          // largest embedding dimension
 constexpr int kNumXcd = 8;         // accelerator complex dies on MI355X
 constexpr int kBlock = 512;        // threads per workgroup of the row-parallel phases

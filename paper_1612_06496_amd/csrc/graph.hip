@@ -94,12 +94,12 @@ static pfe_status exclusive_scan(const int* in, int* out, int64_t n, hipStream_t
     int64_t ntiles = (n + kScanTile - 1) / kScanTile;
     if (ntiles < 1) ntiles = 1;
     int* sums = nullptr;
-    PFE_CHECK_HIP(hipMallocAsync((void**)&sums, sizeof(int) * ntiles, st));
+    PFE_CHECK_HIP(dev_alloc_async((void**)&sums, sizeof(int) * ntiles, st));
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanBlock), 0, st, in, out, sums, n);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, sums, (int)ntiles, out + n);
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, sums, n);
     PFE_CHECK_HIP(hipGetLastError());
-    PFE_CHECK_HIP(hipFreeAsync(sums, st));
+    PFE_CHECK_HIP(dev_free_async(sums, st));
     return PFE_OK;
 }
 
@@ -343,10 +343,10 @@ __global__ void __launch_bounds__(256) k_stream_copy(const uint4* __restrict__ s
 
 static void free_graph_buffers(pfe_graph* g) {
     if (!g) return;
-    (void)hipFree(g->rowptr); (void)hipFree(g->col); (void)hipFree(g->rev); (void)hipFree(g->eid);
-    (void)hipFree(g->w32); (void)hipFree(g->w64); (void)hipFree(g->degree); (void)hipFree(g->wsq);
+    (void)dev_free(g->rowptr); (void)dev_free(g->col); (void)dev_free(g->rev); (void)dev_free(g->eid);
+    (void)dev_free(g->w32); (void)dev_free(g->w64); (void)dev_free(g->degree); (void)dev_free(g->wsq);
     if (g->ell_K > 0) {
-        (void)hipFree(g->s_col); (void)hipFree(g->s_w32); (void)hipFree(g->s_w64); (void)hipFree(g->s_eid);
+        (void)dev_free(g->s_col); (void)dev_free(g->s_w32); (void)dev_free(g->s_w64); (void)dev_free(g->s_eid);
     }
 }
 
@@ -372,11 +372,11 @@ static pfe_status build_impl(const pfe_graph_desc* d, hipStream_t st, pfe_graph*
     void* tmp_in3 = nullptr;
     int64_t n = g->n;
     unsigned gridN = (unsigned)((n + TB - 1) / TB);
-    PFE_CHECK_HIP(hipMallocAsync((void**)&deg, sizeof(int) * (n + 1), st));
-    PFE_CHECK_HIP(hipMallocAsync((void**)&err, sizeof(int), st));
+    PFE_CHECK_HIP(dev_alloc_async((void**)&deg, sizeof(int) * (n + 1), st));
+    PFE_CHECK_HIP(dev_alloc_async((void**)&err, sizeof(int), st));
     PFE_CHECK_HIP(hipMemsetAsync(deg, 0, sizeof(int) * (n + 1), st));
     PFE_CHECK_HIP(hipMemsetAsync(err, 0, sizeof(int), st));
-    PFE_CHECK_HIP(hipMalloc((void**)&g->rowptr, sizeof(int) * (n + 1)));
+    PFE_CHECK_HIP(dev_alloc((void**)&g->rowptr, sizeof(int) * (n + 1)));
 
     if (d->kind == PFE_GRID) {
         Stencil sten{};
@@ -394,7 +394,7 @@ static pfe_status build_impl(const pfe_graph_desc* d, hipStream_t st, pfe_graph*
         const float* feat = d->feat;
         size_t fbytes = sizeof(float) * (size_t)n * d->m;
         if (!d->on_device) {
-            PFE_CHECK_HIP(hipMallocAsync(&tmp_in, fbytes, st));
+            PFE_CHECK_HIP(dev_alloc_async(&tmp_in, fbytes, st));
             PFE_CHECK_HIP(hipMemcpyAsync(tmp_in, d->feat, fbytes, hipMemcpyHostToDevice, st));
             feat = (const float*)tmp_in;
         }
@@ -405,8 +405,8 @@ static pfe_status build_impl(const pfe_graph_desc* d, hipStream_t st, pfe_graph*
         PFE_CHECK_HIP(hipMemcpyAsync(&total, g->rowptr + n, sizeof(int), hipMemcpyDeviceToHost, st));
         PFE_CHECK_HIP(hipStreamSynchronize(st));
         g->slots = total;
-        PFE_CHECK_HIP(hipMalloc((void**)&g->col, sizeof(int) * (g->slots + 1)));
-        PFE_CHECK_HIP(hipMalloc((void**)&g->w64, sizeof(double) * (g->slots + 1)));
+        PFE_CHECK_HIP(dev_alloc((void**)&g->col, sizeof(int) * (g->slots + 1)));
+        PFE_CHECK_HIP(dev_alloc((void**)&g->w64, sizeof(double) * (g->slots + 1)));
         hipLaunchKernelGGL(k_grid_fill, dim3(gridN), dim3(TB), 0, st, d->H, d->W, d->m, feat, sten,
                            inv2s2, g->rowptr, g->col, g->w64);
         hipLaunchKernelGGL(k_row_sort, dim3(gridN), dim3(TB), 0, st, n, g->rowptr, g->col, g->w64, err);
@@ -416,9 +416,9 @@ static pfe_status build_impl(const pfe_graph_desc* d, hipStream_t st, pfe_graph*
         const int32_t* dst = d->dst;
         const double* dist2 = d->dist2;
         if (!d->on_device) {
-            PFE_CHECK_HIP(hipMallocAsync(&tmp_in, sizeof(int32_t) * (ne + 1), st));
-            PFE_CHECK_HIP(hipMallocAsync(&tmp_in2, sizeof(int32_t) * (ne + 1), st));
-            PFE_CHECK_HIP(hipMallocAsync(&tmp_in3, sizeof(double) * (ne + 1), st));
+            PFE_CHECK_HIP(dev_alloc_async(&tmp_in, sizeof(int32_t) * (ne + 1), st));
+            PFE_CHECK_HIP(dev_alloc_async(&tmp_in2, sizeof(int32_t) * (ne + 1), st));
+            PFE_CHECK_HIP(dev_alloc_async(&tmp_in3, sizeof(double) * (ne + 1), st));
             PFE_CHECK_HIP(hipMemcpyAsync(tmp_in, src, sizeof(int32_t) * ne, hipMemcpyHostToDevice, st));
             PFE_CHECK_HIP(hipMemcpyAsync(tmp_in2, dst, sizeof(int32_t) * ne, hipMemcpyHostToDevice, st));
             PFE_CHECK_HIP(hipMemcpyAsync(tmp_in3, dist2, sizeof(double) * ne, hipMemcpyHostToDevice, st));
@@ -437,9 +437,9 @@ static pfe_status build_impl(const pfe_graph_desc* d, hipStream_t st, pfe_graph*
         PFE_CHECK_HIP(hipStreamSynchronize(st));
         if (herr) { set_error("pfe_build_graph: %s", graph_err_text(herr)); return PFE_E_GRAPH; }
         g->slots = total;
-        PFE_CHECK_HIP(hipMalloc((void**)&g->col, sizeof(int) * (g->slots + 1)));
-        PFE_CHECK_HIP(hipMalloc((void**)&g->w64, sizeof(double) * (g->slots + 1)));
-        PFE_CHECK_HIP(hipMallocAsync((void**)&fill, sizeof(int) * (n + 1), st));
+        PFE_CHECK_HIP(dev_alloc((void**)&g->col, sizeof(int) * (g->slots + 1)));
+        PFE_CHECK_HIP(dev_alloc((void**)&g->w64, sizeof(double) * (g->slots + 1)));
+        PFE_CHECK_HIP(dev_alloc_async((void**)&fill, sizeof(int) * (n + 1), st));
         PFE_CHECK_HIP(hipMemsetAsync(fill, 0, sizeof(int) * (n + 1), st));
         if (ne > 0)
             hipLaunchKernelGGL(k_edge_scatter, dim3(gridE), dim3(TB), 0, st, n, ne, src, dst, dist2,
@@ -447,12 +447,12 @@ static pfe_status build_impl(const pfe_graph_desc* d, hipStream_t st, pfe_graph*
         hipLaunchKernelGGL(k_row_sort, dim3(gridN), dim3(TB), 0, st, n, g->rowptr, g->col, g->w64, err);
     }
     g->n_edges = g->slots / 2;
-    PFE_CHECK_HIP(hipMalloc((void**)&g->w32, sizeof(float) * (g->slots + 1)));
-    PFE_CHECK_HIP(hipMalloc((void**)&g->rev, sizeof(int) * (g->slots + 1)));
-    PFE_CHECK_HIP(hipMalloc((void**)&g->eid, sizeof(int) * (g->slots + 1)));
-    PFE_CHECK_HIP(hipMalloc((void**)&g->degree, sizeof(double) * n));
-    PFE_CHECK_HIP(hipMalloc((void**)&g->wsq, sizeof(double) * n));
-    PFE_CHECK_HIP(hipMallocAsync((void**)&upper, sizeof(int) * (n + 1), st));
+    PFE_CHECK_HIP(dev_alloc((void**)&g->w32, sizeof(float) * (g->slots + 1)));
+    PFE_CHECK_HIP(dev_alloc((void**)&g->rev, sizeof(int) * (g->slots + 1)));
+    PFE_CHECK_HIP(dev_alloc((void**)&g->eid, sizeof(int) * (g->slots + 1)));
+    PFE_CHECK_HIP(dev_alloc((void**)&g->degree, sizeof(double) * n));
+    PFE_CHECK_HIP(dev_alloc((void**)&g->wsq, sizeof(double) * n));
+    PFE_CHECK_HIP(dev_alloc_async((void**)&upper, sizeof(int) * (n + 1), st));
     hipLaunchKernelGGL(k_row_finish, dim3(gridN), dim3(TB), 0, st, n, g->rowptr, g->col, g->w64, g->w32,
                        g->degree, g->wsq, upper, err);
     int* uptr = deg;   // reuse: exclusive scan of upper counts
@@ -463,25 +463,25 @@ static pfe_status build_impl(const pfe_graph_desc* d, hipStream_t st, pfe_graph*
     PFE_CHECK_HIP(hipGetLastError());
     int herr = 0;
     PFE_CHECK_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
-    PFE_CHECK_HIP(hipFreeAsync(deg, st));
-    PFE_CHECK_HIP(hipFreeAsync(err, st));
-    PFE_CHECK_HIP(hipFreeAsync(upper, st));
-    if (fill) PFE_CHECK_HIP(hipFreeAsync(fill, st));
-    if (tmp_in) PFE_CHECK_HIP(hipFreeAsync(tmp_in, st));
-    if (tmp_in2) PFE_CHECK_HIP(hipFreeAsync(tmp_in2, st));
-    if (tmp_in3) PFE_CHECK_HIP(hipFreeAsync(tmp_in3, st));
+    PFE_CHECK_HIP(dev_free_async(deg, st));
+    PFE_CHECK_HIP(dev_free_async(err, st));
+    PFE_CHECK_HIP(dev_free_async(upper, st));
+    if (fill) PFE_CHECK_HIP(dev_free_async(fill, st));
+    if (tmp_in) PFE_CHECK_HIP(dev_free_async(tmp_in, st));
+    if (tmp_in2) PFE_CHECK_HIP(dev_free_async(tmp_in2, st));
+    if (tmp_in3) PFE_CHECK_HIP(dev_free_async(tmp_in3, st));
     PFE_CHECK_HIP(hipStreamSynchronize(st));
     if (herr) { set_error("pfe_build_graph: %s", graph_err_text(herr)); return PFE_E_GRAPH; }
 
     // slot layout for the solver: ELL when padding to the largest degree costs
     // at most a quarter more slots (pixel stencils), CSR otherwise.
     int* dmax = nullptr;
-    PFE_CHECK_HIP(hipMalloc((void**)&dmax, sizeof(int)));
+    PFE_CHECK_HIP(dev_alloc((void**)&dmax, sizeof(int)));
     PFE_CHECK_HIP(hipMemsetAsync(dmax, 0, sizeof(int), st));
     hipLaunchKernelGGL(k_max_deg, dim3(gridN), dim3(TB), 0, st, n, g->rowptr, dmax);
     PFE_CHECK_HIP(hipMemcpyAsync(&g->max_deg, dmax, sizeof(int), hipMemcpyDeviceToHost, st));
     PFE_CHECK_HIP(hipStreamSynchronize(st));
-    PFE_CHECK_HIP(hipFree(dmax));
+    PFE_CHECK_HIP(dev_free(dmax));
     const int64_t ell_slots = (int64_t)g->max_deg * n;
     if (d->kind == PFE_GRID) {
         // stencil-ordered ELL (every pixel grid qualifies)
@@ -505,12 +505,12 @@ static pfe_status build_impl(const pfe_graph_desc* d, hipStream_t st, pfe_graph*
         g->ell_K = sten.k;
         g->stencil = 1;
         g->nslot = ns;
-        PFE_CHECK_HIP(hipMalloc((void**)&g->s_col, sizeof(int) * ns));
-        PFE_CHECK_HIP(hipMalloc((void**)&g->s_w32, sizeof(float) * ns));
-        PFE_CHECK_HIP(hipMalloc((void**)&g->s_w64, sizeof(double) * ns));
-        PFE_CHECK_HIP(hipMalloc((void**)&g->s_eid, sizeof(int) * ns));
+        PFE_CHECK_HIP(dev_alloc((void**)&g->s_col, sizeof(int) * ns));
+        PFE_CHECK_HIP(dev_alloc((void**)&g->s_w32, sizeof(float) * ns));
+        PFE_CHECK_HIP(dev_alloc((void**)&g->s_w64, sizeof(double) * ns));
+        PFE_CHECK_HIP(dev_alloc((void**)&g->s_eid, sizeof(int) * ns));
         int* err2 = nullptr;
-        PFE_CHECK_HIP(hipMalloc((void**)&err2, sizeof(int)));
+        PFE_CHECK_HIP(dev_alloc((void**)&err2, sizeof(int)));
         PFE_CHECK_HIP(hipMemsetAsync(err2, 0, sizeof(int), st));
         hipLaunchKernelGGL(k_build_stencil_ell, dim3(gridN), dim3(TB), 0, st, d->H, d->W, sten, g->rowptr, g->col,
                            g->w32, g->w64, g->eid, g->s_col, g->s_w32, g->s_w64, g->s_eid, err2);
@@ -518,15 +518,15 @@ static pfe_status build_impl(const pfe_graph_desc* d, hipStream_t st, pfe_graph*
         int herr2 = 0;
         PFE_CHECK_HIP(hipMemcpyAsync(&herr2, err2, sizeof(int), hipMemcpyDeviceToHost, st));
         PFE_CHECK_HIP(hipStreamSynchronize(st));
-        PFE_CHECK_HIP(hipFree(err2));
+        PFE_CHECK_HIP(dev_free(err2));
         if (herr2) { set_error("pfe_build_graph: %s", graph_err_text(herr2)); return PFE_E_GRAPH; }
     } else if (g->max_deg > 0 && 4 * ell_slots <= 5 * g->slots && ell_slots < (int64_t)INT32_MAX) {
         g->ell_K = g->max_deg;
         g->nslot = ell_slots;
-        PFE_CHECK_HIP(hipMalloc((void**)&g->s_col, sizeof(int) * ell_slots));
-        PFE_CHECK_HIP(hipMalloc((void**)&g->s_w32, sizeof(float) * ell_slots));
-        PFE_CHECK_HIP(hipMalloc((void**)&g->s_w64, sizeof(double) * ell_slots));
-        PFE_CHECK_HIP(hipMalloc((void**)&g->s_eid, sizeof(int) * ell_slots));
+        PFE_CHECK_HIP(dev_alloc((void**)&g->s_col, sizeof(int) * ell_slots));
+        PFE_CHECK_HIP(dev_alloc((void**)&g->s_w32, sizeof(float) * ell_slots));
+        PFE_CHECK_HIP(dev_alloc((void**)&g->s_w64, sizeof(double) * ell_slots));
+        PFE_CHECK_HIP(dev_alloc((void**)&g->s_eid, sizeof(int) * ell_slots));
         hipLaunchKernelGGL(k_build_ell, dim3(gridN), dim3(TB), 0, st, n, g->ell_K, g->rowptr, g->col, g->w32,
                            g->w64, g->eid, g->s_col, g->s_w32, g->s_w64, g->s_eid);
         PFE_CHECK_HIP(hipGetLastError());
@@ -652,7 +652,7 @@ pfe_status pfe_graph_union(const pfe_graph* const* parts, int count, hipStream_t
         return s;
     };
     hipError_t e = hipSuccess;
-#define UALLOC(ptr, bytes) do { if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (bytes)); } while (0)
+#define UALLOC(ptr, bytes) do { if (e == hipSuccess) e = dev_alloc((void**)&(ptr), (bytes)); } while (0)
     UALLOC(g->rowptr, sizeof(int) * (N + 1));
     UALLOC(g->col, sizeof(int) * (SL + 1));
     UALLOC(g->rev, sizeof(int) * (SL + 1));
@@ -671,7 +671,7 @@ pfe_status pfe_graph_union(const pfe_graph* const* parts, int count, hipStream_t
     if (e != hipSuccess) {
         if (!ell) g->ell_K = 0;   // nothing ELL-specific allocated
         else g->ell_K = K;
-        return fail(hip_fail(e, "hipMalloc (graph union)", __FILE__, __LINE__));
+        return fail(hip_fail(e, "device allocation (graph union)", __FILE__, __LINE__));
     }
     g->ell_K = ell ? K : 0;
     const int TB = 256;

@@ -147,13 +147,13 @@ extern "C" pfe_status pfe_kmeans(const void* Y, int64_t n, int d, int dtype, con
     hipLaunchKernelGGL(k_km_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, -1, labels);
     PFE_CHECK_HIP(hipGetLastError());
     unsigned* changed = nullptr;
-    PFE_CHECK_HIP(hipMalloc((void**)&changed, sizeof(unsigned)));
+    PFE_CHECK_HIP(dev_alloc((void**)&changed, sizeof(unsigned)));
     int it = 0;
     pfe_status s = (dtype == PFE_FP64)
                        ? km_dispatch<double>((const double*)Y, n, d, K, max_iter, labels, centroids, changed, &it, stream)
                        : km_dispatch<float>((const float*)Y, n, d, K, max_iter, labels, centroids, changed, &it, stream);
     (void)hipStreamSynchronize(stream);
-    (void)hipFree(changed);
+    (void)dev_free(changed);
     if (s == PFE_OK && iters) *iters = it;
     return s;
 }

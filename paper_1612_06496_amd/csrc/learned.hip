@@ -483,9 +483,9 @@ void free_scratch(pfe_mpnn* w) {
                       &w->gdiag, &w->rho, &w->y1, &w->y2, &w->y3, &w->es, &w->dy2, &w->dy1, &w->dgval, &w->dgdiag,
                       &w->duvz, &w->dpre2, &w->dh1, &w->dagg2, &w->tbuf, &w->dpre1};
     for (float** b : bufs)
-        if (*b) { (void)hipFree(*b); *b = nullptr; }
-    if (w->part) { (void)hipFree(w->part); w->part = nullptr; }
-    if (w->nrm) { (void)hipFree(w->nrm); w->nrm = nullptr; }
+        if (*b) { (void)dev_free(*b); *b = nullptr; }
+    if (w->part) { (void)dev_free(w->part); w->part = nullptr; }
+    if (w->nrm) { (void)dev_free(w->nrm); w->nrm = nullptr; }
     w->cap_n = w->cap_s = 0;
     w->cap_k = 0;
 }
@@ -495,18 +495,18 @@ pfe_status ensure(pfe_mpnn* w, int64_t n, int64_t ns, int k) {
     free_scratch(w);
     const int64_t nk = n * std::max(k, 1);
     hipError_t e = hipSuccess;
-#define AL(p, cnt) do { if (e == hipSuccess) e = hipMalloc((void**)&(p), sizeof(float) * (size_t)(cnt)); } while (0)
+#define AL(p, cnt) do { if (e == hipSuccess) e = dev_alloc((void**)&(p), sizeof(float) * (size_t)(cnt)); } while (0)
     AL(w->at, ns); AL(w->x, n * 4); AL(w->agg1, n * 4); AL(w->pre1, n * kH); AL(w->h1, n * kH);
     AL(w->agg2, n * kH); AL(w->pre2, n * kH); AL(w->h2, n * kH); AL(w->uvz, n * 3); AL(w->gval, ns);
     AL(w->gdiag, n); AL(w->rho, nk); AL(w->y1, nk); AL(w->y2, nk); AL(w->y3, nk); AL(w->es, nk);
     AL(w->dy2, nk); AL(w->dy1, nk); AL(w->dgval, ns); AL(w->dgdiag, n); AL(w->duvz, n * 3);
     AL(w->dpre2, n * kH); AL(w->dh1, n * kH); AL(w->dagg2, n * kH); AL(w->tbuf, n * kH); AL(w->dpre1, n * kH);
 #undef AL
-    if (e == hipSuccess) e = hipMalloc((void**)&w->part, sizeof(double) * (size_t)kRedBlocks * kNP);
-    if (e == hipSuccess) e = hipMalloc((void**)&w->nrm, sizeof(double) * 64);
+    if (e == hipSuccess) e = dev_alloc((void**)&w->part, sizeof(double) * (size_t)kRedBlocks * kNP);
+    if (e == hipSuccess) e = dev_alloc((void**)&w->nrm, sizeof(double) * 64);
     if (e != hipSuccess) {
         free_scratch(w);
-        return hip_fail(e, "hipMalloc (network scratch)", __FILE__, __LINE__);
+        return hip_fail(e, "device allocation (network scratch)", __FILE__, __LINE__);
     }
     w->cap_n = n;
     w->cap_s = ns;
@@ -632,14 +632,14 @@ pfe_status pfe_mpnn_create(const float* params, pfe_mpnn** out) {
     if (!out) { set_error("pfe_mpnn_create: null argument"); return PFE_E_ARG; }
     *out = nullptr;
     pfe_mpnn* w = new pfe_mpnn();
-    hipError_t e = hipMalloc((void**)&w->theta, sizeof(float) * kNP);
-    if (e == hipSuccess) e = hipMalloc((void**)&w->m, sizeof(float) * kNP);
-    if (e == hipSuccess) e = hipMalloc((void**)&w->v, sizeof(float) * kNP);
-    if (e == hipSuccess) e = hipMalloc((void**)&w->grad, sizeof(float) * kNP);
+    hipError_t e = dev_alloc((void**)&w->theta, sizeof(float) * kNP);
+    if (e == hipSuccess) e = dev_alloc((void**)&w->m, sizeof(float) * kNP);
+    if (e == hipSuccess) e = dev_alloc((void**)&w->v, sizeof(float) * kNP);
+    if (e == hipSuccess) e = dev_alloc((void**)&w->grad, sizeof(float) * kNP);
     if (e != hipSuccess) {
-        (void)hipFree(w->theta); (void)hipFree(w->m); (void)hipFree(w->v); (void)hipFree(w->grad);
+        (void)dev_free(w->theta); (void)dev_free(w->m); (void)dev_free(w->v); (void)dev_free(w->grad);
         delete w;
-        return hip_fail(e, "hipMalloc (network)", __FILE__, __LINE__);
+        return hip_fail(e, "device allocation (network)", __FILE__, __LINE__);
     }
     std::vector<float> th(kNP, 0.f);
     if (params) {
@@ -678,7 +678,7 @@ void pfe_mpnn_destroy(pfe_mpnn* w) {
     if (!w) return;
     (void)hipDeviceSynchronize();
     free_scratch(w);
-    (void)hipFree(w->theta); (void)hipFree(w->m); (void)hipFree(w->v); (void)hipFree(w->grad);
+    (void)dev_free(w->theta); (void)dev_free(w->m); (void)dev_free(w->v); (void)dev_free(w->grad);
     delete w;
 }
 

@@ -2949,11 +2949,11 @@ pfe_status make_partition(const std::vector<int64_t>& seg_rows, int want_blocks,
         const int rb = bit[3 * b], re = bit[3 * b + 1], rs = bit[3 * b + 2];
         if (re > rb) P.max_np = std::max(P.max_np, (re - rb + rs - 1) / rs);
     }
-    PFE_CHECK_HIP(hipMalloc((void**)&P.bit, sizeof(int) * bit.size()));
+    PFE_CHECK_HIP(dev_alloc((void**)&P.bit, sizeof(int) * bit.size()));
     PFE_CHECK_HIP(hipMemcpy(P.bit, bit.data(), sizeof(int) * bit.size(), hipMemcpyHostToDevice));
-    PFE_CHECK_HIP(hipMalloc((void**)&P.row0, sizeof(int) * (total + 1)));
-    PFE_CHECK_HIP(hipMalloc((void**)&P.blk_seg, sizeof(int) * total));
-    PFE_CHECK_HIP(hipMalloc((void**)&P.seg_blk0, sizeof(int) * (nseg + 1)));
+    PFE_CHECK_HIP(dev_alloc((void**)&P.row0, sizeof(int) * (total + 1)));
+    PFE_CHECK_HIP(dev_alloc((void**)&P.blk_seg, sizeof(int) * total));
+    PFE_CHECK_HIP(dev_alloc((void**)&P.seg_blk0, sizeof(int) * (nseg + 1)));
     PFE_CHECK_HIP(hipMemcpy(P.row0, row0.data(), sizeof(int) * (total + 1), hipMemcpyHostToDevice));
     PFE_CHECK_HIP(hipMemcpy(P.blk_seg, bseg.data(), sizeof(int) * total, hipMemcpyHostToDevice));
     PFE_CHECK_HIP(hipMemcpy(P.seg_blk0, sb0.data(), sizeof(int) * (nseg + 1), hipMemcpyHostToDevice));
@@ -2961,11 +2961,11 @@ pfe_status make_partition(const std::vector<int64_t>& seg_rows, int want_blocks,
 }
 
 void free_partition(Partition& P) {
-    if (P.geo) (void)hipFree(P.geo);
-    if (P.row0) (void)hipFree(P.row0);
-    if (P.bit) (void)hipFree(P.bit);
-    if (P.blk_seg) (void)hipFree(P.blk_seg);
-    if (P.seg_blk0) (void)hipFree(P.seg_blk0);
+    if (P.geo) (void)dev_free(P.geo);
+    if (P.row0) (void)dev_free(P.row0);
+    if (P.bit) (void)dev_free(P.bit);
+    if (P.blk_seg) (void)dev_free(P.blk_seg);
+    if (P.seg_blk0) (void)dev_free(P.seg_blk0);
     P = Partition{};
 }
 
@@ -3024,11 +3024,11 @@ pfe_status make_strip_partition(const pfe_graph* g, int d, int want_blocks, int 
     P.nblk = total;
     P.team = 1;
     P.max_np = 0;
-    PFE_CHECK_HIP(hipMalloc((void**)&P.geo, sizeof(int) * geo.size()));
-    PFE_CHECK_HIP(hipMalloc((void**)&P.bit, sizeof(int) * 3 * total));
-    PFE_CHECK_HIP(hipMalloc((void**)&P.row0, sizeof(int) * (total + 1)));
-    PFE_CHECK_HIP(hipMalloc((void**)&P.blk_seg, sizeof(int) * total));
-    PFE_CHECK_HIP(hipMalloc((void**)&P.seg_blk0, sizeof(int) * (nseg + 1)));
+    PFE_CHECK_HIP(dev_alloc((void**)&P.geo, sizeof(int) * geo.size()));
+    PFE_CHECK_HIP(dev_alloc((void**)&P.bit, sizeof(int) * 3 * total));
+    PFE_CHECK_HIP(dev_alloc((void**)&P.row0, sizeof(int) * (total + 1)));
+    PFE_CHECK_HIP(dev_alloc((void**)&P.blk_seg, sizeof(int) * total));
+    PFE_CHECK_HIP(dev_alloc((void**)&P.seg_blk0, sizeof(int) * (nseg + 1)));
     PFE_CHECK_HIP(hipMemcpy(P.geo, geo.data(), sizeof(int) * geo.size(), hipMemcpyHostToDevice));
     PFE_CHECK_HIP(hipMemcpy(P.bit, zeros.data(), sizeof(int) * 3 * total, hipMemcpyHostToDevice));
     PFE_CHECK_HIP(hipMemcpy(P.row0, zeros.data(), sizeof(int) * (total + 1), hipMemcpyHostToDevice));
@@ -3384,6 +3384,9 @@ template <typename T>
 pfe_status inner_at(pfe_ctx* c, int l) {
     KA<T> a = make_args<T>(c, c->pm);
     const KA<T> as = use_strips(c) ? make_args<T>(c, c->ps) : a;
+    // cold start: the solve begins from Y = 0 (the right-hand side does not
+    // depend on Y; the previous edge update has already consumed it)
+    if (c->prm.cold_start) PFE_CHECK_HIP(hipMemsetAsync(c->Y, 0, (size_t)c->n * c->d * sizeof(T), c->stream));
     PFE_TRY(launch_phase(c, as, (l == 0) ? PH_E0 : PH_R0, 0, 1));
     PFE_TRY(pcg_any_mk(c, a, as));
     // edge update of this inner step and rhs of the next one (on strips when
@@ -3467,7 +3470,8 @@ pfe_status outer_coop(pfe_ctx* c, int n_outer) {
 // phase; the context stays between SOC iterations (inner index 0)
 template <typename T>
 pfe_status split_bregman_run(pfe_ctx* c, int n_iter) {
-    if (c->prm.persistent && c->pc.nblk > 0 && c->prm.precond == PFE_JACOBI) return launch_soc<T>(c, n_iter, 1, 0);
+    if (c->prm.persistent && c->pc.nblk > 0 && c->prm.precond == PFE_JACOBI && !c->prm.cold_start)
+        return launch_soc<T>(c, n_iter, 1, 0);
     for (int l = 0; l < n_iter; ++l) PFE_TRY(inner_at<T>(c, l));
     return PFE_OK;
 }
@@ -3485,7 +3489,7 @@ pfe_status read_info(pfe_ctx* c, pfe_step_info* info) {
         info->rel_res_max = h.relres_max;
         info->status = h.status;
         info->fallbacks = h.fallbacks;
-        info->workgroups = (c->prm.persistent && c->pc.nblk > 0) ? c->pc.nblk : 0;
+        info->workgroups = c->launched_coop ? c->pc.nblk : 0;
         info->flags = ((c->launched_coop && c->cache_np > 0) ? 1 : 0) | ((!c->launched_coop && use_strips(c)) ? 2 : 0);
     }
     if (h.status != 0) {
@@ -3519,7 +3523,7 @@ void free_ctx(pfe_ctx* c) {
                     c->zl, c->y1, c->part, c->gpart,
                     c->Tm, c->colbuf, c->colint, c->S, c->bar, c->hist};
     for (void* p : bufs)
-        if (p) (void)hipFree(p);
+        if (p) (void)dev_free(p);
     free_partition(c->pm);
     free_partition(c->pc);
     free_partition(c->ps);
@@ -3646,7 +3650,7 @@ pfe_status fsai_factor(pfe_ctx* c) {
     const pfe_graph* g = c->g;
     const int64_t n = c->n;
     int* err = nullptr;
-    PFE_CHECK_HIP(hipMalloc((void**)&err, sizeof(int)));
+    PFE_CHECK_HIP(dev_alloc((void**)&err, sizeof(int)));
     PFE_CHECK_HIP(hipMemsetAsync(err, 0, sizeof(int), c->stream));
     const size_t ns = (size_t)g->nslot + 1;
     hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, c->stream, ns, T(0), (T*)c->gval);
@@ -3661,7 +3665,7 @@ pfe_status fsai_factor(pfe_ctx* c) {
     int h = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    (void)hipFree(err);
+    (void)dev_free(err);
     if (e != hipSuccess) return hip_fail(e, "FSAI factor", __FILE__, __LINE__);
     if (h) {
         set_error("pfe_set_fsai: %s", (h & 2) ? "slot layout is not a symmetric stencil" : "local system not positive definite");
@@ -3717,7 +3721,8 @@ pfe_status rebuild_rhs(pfe_ctx* c) {
 // n_outer SOC iterations in the context's current launch shape
 template <typename T>
 pfe_status run_outer(pfe_ctx* c, int n_outer) {
-    if (c->prm.persistent && c->pc.nblk > 0 && c->prm.precond == PFE_JACOBI) return outer_coop<T>(c, n_outer);
+    if (c->prm.persistent && c->pc.nblk > 0 && c->prm.precond == PFE_JACOBI && !c->prm.cold_start)
+        return outer_coop<T>(c, n_outer);
     for (int k = 0; k < n_outer; ++k) PFE_TRY(outer_mk<T>(c));
     return PFE_OK;
 }
@@ -3837,7 +3842,7 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
     const size_t part_doubles = (size_t)nblk_max * std::max<int64_t>(3 * c->d, 3 + 2 * npair) + 64;
     const size_t ncol = (size_t)c->nseg * c->d;
     hipError_t e = hipSuccess;
-#define ALLOC(ptr, bytes) do { if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (bytes)); } while (0)
+#define ALLOC(ptr, bytes) do { if (e == hipSuccess) e = dev_alloc((void**)&(ptr), (bytes)); } while (0)
     ALLOC(c->Y, nd); ALLOC(c->P, nd); ALLOC(c->B, nd);
     ALLOC(c->bs, sd);
     if (p->keep_split) ALLOC(c->ds, sd);
@@ -3857,7 +3862,7 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
     if (e != hipSuccess) {
         free_ctx(c);
         delete c;
-        return hip_fail(e, "hipMalloc (context)", __FILE__, __LINE__);
+        return hip_fail(e, "device allocation (context)", __FILE__, __LINE__);
     }
     c->cs.gamma = c->colbuf;
     c->cs.alpha = c->colbuf + ncol;
@@ -3940,7 +3945,7 @@ pfe_status pfe_step(pfe_ctx* c, int granularity, pfe_step_info* info) {
         if (c->inner >= c->prm.n_inner) { set_error("all inner iterations done; call pfe_step(PFE_OUTER)"); return PFE_E_STATE; }
         s = f64 ? inner_mk<double>(c) : inner_mk<float>(c);
     } else if (granularity == PFE_OUTER) {
-        if (c->prm.persistent && c->pc.nblk > 0 && c->inner == 0 && c->prm.precond == PFE_JACOBI)
+        if (c->prm.persistent && c->pc.nblk > 0 && c->inner == 0 && c->prm.precond == PFE_JACOBI && !c->prm.cold_start)
             s = f64 ? outer_coop<double>(c, 1) : outer_coop<float>(c, 1);
         else
             s = f64 ? outer_mk<double>(c) : outer_mk<float>(c);
@@ -3958,7 +3963,7 @@ pfe_status pfe_solve(pfe_ctx* c, int n_outer, pfe_step_info* info) {
     c->launched_coop = 0;
     if (info) PFE_TRY(reset_stats(c));
     const bool f64 = c->prm.dtype == PFE_FP64;
-    if (c->prm.persistent && c->pc.nblk > 0 && n_outer > 0 && c->prm.precond == PFE_JACOBI) {
+    if (c->prm.persistent && c->pc.nblk > 0 && n_outer > 0 && c->prm.precond == PFE_JACOBI && !c->prm.cold_start) {
         PFE_TRY(f64 ? outer_coop<double>(c, n_outer) : outer_coop<float>(c, n_outer));
     } else {
         for (int k = 0; k < n_outer; ++k) PFE_TRY(f64 ? outer_mk<double>(c) : outer_mk<float>(c));
@@ -4006,7 +4011,7 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
     double best_ms = 0.0;
     std::vector<pfe_tune_result> found;
     do {
-        if (hipMalloc((void**)&save, 3 * nd) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        if (dev_alloc((void**)&save, 3 * nd) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
             hipEventCreate(&e1) != hipSuccess) {
             st = hip_fail(hipGetLastError(), "pfe_autotune set-up", __FILE__, __LINE__);
             break;
@@ -4019,7 +4024,7 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
         }
         for (int k = 0; k < (int)(sizeof(shapes) / sizeof(shapes[0])) && st == PFE_OK; ++k) {
             const Shape& sh = shapes[k];
-            if (sh.persistent && (c->coop < kNumXcd || c->prm.precond != PFE_JACOBI)) continue;
+            if (sh.persistent && (c->coop < kNumXcd || c->prm.precond != PFE_JACOBI || c->prm.cold_start)) continue;
             if (sh.strips && c->strip_slots == 0) continue;
             if (sh.w2 != 1.0 && c->per_cu != 2) continue;
             c->prm.persistent = sh.persistent;
@@ -4079,7 +4084,7 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
     if (st == PFE_OK) st = s2;
     if (save && st == PFE_OK) st = restore();
     (void)hipStreamSynchronize(c->stream);
-    if (save) (void)hipFree(save);
+    if (save) (void)dev_free(save);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (st == PFE_OK) st = reset_stats(c);

@@ -49,6 +49,41 @@ def kmeans(Y, C0, max_iter: int = 100, stream: Optional[torch.cuda.Stream] = Non
     return labels, cen, iters.value
 
 
+_TORCH_ALLOC = None
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """Route the library's device memory through PyTorch's caching allocator
+    (pfe_set_allocator), or back to hipMalloc.  Only while no graph, solver or
+    network of the library is alive."""
+    global _TORCH_ALLOC
+    if not enable:
+        L.check(L.lib.pfe_set_allocator(None, None, None), "pfe_set_allocator")
+        _TORCH_ALLOC = None
+        return
+    alloc_t = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
+    free_t = C.CFUNCTYPE(None, C.c_void_p, C.c_int, C.c_void_p)
+
+    def _alloc(nbytes, device, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device)
+        except Exception:      # out of memory: the library reports the failure
+            return None
+
+    def _free(ptr, device, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    fns = (alloc_t(_alloc), free_t(_free))       # kept alive while installed
+    L.check(L.lib.pfe_set_allocator(C.cast(fns[0], C.c_void_p), C.cast(fns[1], C.c_void_p), None),
+            "pfe_set_allocator")
+    _TORCH_ALLOC = fns
+
+
+def live_allocations() -> int:
+    """Device allocations of the library currently live."""
+    return int(L.lib.pfe_live_allocations())
+
+
 class Graph:
     """A graph built by pfe_build_graph (CSR adjacency, heat-kernel weights)."""
 
@@ -125,7 +160,8 @@ class Solver:
 
     def __init__(self, graph: Graph, Y0, *, lam: float, r: float, n_inner: int, tol: float = 1e-6,
                  maxit: int = 1000, ortho: str = "polar", fp64: bool = False, init_ortho: bool = True,
-                 keep_split: bool = False, persistent: bool = True, graphs: bool = False, stream=None):
+                 keep_split: bool = False, persistent: bool = True, graphs: bool = False,
+                 warm_start: bool = True, stream=None):
         self.graph = graph
         self.dtype = torch.float64 if fp64 else torch.float32
         y0 = _dev(Y0, self.dtype)
@@ -134,7 +170,8 @@ class Solver:
             d=self.d, lambda_=lam, r=r, n_inner=n_inner, tol=tol, maxit=maxit,
             precond=L.PFE_JACOBI, ortho=L.PFE_POLAR if ortho == "polar" else L.PFE_CHOL,
             dtype=L.PFE_FP64 if fp64 else L.PFE_FP32, init_ortho=int(init_ortho),
-            keep_split=int(keep_split), persistent=int(persistent), graphs=int(graphs))
+            keep_split=int(keep_split), persistent=int(persistent), graphs=int(graphs),
+            cold_start=int(not warm_start))
         self._stream = stream
         h = C.c_void_p()
         L.check(L.lib.pfe_init(graph._h, C.byref(self.params), y0.data_ptr(), _stream_handle(stream),
