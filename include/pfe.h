@@ -167,6 +167,9 @@ typedef struct {
     double constraint;       /* max |Yhat^T D Yhat - I| */
     double split;            /* ||D^{1/2} Y - P||_F / ||P||_F */
     double orthogonality;    /* max |P^T P - I| */
+    double split_nonzero;    /* fraction of nonzero entries of the split variable d
+                                as last stored (keep_split = 1; -1 otherwise): the
+                                share of edge differences the shrink left active */
 } pfe_monitors;
 
 /* ---- graph ------------------------------------------------------------ */

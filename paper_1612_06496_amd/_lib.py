@@ -63,7 +63,7 @@ class pfe_step_info(C.Structure):
 
 class pfe_monitors(C.Structure):
     _fields_ = [("objective", C.c_double), ("constraint", C.c_double),
-                ("split", C.c_double), ("orthogonality", C.c_double)]
+                ("split", C.c_double), ("orthogonality", C.c_double), ("split_nonzero", C.c_double)]
 
 
 class pfe_tune_result(C.Structure):

@@ -2638,6 +2638,24 @@ __global__ void k_hist(KA<T> a, int shift, int nbits, unsigned long long prefix,
 // like the learned factor: Gt = G D_A^{1/2} on both slots of every edge (the
 // edge's lower-triangular entry) and on the diagonal.
 // ---------------------------------------------------------------------------
+// nonzero entries of the stored split variable d over the slots of real
+// edges (each edge's two slots hold d and -d, so the fraction is per edge)
+template <typename T>
+__global__ void k_count_nonzero(int64_t nslot, int d, const int* __restrict__ seid, const T* __restrict__ ds,
+                                unsigned long long* __restrict__ cnt) {
+    __shared__ unsigned long long s_cnt;
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    unsigned long long mine = 0;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslot; s += (int64_t)gridDim.x * blockDim.x) {
+        if (seid[s] < 0) continue;
+        for (int c = 0; c < d; ++c) mine += (ds[(size_t)s * d + c] != T(0));
+    }
+    if (mine) atomicAdd(&s_cnt, mine);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cnt) atomicAdd(cnt, s_cnt);
+}
+
 struct FsaiArgs {
     int64_t n;
     const int* scol;
@@ -3556,6 +3574,20 @@ pfe_status monitor_impl(pfe_ctx* c, pfe_monitors* out) {
     out->constraint = mon[1];
     out->split = mon[2];
     out->orthogonality = mon[3];
+    out->split_nonzero = -1.0;
+    if (c->ds && c->g->n_edges > 0) {
+        unsigned long long* cnt = reinterpret_cast<unsigned long long*>(c->hist);
+        PFE_CHECK_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), c->stream));
+        const int64_t ns = c->g->nslot;
+        const unsigned grid = (unsigned)std::min<int64_t>((ns + 255) / 256, 2048);
+        hipLaunchKernelGGL(k_count_nonzero<T>, dim3(grid), dim3(256), 0, c->stream, ns, (int)c->d, c->g->s_eid,
+                           (const T*)c->ds, cnt);
+        PFE_CHECK_HIP(hipGetLastError());
+        unsigned long long h = 0;
+        PFE_CHECK_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+        PFE_CHECK_HIP(hipStreamSynchronize(c->stream));
+        out->split_nonzero = (double)h / (2.0 * (double)c->g->n_edges * (double)c->d);
+    }
     return PFE_OK;
 }
 

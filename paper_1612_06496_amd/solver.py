@@ -251,7 +251,7 @@ class Solver:
         m = L.pfe_monitors()
         L.check(L.lib.pfe_monitor(self._h, C.byref(m)), "pfe_monitor")
         return dict(objective=m.objective, constraint=m.constraint, split=m.split,
-                    orthogonality=m.orthogonality)
+                    orthogonality=m.orthogonality, split_nonzero=m.split_nonzero)
 
     # -- operator and solver entry points ------------------------------------
     def apply_A(self, X) -> torch.Tensor:

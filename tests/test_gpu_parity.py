@@ -179,6 +179,11 @@ def test_inner_step_parity(name, fp64):
     assert eY <= bound and eb <= bound and ed <= bound
     if wl.lam is None:
         assert frac > 0.0      # the shrink is active
+    # monitor: nonzero fraction of the stored d (entries with |t| at the
+    # threshold may fall either way in FP32)
+    nz = S.monitor()["split_nonzero"]
+    print(f"nonzero d fraction: GPU monitor {nz:.5f}, oracle {frac:.5f}")
+    assert abs(nz - frac) <= (1e-12 if fp64 else 1e-3)
 
 
 @pytest.mark.parametrize("name,fp64", STEP_CASES)
@@ -204,6 +209,7 @@ def test_outer_step_parity(name, fp64, ortho):
     assert eY <= bound and eP <= bound and eB <= bound
     m = S.monitor()
     assert m["orthogonality"] <= (1e-12 if fp64 else 1e-5)
+    assert m["split_nonzero"] == -1.0          # d is not stored without keep_split
 
 
 # --- end to end ------------------------------------------------------------------
