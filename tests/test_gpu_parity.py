@@ -427,3 +427,58 @@ def test_second_workgroup_weight_partition(monkeypatch):
     print(f"weighted vs equal rows: rel {e:.2e}")
     assert e <= 1e-5
     assert all(np.array_equal(out[1][k], out[2][k]) for k in range(2))
+
+
+def test_headline_image_soc_iterations_vs_oracle():
+    """481x321, d = 10, shrink-active penalties: two SOC iterations (10 inner
+    solves each) in the launch shape the autotuner picks, as the benchmark runs
+    them, against the oracle's direct solves; the GPU monitors against the
+    oracle's objective and constraint."""
+    from paper_1612_06496_amd import Solver
+    wl = load("voronoi481x321_8nbr")
+    banner("481x321 full size: 2 SOC iterations in the autotuned shape vs oracle")
+    g = oracle_graph(wl)
+    Y0 = O.orthonormalize_init(g, wl.y0)
+    c = O.shrink_active_scale(g, Y0)
+    ref = O.pfe_run(g, Y0, c, c, 2, wl.n_inner)
+    S = Solver(gpu_graph(wl), Y0, lam=c, r=c, n_inner=wl.n_inner, tol=1e-6, maxit=1000, init_ortho=False)
+    shapes = S.autotune(1)
+    info = S.solve(2, info=True)
+    eY, eP = rel(to_np(S.get("Y")), ref.Y), rel(to_np(S.get("P")), ref.P)
+    yh = ref.yhat(g)
+    m = S.monitor()
+    f_ref = O.objective(g, yh)
+    chosen = [s for s in shapes if s["chosen"]][0]
+    print(f"Y {eY:.2e} P {eP:.2e}; objective {m['objective']:.6e} vs {f_ref:.6e}; constraint {m['constraint']:.2e}; "
+          f"shape {chosen}; CG iterations per solve {info['cg_iters_total'] / info['solves']:.2f}")
+    assert eY <= 2e-5 and eP <= 2e-5
+    assert abs(m["objective"] - f_ref) <= 1e-3 * f_ref
+    assert m["constraint"] <= 1e-5
+    assert O.constraint_residual(g, to_np(S.get("Yhat"))) <= 1e-5
+
+
+@pytest.mark.parametrize("persistent", [True, False])
+def test_lambda_zero_reduces_to_scaled_split_target(persistent):
+    """lambda = 0 (no edge term, infinite shrink threshold): every inner solve
+    gives Y = D^{-1/2} (P - B) exactly (Eq. 13 with A = r/2 D), so a SOC
+    iteration from an oracle state with B != 0 equals the oracle's, in both
+    launch shapes."""
+    from paper_1612_06496_amd import Solver
+    wl = load("voronoi96x80_8nbr")
+    banner(f"lambda = 0, persistent={persistent}")
+    g = oracle_graph(wl)
+    lam0, r0 = penalties(wl, g, O.orthonormalize_init(g, wl.y0))
+    solve, Y, P, B, _, _ = mid_run_state(g, wl, lam0, r0, 1, 0)
+    r = r0
+    S = Solver(gpu_graph(wl), Y, lam=0.0, r=r, n_inner=wl.n_inner, tol=1e-13, maxit=100, fp64=True,
+               init_ortho=False, persistent=persistent)
+    S.set("Y", Y); S.set("P", P); S.set("B", B)
+    info = S.step("outer", info=True)
+    target = (P - B) / np.sqrt(g.D)[:, None]
+    Y1, P1, B1 = O.soc_outer_step(g, O.DirectSolver(O.system_matrix(g, 0.0, r)), Y, P, B, 0.0, r, wl.n_inner)
+    eT = rel(to_np(S.get("Y")), target)
+    eP = rel(to_np(S.get("P")), P1)
+    print(f"Y vs D^-1/2 (P - B): {eT:.2e}; P vs oracle {eP:.2e}; CG iterations per solve "
+          f"{info['cg_iters_total'] / info['solves']:.2f}")
+    assert eT <= 1e-12 and eP <= 1e-12
+    assert info["cg_iters_max"] <= 1
