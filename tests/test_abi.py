@@ -71,3 +71,26 @@ def test_struct_layouts_match_header(tmp_path):
         for fname, _ in st._fields_:
             want.append(getattr(st, fname).offset)
     assert got == want
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpfe.so not built")
+def test_argument_checks_of_later_entry_points_need_no_gpu():
+    """Argument validation of the Stage II, FSAI, k-means and allocator entry
+    points happens on the host before any device call."""
+    import ctypes as C
+    from paper_1612_06496_amd import _lib as L
+    lib = L.lib
+    assert lib.pfe_split_bregman(None, 3, None) == L.PFE_E_ARG
+    assert lib.pfe_set_fsai(None) == L.PFE_E_ARG
+    it = C.c_int32()
+    # k-means: null pointers, K above 256, d above 32, no iteration
+    assert lib.pfe_kmeans(None, 10, 4, L.PFE_FP32, None, 3, 10, None, None, C.byref(it), None) == L.PFE_E_ARG
+    dummy = C.c_void_p(1)
+    assert lib.pfe_kmeans(dummy, 10, 4, L.PFE_FP32, dummy, 300, 10, dummy, dummy, None, None) == L.PFE_E_ARG
+    assert lib.pfe_kmeans(dummy, 10, 40, L.PFE_FP32, dummy, 3, 10, dummy, dummy, None, None) == L.PFE_E_ARG
+    assert lib.pfe_kmeans(dummy, 10, 4, L.PFE_FP32, dummy, 3, 0, dummy, dummy, None, None) == L.PFE_E_ARG
+    assert lib.pfe_kmeans(dummy, 10, 4, 7, dummy, 3, 10, dummy, dummy, None, None) == L.PFE_E_ARG
+    # allocator: both functions or neither; no live allocation in a fresh process
+    assert lib.pfe_live_allocations() == 0
+    assert lib.pfe_set_allocator(dummy, None, None) == L.PFE_E_ARG
+    assert lib.pfe_set_allocator(None, None, None) == L.PFE_OK
