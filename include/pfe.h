@@ -387,7 +387,9 @@ void pfe_destroy_ctx(pfe_ctx* c);
  * labels (device, n int32) and centroids (device, K x d doubles; may be C0)
  * receive the result, iters (host, may be null) the iterations run.
  * 1 <= d <= 32, 1 <= K <= 256, K d <= 8000, n < 2^31.  Synchronises the
- * stream (the stopping test reads a count back after every iteration). */
+ * stream: iterations are launched in groups of 8 and the host reads the
+ * convergence state after each group (iterations after convergence return
+ * at once on the device). */
 pfe_status pfe_kmeans(const void* Y, int64_t n, int d, int dtype, const double* C0, int K, int max_iter,
                       int32_t* labels, double* centroids, int32_t* iters, hipStream_t stream);
 

@@ -6,10 +6,12 @@
 // The squared distance is summed over the coordinates in order with every
 // product and sum rounded on its own (contraction off), so the nearest
 // centroid (ties to the lowest index) is decided in FP64 by a fixed sequence
-// of operations.  Update: one workgroup per centroid; each thread sums the
-// rows of that centroid among its strided share of the rows, then a fixed
-// tree over the workgroup combines them (deterministic); a centroid without
-// rows keeps its position.
+// of operations.  Update: one workgroup per (centroid, row slice) sums that
+// centroid's rows in the slice (strided over the threads, then a fixed tree
+// over the workgroup), and one thread per centroid coordinate adds the slices
+// in order (deterministic); a centroid without rows keeps its position.
+// Iterations run in groups launched back to back; a device flag makes the
+// kernels of the iterations after convergence return at once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,8 +28,10 @@ constexpr int kKmThreads = 256;
 template <typename T, int DMAX>
 __global__ void __launch_bounds__(kKmThreads) k_km_assign(const T* __restrict__ Y, int64_t n, int d,
                                                           const double* __restrict__ C, int K,
-                                                          int32_t* __restrict__ labels, unsigned* __restrict__ changed) {
+                                                          int32_t* __restrict__ labels, unsigned* __restrict__ st) {
 #pragma clang fp contract(off)
+    if (st[1]) return;   // converged in an earlier iteration of the chunk
+    unsigned* changed = st;
     extern __shared__ double sc[];
     __shared__ unsigned s_changed;
     if (threadIdx.x == 0) s_changed = 0;
@@ -60,39 +64,73 @@ __global__ void __launch_bounds__(kKmThreads) k_km_assign(const T* __restrict__ 
     if (threadIdx.x == 0 && s_changed) atomicAdd(changed, s_changed);
 }
 
+// sums of the rows of centroid k (blockIdx.x) in row slice s (blockIdx.y):
+// part[(k S + s) (d + 1) + c] for the d coordinates, then the row count
 template <typename T, int DMAX>
-__global__ void __launch_bounds__(kKmThreads) k_km_update(const T* __restrict__ Y, int64_t n, int d,
-                                                          const int32_t* __restrict__ labels, double* __restrict__ C) {
+__global__ void __launch_bounds__(kKmThreads) k_km_partial(const T* __restrict__ Y, int64_t n, int d,
+                                                           const int32_t* __restrict__ labels,
+                                                           double* __restrict__ part, const unsigned* __restrict__ st) {
+    if (st[1]) return;
     __shared__ double red[kKmThreads];
-    __shared__ double sums[DMAX + 1];
-    const int k = blockIdx.x, t = threadIdx.x;
+    const int k = blockIdx.x, sl = blockIdx.y, S = gridDim.y, t = threadIdx.x;
+    const int64_t per = (n + S - 1) / S;
+    const int64_t r0 = (int64_t)sl * per, r1 = (r0 + per < n) ? r0 + per : n;
     double acc[DMAX];
 #pragma unroll
     for (int c = 0; c < DMAX; ++c) acc[c] = 0.0;
     double cnt = 0.0;
-    for (int64_t i = t; i < n; i += kKmThreads) {
+    for (int64_t i = r0 + t; i < r1; i += kKmThreads) {
         if (labels[i] != k) continue;
         cnt += 1.0;
 #pragma unroll
         for (int c = 0; c < DMAX; ++c)
             if (c < d) acc[c] += (double)Y[i * d + c];
     }
+    double* out = part + ((size_t)k * S + sl) * (d + 1);
     // fixed-order tree over the workgroup, one coordinate at a time (the count last)
 #pragma unroll
     for (int c = 0; c <= DMAX; ++c) {
         if (c < d || c == DMAX) {
             red[t] = (c == DMAX) ? cnt : acc[c];
             __syncthreads();
-            for (int s = kKmThreads / 2; s > 0; s >>= 1) {
-                if (t < s) red[t] += red[t + s];
+            for (int h = kKmThreads / 2; h > 0; h >>= 1) {
+                if (t < h) red[t] += red[t + h];
                 __syncthreads();
             }
-            if (t == 0) sums[c] = red[0];
+            if (t == 0) out[c == DMAX ? d : c] = red[0];
             __syncthreads();
         }
     }
-    const double total = sums[DMAX];
-    if (total > 0.0 && t < d) C[(size_t)k * d + t] = sums[t] / total;
+}
+
+// centroid k moves to the mean of its rows (slices summed in order); a
+// centroid without rows stays
+__global__ void k_km_move(const double* __restrict__ part, int K, int d, int S, double* __restrict__ C,
+                          const unsigned* __restrict__ st) {
+    if (st[1]) return;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= K * d) return;
+    const int k = idx / d, c = idx - k * d;
+    double sum = 0.0, cnt = 0.0;
+    for (int sl = 0; sl < S; ++sl) {
+        const double* p = part + ((size_t)k * S + sl) * (d + 1);
+        sum += p[c];
+        cnt += p[d];
+    }
+    if (cnt > 0.0) C[idx] = sum / cnt;
+}
+
+// before an iteration: clear the change count (unless converged)
+__global__ void k_km_begin(unsigned* st) {
+    if (threadIdx.x == 0 && !st[1]) st[0] = 0;
+}
+
+// after an iteration: count it, and stop when no label changed
+__global__ void k_km_end(unsigned* st) {
+    if (threadIdx.x == 0 && !st[1]) {
+        st[2] += 1;
+        if (st[0] == 0) st[1] = 1;
+    }
 }
 
 __global__ void k_km_fill(int64_t n, int32_t v, int32_t* __restrict__ out) {
@@ -100,34 +138,45 @@ __global__ void k_km_fill(int64_t n, int32_t v, int32_t* __restrict__ out) {
     if (i < n) out[i] = v;
 }
 
+// iterations in chunks of kKmChunk launched back to back; the device state
+// stops the kernels of an iteration after convergence, and the host reads it
+// once per chunk
+constexpr int kKmChunk = 8;
+
 template <typename T, int DMAX>
-pfe_status km_run(const T* Y, int64_t n, int d, int K, int max_iter, int32_t* labels, double* C, unsigned* changed,
-                  int* iters, hipStream_t st) {
+pfe_status km_run(const T* Y, int64_t n, int d, int K, int max_iter, int32_t* labels, double* C, unsigned* st,
+                  double* part, int S, int* iters, hipStream_t stream) {
     const int64_t want = (n + kKmThreads - 1) / kKmThreads;
     const unsigned grid = (unsigned)std::min<int64_t>(want, 4096);
     const size_t lds = sizeof(double) * (size_t)K * d;
-    int it = 0;
-    for (it = 1; it <= max_iter; ++it) {
-        PFE_CHECK_HIP(hipMemsetAsync(changed, 0, sizeof(unsigned), st));
-        hipLaunchKernelGGL((k_km_assign<T, DMAX>), dim3(grid), dim3(kKmThreads), lds, st, Y, n, d, C, K, labels,
-                           changed);
-        hipLaunchKernelGGL((k_km_update<T, DMAX>), dim3(K), dim3(kKmThreads), 0, st, Y, n, d, labels, C);
+    unsigned h[3] = {0, 0, 0};
+    for (int done_it = 0; done_it < max_iter;) {
+        const int chunk = std::min(kKmChunk, max_iter - done_it);
+        for (int k = 0; k < chunk; ++k) {
+            hipLaunchKernelGGL(k_km_begin, dim3(1), dim3(64), 0, stream, st);
+            hipLaunchKernelGGL((k_km_assign<T, DMAX>), dim3(grid), dim3(kKmThreads), lds, stream, Y, n, d, C, K,
+                               labels, st);
+            hipLaunchKernelGGL((k_km_partial<T, DMAX>), dim3(K, S), dim3(kKmThreads), 0, stream, Y, n, d, labels,
+                               part, st);
+            hipLaunchKernelGGL(k_km_move, dim3((K * d + 255) / 256), dim3(256), 0, stream, part, K, d, S, C, st);
+            hipLaunchKernelGGL(k_km_end, dim3(1), dim3(64), 0, stream, st);
+        }
         PFE_CHECK_HIP(hipGetLastError());
-        unsigned h = 0;
-        PFE_CHECK_HIP(hipMemcpyAsync(&h, changed, sizeof(unsigned), hipMemcpyDeviceToHost, st));
-        PFE_CHECK_HIP(hipStreamSynchronize(st));
-        if (h == 0) break;
+        done_it += chunk;
+        PFE_CHECK_HIP(hipMemcpyAsync(h, st, sizeof(h), hipMemcpyDeviceToHost, stream));
+        PFE_CHECK_HIP(hipStreamSynchronize(stream));
+        if (h[1]) break;
     }
-    if (iters) *iters = std::min(it, max_iter);
+    if (iters) *iters = (int)h[2];
     return PFE_OK;
 }
 
 template <typename T>
 pfe_status km_dispatch(const T* Y, int64_t n, int d, int K, int max_iter, int32_t* labels, double* C,
-                       unsigned* changed, int* iters, hipStream_t st) {
-    if (d <= 8) return km_run<T, 8>(Y, n, d, K, max_iter, labels, C, changed, iters, st);
-    if (d <= 16) return km_run<T, 16>(Y, n, d, K, max_iter, labels, C, changed, iters, st);
-    return km_run<T, 32>(Y, n, d, K, max_iter, labels, C, changed, iters, st);
+                       unsigned* changed, double* part, int S, int* iters, hipStream_t st) {
+    if (d <= 8) return km_run<T, 8>(Y, n, d, K, max_iter, labels, C, changed, part, S, iters, st);
+    if (d <= 16) return km_run<T, 16>(Y, n, d, K, max_iter, labels, C, changed, part, S, iters, st);
+    return km_run<T, 32>(Y, n, d, K, max_iter, labels, C, changed, part, S, iters, st);
 }
 
 }  // namespace pfe
@@ -146,13 +195,25 @@ extern "C" pfe_status pfe_kmeans(const void* Y, int64_t n, int d, int dtype, con
         PFE_CHECK_HIP(hipMemcpyAsync(centroids, C0, sizeof(double) * (size_t)K * d, hipMemcpyDeviceToDevice, stream));
     hipLaunchKernelGGL(k_km_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, -1, labels);
     PFE_CHECK_HIP(hipGetLastError());
-    unsigned* changed = nullptr;
-    PFE_CHECK_HIP(dev_alloc((void**)&changed, sizeof(unsigned)));
+    // row slices of the centroid sums: about 4096 rows each, at most 64
+    const int S = (int)std::max<int64_t>(1, std::min<int64_t>(64, n / 4096));
+    unsigned* changed = nullptr;   // device state: change count, converged flag, iterations run
+    double* part = nullptr;        // K x S x (d + 1) slice sums
+    PFE_CHECK_HIP(dev_alloc((void**)&changed, 3 * sizeof(unsigned)));
+    hipError_t e = dev_alloc((void**)&part, sizeof(double) * (size_t)K * S * (d + 1));
+    if (e != hipSuccess) {
+        (void)dev_free(changed);
+        return hip_fail(e, "device allocation (k-means)", __FILE__, __LINE__);
+    }
+    PFE_CHECK_HIP(hipMemsetAsync(changed, 0, 3 * sizeof(unsigned), stream));
     int it = 0;
     pfe_status s = (dtype == PFE_FP64)
-                       ? km_dispatch<double>((const double*)Y, n, d, K, max_iter, labels, centroids, changed, &it, stream)
-                       : km_dispatch<float>((const float*)Y, n, d, K, max_iter, labels, centroids, changed, &it, stream);
+                       ? km_dispatch<double>((const double*)Y, n, d, K, max_iter, labels, centroids, changed, part, S,
+                                             &it, stream)
+                       : km_dispatch<float>((const float*)Y, n, d, K, max_iter, labels, centroids, changed, part, S,
+                                            &it, stream);
     (void)hipStreamSynchronize(stream);
+    (void)dev_free(part);
     (void)dev_free(changed);
     if (s == PFE_OK && iters) *iters = it;
     return s;
