@@ -188,3 +188,26 @@ def test_full_size_counts_match_stored_oracle_counts():
             want = np.asarray(want)
             assert np.all(np.abs(got - want) <= np.maximum(2, 0.03 * want)), (ratio, got, want)
         del S
+
+
+def test_soc_iteration_with_fsai_matches_oracle():
+    """A SOC iteration whose solves use the FSAI factor (FP64, PCG to 1e-12)
+    equals the oracle's (direct solves): the preconditioner changes the
+    iteration counts, not the result."""
+    from gpu_helpers import mid_run_state, penalties
+    wl = case("voronoi48x40_r2")
+    banner("SOC iteration with FSAI vs oracle")
+    g = oracle_graph(wl)
+    lam, r = penalties(wl, g, O.orthonormalize_init(g, wl.y0))
+    solve, Y, P, B, _, _ = mid_run_state(g, wl, lam, r, 1, 0)
+    Y1, P1, B1 = O.soc_outer_step(g, solve, Y, P, B, lam, r, wl.n_inner)
+    from paper_1612_06496_amd import Solver
+    S = Solver(gpu_graph(wl), Y, lam=lam, r=r, n_inner=wl.n_inner, tol=1e-12, maxit=3000, fp64=True,
+               init_ortho=False, persistent=True)
+    S.set("Y", Y); S.set("P", P); S.set("B", B)
+    S.set_fsai()
+    info = S.step("outer", info=True)
+    eY, eP = rel(to_np(S.get("Y")), Y1), rel(to_np(S.get("P")), P1)
+    print(f"Y {eY:.2e} P {eP:.2e}; CG iterations {info['cg_iters_total']}; workgroups {info['workgroups']}")
+    assert eY <= 1e-9 and eP <= 1e-9
+    assert info["workgroups"] == 0     # factor preconditioners run one launch per phase

@@ -194,3 +194,25 @@ def test_stage2_batch_matches_oracle_per_image(persistent):
     print(f"worst image Y rel err {worst:.2e}; solves {info['solves']}")
     assert worst <= 1e-9
     assert np.array_equal(to_np(S.get("P")), P0)
+
+
+def test_stage2_with_factor_preconditioner_and_cold_start(monkeypatch):
+    """Stage II with the identity network as the factor preconditioner (Gt = I
+    is Jacobi) and with cold-started solves: both equal the oracle (FP64)."""
+    from paper_1612_06496_amd import Mpnn, Solver
+    wl = load("voronoi96x80_8nbr")
+    banner("stage II: identity factor, cold start")
+    g = oracle_graph(wl)
+    lam, r = penalties(wl, g, O.orthonormalize_init(g, wl.y0))
+    solve, Y, P, B = oracle_state(g, wl, lam, r, 1)
+    Y_ref, _, _ = O.split_bregman(g, solve, Y, P, B, lam, r, 6)
+    for variant in ("identity factor", "cold start"):
+        S = Solver(gpu_graph(wl), Y, lam=lam, r=r, n_inner=wl.n_inner, tol=1e-12, maxit=3000, fp64=True,
+                   init_ortho=False, persistent=True, warm_start=(variant != "cold start"))
+        S.set("Y", Y); S.set("P", P); S.set("B", B)
+        if variant == "identity factor":
+            S.set_learned(Mpnn(None))
+        info = S.split_bregman(6, info=True)
+        e = rel(to_np(S.get("Y")), Y_ref)
+        print(f"{variant}: Y rel err {e:.2e}; CG iterations {info['cg_iters_total']}")
+        assert e <= 1e-9 and info["workgroups"] == 0
