@@ -335,6 +335,13 @@ pfe_status pfe_mpnn_get_params(pfe_mpnn* net, float* params, float* grad);
 /* Replace the parameters (host array) and reset the Adam state. */
 pfe_status pfe_mpnn_set_params(pfe_mpnn* net, const float* params);
 void pfe_mpnn_destroy(pfe_mpnn* net);
+/* Save the parameters to a network file / create a network from one (host
+ * path): an 8-byte magic "PFEMPNN1", a uint32 count (PFE_MPNN_NPARAMS), then
+ * the parameters as little-endian float32.  pfe_mpnn_load rejects a file of
+ * another size, magic or count, or with non-finite values (PFE_E_ARG) before
+ * any device memory is taken. */
+pfe_status pfe_mpnn_save(pfe_mpnn* net, const char* path);
+pfe_status pfe_mpnn_load(const char* path, pfe_mpnn** out);
 
 /* One training step on the context's system: samples are k residual vectors
  * (device, n x k row-major, context element type, 1 <= k <= 32), scaled to

@@ -101,6 +101,8 @@ SIGNATURES = {
     "pfe_mpnn_get_params": (_S, [_P, _P, _P]),
     "pfe_mpnn_set_params": (_S, [_P, _P]),
     "pfe_mpnn_destroy": (None, [_P]),
+    "pfe_mpnn_save": (_S, [_P, C.c_char_p]),
+    "pfe_mpnn_load": (_S, [C.c_char_p, C.POINTER(_P)]),
     "pfe_mpnn_train_step": (_S, [_P, _P, _P, C.c_int, C.c_float, C.POINTER(C.c_double)]),
     "pfe_set_learned": (_S, [_P, _P]),
     "pfe_set_preconditioner": (_S, [_P, C.c_int]),

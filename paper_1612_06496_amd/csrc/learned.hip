@@ -16,6 +16,7 @@
 // mean_k ||At Gt^T Gt rho_k - rho_k||^2 over unit-norm scaled residuals
 // rho = D_A^{-1/2} r / ||D_A^{-1/2} r|| with Adam.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -672,6 +673,43 @@ pfe_status pfe_mpnn_set_params(pfe_mpnn* w, const float* params) {
     PFE_CHECK_HIP(hipMemset(w->v, 0, sizeof(float) * kNP));
     w->t = 0;
     return PFE_OK;
+}
+
+// network file: 8-byte magic, uint32 parameter count, the parameters as
+// little-endian float32 (the layout of PFE_MPNN_NPARAMS)
+static const char kMpnnMagic[8] = {'P', 'F', 'E', 'M', 'P', 'N', 'N', '1'};
+
+pfe_status pfe_mpnn_save(pfe_mpnn* w, const char* path) {
+    if (!w || !path) { set_error("pfe_mpnn_save: null argument"); return PFE_E_ARG; }
+    std::vector<float> th(kNP);
+    const pfe_status st = pfe_mpnn_get_params(w, th.data(), nullptr);
+    if (st != PFE_OK) return st;
+    FILE* f = fopen(path, "wb");
+    if (!f) { set_error("pfe_mpnn_save: cannot open %s", path); return PFE_E_ARG; }
+    const uint32_t count = (uint32_t)kNP;
+    const bool ok = fwrite(kMpnnMagic, 1, 8, f) == 8 && fwrite(&count, 4, 1, f) == 1 &&
+                    fwrite(th.data(), sizeof(float), kNP, f) == (size_t)kNP;
+    if (fclose(f) != 0 || !ok) { set_error("pfe_mpnn_save: write to %s failed", path); return PFE_E_ARG; }
+    return PFE_OK;
+}
+
+pfe_status pfe_mpnn_load(const char* path, pfe_mpnn** out) {
+    if (!path || !out) { set_error("pfe_mpnn_load: null argument"); return PFE_E_ARG; }
+    *out = nullptr;
+    FILE* f = fopen(path, "rb");
+    if (!f) { set_error("pfe_mpnn_load: cannot open %s", path); return PFE_E_ARG; }
+    char magic[8];
+    uint32_t count = 0;
+    std::vector<float> th(kNP);
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kMpnnMagic, 8) == 0 && fread(&count, 4, 1, f) == 1 &&
+              count == (uint32_t)kNP && fread(th.data(), sizeof(float), kNP, f) == (size_t)kNP;
+    char extra;
+    ok = ok && fread(&extra, 1, 1, f) == 0;   // nothing after the parameters
+    fclose(f);
+    if (!ok) { set_error("pfe_mpnn_load: %s is not a network file of %d parameters", path, kNP); return PFE_E_ARG; }
+    for (float v : th)
+        if (!std::isfinite(v)) { set_error("pfe_mpnn_load: non-finite parameter in %s", path); return PFE_E_ARG; }
+    return pfe_mpnn_create(th.data(), out);
 }
 
 void pfe_mpnn_destroy(pfe_mpnn* w) {

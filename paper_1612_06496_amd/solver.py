@@ -337,6 +337,19 @@ class Mpnn:
         p = np.ascontiguousarray(params, dtype=np.float32)
         L.check(L.lib.pfe_mpnn_set_params(self._h, p.ctypes.data), "pfe_mpnn_set_params")
 
+    def save(self, path: str) -> None:
+        """Write the parameters to a network file (pfe_mpnn_save)."""
+        L.check(L.lib.pfe_mpnn_save(self._h, str(path).encode()), "pfe_mpnn_save")
+
+    @classmethod
+    def load(cls, path: str) -> "Mpnn":
+        """A network from a file written by save (pfe_mpnn_load)."""
+        h = C.c_void_p()
+        L.check(L.lib.pfe_mpnn_load(str(path).encode(), C.byref(h)), "pfe_mpnn_load")
+        net = cls.__new__(cls)
+        net._h = h
+        return net
+
     def train_step(self, solver: Solver, samples, lr: float) -> float:
         """One Adam step (lr = 0: gradient only) on residual samples (n x k)."""
         x = _dev(samples, solver.dtype)

@@ -94,3 +94,31 @@ def test_argument_checks_of_later_entry_points_need_no_gpu():
     assert lib.pfe_live_allocations() == 0
     assert lib.pfe_set_allocator(dummy, None, None) == L.PFE_E_ARG
     assert lib.pfe_set_allocator(None, None, None) == L.PFE_OK
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpfe.so not built")
+def test_network_file_format_is_checked_on_the_host(tmp_path):
+    """pfe_mpnn_load rejects a missing file, a wrong magic, a wrong count, a
+    truncated or over-long file and non-finite values before taking device
+    memory (so without a GPU)."""
+    import ctypes as C
+    import struct
+    import numpy as np
+    from paper_1612_06496_amd import _lib as L
+    h = C.c_void_p()
+    n = L.PFE_MPNN_NPARAMS
+    good = np.zeros(n, dtype="<f4")
+    cases = {
+        "missing": None,
+        "magic": b"XXXXXXXX" + struct.pack("<I", n) + good.tobytes(),
+        "count": b"PFEMPNN1" + struct.pack("<I", n - 1) + good[:-1].tobytes(),
+        "short": b"PFEMPNN1" + struct.pack("<I", n) + good[:-3].tobytes(),
+        "long": b"PFEMPNN1" + struct.pack("<I", n) + good.tobytes() + b"\0",
+        "nan": b"PFEMPNN1" + struct.pack("<I", n) + np.full(n, np.nan, dtype="<f4").tobytes(),
+    }
+    for name, blob in cases.items():
+        path = tmp_path / f"{name}.bin"
+        if blob is not None:
+            path.write_bytes(blob)
+        assert L.lib.pfe_mpnn_load(str(path).encode(), C.byref(h)) == L.PFE_E_ARG, name
+        assert not h.value

@@ -194,3 +194,24 @@ def test_learned_pcg_on_edge_list_graph_matches_oracle():
     print(f"iterations gpu {it} oracle {it_o}; solution rel err {e:.2e}")
     assert info["rel_res_max"] <= 1e-6 and e <= 1e-4
     assert np.all(np.abs(it - it_o) <= 2)
+
+
+def test_network_file_round_trip(tmp_path):
+    """A network written by Mpnn.save and read by Mpnn.load has the same
+    parameters (bitwise) and gives the same factor on a system."""
+    from paper_1612_06496_amd import Mpnn, Solver
+    from gpu_helpers import gpu_graph
+    banner("network file round trip")
+    th = np.random.default_rng(4).normal(0.0, 0.3, size=Mpnn.NPARAMS).astype(np.float32)
+    net = Mpnn(th)
+    path = tmp_path / "net.bin"
+    net.save(path)
+    net2 = Mpnn.load(path)
+    assert np.array_equal(net2.params, th)
+    wl = synth.make_workload("voronoi48x40_r2", 0)
+    S = Solver(gpu_graph(wl), wl.y0, lam=20.0, r=1.0, n_inner=2, persistent=False)
+    S.set_learned(net)
+    f1 = [t.cpu().numpy() for t in S.get_factor()]
+    S.set_learned(net2)
+    f2 = [t.cpu().numpy() for t in S.get_factor()]
+    assert all(np.array_equal(a, b) for a, b in zip(f1, f2))
