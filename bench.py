@@ -285,6 +285,30 @@ def cpu_baseline(wls, lam, r, n_steps=2, max_images=2):
                       f"(factorisation {t_fact:.2f} s once, not in the rate), 1 thread"}
 
 
+def cpu_cg_per_solve(names=("voronoi481x321_8nbr", "voronoi1024_r2")):
+    """The oracle's own FP64 Jacobi-PCG (the GPU's algorithm) on the host: one
+    solve to 1e-6 of each image's first inner step (rhs = r/2 D Y0, x0 = Y0,
+    Y0 D-orthonormalised, lambda = r = the shrink-active scale), one thread."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+    import synth
+    out = {}
+    with threadpool_limits(limits=1):
+        for name in names:
+            wl = synth.make_workload(name, 0)
+            g = O.build_grid_graph(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
+            Y = O.orthonormalize_init(g, wl.y0)
+            c = O.shrink_active_scale(g, Y)
+            A = O.system_matrix(g, c, c).tocsr()
+            rhs = 0.5 * c * g.D[:, None] * Y
+            t0 = time.perf_counter()
+            _, it, _ = O.pcg(A, rhs, Y, 1.0 / A.diagonal(), 1e-6, 5000)
+            out[name] = {"s_per_solve": round(time.perf_counter() - t0, 3), "iterations_max": int(it.max()),
+                         "d": wl.d}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -451,6 +475,8 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wls, c, c)
         line["cpu_baseline"]["value"] = round(line["cpu_baseline"]["value"], 4)
+        if default:
+            line["cpu_baseline"]["cg_per_solve"] = cpu_cg_per_solve()
         progress("CPU baseline (oracle) done")
     print(json.dumps(line), flush=True)
 
