@@ -2,6 +2,8 @@
 exactly Jacobi, G^T G is SPD for any weights, autograd gradients agree with
 central finite differences, bf16 emulation stays within its rounding, and
 training lowers both the loss and the PCG iteration count on held-out data."""
+import math
+
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -136,3 +138,134 @@ def test_adam_matches_its_definition_on_a_quadratic():
     for t in range(1, 3001):
         x, m, v = LN.adam_step(x, x - a, m, v, t, 1e-2)
     assert np.abs(x - a).max() < 1e-3
+
+
+# --- the network and its loss against a plain, loop-by-loop reading of the
+# definitions in the module docstring (dense matrices, no index scatter) ------
+
+def _tiny_five(seed=3):
+    """5 vertices, 7 edges with uneven weights (so rows differ in degree)."""
+    rng = np.random.default_rng(seed)
+    pairs = [(0, 1), (0, 3), (1, 2), (1, 4), (2, 3), (2, 4), (3, 4)]
+    ei = np.array([p[0] for p in pairs])
+    ej = np.array([p[1] for p in pairs])
+    w = rng.uniform(0.3, 1.0, size=len(pairs))
+    return O.Graph(5, ei, ej, w)
+
+
+def _loop_reference(theta, g, lam, r, slip=None):
+    """Gt (dense, lower triangular) and At (dense, unit diagonal) computed entry
+    by entry.  A is written from Eq. (13) entrywise: A_ij = -lam/2 w_ij^2 for an
+    edge, A_ii = lam/2 sum_j w_ij^2 + r/2 sum_j w_ij.  `slip` plants one of the
+    plausible mistakes the oracle must not make, to show this reference tells
+    them apart."""
+    n = g.n
+    W = np.zeros((n, n))
+    for i, j, w in zip(g.ei, g.ej, g.w):
+        W[i, j] = W[j, i] = w
+    A = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            if i != j and W[i, j] > 0:
+                A[i, j] = -0.5 * lam * W[i, j] ** 2
+        A[i, i] = 0.5 * lam * sum(W[i, j] ** 2 for j in range(n)) + 0.5 * r * sum(W[i, :])
+    At = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            At[i, j] = A[i, j] / math.sqrt(A[i, i] * A[j, j])
+    nb = [[j for j in range(n) if j != i and W[i, j] > 0] for i in range(n)]
+    degmax = max(len(v) for v in nb)
+    p = LN.unpack(np.asarray(theta, dtype=np.float64))
+    x = [np.array([1.0, sum(abs(At[i, j]) for j in nb[i]), max(abs(At[i, j]) for j in nb[i]),
+                   len(nb[i]) / degmax]) for i in range(n)]
+    sgn = 1.0 if slip == "agg_sign" else -1.0
+
+    def layer(h, Ws, Wm, b):
+        out = []
+        for i in range(n):
+            agg = sum(sgn * At[i, j] * h[j] for j in nb[i])
+            pre = [sum(Ws[k, f] * h[i][f] for f in range(len(h[i])))
+                   + sum(Wm[k, f] * agg[f] for f in range(len(h[i]))) + b[k]
+                   for k in range(LN.HIDDEN)]
+            out.append(np.array([max(0.0, v) for v in pre]))
+        return out
+
+    h1 = layer(x, p["W1s"], p["W1m"], p["b1"])
+    h2 = layer(h1, p["W2s"], p["W2m"], p["b2"])
+    U = [float(np.dot(p["u"], h)) for h in h2]
+    V = [float(np.dot(p["v"], h)) for h in h2]
+    Z = [float(np.dot(p["q"], h)) + p["bd"][0] for h in h2]
+    Gt = np.zeros((n, n))
+    for i in range(n):
+        for j in nb[i]:
+            if j < i:
+                a, b = (j, i) if slip == "uv_swap" else (i, j)
+                Gt[i, j] = At[i, j] * (U[a] + V[b] + p["c"][0])
+        Gt[i, i] = math.log1p(math.exp(Z[i]))
+    return Gt, At
+
+
+def _loop_loss(Gt, At, rho, slip=None):
+    tot = 0.0
+    M = Gt @ Gt.T if slip == "gt_order" else Gt.T @ Gt
+    for k in range(rho.shape[1]):
+        e = At @ (M @ rho[:, k]) - rho[:, k]
+        tot += float(e @ e)
+    return tot / rho.shape[1]
+
+
+def _active_params(seed):
+    """Random weights with positive biases so most hidden units are active
+    (a relu that is zero everywhere would hide a mistake behind it)."""
+    th = random_params(seed)
+    p = LN.unpack(th)
+    p["b1"][...] = np.abs(p["b1"]) + 0.5
+    p["b2"][...] = np.abs(p["b2"]) + 0.5
+    return th
+
+
+def test_factor_matches_loop_reading_of_its_definition():
+    g = _tiny_five()
+    lam, r = 3.0, 1.0
+    S = LN.ScaledSystem(g, lam, r)
+    for seed in (0, 1, 2):
+        th = _active_params(seed)
+        Gt_ref, At_ref = _loop_reference(th, g, lam, r)
+        # the scaled system itself
+        assert np.abs(S.At.toarray() - At_ref).max() <= 1e-14
+        gv, dg = LN.factor(th, S, bf16=False)
+        Gt = LN.factor_matrix(gv, dg, S).toarray()
+        err = np.abs(Gt - Gt_ref).max() / np.abs(Gt_ref).max()
+        print(f"seed {seed}: factor vs loop reference, max rel err {err:.1e}")
+        assert err <= 1e-13
+        # both slots of an edge carry the edge's lower entry Gt_{max(i,j), min(i,j)}
+        gvn = gv.numpy()
+        for s, (i, j) in enumerate(zip(S.si, S.sj)):
+            assert gvn[s] == pytest.approx(Gt_ref[max(i, j), min(i, j)], rel=1e-13, abs=1e-300)
+        # the mistakes named below change the factor by far more than the bound
+        for slip in ("uv_swap", "agg_sign"):
+            Gs, _ = _loop_reference(th, g, lam, r, slip=slip)
+            assert np.abs(Gs - Gt_ref).max() / np.abs(Gt_ref).max() > 1e-3, slip
+
+
+def test_loss_matches_dense_reading_and_the_pcg_preconditioner():
+    g = _tiny_five(seed=5)
+    lam, r = 4.0, 1.0
+    S = LN.ScaledSystem(g, lam, r)
+    rho = np.random.default_rng(9).normal(size=(g.n, 3))
+    rho /= np.linalg.norm(rho, axis=0)
+    for seed in (3, 4):
+        th = _active_params(seed)
+        Gt_ref, At_ref = _loop_reference(th, g, lam, r)
+        L_ref = _loop_loss(Gt_ref, At_ref, rho)
+        L = float(LN.loss(th, S, rho, bf16=False))
+        print(f"seed {seed}: loss {L:.15e} loop reference {L_ref:.15e}")
+        assert abs(L - L_ref) <= 1e-13 * L_ref
+        assert abs(_loop_loss(Gt_ref, At_ref, rho, slip="gt_order") - L_ref) > 1e-3 * L_ref
+        # the same loss through the preconditioner the PCG applies:
+        # z = D_A^{-1/2} Gt^T Gt D_A^{-1/2} r with r = D_A^{1/2} rho gives
+        # At Gt^T Gt rho = D_A^{-1/2} A z
+        gv, dg = LN.factor(th, S, bf16=False)
+        z = LN.apply_preconditioner(gv, dg, S, np.sqrt(S.dA)[:, None] * rho)
+        e = (S.A @ z) / np.sqrt(S.dA)[:, None] - rho
+        assert abs((e ** 2).sum() / rho.shape[1] - L_ref) <= 1e-13 * L_ref

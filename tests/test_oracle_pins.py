@@ -475,3 +475,27 @@ def test_kmeans_agreement_is_one_for_identical_embeddings():
     # label permutation invariance: relabelled but same partition
     frac2, _ = O.kmeans_agreement(Y, Y[:, ::-1].copy(), 3)
     assert frac2 == 1.0
+
+
+# --- objective: Eq. (5)'s l1 term, once per undirected edge ------------------
+
+def test_objective_hand_computed_once_per_edge():
+    """4 vertices, 4 edges, values chosen so every term is exact in binary:
+      (0,1) w=0.5 : |0-2| + |1-1|  = 2 -> 1.0
+      (0,2) w=0.25: |0-1| + |1+1|  = 3 -> 0.75
+      (1,3) w=1   : |2-2| + |1-3|  = 2 -> 2.0
+      (2,3) w=2   : |1-2| + |-1-3| = 5 -> 10.0
+    ||M Y||_1 = 13.75 (each undirected edge once, Eq. 5); Eq. (1)'s sum over
+    ordered pairs (i, j) counts every edge from both ends: 27.5."""
+    g = O.Graph(4, np.array([0, 0, 1, 2]), np.array([1, 2, 3, 3]),
+                np.array([0.5, 0.25, 1.0, 2.0]))
+    Y = np.array([[0.0, 1.0], [2.0, 1.0], [1.0, -1.0], [2.0, 3.0]])
+    assert O.objective(g, Y) == 13.75
+    # Eq. (1): sum over all ordered pairs with the symmetric W
+    Wd = g.adjacency().toarray()
+    eq1 = sum(Wd[i, j] * np.abs(Y[i] - Y[j]).sum() for i in range(4) for j in range(4))
+    assert eq1 == 27.5
+    assert O.objective(g, Y) == 0.5 * eq1
+    # a constant shift of Y and a sign flip of a column leave it unchanged
+    assert O.objective(g, Y + 3.0) == 13.75
+    assert O.objective(g, Y * np.array([1.0, -1.0])) == 13.75
