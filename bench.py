@@ -160,6 +160,9 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
         S.set_penalties(lam, r)
         losses.append(net.train_step(S, R, lr))
     t_train = time.perf_counter() - t_start
+    for G_, S_ in keep:
+        S_.close()
+        G_.close()
     del keep, samples
     progress(f"learned leg: {steps} training steps in {t_train:.1f} s")
 
@@ -205,7 +208,7 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
             if factor_ms is not None:
                 res[pre]["factor_ms"] = factor_ms
                 res[pre]["ms_per_solve_amortised"] = round(res[pre]["ms_per_solve"] + factor_ms / max(1, info["solves"]), 3)
-            del S
+            S.close()
         rows.append(res)
         progress(f"learned leg: lambda/r = {ratio} done")
     return {"workload": workload, "train_workload": train_workload or workload, "n": wl.n, "d": wl.d,
@@ -246,9 +249,39 @@ def d_sweep_leg(G, wl, dims=(5, 10, 15, 20, 25), steps=10):
         rows.append({"d": d, "outer_iters_per_s": round(steps / (ms / 1e3), 1), "ms_per_step": round(ms / steps, 4),
                      "pcg_iters_per_solve": round(info["cg_iters_total"] / max(1, info["solves"]), 2),
                      "launch": "persistent" if info["workgroups"] else ("strips" if info["flags"] & 2 else "multi")})
-        del S
+        S.close()
         progress(f"d-sweep: d = {d} done")
     return rows
+
+
+def split_activity(G, wl, S, Y0, c):
+    """Share of nonzero entries of the split variable d (edge differences the
+    shrink leaves active) in the first Split-Bregman iteration from the state
+    the timed SOC iterations ended in.  Measured in a second context that stores
+    d (keep_split), loaded with that state, so the timed kernels stay as timed."""
+    from paper_1612_06496_amd import Solver
+    S2 = Solver(G, Y0, lam=c, r=c, n_inner=wl.n_inner, tol=wl.tol, maxit=1000, keep_split=True, persistent=False)
+    for which in ("Y", "P", "B"):
+        S2.set(which, S.get(which))
+    S2.step("inner")
+    frac = S2.monitor()["split_nonzero"]
+    S2.close()
+    return frac
+
+
+def host_cpu():
+    """CPU model and logical CPU count of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
 def cpu_baseline(wls, lam, r, n_steps=2, max_images=2):
@@ -282,7 +315,8 @@ def cpu_baseline(wls, lam, r, n_steps=2, max_images=2):
             if len(wls) > 1 else "the whole image")
     return {"value": n_steps / (dt * scale), "unit": "outer iters/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_steps} SOC iterations x {sample[0].n_inner} inner on {what}; sparse LU solves "
-                      f"(factorisation {t_fact:.2f} s once, not in the rate), 1 thread"}
+                      f"(factorisation {t_fact:.2f} s once, not in the rate), 1 thread",
+            **host_cpu()}
 
 
 def cpu_cg_per_solve(names=("voronoi481x321_8nbr", "voronoi1024_r2")):
@@ -387,6 +421,7 @@ def main():
     info = S.stats(reset=True)          # CG iterations of the timed steps
     progress(f"{args.steps} timed SOC iterations: {ms:.1f} ms")
     mon = S.monitor()
+    mon["split_nonzero"] = split_activity(G, wl, S, Y0, c)
     ms_per_step = ms / args.steps
     value = args.steps / (ms / 1e3)
 
@@ -478,6 +513,9 @@ def main():
         if default:
             line["cpu_baseline"]["cg_per_solve"] = cpu_cg_per_solve()
         progress("CPU baseline (oracle) done")
+    # explicit teardown while the HIP runtime is up (contexts, networks, graphs)
+    from paper_1612_06496_amd import close_all
+    close_all()
     print(json.dumps(line), flush=True)
 
 

@@ -116,7 +116,11 @@ typedef struct {
  *   tol        PCG stop: ||r_c|| <= tol ||rhs_c|| for every column c
  *   maxit      PCG iteration cap per solve
  *   precond    PFE_JACOBI, or PFE_LEARNED / PFE_FSAI (both apply the context's sparse
- *              factor, set by pfe_set_learned or pfe_set_fsai; Gt = I until then)
+ *              factor, set by pfe_set_learned or pfe_set_fsai; Gt = I until then).
+ *              Jacobi-PCG stays the fallback of the factor preconditioners: a
+ *              solve whose factor PCG breaks down (PFE_E_NOT_SPD) or reaches maxit
+ *              (PFE_E_NOCONV) is redone with Jacobi from the same starting point,
+ *              counted in pfe_step_info.fallbacks
  *   ortho      PFE_POLAR (exact argmin, default) or PFE_CHOL (Cholesky QR)
  *   dtype      PFE_FP32 (vectors, SpMM, shrink in float; CG scalars and Gram
  *              in double) or PFE_FP64 (everything in double)
@@ -155,7 +159,9 @@ typedef struct {
     int32_t cg_iters_last;   /* iteration count of the last solve */
     double rel_res_max;      /* largest final ||r_c||/||rhs_c|| (recursive residual) */
     int32_t status;          /* worst pfe_status met (PFE_E_NOCONV, PFE_E_NOT_SPD, ...) */
-    int32_t fallbacks;       /* learned-preconditioner solves redone with Jacobi */
+    int32_t fallbacks;       /* factor-preconditioned (PFE_LEARNED / PFE_FSAI) solves redone
+                                with Jacobi-PCG from the same start after the factor PCG broke
+                                down or reached maxit (the redo's status is reported) */
     int32_t workgroups;      /* workgroups of the persistent launch (0: one launch per phase) */
     int32_t flags;           /* bit 0: persistent launch with the rows' slot data held in LDS;
                                 bit 1: one launch per phase on image strips */
@@ -282,8 +288,24 @@ typedef struct {
  * launch per phase on row chunks and (pixel grids) on image strips sized for
  * one or two waves of co-resident workgroups.  results (host, may be null when max_results is 0)
  * receives up to max_results measured shapes, *n_results their number.
- * Allocates a temporary copy of Y, P, B.  PFE_E_STATE inside a SOC iteration. */
+ * Allocates a temporary copy of Y, P, B.  Each candidate starts from the
+ * saved state with the solver flags cleared, so a shape that breaks down is
+ * skipped without affecting the others.  PFE_E_STATE inside a SOC iteration;
+ * PFE_E_HIP if a grid barrier timed out in some candidate (that candidate is
+ * skipped, the fastest of the others is still kept). */
 pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int max_results, int* n_results);
+
+/* Use a launch shape in the form pfe_autotune reports it: persistent, team,
+ * row_cache and second_weight for the persistent launch, strips (0: row chunks,
+ * 1 or 2: image strips sized for that many waves) for one launch per phase;
+ * the other fields are ignored.  For running a shape measured on another
+ * context of the same graph, or a chosen shape in tests.  Only the summation
+ * order of the FP64 reductions differs between shapes.  The persistent launch
+ * still applies only to Jacobi-PCG with warm starts.  PFE_E_ARG for a shape
+ * this context cannot run (persistent grid that does not fit, strips on a
+ * graph without a pixel layout, fields out of range); PFE_E_STATE inside a
+ * SOC iteration. */
+pfe_status pfe_set_launch_shape(pfe_ctx* c, const pfe_tune_result* shape);
 
 /* Statistics accumulated since the last reset (pfe_step / pfe_solve with a
  * non-null info reset them first).  reset != 0 clears them after reading.

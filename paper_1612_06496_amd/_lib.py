@@ -89,6 +89,7 @@ SIGNATURES = {
     "pfe_split_bregman": (_S, [_P, C.c_int, C.POINTER(pfe_step_info)]),
     "pfe_stats": (_S, [_P, C.POINTER(pfe_step_info), C.c_int]),
     "pfe_autotune": (_S, [_P, C.c_int, C.POINTER(pfe_tune_result), C.c_int, C.POINTER(C.c_int)]),
+    "pfe_set_launch_shape": (_S, [_P, C.POINTER(pfe_tune_result)]),
     "pfe_get": (_S, [_P, C.c_int, _P]),
     "pfe_set": (_S, [_P, C.c_int, _P]),
     "pfe_get_inner_index": (_S, [_P, C.POINTER(C.c_int)]),

@@ -48,14 +48,14 @@ struct alignas(64) Scal {
     int status;             // worst status since the last reset (0 or PFE_E_*)
     int abort_flag;         // a grid barrier timed out
     int ortho_ok;           // the last Gram factorisation succeeded
-    int pad_;
+    int saved_status;       // status set aside while a factor-preconditioned solve runs
     // statistics since the last reset
     long long solves;
     long long iters_total;
     int iters_max;
     int iters_last;
     double relres_max;
-    int fallbacks;
+    int fallbacks;          // factor-preconditioned solves redone with Jacobi
     int pad2_;
 };
 

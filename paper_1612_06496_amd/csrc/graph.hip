@@ -336,9 +336,25 @@ __global__ void k_max_deg(int64_t n, const int* __restrict__ rowptr, int* __rest
 }
 
 // grid-stride 16-byte copy
-__global__ void __launch_bounds__(256) k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n16) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+// Plain copy for the bandwidth probe: each thread keeps kCopyUnroll 16-byte
+// loads in flight (issued together, then their stores), grid-stride over the
+// buffer, streaming (non-temporal) accesses.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kCopyUnroll = 4;
+constexpr int kCopyThreads = 256;
+
+__global__ void __launch_bounds__(kCopyThreads) k_stream_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                               size_t n16) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (kCopyUnroll - 1) * stride < n16; i += kCopyUnroll * stride) {
+        u32x4 v[kCopyUnroll];
+#pragma unroll
+        for (int k = 0; k < kCopyUnroll; ++k) v[k] = __builtin_nontemporal_load(src + i + k * stride);
+#pragma unroll
+        for (int k = 0; k < kCopyUnroll; ++k) __builtin_nontemporal_store(v[k], dst + i + k * stride);
+    }
+    for (; i < n16; i += stride) dst[i] = src[i];
 }
 
 static void free_graph_buffers(pfe_graph* g) {
@@ -772,8 +788,11 @@ pfe_status pfe_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t
     }
     const size_t n16 = bytes / 16;
     if (n16 == 0) return PFE_OK;
-    const unsigned blocks = (unsigned)std::min<size_t>((n16 + 255) / 256, 256 * 64);
-    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, stream, (const uint4*)src, (uint4*)dst, n16);
+    // at most 16 workgroups per CU, fewer when the buffer is small
+    const size_t per_block = (size_t)kCopyThreads * kCopyUnroll;
+    const unsigned blocks = (unsigned)std::min<size_t>((n16 + per_block - 1) / per_block, 256 * 16);
+    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(kCopyThreads), 0, stream, (const u32x4*)src, (u32x4*)dst,
+                       n16);
     PFE_CHECK_HIP(hipGetLastError());
     return PFE_OK;
 }

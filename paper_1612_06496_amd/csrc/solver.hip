@@ -265,6 +265,10 @@ __device__ __forceinline__ int seg_chunk(int nq, int d) {
 // independent loads in flight instead of waiting on each slot.
 // (GM: largest group, 8 in the one-phase kernels, 4 in the persistent kernel
 // whose registers are shared by every phase)
+// unroll factor of the plain slot loops (compiled width or generic CSR rows)
+template <int KC>
+constexpr int kSlotUnroll = KC > 0 ? 4 : 2;
+
 template <int KC, int GM>
 constexpr int slot_group() { return KC <= 0 ? 1 : (KC <= GM ? KC : GM); }
 
@@ -379,7 +383,7 @@ __device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, in
                 }
             } else if (mode == PH_EU) {
                 const T yi = a.Y[e];
-#pragma unroll(KC > 0 ? 4 : 2)
+#pragma unroll kSlotUnroll<KC>
                 for (int k = 0; k < cnt; ++k) {
                     const int s = s0 + k * st;
                     const int j = a.scol[s];
@@ -397,7 +401,7 @@ __device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, in
                     if (do_r0) accA = fma_t(mul_t(ww, ww), a.x[ej], accA);
                 }
             } else if (mode == PH_RHS) {
-#pragma unroll(KC > 0 ? 4 : 2)
+#pragma unroll kSlotUnroll<KC>
                 for (int k = 0; k < cnt; ++k) {
                     const int s = s0 + k * st;
                     const size_t es = (size_t)s * d + c;
@@ -421,7 +425,7 @@ __device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, in
                     for (int k = 0; k < G; ++k) accA = fma_t(mul_t(ww[k], ww[k]), xj[k], accA);
                 }
             } else if (do_r0) {
-#pragma unroll(KC > 0 ? 4 : 2)
+#pragma unroll kSlotUnroll<KC>
                 for (int k = 0; k < cnt; ++k) {
                     const int s = s0 + k * st;
                     const T ww = a.sw[s];
@@ -2291,6 +2295,32 @@ __global__ void k_stats_if_done(KA<T> a) {
     if (threadIdx.x == 0 && blockIdx.x == 0 && a.S->done && a.S->it == 0) solve_stats(a);
 }
 
+// Status bookkeeping of a factor-preconditioned solve, which is judged on its
+// own: the worst status met so far is set aside before it (save), cleared
+// again before a Jacobi redo (clear), and combined with the status of the
+// solve that stands afterwards (merge; a breakdown outranks maxit).
+__device__ __forceinline__ int worse_status(int a, int b) {
+    if (a == 0) return b;
+    if (b == 0) return a;
+    return (a == PFE_E_NOT_SPD || b == PFE_E_NOT_SPD) ? PFE_E_NOT_SPD : a;
+}
+__global__ void k_status_save(Scal* S) {
+    if (threadIdx.x == 0) { S->saved_status = S->status; S->status = 0; }
+}
+__global__ void k_status_clear(Scal* S) {
+    if (threadIdx.x == 0) S->status = 0;
+}
+// autotuner: every candidate launch shape is judged on its own run
+__global__ void k_tune_reset(Scal* S) {
+    if (threadIdx.x == 0) { S->status = 0; S->abort_flag = 0; S->ortho_ok = 1; }
+}
+__global__ void k_status_merge(Scal* S, int fallback) {
+    if (threadIdx.x == 0) {
+        S->status = worse_status(S->saved_status, S->status);
+        if (fallback) S->fallbacks += 1;
+    }
+}
+
 struct Plan {
     int l_begin;      // first inner index of the first SOC iteration
     int n_inner;      // inner iterations per SOC iteration
@@ -2411,7 +2441,7 @@ __global__ void __launch_bounds__(kBlock) k_spmm(KA<T> a, const T* __restrict__ 
         int s0, cnt, st;
         row_slots<KC>(a, i, s0, cnt, st);
         T acc = T(0);
-#pragma unroll(KC > 0 ? 4 : 2)
+#pragma unroll kSlotUnroll<KC>
         for (int k = 0; k < cnt; ++k) {
             const int s = s0 + k * st;
             const T ww = a.sw[s];
@@ -2856,6 +2886,7 @@ struct pfe_ctx {
     void* gdiag = nullptr;
     void* zl = nullptr;
     void* y1 = nullptr;
+    void* xbak = nullptr;      // start of a factor-preconditioned solve (Jacobi fallback)
     int have_factor = 0;
     double* part = nullptr;
     double* gpart = nullptr;
@@ -3370,9 +3401,38 @@ pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
     return PFE_OK;
 }
 
+// One PCG solve of Eq. 13, one launch per phase: the residual phase res_ph
+// (PH_E0 / PH_R0, r0 = rhs - A x), then the iterations.  With a factor
+// preconditioner (learned or FSAI) Jacobi-PCG stays the fallback: the solve's
+// starting x is kept, and when the factor PCG breaks down (PFE_E_NOT_SPD: a
+// non-positive or non-finite scalar) or reaches maxit (PFE_E_NOCONV), x is
+// restored and the same solve is redone with Jacobi from the same start;
+// fallbacks counts such solves, and the status reported is the redo's.
 template <typename T>
-pfe_status pcg_any_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
-    return (c->prm.precond != PFE_JACOBI) ? pcg_loop_learned_mk(c, a, as) : pcg_loop_mk(c, a, as);
+pfe_status pcg_solve_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as, int res_ph) {
+    if (c->prm.precond == PFE_JACOBI) {
+        PFE_TRY(launch_phase(c, as, res_ph, 0, 1));
+        return pcg_loop_mk(c, a, as);
+    }
+    const size_t bytes = (size_t)c->n * c->d * sizeof(T);
+    if (!c->xbak) PFE_CHECK_HIP(dev_alloc(&c->xbak, (size_t)c->n * c->d * 8));
+    PFE_CHECK_HIP(hipMemcpyAsync(c->xbak, a.x, bytes, hipMemcpyDeviceToDevice, c->stream));
+    hipLaunchKernelGGL(k_status_save, dim3(1), dim3(64), 0, c->stream, c->S);
+    PFE_TRY(launch_phase(c, as, res_ph, 0, 1));
+    PFE_TRY(pcg_loop_learned_mk(c, a, as));
+    int st = 0;
+    PFE_CHECK_HIP(hipMemcpyAsync(&st, &c->S->status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    PFE_CHECK_HIP(hipStreamSynchronize(c->stream));
+    const bool redo = (st == PFE_E_NOT_SPD || st == PFE_E_NOCONV);
+    if (redo) {
+        PFE_CHECK_HIP(hipMemcpyAsync(a.x, c->xbak, bytes, hipMemcpyDeviceToDevice, c->stream));
+        hipLaunchKernelGGL(k_status_clear, dim3(1), dim3(64), 0, c->stream, c->S);
+        PFE_TRY(launch_phase(c, as, res_ph, 0, 1));
+        PFE_TRY(pcg_loop_mk(c, a, as));
+    }
+    hipLaunchKernelGGL(k_status_merge, dim3(1), dim3(64), 0, c->stream, c->S, redo ? 1 : 0);
+    PFE_CHECK_HIP(hipGetLastError());
+    return PFE_OK;
 }
 
 // the strip partition is used in the one-launch-per-phase path when the graph
@@ -3405,8 +3465,7 @@ pfe_status inner_at(pfe_ctx* c, int l) {
     // cold start: the solve begins from Y = 0 (the right-hand side does not
     // depend on Y; the previous edge update has already consumed it)
     if (c->prm.cold_start) PFE_CHECK_HIP(hipMemsetAsync(c->Y, 0, (size_t)c->n * c->d * sizeof(T), c->stream));
-    PFE_TRY(launch_phase(c, as, (l == 0) ? PH_E0 : PH_R0, 0, 1));
-    PFE_TRY(pcg_any_mk(c, a, as));
+    PFE_TRY(pcg_solve_mk(c, a, as, (l == 0) ? PH_E0 : PH_R0));
     // edge update of this inner step and rhs of the next one (on strips when
     // the slot data are loaded one image row ahead, widths up to 8)
     KA<T> b = (as.geo && c->g->ell_K <= 8) ? as : a;
@@ -3538,7 +3597,7 @@ pfe_status set_diag(pfe_ctx* c) {
 void free_ctx(pfe_ctx* c) {
     void* bufs[] = {c->Y, c->P, c->B, c->bs, c->ds, c->rhs, c->p, c->rb[0], c->rb[1], c->wb[0], c->wb[1],
                     c->sb[0], c->sb[1], c->diagA, c->invdiag, c->sqrtD, c->isqrtD, c->isq, c->gval, c->gdiag,
-                    c->zl, c->y1, c->part, c->gpart,
+                    c->zl, c->y1, c->xbak, c->part, c->gpart,
                     c->Tm, c->colbuf, c->colint, c->S, c->bar, c->hist};
     for (void* p : bufs)
         if (p) (void)dev_free(p);
@@ -4032,16 +4091,23 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
     char* save = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     pfe_status st = PFE_OK;
+    // the state (Y, P, B) and the solver flags as they were before the call:
+    // a candidate that ends in a breakdown or a barrier time-out leaves no
+    // trace in the next candidate's run or in later calls
     auto restore = [&]() -> pfe_status {
         PFE_CHECK_HIP(hipMemcpyAsync(c->Y, save, nd, hipMemcpyDeviceToDevice, c->stream));
         PFE_CHECK_HIP(hipMemcpyAsync(c->P, save + nd, nd, hipMemcpyDeviceToDevice, c->stream));
         PFE_CHECK_HIP(hipMemcpyAsync(c->B, save + 2 * nd, nd, hipMemcpyDeviceToDevice, c->stream));
+        hipLaunchKernelGGL(k_tune_reset, dim3(1), dim3(64), 0, c->stream, c->S);
+        PFE_CHECK_HIP(hipGetLastError());
         c->inner = 0;
         return PFE_OK;
     };
+    int timeouts = 0;
     int best = -1, count = 0;
     double best_ms = 0.0;
     std::vector<pfe_tune_result> found;
+    Scal h_flags;
     do {
         if (dev_alloc((void**)&save, 3 * nd) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
             hipEventCreate(&e1) != hipSuccess) {
@@ -4071,6 +4137,7 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
                 if (c->pc.nblk == 0 || (sh.cache && c->cache_np == 0)) continue;
             }
             // one untimed SOC iteration (code loading, caches), then the timed ones
+            hipLaunchKernelGGL(k_tune_reset, dim3(1), dim3(64), 0, c->stream, c->S);
             st = f64 ? run_outer<double>(c, 1) : run_outer<float>(c, 1);
             if (st == PFE_OK) st = restore();
             if (st == PFE_OK && hipEventRecord(e0, c->stream) != hipSuccess) st = PFE_E_HIP;
@@ -4079,11 +4146,14 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
             if (st == PFE_OK && hipEventSynchronize(e1) != hipSuccess) st = PFE_E_HIP;
             float ms = 0.f;
             if (st == PFE_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = PFE_E_HIP;
+            if (st == PFE_OK && hipMemcpy(&h_flags, c->S, sizeof(Scal), hipMemcpyDeviceToHost) != hipSuccess)
+                st = PFE_E_HIP;
             if (st == PFE_OK) st = restore();
             if (st != PFE_OK) break;
-            Scal h;
-            if (hipMemcpy(&h, c->S, sizeof(Scal), hipMemcpyDeviceToHost) != hipSuccess) { st = PFE_E_HIP; break; }
-            if (h.abort_flag || (h.status != 0 && h.status != PFE_E_NOCONV)) continue;
+            // flags of the timed run (restore() above resets them after the copy)
+            if (hipStreamSynchronize(c->stream) != hipSuccess) { st = PFE_E_HIP; break; }
+            if (h_flags.abort_flag) ++timeouts;
+            if (h_flags.abort_flag || (h_flags.status != 0 && h_flags.status != PFE_E_NOCONV)) continue;
             pfe_tune_result r{};
             r.persistent = sh.persistent;
             r.team = sh.team;
@@ -4120,9 +4190,52 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (st == PFE_OK) st = reset_stats(c);
+    if (st == PFE_OK && timeouts > 0) {
+        // the shapes that ran normally were still measured and the fastest kept
+        set_error("pfe_autotune: a grid barrier timed out in %d candidate launch shape(s); they were skipped",
+                  timeouts);
+        st = PFE_E_HIP;
+    }
     for (size_t k = 0; k < found.size() && (int)k < max_results; ++k) results[k] = found[k];
     if (n_results) *n_results = (int)std::min<size_t>(found.size(), (size_t)max_results);
     return st;
+}
+
+pfe_status pfe_set_launch_shape(pfe_ctx* c, const pfe_tune_result* sh) {
+    if (!c || !sh) { set_error("pfe_set_launch_shape: null argument"); return PFE_E_ARG; }
+    if (c->inner != 0) { set_error("pfe_set_launch_shape: call between SOC iterations (inner index 0)"); return PFE_E_STATE; }
+    if (sh->team < 1 || sh->team > 64 || sh->strips < 0 || sh->strips > 2 || !(sh->second_weight > 0.0) ||
+        sh->second_weight > 1.0) {
+        set_error("pfe_set_launch_shape: team in [1, 64], strips in [0, 2], second_weight in (0, 1]");
+        return PFE_E_ARG;
+    }
+    if (sh->persistent && c->coop < kNumXcd) {
+        set_error("pfe_set_launch_shape: no persistent launch on this context");
+        return PFE_E_ARG;
+    }
+    if (!sh->persistent && sh->strips > 0 && c->strip_slots == 0) {
+        set_error("pfe_set_launch_shape: image strips need a pixel-grid graph with 4, 8 or 24 slots");
+        return PFE_E_ARG;
+    }
+    c->prm.persistent = sh->persistent ? 1 : 0;
+    if (sh->persistent) {
+        c->team = sh->team;
+        c->want_cache = sh->row_cache ? 1 : 0;
+        c->second_weight = c->per_cu == 2 ? sh->second_weight : 1.0;
+    } else {
+        c->want_strips = sh->strips;
+    }
+    PFE_TRY(setup_persistent(c));
+    PFE_TRY(setup_strips(c));
+    if (sh->persistent && c->pc.nblk == 0) {
+        set_error("pfe_set_launch_shape: the persistent partition does not fit this device");
+        return PFE_E_ARG;
+    }
+    if (!sh->persistent && sh->strips > 0 && c->ps.nblk == 0) {
+        set_error("pfe_set_launch_shape: no strip partition for this graph and d");
+        return PFE_E_ARG;
+    }
+    return PFE_OK;
 }
 
 pfe_status pfe_stats(pfe_ctx* c, pfe_step_info* out, int reset) {
@@ -4245,8 +4358,7 @@ pfe_status pfe_pcg(pfe_ctx* c, const void* RHS, void* X, int32_t* iters, pfe_ste
         KA<double> as = use_strips(c) ? make_args<double>(c, c->ps) : a;
         as.x = a.x;
         as.rhs = a.rhs;
-        PFE_TRY(launch_phase(c, as, PH_R0, 0, 1));
-        PFE_TRY(pcg_any_mk(c, a, as));
+        PFE_TRY(pcg_solve_mk(c, a, as, PH_R0));
     } else {
         KA<float> a = make_args<float>(c, c->pm);
         a.x = (float*)X;
@@ -4254,8 +4366,7 @@ pfe_status pfe_pcg(pfe_ctx* c, const void* RHS, void* X, int32_t* iters, pfe_ste
         KA<float> as = use_strips(c) ? make_args<float>(c, c->ps) : a;
         as.x = a.x;
         as.rhs = a.rhs;
-        PFE_TRY(launch_phase(c, as, PH_R0, 0, 1));
-        PFE_TRY(pcg_any_mk(c, a, as));
+        PFE_TRY(pcg_solve_mk(c, a, as, PH_R0));
     }
     if (iters) {
         // per column, the largest count over the segments of a batch

@@ -4,7 +4,10 @@ piecewise-flat-embedding iteration runs in the HIP library.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import sys
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -51,6 +54,29 @@ def kmeans(Y, C0, max_iter: int = 100, stream: Optional[torch.cuda.Stream] = Non
 
 _TORCH_ALLOC = None
 
+# Library objects still open.  Teardown is explicit: close() destroys an
+# object at once, close_all() (also run at interpreter exit, while the HIP
+# runtime is still up) destroys what is left, contexts and networks before the
+# graphs they use.  A destructor that runs during interpreter finalisation
+# makes no library call.
+_LIVE = weakref.WeakSet()
+
+
+def close_all() -> None:
+    """Destroy every solver, network and graph of the library still open."""
+    objs = list(_LIVE)
+    for kind in (Solver, Mpnn, Graph):
+        for o in objs:
+            if isinstance(o, kind):
+                o.close()
+
+
+atexit.register(close_all)
+
+
+def _finalizing() -> bool:
+    return sys.is_finalizing()
+
 
 def use_torch_allocator(enable: bool = True) -> None:
     """Route the library's device memory through PyTorch's caching allocator
@@ -60,6 +86,29 @@ def use_torch_allocator(enable: bool = True) -> None:
     if not enable:
         L.check(L.lib.pfe_set_allocator(None, None, None), "pfe_set_allocator")
         _TORCH_ALLOC = None
+
+# Library objects still open.  Teardown is explicit: close() destroys an
+# object at once, close_all() (also run at interpreter exit, while the HIP
+# runtime is still up) destroys what is left, contexts and networks before the
+# graphs they use.  A destructor that runs during interpreter finalisation
+# makes no library call.
+_LIVE = weakref.WeakSet()
+
+
+def close_all() -> None:
+    """Destroy every solver, network and graph of the library still open."""
+    objs = list(_LIVE)
+    for kind in (Solver, Mpnn, Graph):
+        for o in objs:
+            if isinstance(o, kind):
+                o.close()
+
+
+atexit.register(close_all)
+
+
+def _finalizing() -> bool:
+    return sys.is_finalizing()
         return
     alloc_t = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
     free_t = C.CFUNCTYPE(None, C.c_void_p, C.c_int, C.c_void_p)
@@ -90,6 +139,7 @@ class Graph:
     def __init__(self, handle: C.c_void_p, stream):
         self._h = handle
         self._stream = stream
+        _LIVE.add(self)
         n, e, nnz = C.c_int64(), C.c_int64(), C.c_int64()
         L.check(L.lib.pfe_graph_info(self._h, C.byref(n), C.byref(e), C.byref(nnz)), "pfe_graph_info")
         self.n, self.n_edges, self.nnz_A = n.value, e.value, nnz.value
@@ -147,8 +197,11 @@ class Graph:
         if self._h:
             L.lib.pfe_destroy_graph(self._h)
             self._h = None
+        _LIVE.discard(self)
 
     def __del__(self):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -177,6 +230,7 @@ class Solver:
         L.check(L.lib.pfe_init(graph._h, C.byref(self.params), y0.data_ptr(), _stream_handle(stream),
                                C.byref(h)), "pfe_init")
         self._h = h
+        _LIVE.add(self)
 
     # -- iteration -----------------------------------------------------------
     @staticmethod
@@ -222,6 +276,16 @@ class Solver:
         return [dict(persistent=r.persistent, team=r.team, row_cache=r.row_cache, strips=r.strips,
                      second_weight=r.second_weight, workgroups=r.workgroups, ms=r.ms, chosen=r.chosen)
                 for r in res[:n.value]]
+
+    def set_launch_shape(self, persistent: bool = False, strips: int = 0, team: int = 1, row_cache: bool = False,
+                         second_weight: float = 1.0) -> None:
+        """Run later iterations in the given launch shape (the fields of an
+        autotune() result): persistent with teams / row cache / second-workgroup
+        share, or one launch per phase on row chunks (strips = 0) or on image
+        strips sized for 1 or 2 waves."""
+        sh = L.pfe_tune_result(persistent=int(persistent), team=int(team), row_cache=int(row_cache),
+                               strips=int(strips), second_weight=float(second_weight))
+        L.check(L.lib.pfe_set_launch_shape(self._h, C.byref(sh)), "pfe_set_launch_shape")
 
     # -- state ---------------------------------------------------------------
     def get(self, which: str) -> torch.Tensor:
@@ -298,8 +362,11 @@ class Solver:
         if getattr(self, "_h", None):
             L.lib.pfe_destroy_ctx(self._h)
             self._h = None
+        _LIVE.discard(self)
 
     def __del__(self):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -320,6 +387,7 @@ class Mpnn:
             assert p.size == self.NPARAMS
             L.check(L.lib.pfe_mpnn_create(p.ctypes.data, C.byref(h)), "pfe_mpnn_create")
         self._h = h
+        _LIVE.add(self)
 
     @property
     def params(self) -> np.ndarray:
@@ -348,6 +416,7 @@ class Mpnn:
         L.check(L.lib.pfe_mpnn_load(str(path).encode(), C.byref(h)), "pfe_mpnn_load")
         net = cls.__new__(cls)
         net._h = h
+        _LIVE.add(net)
         return net
 
     def train_step(self, solver: Solver, samples, lr: float) -> float:
@@ -362,8 +431,11 @@ class Mpnn:
         if getattr(self, "_h", None):
             L.lib.pfe_mpnn_destroy(self._h)
             self._h = None
+        _LIVE.discard(self)
 
     def __del__(self):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:

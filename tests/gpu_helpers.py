@@ -22,6 +22,17 @@ def rel(a, b) -> float:
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
+def maxrel(a, b) -> float:
+    """Element-wise error: the largest |a - b| of each column over that
+    column's largest |b|, maximised over the columns (an error confined to a
+    few rows, e.g. one band of image strips, is not averaged away)."""
+    a = np.asarray(a, dtype=np.float64).reshape(len(a), -1)
+    b = np.asarray(b, dtype=np.float64).reshape(len(b), -1)
+    scale = np.abs(b).max(axis=0)
+    scale[scale == 0] = 1.0
+    return float((np.abs(a - b).max(axis=0) / scale).max())
+
+
 def oracle_graph(wl):
     if wl.kind == "grid":
         return O.build_grid_graph(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
