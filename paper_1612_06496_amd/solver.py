@@ -86,29 +86,6 @@ def use_torch_allocator(enable: bool = True) -> None:
     if not enable:
         L.check(L.lib.pfe_set_allocator(None, None, None), "pfe_set_allocator")
         _TORCH_ALLOC = None
-
-# Library objects still open.  Teardown is explicit: close() destroys an
-# object at once, close_all() (also run at interpreter exit, while the HIP
-# runtime is still up) destroys what is left, contexts and networks before the
-# graphs they use.  A destructor that runs during interpreter finalisation
-# makes no library call.
-_LIVE = weakref.WeakSet()
-
-
-def close_all() -> None:
-    """Destroy every solver, network and graph of the library still open."""
-    objs = list(_LIVE)
-    for kind in (Solver, Mpnn, Graph):
-        for o in objs:
-            if isinstance(o, kind):
-                o.close()
-
-
-atexit.register(close_all)
-
-
-def _finalizing() -> bool:
-    return sys.is_finalizing()
         return
     alloc_t = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
     free_t = C.CFUNCTYPE(None, C.c_void_p, C.c_int, C.c_void_p)

@@ -122,3 +122,12 @@ def test_network_file_format_is_checked_on_the_host(tmp_path):
             path.write_bytes(blob)
         assert L.lib.pfe_mpnn_load(str(path).encode(), C.byref(h)) == L.PFE_E_ARG, name
         assert not h.value
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpfe.so not built")
+def test_binding_module_imports():
+    """The Python binding loads without a GPU (its calls need one)."""
+    import importlib
+    mod = importlib.import_module("paper_1612_06496_amd.solver")
+    for name in ("Graph", "Solver", "Mpnn", "kmeans", "close_all"):
+        assert hasattr(mod, name)
