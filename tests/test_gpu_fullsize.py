@@ -54,14 +54,19 @@ def test_window1024_soc_iteration_on_strips_vs_oracle(window_case, waves):
     S = Solver(G, Y0.astype(np.float32), lam=c, r=c, n_inner=N_INNER, tol=1e-6, maxit=1000, init_ortho=False,
                persistent=False, graphs=True)
     S.set_launch_shape(persistent=False, strips=waves)
-    info = S.step("outer", info=True)
+    # the inner iterations one call each, so that b can be read before the
+    # P-update closes the SOC iteration (b restarts from zero after it)
+    S.step("inner")
+    info = S.step("inner", info=True)
     assert info["flags"] & 2, info
-    errs = {}
-    for name, ref in (("Y", Y1), ("P", P1), ("B", B1), ("b", b1)):
+    got_b = to_np(S.get("b"))
+    S.step("outer")
+    errs = {"b": (rel(got_b, b1), maxrel(got_b, b1))}
+    for name, ref in (("Y", Y1), ("P", P1), ("B", B1)):
         got = to_np(S.get(name))
         errs[name] = (rel(got, ref), maxrel(got, ref))
     print("errors (Frobenius, element-wise):", {k: f"{a:.2e}, {m:.2e}" for k, (a, m) in errs.items()},
-          f"CG iterations per solve {info['cg_iters_total'] / info['solves']:.2f}")
+          f"CG iterations in the second solve {info['cg_iters_total']}")
     for name in ("Y", "P"):
         assert errs[name][0] <= 2e-5 and errs[name][1] <= 1e-4, name
     # B = Z - P is a small difference of O(1) quantities; b is t - Shrink(t)
