@@ -62,15 +62,26 @@ def test_window1024_soc_iteration_on_strips_vs_oracle(window_case, waves):
     got_b = to_np(S.get("b"))
     S.step("outer")
     errs = {"b": (rel(got_b, b1), maxrel(got_b, b1))}
+    got = {}
     for name, ref in (("Y", Y1), ("P", P1), ("B", B1)):
-        got = to_np(S.get(name))
-        errs[name] = (rel(got, ref), maxrel(got, ref))
+        got[name] = to_np(S.get(name))
+        errs[name] = (rel(got[name], ref), maxrel(got[name], ref))
+    # b = clamp(t, -1/lambda, 1/lambda) with t = w (y_i - y_j) + b_old (Eqs. 9-10)
+    # and w <= 1: over the two inner iterations an error in Y moves b by at most
+    # 2 max|dY| per iteration, so max|db| <= 4 max|dY| (twice that as margin for
+    # the first solve's Y, which is not compared), plus FP32 rounding at the
+    # threshold 1/lambda
+    db = np.abs(got_b - b1).max()
+    dY = np.abs(got["Y"] - Y1).max()
+    bound_b = 8.0 * dY + 1e-6 / c
     print("errors (Frobenius, element-wise):", {k: f"{a:.2e}, {m:.2e}" for k, (a, m) in errs.items()},
-          f"CG iterations in the second solve {info['cg_iters_total']}")
+          f"max|db| {db:.2e} (bound from max|dY| {bound_b:.2e}); CG iterations in the second solve "
+          f"{info['cg_iters_total']}")
     for name in ("Y", "P"):
         assert errs[name][0] <= 2e-5 and errs[name][1] <= 1e-4, name
-    # B = Z - P is a small difference of O(1) quantities; b is t - Shrink(t)
-    assert errs["B"][0] <= 1e-3 and errs["b"][0] <= 1e-4 and errs["b"][1] <= 1e-3
+    # B = Z - P is a small difference of O(1) quantities
+    assert errs["B"][0] <= 1e-3
+    assert errs["b"][0] <= 1e-4 and db <= bound_b
     S.close()
     G.close()
 
