@@ -422,6 +422,22 @@ void pfe_destroy_ctx(pfe_ctx* c);
 pfe_status pfe_kmeans(const void* Y, int64_t n, int d, int dtype, const double* C0, int K, int max_iter,
                       int32_t* labels, double* centroids, int32_t* iters, hipStream_t stream);
 
+/* The same as pfe_kmeans, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): it calls no hipMalloc, hipFree or other allocating routine.  Its
+ * scratch (the change counters and the K x S x (d + 1) FP64 slice sums, S <= 64
+ * row slices) lives in a static device array of the library, 4,227,328 bytes on
+ * each GPU it runs on, held until the process ends; its device address is
+ * looked up on the first call on a device.  Every argument limit of pfe_kmeans
+ * applies (they keep the scratch within the array; a larger need would be
+ * rejected with PFE_E_ARG).  All calls on one GPU share that array and leave
+ * it holding the last call's values (each call clears what must start at
+ * zero): calls that overlap on one GPU, from several threads or streams, race
+ * and must be serialised by the caller.  Labels, centroids and iteration
+ * counts are identical to pfe_kmeans's. */
+pfe_status pfe_kmeans_noalloc(const void* Y, int64_t n, int d, int dtype, const double* C0, int K, int max_iter,
+                              int32_t* labels, double* centroids, int32_t* iters, hipStream_t stream);
+
 /* ---- device memory ------------------------------------------------------------
  * Graphs, contexts, networks and the temporaries of a call take device memory
  * from hipMalloc / hipFree unless the caller routes it through its own

@@ -114,6 +114,8 @@ SIGNATURES = {
     "pfe_set_allocator": (_S, [_P, _P, _P]),
     "pfe_live_allocations": (C.c_int64, []),
     "pfe_kmeans": (_S, [_P, C.c_int64, C.c_int, C.c_int, _P, C.c_int, C.c_int, _P, _P, C.POINTER(C.c_int32), _P]),
+    "pfe_kmeans_noalloc": (_S, [_P, C.c_int64, C.c_int, C.c_int, _P, C.c_int, C.c_int, _P, _P, C.POINTER(C.c_int32),
+                                _P]),
     "pfe_status_string": (C.c_char_p, [C.c_int]),
     "pfe_last_error": (C.c_char_p, []),
 }

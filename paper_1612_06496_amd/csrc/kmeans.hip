@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -120,6 +121,11 @@ __global__ void k_km_move(const double* __restrict__ part, int K, int d, int S, 
     if (cnt > 0.0) C[idx] = sum / cnt;
 }
 
+// start of a call: change count, converged flag and iteration count to zero
+__global__ void k_km_clear(unsigned* st) {
+    if (threadIdx.x < 3) st[threadIdx.x] = 0;
+}
+
 // before an iteration: clear the change count (unless converged)
 __global__ void k_km_begin(unsigned* st) {
     if (threadIdx.x == 0 && !st[1]) st[0] = 0;
@@ -179,24 +185,81 @@ pfe_status km_dispatch(const T* Y, int64_t n, int d, int K, int max_iter, int32_
     return km_run<T, 32>(Y, n, d, K, max_iter, labels, C, changed, part, S, iters, st);
 }
 
+bool km_args_ok(const void* Y, int64_t n, int d, int dtype, const double* C0, int K, int max_iter,
+                const int32_t* labels, const double* centroids, const char* who) {
+    if (!Y || !C0 || !labels || !centroids || n < 1 || n >= (int64_t)INT32_MAX || d < 1 || d > kMaxD || K < 1 ||
+        K > kKmMaxK || K * d > kKmMaxKD || max_iter < 1 || (dtype != PFE_FP32 && dtype != PFE_FP64)) {
+        set_error("%s: bad argument (1 <= d <= %d, 1 <= K <= %d, K d <= %d, max_iter >= 1)", who, kMaxD, kKmMaxK,
+                  kKmMaxKD);
+        return false;
+    }
+    return true;
+}
+
+// row slices of the centroid sums: about 4096 rows each, at most kKmMaxSlices
+constexpr int kKmMaxSlices = 64;
+inline int km_slices(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(kKmMaxSlices, n / 4096)); }
+
+// Lloyd iterations with the caller's scratch: st (3 unsigned: change count,
+// converged flag, iterations run) and part (K x S x (d + 1) doubles)
+pfe_status km_call(const void* Y, int64_t n, int d, int dtype, const double* C0, int K, int max_iter, int32_t* labels,
+                   double* centroids, int32_t* iters, unsigned* st, double* part, int S, hipStream_t stream) {
+    if (centroids != C0)
+        PFE_CHECK_HIP(hipMemcpyAsync(centroids, C0, sizeof(double) * (size_t)K * d, hipMemcpyDeviceToDevice, stream));
+    hipLaunchKernelGGL(k_km_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, -1, labels);
+    hipLaunchKernelGGL(k_km_clear, dim3(1), dim3(64), 0, stream, st);
+    PFE_CHECK_HIP(hipGetLastError());
+    int it = 0;
+    pfe_status s = (dtype == PFE_FP64)
+                       ? km_dispatch<double>((const double*)Y, n, d, K, max_iter, labels, centroids, st, part, S, &it,
+                                             stream)
+                       : km_dispatch<float>((const float*)Y, n, d, K, max_iter, labels, centroids, st, part, S, &it,
+                                            stream);
+    if (s == PFE_OK && iters) *iters = it;
+    return s;
+}
+
+// Scratch of the allocation-free entry point: the three counters (padded to
+// 256 bytes), then the slice sums of the largest call the argument checks
+// allow (K d <= kKmMaxKD and K <= kKmMaxK, so K (d + 1) <= kKmMaxKD + kKmMaxK).
+constexpr size_t kKmCounterBytes = 256;
+constexpr size_t kKmScratchBytes =
+    kKmCounterBytes + sizeof(double) * (size_t)(kKmMaxKD + kKmMaxK) * kKmMaxSlices;   // 4,227,328 bytes
+static __device__ __align__(256) unsigned char scratch[kKmScratchBytes];
+
+// device address of this GPU's copy of scratch, looked up once per device
+// (with that device current) and kept; the array's host-side name is never
+// passed to a kernel or a copy
+constexpr int kKmMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kKmMaxDevices] = {};
+
+pfe_status scratch_address(void** out) {
+    int dev = 0;
+    PFE_CHECK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kKmMaxDevices) {
+        set_error("pfe_kmeans_noalloc: device index %d above %d", dev, kKmMaxDevices - 1);
+        return PFE_E_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        PFE_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) { set_error("pfe_kmeans_noalloc: no device address for the scratch array"); return PFE_E_HIP; }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PFE_OK;
+}
+
 }  // namespace pfe
 
 using namespace pfe;
 
 extern "C" pfe_status pfe_kmeans(const void* Y, int64_t n, int d, int dtype, const double* C0, int K, int max_iter,
                                  int32_t* labels, double* centroids, int32_t* iters, hipStream_t stream) {
-    if (!Y || !C0 || !labels || !centroids || n < 1 || n >= (int64_t)INT32_MAX || d < 1 || d > kMaxD || K < 1 ||
-        K > kKmMaxK || K * d > kKmMaxKD || max_iter < 1 || (dtype != PFE_FP32 && dtype != PFE_FP64)) {
-        set_error("pfe_kmeans: bad argument (1 <= d <= %d, 1 <= K <= %d, K d <= %d, max_iter >= 1)", kMaxD, kKmMaxK,
-                  kKmMaxKD);
-        return PFE_E_ARG;
-    }
-    if (centroids != C0)
-        PFE_CHECK_HIP(hipMemcpyAsync(centroids, C0, sizeof(double) * (size_t)K * d, hipMemcpyDeviceToDevice, stream));
-    hipLaunchKernelGGL(k_km_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, -1, labels);
-    PFE_CHECK_HIP(hipGetLastError());
-    // row slices of the centroid sums: about 4096 rows each, at most 64
-    const int S = (int)std::max<int64_t>(1, std::min<int64_t>(64, n / 4096));
+    if (!km_args_ok(Y, n, d, dtype, C0, K, max_iter, labels, centroids, "pfe_kmeans")) return PFE_E_ARG;
+    const int S = km_slices(n);
     unsigned* changed = nullptr;   // device state: change count, converged flag, iterations run
     double* part = nullptr;        // K x S x (d + 1) slice sums
     PFE_CHECK_HIP(dev_alloc((void**)&changed, 3 * sizeof(unsigned)));
@@ -205,16 +268,29 @@ extern "C" pfe_status pfe_kmeans(const void* Y, int64_t n, int d, int dtype, con
         (void)dev_free(changed);
         return hip_fail(e, "device allocation (k-means)", __FILE__, __LINE__);
     }
-    PFE_CHECK_HIP(hipMemsetAsync(changed, 0, 3 * sizeof(unsigned), stream));
-    int it = 0;
-    pfe_status s = (dtype == PFE_FP64)
-                       ? km_dispatch<double>((const double*)Y, n, d, K, max_iter, labels, centroids, changed, part, S,
-                                             &it, stream)
-                       : km_dispatch<float>((const float*)Y, n, d, K, max_iter, labels, centroids, changed, part, S,
-                                            &it, stream);
+    pfe_status s = km_call(Y, n, d, dtype, C0, K, max_iter, labels, centroids, iters, changed, part, S, stream);
     (void)hipStreamSynchronize(stream);
     (void)dev_free(part);
     (void)dev_free(changed);
-    if (s == PFE_OK && iters) *iters = it;
+    return s;
+}
+
+extern "C" pfe_status pfe_kmeans_noalloc(const void* Y, int64_t n, int d, int dtype, const double* C0, int K,
+                                         int max_iter, int32_t* labels, double* centroids, int32_t* iters,
+                                         hipStream_t stream) {
+    if (!km_args_ok(Y, n, d, dtype, C0, K, max_iter, labels, centroids, "pfe_kmeans_noalloc")) return PFE_E_ARG;
+    const int S = km_slices(n);
+    const size_t need = kKmCounterBytes + sizeof(double) * (size_t)K * S * (d + 1);
+    if (need > kKmScratchBytes) {
+        set_error("pfe_kmeans_noalloc: needs %zu bytes of scratch, the static array holds %zu", need,
+                  kKmScratchBytes);
+        return PFE_E_ARG;
+    }
+    void* base = nullptr;
+    PFE_TRY_STATUS(scratch_address(&base));
+    unsigned* st = static_cast<unsigned*>(base);
+    double* part = reinterpret_cast<double*>(static_cast<unsigned char*>(base) + kKmCounterBytes);
+    pfe_status s = km_call(Y, n, d, dtype, C0, K, max_iter, labels, centroids, iters, st, part, S, stream);
+    (void)hipStreamSynchronize(stream);
     return s;
 }
