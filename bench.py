@@ -113,21 +113,60 @@ def load_graph(name, seed):
     return wl, Graph.grid(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
 
 
-def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0), captures=6, steps=300,
-                lr=3e-3, workload="voronoi1024_r2", train_workload=None, n_outer=2):
+def training_residuals(workload, seeds, ratios, solves_per_image, cols, rng):
+    """Residuals of the PFE solves themselves, the network's training data:
+    on each held-out image (seed), solves_per_image Jacobi-PCG inner solves
+    split evenly over the lambda/r of the sweep, each contributing `cols`
+    randomly chosen columns of its initial residual (rhs - A Y of the solve).
+    Returns the open solvers/graphs and groups (solver, lambda, r, n x m
+    residual columns) of one system each."""
+    import torch
+
+    from paper_1612_06496_amd import Solver
+    keep, groups = [], []
+    for seed in seeds:
+        wl, G = load_graph(workload, seed)
+        S = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=5000, persistent=False,
+                   graphs=True)
+        c = 1.0 / S.edge_quantile(0.99)
+        per_ratio = max(1, solves_per_image // len(ratios))
+        for ratio in ratios:
+            S.set_penalties(ratio * c, c)
+            S.inner_index = 0
+            cap = []
+            for _ in range(per_ratio):
+                R = S.get("resid")
+                pick = torch.as_tensor(rng.choice(wl.d, cols, replace=False), device="cuda")
+                cap.append(R[:, pick].clone())
+                S.step("inner", allow_noconv=True)
+                if S.inner_index == wl.n_inner:
+                    S.step("outer", allow_noconv=True)     # the P- and B-update closing the SOC iteration
+            groups.append((S, ratio * c, c, torch.cat(cap, dim=1)))
+        keep.append((G, S))
+    return keep, groups
+
+
+def learned_leg(train_seeds=(1000, 1001, 1002, 1003, 1004), ratios=(1.0, 10.0, 100.0, 1000.0),
+                solves_per_image=100, cols_per_solve=2, steps=600, batch_cols=16, lr=3e-3,
+                workload="voronoi1024_r2", train_workload=None, n_outer=2):
     """PCG iterations to 1e-6 with the learned preconditioner vs Jacobi, and
     vs FSAI (a classical sparse approximate inverse factor of the same form).
 
-    Training data: residuals of PFE inner solves on held-out images (training
-    seeds) at every lambda/r of the sweep.  Evaluation on the evaluation image
-    (seed 0): from the same start, one untimed SOC iteration, then n_outer
-    timed ones (n_outer x n_inner solves) with each preconditioner in its
-    fastest launch mode (Jacobi: the shape autotuned at the first ratio,
-    persistent or one launch per phase, on image strips for pixel grids;
-    learned and FSAI: one launch per phase with the PCG replayed from HIP
-    graphs); the network's factor inference and the FSAI factor are timed
-    separately (once per graph and penalties).  train_workload: the workload of the training images (default:
-    the evaluation workload; the network is size-independent)."""
+    Training data: 500 PFE inner solves on five held-out images (training
+    seeds, 100 solves each, 25 per lambda/r of the sweep), two columns of each
+    solve's initial residual.  A training step draws batch_cols columns of one
+    (image, lambda/r) system.  The held-out loss per lambda/r is measured on
+    the evaluation image's residuals before and after training, next to the
+    identity network's (Jacobi).  Evaluation on the evaluation image (seed 0):
+    from the same start, one untimed SOC iteration, then n_outer timed ones
+    (n_outer x n_inner solves) with each preconditioner in its autotuned launch
+    shape (tuned at the first ratio, kept for the others; Jacobi persistent or
+    one launch per phase, the factor preconditioners one launch per phase on
+    image strips or row chunks, with one or two passes per CG iteration; PCG
+    replayed from HIP graphs); the network's factor inference and the FSAI
+    factor are timed separately (once per graph and penalties).
+    train_workload: the workload of the training images (default: the
+    evaluation workload; the network is size-independent)."""
     import numpy as np
     import torch
 
@@ -135,41 +174,58 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
     from paper_1612_06496_amd import Graph, Mpnn, Solver
 
     t_start = time.perf_counter()
-    samples = []
-    keep = []
-    for seed in train_seeds:
-        wl, G = load_graph(train_workload or workload, seed)
-        S = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=3000, persistent=False,
-                   graphs=True)
-        c = 1.0 / S.edge_quantile(0.99)
-        for ratio in ratios:
-            S.set_penalties(ratio * c, c)
-            S.inner_index = 0
-            for _ in range(captures):
-                samples.append((S, ratio * c, c, S.get("resid")))
-                S.step("inner", allow_noconv=True)
-        keep.append((G, S))
     rng = np.random.default_rng(0)
+    keep, groups = training_residuals(train_workload or workload, train_seeds, ratios, solves_per_image,
+                                      cols_per_solve, rng)
+    t_data = time.perf_counter() - t_start
+    progress(f"learned leg: {len(train_seeds) * solves_per_image} training solves in {t_data:.1f} s")
     init = rng.normal(0.0, 0.1, size=Mpnn.NPARAMS).astype(np.float32)
     init[672:] = 0.0
     init[721] = np.log(np.e - 1.0)
     net = Mpnn(init)
+
+    # held-out residuals: the evaluation image's first inner solve per ratio
+    wl, G = load_graph(workload, 0)
+    Sh = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=5000, persistent=False)
+    c = 1.0 / Sh.edge_quantile(0.99)
+    held = []
+    for ratio in ratios:
+        Sh.set_penalties(ratio * c, c)
+        held.append((ratio, Sh.get("resid")))
+    ident = Mpnn(None)
+
+    def held_losses(network):
+        out = {}
+        for ratio, R in held:
+            Sh.set_penalties(ratio * c, c)
+            out[str(ratio)] = round(network.train_step(Sh, R, 0.0), 5)
+        return out
+
+    loss_before, loss_jacobi = held_losses(net), held_losses(ident)
+    t0 = time.perf_counter()
     losses = []
     for t in range(steps):
-        S, lam, r, R = samples[rng.integers(len(samples))]
+        S, lam, r, R = groups[rng.integers(len(groups))]
+        pick = torch.as_tensor(rng.choice(R.shape[1], batch_cols, replace=False), device="cuda")
         S.set_penalties(lam, r)
-        losses.append(net.train_step(S, R, lr))
-    t_train = time.perf_counter() - t_start
+        losses.append(net.train_step(S, R[:, pick], lr))
+    t_train = time.perf_counter() - t0
+    loss_after = held_losses(net)
+    ident.close()
+    Sh.close()
     for G_, S_ in keep:
         S_.close()
         G_.close()
-    del keep, samples
+    del keep, groups
     progress(f"learned leg: {steps} training steps in {t_train:.1f} s")
+    training = {"train_images": list(train_seeds), "train_solves": len(train_seeds) * solves_per_image,
+                "columns_per_solve": cols_per_solve, "train_steps": steps, "batch_columns": batch_cols,
+                "data_s": round(t_data, 1), "train_s": round(t_train, 1),
+                "held_out_loss": {"jacobi": loss_jacobi, "initial": loss_before, "trained": loss_after}}
 
-    wl, G = load_graph(workload, 0)
-    c = 1.0 / Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=1, persistent=False).edge_quantile(0.99)
     rows = []
-    jshape = None
+    jshape = None     # launch shapes autotuned at the first ratio, Jacobi and the factor path
+    fshape = None
     for ratio in ratios:
         res = {"lambda_over_r": ratio}
         # FSAI is built for pixel grids (stencil slot layout) only
@@ -187,10 +243,17 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
                     S.set_fsai()
                 torch.cuda.synchronize()
                 factor_ms = round((time.perf_counter() - t0) * 1e3, 2)
+                if fshape is None:
+                    shape = fshape = [t for t in S.autotune(trials=1) if t["chosen"]][0]
+                else:
+                    shape = fshape
+                    S.set_launch_shape(persistent=False, strips=shape["strips"], one_pass=bool(shape["one_pass"]))
             elif jshape is None:
                 shape = jshape = [t for t in S.autotune(trials=1) if t["chosen"]][0]
             else:
-                shape = jshape   # persistent or not as autotuned at the first ratio (other knobs default)
+                shape = jshape
+                S.set_launch_shape(persistent=bool(shape["persistent"]), strips=shape["strips"], team=shape["team"],
+                                   row_cache=bool(shape["row_cache"]), second_weight=shape["second_weight"])
             S.solve(1, allow_noconv=True)
             S.stats(reset=True)
             torch.cuda.synchronize()
@@ -204,17 +267,18 @@ def learned_leg(train_seeds=(1000, 1001, 1002), ratios=(1.0, 10.0, 100.0, 1000.0
                         "rel_res_max": float(f"{info['rel_res_max']:.3g}"), "status": info["status"]}
             if shape is not None:
                 res[pre]["launch"] = ("persistent" if shape["persistent"] else
-                                      "strips" if shape["strips"] else "one launch per phase")
+                                      (f"strips ({shape['strips']} wave(s)"
+                                       + (", one pass per iteration)" if shape.get("one_pass") else ")"))
+                                      if shape["strips"] else "one launch per phase")
             if factor_ms is not None:
                 res[pre]["factor_ms"] = factor_ms
                 res[pre]["ms_per_solve_amortised"] = round(res[pre]["ms_per_solve"] + factor_ms / max(1, info["solves"]), 3)
             S.close()
         rows.append(res)
         progress(f"learned leg: lambda/r = {ratio} done")
+    net.close()
     return {"workload": workload, "train_workload": train_workload or workload, "n": wl.n, "d": wl.d,
-            "train_images": list(train_seeds), "train_steps": steps,
-            "train_samples": len(train_seeds) * len(ratios) * captures, "loss_first": round(losses[0], 4),
-            "loss_last10": round(float(np.mean(losses[-10:])), 4), "train_s": round(t_train, 1),
+            "training": training,
             "run": f"{n_outer} SOC iterations x {wl.n_inner} inner solves per preconditioner and lambda/r",
             "sweep": rows}
 

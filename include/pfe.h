@@ -277,6 +277,10 @@ typedef struct {
                                 co-resident workgroups (0: row chunks) */
     double second_weight;    /* persistent, teams of 1: rows of the second workgroup placed on each CU
                                 relative to the first (1: equal) */
+    int32_t one_pass;        /* factor preconditioners (learned, FSAI) on image strips: 1 = one pass
+                                per CG iteration (Chronopoulos-Gear form, M^{-1} r and A M^{-1} r
+                                through three LDS rings over a three-radius halo), 0 = two passes
+                                (A p, then the factor apply with the x, r update) */
 } pfe_tune_result;
 
 /* Autotune the launch shape on this context's graph: from the current state
@@ -286,7 +290,8 @@ typedef struct {
  * or 1, each with and without the LDS row cache (when the rows fit), teams of 1
  * also with second_weight 0.9, 0.85 and 0.8, and one
  * launch per phase on row chunks and (pixel grids) on image strips sized for
- * one or two waves of co-resident workgroups.  results (host, may be null when max_results is 0)
+ * one or two waves of co-resident workgroups (with a factor preconditioner,
+ * strips with one and with two passes per CG iteration).  results (host, may be null when max_results is 0)
  * receives up to max_results measured shapes, *n_results their number.
  * Allocates a temporary copy of Y, P, B.  Each candidate starts from the
  * saved state with the solver flags cleared, so a shape that breaks down is

@@ -54,7 +54,11 @@ enum Phase : int {
     PH_LA = 9,      // p = z + beta p, q = A p, p.q
     PH_LC = 11,     // x += alpha p, r -= alpha q, y1 = Gt D_A^{-1/2} r
     PH_LD = 12,     // z = D_A^{-1/2} Gt^T y1, r.z, r.r
-    PH_LCD = 13     // LC and LD fused (strips with a two-radius halo)
+    PH_LCD = 13,    // LC and LD fused (strips with a two-radius halo)
+    // factor-preconditioned CG in Chronopoulos-Gear form, one pass per iteration
+    // (strips with a three-radius halo)
+    PH_FW0 = 14,    // u0 = M^{-1} r0, w0 = A u0, gamma0 = r0.u0, delta0 = w0.u0
+    PH_FIT = 15     // one iteration: p, s, x, r, u = M^{-1} r, w = A u and their dots
 };
 
 // per (segment, column) CG state, struct of arrays of length nseg * d
@@ -1327,6 +1331,315 @@ __device__ __forceinline__ void st_ld(const KA<T>& a, int lb, double* sh, int in
     block_partials<2>(acc2, sh, d, kBlock / d, a.part, a.nblk, lb);
 }
 
+// Factor-preconditioned CG in Chronopoulos-Gear form, one pass per
+// iteration over a strip whose ring rows span three stencil radii on each
+// side.  With M^{-1} = D_A^{-1/2} Gt^T Gt D_A^{-1/2}, iteration i updates
+//   p = u + beta p, s = w + beta s, x += alpha p, r' = r - alpha s,
+// forms u' = M^{-1} r' and w' = A u', and the partials of r'.u', w'.u', r'.r'
+// (the same scalars and finaliser as the Jacobi iteration).  Per image row Y
+// of the walk: publish D_A^{-1/2} r' of row Y (ring A), barrier, y1 = Gt
+// D_A^{-1/2} r' of row Y over the lower neighbours (ring B), barrier,
+// u' = D_A^{-1/2} Gt^T y1 of row Y - rho over the upper neighbours (ring C),
+// barrier, then the owned pixels of row Y - 2 rho: w' = A u' from ring C and
+// the vector updates.  r', y1 and u' of the halo pixels are formed from the
+// neighbours' stored r, w, s with the arithmetic their owners use, so every
+// value is the one the owner stores.  mode 0 (before the first iteration):
+// r' = r0, u0 = M^{-1} r0, w0 = A u0 and the partials of r0.u0, w0.u0 (the
+// w0-phase finaliser); nothing else is written.
+template <int KC, typename T, int CPL>
+struct FcgRings {
+    static constexpr int rho = Sten<KC>::rho;
+    static constexpr int na = rho + 1, nb = rho + 1, nc = 2 * rho + 1;
+    static constexpr int rows = na + nb + nc;
+    static constexpr int row_len = kBlock * CPL;   // elements of one ring row
+    // LDS doubles: the three rings, or the partial sums and the finaliser's
+    // scratch after the walk (the size the other phases use)
+    static constexpr int ring_doubles = rows * row_len * (int)sizeof(T) / 8;
+    static constexpr int doubles = ring_doubles > kSmemDoubles ? ring_doubles : kSmemDoubles;
+};
+
+// CPL consecutive values of a lane (CPL columns of one pixel), loaded and
+// stored as one vector access
+template <typename T, int CPL>
+struct Lane { T v[CPL]; };
+template <typename T, int CPL>
+__device__ __forceinline__ Lane<T, CPL> ld_lane(const T* p) {
+    Lane<T, CPL> o;
+    if constexpr (CPL == 2) {
+        typedef T V2 __attribute__((ext_vector_type(2)));
+        const V2 x = *reinterpret_cast<const V2*>(p);
+        o.v[0] = x[0];
+        o.v[1] = x[1];
+    } else {
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) o.v[j] = p[j];
+    }
+    return o;
+}
+template <typename T, int CPL>
+__device__ __forceinline__ void st_lane(T* p, const Lane<T, CPL>& o) {
+    if constexpr (CPL == 2) {
+        typedef T V2 __attribute__((ext_vector_type(2)));
+        V2 x;
+        x[0] = o.v[0];
+        x[1] = o.v[1];
+        *reinterpret_cast<V2*>(p) = x;
+    } else {
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) p[j] = o.v[j];
+    }
+}
+
+// per-thread FP64 accumulators of CPL columns -> one partial per (quantity,
+// column) per workgroup; lane t holds columns (t mod (d / CPL)) CPL + j of
+// pixel t / (d / CPL); the sums over the pixels run in pixel order
+template <int NQ, int CPL>
+__device__ __forceinline__ void block_partials_cpl(const double (&acc)[NQ][CPL], double* sh, int d, double* part,
+                                                   int nblk, int lb) {
+    const int t = threadIdx.x;
+    const int B = blockDim.x;
+    const int dl = d / CPL;
+    const int npx = B / dl;                  // pixels per workgroup row
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) sh[q * B * CPL + t * CPL + j] = (t < npx * dl) ? acc[q][j] : 0.0;
+    __syncthreads();
+    if (t < NQ * d) {
+        const int q = t / d, c = t - q * d;
+        double s = 0.0;
+        for (int k = 0; k < npx; ++k) s += sh[q * B * CPL + k * d + c];
+        part[((size_t)q * nblk + lb) * d + c] = s;
+    }
+    __syncthreads();
+}
+
+template <int KC, int CPL, typename T>
+__device__ __forceinline__ void st_fcg(const KA<T>& a, int lb, double* sh, int mode) {
+    using S = Sten<KC>;
+    using FR = FcgRings<KC, T, CPL>;
+    using L = Lane<T, CPL>;
+    constexpr int rho = S::rho, H = KC / 2, RL = FR::row_len;
+    const StripGeo g = strip_geo(a.geo, lb);
+    const int d = a.d, t = threadIdx.x, dl = d / CPL;
+    const int qx = t / dl, c0 = (t - qx * dl) * CPL;   // pixel column of the lane, its first column
+    const int lt = qx * d + c0;                        // the lane's first element in a ring row
+    const int px = g.x0 - 3 * rho + qx;
+    const bool loader = qx < g.len + 6 * rho;
+    const bool in_image = loader && px >= 0 && px < g.W;
+    const bool blane = in_image && qx >= rho && qx < g.len + 5 * rho;        // forms y1
+    const bool clane = in_image && qx >= 2 * rho && qx < g.len + 4 * rho;    // forms u'
+    const bool owner = qx >= 3 * rho && qx < g.len + 3 * rho;
+    const bool iter = mode != 0;
+    const int it = iter ? ld_flag(&a.S->it) : 0;
+    const bool first = (it == 0);
+    const int cur = it & 1, nxt = cur ^ 1;
+    const T* r = a.rb[cur];
+    const T* w = a.wb[cur];
+    const T* sp = a.sb[cur];
+    T* rn = a.rb[nxt];
+    T* wn = iter ? a.wb[nxt] : a.wb[0];
+    T* sn = a.sb[nxt];
+    const int ci = a.blk_seg[lb] * d + c0;
+    T alpha[CPL], beta[CPL];
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        alpha[j] = iter ? (T)a.cs.alpha[ci + j] : T(0);
+        beta[j] = iter ? (T)a.cs.beta[ci + j] : T(0);
+    }
+    T* ringA = reinterpret_cast<T*>(sh);             // D_A^{-1/2} r'
+    T* ringB = ringA + FR::na * RL;                  // y1
+    T* ringC = ringB + FR::nb * RL;                  // u'
+    auto sa = [](int y) { return (y + 8 * FR::na) % FR::na; };
+    auto sb_ = [](int y) { return (y + 8 * FR::nb) % FR::nb; };
+    auto sc = [](int y) { return (y + 8 * FR::nc) % FR::nc; };
+    struct Raw { L r, w, sp; T isq; };
+    struct MidB { T gd, gv[H]; };
+    struct MidC { T gd, isq, gv[KC - H]; };
+    struct Own { Raw v; L p, x, u; T dA, ww[KC]; };
+    const int yA0 = max(0, g.y0 - 2 * rho), yA1 = min(g.H, g.y1 + 2 * rho);   // rows of r' read
+    auto ldr = [&](int y) {
+        Raw v{};
+        if (in_image && y >= yA0 && y < yA1) {
+            const int j = g.row0 + y * g.W + px;
+            const size_t e = (size_t)j * d + c0;
+            v.r = ld_lane<T, CPL>(r + e);
+            if (iter) {
+                v.w = ld_lane<T, CPL>(w + e);
+                if (!first) v.sp = ld_lane<T, CPL>(sp + e);
+            }
+            v.isq = a.isq[j];
+        }
+        return v;
+    };
+    auto ldb = [&](int y) {
+        MidB m{};
+        if (blane && y >= max(0, g.y0 - rho) && y < yA1) {
+            const int j = g.row0 + y * g.W + px;
+            m.gd = a.gdiag[j];
+#pragma unroll
+            for (int k = 0; k < H; ++k) m.gv[k] = a.gval[(size_t)k * a.n + j];
+        }
+        return m;
+    };
+    auto ldc = [&](int y) {
+        MidC m{};
+        if (clane && y >= max(0, g.y0 - rho) && y < min(g.H, g.y1 + rho)) {
+            const int j = g.row0 + y * g.W + px;
+            m.gd = a.gdiag[j];
+            m.isq = a.isq[j];
+#pragma unroll
+            for (int k = H; k < KC; ++k) m.gv[k - H] = a.gval[(size_t)k * a.n + j];
+        }
+        return m;
+    };
+    // an owner's values of its pixel, its r, w, s included (loaded again
+    // rather than carried through the rows of the walk, to keep registers)
+    auto ldo = [&](int y) {
+        Own o{};
+        if (owner && y >= g.y0 && y < g.y1) {
+            const int i = g.row0 + y * g.W + px;
+            const size_t e = (size_t)i * d + c0;
+            o.v.r = ld_lane<T, CPL>(r + e);
+            if (iter) {
+                o.v.w = ld_lane<T, CPL>(w + e);
+                if (!first) o.v.sp = ld_lane<T, CPL>(sp + e);
+                o.x = ld_lane<T, CPL>(a.x + e);
+                o.u = ld_lane<T, CPL>(a.zl + e);
+                if (!first) o.p = ld_lane<T, CPL>(a.p + e);
+            }
+            o.dA = a.diagA[i];
+#pragma unroll
+            for (int k = 0; k < KC; ++k) o.ww[k] = a.sw[(size_t)k * a.n + i];
+        }
+        return o;
+    };
+    // s and r' of a lane's pixel from its raw values (the owners' arithmetic)
+    auto s_of = [&](const Raw& v, int j) { return cg_s(first, beta[j], v.sp.v[j], v.w.v[j]); };
+    auto rp_of = [&](const Raw& v, int j) { return iter ? cg_r(alpha[j], s_of(v, j), v.r.v[j]) : v.r.v[j]; };
+    double acc[3][CPL];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) acc[q][j] = 0.0;
+    if (g.len > 0 && g.y1 > g.y0) {
+        const int Yb = g.y0 - 2 * rho, Ye = g.y1 + 2 * rho;
+        // every value a step uses is loaded one step ahead (the raw values two)
+        Raw raw = ldr(Yb), rnext1 = ldr(Yb + 1);   // rows Y and Y + 1
+        MidB mb = ldb(Yb);
+        MidC mc = ldc(Yb - rho);
+        Own own = ldo(Yb - 2 * rho);
+        for (int Y = Yb; Y < Ye; ++Y) {
+            const Raw rnext = ldr(Y + 2);
+            const MidB mbn = ldb(Y + 1);
+            const MidC mcn = ldc(Y + 1 - rho);
+            const Own ownn = ldo(Y + 1 - 2 * rho);
+            // A: publish D_A^{-1/2} r' of row Y (zero outside the image)
+            if (loader) {
+                L pa;
+#pragma unroll
+                for (int j = 0; j < CPL; ++j) pa.v[j] = mul_t(raw.isq, rp_of(raw, j));
+                st_lane<T, CPL>(ringA + sa(Y) * RL + lt, pa);
+            }
+            __syncthreads();
+            // B: y1 of row Y
+            if (loader) {
+                L y1{};
+                if (blane && Y >= 0 && Y < g.H && Y >= g.y0 - rho) {
+                    const L a0 = ld_lane<T, CPL>(ringA + sa(Y) * RL + lt);
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) y1.v[j] = mul_t(mb.gd, a0.v[j]);
+#pragma unroll
+                    for (int k = 0; k < H; ++k) {
+                        const L an = ld_lane<T, CPL>(ringA + sa(Y + S::dy(k)) * RL + lt + S::dx(k) * d);
+#pragma unroll
+                        for (int j = 0; j < CPL; ++j) y1.v[j] = fma_t(mb.gv[k], an.v[j], y1.v[j]);
+                    }
+                }
+                st_lane<T, CPL>(ringB + sb_(Y) * RL + lt, y1);
+            }
+            __syncthreads();
+            // C: u' of row Y - rho
+            const int Yc = Y - rho;
+            if (loader && Yc >= g.y0 - rho) {
+                L u{};
+                if (clane && Yc >= 0 && Yc < g.H) {
+                    const L b0 = ld_lane<T, CPL>(ringB + sb_(Yc) * RL + lt);
+                    T accg[CPL];
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) accg[j] = mul_t(mc.gd, b0.v[j]);
+#pragma unroll
+                    for (int k = H; k < KC; ++k) {
+                        const L bn = ld_lane<T, CPL>(ringB + sb_(Yc + S::dy(k)) * RL + lt + S::dx(k) * d);
+#pragma unroll
+                        for (int j = 0; j < CPL; ++j) accg[j] = fma_t(mc.gv[k - H], bn.v[j], accg[j]);
+                    }
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) u.v[j] = mul_t(mc.isq, accg[j]);
+                }
+                st_lane<T, CPL>(ringC + sc(Yc) * RL + lt, u);
+            }
+            __syncthreads();
+            // D: the owned pixels of row Y - 2 rho
+            const int Yd = Y - 2 * rho;
+            if (owner && Yd >= g.y0 && Yd < g.y1) {
+                const int i = g.row0 + Yd * g.W + px;
+                const size_t e = (size_t)i * d + c0;
+                const L un = ld_lane<T, CPL>(ringC + sc(Yd) * RL + lt);
+                T accA[CPL];
+#pragma unroll
+                for (int j = 0; j < CPL; ++j) accA[j] = T(0);
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    const T w2 = mul_t(own.ww[k], own.ww[k]);
+                    const L cn = ld_lane<T, CPL>(ringC + sc(Yd + S::dy(k)) * RL + lt + S::dx(k) * d);
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) accA[j] = fma_t(w2, cn.v[j], accA[j]);
+                }
+                const Raw& v = own.v;
+                L wnew, pi, si, ri, xn;
+#pragma unroll
+                for (int j = 0; j < CPL; ++j) {
+                    wnew.v[j] = fma_t(own.dA, un.v[j], -mul_t(a.c_off, accA[j]));
+                    if (iter) {
+                        si.v[j] = s_of(v, j);
+                        ri.v[j] = cg_r(alpha[j], si.v[j], v.r.v[j]);
+                        pi.v[j] = first ? own.u.v[j] : fma_t(beta[j], own.p.v[j], own.u.v[j]);
+                        xn.v[j] = fma_t(alpha[j], pi.v[j], own.x.v[j]);
+                        acc[0][j] += (double)ri.v[j] * (double)un.v[j];
+                        acc[2][j] += (double)ri.v[j] * (double)ri.v[j];
+                    } else {
+                        acc[0][j] += (double)v.r.v[j] * (double)un.v[j];
+                    }
+                    acc[1][j] += (double)wnew.v[j] * (double)un.v[j];
+                }
+                if (iter) {
+                    st_lane<T, CPL>(a.p + e, pi);
+                    st_lane<T, CPL>(sn + e, si);
+                    st_lane<T, CPL>(a.x + e, xn);
+                    st_lane<T, CPL>(rn + e, ri);
+                }
+                st_lane<T, CPL>(a.zl + e, un);
+                st_lane<T, CPL>(wn + e, wnew);
+            }
+            raw = rnext1;
+            rnext1 = rnext;
+            mb = mbn;
+            mc = mcn;
+            own = ownn;
+        }
+    }
+    __syncthreads();
+    if (iter) {
+        block_partials_cpl<3, CPL>(acc, sh, d, a.part, a.nblk, lb);
+    } else {
+        double acc2[2][CPL];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) { acc2[0][j] = acc[0][j]; acc2[1][j] = acc[1][j]; }
+        block_partials_cpl<2, CPL>(acc2, sh, d, a.part, a.nblk, lb);
+    }
+}
+
 // LC and LD fused (the ph_lc + ph_ld arithmetic) over a strip whose ring rows
 // span two stencil radii on each side: x += alpha p and r' = r - alpha q on the
 // owned pixels; y1 = Gt D_A^{-1/2} r' over the lower neighbours for every pixel
@@ -2232,6 +2545,43 @@ __global__ void __launch_bounds__(kBlock) k_st_lcd(KA<T> a, int upd) {
     }
 }
 
+// factor-preconditioned CG on strips, one kernel per iteration (mode 1) and
+// one for u0, w0 before the first (mode 0)
+template <typename T, int KC, int CPL>
+__global__ void __launch_bounds__(kBlock) k_st_fcg(KA<T> a, int mode) {
+    __shared__ double sh[FcgRings<KC, T, CPL>::doubles];
+    if (ld_flag(&a.S->done)) return;
+    st_fcg<KC, CPL>(a, logical_block(a.nblk), sh, mode);
+    if (last_block(a.bar + kBarLast, a.nblk)) {
+        if (mode == 0) {
+            fin_w0(a, sh, false);
+        } else {
+            fin_it(a, sh, false);
+            if (threadIdx.x == 0 && a.S->done) solve_stats(a);
+        }
+    }
+}
+
+// columns per lane of the one-pass factor CG: two (8-byte vector accesses,
+// twice the pixels per strip) for FP32 and even d; one otherwise (the FP64
+// rings of two columns per lane would not fit the LDS of a workgroup)
+template <typename T>
+constexpr int fcg_cpl(int d) { return (sizeof(T) == 4 && d % 2 == 0) ? 2 : 1; }
+
+template <typename T>
+const void* fcg_kernel(int ellK, int cpl) {
+    const bool two = (cpl == 2 && sizeof(T) == 4);
+#define PFE_FCG(K) (two ? reinterpret_cast<const void*>(&k_st_fcg<T, K, (sizeof(T) == 4 ? 2 : 1)>) \
+                        : reinterpret_cast<const void*>(&k_st_fcg<T, K, 1>))
+    switch (ellK) {
+        case 4: return PFE_FCG(4);
+        case 8: return PFE_FCG(8);
+        case 24: return PFE_FCG(24);
+        default: return nullptr;
+    }
+#undef PFE_FCG
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_cg_zero(KA<T> a) {
     ph_zero(a, logical_block(a.nblk), a.cs.zero);
@@ -2869,9 +3219,13 @@ struct pfe_ctx {
     Partition pc;            // persistent partition (pc.nblk == 0: not available)
     Partition ps;            // strip partition of pixel grids (ps.nblk == 0: not available)
     Partition pl;            // strips with a two-radius halo (fused learned apply)
+    Partition pf;            // strips with a three-radius halo (one-pass factor CG)
+    int one_pass = 0;        // factor preconditioners on strips: one pass per CG iteration (0: two)
     int want_strips = 2;     // one launch per phase: residual, w0 and CG kernels on image strips sized
                              // for this many waves of co-resident strip workgroups (0: row chunks)
     int strip_slots = 0;     // co-resident strip workgroups on the device (0: no strip kernel)
+    int fcg_slots = 0;       // co-resident workgroups of the one-pass factor CG kernel
+    int fcg_cpl = 1;         // its columns per lane
     int ps_waves = 0;        // waves the strip partition was built for
     int part_blocks = 0;     // workgroups the partial-sum buffer holds
     void* Y = nullptr; void* P = nullptr; void* B = nullptr;
@@ -3191,6 +3545,15 @@ pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0)
             case PH_LC: PFE_LAUNCH_ST(k_st_lc, K, grid, st, a, mode); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
             case PH_LD: PFE_LAUNCH_ST(k_st_ld, K, grid, st, a, mode); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
             case PH_LCD: PFE_LAUNCH_ST(k_st_lcd, K, grid, st, a, mode); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
+            case PH_FW0: case PH_FIT: {
+                const void* fn = fcg_kernel<T>(K, c->fcg_cpl);
+                if (!fn) break;
+                KA<T> args = a;
+                int fmode = (ph == PH_FIT) ? 1 : 0;
+                void* kp[] = {(void*)&args, (void*)&fmode};
+                PFE_CHECK_HIP(hipLaunchKernel(fn, grid, dim3(kBlock), kp, 0, st));
+                return PFE_OK;
+            }
             case PH_IT: PFE_LAUNCH_ST(k_st_it, K, grid, st, a); PFE_CHECK_HIP(hipGetLastError()); return PFE_OK;
             default: break;
         }
@@ -3221,7 +3584,8 @@ pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0)
 constexpr int kCgChunk = 8;
 
 template <typename T>
-const void* kernel_for(int which, int ellK, bool strip) {
+const void* kernel_for(int which, int ellK, bool strip, int cpl = 1) {
+    if (which == PH_FIT) return fcg_kernel<T>(ellK, cpl);
 #define PFE_SSEL(K) switch (ellK) { \
         case 4: return reinterpret_cast<const void*>(&K<T, 4>); \
         case 8: return reinterpret_cast<const void*>(&K<T, 8>); \
@@ -3254,24 +3618,29 @@ const void* kernel_for(int which, int ellK, bool strip) {
 }
 
 template <typename T>
-pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, const KA<T>* al, hipGraphExec_t* out) {
-    // al: arguments of the fused learned apply (strips with a two-radius halo), or null
-    std::vector<unsigned char> key(2 * sizeof(KA<T>) + 2, 0);
+pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, const KA<T>* al, hipGraphExec_t* out,
+                          const KA<T>* af = nullptr) {
+    // al: arguments of the fused learned apply (strips with a two-radius halo), or null;
+    // af: arguments of the one-pass factor CG (strips with a three-radius halo), or null
+    std::vector<unsigned char> key(3 * sizeof(KA<T>) + 2, 0);
     std::memcpy(key.data(), &a, sizeof(KA<T>));
     if (al) std::memcpy(key.data() + sizeof(KA<T>), al, sizeof(KA<T>));
-    key[2 * sizeof(KA<T>)] = learned ? 1 : 0;
-    key[2 * sizeof(KA<T>) + 1] = (unsigned char)sizeof(T);
+    if (af) std::memcpy(key.data() + 2 * sizeof(KA<T>), af, sizeof(KA<T>));
+    key[3 * sizeof(KA<T>)] = learned ? 1 : 0;
+    key[3 * sizeof(KA<T>) + 1] = (unsigned char)sizeof(T);
     if (c->cg_exec && key == c->cg_key) { *out = c->cg_exec; return PFE_OK; }
     if (c->cg_exec) { (void)hipGraphExecDestroy(c->cg_exec); c->cg_exec = nullptr; }
     hipGraph_t g = nullptr;
     PFE_CHECK_HIP(hipGraphCreate(&g, 0));
     KA<T> args = a;
     KA<T> largs = al ? *al : a;
+    KA<T> fargs = af ? *af : a;
     int initial = 0, upd = 1;
     void* p1[] = {(void*)&args};
     void* p2[] = {(void*)&args, (void*)&initial};
     void* p3[] = {(void*)&args, (void*)&upd};
     void* p4[] = {(void*)&largs, (void*)&upd};
+    void* p5[] = {(void*)&fargs, (void*)&upd};
     hipGraphNode_t prev = nullptr;
     hipError_t e = hipSuccess;
     auto add = [&](const void* fn, void** kp, int nblk) {
@@ -3291,7 +3660,9 @@ pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, const KA<T>*
     const int K = a.ell_K;
     const bool st = a.geo != nullptr;
     for (int k = 0; k < kCgChunk; ++k) {
-        if (learned) {
+        if (learned && af) {
+            add(kernel_for<T>(PH_FIT, K, true, c->fcg_cpl), p5, af->nblk);
+        } else if (learned) {
             add(kernel_for<T>(PH_LA, K, st), p1, a.nblk);
             if (al) {
                 add(kernel_for<T>(PH_LCD, K, true), p4, al->nblk);
@@ -3315,9 +3686,10 @@ pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, const KA<T>*
 
 // replay the chunk graph until the solve is done
 template <typename T>
-pfe_status pcg_replay(pfe_ctx* c, const KA<T>& a, bool learned, const KA<T>* al = nullptr) {
+pfe_status pcg_replay(pfe_ctx* c, const KA<T>& a, bool learned, const KA<T>* al = nullptr,
+                      const KA<T>* af = nullptr) {
     hipGraphExec_t ex = nullptr;
-    PFE_TRY(cg_chunk_graph(c, a, learned, al, &ex));
+    PFE_TRY(cg_chunk_graph(c, a, learned, al, &ex, af));
     int it = 0, done = 0;
     while (true) {
         PFE_CHECK_HIP(hipGraphLaunch(ex, c->stream));
@@ -3359,6 +3731,28 @@ pfe_status pcg_loop_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
 // the PCG phases run on the arguments 'as' (strips of a pixel grid, or 'a').
 template <typename T>
 pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
+    // on strips with a three-radius halo: one pass per iteration
+    if (as.geo && c->pf.nblk > 0 && c->one_pass) {
+        KA<T> af = make_args<T>(c, c->pf);
+        af.x = as.x;       // the iterate and rhs of this solve (a caller's buffers in pfe_pcg)
+        af.rhs = as.rhs;
+        hipLaunchKernelGGL(k_stats_if_done<T>, dim3(1), dim3(64), 0, c->stream, a);
+        PFE_TRY(launch_phase(c, af, PH_FW0, 0, 0));
+        if (c->prm.graphs) {
+            PFE_TRY(pcg_replay<T>(c, as, true, nullptr, &af));
+            return launch_phase(c, a, PH_ZERO, 0, 0);
+        }
+        int it = 0, done = 0;
+        const int chunk = 4;
+        while (true) {
+            for (int k = 0; k < chunk; ++k) PFE_TRY(launch_phase(c, af, PH_FIT, 0, 0));
+            it += chunk;
+            PFE_CHECK_HIP(hipMemcpyAsync(&done, &c->S->done, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            PFE_CHECK_HIP(hipStreamSynchronize(c->stream));
+            if (done || it > c->prm.maxit + chunk) break;
+        }
+        return launch_phase(c, a, PH_ZERO, 0, 0);
+    }
     // on strips the two factor products run as one kernel on strips with a
     // two-radius halo
     const bool fused = as.geo && c->pl.nblk > 0;
@@ -3446,10 +3840,19 @@ pfe_status setup_strips(pfe_ctx* c) {
     if (const char* ev = getenv("PFE_STRIP_WG")) want = std::max(1, atoi(ev));   // launch-shape experiments
     PFE_TRY(make_strip_partition(c->g, (int)c->d, want, 1, c->ps));
     PFE_TRY(make_strip_partition(c->g, (int)c->d, want, 2, c->pl));
+    {
+        // one-pass factor CG: strips of CPL columns per lane, as many as its own
+        // co-resident workgroups for the wanted waves
+        const int cpl = c->fcg_cpl;
+        int want_f = c->want_strips * (c->fcg_slots > 0 ? c->fcg_slots : c->strip_slots);
+        if (const char* ev = getenv("PFE_STRIP_WG")) want_f = std::max(1, atoi(ev));
+        PFE_TRY(make_strip_partition(c->g, (int)c->d / cpl, want_f, 3, c->pf));
+    }
     c->ps_waves = c->want_strips;
-    if (c->part_blocks > 0 && std::max(c->ps.nblk, c->pl.nblk) > c->part_blocks) {
+    if (c->part_blocks > 0 && std::max(std::max(c->ps.nblk, c->pl.nblk), c->pf.nblk) > c->part_blocks) {
         free_partition(c->ps);
         free_partition(c->pl);
+        free_partition(c->pf);
         c->ps_waves = 0;
         set_error("strip partition of %d workgroups exceeds the partial-sum buffer", c->ps.nblk);
         return PFE_E_STATE;
@@ -3605,6 +4008,7 @@ void free_ctx(pfe_ctx* c) {
     free_partition(c->pc);
     free_partition(c->ps);
     free_partition(c->pl);
+    free_partition(c->pf);
     if (c->cg_exec) (void)hipGraphExecDestroy(c->cg_exec);
     c->cg_exec = nullptr;
 }
@@ -3906,6 +4310,7 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
     c->coop -= c->coop % kNumXcd;
     if (s == PFE_OK) s = setup_persistent(c);
     if (const char* ev = getenv("PFE_STRIPS")) c->want_strips = std::max(0, atoi(ev));   // launch-shape experiments
+    if (const char* ev = getenv("PFE_ONE_PASS")) c->one_pass = atoi(ev) != 0;
     if (s == PFE_OK) {
         // strip partition: built first for the most waves any later shape asks
         // for (it has the most workgroups), then for the wanted count
@@ -3919,13 +4324,21 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
         }
         if (kst && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_st, kst, kBlock, 0) != hipSuccess) occ_st = 0;
         c->strip_slots = kst ? std::max(1, occ_st) * ncu : 0;
+        c->fcg_cpl = (p->dtype == PFE_FP64) ? fcg_cpl<double>((int)c->d) : fcg_cpl<float>((int)c->d);
+        if (const char* ev = getenv("PFE_FCG_CPL")) c->fcg_cpl = (atoi(ev) == 2 && c->fcg_cpl == 2) ? 2 : 1;
+        const void* kf = (p->dtype == PFE_FP64) ? fcg_kernel<double>(g->ell_K, c->fcg_cpl)
+                                                : fcg_kernel<float>(g->ell_K, c->fcg_cpl);
+        int occ_f = 0;
+        if (kf && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_f, kf, kBlock, 0) != hipSuccess) occ_f = 0;
+        c->fcg_slots = kf ? std::max(1, occ_f) * ncu : 0;
         const int want = c->want_strips;
         c->want_strips = std::max(want, 2);
         s = setup_strips(c);
         c->want_strips = want;
     }
     if (s != PFE_OK) { free_ctx(c); delete c; return s; }
-    const int nblk_max = std::max(std::max(c->pm.nblk, c->pc.nblk), std::max(c->ps.nblk, c->pl.nblk));
+    const int nblk_max = std::max(std::max(std::max(c->pm.nblk, c->pc.nblk), std::max(c->ps.nblk, c->pl.nblk)),
+                                  c->pf.nblk);
     c->part_blocks = nblk_max;
     if (s == PFE_OK) s = setup_strips(c);
     if (s != PFE_OK) { free_ctx(c); delete c; return s; }
@@ -4082,12 +4495,13 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
     if (n_results) *n_results = 0;
     const bool f64 = c->prm.dtype == PFE_FP64;
     const size_t nd = (size_t)c->n * c->d * c->esz;
-    struct Shape { int persistent, team, cache, strips; double w2; };
-    const Shape shapes[] = {{1, 64, 1, 0, 1.0}, {1, 64, 0, 0, 1.0}, {1, 1, 1, 0, 1.0}, {1, 1, 0, 0, 1.0},
-                            {1, 1, 1, 0, 0.9}, {1, 1, 0, 0, 0.9}, {1, 1, 1, 0, 0.85}, {1, 1, 0, 0, 0.85},
-                            {1, 1, 1, 0, 0.8}, {1, 1, 0, 0, 0.8},
-                            {0, c->team, 0, 0, 1.0}, {0, c->team, 0, 1, 1.0}, {0, c->team, 0, 2, 1.0}};
-    const Shape orig{c->prm.persistent, c->team, c->want_cache, c->want_strips, c->second_weight};
+    struct Shape { int persistent, team, cache, strips; double w2; int one_pass; };
+    const Shape shapes[] = {{1, 64, 1, 0, 1.0, 0}, {1, 64, 0, 0, 1.0, 0}, {1, 1, 1, 0, 1.0, 0}, {1, 1, 0, 0, 1.0, 0},
+                            {1, 1, 1, 0, 0.9, 0}, {1, 1, 0, 0, 0.9, 0}, {1, 1, 1, 0, 0.85, 0}, {1, 1, 0, 0, 0.85, 0},
+                            {1, 1, 1, 0, 0.8, 0}, {1, 1, 0, 0, 0.8, 0},
+                            {0, c->team, 0, 0, 1.0, 0}, {0, c->team, 0, 1, 1.0, 0}, {0, c->team, 0, 2, 1.0, 0},
+                            {0, c->team, 0, 1, 1.0, 1}, {0, c->team, 0, 2, 1.0, 1}};
+    const Shape orig{c->prm.persistent, c->team, c->want_cache, c->want_strips, c->second_weight, c->one_pass};
     char* save = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     pfe_status st = PFE_OK;
@@ -4125,6 +4539,8 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
             if (sh.persistent && (c->coop < kNumXcd || c->prm.precond != PFE_JACOBI || c->prm.cold_start)) continue;
             if (sh.strips && c->strip_slots == 0) continue;
             if (sh.w2 != 1.0 && c->per_cu != 2) continue;
+            if (sh.one_pass && (c->prm.precond == PFE_JACOBI || c->fcg_slots == 0)) continue;
+            c->one_pass = sh.one_pass;
             c->prm.persistent = sh.persistent;
             c->team = sh.team;
             c->want_cache = sh.cache;
@@ -4132,6 +4548,7 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
             c->second_weight = sh.w2;
             if ((st = setup_strips(c)) != PFE_OK) break;
             if (sh.strips && c->ps.nblk == 0) continue;
+            if (sh.one_pass && c->pf.nblk == 0) continue;
             if (sh.persistent) {
                 if ((st = setup_persistent(c)) != PFE_OK) break;
                 if (c->pc.nblk == 0 || (sh.cache && c->cache_np == 0)) continue;
@@ -4160,7 +4577,8 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
             r.row_cache = sh.persistent ? (c->cache_np > 0) : 0;
             r.strips = sh.strips;
             r.second_weight = sh.persistent ? sh.w2 : 1.0;
-            r.workgroups = sh.persistent ? c->pc.nblk : (sh.strips ? c->ps.nblk : c->pm.nblk);
+            r.one_pass = sh.one_pass;
+            r.workgroups = sh.persistent ? c->pc.nblk : (sh.one_pass ? c->pf.nblk : (sh.strips ? c->ps.nblk : c->pm.nblk));
             r.ms = ms / trials;
             found.push_back(r);
             if (best < 0 || r.ms < best_ms) { best = (int)found.size() - 1; best_ms = r.ms; }
@@ -4173,6 +4591,7 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
         c->want_cache = found[best].persistent ? found[best].row_cache : orig.cache;
         c->want_strips = found[best].persistent ? orig.strips : found[best].strips;
         c->second_weight = found[best].persistent ? found[best].second_weight : orig.w2;
+        c->one_pass = found[best].persistent ? orig.one_pass : found[best].one_pass;
         found[best].chosen = 1;
     } else {
         c->prm.persistent = orig.persistent;
@@ -4180,6 +4599,7 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
         c->want_cache = orig.cache;
         c->want_strips = orig.strips;
         c->second_weight = orig.w2;
+        c->one_pass = orig.one_pass;
     }
     pfe_status s2 = setup_persistent(c);
     if (s2 == PFE_OK) s2 = setup_strips(c);
@@ -4217,6 +4637,10 @@ pfe_status pfe_set_launch_shape(pfe_ctx* c, const pfe_tune_result* sh) {
         set_error("pfe_set_launch_shape: image strips need a pixel-grid graph with 4, 8 or 24 slots");
         return PFE_E_ARG;
     }
+    if (!sh->persistent && sh->one_pass && (sh->strips == 0 || c->fcg_slots == 0)) {
+        set_error("pfe_set_launch_shape: the one-pass factor CG runs on image strips of a pixel-grid graph");
+        return PFE_E_ARG;
+    }
     c->prm.persistent = sh->persistent ? 1 : 0;
     if (sh->persistent) {
         c->team = sh->team;
@@ -4224,6 +4648,7 @@ pfe_status pfe_set_launch_shape(pfe_ctx* c, const pfe_tune_result* sh) {
         c->second_weight = c->per_cu == 2 ? sh->second_weight : 1.0;
     } else {
         c->want_strips = sh->strips;
+        c->one_pass = sh->one_pass ? 1 : 0;
     }
     PFE_TRY(setup_persistent(c));
     PFE_TRY(setup_strips(c));

@@ -194,3 +194,34 @@ def test_learned_pcg_strips_match_row_chunks(stencil, d, monkeypatch):
     assert np.all(np.abs(out[0][1] - out[1][1]) <= 1)
     assert e <= 1e-9
     assert out[0][2]["rel_res_max"] <= 1e-10
+
+
+@pytest.mark.parametrize("stencil,d,fp64", [(8, 4, True), (-2, 5, True), (4, 3, True), (-2, 16, False), (8, 10, False)])
+def test_one_pass_factor_pcg_matches_two_pass(stencil, d, fp64):
+    """Factor-preconditioned PCG on image strips: the one-pass
+    Chronopoulos-Gear iteration (u = M^{-1} r and w = A u formed through three
+    LDS rings) against the two-pass iteration (A p, then the factor apply with
+    the x, r update): the same solution to the tolerance and the same
+    iteration counts within one, on ragged images."""
+    from paper_1612_06496_amd import Mpnn, Solver
+    banner(f"one-pass vs two-pass factor PCG stencil={stencil} d={d} fp64={fp64}")
+    wl = synth.grid_workload("t", 45, 101, 6, 0.05, 3, stencil=stencil, d=d)
+    th = np.random.default_rng(1).normal(0.0, 0.3, size=Mpnn.NPARAMS)
+    th[Mpnn.NPARAMS - 1] = np.log(np.e - 1.0)
+    rhs = np.random.default_rng(2).normal(size=(wl.n, d))
+    tol = 1e-10 if fp64 else 1e-6
+    out = []
+    for one_pass in (True, False):
+        S = Solver(gpu_graph(wl), wl.y0, lam=20.0, r=1.0, n_inner=2, tol=tol, maxit=5000, fp64=fp64,
+                   persistent=False, graphs=one_pass)
+        S.set_launch_shape(persistent=False, strips=1, one_pass=one_pass)
+        S.set_learned(Mpnn(th.astype(np.float32)))
+        x, iters, info = S.pcg(rhs, np.zeros_like(rhs))
+        out.append((to_np(x), np.asarray(iters), info))
+        S.close()
+    e = rel(out[0][0], out[1][0])
+    print(f"rel diff {e:.2e}; iterations {out[0][1].tolist()} vs {out[1][1].tolist()}; "
+          f"rel res {out[0][2]['rel_res_max']:.2e}")
+    assert np.all(np.abs(out[0][1] - out[1][1]) <= 1)
+    assert out[0][2]["rel_res_max"] <= tol
+    assert e <= (1e-8 if fp64 else 1e-4)
