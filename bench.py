@@ -348,6 +348,53 @@ def host_cpu():
             "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
+def d_sweep_batched_leg(wl, c, dims=(5, 10, 15, 20, 25), steps=10):
+    """The same d-sweep in ONE launch per SOC iteration: copies of the image in
+    a block-diagonal union, copy k embedded in dims[k] dimensions (its initial
+    embedding padded with zero columns to the largest d; the library keeps
+    them zero and orthonormalises each copy on its active block).  One
+    lambda = r = c for all copies (a batch shares its penalties); autotuned
+    launch shape; one untimed and `steps` timed SOC iterations."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1612_06496_amd import Graph, Solver
+    dmax = max(dims)
+    parts = [Graph.grid(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma) for _ in dims]
+    U = Graph.union(parts)
+    for p_ in parts:
+        p_.close()
+    Y0 = np.zeros((U.n, dmax), dtype=np.float32)
+    for k, d in enumerate(dims):
+        Y0[k * wl.n:(k + 1) * wl.n, :d] = synth.smooth_y0(wl.H, wl.W, d, 7919)
+    S = Solver(U, Y0, lam=c, r=c, n_inner=wl.n_inner, tol=wl.tol, maxit=1000)
+    tuned = [t for t in S.autotune(trials=1) if t["chosen"]]
+    S.solve(1)
+    S.stats(reset=True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        S.solve(1)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    info = S.stats(reset=True)
+    mon = S.monitor()
+    S.close()
+    U.close()
+    progress("d-sweep in one launch done")
+    return {"dims": list(dims), "images": len(dims), "n": int(len(dims) * wl.n), "d_max": dmax,
+            "lambda": c, "r": c, "ms_per_step": round(ms / steps, 4),
+            "outer_iters_per_s": round(steps / (ms / 1e3), 1),
+            "pcg_iters_per_solve": round(info["cg_iters_total"] / max(1, info["solves"]), 2),
+            "constraint": float(f"{mon['constraint']:.3g}"),
+            "launch": ("persistent" if info["workgroups"] else ("strips" if info["flags"] & 2 else "multi")),
+            "autotuned": tuned[0] if tuned else None}
+
+
 def cpu_baseline(wls, lam, r, n_steps=2, max_images=2):
     """The FP64 oracle on the host, on a bounded sample: n_steps SOC iterations
     of the workload's first max_images images (sparse LU factorisation reported
@@ -558,6 +605,9 @@ def main():
         progress(f"k-means, {kit} Lloyd iterations: {ms3:.1f} ms")
     if not args.no_d_sweep and default:
         line["d_sweep"] = d_sweep_leg(G, wl)
+        batched = d_sweep_batched_leg(wl, c)
+        batched["separate_ms_sum"] = round(sum(r_["ms_per_step"] for r_ in line["d_sweep"]), 4)
+        line["d_sweep_one_launch"] = batched
     if not args.no_learned and default:
         leg = learned_leg(workload=args.learned_workload, train_workload=args.learned_train_workload,
                           n_outer=args.learned_outer)

@@ -123,6 +123,7 @@ struct KA {
     int b_zero;        // first edge update of a SOC iteration: b starts from 0
     int ortho;         // PFE_POLAR / PFE_CHOL
     int sten;          // ELL slots in pixel-stencil order (lower neighbours first)
+    const int* dact;   // per segment: active columns (the leading ones; the others stay zero), or null (all d)
 };
 
 // ---------------------------------------------------------------------------
@@ -2009,9 +2010,11 @@ __device__ __forceinline__ void solve_stats(const KA<T>& a) {
 // definite.  LDS use: sh[1024, 4608).
 template <typename T>
 __device__ __forceinline__ bool factor_gram(const KA<T>& a, int mode, const double* gsum, double* sh, double* Tout,
-                                            bool report) {
-    const int d = a.d, t = threadIdx.x, nb = blockDim.x;
-    const int npair = d * (d + 1) / 2;
+                                            bool report, int da) {
+    // da <= a.d: the segment's active columns (the leading block of G is
+    // factored; T is zero outside it, so inactive columns of P and B stay zero)
+    const int dfull = a.d, d = da, t = threadIdx.x, nb = blockDim.x;
+    const int npair = dfull * (dfull + 1) / 2;
     double* G = sh + 1024;
     double* L = sh + 2048;
     double* Ym = sh + 3072;
@@ -2019,10 +2022,17 @@ __device__ __forceinline__ bool factor_gram(const KA<T>& a, int mode, const doub
     double* red = sh + 4096;
     for (int k = t; k < npair; k += nb) {
         int r, cc;
-        pair_of(k, d, r, cc);
-        G[r * d + cc] = gsum[k];
-        G[cc * d + r] = gsum[k];
+        pair_of(k, dfull, r, cc);
+        if (r < d && cc < d) {
+            G[r * d + cc] = gsum[k];
+            G[cc * d + r] = gsum[k];
+        }
     }
+    if (d < dfull)
+        for (int k = t; k < dfull * dfull; k += nb) {
+            const int r = k / dfull, cc = k - r * dfull;
+            if (r >= d || cc >= d) Tout[r * kMaxD + cc] = 0.0;
+        }
     __syncthreads();
     for (int k = t; k < d * d; k += nb) L[k] = G[k];
     __shared__ int s_bad;
@@ -2162,7 +2172,7 @@ __device__ __forceinline__ bool seg_factor(const KA<T>& a, int sg, int mode, dou
     __shared__ double gsum[kMaxD * (kMaxD + 1) / 2];
     if (grouped) reduce_range(gp, kNumXcd, 0, kNumXcd, npair, 1, gsum, sh);
     else reduce_range(a.part, a.nblk, a.seg_blk0[sg], a.seg_blk0[sg + 1], npair, 1, gsum, sh);
-    return factor_gram(a, mode, gsum, sh, Tout, report);
+    return factor_gram(a, mode, gsum, sh, Tout, report, a.dact ? a.dact[sg] : a.d);
 }
 
 // ---------------------------------------------------------------------------
@@ -2854,6 +2864,14 @@ __global__ void k_edges_to_slots(KA<T> a, const int* __restrict__ seid, const T*
     }
 }
 
+// flags[c] = 1 when column c of rows [r0, r1) of Y has a nonzero entry
+template <typename T>
+__global__ void k_col_flags(const T* __restrict__ Y, int64_t r0, int64_t r1, int d, int* __restrict__ flags) {
+    const size_t ne = (size_t)(r1 - r0) * d;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (size_t)gridDim.x * blockDim.x)
+        if (Y[(size_t)r0 * d + e] != T(0)) atomicOr(&flags[e % d], 1);
+}
+
 template <typename T>
 __global__ void k_fill(size_t n, T v, T* __restrict__ out) {
     size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2947,9 +2965,11 @@ __global__ void __launch_bounds__(kBlock) k_monitor(KA<T> a) {
                 s_obj += tot[0];
                 s_spl += tot[1];
                 s_pp += tot[2];
+                const int da = a.dact ? a.dact[sg] : d;
                 for (int k = 0; k < npair; ++k) {
                     int r, cc;
                     pair_of(k, d, r, cc);
+                    if (r >= da || cc >= da) continue;
                     double id = (r == cc) ? 1.0 : 0.0;
                     omax = fmax(omax, fabs(tot[3 + k] - id));
                     cmax = fmax(cmax, fabs(tot[3 + npair + k] - id));
@@ -3241,6 +3261,8 @@ struct pfe_ctx {
     void* zl = nullptr;
     void* y1 = nullptr;
     void* xbak = nullptr;      // start of a factor-preconditioned solve (Jacobi fallback)
+    int* dact = nullptr;       // per segment: active (leading) columns of Y0, when some segment has fewer than d
+    std::vector<int> dact_h;
     int have_factor = 0;
     double* part = nullptr;
     double* gpart = nullptr;
@@ -3496,6 +3518,7 @@ KA<T> make_args(pfe_ctx* c, const Partition& pt) {
     a.b_zero = 0;
     a.ortho = c->prm.ortho;
     a.sten = c->g->stencil;
+    a.dact = c->dact;
     return a;
 }
 
@@ -4000,7 +4023,7 @@ pfe_status set_diag(pfe_ctx* c) {
 void free_ctx(pfe_ctx* c) {
     void* bufs[] = {c->Y, c->P, c->B, c->bs, c->ds, c->rhs, c->p, c->rb[0], c->rb[1], c->wb[0], c->wb[1],
                     c->sb[0], c->sb[1], c->diagA, c->invdiag, c->sqrtD, c->isqrtD, c->isq, c->gval, c->gdiag,
-                    c->zl, c->y1, c->xbak, c->part, c->gpart,
+                    c->zl, c->y1, c->xbak, c->dact, c->part, c->gpart,
                     c->Tm, c->colbuf, c->colint, c->S, c->bar, c->hist};
     for (void* p : bufs)
         if (p) (void)dev_free(p);
@@ -4023,6 +4046,60 @@ bool params_ok(const pfe_params* p, int64_t n) {
     if (p->ortho != PFE_POLAR && p->ortho != PFE_CHOL) { set_error("unknown ortho mode"); return false; }
     if (p->dtype != PFE_FP32 && p->dtype != PFE_FP64) { set_error("unknown dtype"); return false; }
     return true;
+}
+
+// Per segment, the active columns of Y0: a segment whose Y0 has trailing
+// all-zero columns is embedded in that many fewer dimensions (its zero columns
+// stay zero: zero right-hand sides, zero edge differences, and a P-update on
+// the leading block of its Gram matrix).  This is how one launch carries
+// problems of several d (the largest d, the others padded with zero columns).
+// A zero column before a nonzero one is a rank deficiency.
+template <typename T>
+pfe_status active_dims(pfe_ctx* c) {
+    const int nseg = c->nseg, d = (int)c->d;
+    int* flags = nullptr;
+    PFE_CHECK_HIP(dev_alloc((void**)&flags, sizeof(int) * (size_t)nseg * d));
+    pfe_status st = PFE_OK;
+    std::vector<int> h((size_t)nseg * d, 0);
+    do {
+        if (hipMemsetAsync(flags, 0, sizeof(int) * h.size(), c->stream) != hipSuccess) { st = PFE_E_HIP; break; }
+        for (int sg = 0; sg < nseg; ++sg) {
+            const int64_t r0 = c->g->seg_row0[sg], r1 = c->g->seg_row0[sg + 1];
+            const unsigned grid = (unsigned)std::min<int64_t>(((r1 - r0) * d + 255) / 256, 4096);
+            hipLaunchKernelGGL(k_col_flags<T>, dim3(std::max(1u, grid)), dim3(256), 0, c->stream, (const T*)c->Y, r0,
+                               r1, d, flags + (size_t)sg * d);
+        }
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(h.data(), flags, sizeof(int) * h.size(), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+            st = PFE_E_HIP;
+            break;
+        }
+    } while (0);
+    (void)dev_free(flags);
+    if (st != PFE_OK) { set_error("pfe_init: column scan of Y0 failed"); return st; }
+    c->dact_h.assign(nseg, d);
+    bool padded = false;
+    for (int sg = 0; sg < nseg; ++sg) {
+        int da = 0;
+        for (int col = 0; col < d; ++col)
+            if (h[(size_t)sg * d + col]) da = col + 1;
+        for (int col = 0; col < da; ++col)
+            if (!h[(size_t)sg * d + col]) {
+                set_error("pfe_init: Y0 has a zero column %d before a nonzero one on segment %d", col, sg);
+                return PFE_E_RANK;
+            }
+        if (da == 0) {
+            set_error("pfe_init: Y0 is zero on segment %d", sg);
+            return PFE_E_RANK;
+        }
+        c->dact_h[sg] = da;
+        padded = padded || da < d;
+    }
+    if (!padded) { c->dact_h.clear(); return PFE_OK; }
+    PFE_CHECK_HIP(dev_alloc((void**)&c->dact, sizeof(int) * nseg));
+    PFE_CHECK_HIP(hipMemcpy(c->dact, c->dact_h.data(), sizeof(int) * nseg, hipMemcpyHostToDevice));
+    return PFE_OK;
 }
 
 template <typename T>
@@ -4049,7 +4126,14 @@ pfe_status monitor_impl(pfe_ctx* c, pfe_monitors* out) {
         unsigned long long h = 0;
         PFE_CHECK_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, c->stream));
         PFE_CHECK_HIP(hipStreamSynchronize(c->stream));
-        out->split_nonzero = (double)h / (2.0 * (double)c->g->n_edges * (double)c->d);
+        // out of the 2 |E_s| d_s entries of each segment's active columns
+        double entries = 2.0 * (double)c->g->n_edges * (double)c->d;
+        if (!c->dact_h.empty()) {
+            entries = 0.0;
+            for (int sg = 0; sg < c->nseg; ++sg)
+                entries += 2.0 * (double)(c->g->seg_edge0[sg + 1] - c->g->seg_edge0[sg]) * (double)c->dact_h[sg];
+        }
+        out->split_nonzero = (double)h / entries;
     }
     return PFE_OK;
 }
@@ -4381,6 +4465,12 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
             hipMemsetAsync(c->bar, 0, 512 * sizeof(unsigned), stream) != hipSuccess ||
             hipMemsetAsync(c->bs, 0, sd, stream) != hipSuccess ||
             hipMemsetAsync(c->p, 0, nd, stream) != hipSuccess ||
+            // vectors start at zero (every phase then reads defined values,
+            // whatever launch shape ran before)
+            hipMemsetAsync(c->rhs, 0, nd, stream) != hipSuccess ||
+            hipMemsetAsync(c->rb[0], 0, nd, stream) != hipSuccess || hipMemsetAsync(c->rb[1], 0, nd, stream) != hipSuccess ||
+            hipMemsetAsync(c->wb[0], 0, nd, stream) != hipSuccess || hipMemsetAsync(c->wb[1], 0, nd, stream) != hipSuccess ||
+            hipMemsetAsync(c->sb[0], 0, nd, stream) != hipSuccess || hipMemsetAsync(c->sb[1], 0, nd, stream) != hipSuccess ||
             hipMemsetAsync(c->colbuf, 0, sizeof(double) * ncol * 5, stream) != hipSuccess ||
             hipMemsetAsync(c->colint, 0, sizeof(int) * ncol * 3, stream) != hipSuccess ||
             (c->ds && hipMemsetAsync(c->ds, 0, sd, stream) != hipSuccess) ||
@@ -4391,6 +4481,8 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
         s = (p->dtype == PFE_FP64) ? set_diag<double>(c) : set_diag<float>(c);
         if (s != PFE_OK) break;
         s = (p->dtype == PFE_FP64) ? identity_factor<double>(c) : identity_factor<float>(c);
+        if (s != PFE_OK) break;
+        s = (p->dtype == PFE_FP64) ? active_dims<double>(c) : active_dims<float>(c);
         if (s != PFE_OK) break;
         if (p->init_ortho) {
             s = (p->dtype == PFE_FP64) ? ortho_mk<double>(c, 1) : ortho_mk<float>(c, 1);

@@ -298,3 +298,60 @@ def test_autotune_restores_state_and_keeps_results():
     e = max(rel(to_np(S.get(k)), to_np(R.get(k))) for k in ("Y", "P"))
     print(f"tuned vs default rel err {e:.2e}")
     assert e <= 1e-5
+
+
+@pytest.mark.parametrize("shape", ["persistent", "strips", "rows"])
+def test_several_dimensions_in_one_launch(shape):
+    """A d-sweep in one launch: copies of one image in a block-diagonal union,
+    copy s embedded in d_s dimensions (Y0 of the largest d with the columns
+    beyond d_s set to zero).  Each copy must match the same image solved alone
+    at its d_s (GPU, FP64) and the oracle at d_s; the padded columns stay
+    exactly zero; monitors count only the active columns."""
+    from paper_1612_06496_amd import Graph, Solver
+    banner(f"several d in one launch, {shape}")
+    wl = synth.make_workload("voronoi48x40_r2", 0)
+    dims = [2, 5, 8]
+    dmax = max(dims)
+    g = oracle_graph(wl)
+    lam, r = 40.0, 4.0
+    parts = [gpu_graph(wl) for _ in dims]
+    U = Graph.union(parts)
+    Y0s = [synth.smooth_y0(wl.H, wl.W, dd, 100 + dd).astype(np.float64) for dd in dims]
+    Y0 = np.zeros((U.n, dmax))
+    row0, _ = U.segments
+    for k, (dd, y) in enumerate(zip(dims, Y0s)):
+        Y0[row0[k]:row0[k + 1], :dd] = y
+    kw = dict(lam=lam, r=r, n_inner=3, tol=1e-12, maxit=3000, fp64=True, persistent=(shape == "persistent"))
+    S = Solver(U, Y0, **kw)
+    if shape != "persistent":
+        S.set_launch_shape(persistent=False, strips=1 if shape == "strips" else 0)
+    info = S.solve(2, info=True)
+    if shape == "persistent":
+        assert info["workgroups"] > 0
+    Yg, Pg, Bg = (to_np(S.get(k)) for k in ("Y", "P", "B"))
+    mon = S.monitor()
+    print(f"monitors {mon}")
+    assert mon["constraint"] <= 1e-9
+    for k, dd in enumerate(dims):
+        sl = slice(row0[k], row0[k + 1])
+        assert np.all(Yg[sl, dd:] == 0.0) and np.all(Pg[sl, dd:] == 0.0) and np.all(Bg[sl, dd:] == 0.0)
+        Ss = Solver(parts[k], Y0s[k], **{**kw, "persistent": False})
+        Ss.solve(2)
+        eS = max(rel(Yg[sl, :dd], to_np(Ss.get("Y"))), rel(Pg[sl, :dd], to_np(Ss.get("P"))))
+        ref = O.pfe_run(g, Y0s[k], lam, r, 2, 3)
+        eO = max(rel(Yg[sl, :dd], ref.Y), rel(Pg[sl, :dd], ref.P))
+        print(f"d = {dd}: vs solo {eS:.2e}, vs oracle {eO:.2e}")
+        assert eS <= 1e-9 and eO <= 1e-9
+        Ss.close()
+    S.close()
+
+
+def test_zero_column_before_a_nonzero_one_is_rejected():
+    from paper_1612_06496_amd import Solver
+    from paper_1612_06496_amd import _lib as L
+    banner("padded columns must trail")
+    wl = synth.make_workload("voronoi48x40_r2", 0)
+    Y0 = synth.smooth_y0(wl.H, wl.W, 4, 3).astype(np.float64)
+    Y0[:, 1] = 0.0
+    with pytest.raises(L.PFEError):
+        Solver(gpu_graph(wl), Y0, lam=10.0, r=1.0, n_inner=2, fp64=True)
