@@ -348,6 +348,58 @@ def host_cpu():
             "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
+def le_init_leg(G, wl, k=32, tol=1e-12, steps=10, oracle_time=True):
+    """The Laplacian-eigenmap initialisation on the device (pfe_le_init,
+    d = the workload's d, a block of k vectors from a seeded Gaussian start,
+    FP64) timed with HIP events; then the headline measurement repeated from
+    that embedding (one untimed and `steps` timed SOC iterations, shrink-active
+    penalties from it, autotuned shape).  With oracle_time, the oracle's
+    shift-invert Lanczos on the same graph is timed on the host for context."""
+    import numpy as np
+    import torch
+
+    from paper_1612_06496_amd import Solver, le_init
+    X0 = torch.as_tensor(np.random.default_rng(5).normal(size=(wl.n, k)), device="cuda")
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    Y, mu, info = le_init(G, wl.d, X0, tol=tol, max_iter=400)
+    stop.record()
+    torch.cuda.synchronize()
+    ms_le = start.elapsed_time(stop)
+    out = {"d": wl.d, "k": k, "tol": tol, "ms": round(ms_le, 2), "iterations": info["iterations"],
+           "degree": info["degree"], "residual": float(f"{info['residual']:.3g}"),
+           "mu": [float(f"{m:.4g}") for m in mu]}
+    progress(f"LE initialisation on the GPU: {ms_le:.1f} ms")
+    S = Solver(G, Y.float(), lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=1000)
+    c = 1.0 / S.edge_quantile(0.99)
+    S.set_penalties(c, c)
+    S.autotune(trials=1)
+    S.solve(1)
+    S.stats(reset=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        S.solve(1)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    st = S.stats(reset=True)
+    S.close()
+    out["headline_from_le"] = {"lambda": c, "r": c, "ms_per_step": round(ms / steps, 4),
+                               "outer_iters_per_s": round(steps / (ms / 1e3), 1),
+                               "pcg_iters_per_solve": round(st["cg_iters_total"] / max(1, st["solves"]), 2),
+                               "launch": "persistent" if st["workgroups"] else ("strips" if st["flags"] & 2 else "multi")}
+    if oracle_time:
+        import oracle as O
+        g = O.build_grid_graph(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
+        t0 = time.perf_counter()
+        O.le_init(g, wl.d)
+        out["oracle_s"] = round(time.perf_counter() - t0, 2)
+    return out
+
+
 def d_sweep_batched_leg(wl, c, dims=(5, 10, 15, 20, 25), steps=10):
     """The same d-sweep in ONE launch per SOC iteration: copies of the image in
     a block-diagonal union, copy k embedded in dims[k] dimensions (its initial
@@ -476,6 +528,8 @@ def main():
                     help="Split-Bregman iterations of the timed Stage II run after the SOC iterations (0: skip)")
     ap.add_argument("--kmeans-iters", type=int, default=100,
                     help="cap of the timed k-means (Lloyd) run on the final embedding, single images (0: skip)")
+    ap.add_argument("--no-le", action="store_true",
+                    help="skip the Laplacian-eigenmap initialisation leg (and the headline from its embedding)")
     ap.add_argument("--no-d-sweep", action="store_true",
                     help="skip the SOC-iteration rate at d = 5, 10, 15, 20, 25 on the headline image")
     ap.add_argument("--workload", default=WORKLOAD,
@@ -603,6 +657,8 @@ def main():
         line["kmeans"] = {"clusters": K, "iterations": kit, "ms": round(ms3, 3),
                           "ms_per_iteration": round(ms3 / max(1, kit), 4)}
         progress(f"k-means, {kit} Lloyd iterations: {ms3:.1f} ms")
+    if not args.no_le and default:
+        line["le_init"] = le_init_leg(G, wl, oracle_time=not args.no_cpu_baseline)
     if not args.no_d_sweep and default:
         line["d_sweep"] = d_sweep_leg(G, wl)
         batched = d_sweep_batched_leg(wl, c)

@@ -408,6 +408,35 @@ pfe_status pfe_edge_quantile(pfe_ctx* c, double q, double* out);
 
 void pfe_destroy_ctx(pfe_ctx* c);
 
+/* ---- Laplacian-eigenmap initialisation ----------------------------------------
+ * The spectral embedding the method starts from (Sec. I): the solutions of the
+ * generalised eigenproblem (D - W) y = mu D y with the d smallest nonzero mu,
+ * computed on the device in FP64 for a graph built by pfe_build_graph (a single
+ * graph, not a union).  Chebyshev-filtered subspace iteration on the normalised
+ * adjacency D^{-1/2} W D^{-1/2} with a block of k vectors (d <= k <= 32; more
+ * guard vectors than d speed up clustered spectra), the trivial solution
+ * (mu = 0) projected out exactly, Rayleigh-Ritz by Jacobi rotations.
+ *   X0       device, n x k doubles row-major: the starting block (the caller's
+ *            random draw), must have full rank after removing the trivial vector
+ *   tol      stop when every one of the d wanted Ritz pairs has
+ *            ||N x - theta x|| <= tol (x = D^{1/2} y with unit norm)
+ *   Y        device, n x d doubles: y_i with y_i^T D y_i = 1, ordered by
+ *            increasing mu, each column's entry of largest magnitude (lowest
+ *            row on ties) positive
+ *   mu       host, d doubles (may be null)
+ * PFE_E_NOCONV after max_iter outer iterations without reaching tol (Y and mu
+ * hold the last iterate); PFE_E_RANK if the block loses rank; PFE_E_ARG for
+ * bad sizes.  Allocates its work space (about 3 n k doubles) for the call and
+ * synchronises the stream. */
+typedef struct {
+    int32_t iterations;      /* outer (filter + Rayleigh-Ritz) iterations run */
+    int32_t degree;          /* Chebyshev degree of the last filter */
+    double residual;         /* largest ||N x - theta x|| over the d wanted pairs */
+    int32_t converged;
+} pfe_le_info;
+pfe_status pfe_le_init(const pfe_graph* g, int d, const double* X0, int k, double tol, int max_iter, double* Y,
+                       double* mu, pfe_le_info* info, hipStream_t stream);
+
 /* ---- k-means on an embedding ----------------------------------------------------
  * The segmentation experiment (Sec. IV) clusters the embedding by k-means.
  * Lloyd iterations on the n rows of Y (device, n x d row-major, dtype

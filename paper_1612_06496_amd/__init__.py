@@ -8,7 +8,7 @@ Graph and Solver load libpfe.so on first use and raise ImportError if it has
 not been built (there is no fallback implementation).
 """
 
-__all__ = ["Graph", "Solver", "Mpnn", "kmeans", "use_torch_allocator", "live_allocations", "close_all"]
+__all__ = ["Graph", "Solver", "Mpnn", "kmeans", "le_init", "use_torch_allocator", "live_allocations", "close_all"]
 
 
 def __getattr__(name):

@@ -66,6 +66,11 @@ class pfe_monitors(C.Structure):
                 ("split", C.c_double), ("orthogonality", C.c_double), ("split_nonzero", C.c_double)]
 
 
+class pfe_le_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("degree", C.c_int32), ("residual", C.c_double),
+                ("converged", C.c_int32)]
+
+
 class pfe_tune_result(C.Structure):
     _fields_ = [("persistent", C.c_int32), ("team", C.c_int32), ("row_cache", C.c_int32),
                 ("workgroups", C.c_int32), ("ms", C.c_double), ("chosen", C.c_int32),
@@ -114,6 +119,7 @@ SIGNATURES = {
     "pfe_set_allocator": (_S, [_P, _P, _P]),
     "pfe_live_allocations": (C.c_int64, []),
     "pfe_kmeans": (_S, [_P, C.c_int64, C.c_int, C.c_int, _P, C.c_int, C.c_int, _P, _P, C.POINTER(C.c_int32), _P]),
+    "pfe_le_init": (_S, [_P, C.c_int, _P, C.c_int, C.c_double, C.c_int, _P, _P, C.POINTER(pfe_le_info), _P]),
     "pfe_kmeans_noalloc": (_S, [_P, C.c_int64, C.c_int, C.c_int, _P, C.c_int, C.c_int, _P, _P, C.POINTER(C.c_int32),
                                 _P]),
     "pfe_status_string": (C.c_char_p, [C.c_int]),

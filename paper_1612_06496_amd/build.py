@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpfe.so")
 OBJ = os.path.join(ROOT, "_build")
 
-SOURCES = ["alloc.hip", "graph.hip", "solver.hip", "learned.hip", "kmeans.hip"]
+SOURCES = ["alloc.hip", "graph.hip", "solver.hip", "learned.hip", "kmeans.hip", "eigen.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -52,6 +52,23 @@ def kmeans(Y, C0, max_iter: int = 100, stream: Optional[torch.cuda.Stream] = Non
     return labels, cen, iters.value
 
 
+def le_init(graph: "Graph", d: int, X0, tol: float = 1e-10, max_iter: int = 200,
+            stream: Optional[torch.cuda.Stream] = None):
+    """Laplacian-eigenmap embedding of a graph (pfe_le_init): the d smallest
+    nontrivial solutions of (D - W) y = mu D y from the starting block X0
+    (n x k, k >= d, the caller's random draw).  Returns (Y float64 n x d on the
+    device, mu numpy array, info dict); raises on failure (PFE_E_NOCONV too)."""
+    x0 = _dev(X0, torch.float64)
+    n, k = x0.shape
+    Y = torch.empty((n, d), dtype=torch.float64, device="cuda")
+    mu = np.empty(d, dtype=np.float64)
+    inf = L.pfe_le_info()
+    L.check(L.lib.pfe_le_init(graph._h, int(d), x0.data_ptr(), int(k), float(tol), int(max_iter), Y.data_ptr(),
+                              mu.ctypes.data, C.byref(inf), _stream_handle(stream)), "pfe_le_init")
+    return Y, mu, dict(iterations=inf.iterations, degree=inf.degree, residual=inf.residual,
+                       converged=inf.converged)
+
+
 _TORCH_ALLOC = None
 
 # Library objects still open.  Teardown is explicit: close() destroys an
