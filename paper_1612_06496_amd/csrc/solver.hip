@@ -95,8 +95,9 @@ struct KA {
     T* Y;
     T* P;
     T* B;
-    T* bs;             // Split-Bregman b per slot
-    T* ds;             // Split-Bregman d per slot (keep_split)
+    T* bsb[2];         // Split-Bregman b: edge update m reads bsb[m & 1] and writes bsb[(m + 1) & 1]
+                       // (one buffer, updated in place, with per-slot storage)
+    T* ds;             // Split-Bregman d (keep_split), stored like b
     T* rhs;
     T* rb[2];          // r, double-buffered across iterations
     T* wb[2];          // w = A u
@@ -121,6 +122,8 @@ struct KA {
     int keep_split;
     int store_rhs;
     int b_zero;        // first edge update of a SOC iteration: b starts from 0
+    int bpar;          // parity m & 1 of this launch's edge update (which b buffer it reads)
+    int bhalf;         // b, d once per undirected edge (pixel stencils) instead of per slot
     int ortho;         // PFE_POLAR / PFE_CHOL
     int sten;          // ELL slots in pixel-stencil order (lower neighbours first)
     const int* dact;   // per segment: active columns (the leading ones; the others stay zero), or null (all d)
@@ -163,6 +166,28 @@ __device__ __forceinline__ void row_slots(const KA<T>& a, int i, int& s0, int& c
     if constexpr (KC > 0) { s0 = i; cnt = KC; stride = a.n; }
     else if (a.ell_K > 0) { s0 = i; cnt = a.ell_K; stride = a.n; }
     else { s0 = a.rowptr[i]; cnt = a.rowptr[i + 1] - s0; stride = 1; }
+}
+
+// Storage of the split variables b and d.  Per directed slot, "row minus
+// column", for every layout; on pixel-stencil layouts (bhalf) once per
+// undirected edge instead: on the lower-neighbour slot k < K/2 of the edge's
+// later pixel i (orientation y_i - y_j).  The earlier pixel j reaches it
+// through its mirrored upper slot K-1-k with the opposite sign: the shrink and
+// the clamp are odd and w (y_j - y_i) is exactly -(w (y_i - y_j)), so both
+// endpoints form exactly opposite values from the same stored b, and only the
+// owner writes (into the other buffer of the pair, as the other endpoint reads
+// the old value in the same pass).  Returns the storage slot of slot k of row
+// i (neighbour j), and whether this row owns it.
+template <int KC, typename T>
+__device__ __forceinline__ size_t split_slot(const KA<T>& a, int i, int k, int j, size_t sl, bool& owner) {
+    if constexpr (KC > 0) {
+        if (a.bhalf) {
+            owner = k < KC / 2;
+            return owner ? sl : (size_t)(KC - 1 - k) * a.n + j;
+        }
+    }
+    owner = true;
+    return sl;
 }
 
 // Z = D^{1/2} Y + B of the P-update
@@ -339,9 +364,11 @@ __device__ __forceinline__ RowCache<T> fill_row_cache(const KA<T>& a, int lb, un
 //   RHS: rhs from the stored b and d
 // then (unless RHS) r0 = rhs - A x, with FP64 partials of rhs^T rhs and r0^T r0.
 template <int KC = 0, int GM = 8, bool LC = false, typename T>
-__device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, int do_r0, int b_zero, double* sh,
+__device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, int do_r0, int b_zero, int par, double* sh,
                                             const RowCache<T>& rc = RowCache<T>()) {
     const int d = a.d, R = a.R, t = threadIdx.x;
+    const T* bread = a.bsb[par & 1];
+    T* bwrite = a.bsb[(par & 1) ^ 1];
     const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     double acc[2] = {0.0, 0.0};
     T* r0 = a.rb[0];
@@ -360,13 +387,20 @@ __device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, in
                 for (int k0 = 0; k0 < cnt; k0 += G) {
                     int jj[G];
                     T ww[G], yj[G], bo[G], xj[G];
+                    size_t ss[G];
+                    bool own[G];
 #pragma unroll
                     for (int k = 0; k < G; ++k) {
                         const int sl = s0 + (k0 + k) * st;
                         const int cix = (p * KC + k0 + k) * R + rl;
                         jj[k] = LC ? rc.col[cix] : a.scol[sl];
                         ww[k] = LC ? rc.w[cix] : a.sw[sl];
-                        bo[k] = b_zero ? T(0) : a.bs[(size_t)sl * d + c];
+                        ss[k] = split_slot<KC>(a, i, k0 + k, jj[k], (size_t)sl, own[k]);
+                        bo[k] = T(0);
+                        if (!b_zero) {
+                            const T b = bread[ss[k] * d + c];
+                            bo[k] = own[k] ? b : -b;
+                        }
                     }
 #pragma unroll
                     for (int k = 0; k < G; ++k) {
@@ -376,12 +410,14 @@ __device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, in
                     }
 #pragma unroll
                     for (int k = 0; k < G; ++k) {
-                        const size_t es = (size_t)(s0 + (k0 + k) * st) * d + c;
+                        const size_t es = ss[k] * d + c;
                         const T tv = fma_t(ww[k], yi - yj[k], bo[k]);
                         const T dv = shrink(tv, a.gamma);
                         const T bn = tv - dv;
-                        a.bs[es] = bn;
-                        if (a.keep_split) a.ds[es] = dv;
+                        if (own[k]) {
+                            bwrite[es] = bn;
+                            if (a.keep_split) a.ds[es] = dv;
+                        }
                         accR = fma_t(ww[k], dv - bn, accR);
                         if (do_r0) accA = fma_t(mul_t(ww[k], ww[k]), xj[k], accA);
                     }
@@ -396,11 +432,11 @@ __device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, in
                     const size_t ej = (size_t)j * d + c;
                     const T yj = a.Y[ej];
                     const size_t es = (size_t)s * d + c;
-                    const T bold = b_zero ? T(0) : a.bs[es];
+                    const T bold = b_zero ? T(0) : bread[es];
                     const T tv = fma_t(ww, yi - yj, bold);
                     const T dv = shrink(tv, a.gamma);
                     const T bn = tv - dv;
-                    a.bs[es] = bn;
+                    bwrite[es] = bn;
                     if (a.keep_split) a.ds[es] = dv;
                     accR = fma_t(ww, dv - bn, accR);
                     if (do_r0) accA = fma_t(mul_t(ww, ww), a.x[ej], accA);
@@ -409,8 +445,10 @@ __device__ __forceinline__ void ph_residual(const KA<T>& a, int lb, int mode, in
 #pragma unroll kSlotUnroll<KC>
                 for (int k = 0; k < cnt; ++k) {
                     const int s = s0 + k * st;
-                    const size_t es = (size_t)s * d + c;
-                    accR = fma_t(a.sw[s], a.ds[es] - a.bs[es], accR);
+                    bool own;
+                    const size_t es = split_slot<KC>(a, i, k, a.scol[s], (size_t)s, own) * d + c;
+                    const T dmb = a.ds[es] - bread[es];
+                    accR = fma_t(a.sw[s], own ? dmb : -dmb, accR);
                 }
             } else if (do_r0 && KC > 0) {
                 constexpr int G = slot_group<KC, GM>();
@@ -1170,6 +1208,17 @@ __device__ __forceinline__ void st_eu(const KA<T>& a, int lb, double* sh) {
     const int d = a.d;
     const StripLane ln(g, d, Sten<KC>::rho);
     const int b_zero = a.b_zero;
+    const T* bread = a.bsb[a.bpar & 1];
+    T* bwrite = a.bsb[(a.bpar & 1) ^ 1];
+    // b of slot k of row i (the stored value, signed for this row)
+    auto b_of = [&](int i, int k) {
+        if (b_zero) return T(0);
+        const size_t sl = (size_t)k * a.n + i;
+        bool own;
+        const size_t ss = split_slot<KC>(a, i, k, (a.bhalf && k >= KC / 2) ? a.scol[sl] : i, sl, own);
+        const T b = bread[ss * d + ln.c];
+        return own ? b : -b;
+    };
     struct Raw { T y; };
     struct Own { T split, ww[PW ? KC : 1], bo[PW ? KC : 1]; };
     strip_walk<KC>(a, g, ln, reinterpret_cast<T*>(sh),
@@ -1181,9 +1230,8 @@ __device__ __forceinline__ void st_eu(const KA<T>& a, int lb, double* sh) {
             if constexpr (PW) {
 #pragma unroll
                 for (int k = 0; k < KC; ++k) {
-                    const size_t sl = (size_t)k * a.n + i;
-                    o.ww[k] = a.sw[sl];
-                    o.bo[k] = b_zero ? T(0) : a.bs[sl * d + ln.c];
+                    o.ww[k] = a.sw[(size_t)k * a.n + i];
+                    o.bo[k] = b_of(i, k);
                 }
             }
             return o;
@@ -1194,12 +1242,14 @@ __device__ __forceinline__ void st_eu(const KA<T>& a, int lb, double* sh) {
             for (int k = 0; k < KC; ++k) {
                 const size_t sl = (size_t)k * a.n + i;
                 const T wk = PW ? own.ww[PW ? k : 0] : a.sw[sl];
-                const T bo = PW ? own.bo[PW ? k : 0] : (b_zero ? T(0) : a.bs[sl * d + ln.c]);
+                const T bo = PW ? own.bo[PW ? k : 0] : b_of(i, k);
                 const T tv = fma_t(wk, v.y - nb(k), bo);
                 const T dv = shrink(tv, a.gamma);
                 const T bn = tv - dv;
-                a.bs[sl * d + ln.c] = bn;
-                if (a.keep_split) a.ds[sl * d + ln.c] = dv;
+                if (!a.bhalf || k < KC / 2) {
+                    bwrite[sl * d + ln.c] = bn;
+                    if (a.keep_split) a.ds[sl * d + ln.c] = dv;
+                }
                 accR = fma_t(wk, dv - bn, accR);
             }
             a.rhs[e] = fma_t(a.c_off, accR, own.split);
@@ -2455,7 +2505,7 @@ template <typename T, int KC>
 __global__ void __launch_bounds__(kBlock) k_residual(KA<T> a, int ph, int do_r0) {
     __shared__ double sh[kSmemDoubles];
     const int lb = logical_block(a.nblk);
-    ph_residual<KC>(a, lb, ph, do_r0, a.b_zero, sh);
+    ph_residual<KC>(a, lb, ph, do_r0, a.b_zero, a.bpar, sh);
     if (do_r0 && last_block(a.bar + kBarLast, a.nblk)) fin_res(a, sh, false);
 }
 
@@ -2719,7 +2769,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
         auto gbuf = [&]() { double* gp = a.gpart + (size_t)par * kGroupStride; par ^= 1; return gp; };
         for (int outer = 0; outer < plan.n_outer; ++outer) {
             for (int l = l0; l < plan.n_inner; ++l) {
-                ph_residual<KC, 4, LC>(a, lb, (l == 0) ? PH_E0 : PH_EU, 1, (l == 1) ? 1 : 0, sh, rc);
+                ph_residual<KC, 4, LC>(a, lb, (l == 0) ? PH_E0 : PH_EU, 1, (l == 1) ? 1 : 0, (l - 1) & 1, sh, rc);
                 double* gp = gbuf();
                 if (!grid_sync(a.bar, nb, S, nbar, [&](unsigned g) { group_reduce(a, g, d, 2, sh, gp); }, NoFin{})) return;
                 lfin_res(a, L, gp, sh);
@@ -2757,7 +2807,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
     }
     for (int outer = 0; outer < plan.n_outer; ++outer) {
         for (int l = l0; l < plan.n_inner; ++l) {
-            ph_residual<KC, 4, LC>(a, lb, (l == 0) ? PH_E0 : PH_EU, 1, (l == 1) ? 1 : 0, sh, rc);
+            ph_residual<KC, 4, LC>(a, lb, (l == 0) ? PH_E0 : PH_EU, 1, (l == 1) ? 1 : 0, (l - 1) & 1, sh, rc);
             if (!grid_sync(a.bar, nb, S, nbar, NoFin{}, [&] { fin_res(a, sh, false); })) return;
             if (!ld_flag(&S->done)) {
                 ph_w0<KC, 4, LC>(a, lb, sh, rc);
@@ -2843,6 +2893,38 @@ __global__ void k_slots_to_edges(KA<T> a, const int* __restrict__ seid, const T*
     }
 }
 
+// per-edge storage (lower slots of the later pixel, orientation later minus
+// earlier) <-> per-undirected-edge blocks (earlier minus later): a sign flip
+template <typename T>
+__global__ void k_half_to_edges(KA<T> a, const int* __restrict__ seid, const T* __restrict__ s, T* __restrict__ e) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int d = a.d;
+    for (int k = 0; k < a.ell_K / 2; ++k) {
+        const size_t sl = (size_t)k * a.n + i;
+        if (seid[sl] < 0) continue;
+        const size_t eo = (size_t)seid[sl] * d, so = sl * d;
+        for (int c = 0; c < d; ++c) e[eo + c] = -s[so + c];
+    }
+}
+
+template <typename T>
+__global__ void k_edges_to_half(KA<T> a, const int* __restrict__ seid, const T* __restrict__ e, T* __restrict__ s) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int d = a.d;
+    for (int k = 0; k < a.ell_K / 2; ++k) {
+        const size_t sl = (size_t)k * a.n + i;
+        const size_t so = sl * d;
+        if (seid[sl] < 0) {
+            for (int c = 0; c < d; ++c) s[so + c] = T(0);
+            continue;
+        }
+        const size_t eo = (size_t)seid[sl] * d;
+        for (int c = 0; c < d; ++c) s[so + c] = -e[eo + c];
+    }
+}
+
 template <typename T>
 __global__ void k_edges_to_slots(KA<T> a, const int* __restrict__ seid, const T* __restrict__ e,
                                  T* __restrict__ s) {
@@ -2864,12 +2946,20 @@ __global__ void k_edges_to_slots(KA<T> a, const int* __restrict__ seid, const T*
     }
 }
 
-// flags[c] = 1 when column c of rows [r0, r1) of Y has a nonzero entry
+// mask bit c set when column c (< 32) of rows [r0, r1) of Y has a nonzero
+// entry: a bit mask per thread, OR-reduced in LDS, one atomic per workgroup
 template <typename T>
-__global__ void k_col_flags(const T* __restrict__ Y, int64_t r0, int64_t r1, int d, int* __restrict__ flags) {
+__global__ void k_col_flags(const T* __restrict__ Y, int64_t r0, int64_t r1, int d, unsigned* __restrict__ mask) {
+    __shared__ unsigned s_mask;
+    if (threadIdx.x == 0) s_mask = 0u;
+    __syncthreads();
     const size_t ne = (size_t)(r1 - r0) * d;
+    unsigned m = 0u;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (size_t)gridDim.x * blockDim.x)
-        if (Y[(size_t)r0 * d + e] != T(0)) atomicOr(&flags[e % d], 1);
+        if (Y[(size_t)r0 * d + e] != T(0)) m |= 1u << (unsigned)(e % d);
+    if (m) atomicOr(&s_mask, m);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_mask) atomicOr(mask, s_mask);
 }
 
 template <typename T>
@@ -3250,6 +3340,9 @@ struct pfe_ctx {
     int part_blocks = 0;     // workgroups the partial-sum buffer holds
     void* Y = nullptr; void* P = nullptr; void* B = nullptr;
     void* bs = nullptr; void* ds = nullptr;
+    void* bs2 = nullptr;     // second b buffer (per-edge storage: read one, write the other)
+    int bhalf = 0;           // b, d once per undirected edge (pixel stencils), else per slot
+    int64_t sslots = 0;      // storage slots of b and d
     void* rhs = nullptr; void* p = nullptr;
     void* rb[2] = {nullptr, nullptr};
     void* wb[2] = {nullptr, nullptr};
@@ -3488,8 +3581,11 @@ KA<T> make_args(pfe_ctx* c, const Partition& pt) {
     a.Y = (T*)c->Y;
     a.P = (T*)c->P;
     a.B = (T*)c->B;
-    a.bs = (T*)c->bs;
+    a.bsb[0] = (T*)c->bs;
+    a.bsb[1] = c->bs2 ? (T*)c->bs2 : (T*)c->bs;
     a.ds = (T*)c->ds;
+    a.bhalf = c->bhalf;
+    a.bpar = 0;
     a.rhs = (T*)c->rhs;
     for (int k = 0; k < 2; ++k) {
         a.rb[k] = (T*)c->rb[k];
@@ -3897,6 +3993,7 @@ pfe_status inner_at(pfe_ctx* c, int l) {
     KA<T> b = (as.geo && c->g->ell_K <= 8) ? as : a;
     b.store_rhs = 1;
     b.b_zero = (l == 0);
+    b.bpar = l & 1;
     PFE_TRY(launch_phase(c, b, PH_EU, 0, 0));
     return PFE_OK;
 }
@@ -4021,7 +4118,7 @@ pfe_status set_diag(pfe_ctx* c) {
 }
 
 void free_ctx(pfe_ctx* c) {
-    void* bufs[] = {c->Y, c->P, c->B, c->bs, c->ds, c->rhs, c->p, c->rb[0], c->rb[1], c->wb[0], c->wb[1],
+    void* bufs[] = {c->Y, c->P, c->B, c->bs, c->bs2, c->ds, c->rhs, c->p, c->rb[0], c->rb[1], c->wb[0], c->wb[1],
                     c->sb[0], c->sb[1], c->diagA, c->invdiag, c->sqrtD, c->isqrtD, c->isq, c->gval, c->gdiag,
                     c->zl, c->y1, c->xbak, c->dact, c->part, c->gpart,
                     c->Tm, c->colbuf, c->colint, c->S, c->bar, c->hist};
@@ -4057,20 +4154,20 @@ bool params_ok(const pfe_params* p, int64_t n) {
 template <typename T>
 pfe_status active_dims(pfe_ctx* c) {
     const int nseg = c->nseg, d = (int)c->d;
-    int* flags = nullptr;
-    PFE_CHECK_HIP(dev_alloc((void**)&flags, sizeof(int) * (size_t)nseg * d));
+    unsigned* flags = nullptr;
+    PFE_CHECK_HIP(dev_alloc((void**)&flags, sizeof(unsigned) * (size_t)nseg));
     pfe_status st = PFE_OK;
-    std::vector<int> h((size_t)nseg * d, 0);
+    std::vector<unsigned> h((size_t)nseg, 0u);
     do {
-        if (hipMemsetAsync(flags, 0, sizeof(int) * h.size(), c->stream) != hipSuccess) { st = PFE_E_HIP; break; }
+        if (hipMemsetAsync(flags, 0, sizeof(unsigned) * h.size(), c->stream) != hipSuccess) { st = PFE_E_HIP; break; }
         for (int sg = 0; sg < nseg; ++sg) {
             const int64_t r0 = c->g->seg_row0[sg], r1 = c->g->seg_row0[sg + 1];
-            const unsigned grid = (unsigned)std::min<int64_t>(((r1 - r0) * d + 255) / 256, 4096);
+            const unsigned grid = (unsigned)std::min<int64_t>(((r1 - r0) * d + 255) / 256, 1024);
             hipLaunchKernelGGL(k_col_flags<T>, dim3(std::max(1u, grid)), dim3(256), 0, c->stream, (const T*)c->Y, r0,
-                               r1, d, flags + (size_t)sg * d);
+                               r1, d, flags + sg);
         }
         if (hipGetLastError() != hipSuccess ||
-            hipMemcpyAsync(h.data(), flags, sizeof(int) * h.size(), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipMemcpyAsync(h.data(), flags, sizeof(unsigned) * h.size(), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
             hipStreamSynchronize(c->stream) != hipSuccess) {
             st = PFE_E_HIP;
             break;
@@ -4083,9 +4180,9 @@ pfe_status active_dims(pfe_ctx* c) {
     for (int sg = 0; sg < nseg; ++sg) {
         int da = 0;
         for (int col = 0; col < d; ++col)
-            if (h[(size_t)sg * d + col]) da = col + 1;
+            if ((h[sg] >> col) & 1u) da = col + 1;
         for (int col = 0; col < da; ++col)
-            if (!h[(size_t)sg * d + col]) {
+            if (!((h[sg] >> col) & 1u)) {
                 set_error("pfe_init: Y0 has a zero column %d before a nonzero one on segment %d", col, sg);
                 return PFE_E_RANK;
             }
@@ -4118,7 +4215,7 @@ pfe_status monitor_impl(pfe_ctx* c, pfe_monitors* out) {
     if (c->ds && c->g->n_edges > 0) {
         unsigned long long* cnt = reinterpret_cast<unsigned long long*>(c->hist);
         PFE_CHECK_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), c->stream));
-        const int64_t ns = c->g->nslot;
+        const int64_t ns = c->sslots;
         const unsigned grid = (unsigned)std::min<int64_t>((ns + 255) / 256, 2048);
         hipLaunchKernelGGL(k_count_nonzero<T>, dim3(grid), dim3(256), 0, c->stream, ns, (int)c->d, c->g->s_eid,
                            (const T*)c->ds, cnt);
@@ -4126,12 +4223,14 @@ pfe_status monitor_impl(pfe_ctx* c, pfe_monitors* out) {
         unsigned long long h = 0;
         PFE_CHECK_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, c->stream));
         PFE_CHECK_HIP(hipStreamSynchronize(c->stream));
-        // out of the 2 |E_s| d_s entries of each segment's active columns
-        double entries = 2.0 * (double)c->g->n_edges * (double)c->d;
+        // out of the entries of each segment's active columns (each edge stored
+        // once per direction with per-slot storage, once with per-edge storage)
+        const double per_edge = c->bhalf ? 1.0 : 2.0;
+        double entries = per_edge * (double)c->g->n_edges * (double)c->d;
         if (!c->dact_h.empty()) {
             entries = 0.0;
             for (int sg = 0; sg < c->nseg; ++sg)
-                entries += 2.0 * (double)(c->g->seg_edge0[sg + 1] - c->g->seg_edge0[sg]) * (double)c->dact_h[sg];
+                entries += per_edge * (double)(c->g->seg_edge0[sg + 1] - c->g->seg_edge0[sg]) * (double)c->dact_h[sg];
         }
         out->split_nonzero = (double)h / entries;
     }
@@ -4185,8 +4284,12 @@ template <typename T>
 pfe_status split_to_edges(pfe_ctx* c, const void* src, void* dst) {
     KA<T> a = make_args<T>(c, c->pm);
     const int n = (int)c->n;
-    hipLaunchKernelGGL(k_slots_to_edges<T>, dim3((n + 255) / 256), dim3(256), 0, c->stream, a, c->g->s_eid,
-                       (const T*)src, (T*)dst);
+    if (c->bhalf)
+        hipLaunchKernelGGL(k_half_to_edges<T>, dim3((n + 255) / 256), dim3(256), 0, c->stream, a, c->g->s_eid,
+                           (const T*)src, (T*)dst);
+    else
+        hipLaunchKernelGGL(k_slots_to_edges<T>, dim3((n + 255) / 256), dim3(256), 0, c->stream, a, c->g->s_eid,
+                           (const T*)src, (T*)dst);
     PFE_CHECK_HIP(hipGetLastError());
     return PFE_OK;
 }
@@ -4195,8 +4298,12 @@ template <typename T>
 pfe_status edges_to_split(pfe_ctx* c, const void* src, void* dst) {
     KA<T> a = make_args<T>(c, c->pm);
     const int n = (int)c->n;
-    hipLaunchKernelGGL(k_edges_to_slots<T>, dim3((n + 255) / 256), dim3(256), 0, c->stream, a, c->g->s_eid,
-                       (const T*)src, (T*)dst);
+    if (c->bhalf)
+        hipLaunchKernelGGL(k_edges_to_half<T>, dim3((n + 255) / 256), dim3(256), 0, c->stream, a, c->g->s_eid,
+                           (const T*)src, (T*)dst);
+    else
+        hipLaunchKernelGGL(k_edges_to_slots<T>, dim3((n + 255) / 256), dim3(256), 0, c->stream, a, c->g->s_eid,
+                           (const T*)src, (T*)dst);
     PFE_CHECK_HIP(hipGetLastError());
     return PFE_OK;
 }
@@ -4294,8 +4401,12 @@ pfe_status factor_to_edges(pfe_ctx* c, void* edge_vals, void* diag) {
 template <typename T>
 pfe_status rebuild_rhs(pfe_ctx* c) {
     KA<T> a = make_args<T>(c, c->pm);
+    a.bpar = c->inner & 1;     // the buffer holding b after c->inner edge updates
     return launch_phase(c, a, PH_RHS, 0, 0);
 }
+
+// the b buffer holding the current b (after c->inner edge updates)
+inline void* current_b(pfe_ctx* c) { return ((c->inner & 1) && c->bs2) ? c->bs2 : c->bs; }
 
 // n_outer SOC iterations in the context's current launch shape
 template <typename T>
@@ -4364,7 +4475,11 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
         }
     }
     const size_t nd = (size_t)c->n * c->d * c->esz;
-    const size_t sd = (size_t)(g->nslot + 1) * c->d * c->esz;
+    // b and d once per undirected edge on pixel stencils (lower slots), else per slot
+    c->bhalf = (g->stencil && (g->ell_K == 4 || g->ell_K == 8 || g->ell_K == 24)) ? 1 : 0;
+    if (const char* ev = getenv("PFE_SPLIT_PER_SLOT")) if (atoi(ev)) c->bhalf = 0;   // layout experiments
+    c->sslots = c->bhalf ? (int64_t)(g->ell_K / 2) * g->n : g->nslot;
+    const size_t sd = (size_t)(c->sslots + 1) * c->d * c->esz;
     const size_t nv = (size_t)c->n * c->esz;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) { delete c; set_error("hipGetDeviceProperties failed"); return PFE_E_HIP; }
@@ -4433,6 +4548,7 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
 #define ALLOC(ptr, bytes) do { if (e == hipSuccess) e = dev_alloc((void**)&(ptr), (bytes)); } while (0)
     ALLOC(c->Y, nd); ALLOC(c->P, nd); ALLOC(c->B, nd);
     ALLOC(c->bs, sd);
+    if (c->bhalf) ALLOC(c->bs2, sd);
     if (p->keep_split) ALLOC(c->ds, sd);
     ALLOC(c->rhs, nd); ALLOC(c->p, nd);
     for (int k = 0; k < 2; ++k) { ALLOC(c->rb[k], nd); ALLOC(c->wb[k], nd); ALLOC(c->sb[k], nd); }
@@ -4464,6 +4580,7 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
         if (hipMemsetAsync(c->S, 0, sizeof(Scal), stream) != hipSuccess ||
             hipMemsetAsync(c->bar, 0, 512 * sizeof(unsigned), stream) != hipSuccess ||
             hipMemsetAsync(c->bs, 0, sd, stream) != hipSuccess ||
+            (c->bs2 && hipMemsetAsync(c->bs2, 0, sd, stream) != hipSuccess) ||
             hipMemsetAsync(c->p, 0, nd, stream) != hipSuccess ||
             // vectors start at zero (every phase then reads defined values,
             // whatever launch shape ran before)
@@ -4786,7 +4903,7 @@ pfe_status pfe_get(pfe_ctx* c, int which, void* dst) {
         }
         case PFE_BSPLIT:
         case PFE_DSPLIT: {
-            void* src = (which == PFE_BSPLIT) ? c->bs : c->ds;
+            void* src = (which == PFE_BSPLIT) ? current_b(c) : c->ds;
             if (!src) { set_error("pfe_get: split variable d not kept (keep_split = 0)"); return PFE_E_STATE; }
             if (c->inner == 0) {
                 // b and d restart from zero at every SOC iteration
@@ -4812,7 +4929,7 @@ pfe_status pfe_set(pfe_ctx* c, int which, const void* src) {
         case PFE_B: PFE_CHECK_HIP(hipMemcpyAsync(c->B, src, nd, hipMemcpyDeviceToDevice, st)); break;
         case PFE_BSPLIT:
         case PFE_DSPLIT: {
-            void* dstp = (which == PFE_BSPLIT) ? c->bs : c->ds;
+            void* dstp = (which == PFE_BSPLIT) ? current_b(c) : c->ds;
             if (!dstp) { set_error("pfe_set: split variable d not kept (keep_split = 0)"); return PFE_E_STATE; }
             PFE_TRY(c->esz == 8 ? edges_to_split<double>(c, src, dstp) : edges_to_split<float>(c, src, dstp));
             break;
@@ -4835,10 +4952,19 @@ pfe_status pfe_set_inner_index(pfe_ctx* c, int inner_index) {
     if (!c) { set_error("null context"); return PFE_E_ARG; }
     if (inner_index < 0 || inner_index > c->prm.n_inner) { set_error("inner index out of range"); return PFE_E_ARG; }
     if (inner_index > 0 && !c->ds) { set_error("resuming inside a SOC iteration needs keep_split = 1"); return PFE_E_STATE; }
+    if (inner_index > 0 && c->bs2 && ((inner_index ^ c->inner) & 1)) {
+        // the b buffer of the new position holds the current b
+        const size_t sd = (size_t)(c->sslots + 1) * c->d * c->esz;
+        void* from = current_b(c);
+        void* to = (from == c->bs) ? c->bs2 : c->bs;
+        PFE_CHECK_HIP(hipMemcpyAsync(to, from, sd, hipMemcpyDeviceToDevice, c->stream));
+    }
     c->inner = inner_index;
     if (inner_index == 0) {
-        PFE_CHECK_HIP(hipMemsetAsync(c->bs, 0, (size_t)(c->g->nslot + 1) * c->d * c->esz, c->stream));
-        if (c->ds) PFE_CHECK_HIP(hipMemsetAsync(c->ds, 0, (size_t)(c->g->nslot + 1) * c->d * c->esz, c->stream));
+        const size_t sd = (size_t)(c->sslots + 1) * c->d * c->esz;
+        PFE_CHECK_HIP(hipMemsetAsync(c->bs, 0, sd, c->stream));
+        if (c->bs2) PFE_CHECK_HIP(hipMemsetAsync(c->bs2, 0, sd, c->stream));
+        if (c->ds) PFE_CHECK_HIP(hipMemsetAsync(c->ds, 0, sd, c->stream));
     } else {
         PFE_TRY(c->esz == 8 ? rebuild_rhs<double>(c) : rebuild_rhs<float>(c));
     }

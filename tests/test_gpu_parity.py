@@ -147,20 +147,23 @@ def test_pcg_zero_rhs_column_and_noconv():
 STEP_CASES = [("voronoi96x80_8nbr", False), ("voronoi64_4nbr", True), ("edges", False)]
 
 
+@pytest.mark.parametrize("k_in", [1, 2])
 @pytest.mark.parametrize("name,fp64", STEP_CASES)
-def test_inner_step_parity(name, fp64):
+def test_inner_step_parity(name, fp64, k_in):
+    """One Split-Bregman iteration from an injected oracle state at inner
+    index 1 or 2 (the two parities of the double-buffered split variable)."""
     from paper_1612_06496_amd import Solver
-    banner(f"inner step {name} fp64={fp64}")
+    banner(f"inner step {name} fp64={fp64} inner index {k_in}")
     wl = load(name)
     g = oracle_graph(wl)
     G = gpu_graph(wl)
     lam, r = penalties(wl, g, O.orthonormalize_init(g, wl.y0))
-    solve, Y, P, B, b, dd = mid_run_state(g, wl, lam, r, 1, 2)
+    solve, Y, P, B, b, dd = mid_run_state(g, wl, lam, r, 1, k_in)
     tol = 1e-12 if fp64 else 1e-6
     S = Solver(G, Y, lam=lam, r=r, n_inner=wl.n_inner, tol=tol, maxit=2000, fp64=fp64,
                keep_split=True, init_ortho=False, persistent=False)
     S.set("Y", Y); S.set("P", P); S.set("B", B)
-    S.inner_index = 2
+    S.inner_index = k_in
     S.set("b", b); S.set("d", dd)
     # the stored right-hand side equals Eq. 13's
     rhs_o = O.sb_rhs(g, P, B, b, dd, lam, r)
