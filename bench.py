@@ -400,6 +400,64 @@ def le_init_leg(G, wl, k=32, tol=1e-12, steps=10, oracle_time=True):
     return out
 
 
+def clustering_leg(name="gmm200k_knn16_rcm", steps=3):
+    """The general data-clustering configuration (Sec. IV's use beyond images):
+    a Gaussian-mixture point cloud's symmetrised exact k-NN graph (edge list,
+    general CSR slot layout), d = 20, shrink-active penalties, Jacobi-PCG;
+    autotuned launch shape, one untimed and `steps` timed SOC iterations; then
+    k-means (K = the mixture's components) on the embedding and its label
+    agreement with the mixture components (Hungarian matching)."""
+    import numpy as np
+    import torch
+    from scipy.optimize import linear_sum_assignment
+
+    import synth
+    from paper_1612_06496_amd import Graph, Solver, kmeans
+    t0 = time.perf_counter()
+    wl = synth.make_edges_workload(name, 0)
+    t_input = time.perf_counter() - t0
+    G = Graph.edges(wl.n, wl.src, wl.dst, wl.dist2, wl.sigma)
+    S = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=1000)
+    c = 1.0 / S.edge_quantile(0.99)
+    S.set_penalties(c, c)
+    tuned = [t for t in S.autotune(trials=1) if t["chosen"]]
+    S.solve(1)
+    S.stats(reset=True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        S.solve(1)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    info = S.stats(reset=True)
+    byt = algorithmic_bytes(G.n, G.n_edges, wl.d, 4, info["cg_iters_total"], info["solves"], wl.n_inner, steps)
+    yh = S.get("Yhat")
+    K = wl.n_clusters
+    rows = np.random.default_rng(0).choice(G.n, K, replace=False)
+    labels, _, kit = kmeans(yh, yh[torch.as_tensor(rows, device="cuda")].double(), 300)
+    lab = labels.cpu().numpy()
+    conf = np.zeros((K, K))
+    np.add.at(conf, (lab, np.asarray(wl.labels)), 1)
+    ri, ci = linear_sum_assignment(-conf)
+    agree = float(conf[ri, ci].sum() / G.n)
+    out = {"workload": name, "n": G.n, "edges": G.n_edges, "d": wl.d, "lambda": c, "r": c,
+           "input_s": round(t_input, 1), "ms_per_step": round(ms / steps, 3),
+           "outer_iters_per_s": round(steps / (ms / 1e3), 2),
+           "pcg_iters_per_solve": round(info["cg_iters_total"] / max(1, info["solves"]), 2),
+           "algorithmic_gbs": round(byt / (ms / 1e3) / 1e9, 1),
+           "frac": round(byt / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+           "launch": "persistent" if info["workgroups"] else ("strips" if info["flags"] & 2 else "multi"),
+           "autotuned": tuned[0] if tuned else None,
+           "kmeans_iterations": kit, "label_agreement_with_components": round(agree, 4)}
+    S.close()
+    G.close()
+    progress(f"clustering leg ({name}): {ms / steps:.1f} ms per SOC iteration")
+    return out
+
+
 def d_sweep_batched_leg(wl, c, dims=(5, 10, 15, 20, 25), steps=10):
     """The same d-sweep in ONE launch per SOC iteration: copies of the image in
     a block-diagonal union, copy k embedded in dims[k] dimensions (its initial
@@ -528,6 +586,9 @@ def main():
                     help="Split-Bregman iterations of the timed Stage II run after the SOC iterations (0: skip)")
     ap.add_argument("--kmeans-iters", type=int, default=100,
                     help="cap of the timed k-means (Lloyd) run on the final embedding, single images (0: skip)")
+    ap.add_argument("--clustering-workload", default="gmm200k_knn16_rcm",
+                    help="point-cloud workload of the data-clustering leg ('' to skip; gmm2m_knn16_rcm is the "
+                         "2 M-point configuration, its k-NN input takes about a minute to build)")
     ap.add_argument("--no-le", action="store_true",
                     help="skip the Laplacian-eigenmap initialisation leg (and the headline from its embedding)")
     ap.add_argument("--no-d-sweep", action="store_true",
@@ -664,6 +725,8 @@ def main():
         batched = d_sweep_batched_leg(wl, c)
         batched["separate_ms_sum"] = round(sum(r_["ms_per_step"] for r_ in line["d_sweep"]), 4)
         line["d_sweep_one_launch"] = batched
+    if args.clustering_workload and default:
+        line["clustering"] = clustering_leg(args.clustering_workload)
     if not args.no_learned and default:
         leg = learned_leg(workload=args.learned_workload, train_workload=args.learned_train_workload,
                           n_outer=args.learned_outer)

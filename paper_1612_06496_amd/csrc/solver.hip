@@ -204,7 +204,11 @@ __device__ __forceinline__ T cg_s(bool first, T beta, T sprev, T w) { return fir
 template <typename T>
 __device__ __forceinline__ T cg_r(T alpha, T s, T r) { return fma_t(-alpha, s, r); }
 
-// per-thread FP64 accumulators -> one partial per (quantity, column) per workgroup
+// per-thread FP64 accumulators -> one partial per (quantity, column) per
+// workgroup: staged in LDS, then one thread per (quantity, column) adds the
+// rows in order.  (A version with one wavefront per pair and a butterfly of
+// lane shuffles was slower in the persistent kernel: 397 against 424 SOC
+// iterations/s on the 481 x 321 image.)
 template <int NQ>
 __device__ __forceinline__ void block_partials(const double (&acc)[NQ], double* sh, int d, int R, double* part,
                                int nblk, int lb) {
@@ -867,9 +871,14 @@ __device__ __forceinline__ void ph_gram(const KA<T>& a, int lb, int mode, double
     const int npair = d * (d + 1) / 2;
     const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
     double* zt = sh;                  // R x d staged rows
+    // (pair, row slice) per thread: nsl slices of the staged rows per pair
+    // (one when the pairs outnumber the threads: two pairs per thread), the
+    // slices added in order at the end
+    const int nsl = max(1, (int)blockDim.x / npair);
+    const int sl = t / npair;
     int pa[2] = {0, 0}, pb[2] = {0, 0};
     for (int h = 0; h < 2; ++h) {
-        int k = t + h * (int)blockDim.x;
+        int k = (nsl > 1) ? t - sl * npair : t + h * (int)blockDim.x;
         if (k < npair) pair_of(k, d, pa[h], pb[h]);
     }
     double acc[2] = {0.0, 0.0};
@@ -885,15 +894,35 @@ __device__ __forceinline__ void ph_gram(const KA<T>& a, int lb, int mode, double
             zt[t] = (double)z;
         }
         __syncthreads();
-        for (int h = 0; h < 2; ++h) {
-            int k = t + h * (int)blockDim.x;
-            if (k < npair) {
-                double s = acc[h];
-                for (int rr = 0; rr < rows; ++rr) s += zt[rr * d + pa[h]] * zt[rr * d + pb[h]];
-                acc[h] = s;
+        if (nsl > 1) {
+            if (sl < nsl) {
+                double s = acc[0];
+                for (int rr = sl; rr < rows; rr += nsl) s += zt[rr * d + pa[0]] * zt[rr * d + pb[0]];
+                acc[0] = s;
+            }
+        } else {
+            for (int h = 0; h < 2; ++h) {
+                int k = t + h * (int)blockDim.x;
+                if (k < npair) {
+                    double s = acc[h];
+                    for (int rr = 0; rr < rows; ++rr) s += zt[rr * d + pa[h]] * zt[rr * d + pb[h]];
+                    acc[h] = s;
+                }
             }
         }
         __syncthreads();
+    }
+    if (nsl > 1) {
+        double* red = sh + kBlock;    // beyond the staged rows
+        if (sl < nsl) red[sl * npair + (t - sl * npair)] = acc[0];
+        __syncthreads();
+        if (t < npair) {
+            double s = 0.0;
+            for (int k = 0; k < nsl; ++k) s += red[k * npair + t];
+            a.part[(size_t)lb * npair + t] = s;
+        }
+        __syncthreads();
+        return;
     }
     for (int h = 0; h < 2; ++h) {
         int k = t + h * (int)blockDim.x;
