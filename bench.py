@@ -417,7 +417,7 @@ def clustering_leg(name="gmm200k_knn16_rcm", steps=3):
     wl = synth.make_edges_workload(name, 0)
     t_input = time.perf_counter() - t0
     G = Graph.edges(wl.n, wl.src, wl.dst, wl.dist2, wl.sigma)
-    S = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=1000)
+    S = Solver(G, wl.y0, lam=1.0, r=1.0, n_inner=wl.n_inner, tol=wl.tol, maxit=1000, graphs=True)
     c = 1.0 / S.edge_quantile(0.99)
     S.set_penalties(c, c)
     tuned = [t for t in S.autotune(trials=1) if t["chosen"]]

@@ -303,6 +303,9 @@ __device__ __forceinline__ int seg_chunk(int nq, int d) {
 template <int KC>
 constexpr int kSlotUnroll = KC > 0 ? 4 : 2;
 
+// slots per group of the loops over rows of any length (general CSR layout)
+constexpr int kGenGroup = 4;
+
 template <int KC, int GM>
 constexpr int slot_group() { return KC <= 0 ? 1 : (KC <= GM ? KC : GM); }
 
@@ -538,8 +541,27 @@ __device__ __forceinline__ void ph_w0(const KA<T>& a, int lb, double* sh, const 
                     for (int k = 0; k < G; ++k) accA = fma_t(mul_t(ww[k], ww[k]), mul_t(ij[k], rj[k]), accA);
                 }
             } else {
-#pragma unroll 2
-                for (int k = 0; k < cnt; ++k) {
+                // rows of any length: groups of kGenGroup slots (their column
+                // and weight loads, then their gathers), then the tail
+                int k = 0;
+                for (; k + kGenGroup <= cnt; k += kGenGroup) {
+                    int jj[kGenGroup];
+                    T ww[kGenGroup], rj[kGenGroup], ij[kGenGroup];
+#pragma unroll
+                    for (int q = 0; q < kGenGroup; ++q) {
+                        const int sl = s0 + (k + q) * st;
+                        jj[q] = a.scol[sl];
+                        ww[q] = a.sw[sl];
+                    }
+#pragma unroll
+                    for (int q = 0; q < kGenGroup; ++q) {
+                        rj[q] = r[(size_t)jj[q] * d + c];
+                        ij[q] = a.invdiag[jj[q]];
+                    }
+#pragma unroll
+                    for (int q = 0; q < kGenGroup; ++q) accA = fma_t(mul_t(ww[q], ww[q]), mul_t(ij[q], rj[q]), accA);
+                }
+                for (; k < cnt; ++k) {
                     const int s = s0 + k * st;
                     const int j = a.scol[s];
                     const T ww = a.sw[s];
@@ -626,8 +648,32 @@ __device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh, int it
                     }
                 }
             } else {
-#pragma unroll 2
-                for (int k = 0; k < cnt; ++k) {
+                int k = 0;
+                for (; k + kGenGroup <= cnt; k += kGenGroup) {
+                    int jj[kGenGroup];
+                    T ww[kGenGroup], spj[kGenGroup], wj[kGenGroup], rj[kGenGroup], ij[kGenGroup];
+#pragma unroll
+                    for (int q = 0; q < kGenGroup; ++q) {
+                        const int sl = s0 + (k + q) * st;
+                        jj[q] = a.scol[sl];
+                        ww[q] = a.sw[sl];
+                    }
+#pragma unroll
+                    for (int q = 0; q < kGenGroup; ++q) {
+                        const size_t ej = (size_t)jj[q] * d + c;
+                        spj[q] = sp[ej];
+                        wj[q] = w[ej];
+                        rj[q] = r[ej];
+                        ij[q] = a.invdiag[jj[q]];
+                    }
+#pragma unroll
+                    for (int q = 0; q < kGenGroup; ++q) {
+                        const T sj = cg_s(first, beta, spj[q], wj[q]);
+                        const T uj = mul_t(ij[q], cg_r(alpha, sj, rj[q]));
+                        accA = fma_t(mul_t(ww[q], ww[q]), uj, accA);
+                    }
+                }
+                for (; k < cnt; ++k) {
                     const int s = s0 + k * st;
                     const int j = a.scol[s];
                     const T ww = a.sw[s];
@@ -649,6 +695,119 @@ __device__ __forceinline__ void ph_it(const KA<T>& a, int lb, double* sh, int it
         }
     }
     block_partials<3>(acc, sh, d, R, a.part, a.nblk, lb);
+}
+
+// General layouts (rows of any length, KC = 0): one CG iteration in two
+// passes, so that the neighbour values gathered are u' alone (stored by its
+// owner) rather than the three vectors r, w, s from which the one-pass form
+// recomputes them; on graphs of high and uneven degree (k-NN graphs) the
+// gathers dominate, and the extra grid synchronisation is the cheaper price.
+// Vectors in place (no neighbour reads them): r = rb[0], w = wb[0], s = sb[0],
+// u' in zl.
+//   GA (own rows): u = r / diag(A), p = u + beta p, s = w + beta s,
+//       x += alpha p, r' = r - alpha s, u' = r' / diag(A); partials of r'.u'
+//       (quantity 0) and r'.r' (quantity 2)
+//   GB: w' = A u'; partials of w'.u' (quantity 1)
+// The iteration's finaliser (the one-pass one) reads the three quantities.
+template <int NQ>
+__device__ __forceinline__ void block_partials_at(const double (&acc)[NQ], const int (&qout)[NQ], double* sh, int d,
+                                                  int R, double* part, int nblk, int lb) {
+    const int t = threadIdx.x;
+    const int B = blockDim.x;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sh[q * B + t] = (t < R * d) ? acc[q] : 0.0;
+    __syncthreads();
+    if (t < NQ * d) {
+        const int q = t / d, c = t - q * d;
+        double s = 0.0;
+        for (int k = 0; k < R; ++k) s += sh[q * B + k * d + c];
+        part[((size_t)qout[q] * nblk + lb) * d + c] = s;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void ph_ga(const KA<T>& a, int lb, double* sh, int it, const double* alphas,
+                                      const double* betas) {
+    const int d = a.d, R = a.R, t = threadIdx.x;
+    const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
+    const bool first = (it == 0);
+    T* r = a.rb[0];
+    T* w = a.wb[0];
+    T* sv = a.sb[0];
+    double acc[2] = {0.0, 0.0};
+    if (t < R * d) {
+        const int rl = t / d, c = t - rl * d;
+        const int ci = a.blk_seg[lb] * d + c;
+        const T alpha = (T)alphas[ci];
+        const T beta = (T)betas[ci];
+        for (int i = rb + rl; i < re; i += rs) {
+            const size_t e = (size_t)i * d + c;
+            const T inv = a.invdiag[i];
+            const T ri = r[e];
+            const T pold = a.p[e];
+            const T spi = sv[e];
+            const T wi = w[e];
+            const T ui = mul_t(inv, ri);
+            const T pi = first ? ui : fma_t(beta, pold, ui);
+            const T si = cg_s(first, beta, spi, wi);
+            const T rn_i = cg_r(alpha, si, ri);
+            const T un_i = mul_t(inv, rn_i);
+            a.p[e] = pi;
+            sv[e] = si;
+            a.x[e] = fma_t(alpha, pi, a.x[e]);
+            r[e] = rn_i;
+            a.zl[e] = un_i;
+            acc[0] += (double)rn_i * (double)un_i;
+            acc[1] += (double)rn_i * (double)rn_i;
+        }
+    }
+    const int qo[2] = {0, 2};
+    block_partials_at<2>(acc, qo, sh, d, R, a.part, a.nblk, lb);
+}
+
+template <typename T>
+__device__ __forceinline__ void ph_gb(const KA<T>& a, int lb, double* sh) {
+    const int d = a.d, R = a.R, t = threadIdx.x;
+    const int rb = a.bit[3 * lb], re = a.bit[3 * lb + 1], rs = a.bit[3 * lb + 2];
+    const T* u = a.zl;
+    T* w = a.wb[0];
+    double acc[1] = {0.0};
+    if (t < R * d) {
+        const int rl = t / d, c = t - rl * d;
+        for (int i = rb + rl; i < re; i += rs) {
+            const size_t e = (size_t)i * d + c;
+            int s0, cnt, st;
+            row_slots<0>(a, i, s0, cnt, st);
+            const T ui = u[e];
+            T accA = T(0);
+            int k = 0;
+            for (; k + kGenGroup <= cnt; k += kGenGroup) {
+                int jj[kGenGroup];
+                T ww[kGenGroup], uj[kGenGroup];
+#pragma unroll
+                for (int q = 0; q < kGenGroup; ++q) {
+                    const int sl = s0 + (k + q) * st;
+                    jj[q] = a.scol[sl];
+                    ww[q] = a.sw[sl];
+                }
+#pragma unroll
+                for (int q = 0; q < kGenGroup; ++q) uj[q] = u[(size_t)jj[q] * d + c];
+#pragma unroll
+                for (int q = 0; q < kGenGroup; ++q) accA = fma_t(mul_t(ww[q], ww[q]), uj[q], accA);
+            }
+            for (; k < cnt; ++k) {
+                const int sl = s0 + k * st;
+                const T ww = a.sw[sl];
+                accA = fma_t(mul_t(ww, ww), u[(size_t)a.scol[sl] * d + c], accA);
+            }
+            const T wi = fma_t(a.diagA[i], ui, -mul_t(a.c_off, accA));
+            w[e] = wi;
+            acc[0] += (double)wi * (double)ui;
+        }
+    }
+    const int qo[1] = {1};
+    block_partials_at<1>(acc, qo, sh, d, R, a.part, a.nblk, lb);
 }
 
 // Learned-preconditioner PCG phases (standard PCG with M^{-1} = G^T G, one
@@ -2559,6 +2718,25 @@ __global__ void __launch_bounds__(kBlock) k_cg_it(KA<T> a) {
     }
 }
 
+// general layouts: the CG iteration in two passes
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cg_ga(KA<T> a) {
+    __shared__ double sh[kSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    ph_ga(a, logical_block(a.nblk), sh, ld_flag(&a.S->it), a.cs.alpha, a.cs.beta);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cg_gb(KA<T> a) {
+    __shared__ double sh[kSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    ph_gb(a, logical_block(a.nblk), sh);
+    if (last_block(a.bar + kBarLast, a.nblk)) {
+        fin_it(a, sh, false);
+        if (threadIdx.x == 0 && a.S->done) solve_stats(a);
+    }
+}
+
 // strip kernels (pixel grids): the residual with r0, w0 and the CG iteration
 template <typename T, int KC>
 __global__ void __launch_bounds__(kBlock) k_st_res(KA<T> a, int ph) {
@@ -2809,7 +2987,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                     lfin_w0(a, L, gp, sh);
                 }
                 while (!L.done) {
-                    ph_it<KC, 4, LC>(a, lb, sh, L.it, L.alpha, L.beta, rc);
+                    if constexpr (KC == 0) {
+                        ph_ga(a, lb, sh, L.it, L.alpha, L.beta);
+                        gbuf();
+                        if (!grid_sync(a.bar, nb, S, nbar, NoFin{}, NoFin{})) return;
+                        ph_gb(a, lb, sh);
+                    } else {
+                        ph_it<KC, 4, LC>(a, lb, sh, L.it, L.alpha, L.beta, rc);
+                    }
                     gp = gbuf();
                     if (!grid_sync(a.bar, nb, S, nbar, [&](unsigned g) { group_reduce(a, g, d, 3, sh, gp); }, NoFin{})) return;
                     lfin_it(a, L, gp, sh);
@@ -2843,7 +3028,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                 if (!grid_sync(a.bar, nb, S, nbar, NoFin{}, [&] { fin_w0(a, sh, false); })) return;
             }
             while (!ld_flag(&S->done)) {
-                ph_it<KC, 4, LC>(a, lb, sh, ld_flag(&S->it), a.cs.alpha, a.cs.beta, rc);
+                if constexpr (KC == 0) {
+                    ph_ga(a, lb, sh, ld_flag(&S->it), a.cs.alpha, a.cs.beta);
+                    if (!grid_sync(a.bar, nb, S, nbar, NoFin{}, NoFin{})) return;
+                    ph_gb(a, lb, sh);
+                } else {
+                    ph_it<KC, 4, LC>(a, lb, sh, ld_flag(&S->it), a.cs.alpha, a.cs.beta, rc);
+                }
                 if (!grid_sync(a.bar, nb, S, nbar, NoFin{}, [&] { fin_it(a, sh, false); })) return;
             }
             if (lb == 0 && threadIdx.x == 0) solve_stats(a);
@@ -3711,7 +3902,14 @@ pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0)
     switch (ph) {
         case PH_E0: case PH_EU: case PH_R0: case PH_RHS: PFE_LAUNCH_KC(k_residual, K, grid, st, a, ph, do_r0); break;
         case PH_W0: PFE_LAUNCH_KC(k_cg_w0, K, grid, st, a); break;
-        case PH_IT: PFE_LAUNCH_KC(k_cg_it, K, grid, st, a); break;
+        case PH_IT:
+            if (K == 4 || K == 8 || K == 24) {
+                PFE_LAUNCH_KC(k_cg_it, K, grid, st, a);
+            } else {
+                hipLaunchKernelGGL(k_cg_ga<T>, grid, dim3(kBlock), 0, st, a);
+                hipLaunchKernelGGL(k_cg_gb<T>, grid, dim3(kBlock), 0, st, a);
+            }
+            break;
         case PH_ZERO: hipLaunchKernelGGL(k_cg_zero<T>, grid, dim3(kBlock), 0, st, a); break;
         case PH_LA: PFE_LAUNCH_KC(k_lpcg_aq, K, grid, st, a); break;
         case PH_LC: PFE_LAUNCH_KC(k_lpcg_g, K, grid, st, a, mode); break;
@@ -3818,6 +4016,9 @@ pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, const KA<T>*
                 add(kernel_for<T>(PH_LC, K, st), p3, a.nblk);
                 add(kernel_for<T>(PH_LD, K, st), p2, a.nblk);
             }
+        } else if (!st && K != 4 && K != 8 && K != 24) {
+            add(reinterpret_cast<const void*>(&k_cg_ga<T>), p1, a.nblk);
+            add(reinterpret_cast<const void*>(&k_cg_gb<T>), p1, a.nblk);
         } else {
             add(kernel_for<T>(PH_IT, K, st), p1, a.nblk);
         }
