@@ -53,9 +53,7 @@ def algorithmic_bytes(n, E, d, esz, cg_iters, solves, n_inner, n_outer, pupdate=
 # committed rocprofv3 FETCH_SIZE / WRITE_SIZE records: (workload, launch) ->
 # file; persistent records count one k_soc launch, strip records one SOC
 # iteration of the one-launch-per-phase path on image strips
-TRAFFIC_FILES = {("voronoi481x321_8nbr", "persistent"): "k_soc_voronoi481x321_traffic.json",
-                 ("voronoi_batch64_8nbr", "strips"): "strips_voronoi_batch64_traffic.json",
-                 ("voronoi1024_r2", "strips"): "strips_voronoi1024_r2_traffic.json"}
+TRAFFIC_FILES = {("voronoi481x321_8nbr", "persistent"): "k_soc_voronoi481x321_traffic.json"}
 
 
 def measured_traffic(workload, launch):
