@@ -2773,6 +2773,112 @@ __global__ void __launch_bounds__(kBlock) k_st_eu(KA<T> a) {
     st_eu<KC>(a, logical_block(a.nblk), sh);
 }
 
+// V consecutive columns of one row, moved as one 4-, 8- or 16-byte access
+template <typename T, int V> struct VecOf;
+template <> struct VecOf<float, 1> { using type = float; };
+template <> struct VecOf<float, 2> { using type = float2; };
+template <> struct VecOf<float, 4> { using type = float4; };
+template <> struct VecOf<double, 1> { using type = double; };
+template <> struct VecOf<double, 2> { using type = double2; };
+template <typename T, int V>
+__device__ __forceinline__ T& lane_el(typename VecOf<T, V>::type& v, int u) { return reinterpret_cast<T*>(&v)[u]; }
+
+// Edge update of the pixel-stencil layouts with b once per undirected edge (the
+// PH_EU arithmetic without r0, element by element and in the same slot order):
+// one thread per pixel and V consecutive columns, no LDS, one workgroup per
+// kBlock / (d / V) pixels.  The edge update has no neighbour value shared by a
+// recurrence, so it needs neither strips nor a co-resident grid: what bounds it
+// is the number of independent loads in flight, which wide accesses and a full
+// grid of small workgroups maximise.  With GEO (one image of W x H pixels) the
+// neighbour of slot k is the stencil offset, and the slot columns are not read;
+// otherwise (batches) they are.
+template <typename T, int KC, int V, bool GEO>
+__global__ void __launch_bounds__(kBlock) k_eu_px(KA<T> a, int W, int H) {
+    using VT = typename VecOf<T, V>::type;
+    using S = Sten<KC>;
+    constexpr int KH = KC / 2;
+    constexpr int G = (KC < 8) ? KC : 8;   // slots whose loads are issued together
+    const int d = a.d, L = d / V, ppb = kBlock / L;
+    const int q = threadIdx.x / L;
+    const int64_t i64 = (int64_t)blockIdx.x * ppb + q;
+    if (q >= ppb || i64 >= a.n) return;
+    const int i = (int)i64;
+    const int c0 = (threadIdx.x - q * L) * V;
+    const size_t e = (size_t)i * d + c0;
+    const T* bread = a.bsb[a.bpar & 1];
+    T* bwrite = a.bsb[(a.bpar & 1) ^ 1];
+    const VT yi = *reinterpret_cast<const VT*>(a.Y + e);
+    VT acc;
+#pragma unroll
+    for (int u = 0; u < V; ++u) lane_el<T, V>(acc, u) = T(0);
+    int py = 0, px = 0;
+    if constexpr (GEO) {
+        py = i / W;
+        px = i - py * W;
+    }
+#pragma unroll
+    for (int k0 = 0; k0 < KC; k0 += G) {
+        int jj[G];
+        T ww[G];
+        VT yj[G], bo[G];
+        size_t ss[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int kk = k0 + k;
+            const size_t sl = (size_t)kk * a.n + i;
+            if constexpr (GEO) {
+                const int yy = py + S::dy(kk), xx = px + S::dx(kk);
+                jj[k] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? i + S::dy(kk) * W + S::dx(kk) : i;
+            } else {
+                jj[k] = a.scol[sl];
+            }
+            ww[k] = a.sw[sl];
+            ss[k] = (kk < KH) ? sl : (size_t)(KC - 1 - kk) * a.n + jj[k];
+            if (a.b_zero) {
+#pragma unroll
+                for (int u = 0; u < V; ++u) lane_el<T, V>(bo[k], u) = T(0);
+            } else {
+                bo[k] = *reinterpret_cast<const VT*>(bread + ss[k] * d + c0);
+                if (kk >= KH) {
+#pragma unroll
+                    for (int u = 0; u < V; ++u) lane_el<T, V>(bo[k], u) = -lane_el<T, V>(bo[k], u);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) yj[k] = *reinterpret_cast<const VT*>(a.Y + (size_t)jj[k] * d + c0);
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int kk = k0 + k;
+            VT bn, dn;
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                VT yv = yi;
+                const T tv = fma_t(ww[k], lane_el<T, V>(yv, u) - lane_el<T, V>(yj[k], u), lane_el<T, V>(bo[k], u));
+                const T dv = shrink(tv, a.gamma);
+                const T b1 = tv - dv;
+                lane_el<T, V>(bn, u) = b1;
+                lane_el<T, V>(dn, u) = dv;
+                lane_el<T, V>(acc, u) = fma_t(ww[k], dv - b1, lane_el<T, V>(acc, u));
+            }
+            if (kk < KH) {
+                *reinterpret_cast<VT*>(bwrite + ss[k] * d + c0) = bn;
+                if (a.keep_split) *reinterpret_cast<VT*>(a.ds + ss[k] * d + c0) = dn;
+            }
+        }
+    }
+    const T sq = a.sqrtD[i];
+    VT pv = *reinterpret_cast<const VT*>(a.P + e);
+    VT bv = *reinterpret_cast<const VT*>(a.B + e);
+    VT rv;
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+        const T split = mul_t(a.half_r, mul_t(sq, lane_el<T, V>(pv, u) - lane_el<T, V>(bv, u)));
+        lane_el<T, V>(rv, u) = fma_t(a.c_off, lane_el<T, V>(acc, u), split);
+    }
+    *reinterpret_cast<VT*>(a.rhs + e) = rv;
+}
+
 // learned-preconditioner PCG phases on strips
 template <typename T, int KC>
 __global__ void __launch_bounds__(kBlock) k_st_la(KA<T> a) {
@@ -3551,6 +3657,8 @@ struct pfe_ctx {
     Partition pl;            // strips with a two-radius halo (fused learned apply)
     Partition pf;            // strips with a three-radius halo (one-pass factor CG)
     int one_pass = 0;        // factor preconditioners on strips: one pass per CG iteration (0: two)
+    int eu_px = 1;           // pixel stencils with b once per edge: the edge update by the per-pixel
+                             // kernel (0: by the strip or row-chunk phase kernel)
     int want_strips = 2;     // one launch per phase: residual, w0 and CG kernels on image strips sized
                              // for this many waves of co-resident strip workgroups (0: row chunks)
     int strip_slots = 0;     // co-resident strip workgroups on the device (0: no strip kernel)
@@ -4209,6 +4317,51 @@ pfe_status setup_strips(pfe_ctx* c) {
     return PFE_OK;
 }
 
+// the per-pixel edge update (k_eu_px): pixel stencils of 4, 8 or 24 slots with b
+// once per undirected edge
+inline bool eu_px_ok(const pfe_ctx* c) {
+    const int K = c->g->ell_K;
+    return c->eu_px && c->bhalf && c->g->stencil && (K == 4 || K == 8 || K == 24);
+}
+
+template <typename T, int KC, int V>
+pfe_status launch_eu_px_v(pfe_ctx* c, const KA<T>& a, dim3 grid, bool geo, int W, int H) {
+    if (geo) hipLaunchKernelGGL((k_eu_px<T, KC, V, true>), grid, dim3(kBlock), 0, c->stream, a, W, H);
+    else hipLaunchKernelGGL((k_eu_px<T, KC, V, false>), grid, dim3(kBlock), 0, c->stream, a, W, H);
+    PFE_CHECK_HIP(hipGetLastError());
+    return PFE_OK;
+}
+
+template <typename T, int V>
+pfe_status launch_eu_px_k(pfe_ctx* c, const KA<T>& a, dim3 grid, bool geo, int W, int H) {
+    switch (c->g->ell_K) {
+        case 4: return launch_eu_px_v<T, 4, V>(c, a, grid, geo, W, H);
+        case 8: return launch_eu_px_v<T, 8, V>(c, a, grid, geo, W, H);
+        case 24: return launch_eu_px_v<T, 24, V>(c, a, grid, geo, W, H);
+        default: set_error("the per-pixel edge update needs a stencil of 4, 8 or 24 slots"); return PFE_E_STATE;
+    }
+}
+
+// columns per thread: 16-byte accesses where d allows (4 FP32 or 2 FP64 columns), else one
+template <typename T>
+pfe_status launch_eu_px(pfe_ctx* c, const KA<T>& a) {
+    const int d = (int)c->d;
+    const int V = (sizeof(T) == 4) ? ((d % 4 == 0) ? 4 : 1) : ((d % 2 == 0) ? 2 : 1);
+    const int ppb = kBlock / (d / V);
+    const dim3 grid((unsigned)((c->n + ppb - 1) / ppb));
+    // one image: neighbours from the stencil offsets; batches read the slot columns
+    const pfe_graph* g = c->g;
+    const bool geo = c->nseg == 1 && g->seg_W.size() == 1 && g->seg_W[0] > 0 && g->seg_H[0] > 0 &&
+                     (int64_t)g->seg_W[0] * g->seg_H[0] == c->n;
+    const int W = geo ? g->seg_W[0] : 0, H = geo ? g->seg_H[0] : 0;
+    if constexpr (sizeof(T) == 4) {
+        if (V == 4) return launch_eu_px_k<T, 4>(c, a, grid, geo, W, H);
+    } else {
+        if (V == 2) return launch_eu_px_k<T, 2>(c, a, grid, geo, W, H);
+    }
+    return launch_eu_px_k<T, 1>(c, a, grid, geo, W, H);
+}
+
 // inner iteration l of a Split-Bregman run (l = 0: b = d = 0), one launch per phase
 template <typename T>
 pfe_status inner_at(pfe_ctx* c, int l) {
@@ -4224,6 +4377,7 @@ pfe_status inner_at(pfe_ctx* c, int l) {
     b.store_rhs = 1;
     b.b_zero = (l == 0);
     b.bpar = l & 1;
+    if (eu_px_ok(c)) return launch_eu_px(c, b);
     PFE_TRY(launch_phase(c, b, PH_EU, 0, 0));
     return PFE_OK;
 }
@@ -4740,6 +4894,7 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
     if (s == PFE_OK) s = setup_persistent(c);
     if (const char* ev = getenv("PFE_STRIPS")) c->want_strips = std::max(0, atoi(ev));   // launch-shape experiments
     if (const char* ev = getenv("PFE_ONE_PASS")) c->one_pass = atoi(ev) != 0;
+    if (const char* ev = getenv("PFE_EU_PX")) c->eu_px = atoi(ev) != 0;     // launch-shape experiments
     if (s == PFE_OK) {
         // strip partition: built first for the most waves any later shape asks
         // for (it has the most workgroups), then for the wanted count

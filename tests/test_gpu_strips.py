@@ -225,3 +225,46 @@ def test_one_pass_factor_pcg_matches_two_pass(stencil, d, fp64):
     assert np.all(np.abs(out[0][1] - out[1][1]) <= 1)
     assert out[0][2]["rel_res_max"] <= tol
     assert e <= (1e-8 if fp64 else 1e-4)
+
+
+def run_eu(wl_or_graph, y0, monkeypatch, eu_px, fp64, keep_split, inner_steps):
+    from paper_1612_06496_amd import Solver
+    monkeypatch.setenv("PFE_EU_PX", "1" if eu_px else "0")
+    monkeypatch.setenv("PFE_STRIPS", "1")
+    S = Solver(wl_or_graph, y0, lam=30.0, r=3.0, n_inner=3, tol=1e-10 if fp64 else 1e-6, maxit=3000, fp64=fp64,
+               persistent=False, keep_split=keep_split)
+    S.solve(1)
+    for _ in range(inner_steps):
+        S.step("inner")
+    out = {k: S.get(k).cpu().numpy() for k in ("Y", "P", "B", "b") + (("d",) if keep_split else ())}
+    S.close()
+    return out
+
+
+EU_CASES = ["voronoi96x80_8nbr", "voronoi48x40_r2", "voronoi64_4nbr", "narrow300x7_r2", "wide33x70_d32_r2",
+            "multi23x95_8_d16"]
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+@pytest.mark.parametrize("name", EU_CASES + ["batch5"])
+def test_pixel_edge_update_bitwise_equals_phase_kernels(name, fp64, monkeypatch):
+    """The per-pixel edge update (one thread per pixel and 1, 2 or 4 columns;
+    neighbours from the stencil offsets on one image, from the slot columns on a
+    batch) does the phase kernels' arithmetic element by element in the same
+    slot order: Y, P, B, b and d after a SOC iteration and two inner steps (both
+    b-buffer parities) are bitwise those of the strip / row-chunk edge update."""
+    from paper_1612_06496_amd import Graph
+    banner(f"per-pixel edge update == phase kernels: {name} fp64={fp64}")
+    if name == "batch5":
+        wls = synth.make_batch("voronoi_batch5_8nbr")
+        G = Graph.union([gpu_graph(w) for w in wls])
+        y0 = np.concatenate([w.y0 for w in wls])
+    else:
+        wl = case_workload(next(c for c in CASES if c[0] == name))
+        G, y0 = gpu_graph(wl), wl.y0
+    keep = name in ("voronoi48x40_r2", "batch5")
+    a = run_eu(G, y0, monkeypatch, True, fp64, keep, 2)
+    b = run_eu(G, y0, monkeypatch, False, fp64, keep, 2)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), f"{k} differs: max {np.abs(a[k] - b[k]).max():.3e}"
+    print("bitwise equal:", sorted(a))
