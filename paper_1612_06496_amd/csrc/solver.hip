@@ -2531,6 +2531,46 @@ __device__ __forceinline__ void group_reduce(const KA<T>& a, unsigned g, int m, 
     __syncthreads();
 }
 
+// One-launch-per-phase kernels, single segment, a grid of whole XCD groups: the
+// workgroup partials are summed in two levels instead of by one workgroup alone.
+// The last workgroup of each XCD group (logical workgroups [g gs, (g + 1) gs),
+// the ones launched on XCD g) sums its group's partials in order into gpart;
+// the last of the eight group leaders returns true and runs the finaliser on the
+// eight group sums (grouped).  Each level reads only a group's worth of
+// partials, with many loads in flight, where one workgroup summing every
+// partial waits on a long chain of memory round trips.
+constexpr int kBarLastGroup = 456;   // bar[456 + 4 g]: group counters of the multi-launch path
+
+template <typename T>
+__device__ __forceinline__ bool grouped_fin(const KA<T>& a) {
+    return a.nseg == 1 && a.nblk >= 8 * kNumXcd && (a.nblk % kNumXcd) == 0;
+}
+
+template <typename T>
+__device__ bool last_block_grouped(const KA<T>& a, int nq, double* sh) {
+    __shared__ int s_last;
+    const unsigned g = blockIdx.x % kNumXcd;
+    const unsigned gs = (unsigned)a.nblk / kNumXcd;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned* ctr = a.bar + kBarLastGroup + 4 * g;
+        unsigned prev = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (prev == gs - 1);
+        if (s_last) __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    group_reduce(a, g, a.d, nq, sh, a.gpart);
+    return last_block(a.bar + kBarLast, kNumXcd);
+}
+
+// the last workgroup of a one-launch-per-phase kernel (grouped: see above);
+// the finaliser then reads gpart when grouped_fin(a), else part
+template <typename T>
+__device__ __forceinline__ bool last_of_launch(const KA<T>& a, int nq, double* sh) {
+    return grouped_fin(a) ? last_block_grouped(a, nq, sh) : last_block(a.bar + kBarLast, a.nblk);
+}
+
 // ---------------------------------------------------------------------------
 // Per-workgroup CG state (persistent kernel, single segment).  After each grid
 // barrier every workgroup sums the eight per-XCD-group partials itself, in the
@@ -2694,7 +2734,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(KA<T> a, int ph, int do_r0)
     __shared__ double sh[kSmemDoubles];
     const int lb = logical_block(a.nblk);
     ph_residual<KC>(a, lb, ph, do_r0, a.b_zero, a.bpar, sh);
-    if (do_r0 && last_block(a.bar + kBarLast, a.nblk)) fin_res(a, sh, false);
+    if (do_r0 && last_of_launch(a, 2, sh)) fin_res(a, sh, grouped_fin(a));
 }
 
 template <typename T, int KC>
@@ -2703,7 +2743,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_w0(KA<T> a) {
     if (ld_flag(&a.S->done)) return;
     const int lb = logical_block(a.nblk);
     ph_w0<KC>(a, lb, sh);
-    if (last_block(a.bar + kBarLast, a.nblk)) fin_w0(a, sh, false);
+    if (last_of_launch(a, 2, sh)) fin_w0(a, sh, grouped_fin(a));
 }
 
 template <typename T, int KC>
@@ -2712,8 +2752,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_it(KA<T> a) {
     if (ld_flag(&a.S->done)) return;
     const int lb = logical_block(a.nblk);
     ph_it<KC>(a, lb, sh, ld_flag(&a.S->it), a.cs.alpha, a.cs.beta);
-    if (last_block(a.bar + kBarLast, a.nblk)) {
-        fin_it(a, sh, false);
+    if (last_of_launch(a, 3, sh)) {
+        fin_it(a, sh, grouped_fin(a));
         if (threadIdx.x == 0 && a.S->done) solve_stats(a);
     }
 }
@@ -2731,8 +2771,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_gb(KA<T> a) {
     __shared__ double sh[kSmemDoubles];
     if (ld_flag(&a.S->done)) return;
     ph_gb(a, logical_block(a.nblk), sh);
-    if (last_block(a.bar + kBarLast, a.nblk)) {
-        fin_it(a, sh, false);
+    if (last_of_launch(a, 3, sh)) {
+        fin_it(a, sh, grouped_fin(a));
         if (threadIdx.x == 0 && a.S->done) solve_stats(a);
     }
 }
@@ -2743,7 +2783,7 @@ __global__ void __launch_bounds__(kBlock) k_st_res(KA<T> a, int ph) {
     __shared__ double sh[kSmemDoubles];
     const int lb = logical_block(a.nblk);
     st_res<KC>(a, lb, ph, sh);
-    if (last_block(a.bar + kBarLast, a.nblk)) fin_res(a, sh, false);
+    if (last_of_launch(a, 2, sh)) fin_res(a, sh, grouped_fin(a));
 }
 
 template <typename T, int KC>
@@ -2752,7 +2792,7 @@ __global__ void __launch_bounds__(kBlock) k_st_w0(KA<T> a) {
     if (ld_flag(&a.S->done)) return;
     const int lb = logical_block(a.nblk);
     st_w0<KC>(a, lb, sh);
-    if (last_block(a.bar + kBarLast, a.nblk)) fin_w0(a, sh, false);
+    if (last_of_launch(a, 2, sh)) fin_w0(a, sh, grouped_fin(a));
 }
 
 template <typename T, int KC>
@@ -2761,8 +2801,8 @@ __global__ void __launch_bounds__(kBlock) k_st_it(KA<T> a) {
     if (ld_flag(&a.S->done)) return;
     const int lb = logical_block(a.nblk);
     st_it<KC>(a, lb, sh, ld_flag(&a.S->it), a.cs.alpha, a.cs.beta);
-    if (last_block(a.bar + kBarLast, a.nblk)) {
-        fin_it(a, sh, false);
+    if (last_of_launch(a, 3, sh)) {
+        fin_it(a, sh, grouped_fin(a));
         if (threadIdx.x == 0 && a.S->done) solve_stats(a);
     }
 }
