@@ -164,7 +164,8 @@ typedef struct {
                                 down or reached maxit (the redo's status is reported) */
     int32_t workgroups;      /* workgroups of the persistent launch (0: one launch per phase) */
     int32_t flags;           /* bit 0: persistent launch with the rows' slot data held in LDS;
-                                bit 1: one launch per phase on image strips */
+                                bit 1: one launch per phase on image strips;
+                                bit 2: Jacobi PCG by pixel launches (pfe_tune_result.pixel) */
 } pfe_step_info;
 
 /* Monitors of the current state (Eq. 1, Eq. 2). */
@@ -281,6 +282,11 @@ typedef struct {
                                 per CG iteration (Chronopoulos-Gear form, M^{-1} r and A M^{-1} r
                                 through three LDS rings over a three-radius halo), 0 = two passes
                                 (A p, then the factor apply with the x, r update) */
+    int32_t pixel;           /* one launch per phase, Jacobi PCG of a one-image pixel grid by per-pixel
+                                kernels: the residual, w0 and each CG iteration in two passes (the
+                                own-row updates storing u' = r'/diag(A), then w' = A u' gathering u'),
+                                one thread per pixel and 1, 2 or 4 columns, neighbours through L2
+                                (flags bit 2 of pfe_step_info) */
 } pfe_tune_result;
 
 /* Autotune the launch shape on this context's graph: from the current state

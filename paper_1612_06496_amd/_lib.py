@@ -74,7 +74,8 @@ class pfe_le_info(C.Structure):
 class pfe_tune_result(C.Structure):
     _fields_ = [("persistent", C.c_int32), ("team", C.c_int32), ("row_cache", C.c_int32),
                 ("workgroups", C.c_int32), ("ms", C.c_double), ("chosen", C.c_int32),
-                ("strips", C.c_int32), ("second_weight", C.c_double), ("one_pass", C.c_int32)]
+                ("strips", C.c_int32), ("second_weight", C.c_double), ("one_pass", C.c_int32),
+                ("pixel", C.c_int32)]
 
 
 _P = C.c_void_p

@@ -58,7 +58,8 @@ enum Phase : int {
     // factor-preconditioned CG in Chronopoulos-Gear form, one pass per iteration
     // (strips with a three-radius halo)
     PH_FW0 = 14,    // u0 = M^{-1} r0, w0 = A u0, gamma0 = r0.u0, delta0 = w0.u0
-    PH_FIT = 15     // one iteration: p, s, x, r, u = M^{-1} r, w = A u and their dots
+    PH_FIT = 15,    // one iteration: p, s, x, r, u = M^{-1} r, w = A u and their dots
+    PH_GA = 16      // pixel launches: the CG iteration's own-row pass (kernel selection only)
 };
 
 // per (segment, column) CG state, struct of arrays of length nseg * d
@@ -127,6 +128,7 @@ struct KA {
     int ortho;         // PFE_POLAR / PFE_CHOL
     int sten;          // ELL slots in pixel-stencil order (lower neighbours first)
     const int* dact;   // per segment: active columns (the leading ones; the others stay zero), or null (all d)
+    int pxW, pxH;      // pixel launches: the image's width and height (0: not a pixel launch)
 };
 
 // ---------------------------------------------------------------------------
@@ -227,26 +229,41 @@ __device__ __forceinline__ void block_partials(const double (&acc)[NQ], double* 
 }
 
 // out[q * d + c] = sum over workgroups b in [b0, b1) of src[(q * stride + b) * d + c],
-// in a fixed order; one workgroup; sh needs max(blockDim, nq * d) doubles.
+// in a fixed order; one workgroup; sh needs blockDim doubles (out must not
+// overlap them).  Thread idx = s * pairs + pr (pr = q * d + c, so a wave reads
+// consecutive columns of one workgroup) sums the workgroups b0 + s + k team, up
+// to eight loads in flight; then the team's sums of each pair are added in s
+// order.  The partials are usually written on other XCDs, so each round of
+// loads is a trip beyond L2: the team is as large as makes one round of eight
+// loads per thread, within the workgroup.
 __device__ __forceinline__ void reduce_range(const double* src, int stride, int b0, int b1, int d, int nq, double* out,
                              double* sh) {
+    constexpr int U = 8;
     const int pairs = nq * d;
+    const int nb = b1 - b0;
     int team = (int)blockDim.x / pairs;
-    if (team > 64) team = 64;
+    team = min(team, (nb + U - 1) / U);
     if (team < 1) team = 1;
     for (int idx = threadIdx.x; idx < pairs * team; idx += blockDim.x) {
-        int pr = idx / team, sidx = idx - pr * team;
-        int q = pr / d, c = pr - q * d;
+        const int s = idx / pairs, pr = idx - s * pairs;
+        const int q = pr / d, c = pr - q * d;
         const double* base = src + (size_t)q * stride * d + c;
         double acc = 0.0;
-#pragma unroll 4
-        for (int b = b0 + sidx; b < b1; b += team) acc += base[(size_t)b * d];
+        int b = b0 + s;
+        for (; b + (U - 1) * team < b1; b += U * team) {
+            double v[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) v[k] = base[(size_t)(b + k * team) * d];
+#pragma unroll
+            for (int k = 0; k < U; ++k) acc += v[k];
+        }
+        for (; b < b1; b += team) acc += base[(size_t)b * d];
         sh[idx] = acc;
     }
     __syncthreads();
     for (int pr = threadIdx.x; pr < pairs; pr += blockDim.x) {
         double acc = 0.0;
-        for (int s = 0; s < team; ++s) acc += sh[pr * team + s];
+        for (int s = 0; s < team; ++s) acc += sh[s * pairs + pr];
         out[pr] = acc;
     }
     __syncthreads();
@@ -2813,15 +2830,17 @@ __global__ void __launch_bounds__(kBlock) k_st_eu(KA<T> a) {
     st_eu<KC>(a, logical_block(a.nblk), sh);
 }
 
-// V consecutive columns of one row, moved as one 4-, 8- or 16-byte access
-template <typename T, int V> struct VecOf;
-template <> struct VecOf<float, 1> { using type = float; };
-template <> struct VecOf<float, 2> { using type = float2; };
-template <> struct VecOf<float, 4> { using type = float4; };
-template <> struct VecOf<double, 1> { using type = double; };
-template <> struct VecOf<double, 2> { using type = double2; };
+// V consecutive columns of one row as one 4-, 8- or 16-byte access: an aligned
+// array of V elements (the loads and stores move the whole array; the lanes are
+// plain array elements, so no element is written through a pointer of another type)
 template <typename T, int V>
-__device__ __forceinline__ T& lane_el(typename VecOf<T, V>::type& v, int u) { return reinterpret_cast<T*>(&v)[u]; }
+struct alignas(sizeof(T) * V) Lanes {
+    T v[V];
+};
+template <typename T, int V>
+__device__ __forceinline__ Lanes<T, V> ld_lanes(const T* p) { return *reinterpret_cast<const Lanes<T, V>*>(p); }
+template <typename T, int V>
+__device__ __forceinline__ void st_lanes(T* p, const Lanes<T, V>& x) { *reinterpret_cast<Lanes<T, V>*>(p) = x; }
 
 // Edge update of the pixel-stencil layouts with b once per undirected edge (the
 // PH_EU arithmetic without r0, element by element and in the same slot order):
@@ -2834,7 +2853,7 @@ __device__ __forceinline__ T& lane_el(typename VecOf<T, V>::type& v, int u) { re
 // otherwise (batches) they are.
 template <typename T, int KC, int V, bool GEO>
 __global__ void __launch_bounds__(kBlock) k_eu_px(KA<T> a, int W, int H) {
-    using VT = typename VecOf<T, V>::type;
+    using VT = Lanes<T, V>;
     using S = Sten<KC>;
     constexpr int KH = KC / 2;
     constexpr int G = (KC < 8) ? KC : 8;   // slots whose loads are issued together
@@ -2847,10 +2866,10 @@ __global__ void __launch_bounds__(kBlock) k_eu_px(KA<T> a, int W, int H) {
     const size_t e = (size_t)i * d + c0;
     const T* bread = a.bsb[a.bpar & 1];
     T* bwrite = a.bsb[(a.bpar & 1) ^ 1];
-    const VT yi = *reinterpret_cast<const VT*>(a.Y + e);
+    const VT yi = ld_lanes<T, V>(a.Y + e);
     VT acc;
 #pragma unroll
-    for (int u = 0; u < V; ++u) lane_el<T, V>(acc, u) = T(0);
+    for (int u = 0; u < V; ++u) acc.v[u] = T(0);
     int py = 0, px = 0;
     if constexpr (GEO) {
         py = i / W;
@@ -2876,47 +2895,297 @@ __global__ void __launch_bounds__(kBlock) k_eu_px(KA<T> a, int W, int H) {
             ss[k] = (kk < KH) ? sl : (size_t)(KC - 1 - kk) * a.n + jj[k];
             if (a.b_zero) {
 #pragma unroll
-                for (int u = 0; u < V; ++u) lane_el<T, V>(bo[k], u) = T(0);
+                for (int u = 0; u < V; ++u) bo[k].v[u] = T(0);
             } else {
-                bo[k] = *reinterpret_cast<const VT*>(bread + ss[k] * d + c0);
+                bo[k] = ld_lanes<T, V>(bread + ss[k] * d + c0);
                 if (kk >= KH) {
 #pragma unroll
-                    for (int u = 0; u < V; ++u) lane_el<T, V>(bo[k], u) = -lane_el<T, V>(bo[k], u);
+                    for (int u = 0; u < V; ++u) bo[k].v[u] = -bo[k].v[u];
                 }
             }
         }
 #pragma unroll
-        for (int k = 0; k < G; ++k) yj[k] = *reinterpret_cast<const VT*>(a.Y + (size_t)jj[k] * d + c0);
+        for (int k = 0; k < G; ++k) yj[k] = ld_lanes<T, V>(a.Y + (size_t)jj[k] * d + c0);
 #pragma unroll
         for (int k = 0; k < G; ++k) {
             const int kk = k0 + k;
             VT bn, dn;
 #pragma unroll
             for (int u = 0; u < V; ++u) {
-                VT yv = yi;
-                const T tv = fma_t(ww[k], lane_el<T, V>(yv, u) - lane_el<T, V>(yj[k], u), lane_el<T, V>(bo[k], u));
+                const T tv = fma_t(ww[k], yi.v[u] - yj[k].v[u], bo[k].v[u]);
                 const T dv = shrink(tv, a.gamma);
                 const T b1 = tv - dv;
-                lane_el<T, V>(bn, u) = b1;
-                lane_el<T, V>(dn, u) = dv;
-                lane_el<T, V>(acc, u) = fma_t(ww[k], dv - b1, lane_el<T, V>(acc, u));
+                bn.v[u] = b1;
+                dn.v[u] = dv;
+                acc.v[u] = fma_t(ww[k], dv - b1, acc.v[u]);
             }
             if (kk < KH) {
-                *reinterpret_cast<VT*>(bwrite + ss[k] * d + c0) = bn;
-                if (a.keep_split) *reinterpret_cast<VT*>(a.ds + ss[k] * d + c0) = dn;
+                st_lanes<T, V>(bwrite + ss[k] * d + c0, bn);
+                if (a.keep_split) st_lanes<T, V>(a.ds + ss[k] * d + c0, dn);
             }
         }
     }
     const T sq = a.sqrtD[i];
-    VT pv = *reinterpret_cast<const VT*>(a.P + e);
-    VT bv = *reinterpret_cast<const VT*>(a.B + e);
+    VT pv = ld_lanes<T, V>(a.P + e);
+    VT bv = ld_lanes<T, V>(a.B + e);
     VT rv;
 #pragma unroll
     for (int u = 0; u < V; ++u) {
-        const T split = mul_t(a.half_r, mul_t(sq, lane_el<T, V>(pv, u) - lane_el<T, V>(bv, u)));
-        lane_el<T, V>(rv, u) = fma_t(a.c_off, lane_el<T, V>(acc, u), split);
+        const T split = mul_t(a.half_r, mul_t(sq, pv.v[u] - bv.v[u]));
+        rv.v[u] = fma_t(a.c_off, acc.v[u], split);
     }
-    *reinterpret_cast<VT*>(a.rhs + e) = rv;
+    st_lanes<T, V>(a.rhs + e, rv);
+}
+
+// ---------------------------------------------------------------------------
+// Pixel launches (one image of a pixel-stencil layout, Jacobi PCG): the
+// residual, w0 and each CG iteration as per-pixel kernels.  Logical workgroup
+// lb owns the pixels [row0[lb], row0[lb + 1]) and walks them kBlock / (d / V)
+// at a time, one thread per pixel and V consecutive columns (16-byte accesses
+// where d allows); neighbour j of slot k is the stencil offset (slots leaving
+// the image have weight 0 and point at the pixel itself, as in the slot
+// layout).  The CG iteration runs in two passes, as on general layouts: the
+// own-row updates storing u' = r' / diag(A) (k_px_ga), then w' = A u' gathering
+// u' alone (k_px_gb); the neighbours' values come through L2 rather than an
+// LDS ring, which keeps LDS small (10 KB) and the grid full.  The per-element
+// arithmetic and slot order are those of the row-chunk phases.
+// ---------------------------------------------------------------------------
+constexpr int kPxSmemDoubles = 1024 + 3 * kMaxD;   // block partials of one quantity (V <= 4), finaliser
+
+// neighbour of slot k of pixel i at (py, px) of a W x H image
+template <int KC>
+__device__ __forceinline__ int px_nb(int i, int py, int px, int W, int H, int k) {
+    using S = Sten<KC>;
+    const int yy = py + S::dy(k), xx = px + S::dx(k);
+    return (yy >= 0 && yy < H && xx >= 0 && xx < W) ? i + S::dy(k) * W + S::dx(k) : i;
+}
+
+// per-thread FP64 accumulators of V columns -> the workgroup's partial of each
+// (quantity, column) in part row qout[q]: one column lane u at a time, staged
+// in LDS (pixel slot qp, thread lane l -> column l V + u), then one thread per
+// column adds the workgroup's pixel slots in order
+template <int NQ, int V>
+__device__ __forceinline__ void block_partials_px(const double (&acc)[NQ][V], const int (&qout)[NQ], double* sh,
+                                                  int d, double* part, int nblk, int lb) {
+    const int t = threadIdx.x, L = d / V, ppb = kBlock / L;
+    const int qp = t / L;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            if (qp < ppb) sh[t] = acc[q][u];
+            __syncthreads();
+            if (t < L) {
+                double s = 0.0;
+                for (int k = 0; k < ppb; ++k) s += sh[k * L + t];
+                part[((size_t)qout[q] * nblk + lb) * d + t * V + u] = s;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// the pixels of logical workgroup lb, kBlock / (d / V) per step: f(i, e, c0)
+// for each of this thread's pixels (element e = i d + c0)
+template <int V, typename T, class F>
+__device__ __forceinline__ void px_walk(const KA<T>& a, int lb, F&& f) {
+    const int d = a.d, L = d / V, ppb = kBlock / L;
+    const int qp = (int)threadIdx.x / L;
+    if (qp >= ppb) return;
+    const int c0 = ((int)threadIdx.x - qp * L) * V;
+    const int r1 = a.row0[lb + 1];
+    for (int i = a.row0[lb] + qp; i < r1; i += ppb) f(i, (size_t)i * d + c0, c0);
+}
+
+// residual r0 = rhs - A x (PH_E0: rhs = r/2 D^{1/2} (P - B), stored when
+// store_rhs; PH_R0: the stored rhs), with u0 = r0 / diag(A) stored for w0;
+// partials of rhs.rhs and r0.r0 (the st_res / ph_residual arithmetic)
+template <typename T, int KC, int V>
+__global__ void __launch_bounds__(kBlock) k_px_res(KA<T> a, int mode) {
+    using VT = Lanes<T, V>;
+    __shared__ double sh[kPxSmemDoubles];
+    const int lb = logical_block(a.nblk);
+    const int W = a.pxW, H = a.pxH;
+    double acc[2][V] = {};
+    px_walk<V>(a, lb, [&](int i, size_t e, int c0) {
+        const int py = i / W, px = i - py * W;
+        VT accA;
+#pragma unroll
+        for (int u = 0; u < V; ++u) accA.v[u] = T(0);
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const T wk = a.sw[(size_t)k * a.n + i];
+            VT xj = ld_lanes<T, V>(a.x + (size_t)px_nb<KC>(i, py, px, W, H, k) * a.d + c0);
+            const T w2 = mul_t(wk, wk);
+#pragma unroll
+            for (int u = 0; u < V; ++u) accA.v[u] = fma_t(w2, xj.v[u], accA.v[u]);
+        }
+        VT rhs;
+        if (mode == PH_R0) {
+            rhs = ld_lanes<T, V>(a.rhs + e);
+        } else {
+            const T sq = a.sqrtD[i];
+            VT pv = ld_lanes<T, V>(a.P + e);
+            VT bv = ld_lanes<T, V>(a.B + e);
+#pragma unroll
+            for (int u = 0; u < V; ++u)
+                rhs.v[u] = mul_t(a.half_r, mul_t(sq, pv.v[u] - bv.v[u]));
+            if (a.store_rhs) st_lanes<T, V>(a.rhs + e, rhs);
+        }
+        const T dA = a.diagA[i], inv = a.invdiag[i];
+        VT xi = ld_lanes<T, V>(a.x + e);
+        VT rv, uv;
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            const T ax = fma_t(dA, xi.v[u], -mul_t(a.c_off, accA.v[u]));
+            const T r = rhs.v[u] - ax;
+            rv.v[u] = r;
+            uv.v[u] = mul_t(inv, r);
+            acc[0][u] += (double)rhs.v[u] * (double)rhs.v[u];
+            acc[1][u] += (double)r * (double)r;
+        }
+        st_lanes<T, V>(a.rb[0] + e, rv);
+        st_lanes<T, V>(a.zl + e, uv);
+    });
+    const int qo[2] = {0, 1};
+    block_partials_px<2, V>(acc, qo, sh, a.d, a.part, a.nblk, lb);
+    if (last_of_launch(a, 2, sh)) fin_res(a, sh, grouped_fin(a));
+}
+
+// w = A u for u in zl: the neighbours' u gathered, slot loads issued in groups
+template <typename T, int KC, int V>
+__device__ __forceinline__ Lanes<T, V> px_apply(const KA<T>& a, const T* u, int i, int c0,
+                                                                const Lanes<T, V>& ui) {
+    using VT = Lanes<T, V>;
+    constexpr int G = (KC < 8) ? KC : 8;
+    const int W = a.pxW, H = a.pxH, d = a.d;
+    const int py = i / W, px = i - py * W;
+    VT accA;
+#pragma unroll
+    for (int u0 = 0; u0 < V; ++u0) accA.v[u0] = T(0);
+#pragma unroll
+    for (int k0 = 0; k0 < KC; k0 += G) {
+        T ww[G];
+        VT uj[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            ww[k] = a.sw[(size_t)(k0 + k) * a.n + i];
+            uj[k] = ld_lanes<T, V>(u + (size_t)px_nb<KC>(i, py, px, W, H, k0 + k) * d + c0);
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const T w2 = mul_t(ww[k], ww[k]);
+#pragma unroll
+            for (int q = 0; q < V; ++q) accA.v[q] = fma_t(w2, uj[k].v[q], accA.v[q]);
+        }
+    }
+    const T dA = a.diagA[i];
+    VT wv;
+#pragma unroll
+    for (int q = 0; q < V; ++q) wv.v[q] = fma_t(dA, ui.v[q], -mul_t(a.c_off, accA.v[q]));
+    return wv;
+}
+
+// w0 = A u0 (u0 = r0 / diag(A) in zl); partials of r0.u0 and w0.u0 (the st_w0 arithmetic)
+template <typename T, int KC, int V>
+__global__ void __launch_bounds__(kBlock) k_px_w0(KA<T> a) {
+    using VT = Lanes<T, V>;
+    __shared__ double sh[kPxSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    const int lb = logical_block(a.nblk);
+    double acc[2][V] = {};
+    px_walk<V>(a, lb, [&](int i, size_t e, int c0) {
+        VT ui = ld_lanes<T, V>(a.zl + e);
+        VT ri = ld_lanes<T, V>(a.rb[0] + e);
+        VT wv = px_apply<T, KC, V>(a, a.zl, i, c0, ui);
+        st_lanes<T, V>(a.wb[0] + e, wv);
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            acc[0][u] += (double)ri.v[u] * (double)ui.v[u];
+            acc[1][u] += (double)wv.v[u] * (double)ui.v[u];
+        }
+    });
+    const int qo[2] = {0, 1};
+    block_partials_px<2, V>(acc, qo, sh, a.d, a.part, a.nblk, lb);
+    if (last_of_launch(a, 2, sh)) fin_w0(a, sh, grouped_fin(a));
+}
+
+// CG iteration, pass 1 (the ph_ga arithmetic, in place on buffer 0): p, s, x,
+// r' = r - alpha s, u' = r' / diag(A) into zl; partials r'.u' (q0), r'.r' (q2)
+template <typename T, int V>
+__global__ void __launch_bounds__(kBlock) k_px_ga(KA<T> a) {
+    using VT = Lanes<T, V>;
+    __shared__ double sh[kPxSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    const int lb = logical_block(a.nblk);
+    const bool first = ld_flag(&a.S->it) == 0;
+    const int d = a.d;
+    double acc[2][V] = {};
+    {
+        const int L = d / V;
+        const int c0 = ((int)threadIdx.x % L) * V;
+        T alpha[V], beta[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            alpha[u] = (T)a.cs.alpha[c0 + u < d ? c0 + u : 0];
+            beta[u] = (T)a.cs.beta[c0 + u < d ? c0 + u : 0];
+        }
+        px_walk<V>(a, lb, [&](int i, size_t e, int) {
+            const T inv = a.invdiag[i];
+            VT r = ld_lanes<T, V>(a.rb[0] + e);
+            VT pold = ld_lanes<T, V>(a.p + e);
+            VT sp = ld_lanes<T, V>(a.sb[0] + e);
+            VT w = ld_lanes<T, V>(a.wb[0] + e);
+            VT x = ld_lanes<T, V>(a.x + e);
+            VT pn, sn, xn, rn, un;
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                const T ri = r.v[u];
+                const T ui = mul_t(inv, ri);
+                const T pi = first ? ui : fma_t(beta[u], pold.v[u], ui);
+                const T si = cg_s(first, beta[u], sp.v[u], w.v[u]);
+                const T rn_i = cg_r(alpha[u], si, ri);
+                const T un_i = mul_t(inv, rn_i);
+                pn.v[u] = pi;
+                sn.v[u] = si;
+                xn.v[u] = fma_t(alpha[u], pi, x.v[u]);
+                rn.v[u] = rn_i;
+                un.v[u] = un_i;
+                acc[0][u] += (double)rn_i * (double)un_i;
+                acc[1][u] += (double)rn_i * (double)rn_i;
+            }
+            st_lanes<T, V>(a.p + e, pn);
+            st_lanes<T, V>(a.sb[0] + e, sn);
+            st_lanes<T, V>(a.x + e, xn);
+            st_lanes<T, V>(a.rb[0] + e, rn);
+            st_lanes<T, V>(a.zl + e, un);
+        });
+    }
+    const int qo[2] = {0, 2};
+    block_partials_px<2, V>(acc, qo, sh, d, a.part, a.nblk, lb);
+}
+
+// CG iteration, pass 2 (the ph_gb arithmetic): w' = A u'; partial w'.u' (q1); finaliser
+template <typename T, int KC, int V>
+__global__ void __launch_bounds__(kBlock) k_px_gb(KA<T> a) {
+    using VT = Lanes<T, V>;
+    __shared__ double sh[kPxSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    const int lb = logical_block(a.nblk);
+    double acc[1][V] = {};
+    px_walk<V>(a, lb, [&](int i, size_t e, int c0) {
+        VT ui = ld_lanes<T, V>(a.zl + e);
+        VT wv = px_apply<T, KC, V>(a, a.zl, i, c0, ui);
+        st_lanes<T, V>(a.wb[0] + e, wv);
+#pragma unroll
+        for (int u = 0; u < V; ++u) acc[0][u] += (double)wv.v[u] * (double)ui.v[u];
+    });
+    const int qo[1] = {1};
+    block_partials_px<1, V>(acc, qo, sh, a.d, a.part, a.nblk, lb);
+    if (last_of_launch(a, 3, sh)) {
+        fin_it(a, sh, grouped_fin(a));
+        if (threadIdx.x == 0 && a.S->done) solve_stats(a);
+    }
 }
 
 // learned-preconditioner PCG phases on strips
@@ -3696,6 +3965,8 @@ struct pfe_ctx {
     Partition ps;            // strip partition of pixel grids (ps.nblk == 0: not available)
     Partition pl;            // strips with a two-radius halo (fused learned apply)
     Partition pf;            // strips with a three-radius halo (one-pass factor CG)
+    Partition px;            // pixel launches: contiguous pixel ranges (px.nblk == 0: not available)
+    int want_px = 0;         // Jacobi PCG of a one-image pixel grid by the per-pixel kernels
     int one_pass = 0;        // factor preconditioners on strips: one pass per CG iteration (0: two)
     int eu_px = 1;           // pixel stencils with b once per edge: the edge update by the per-pixel
                              // kernel (0: by the strip or row-chunk phase kernel)
@@ -4009,11 +4280,72 @@ KA<T> make_args(pfe_ctx* c, const Partition& pt) {
         }                                                                                          \
     } while (0)
 
+// pixel launch kernels of the ELL width K and V columns per thread
+template <typename T, int V>
+const void* px_kernel(int ph, int K) {
+#define PFE_PXSEL(KN) switch (K) {                                                      \
+        case 4: return reinterpret_cast<const void*>(&KN<T, 4, V>);                    \
+        case 8: return reinterpret_cast<const void*>(&KN<T, 8, V>);                    \
+        case 24: return reinterpret_cast<const void*>(&KN<T, 24, V>);                  \
+        default: return nullptr; }
+    switch (ph) {
+        case PH_R0: PFE_PXSEL(k_px_res)
+        case PH_W0: PFE_PXSEL(k_px_w0)
+        case PH_IT: PFE_PXSEL(k_px_gb)
+        case PH_GA: return reinterpret_cast<const void*>(&k_px_ga<T, V>);
+        default: return nullptr;
+    }
+#undef PFE_PXSEL
+}
+
+// columns per thread of the per-pixel kernels: 16-byte accesses where d allows
+template <typename T>
+int px_cols(int d) {
+    static const int force = getenv("PFE_PX_COLS") ? atoi(getenv("PFE_PX_COLS")) : 0;   // launch-shape experiments
+    if ((force == 1 || force == 2 || force == 4) && d % force == 0 && force * (int)sizeof(T) <= 16) return force;
+    return (sizeof(T) == 4) ? ((d % 4 == 0) ? 4 : 1) : ((d % 2 == 0) ? 2 : 1);
+}
+
+template <typename T>
+const void* px_kernel_for(int ph, int K, int d) {
+    const int V = px_cols<T>(d);
+    if constexpr (sizeof(T) == 4) {
+        if (V == 4) return px_kernel<T, 4>(ph, K);
+    }
+    if (V == 2) return px_kernel<T, 2>(ph, K);
+    return px_kernel<T, 1>(ph, K);
+}
+
 template <typename T>
 pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0) {
     const dim3 grid(a.nblk);
     hipStream_t st = c->stream;
     const int K = a.ell_K;
+    if (a.pxW > 0) {
+        // pixel launch: the residual with r0, w0 and the CG iteration (two kernels)
+        KA<T> args = a;
+        int pm = ph;
+        void* kp1[] = {(void*)&args};
+        void* kp2[] = {(void*)&args, (void*)&pm};
+        const void* fn = nullptr;
+        if ((ph == PH_E0 || ph == PH_R0) && do_r0) {
+            fn = px_kernel_for<T>(PH_R0, K, a.d);
+            if (fn) { PFE_CHECK_HIP(hipLaunchKernel(fn, grid, dim3(kBlock), kp2, 0, st)); return PFE_OK; }
+        } else if (ph == PH_W0) {
+            fn = px_kernel_for<T>(PH_W0, K, a.d);
+            if (fn) { PFE_CHECK_HIP(hipLaunchKernel(fn, grid, dim3(kBlock), kp1, 0, st)); return PFE_OK; }
+        } else if (ph == PH_IT) {
+            const void* fa = px_kernel_for<T>(PH_GA, K, a.d);
+            fn = px_kernel_for<T>(PH_IT, K, a.d);
+            if (fa && fn) {
+                PFE_CHECK_HIP(hipLaunchKernel(fa, grid, dim3(kBlock), kp1, 0, st));
+                PFE_CHECK_HIP(hipLaunchKernel(fn, grid, dim3(kBlock), kp1, 0, st));
+                return PFE_OK;
+            }
+        }
+        set_error("phase %d has no pixel-launch kernel", ph);
+        return PFE_E_STATE;
+    }
     if (a.geo) {
         // strip partition: only the phases with a strip kernel
         switch (ph) {
@@ -4164,6 +4496,9 @@ pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, const KA<T>*
                 add(kernel_for<T>(PH_LC, K, st), p3, a.nblk);
                 add(kernel_for<T>(PH_LD, K, st), p2, a.nblk);
             }
+        } else if (a.pxW > 0) {
+            add(px_kernel_for<T>(PH_GA, K, a.d), p1, a.nblk);
+            add(px_kernel_for<T>(PH_IT, K, a.d), p1, a.nblk);
         } else if (!st && K != 4 && K != 8 && K != 24) {
             add(reinterpret_cast<const void*>(&k_cg_ga<T>), p1, a.nblk);
             add(reinterpret_cast<const void*>(&k_cg_gb<T>), p1, a.nblk);
@@ -4330,6 +4665,30 @@ pfe_status pcg_solve_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as, int res_ph)
 // has one and the context wants it
 inline bool use_strips(const pfe_ctx* c) { return c->want_strips > 0 && c->ps.nblk > 0; }
 
+// pixel launches: Jacobi PCG of a one-image pixel grid, when the context wants them
+inline bool use_px(const pfe_ctx* c) { return c->want_px && c->px.nblk > 0 && c->prm.precond == PFE_JACOBI; }
+
+// arguments of the PCG phases (residual, w0, iterations) for the iterate and
+// right-hand side of a: pixel launches, strips or row chunks
+template <typename T>
+KA<T> pcg_args(pfe_ctx* c, const KA<T>& a) {
+    if (use_px(c)) {
+        KA<T> ap = make_args<T>(c, c->px);
+        ap.x = a.x;
+        ap.rhs = a.rhs;
+        ap.pxW = c->g->seg_W[0];
+        ap.pxH = c->g->seg_H[0];
+        return ap;
+    }
+    if (use_strips(c)) {
+        KA<T> as = make_args<T>(c, c->ps);
+        as.x = a.x;
+        as.rhs = a.rhs;
+        return as;
+    }
+    return a;
+}
+
 // (re)build the strip partition for the wanted number of waves
 pfe_status setup_strips(pfe_ctx* c) {
     if (c->want_strips <= 0 || c->strip_slots <= 0 || c->ps_waves == c->want_strips) return PFE_OK;
@@ -4406,7 +4765,7 @@ pfe_status launch_eu_px(pfe_ctx* c, const KA<T>& a) {
 template <typename T>
 pfe_status inner_at(pfe_ctx* c, int l) {
     KA<T> a = make_args<T>(c, c->pm);
-    const KA<T> as = use_strips(c) ? make_args<T>(c, c->ps) : a;
+    const KA<T> as = pcg_args<T>(c, a);
     // cold start: the solve begins from Y = 0 (the right-hand side does not
     // depend on Y; the previous edge update has already consumed it)
     if (c->prm.cold_start) PFE_CHECK_HIP(hipMemsetAsync(c->Y, 0, (size_t)c->n * c->d * sizeof(T), c->stream));
@@ -4514,7 +4873,8 @@ pfe_status read_info(pfe_ctx* c, pfe_step_info* info) {
         info->status = h.status;
         info->fallbacks = h.fallbacks;
         info->workgroups = c->launched_coop ? c->pc.nblk : 0;
-        info->flags = ((c->launched_coop && c->cache_np > 0) ? 1 : 0) | ((!c->launched_coop && use_strips(c)) ? 2 : 0);
+        info->flags = ((c->launched_coop && c->cache_np > 0) ? 1 : 0) | ((!c->launched_coop && use_strips(c)) ? 2 : 0) |
+                      ((!c->launched_coop && use_px(c)) ? 4 : 0);
     }
     if (h.status != 0) {
         set_error("%s", pfe_status_string((pfe_status)h.status));
@@ -4553,6 +4913,7 @@ void free_ctx(pfe_ctx* c) {
     free_partition(c->ps);
     free_partition(c->pl);
     free_partition(c->pf);
+    free_partition(c->px);
     if (c->cg_exec) (void)hipGraphExecDestroy(c->cg_exec);
     c->cg_exec = nullptr;
 }
@@ -4960,9 +5321,22 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
         s = setup_strips(c);
         c->want_strips = want;
     }
+    if (s == PFE_OK && g->stencil && (g->ell_K == 4 || g->ell_K == 8 || g->ell_K == 24) && c->nseg == 1 &&
+        g->seg_W.size() == 1 && g->seg_W[0] > 0 && g->seg_H[0] > 0 && (int64_t)g->seg_W[0] * g->seg_H[0] == c->n) {
+        // pixel launches: one wave of workgroups (four per CU), each a contiguous pixel range
+        const int V = (p->dtype == PFE_FP64) ? px_cols<double>((int)c->d) : px_cols<float>((int)c->d);
+        const int ppb = kBlock / ((int)c->d / V);
+        int want_px = 4 * ncu;
+        if (const char* ev = getenv("PFE_PX_BLOCKS")) want_px = std::max(kNumXcd, atoi(ev));   // launch-shape experiments
+        const int64_t steps = (c->n + ppb - 1) / ppb;
+        want_px = (int)std::min<int64_t>(want_px, steps);
+        want_px -= want_px % kNumXcd;
+        if (want_px >= kNumXcd) s = make_partition(seg_rows, want_px, ppb, 1, c->px);
+    }
+    if (const char* ev = getenv("PFE_PIXEL")) c->want_px = atoi(ev) != 0;   // launch-shape experiments
     if (s != PFE_OK) { free_ctx(c); delete c; return s; }
-    const int nblk_max = std::max(std::max(std::max(c->pm.nblk, c->pc.nblk), std::max(c->ps.nblk, c->pl.nblk)),
-                                  c->pf.nblk);
+    const int nblk_max = std::max(std::max(std::max(std::max(c->pm.nblk, c->pc.nblk), std::max(c->ps.nblk, c->pl.nblk)),
+                                  c->pf.nblk), c->px.nblk);
     c->part_blocks = nblk_max;
     if (s == PFE_OK) s = setup_strips(c);
     if (s != PFE_OK) { free_ctx(c); delete c; return s; }
@@ -5129,13 +5503,16 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
     if (n_results) *n_results = 0;
     const bool f64 = c->prm.dtype == PFE_FP64;
     const size_t nd = (size_t)c->n * c->d * c->esz;
-    struct Shape { int persistent, team, cache, strips; double w2; int one_pass; };
-    const Shape shapes[] = {{1, 64, 1, 0, 1.0, 0}, {1, 64, 0, 0, 1.0, 0}, {1, 1, 1, 0, 1.0, 0}, {1, 1, 0, 0, 1.0, 0},
-                            {1, 1, 1, 0, 0.9, 0}, {1, 1, 0, 0, 0.9, 0}, {1, 1, 1, 0, 0.85, 0}, {1, 1, 0, 0, 0.85, 0},
-                            {1, 1, 1, 0, 0.8, 0}, {1, 1, 0, 0, 0.8, 0},
-                            {0, c->team, 0, 0, 1.0, 0}, {0, c->team, 0, 1, 1.0, 0}, {0, c->team, 0, 2, 1.0, 0},
-                            {0, c->team, 0, 1, 1.0, 1}, {0, c->team, 0, 2, 1.0, 1}};
-    const Shape orig{c->prm.persistent, c->team, c->want_cache, c->want_strips, c->second_weight, c->one_pass};
+    struct Shape { int persistent, team, cache, strips; double w2; int one_pass, pixel; };
+    const Shape shapes[] = {{1, 64, 1, 0, 1.0, 0, 0}, {1, 64, 0, 0, 1.0, 0, 0}, {1, 1, 1, 0, 1.0, 0, 0},
+                            {1, 1, 0, 0, 1.0, 0, 0}, {1, 1, 1, 0, 0.9, 0, 0}, {1, 1, 0, 0, 0.9, 0, 0},
+                            {1, 1, 1, 0, 0.85, 0, 0}, {1, 1, 0, 0, 0.85, 0, 0}, {1, 1, 1, 0, 0.8, 0, 0},
+                            {1, 1, 0, 0, 0.8, 0, 0},
+                            {0, c->team, 0, 0, 1.0, 0, 0}, {0, c->team, 0, 1, 1.0, 0, 0}, {0, c->team, 0, 2, 1.0, 0, 0},
+                            {0, c->team, 0, 1, 1.0, 1, 0}, {0, c->team, 0, 2, 1.0, 1, 0},
+                            {0, c->team, 0, 0, 1.0, 0, 1}};
+    const Shape orig{c->prm.persistent, c->team, c->want_cache, c->want_strips, c->second_weight, c->one_pass,
+                     c->want_px};
     char* save = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     pfe_status st = PFE_OK;
@@ -5174,7 +5551,9 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
             if (sh.strips && c->strip_slots == 0) continue;
             if (sh.w2 != 1.0 && c->per_cu != 2) continue;
             if (sh.one_pass && (c->prm.precond == PFE_JACOBI || c->fcg_slots == 0)) continue;
+            if (sh.pixel && (c->prm.precond != PFE_JACOBI || c->px.nblk == 0)) continue;
             c->one_pass = sh.one_pass;
+            c->want_px = sh.pixel;
             c->prm.persistent = sh.persistent;
             c->team = sh.team;
             c->want_cache = sh.cache;
@@ -5212,7 +5591,10 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
             r.strips = sh.strips;
             r.second_weight = sh.persistent ? sh.w2 : 1.0;
             r.one_pass = sh.one_pass;
-            r.workgroups = sh.persistent ? c->pc.nblk : (sh.one_pass ? c->pf.nblk : (sh.strips ? c->ps.nblk : c->pm.nblk));
+            r.pixel = sh.pixel;
+            r.workgroups = sh.persistent ? c->pc.nblk
+                                         : (sh.pixel ? c->px.nblk
+                                                     : (sh.one_pass ? c->pf.nblk : (sh.strips ? c->ps.nblk : c->pm.nblk)));
             r.ms = ms / trials;
             found.push_back(r);
             if (best < 0 || r.ms < best_ms) { best = (int)found.size() - 1; best_ms = r.ms; }
@@ -5226,6 +5608,7 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
         c->want_strips = found[best].persistent ? orig.strips : found[best].strips;
         c->second_weight = found[best].persistent ? found[best].second_weight : orig.w2;
         c->one_pass = found[best].persistent ? orig.one_pass : found[best].one_pass;
+        c->want_px = found[best].persistent ? orig.pixel : found[best].pixel;
         found[best].chosen = 1;
     } else {
         c->prm.persistent = orig.persistent;
@@ -5234,6 +5617,7 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
         c->want_strips = orig.strips;
         c->second_weight = orig.w2;
         c->one_pass = orig.one_pass;
+        c->want_px = orig.pixel;
     }
     pfe_status s2 = setup_persistent(c);
     if (s2 == PFE_OK) s2 = setup_strips(c);
@@ -5275,6 +5659,10 @@ pfe_status pfe_set_launch_shape(pfe_ctx* c, const pfe_tune_result* sh) {
         set_error("pfe_set_launch_shape: the one-pass factor CG runs on image strips of a pixel-grid graph");
         return PFE_E_ARG;
     }
+    if (!sh->persistent && sh->pixel && c->px.nblk == 0) {
+        set_error("pfe_set_launch_shape: pixel launches need a one-image pixel grid with 4, 8 or 24 slots");
+        return PFE_E_ARG;
+    }
     c->prm.persistent = sh->persistent ? 1 : 0;
     if (sh->persistent) {
         c->team = sh->team;
@@ -5283,6 +5671,7 @@ pfe_status pfe_set_launch_shape(pfe_ctx* c, const pfe_tune_result* sh) {
     } else {
         c->want_strips = sh->strips;
         c->one_pass = sh->one_pass ? 1 : 0;
+        c->want_px = sh->pixel ? 1 : 0;
     }
     PFE_TRY(setup_persistent(c));
     PFE_TRY(setup_strips(c));
@@ -5423,17 +5812,13 @@ pfe_status pfe_pcg(pfe_ctx* c, const void* RHS, void* X, int32_t* iters, pfe_ste
         KA<double> a = make_args<double>(c, c->pm);
         a.x = (double*)X;
         a.rhs = (double*)RHS;
-        KA<double> as = use_strips(c) ? make_args<double>(c, c->ps) : a;
-        as.x = a.x;
-        as.rhs = a.rhs;
+        const KA<double> as = pcg_args<double>(c, a);
         PFE_TRY(pcg_solve_mk(c, a, as, PH_R0));
     } else {
         KA<float> a = make_args<float>(c, c->pm);
         a.x = (float*)X;
         a.rhs = (float*)RHS;
-        KA<float> as = use_strips(c) ? make_args<float>(c, c->ps) : a;
-        as.x = a.x;
-        as.rhs = a.rhs;
+        const KA<float> as = pcg_args<float>(c, a);
         PFE_TRY(pcg_solve_mk(c, a, as, PH_R0));
     }
     if (iters) {

@@ -263,24 +263,25 @@ class Solver:
 
     def autotune(self, trials: int = 2) -> list:
         """Time the candidate launch shapes on this graph and keep the fastest."""
-        res = (L.pfe_tune_result * 16)()
+        res = (L.pfe_tune_result * 32)()
         n = C.c_int()
-        L.check(L.lib.pfe_autotune(self._h, int(trials), res, 16, C.byref(n)), "pfe_autotune",
+        L.check(L.lib.pfe_autotune(self._h, int(trials), res, 32, C.byref(n)), "pfe_autotune",
                 allow=(L.PFE_E_NOCONV,))
         return [dict(persistent=r.persistent, team=r.team, row_cache=r.row_cache, strips=r.strips,
-                     second_weight=r.second_weight, one_pass=r.one_pass, workgroups=r.workgroups, ms=r.ms,
-                     chosen=r.chosen)
+                     second_weight=r.second_weight, one_pass=r.one_pass, pixel=r.pixel, workgroups=r.workgroups,
+                     ms=r.ms, chosen=r.chosen)
                 for r in res[:n.value]]
 
     def set_launch_shape(self, persistent: bool = False, strips: int = 0, team: int = 1, row_cache: bool = False,
-                         second_weight: float = 1.0, one_pass: bool = False) -> None:
+                         second_weight: float = 1.0, one_pass: bool = False, pixel: bool = False) -> None:
         """Run later iterations in the given launch shape (the fields of an
         autotune() result): persistent with teams / row cache / second-workgroup
         share, or one launch per phase on row chunks (strips = 0) or on image
         strips sized for 1 or 2 waves (factor preconditioners: one or two passes
-        per CG iteration)."""
+        per CG iteration), with Jacobi PCG by pixel launches when pixel."""
         sh = L.pfe_tune_result(persistent=int(persistent), team=int(team), row_cache=int(row_cache),
-                               strips=int(strips), second_weight=float(second_weight), one_pass=int(one_pass))
+                               strips=int(strips), second_weight=float(second_weight), one_pass=int(one_pass),
+                               pixel=int(pixel))
         L.check(L.lib.pfe_set_launch_shape(self._h, C.byref(sh)), "pfe_set_launch_shape")
 
     # -- state ---------------------------------------------------------------

@@ -1,0 +1,179 @@
+"""GPU pixel launches: on a one-image pixel grid the Jacobi PCG phases can run
+as per-pixel kernels (one thread per pixel and 1, 2 or 4 columns, neighbours
+through L2): the residual, w0 = A u0, and each CG iteration in two passes (the
+own-row updates storing u' = r'/diag(A), then w' = A u').  The per-element
+arithmetic is the row-chunk phases', so the results agree with the strip and
+row-chunk launches up to the summation order of the FP64 partial sums, and with
+the oracle (Eq. 13 solved by Jacobi-PCG, Algorithms 1-2)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_helpers import banner, gpu_graph, oracle_graph, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def to_np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+# every stencil width, ragged sizes, d with 1, 2 and 4 columns per thread
+CASES = [
+    ("voronoi96x80_8nbr", None, None, None, None),
+    ("voronoi48x40_r2", None, None, None, None),
+    ("voronoi64_4nbr", None, None, None, None),
+    ("ragged37x41_8", 37, 41, 8, 6),
+    ("narrow300x7_r2", 300, 7, -2, 5),
+    ("flat5x333_4", 5, 333, 4, 3),
+    ("wide33x70_d32_r2", 33, 70, -2, 32),
+    ("multi23x95_8_d16", 23, 95, 8, 16),
+]
+
+
+def case_workload(case):
+    name, H, W, st, d = case
+    if H is None:
+        return synth.make_workload(name, 0)
+    return synth.grid_workload(name, H, W, 4, 0.05, 11, gradient=0.2, stencil=st, d=d, n_inner=3, n_outer=2)
+
+
+def run(wl, monkeypatch, pixel, fp64, strips=1, n_outer=2, lam=30.0, r=3.0, graphs=False, tol=None):
+    from paper_1612_06496_amd import Solver
+    monkeypatch.setenv("PFE_PIXEL", "1" if pixel else "0")
+    monkeypatch.setenv("PFE_STRIPS", str(strips))
+    G = gpu_graph(wl)
+    if tol is None:
+        tol = 1e-10 if fp64 else 1e-6
+    S = Solver(G, wl.y0, lam=lam, r=r, n_inner=3, tol=tol, maxit=3000, fp64=fp64, persistent=False, graphs=graphs)
+    info = S.solve(n_outer, info=True)
+    out = {k: to_np(S.get(k)) for k in ("Y", "P", "B")}
+    S.close()
+    G.close()
+    return info, out
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_pixel_launch_matches_strips_and_row_chunks(case, fp64, monkeypatch):
+    wl = case_workload(case)
+    banner(f"pixel launch vs strips / row chunks {case[0]} fp64={fp64}")
+    ip, px = run(wl, monkeypatch, True, fp64)
+    assert ip["flags"] & 4, "the pixel kernels did not run"
+    bound = 1e-10 if fp64 else 1e-5
+    for strips in (1, 0):
+        io, other = run(wl, monkeypatch, False, fp64, strips=strips)
+        assert not (io["flags"] & 4)
+        worst = max(rel(px[k], other[k]) for k in ("Y", "P"))
+        eB = np.linalg.norm(px["B"] - other["B"]) / np.linalg.norm(other["P"])
+        print(f"strips={strips}: Y/P rel {worst:.2e}, B {eB:.2e}; CG iterations "
+              f"{ip['cg_iters_total']} vs {io['cg_iters_total']}")
+        assert worst <= bound and eB <= bound
+        if fp64:
+            assert ip["cg_iters_total"] == io["cg_iters_total"]
+        else:
+            assert abs(ip["cg_iters_total"] - io["cg_iters_total"]) <= max(2, io["cg_iters_total"] // 50)
+
+
+def test_pixel_launch_outer_step_matches_oracle(monkeypatch):
+    """Two SOC iterations by pixel launches in FP64 (ragged 8-neighbour image) against the oracle."""
+    wl = case_workload(CASES[3])
+    banner("pixel launch vs oracle (ragged 37x41)")
+    g = oracle_graph(wl)
+    lam, r = 30.0, 3.0
+    ref = O.pfe_run(g, wl.y0, lam, r, 2, 3)
+    info, got = run(wl, monkeypatch, True, True, lam=lam, r=r, tol=1e-12)
+    assert info["flags"] & 4
+    e = rel(got["P"], ref.P)
+    print(f"P rel err vs oracle {e:.2e}")
+    assert e <= 1e-8
+
+
+def test_pixel_launch_graph_replay_bitwise_and_deterministic(monkeypatch):
+    """CG iterations replayed from HIP graphs (two nodes per iteration) give
+    bitwise the host-launched ones, and a rerun gives bitwise the same state."""
+    wl = synth.make_workload("voronoi48x40_r2", 0)
+    banner("pixel launch + graph replay, determinism")
+    out = [run(wl, monkeypatch, True, False, graphs=g) for g in (True, False, False)]
+    assert out[0][0]["cg_iters_total"] == out[1][0]["cg_iters_total"]
+    for k in ("Y", "P", "B"):
+        assert np.array_equal(out[0][1][k], out[1][1][k])
+        assert np.array_equal(out[1][1][k], out[2][1][k])
+
+
+@pytest.mark.parametrize("name,d", [("voronoi48x40_r2", None), ("voronoi64_4nbr", None), ("voronoi64_4nbr", 3)])
+def test_pixel_launch_pcg_matches_direct_solve(name, d, monkeypatch):
+    """The standalone PCG call by pixel launches (FP64) reaches the direct
+    solution within the condition-number bound of its stopping rule, in the
+    oracle's Jacobi-PCG iteration count (+-1)."""
+    from paper_1612_06496_amd import Solver
+    monkeypatch.setenv("PFE_PIXEL", "1")
+    wl = synth.make_workload(name, 0)
+    y0 = wl.y0 if d is None else wl.y0[:, :d]
+    banner(f"pfe_pcg by pixel launches vs direct solve: {name}")
+    g = oracle_graph(wl)
+    lam, r, tol = 40.0, 2.0, 1e-12
+    G = gpu_graph(wl)
+    S = Solver(G, y0, lam=lam, r=r, n_inner=2, tol=tol, maxit=5000, fp64=True, persistent=False)
+    A = O.system_matrix(g, lam, r)
+    rhs = np.random.default_rng(5).normal(size=(g.n, y0.shape[1]))
+    x, iters, info = S.pcg(rhs, np.zeros_like(rhs))
+    assert info["flags"] & 4
+    exact = O.DirectSolver(A)(rhs)
+    kappa = O.jacobi_condition_number(A)
+    e = rel(to_np(x), exact)
+    print(f"rel err {e:.2e}, kappa {kappa:.1f}, iterations {iters.max()}")
+    assert info["rel_res_max"] <= tol
+    assert e <= kappa * tol * 4
+    _, it_o, _ = O.pcg(A, rhs, np.zeros_like(rhs), 1.0 / A.diagonal(), tol, 5000)
+    assert np.all(np.abs(iters - it_o) <= 1)
+    S.close()
+    G.close()
+
+
+def test_autotune_offers_pixel_launches(monkeypatch):
+    from paper_1612_06496_amd import Solver
+    monkeypatch.delenv("PFE_PIXEL", raising=False)
+    wl = synth.make_workload("voronoi96x80_8nbr", 0)
+    banner("autotune with pixel launches")
+    G = gpu_graph(wl)
+    S = Solver(G, wl.y0, lam=30.0, r=3.0, n_inner=3, tol=1e-6, maxit=1000)
+    res = S.autotune(1)
+    assert any(r["pixel"] == 1 and r["persistent"] == 0 for r in res), res
+    assert sum(r["chosen"] for r in res) == 1
+    S.set_launch_shape(persistent=False, pixel=True)
+    info = S.solve(1, info=True)
+    assert info["flags"] & 4
+    S.close()
+    G.close()
+
+
+def test_pixel_launch_not_offered_for_batches_or_factor_preconditioners(monkeypatch):
+    """Batches (several images) and the learned / FSAI factor preconditioners
+    keep the strip launches: set_launch_shape rejects pixel launches on a batch,
+    and a factor-preconditioned solve on a context that wants them runs on strips."""
+    from paper_1612_06496_amd import Graph, Solver
+    from paper_1612_06496_amd import _lib as L
+    monkeypatch.setenv("PFE_PIXEL", "1")
+    banner("pixel launches: batch rejected, FSAI on strips")
+    wls = synth.make_batch("voronoi_batch5_8nbr")
+    U = Graph.union([gpu_graph(w) for w in wls])
+    S = Solver(U, np.concatenate([w.y0 for w in wls]), lam=20.0, r=2.0, n_inner=2, tol=1e-6, persistent=False)
+    with pytest.raises(L.PFEError):
+        S.set_launch_shape(persistent=False, pixel=True)
+    info = S.solve(1, info=True)
+    assert not (info["flags"] & 4)
+    S.close()
+    wl = synth.make_workload("voronoi48x40_r2", 0)
+    G = gpu_graph(wl)
+    S = Solver(G, wl.y0, lam=20.0, r=2.0, n_inner=2, tol=1e-6, persistent=False)
+    S.set_fsai()
+    info = S.solve(1, info=True)
+    assert not (info["flags"] & 4)
+    S.close()
+    G.close()
