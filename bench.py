@@ -252,7 +252,7 @@ def learned_leg(train_seeds=(1000, 1001, 1002, 1003, 1004), ratios=(1.0, 10.0, 1
                 shape = jshape
                 S.set_launch_shape(persistent=bool(shape["persistent"]), strips=shape["strips"], team=shape["team"],
                                    row_cache=bool(shape["row_cache"]), second_weight=shape["second_weight"],
-                                   pixel=bool(shape["pixel"]))
+                                   pixel=int(shape["pixel"]))
             S.solve(1, allow_noconv=True)
             S.stats(reset=True)
             torch.cuda.synchronize()

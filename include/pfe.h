@@ -282,11 +282,13 @@ typedef struct {
                                 per CG iteration (Chronopoulos-Gear form, M^{-1} r and A M^{-1} r
                                 through three LDS rings over a three-radius halo), 0 = two passes
                                 (A p, then the factor apply with the x, r update) */
-    int32_t pixel;           /* one launch per phase, Jacobi PCG of a one-image pixel grid by per-pixel
-                                kernels: the residual, w0 and each CG iteration in two passes (the
-                                own-row updates storing u' = r'/diag(A), then w' = A u' gathering u'),
-                                one thread per pixel and 1, 2 or 4 columns, neighbours through L2
-                                (flags bit 2 of pfe_step_info) */
+    int32_t pixel;           /* one launch per phase, Jacobi PCG of a one-segment graph (one image or
+                                one edge list) by per-row kernels on 1 or 2 workgroups per CU (0: not):
+                                the residual, w0 and each CG iteration in two passes (the own-row
+                                updates storing u' = r'/diag(A), then w' = A u' gathering u'), one
+                                thread per row (pixel) and 1, 2 or 4 columns, neighbours through L2
+                                from the stencil offsets (pixel grids) or the slot columns (flags
+                                bit 2 of pfe_step_info) */
 } pfe_tune_result;
 
 /* Autotune the launch shape on this context's graph: from the current state

@@ -128,7 +128,8 @@ struct KA {
     int ortho;         // PFE_POLAR / PFE_CHOL
     int sten;          // ELL slots in pixel-stencil order (lower neighbours first)
     const int* dact;   // per segment: active columns (the leading ones; the others stay zero), or null (all d)
-    int pxW, pxH;      // pixel launches: the image's width and height (0: not a pixel launch)
+    int pxl;           // per-row ("pixel") launch of the Jacobi PCG phases
+    int pxW, pxH;      // its image's width and height on pixel-stencil layouts
 };
 
 // ---------------------------------------------------------------------------
@@ -2947,10 +2948,11 @@ __global__ void __launch_bounds__(kBlock) k_eu_px(KA<T> a, int W, int H) {
 // layout).  The CG iteration runs in two passes, as on general layouts: the
 // own-row updates storing u' = r' / diag(A) (k_px_ga), then w' = A u' gathering
 // u' alone (k_px_gb); the neighbours' values come through L2 rather than an
-// LDS ring, which keeps LDS small (10 KB) and the grid full.  The per-element
-// arithmetic and slot order are those of the row-chunk phases.
+// LDS ring, which keeps LDS small (9 KB).  The per-element arithmetic and slot
+// order are those of the row-chunk phases.
 // ---------------------------------------------------------------------------
-constexpr int kPxSmemDoubles = 1024 + 3 * kMaxD;   // block partials of one quantity (V <= 4), finaliser
+constexpr int kPxSmemDoubles = 1024 + 3 * kMaxD;   // block partials of one column lane (kBlock), finaliser
+static_assert(kBlock <= 1024, "the finalisers keep their sums at sh + 1024");
 
 // neighbour of slot k of pixel i at (py, px) of a W x H image
 template <int KC>
@@ -2985,6 +2987,67 @@ __device__ __forceinline__ void block_partials_px(const double (&acc)[NQ][V], co
     }
 }
 
+// sum over the slots k of row i of w_k^2 v_j (slot order), V columns from c0:
+// stencil offsets on pixel grids (KC > 0), the row's slot columns otherwise
+// (ELL or CSR; loads in groups of kGenGroup slots, as in the row-chunk phases)
+template <typename T, int KC, int V>
+__device__ __forceinline__ Lanes<T, V> px_nbsum(const KA<T>& a, const T* v, int i, int c0) {
+    using VT = Lanes<T, V>;
+    const int d = a.d;
+    VT acc;
+#pragma unroll
+    for (int q = 0; q < V; ++q) acc.v[q] = T(0);
+    if constexpr (KC > 0) {
+        constexpr int G = (KC < 8) ? KC : 8;
+        const int W = a.pxW, H = a.pxH;
+        const int py = i / W, px = i - py * W;
+#pragma unroll
+        for (int k0 = 0; k0 < KC; k0 += G) {
+            T ww[G];
+            VT vj[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                ww[k] = a.sw[(size_t)(k0 + k) * a.n + i];
+                vj[k] = ld_lanes<T, V>(v + (size_t)px_nb<KC>(i, py, px, W, H, k0 + k) * d + c0);
+            }
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const T w2 = mul_t(ww[k], ww[k]);
+#pragma unroll
+                for (int q = 0; q < V; ++q) acc.v[q] = fma_t(w2, vj[k].v[q], acc.v[q]);
+            }
+        }
+    } else {
+        int s0, cnt, st;
+        row_slots<0>(a, i, s0, cnt, st);
+        int k = 0;
+        for (; k + kGenGroup <= cnt; k += kGenGroup) {
+            T ww[kGenGroup];
+            VT vj[kGenGroup];
+#pragma unroll
+            for (int g = 0; g < kGenGroup; ++g) {
+                const int sl = s0 + (k + g) * st;
+                ww[g] = a.sw[sl];
+                vj[g] = ld_lanes<T, V>(v + (size_t)a.scol[sl] * d + c0);
+            }
+#pragma unroll
+            for (int g = 0; g < kGenGroup; ++g) {
+                const T w2 = mul_t(ww[g], ww[g]);
+#pragma unroll
+                for (int q = 0; q < V; ++q) acc.v[q] = fma_t(w2, vj[g].v[q], acc.v[q]);
+            }
+        }
+        for (; k < cnt; ++k) {
+            const int sl = s0 + k * st;
+            const T w2 = mul_t(a.sw[sl], a.sw[sl]);
+            VT vj = ld_lanes<T, V>(v + (size_t)a.scol[sl] * d + c0);
+#pragma unroll
+            for (int q = 0; q < V; ++q) acc.v[q] = fma_t(w2, vj.v[q], acc.v[q]);
+        }
+    }
+    return acc;
+}
+
 // the pixels of logical workgroup lb, kBlock / (d / V) per step: f(i, e, c0)
 // for each of this thread's pixels (element e = i d + c0)
 template <int V, typename T, class F>
@@ -3005,21 +3068,9 @@ __global__ void __launch_bounds__(kBlock) k_px_res(KA<T> a, int mode) {
     using VT = Lanes<T, V>;
     __shared__ double sh[kPxSmemDoubles];
     const int lb = logical_block(a.nblk);
-    const int W = a.pxW, H = a.pxH;
     double acc[2][V] = {};
     px_walk<V>(a, lb, [&](int i, size_t e, int c0) {
-        const int py = i / W, px = i - py * W;
-        VT accA;
-#pragma unroll
-        for (int u = 0; u < V; ++u) accA.v[u] = T(0);
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            const T wk = a.sw[(size_t)k * a.n + i];
-            VT xj = ld_lanes<T, V>(a.x + (size_t)px_nb<KC>(i, py, px, W, H, k) * a.d + c0);
-            const T w2 = mul_t(wk, wk);
-#pragma unroll
-            for (int u = 0; u < V; ++u) accA.v[u] = fma_t(w2, xj.v[u], accA.v[u]);
-        }
+        const VT accA = px_nbsum<T, KC, V>(a, a.x, i, c0);
         VT rhs;
         if (mode == PH_R0) {
             rhs = ld_lanes<T, V>(a.rhs + e);
@@ -3057,28 +3108,7 @@ template <typename T, int KC, int V>
 __device__ __forceinline__ Lanes<T, V> px_apply(const KA<T>& a, const T* u, int i, int c0,
                                                                 const Lanes<T, V>& ui) {
     using VT = Lanes<T, V>;
-    constexpr int G = (KC < 8) ? KC : 8;
-    const int W = a.pxW, H = a.pxH, d = a.d;
-    const int py = i / W, px = i - py * W;
-    VT accA;
-#pragma unroll
-    for (int u0 = 0; u0 < V; ++u0) accA.v[u0] = T(0);
-#pragma unroll
-    for (int k0 = 0; k0 < KC; k0 += G) {
-        T ww[G];
-        VT uj[G];
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-            ww[k] = a.sw[(size_t)(k0 + k) * a.n + i];
-            uj[k] = ld_lanes<T, V>(u + (size_t)px_nb<KC>(i, py, px, W, H, k0 + k) * d + c0);
-        }
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-            const T w2 = mul_t(ww[k], ww[k]);
-#pragma unroll
-            for (int q = 0; q < V; ++q) accA.v[q] = fma_t(w2, uj[k].v[q], accA.v[q]);
-        }
-    }
+    const VT accA = px_nbsum<T, KC, V>(a, u, i, c0);
     const T dA = a.diagA[i];
     VT wv;
 #pragma unroll
@@ -3965,8 +3995,10 @@ struct pfe_ctx {
     Partition ps;            // strip partition of pixel grids (ps.nblk == 0: not available)
     Partition pl;            // strips with a two-radius halo (fused learned apply)
     Partition pf;            // strips with a three-radius halo (one-pass factor CG)
-    Partition px;            // pixel launches: contiguous pixel ranges (px.nblk == 0: not available)
-    int want_px = 0;         // Jacobi PCG of a one-image pixel grid by the per-pixel kernels
+    Partition px[2];         // pixel launches: contiguous pixel (row) ranges, one / two workgroups
+                             // per CU (nblk == 0: not available)
+    int want_px = 0;         // Jacobi PCG of a one-segment graph by the per-pixel (per-row) kernels
+                             // on px[want_px - 1] (0: not)
     int one_pass = 0;        // factor preconditioners on strips: one pass per CG iteration (0: two)
     int eu_px = 1;           // pixel stencils with b once per edge: the edge update by the per-pixel
                              // kernel (0: by the strip or row-chunk phase kernel)
@@ -4287,7 +4319,7 @@ const void* px_kernel(int ph, int K) {
         case 4: return reinterpret_cast<const void*>(&KN<T, 4, V>);                    \
         case 8: return reinterpret_cast<const void*>(&KN<T, 8, V>);                    \
         case 24: return reinterpret_cast<const void*>(&KN<T, 24, V>);                  \
-        default: return nullptr; }
+        default: return reinterpret_cast<const void*>(&KN<T, 0, V>); }
     switch (ph) {
         case PH_R0: PFE_PXSEL(k_px_res)
         case PH_W0: PFE_PXSEL(k_px_w0)
@@ -4321,22 +4353,24 @@ pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0)
     const dim3 grid(a.nblk);
     hipStream_t st = c->stream;
     const int K = a.ell_K;
-    if (a.pxW > 0) {
-        // pixel launch: the residual with r0, w0 and the CG iteration (two kernels)
+    if (a.pxl) {
+        // pixel launch: the residual with r0, w0 and the CG iteration (two
+        // kernels); stencil offsets on pixel grids, the slot columns otherwise
+        const int KP = (a.pxW > 0) ? K : 0;
         KA<T> args = a;
         int pm = ph;
         void* kp1[] = {(void*)&args};
         void* kp2[] = {(void*)&args, (void*)&pm};
         const void* fn = nullptr;
         if ((ph == PH_E0 || ph == PH_R0) && do_r0) {
-            fn = px_kernel_for<T>(PH_R0, K, a.d);
+            fn = px_kernel_for<T>(PH_R0, KP, a.d);
             if (fn) { PFE_CHECK_HIP(hipLaunchKernel(fn, grid, dim3(kBlock), kp2, 0, st)); return PFE_OK; }
         } else if (ph == PH_W0) {
-            fn = px_kernel_for<T>(PH_W0, K, a.d);
+            fn = px_kernel_for<T>(PH_W0, KP, a.d);
             if (fn) { PFE_CHECK_HIP(hipLaunchKernel(fn, grid, dim3(kBlock), kp1, 0, st)); return PFE_OK; }
         } else if (ph == PH_IT) {
-            const void* fa = px_kernel_for<T>(PH_GA, K, a.d);
-            fn = px_kernel_for<T>(PH_IT, K, a.d);
+            const void* fa = px_kernel_for<T>(PH_GA, KP, a.d);
+            fn = px_kernel_for<T>(PH_IT, KP, a.d);
             if (fa && fn) {
                 PFE_CHECK_HIP(hipLaunchKernel(fa, grid, dim3(kBlock), kp1, 0, st));
                 PFE_CHECK_HIP(hipLaunchKernel(fn, grid, dim3(kBlock), kp1, 0, st));
@@ -4496,9 +4530,9 @@ pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, const KA<T>*
                 add(kernel_for<T>(PH_LC, K, st), p3, a.nblk);
                 add(kernel_for<T>(PH_LD, K, st), p2, a.nblk);
             }
-        } else if (a.pxW > 0) {
-            add(px_kernel_for<T>(PH_GA, K, a.d), p1, a.nblk);
-            add(px_kernel_for<T>(PH_IT, K, a.d), p1, a.nblk);
+        } else if (a.pxl) {
+            add(px_kernel_for<T>(PH_GA, a.pxW > 0 ? K : 0, a.d), p1, a.nblk);
+            add(px_kernel_for<T>(PH_IT, a.pxW > 0 ? K : 0, a.d), p1, a.nblk);
         } else if (!st && K != 4 && K != 8 && K != 24) {
             add(reinterpret_cast<const void*>(&k_cg_ga<T>), p1, a.nblk);
             add(reinterpret_cast<const void*>(&k_cg_gb<T>), p1, a.nblk);
@@ -4665,19 +4699,24 @@ pfe_status pcg_solve_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as, int res_ph)
 // has one and the context wants it
 inline bool use_strips(const pfe_ctx* c) { return c->want_strips > 0 && c->ps.nblk > 0; }
 
-// pixel launches: Jacobi PCG of a one-image pixel grid, when the context wants them
-inline bool use_px(const pfe_ctx* c) { return c->want_px && c->px.nblk > 0 && c->prm.precond == PFE_JACOBI; }
+// pixel launches: Jacobi PCG of a one-segment graph, when the context wants them
+inline bool use_px(const pfe_ctx* c) {
+    return c->want_px > 0 && c->want_px <= 2 && c->px[c->want_px - 1].nblk > 0 && c->prm.precond == PFE_JACOBI;
+}
 
 // arguments of the PCG phases (residual, w0, iterations) for the iterate and
 // right-hand side of a: pixel launches, strips or row chunks
 template <typename T>
 KA<T> pcg_args(pfe_ctx* c, const KA<T>& a) {
     if (use_px(c)) {
-        KA<T> ap = make_args<T>(c, c->px);
+        KA<T> ap = make_args<T>(c, c->px[c->want_px - 1]);
         ap.x = a.x;
         ap.rhs = a.rhs;
-        ap.pxW = c->g->seg_W[0];
-        ap.pxH = c->g->seg_H[0];
+        ap.pxl = 1;
+        if (c->g->stencil) {
+            ap.pxW = c->g->seg_W[0];
+            ap.pxH = c->g->seg_H[0];
+        }
         return ap;
     }
     if (use_strips(c)) {
@@ -4913,7 +4952,8 @@ void free_ctx(pfe_ctx* c) {
     free_partition(c->ps);
     free_partition(c->pl);
     free_partition(c->pf);
-    free_partition(c->px);
+    free_partition(c->px[0]);
+    free_partition(c->px[1]);
     if (c->cg_exec) (void)hipGraphExecDestroy(c->cg_exec);
     c->cg_exec = nullptr;
 }
@@ -5321,24 +5361,30 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
         s = setup_strips(c);
         c->want_strips = want;
     }
-    if (s == PFE_OK && g->stencil && (g->ell_K == 4 || g->ell_K == 8 || g->ell_K == 24) && c->nseg == 1 &&
-        g->seg_W.size() == 1 && g->seg_W[0] > 0 && g->seg_H[0] > 0 && (int64_t)g->seg_W[0] * g->seg_H[0] == c->n) {
-        // pixel launches: one workgroup per CU, each a contiguous pixel range (on
+    const bool px_image = g->stencil && (g->ell_K == 4 || g->ell_K == 8 || g->ell_K == 24) && c->nseg == 1 &&
+                          g->seg_W.size() == 1 && g->seg_W[0] > 0 && g->seg_H[0] > 0 &&
+                          (int64_t)g->seg_W[0] * g->seg_H[0] == c->n;
+    if (s == PFE_OK && (px_image || (!g->stencil && c->nseg == 1))) {
+        // pixel (per-row) launches of one image or one general graph: one
+        // workgroup per CU, each a contiguous pixel (row) range (on
         // the 1024 x 1024 window graph 256 workgroups ran a SOC iteration in
         // 20.3 ms, 512 in 21.5, 768 in 22.4, 1024 in 23.0, 2048 in 25.9)
         const int V = (p->dtype == PFE_FP64) ? px_cols<double>((int)c->d) : px_cols<float>((int)c->d);
         const int ppb = kBlock / ((int)c->d / V);
-        int want_px = ncu;
-        if (const char* ev = getenv("PFE_PX_BLOCKS")) want_px = std::max(kNumXcd, atoi(ev));   // launch-shape experiments
         const int64_t steps = (c->n + ppb - 1) / ppb;
-        want_px = (int)std::min<int64_t>(want_px, steps);
-        want_px -= want_px % kNumXcd;
-        if (want_px >= kNumXcd) s = make_partition(seg_rows, want_px, ppb, 1, c->px);
+        for (int k = 0; k < 2 && s == PFE_OK; ++k) {
+            int want_px = (k + 1) * ncu;
+            if (const char* ev = getenv("PFE_PX_BLOCKS")) want_px = std::max(kNumXcd, atoi(ev));   // launch-shape experiments
+            want_px = (int)std::min<int64_t>(want_px, steps);
+            if (want_px >= kNumXcd) want_px -= want_px % kNumXcd;   // whole XCD groups where there are enough
+            if (k == 1 && want_px <= c->px[0].nblk) break;          // no second size
+            s = make_partition(seg_rows, std::max(1, want_px), ppb, 1, c->px[k]);
+        }
     }
-    if (const char* ev = getenv("PFE_PIXEL")) c->want_px = atoi(ev) != 0;   // launch-shape experiments
+    if (const char* ev = getenv("PFE_PIXEL")) c->want_px = std::min(2, std::max(0, atoi(ev)));   // launch-shape experiments
     if (s != PFE_OK) { free_ctx(c); delete c; return s; }
     const int nblk_max = std::max(std::max(std::max(std::max(c->pm.nblk, c->pc.nblk), std::max(c->ps.nblk, c->pl.nblk)),
-                                  c->pf.nblk), c->px.nblk);
+                                  c->pf.nblk), std::max(c->px[0].nblk, c->px[1].nblk));
     c->part_blocks = nblk_max;
     if (s == PFE_OK) s = setup_strips(c);
     if (s != PFE_OK) { free_ctx(c); delete c; return s; }
@@ -5512,7 +5558,7 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
                             {1, 1, 0, 0, 0.8, 0, 0},
                             {0, c->team, 0, 0, 1.0, 0, 0}, {0, c->team, 0, 1, 1.0, 0, 0}, {0, c->team, 0, 2, 1.0, 0, 0},
                             {0, c->team, 0, 1, 1.0, 1, 0}, {0, c->team, 0, 2, 1.0, 1, 0},
-                            {0, c->team, 0, 0, 1.0, 0, 1}};
+                            {0, c->team, 0, 0, 1.0, 0, 1}, {0, c->team, 0, 0, 1.0, 0, 2}};
     const Shape orig{c->prm.persistent, c->team, c->want_cache, c->want_strips, c->second_weight, c->one_pass,
                      c->want_px};
     char* save = nullptr;
@@ -5553,7 +5599,7 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
             if (sh.strips && c->strip_slots == 0) continue;
             if (sh.w2 != 1.0 && c->per_cu != 2) continue;
             if (sh.one_pass && (c->prm.precond == PFE_JACOBI || c->fcg_slots == 0)) continue;
-            if (sh.pixel && (c->prm.precond != PFE_JACOBI || c->px.nblk == 0)) continue;
+            if (sh.pixel && (c->prm.precond != PFE_JACOBI || c->px[sh.pixel - 1].nblk == 0)) continue;
             c->one_pass = sh.one_pass;
             c->want_px = sh.pixel;
             c->prm.persistent = sh.persistent;
@@ -5595,7 +5641,7 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
             r.one_pass = sh.one_pass;
             r.pixel = sh.pixel;
             r.workgroups = sh.persistent ? c->pc.nblk
-                                         : (sh.pixel ? c->px.nblk
+                                         : (sh.pixel ? c->px[sh.pixel - 1].nblk
                                                      : (sh.one_pass ? c->pf.nblk : (sh.strips ? c->ps.nblk : c->pm.nblk)));
             r.ms = ms / trials;
             found.push_back(r);
@@ -5661,8 +5707,9 @@ pfe_status pfe_set_launch_shape(pfe_ctx* c, const pfe_tune_result* sh) {
         set_error("pfe_set_launch_shape: the one-pass factor CG runs on image strips of a pixel-grid graph");
         return PFE_E_ARG;
     }
-    if (!sh->persistent && sh->pixel && c->px.nblk == 0) {
-        set_error("pfe_set_launch_shape: pixel launches need a one-image pixel grid with 4, 8 or 24 slots");
+    if (!sh->persistent && (sh->pixel < 0 || sh->pixel > 2 || (sh->pixel > 0 && c->px[sh->pixel - 1].nblk == 0))) {
+        set_error("pfe_set_launch_shape: pixel launches (1 or 2 workgroups per CU) need a graph of one segment "
+                  "(one image or one edge list; 2: one large enough for more workgroups than CUs)");
         return PFE_E_ARG;
     }
     c->prm.persistent = sh->persistent ? 1 : 0;
@@ -5673,7 +5720,7 @@ pfe_status pfe_set_launch_shape(pfe_ctx* c, const pfe_tune_result* sh) {
     } else {
         c->want_strips = sh->strips;
         c->one_pass = sh->one_pass ? 1 : 0;
-        c->want_px = sh->pixel ? 1 : 0;
+        c->want_px = sh->pixel;
     }
     PFE_TRY(setup_persistent(c));
     PFE_TRY(setup_strips(c));

@@ -273,12 +273,13 @@ class Solver:
                 for r in res[:n.value]]
 
     def set_launch_shape(self, persistent: bool = False, strips: int = 0, team: int = 1, row_cache: bool = False,
-                         second_weight: float = 1.0, one_pass: bool = False, pixel: bool = False) -> None:
+                         second_weight: float = 1.0, one_pass: bool = False, pixel: int = 0) -> None:
         """Run later iterations in the given launch shape (the fields of an
         autotune() result): persistent with teams / row cache / second-workgroup
         share, or one launch per phase on row chunks (strips = 0) or on image
         strips sized for 1 or 2 waves (factor preconditioners: one or two passes
-        per CG iteration), with Jacobi PCG by pixel launches when pixel."""
+        per CG iteration), with Jacobi PCG by per-row (pixel) launches on pixel
+        (1 or 2) workgroups per CU."""
         sh = L.pfe_tune_result(persistent=int(persistent), team=int(team), row_cache=int(row_cache),
                                strips=int(strips), second_weight=float(second_weight), one_pass=int(one_pass),
                                pixel=int(pixel))

@@ -112,15 +112,10 @@ def test_window1024_learned_factor_vs_oracle(window_case):
     G.close()
 
 
-@pytest.mark.timeout(900)
-def test_knn200k_soc_iteration_vs_oracle():
-    """The data-clustering workload's graph family at 200,000 points (Gaussian
-    mixture in R^32, symmetrised exact 16-NN graph in reverse Cuthill-McKee
-    order, d = 20; general CSR slot layout): one SOC iteration with two
-    Split-Bregman iterations in the autotuned launch shape against the oracle
-    (CG to 1e-12), by Frobenius norm and element-wise per column."""
-    from paper_1612_06496_amd import Graph, Solver
-    banner("200k-point k-NN graph, d = 20: one SOC iteration vs oracle")
+@pytest.fixture(scope="module")
+def knn200k_case():
+    """The data-clustering workload's graph family at 200,000 points and its
+    oracle SOC iteration (two Split-Bregman iterations, CG to 1e-12)."""
     wl = synth.make_edges_workload("gmm200k_knn16_rcm", 0)
     src, dst, dist2 = (t.cpu().numpy() for t in (wl.src, wl.dst, wl.dist2))
     g = O.build_edge_graph(wl.n, src, dst, dist2, wl.sigma)
@@ -128,14 +123,36 @@ def test_knn200k_soc_iteration_vs_oracle():
     c = O.shrink_active_scale(g, Y0)
     solve = O.CGSolver(O.system_matrix(g, c, c), tol=1e-12)
     Y1, P1, _ = O.soc_outer_step(g, solve, Y0, np.sqrt(g.D)[:, None] * Y0, np.zeros_like(Y0), c, c, 2)
+    return wl, Y0, c, Y1, P1
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("shape", ["autotuned", "per-row", "per-row-2"])
+def test_knn200k_soc_iteration_vs_oracle(knn200k_case, shape):
+    """The data-clustering workload's graph family at 200,000 points (Gaussian
+    mixture in R^32, symmetrised exact 16-NN graph in reverse Cuthill-McKee
+    order, d = 20; general CSR slot layout): one SOC iteration with two
+    Split-Bregman iterations in the autotuned launch shape and in per-row
+    launches (one and two workgroups per CU) against the oracle (CG to 1e-12),
+    by Frobenius norm and element-wise per column."""
+    from paper_1612_06496_amd import Graph, Solver
+    banner(f"200k-point k-NN graph, d = 20: one SOC iteration vs oracle ({shape})")
+    wl, Y0, c, Y1, P1 = knn200k_case
     G = Graph.edges(wl.n, wl.src, wl.dst, wl.dist2, wl.sigma)
     S = Solver(G, Y0.astype(np.float32), lam=c, r=c, n_inner=2, tol=1e-6, maxit=1000, init_ortho=False)
-    shapes = S.autotune(1)
+    if shape == "autotuned":
+        shapes = S.autotune(1)
+        chosen = [s_ for s_ in shapes if s_["chosen"]][0]
+    else:
+        wpc = 2 if shape == "per-row-2" else 1
+        S.set_launch_shape(persistent=False, pixel=wpc)
+        chosen = f"per-row launches, {wpc} workgroup(s) per CU"
     info = S.solve(1, info=True)
+    if shape != "autotuned":
+        assert info["flags"] & 4
     Yg, Pg = to_np(S.get("Y")), to_np(S.get("P"))
     eY, eP = rel(Yg, Y1), rel(Pg, P1)
     mY, mP = maxrel(Yg, Y1), maxrel(Pg, P1)
-    chosen = [s_ for s_ in shapes if s_["chosen"]][0]
     print(f"Y {eY:.2e} ({mY:.2e} element-wise) P {eP:.2e} ({mP:.2e}); shape {chosen}; "
           f"CG iterations per solve {info['cg_iters_total'] / info['solves']:.2f}")
     assert eY <= 2e-5 and eP <= 2e-5

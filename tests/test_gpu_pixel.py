@@ -155,8 +155,9 @@ def test_autotune_offers_pixel_launches(monkeypatch):
 
 def test_pixel_launch_not_offered_for_batches_or_factor_preconditioners(monkeypatch):
     """Batches (several images) and the learned / FSAI factor preconditioners
-    keep the strip launches: set_launch_shape rejects pixel launches on a batch,
-    and a factor-preconditioned solve on a context that wants them runs on strips."""
+    keep the strip launches: set_launch_shape rejects pixel launches on a batch
+    (and two workgroups per CU on a graph too small for them), and a
+    factor-preconditioned solve on a context that wants them runs on strips."""
     from paper_1612_06496_amd import Graph, Solver
     from paper_1612_06496_amd import _lib as L
     monkeypatch.setenv("PFE_PIXEL", "1")
@@ -172,8 +173,66 @@ def test_pixel_launch_not_offered_for_batches_or_factor_preconditioners(monkeypa
     wl = synth.make_workload("voronoi48x40_r2", 0)
     G = gpu_graph(wl)
     S = Solver(G, wl.y0, lam=20.0, r=2.0, n_inner=2, tol=1e-6, persistent=False)
+    with pytest.raises(L.PFEError):
+        S.set_launch_shape(persistent=False, pixel=2)    # too few rows for more workgroups than CUs
+    with pytest.raises(L.PFEError):
+        S.set_launch_shape(persistent=False, pixel=3)
     S.set_fsai()
     info = S.solve(1, info=True)
     assert not (info["flags"] & 4)
+    S.close()
+    G.close()
+
+
+def edge_workload(d, n=5000):
+    # 5000 points: several 512-thread workgroups of rows even at four columns per thread
+    return synth.edges_workload("gmm_small", n, 8, 4, 6, 3, d=d, n_outer=2, n_inner=3)
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+@pytest.mark.parametrize("d,n", [(4, 5000), (5, 5000), (4, 900)])
+def test_row_launch_general_graph_matches_row_chunks(d, n, fp64, monkeypatch):
+    """Per-row launches on an edge-list graph (k-NN, general slot layout; the
+    neighbours from the slot columns): two SOC iterations equal the row-chunk
+    launches' up to the FP64 summation order (900 points: fewer workgroups
+    than XCDs)."""
+    wl = edge_workload(d, n)
+    banner(f"row launch vs row chunks, edge-list graph d={d} fp64={fp64}")
+    ip, px = run(wl, monkeypatch, True, fp64, strips=0)
+    assert ip["flags"] & 4, "the per-row kernels did not run"
+    io, rc = run(wl, monkeypatch, False, fp64, strips=0)
+    assert not (io["flags"] & 4)
+    bound = 1e-10 if fp64 else 1e-5
+    worst = max(rel(px[k], rc[k]) for k in ("Y", "P"))
+    eB = np.linalg.norm(px["B"] - rc["B"]) / np.linalg.norm(rc["P"])
+    print(f"Y/P rel {worst:.2e}, B {eB:.2e}; CG iterations {ip['cg_iters_total']} vs {io['cg_iters_total']}")
+    assert worst <= bound and eB <= bound
+    if fp64:
+        assert ip["cg_iters_total"] == io["cg_iters_total"]
+    else:
+        assert abs(ip["cg_iters_total"] - io["cg_iters_total"]) <= max(2, io["cg_iters_total"] // 50)
+
+
+def test_row_launch_general_graph_pcg_matches_direct_solve(monkeypatch):
+    from paper_1612_06496_amd import Solver
+    monkeypatch.setenv("PFE_PIXEL", "1")
+    wl = edge_workload(4)
+    banner("pfe_pcg by per-row launches on an edge-list graph vs direct solve")
+    g = oracle_graph(wl)
+    lam, r, tol = 40.0, 2.0, 1e-12
+    G = gpu_graph(wl)
+    S = Solver(G, wl.y0, lam=lam, r=r, n_inner=2, tol=tol, maxit=5000, fp64=True, persistent=False)
+    A = O.system_matrix(g, lam, r)
+    rhs = np.random.default_rng(7).normal(size=(g.n, wl.y0.shape[1]))
+    x, iters, info = S.pcg(rhs, np.zeros_like(rhs))
+    assert info["flags"] & 4
+    exact = O.DirectSolver(A)(rhs)
+    kappa = O.jacobi_condition_number(A)
+    e = rel(to_np(x), exact)
+    print(f"rel err {e:.2e}, kappa {kappa:.1f}, iterations {iters.max()}")
+    assert info["rel_res_max"] <= tol
+    assert e <= kappa * tol * 4
+    _, it_o, _ = O.pcg(A, rhs, np.zeros_like(rhs), 1.0 / A.diagonal(), tol, 5000)
+    assert np.all(np.abs(iters - it_o) <= 1)
     S.close()
     G.close()
