@@ -2843,7 +2843,7 @@ __device__ __forceinline__ Lanes<T, V> ld_lanes(const T* p) { return *reinterpre
 template <typename T, int V>
 __device__ __forceinline__ void st_lanes(T* p, const Lanes<T, V>& x) { *reinterpret_cast<Lanes<T, V>*>(p) = x; }
 
-// Edge update of the pixel-stencil layouts with b once per undirected edge (the
+// Edge update, one thread per row (the
 // PH_EU arithmetic without r0, element by element and in the same slot order):
 // one thread per pixel and V consecutive columns, no LDS, one workgroup per
 // kBlock / (d / V) pixels.  The edge update has no neighbour value shared by a
@@ -2851,13 +2851,14 @@ __device__ __forceinline__ void st_lanes(T* p, const Lanes<T, V>& x) { *reinterp
 // is the number of independent loads in flight, which wide accesses and a full
 // grid of small workgroups maximise.  With GEO (one image of W x H pixels) the
 // neighbour of slot k is the stencil offset, and the slot columns are not read;
-// otherwise (batches) they are.
+// otherwise (batches) they are.  KC = 0: general layouts (ELL or CSR rows), b
+// and d stored per slot and updated in place, as in the row-chunk phase.
 template <typename T, int KC, int V, bool GEO>
 __global__ void __launch_bounds__(kBlock) k_eu_px(KA<T> a, int W, int H) {
     using VT = Lanes<T, V>;
     using S = Sten<KC>;
     constexpr int KH = KC / 2;
-    constexpr int G = (KC < 8) ? KC : 8;   // slots whose loads are issued together
+    constexpr int G = (KC < 8) ? (KC > 0 ? KC : 1) : 8;   // slots whose loads are issued together
     const int d = a.d, L = d / V, ppb = kBlock / L;
     const int q = threadIdx.x / L;
     const int64_t i64 = (int64_t)blockIdx.x * ppb + q;
@@ -2871,58 +2872,108 @@ __global__ void __launch_bounds__(kBlock) k_eu_px(KA<T> a, int W, int H) {
     VT acc;
 #pragma unroll
     for (int u = 0; u < V; ++u) acc.v[u] = T(0);
-    int py = 0, px = 0;
-    if constexpr (GEO) {
-        py = i / W;
-        px = i - py * W;
-    }
-#pragma unroll
-    for (int k0 = 0; k0 < KC; k0 += G) {
-        int jj[G];
-        T ww[G];
-        VT yj[G], bo[G];
-        size_t ss[G];
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-            const int kk = k0 + k;
-            const size_t sl = (size_t)kk * a.n + i;
-            if constexpr (GEO) {
-                const int yy = py + S::dy(kk), xx = px + S::dx(kk);
-                jj[k] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? i + S::dy(kk) * W + S::dx(kk) : i;
-            } else {
-                jj[k] = a.scol[sl];
-            }
-            ww[k] = a.sw[sl];
-            ss[k] = (kk < KH) ? sl : (size_t)(KC - 1 - kk) * a.n + jj[k];
-            if (a.b_zero) {
-#pragma unroll
-                for (int u = 0; u < V; ++u) bo[k].v[u] = T(0);
-            } else {
-                bo[k] = ld_lanes<T, V>(bread + ss[k] * d + c0);
-                if (kk >= KH) {
-#pragma unroll
-                    for (int u = 0; u < V; ++u) bo[k].v[u] = -bo[k].v[u];
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < G; ++k) yj[k] = ld_lanes<T, V>(a.Y + (size_t)jj[k] * d + c0);
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-            const int kk = k0 + k;
+    if constexpr (KC == 0) {
+        // general layouts: the row's slots (ELL or CSR), b and d per slot, updated in place
+        int s0, cnt, st;
+        row_slots<0>(a, i, s0, cnt, st);
+        auto slot = [&](int sl, T w, const VT& yj, const VT& bo) {
             VT bn, dn;
 #pragma unroll
             for (int u = 0; u < V; ++u) {
-                const T tv = fma_t(ww[k], yi.v[u] - yj[k].v[u], bo[k].v[u]);
+                const T tv = fma_t(w, yi.v[u] - yj.v[u], bo.v[u]);
                 const T dv = shrink(tv, a.gamma);
                 const T b1 = tv - dv;
                 bn.v[u] = b1;
                 dn.v[u] = dv;
-                acc.v[u] = fma_t(ww[k], dv - b1, acc.v[u]);
+                acc.v[u] = fma_t(w, dv - b1, acc.v[u]);
             }
-            if (kk < KH) {
-                st_lanes<T, V>(bwrite + ss[k] * d + c0, bn);
-                if (a.keep_split) st_lanes<T, V>(a.ds + ss[k] * d + c0, dn);
+            st_lanes<T, V>(bwrite + (size_t)sl * d + c0, bn);
+            if (a.keep_split) st_lanes<T, V>(a.ds + (size_t)sl * d + c0, dn);
+        };
+        int k = 0;
+        for (; k + kGenGroup <= cnt; k += kGenGroup) {
+            T ww[kGenGroup];
+            VT yj[kGenGroup], bo[kGenGroup];
+#pragma unroll
+            for (int g = 0; g < kGenGroup; ++g) {
+                const int sl = s0 + (k + g) * st;
+                ww[g] = a.sw[sl];
+                yj[g] = ld_lanes<T, V>(a.Y + (size_t)a.scol[sl] * d + c0);
+                if (a.b_zero) {
+#pragma unroll
+                    for (int u = 0; u < V; ++u) bo[g].v[u] = T(0);
+                } else {
+                    bo[g] = ld_lanes<T, V>(bread + (size_t)sl * d + c0);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < kGenGroup; ++g) slot(s0 + (k + g) * st, ww[g], yj[g], bo[g]);
+        }
+        for (; k < cnt; ++k) {
+            const int sl = s0 + k * st;
+            VT bo;
+            if (a.b_zero) {
+#pragma unroll
+                for (int u = 0; u < V; ++u) bo.v[u] = T(0);
+            } else {
+                bo = ld_lanes<T, V>(bread + (size_t)sl * d + c0);
+            }
+            slot(sl, a.sw[sl], ld_lanes<T, V>(a.Y + (size_t)a.scol[sl] * d + c0), bo);
+        }
+    } else {
+        int py = 0, px = 0;
+        if constexpr (GEO) {
+            py = i / W;
+            px = i - py * W;
+        }
+    #pragma unroll
+        for (int k0 = 0; k0 < KC; k0 += G) {
+            int jj[G];
+            T ww[G];
+            VT yj[G], bo[G];
+            size_t ss[G];
+    #pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const int kk = k0 + k;
+                const size_t sl = (size_t)kk * a.n + i;
+                if constexpr (GEO) {
+                    const int yy = py + S::dy(kk), xx = px + S::dx(kk);
+                    jj[k] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? i + S::dy(kk) * W + S::dx(kk) : i;
+                } else {
+                    jj[k] = a.scol[sl];
+                }
+                ww[k] = a.sw[sl];
+                ss[k] = (kk < KH) ? sl : (size_t)(KC - 1 - kk) * a.n + jj[k];
+                if (a.b_zero) {
+    #pragma unroll
+                    for (int u = 0; u < V; ++u) bo[k].v[u] = T(0);
+                } else {
+                    bo[k] = ld_lanes<T, V>(bread + ss[k] * d + c0);
+                    if (kk >= KH) {
+    #pragma unroll
+                        for (int u = 0; u < V; ++u) bo[k].v[u] = -bo[k].v[u];
+                    }
+                }
+            }
+    #pragma unroll
+            for (int k = 0; k < G; ++k) yj[k] = ld_lanes<T, V>(a.Y + (size_t)jj[k] * d + c0);
+    #pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const int kk = k0 + k;
+                VT bn, dn;
+    #pragma unroll
+                for (int u = 0; u < V; ++u) {
+                    const T tv = fma_t(ww[k], yi.v[u] - yj[k].v[u], bo[k].v[u]);
+                    const T dv = shrink(tv, a.gamma);
+                    const T b1 = tv - dv;
+                    bn.v[u] = b1;
+                    dn.v[u] = dv;
+                    acc.v[u] = fma_t(ww[k], dv - b1, acc.v[u]);
+                }
+                if (kk < KH) {
+                    st_lanes<T, V>(bwrite + ss[k] * d + c0, bn);
+                    if (a.keep_split) st_lanes<T, V>(a.ds + ss[k] * d + c0, dn);
+                }
             }
         }
     }
@@ -4756,23 +4807,30 @@ pfe_status setup_strips(pfe_ctx* c) {
 }
 
 // the per-pixel edge update (k_eu_px): pixel stencils of 4, 8 or 24 slots with b
-// once per undirected edge
+// once per undirected edge, and general layouts (ELL or CSR) with b per slot
 inline bool eu_px_ok(const pfe_ctx* c) {
     const int K = c->g->ell_K;
-    return c->eu_px && c->bhalf && c->g->stencil && (K == 4 || K == 8 || K == 24);
+    if (!c->eu_px) return false;
+    if (!c->g->stencil) return !c->bhalf;    // general layouts: b per slot
+    return c->bhalf && (K == 4 || K == 8 || K == 24);
 }
 
 template <typename T, int KC, int V>
 pfe_status launch_eu_px_v(pfe_ctx* c, const KA<T>& a, dim3 grid, bool geo, int W, int H) {
-    if (geo) hipLaunchKernelGGL((k_eu_px<T, KC, V, true>), grid, dim3(kBlock), 0, c->stream, a, W, H);
-    else hipLaunchKernelGGL((k_eu_px<T, KC, V, false>), grid, dim3(kBlock), 0, c->stream, a, W, H);
+    if constexpr (KC > 0) {
+        if (geo) hipLaunchKernelGGL((k_eu_px<T, KC, V, true>), grid, dim3(kBlock), 0, c->stream, a, W, H);
+        else hipLaunchKernelGGL((k_eu_px<T, KC, V, false>), grid, dim3(kBlock), 0, c->stream, a, W, H);
+    } else {
+        hipLaunchKernelGGL((k_eu_px<T, 0, V, false>), grid, dim3(kBlock), 0, c->stream, a, W, H);
+    }
     PFE_CHECK_HIP(hipGetLastError());
     return PFE_OK;
 }
 
 template <typename T, int V>
 pfe_status launch_eu_px_k(pfe_ctx* c, const KA<T>& a, dim3 grid, bool geo, int W, int H) {
-    switch (c->g->ell_K) {
+    switch (c->g->stencil ? c->g->ell_K : 0) {
+        case 0: return launch_eu_px_v<T, 0, V>(c, a, grid, false, W, H);
         case 4: return launch_eu_px_v<T, 4, V>(c, a, grid, geo, W, H);
         case 8: return launch_eu_px_v<T, 8, V>(c, a, grid, geo, W, H);
         case 24: return launch_eu_px_v<T, 24, V>(c, a, grid, geo, W, H);

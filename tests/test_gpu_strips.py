@@ -246,23 +246,28 @@ EU_CASES = ["voronoi96x80_8nbr", "voronoi48x40_r2", "voronoi64_4nbr", "narrow300
 
 
 @pytest.mark.parametrize("fp64", [False, True])
-@pytest.mark.parametrize("name", EU_CASES + ["batch5"])
+@pytest.mark.parametrize("name", EU_CASES + ["batch5", "edges_d4", "edges_d5"])
 def test_pixel_edge_update_bitwise_equals_phase_kernels(name, fp64, monkeypatch):
     """The per-pixel edge update (one thread per pixel and 1, 2 or 4 columns;
     neighbours from the stencil offsets on one image, from the slot columns on a
-    batch) does the phase kernels' arithmetic element by element in the same
-    slot order: Y, P, B, b and d after a SOC iteration and two inner steps (both
-    b-buffer parities) are bitwise those of the strip / row-chunk edge update."""
+    batch and on edge-list graphs, whose b and d are stored per slot) does the
+    phase kernels' arithmetic element by element in the same slot order: Y, P,
+    B, b and d after a SOC iteration and two inner steps (both b-buffer
+    parities) are bitwise those of the strip / row-chunk edge update."""
     from paper_1612_06496_amd import Graph
     banner(f"per-pixel edge update == phase kernels: {name} fp64={fp64}")
     if name == "batch5":
         wls = synth.make_batch("voronoi_batch5_8nbr")
         G = Graph.union([gpu_graph(w) for w in wls])
         y0 = np.concatenate([w.y0 for w in wls])
+    elif name.startswith("edges"):
+        # an edge-list graph: b and d per slot, the slot columns of the general layout
+        wl = synth.edges_workload("gmm_small", 5000, 8, 4, 6, 3, d=int(name[-1]), n_outer=2, n_inner=3)
+        G, y0 = gpu_graph(wl), wl.y0
     else:
         wl = case_workload(next(c for c in CASES if c[0] == name))
         G, y0 = gpu_graph(wl), wl.y0
-    keep = name in ("voronoi48x40_r2", "batch5")
+    keep = name in ("voronoi48x40_r2", "batch5", "edges_d4")
     a = run_eu(G, y0, monkeypatch, True, fp64, keep, 2)
     b = run_eu(G, y0, monkeypatch, False, fp64, keep, 2)
     for k in a:
