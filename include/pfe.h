@@ -282,8 +282,8 @@ typedef struct {
                                 per CG iteration (Chronopoulos-Gear form, M^{-1} r and A M^{-1} r
                                 through three LDS rings over a three-radius halo), 0 = two passes
                                 (A p, then the factor apply with the x, r update) */
-    int32_t pixel;           /* one launch per phase, Jacobi PCG of a one-segment graph (one image or
-                                one edge list) by per-row kernels on 1 or 2 workgroups per CU (0: not):
+    int32_t pixel;           /* one launch per phase, Jacobi PCG by per-row kernels on 1 or 2 workgroups
+                                per CU (0: not), each a row range of one segment (image or graph):
                                 the residual, w0 and each CG iteration in two passes (the own-row
                                 updates storing u' = r'/diag(A), then w' = A u' gathering u'), one
                                 thread per row (pixel) and 1, 2 or 4 columns, neighbours through L2

@@ -128,8 +128,8 @@ struct KA {
     int ortho;         // PFE_POLAR / PFE_CHOL
     int sten;          // ELL slots in pixel-stencil order (lower neighbours first)
     const int* dact;   // per segment: active columns (the leading ones; the others stay zero), or null (all d)
-    int pxl;           // per-row ("pixel") launch of the Jacobi PCG phases
-    int pxW, pxH;      // its image's width and height on pixel-stencil layouts
+    int pxl;           // per-row ("pixel") launch of the Jacobi PCG phases (geo: per workgroup
+                       // {row0, W, H} of its image on pixel-stencil layouts, else null)
 };
 
 // ---------------------------------------------------------------------------
@@ -2999,10 +2999,13 @@ __global__ void __launch_bounds__(kBlock) k_eu_px(KA<T> a, int W, int H) {
 // layout).  The CG iteration runs in two passes, as on general layouts: the
 // own-row updates storing u' = r' / diag(A) (k_px_ga), then w' = A u' gathering
 // u' alone (k_px_gb); the neighbours' values come through L2 rather than an
-// LDS ring, which keeps LDS small (9 KB).  The per-element arithmetic and slot
-// order are those of the row-chunk phases.
+// LDS ring.  The per-element arithmetic and slot order are those of the
+// row-chunk phases.
 // ---------------------------------------------------------------------------
-constexpr int kPxSmemDoubles = 1024 + 3 * kMaxD;   // block partials of one column lane (kBlock), finaliser
+// LDS of the pixel kernels: the finalisers' layout (partials of one column lane
+// below 1024, the sums of up to seg_chunk() segments above); one or two
+// workgroups per CU leave LDS to spare
+constexpr int kPxSmemDoubles = kSmemDoubles;
 static_assert(kBlock <= 1024, "the finalisers keep their sums at sh + 1024");
 
 // neighbour of slot k of pixel i at (py, px) of a W x H image
@@ -3042,7 +3045,7 @@ __device__ __forceinline__ void block_partials_px(const double (&acc)[NQ][V], co
 // stencil offsets on pixel grids (KC > 0), the row's slot columns otherwise
 // (ELL or CSR; loads in groups of kGenGroup slots, as in the row-chunk phases)
 template <typename T, int KC, int V>
-__device__ __forceinline__ Lanes<T, V> px_nbsum(const KA<T>& a, const T* v, int i, int c0) {
+__device__ __forceinline__ Lanes<T, V> px_nbsum(const KA<T>& a, const T* v, int i, int c0, int lb) {
     using VT = Lanes<T, V>;
     const int d = a.d;
     VT acc;
@@ -3050,8 +3053,10 @@ __device__ __forceinline__ Lanes<T, V> px_nbsum(const KA<T>& a, const T* v, int 
     for (int q = 0; q < V; ++q) acc.v[q] = T(0);
     if constexpr (KC > 0) {
         constexpr int G = (KC < 8) ? KC : 8;
-        const int W = a.pxW, H = a.pxH;
-        const int py = i / W, px = i - py * W;
+        const int* gg = a.geo + 8 * lb;   // the workgroup's image: first row, width, height
+        const int W = gg[1], H = gg[2];
+        const int il = i - gg[0];
+        const int py = il / W, px = il - py * W;
 #pragma unroll
         for (int k0 = 0; k0 < KC; k0 += G) {
             T ww[G];
@@ -3121,7 +3126,7 @@ __global__ void __launch_bounds__(kBlock) k_px_res(KA<T> a, int mode) {
     const int lb = logical_block(a.nblk);
     double acc[2][V] = {};
     px_walk<V>(a, lb, [&](int i, size_t e, int c0) {
-        const VT accA = px_nbsum<T, KC, V>(a, a.x, i, c0);
+        const VT accA = px_nbsum<T, KC, V>(a, a.x, i, c0, lb);
         VT rhs;
         if (mode == PH_R0) {
             rhs = ld_lanes<T, V>(a.rhs + e);
@@ -3157,9 +3162,9 @@ __global__ void __launch_bounds__(kBlock) k_px_res(KA<T> a, int mode) {
 // w = A u for u in zl: the neighbours' u gathered, slot loads issued in groups
 template <typename T, int KC, int V>
 __device__ __forceinline__ Lanes<T, V> px_apply(const KA<T>& a, const T* u, int i, int c0,
-                                                                const Lanes<T, V>& ui) {
+                                                                const Lanes<T, V>& ui, int lb) {
     using VT = Lanes<T, V>;
-    const VT accA = px_nbsum<T, KC, V>(a, u, i, c0);
+    const VT accA = px_nbsum<T, KC, V>(a, u, i, c0, lb);
     const T dA = a.diagA[i];
     VT wv;
 #pragma unroll
@@ -3178,7 +3183,7 @@ __global__ void __launch_bounds__(kBlock) k_px_w0(KA<T> a) {
     px_walk<V>(a, lb, [&](int i, size_t e, int c0) {
         VT ui = ld_lanes<T, V>(a.zl + e);
         VT ri = ld_lanes<T, V>(a.rb[0] + e);
-        VT wv = px_apply<T, KC, V>(a, a.zl, i, c0, ui);
+        VT wv = px_apply<T, KC, V>(a, a.zl, i, c0, ui, lb);
         st_lanes<T, V>(a.wb[0] + e, wv);
 #pragma unroll
         for (int u = 0; u < V; ++u) {
@@ -3205,11 +3210,12 @@ __global__ void __launch_bounds__(kBlock) k_px_ga(KA<T> a) {
     {
         const int L = d / V;
         const int c0 = ((int)threadIdx.x % L) * V;
+        const int ci = a.blk_seg[lb] * d + c0;   // the workgroup's segment's column scalars
         T alpha[V], beta[V];
 #pragma unroll
         for (int u = 0; u < V; ++u) {
-            alpha[u] = (T)a.cs.alpha[c0 + u < d ? c0 + u : 0];
-            beta[u] = (T)a.cs.beta[c0 + u < d ? c0 + u : 0];
+            alpha[u] = (T)a.cs.alpha[ci + u];
+            beta[u] = (T)a.cs.beta[ci + u];
         }
         px_walk<V>(a, lb, [&](int i, size_t e, int) {
             const T inv = a.invdiag[i];
@@ -3256,7 +3262,7 @@ __global__ void __launch_bounds__(kBlock) k_px_gb(KA<T> a) {
     double acc[1][V] = {};
     px_walk<V>(a, lb, [&](int i, size_t e, int c0) {
         VT ui = ld_lanes<T, V>(a.zl + e);
-        VT wv = px_apply<T, KC, V>(a, a.zl, i, c0, ui);
+        VT wv = px_apply<T, KC, V>(a, a.zl, i, c0, ui, lb);
         st_lanes<T, V>(a.wb[0] + e, wv);
 #pragma unroll
         for (int u = 0; u < V; ++u) acc[0][u] += (double)wv.v[u] * (double)ui.v[u];
@@ -4029,7 +4035,8 @@ struct Partition {
     int* bit = nullptr;       // device, 3 nblk: first row, end row, stride
     int* blk_seg = nullptr;   // device, nblk
     int* seg_blk0 = nullptr;  // device, nseg + 1
-    int* geo = nullptr;       // device, 8 nblk: strip geometry (strip partitions only)
+    int* geo = nullptr;       // device, 8 nblk: strip geometry (strip partitions), or the image
+                              // {row0, W, H} of each workgroup (pixel partitions of pixel grids)
 };
 
 struct pfe_ctx {
@@ -4048,7 +4055,7 @@ struct pfe_ctx {
     Partition pf;            // strips with a three-radius halo (one-pass factor CG)
     Partition px[2];         // pixel launches: contiguous pixel (row) ranges, one / two workgroups
                              // per CU (nblk == 0: not available)
-    int want_px = 0;         // Jacobi PCG of a one-segment graph by the per-pixel (per-row) kernels
+    int want_px = 0;         // Jacobi PCG by the per-pixel (per-row) kernels
                              // on px[want_px - 1] (0: not)
     int one_pass = 0;        // factor preconditioners on strips: one pass per CG iteration (0: two)
     int eu_px = 1;           // pixel stencils with b once per edge: the edge update by the per-pixel
@@ -4386,7 +4393,9 @@ template <typename T>
 int px_cols(int d) {
     static const int force = getenv("PFE_PX_COLS") ? atoi(getenv("PFE_PX_COLS")) : 0;   // launch-shape experiments
     if ((force == 1 || force == 2 || force == 4) && d % force == 0 && force * (int)sizeof(T) <= 16) return force;
-    return (sizeof(T) == 4) ? ((d % 4 == 0) ? 4 : 1) : ((d % 2 == 0) ? 2 : 1);
+    // (on the 64-image batch, d = 10, two columns per thread ran a SOC
+    // iteration in 71.6 ms against 74.8 ms for one)
+    return (sizeof(T) == 4) ? ((d % 4 == 0) ? 4 : ((d % 2 == 0) ? 2 : 1)) : ((d % 2 == 0) ? 2 : 1);
 }
 
 template <typename T>
@@ -4407,7 +4416,7 @@ pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0)
     if (a.pxl) {
         // pixel launch: the residual with r0, w0 and the CG iteration (two
         // kernels); stencil offsets on pixel grids, the slot columns otherwise
-        const int KP = (a.pxW > 0) ? K : 0;
+        const int KP = a.geo ? K : 0;
         KA<T> args = a;
         int pm = ph;
         void* kp1[] = {(void*)&args};
@@ -4582,8 +4591,8 @@ pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, const KA<T>*
                 add(kernel_for<T>(PH_LD, K, st), p2, a.nblk);
             }
         } else if (a.pxl) {
-            add(px_kernel_for<T>(PH_GA, a.pxW > 0 ? K : 0, a.d), p1, a.nblk);
-            add(px_kernel_for<T>(PH_IT, a.pxW > 0 ? K : 0, a.d), p1, a.nblk);
+            add(px_kernel_for<T>(PH_GA, a.geo ? K : 0, a.d), p1, a.nblk);
+            add(px_kernel_for<T>(PH_IT, a.geo ? K : 0, a.d), p1, a.nblk);
         } else if (!st && K != 4 && K != 8 && K != 24) {
             add(reinterpret_cast<const void*>(&k_cg_ga<T>), p1, a.nblk);
             add(reinterpret_cast<const void*>(&k_cg_gb<T>), p1, a.nblk);
@@ -4750,7 +4759,7 @@ pfe_status pcg_solve_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as, int res_ph)
 // has one and the context wants it
 inline bool use_strips(const pfe_ctx* c) { return c->want_strips > 0 && c->ps.nblk > 0; }
 
-// pixel launches: Jacobi PCG of a one-segment graph, when the context wants them
+// pixel launches: Jacobi PCG by the per-row kernels, when the context wants them
 inline bool use_px(const pfe_ctx* c) {
     return c->want_px > 0 && c->want_px <= 2 && c->px[c->want_px - 1].nblk > 0 && c->prm.precond == PFE_JACOBI;
 }
@@ -4764,10 +4773,6 @@ KA<T> pcg_args(pfe_ctx* c, const KA<T>& a) {
         ap.x = a.x;
         ap.rhs = a.rhs;
         ap.pxl = 1;
-        if (c->g->stencil) {
-            ap.pxW = c->g->seg_W[0];
-            ap.pxH = c->g->seg_H[0];
-        }
         return ap;
     }
     if (use_strips(c)) {
@@ -4869,7 +4874,7 @@ pfe_status inner_at(pfe_ctx* c, int l) {
     PFE_TRY(pcg_solve_mk(c, a, as, (l == 0) ? PH_E0 : PH_R0));
     // edge update of this inner step and rhs of the next one (on strips when
     // the slot data are loaded one image row ahead, widths up to 8)
-    KA<T> b = (as.geo && c->g->ell_K <= 8) ? as : a;
+    KA<T> b = (as.geo && !as.pxl && c->g->ell_K <= 8) ? as : a;
     b.store_rhs = 1;
     b.b_zero = (l == 0);
     b.bpar = l & 1;
@@ -4970,8 +4975,9 @@ pfe_status read_info(pfe_ctx* c, pfe_step_info* info) {
         info->status = h.status;
         info->fallbacks = h.fallbacks;
         info->workgroups = c->launched_coop ? c->pc.nblk : 0;
-        info->flags = ((c->launched_coop && c->cache_np > 0) ? 1 : 0) | ((!c->launched_coop && use_strips(c)) ? 2 : 0) |
-                      ((!c->launched_coop && use_px(c)) ? 4 : 0);
+        const bool px = !c->launched_coop && use_px(c);
+        info->flags = ((c->launched_coop && c->cache_np > 0) ? 1 : 0) |
+                      ((!c->launched_coop && !px && use_strips(c)) ? 2 : 0) | (px ? 4 : 0);
     }
     if (h.status != 0) {
         set_error("%s", pfe_status_string((pfe_status)h.status));
@@ -5334,6 +5340,23 @@ pfe_status setup_persistent(pfe_ctx* c) {
 
 extern "C" {
 
+// the image {row0, W, H} of each workgroup of a pixel partition of pixel-grid
+// segments (the workgroups of make_partition lie in one segment each)
+pfe_status set_px_geo(pfe_ctx* c, Partition& P) {
+    const pfe_graph* g = c->g;
+    std::vector<int> bseg(P.nblk), geo((size_t)8 * P.nblk, 0);
+    PFE_CHECK_HIP(hipMemcpy(bseg.data(), P.blk_seg, sizeof(int) * P.nblk, hipMemcpyDeviceToHost));
+    for (int b = 0; b < P.nblk; ++b) {
+        const int sg = bseg[b];
+        geo[8 * (size_t)b] = (int)g->seg_row0[sg];
+        geo[8 * (size_t)b + 1] = g->seg_W[sg];
+        geo[8 * (size_t)b + 2] = g->seg_H[sg];
+    }
+    PFE_CHECK_HIP(dev_alloc((void**)&P.geo, sizeof(int) * geo.size()));
+    PFE_CHECK_HIP(hipMemcpy(P.geo, geo.data(), sizeof(int) * geo.size(), hipMemcpyHostToDevice));
+    return PFE_OK;
+}
+
 pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream_t stream, pfe_ctx** out) {
     if (!g || !p || !Y0 || !out) { set_error("pfe_init: null argument"); return PFE_E_ARG; }
     *out = nullptr;
@@ -5419,12 +5442,14 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
         s = setup_strips(c);
         c->want_strips = want;
     }
-    const bool px_image = g->stencil && (g->ell_K == 4 || g->ell_K == 8 || g->ell_K == 24) && c->nseg == 1 &&
-                          g->seg_W.size() == 1 && g->seg_W[0] > 0 && g->seg_H[0] > 0 &&
-                          (int64_t)g->seg_W[0] * g->seg_H[0] == c->n;
-    if (s == PFE_OK && (px_image || (!g->stencil && c->nseg == 1))) {
-        // pixel (per-row) launches of one image or one general graph: one
-        // workgroup per CU, each a contiguous pixel (row) range (on
+    bool px_grid = g->stencil && (g->ell_K == 4 || g->ell_K == 8 || g->ell_K == 24) &&
+                   (int)g->seg_W.size() == c->nseg;
+    for (int sg = 0; px_grid && sg < c->nseg; ++sg)
+        px_grid = g->seg_W[sg] > 0 && g->seg_H[sg] > 0 && (int64_t)g->seg_W[sg] * g->seg_H[sg] == seg_rows[sg];
+    if (s == PFE_OK && (px_grid || !g->stencil)) {
+        // pixel (per-row) launches of pixel-grid images (one or a batch) or of a
+        // general layout: one workgroup per CU, each a contiguous pixel (row)
+        // range of one segment (on
         // the 1024 x 1024 window graph 256 workgroups ran a SOC iteration in
         // 20.3 ms, 512 in 21.5, 768 in 22.4, 1024 in 23.0, 2048 in 25.9)
         const int V = (p->dtype == PFE_FP64) ? px_cols<double>((int)c->d) : px_cols<float>((int)c->d);
@@ -5437,6 +5462,7 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
             if (want_px >= kNumXcd) want_px -= want_px % kNumXcd;   // whole XCD groups where there are enough
             if (k == 1 && want_px <= c->px[0].nblk) break;          // no second size
             s = make_partition(seg_rows, std::max(1, want_px), ppb, 1, c->px[k]);
+            if (s == PFE_OK && px_grid) s = set_px_geo(c, c->px[k]);
         }
     }
     if (const char* ev = getenv("PFE_PIXEL")) c->want_px = std::min(2, std::max(0, atoi(ev)));   // launch-shape experiments
@@ -5766,8 +5792,8 @@ pfe_status pfe_set_launch_shape(pfe_ctx* c, const pfe_tune_result* sh) {
         return PFE_E_ARG;
     }
     if (!sh->persistent && (sh->pixel < 0 || sh->pixel > 2 || (sh->pixel > 0 && c->px[sh->pixel - 1].nblk == 0))) {
-        set_error("pfe_set_launch_shape: pixel launches (1 or 2 workgroups per CU) need a graph of one segment "
-                  "(one image or one edge list; 2: one large enough for more workgroups than CUs)");
+        set_error("pfe_set_launch_shape: pixel launches take 1 or 2 workgroups per CU (2: a graph with more "
+                  "pixel steps than CUs)");
         return PFE_E_ARG;
     }
     c->prm.persistent = sh->persistent ? 1 : 0;

@@ -153,23 +153,51 @@ def test_autotune_offers_pixel_launches(monkeypatch):
     G.close()
 
 
-def test_pixel_launch_not_offered_for_batches_or_factor_preconditioners(monkeypatch):
-    """Batches (several images) and the learned / FSAI factor preconditioners
-    keep the strip launches: set_launch_shape rejects pixel launches on a batch
-    (and two workgroups per CU on a graph too small for them), and a
-    factor-preconditioned solve on a context that wants them runs on strips."""
+@pytest.mark.parametrize("fp64", [True, False])
+def test_pixel_launch_batch_matches_solo_and_strips(fp64, monkeypatch):
+    """A batch of uneven images by pixel launches (each workgroup a row range of
+    one image, its geometry and its segment's CG scalars): every image equals
+    its solo pixel-launch run, and the batch equals the strip launches."""
     from paper_1612_06496_amd import Graph, Solver
+    wls = synth.make_batch("voronoi_batch5_8nbr")
+    banner(f"pixel-launch batch == solo and == strips, fp64={fp64}")
+    kw = dict(lam=20.0, r=2.0, n_inner=wls[0].n_inner, tol=1e-11 if fp64 else 1e-6, maxit=3000, fp64=fp64,
+              persistent=False)
+    y0 = np.concatenate([w.y0 for w in wls])
+    out = {}
+    for pixel in (1, 0):
+        monkeypatch.setenv("PFE_PIXEL", str(pixel))
+        monkeypatch.setenv("PFE_STRIPS", "1")
+        parts = [gpu_graph(w) for w in wls]
+        U = Graph.union(parts)
+        S = Solver(U, y0, **kw)
+        info = S.solve(2, info=True)
+        assert bool(info["flags"] & 4) == bool(pixel) and bool(info["flags"] & 2) != bool(pixel)
+        out[pixel] = {k: to_np(S.get(k)) for k in ("Y", "P")}
+        row0, _ = U.segments
+        if pixel:
+            worst = 0.0
+            for k, (w, p) in enumerate(zip(wls, parts)):
+                Ss = Solver(p, w.y0, **kw)
+                Ss.solve(2)
+                sl = slice(row0[k], row0[k + 1])
+                worst = max(worst, rel(out[1]["Y"][sl], to_np(Ss.get("Y"))), rel(out[1]["P"][sl], to_np(Ss.get("P"))))
+                Ss.close()
+        S.close()
+    bound = 1e-8 if fp64 else 1e-5
+    vs_strips = max(rel(out[1][k], out[0][k]) for k in ("Y", "P"))
+    print(f"worst segment vs solo {worst:.2e}; batch vs strips {vs_strips:.2e} (bound {bound})")
+    assert worst <= bound and vs_strips <= bound
+
+
+def test_pixel_launch_shape_checks_and_factor_preconditioners(monkeypatch):
+    """set_launch_shape rejects two workgroups per CU on a graph too small for
+    them and sizes other than 1 and 2; a factor-preconditioned (FSAI) solve on a
+    context that wants pixel launches runs on strips."""
+    from paper_1612_06496_amd import Solver
     from paper_1612_06496_amd import _lib as L
     monkeypatch.setenv("PFE_PIXEL", "1")
-    banner("pixel launches: batch rejected, FSAI on strips")
-    wls = synth.make_batch("voronoi_batch5_8nbr")
-    U = Graph.union([gpu_graph(w) for w in wls])
-    S = Solver(U, np.concatenate([w.y0 for w in wls]), lam=20.0, r=2.0, n_inner=2, tol=1e-6, persistent=False)
-    with pytest.raises(L.PFEError):
-        S.set_launch_shape(persistent=False, pixel=True)
-    info = S.solve(1, info=True)
-    assert not (info["flags"] & 4)
-    S.close()
+    banner("pixel launches: shape checks, FSAI on strips")
     wl = synth.make_workload("voronoi48x40_r2", 0)
     G = gpu_graph(wl)
     S = Solver(G, wl.y0, lam=20.0, r=2.0, n_inner=2, tol=1e-6, persistent=False)
