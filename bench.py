@@ -31,6 +31,24 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def shape_label(shape):
+    """A readable name of an autotuned launch shape."""
+    if shape["persistent"]:
+        return "persistent"
+    if shape.get("pixel"):
+        return f"per-row ({shape['pixel']} workgroup(s) per CU)"
+    if shape["strips"]:
+        return f"strips ({shape['strips']} wave(s)" + (", one pass per iteration)" if shape.get("one_pass") else ")")
+    return "row chunks"
+
+
+def launch_of(info):
+    """Launch of a run from its step flags."""
+    if info["workgroups"]:
+        return "persistent"
+    return "per-row" if info["flags"] & 4 else ("strips" if info["flags"] & 2 else "multi")
+
+
 def algorithmic_bytes(n, E, d, esz, cg_iters, solves, n_inner, n_outer, pupdate=True):
     """Bytes the method has to move (FP32 values, int32 indices): per CG
     iteration the slot columns and weights, row pointers, diagonal and ten n x d
@@ -222,8 +240,8 @@ def learned_leg(train_seeds=(1000, 1001, 1002, 1003, 1004), ratios=(1.0, 10.0, 1
                 "held_out_loss": {"jacobi": loss_jacobi, "initial": loss_before, "trained": loss_after}}
 
     rows = []
-    jshape = None     # launch shapes autotuned at the first ratio, Jacobi and the factor path
-    fshape = None
+    jshape = None     # Jacobi's launch shape, autotuned at the first ratio (the factor path: at every
+                      # ratio, its best shape depends on the iteration count)
     for ratio in ratios:
         res = {"lambda_over_r": ratio}
         # FSAI is built for pixel grids (stencil slot layout) only
@@ -241,11 +259,7 @@ def learned_leg(train_seeds=(1000, 1001, 1002, 1003, 1004), ratios=(1.0, 10.0, 1
                     S.set_fsai()
                 torch.cuda.synchronize()
                 factor_ms = round((time.perf_counter() - t0) * 1e3, 2)
-                if fshape is None:
-                    shape = fshape = [t for t in S.autotune(trials=1) if t["chosen"]][0]
-                else:
-                    shape = fshape
-                    S.set_launch_shape(persistent=False, strips=shape["strips"], one_pass=bool(shape["one_pass"]))
+                shape = [t for t in S.autotune(trials=1) if t["chosen"]][0]
             elif jshape is None:
                 shape = jshape = [t for t in S.autotune(trials=1) if t["chosen"]][0]
             else:
@@ -265,10 +279,7 @@ def learned_leg(train_seeds=(1000, 1001, 1002, 1003, 1004), ratios=(1.0, 10.0, 1
                         "ms_per_solve": round(dt * 1e3 / max(1, info["solves"]), 3),
                         "rel_res_max": float(f"{info['rel_res_max']:.3g}"), "status": info["status"]}
             if shape is not None:
-                res[pre]["launch"] = ("persistent" if shape["persistent"] else
-                                      (f"strips ({shape['strips']} wave(s)"
-                                       + (", one pass per iteration)" if shape.get("one_pass") else ")"))
-                                      if shape["strips"] else "one launch per phase")
+                res[pre]["launch"] = shape_label(shape)
             if factor_ms is not None:
                 res[pre]["factor_ms"] = factor_ms
                 res[pre]["ms_per_solve_amortised"] = round(res[pre]["ms_per_solve"] + factor_ms / max(1, info["solves"]), 3)
@@ -311,7 +322,7 @@ def d_sweep_leg(G, wl, dims=(5, 10, 15, 20, 25), steps=10):
         info = S.stats(reset=True)
         rows.append({"d": d, "outer_iters_per_s": round(steps / (ms / 1e3), 1), "ms_per_step": round(ms / steps, 4),
                      "pcg_iters_per_solve": round(info["cg_iters_total"] / max(1, info["solves"]), 2),
-                     "launch": "persistent" if info["workgroups"] else ("strips" if info["flags"] & 2 else "multi")})
+                     "launch": launch_of(info)})
         S.close()
         progress(f"d-sweep: d = {d} done")
     return rows
@@ -389,7 +400,7 @@ def le_init_leg(G, wl, k=32, tol=1e-12, steps=10, oracle_time=True):
     out["headline_from_le"] = {"lambda": c, "r": c, "ms_per_step": round(ms / steps, 4),
                                "outer_iters_per_s": round(steps / (ms / 1e3), 1),
                                "pcg_iters_per_solve": round(st["cg_iters_total"] / max(1, st["solves"]), 2),
-                               "launch": "persistent" if st["workgroups"] else ("strips" if st["flags"] & 2 else "multi")}
+                               "launch": launch_of(st)}
     if oracle_time:
         import oracle as O
         g = O.build_grid_graph(wl.feat, wl.H, wl.W, wl.stencil, wl.sigma)
@@ -448,7 +459,7 @@ def clustering_leg(name="gmm200k_knn16_rcm", steps=3):
            "pcg_iters_per_solve": round(info["cg_iters_total"] / max(1, info["solves"]), 2),
            "algorithmic_gbs": round(byt / (ms / 1e3) / 1e9, 1),
            "frac": round(byt / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
-           "launch": "persistent" if info["workgroups"] else ("strips" if info["flags"] & 2 else "multi"),
+           "launch": launch_of(info),
            "autotuned": tuned[0] if tuned else None,
            "kmeans_iterations": kit, "label_agreement_with_components": round(agree, 4)}
     S.close()
@@ -500,7 +511,7 @@ def d_sweep_batched_leg(wl, c, dims=(5, 10, 15, 20, 25), steps=10):
             "outer_iters_per_s": round(steps / (ms / 1e3), 1),
             "pcg_iters_per_solve": round(info["cg_iters_total"] / max(1, info["solves"]), 2),
             "constraint": float(f"{mon['constraint']:.3g}"),
-            "launch": ("persistent" if info["workgroups"] else ("strips" if info["flags"] & 2 else "multi")),
+            "launch": launch_of(info),
             "autotuned": tuned[0] if tuned else None}
 
 
@@ -653,7 +664,7 @@ def main():
     n, E, d = G.n, G.n_edges, wl.d
     byt = algorithmic_bytes(n, E, d, 4, info["cg_iters_total"], info["solves"], wl.n_inner, args.steps)
     achieved = byt / (ms / 1e3) / 1e9
-    launch = "persistent" if info["workgroups"] else ("strips" if info["flags"] & 2 else "multi")
+    launch = launch_of(info)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.workload, launch),
             "kernel": "k_soc (one SOC iteration per launch)" if info["workgroups"] else
@@ -697,7 +708,7 @@ def main():
         line["stage2"] = {"iterations": args.stage2_iters, "ms": round(ms2, 3),
                           "sb_iters_per_s": round(args.stage2_iters / (ms2 / 1e3), 1),
                           "pcg_iters_per_solve": round(i2["cg_iters_total"] / max(1, i2["solves"]), 2),
-                          "launch": "persistent" if i2["workgroups"] else ("strips" if i2["flags"] & 2 else "multi"),
+                          "launch": launch_of(i2),
                           "algorithmic_gbs": round(b2 / (ms2 / 1e3) / 1e9, 1),
                           "frac": round(b2 / (ms2 / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
     if args.kmeans_iters > 0 and len(wls) == 1:

@@ -2159,7 +2159,7 @@ __device__ __forceinline__ void fin_it(const KA<T>& a, double* sh, bool grouped)
 // learned path, after PH_LD: initial (before the first iteration) or after an
 // iteration: convergence on ||r||, beta = (r.z)_new / (r.z)_old
 template <typename T>
-__device__ __forceinline__ void fin_ld(const KA<T>& a, double* sh, bool initial) {
+__device__ __forceinline__ void fin_ld(const KA<T>& a, double* sh, bool initial, bool grouped = false) {
     const int d = a.d;
     double* out = sh + 1024;
     __shared__ int s_any, s_bad;
@@ -2167,7 +2167,7 @@ __device__ __forceinline__ void fin_ld(const KA<T>& a, double* sh, bool initial)
     const int chunk = seg_chunk(2, d);
     for (int sg0 = 0; sg0 < a.nseg; sg0 += chunk) {
         const int ns = min(chunk, a.nseg - sg0);
-        seg_sums_all(a, sg0, ns, 2, out, sh, false);
+        seg_sums_all(a, sg0, ns, 2, out, sh, grouped);
         for (int idx = threadIdx.x; idx < ns * d; idx += blockDim.x) {
             const int k = idx / d, c = idx - k * d, ci = (sg0 + k) * d + c;
             const double* o = out + k * 2 * d;
@@ -2212,7 +2212,7 @@ __device__ __forceinline__ void fin_ld(const KA<T>& a, double* sh, bool initial)
 
 // learned path, after PH_LA: alpha = (r.z) / (p.q)
 template <typename T>
-__device__ __forceinline__ void fin_la(const KA<T>& a, double* sh) {
+__device__ __forceinline__ void fin_la(const KA<T>& a, double* sh, bool grouped = false) {
     const int d = a.d;
     double* out = sh + 1024;
     __shared__ int s_bad;
@@ -2220,7 +2220,7 @@ __device__ __forceinline__ void fin_la(const KA<T>& a, double* sh) {
     const int chunk = seg_chunk(1, d);
     for (int sg0 = 0; sg0 < a.nseg; sg0 += chunk) {
         const int ns = min(chunk, a.nseg - sg0);
-        seg_sums_all(a, sg0, ns, 1, out, sh, false);
+        seg_sums_all(a, sg0, ns, 1, out, sh, grouped);
         for (int idx = threadIdx.x; idx < ns * d; idx += blockDim.x) {
             const int k = idx / d, c = idx - k * d, ci = (sg0 + k) * d + c;
             double al = 0.0;
@@ -3271,6 +3271,191 @@ __global__ void __launch_bounds__(kBlock) k_px_gb(KA<T> a) {
     block_partials_px<1, V>(acc, qo, sh, a.d, a.part, a.nblk, lb);
     if (last_of_launch(a, 3, sh)) {
         fin_it(a, sh, grouped_fin(a));
+        if (threadIdx.x == 0 && a.S->done) solve_stats(a);
+    }
+}
+
+// Factor-preconditioned PCG (M^{-1} = D_A^{-1/2} Gt^T Gt D_A^{-1/2}) by pixel
+// launches on pixel grids, three passes per iteration with the st_la / st_lcd
+// arithmetic; a neighbour's value is formed again from its loaded inputs where
+// the strip kernels read it from an LDS ring:
+//   k_pl_a: p = z + beta p, q = A p (neighbours' p from their z and old p);
+//           partial p.q -> alpha
+//   k_pl_c: x += alpha p, r' = r - alpha q (upd), y1 = Gt D_A^{-1/2} r' over the
+//           lower slots (neighbours' r' from their r and q); y1 stored
+//   k_pl_d: z = D_A^{-1/2} Gt^T y1 over the upper slots; partials r'.z, r'.r'
+//           -> beta, convergence (initial: from the initial residual)
+template <typename T, int KC, int V>
+__global__ void __launch_bounds__(kBlock) k_pl_a(KA<T> a) {
+    using VT = Lanes<T, V>;
+    constexpr int G = (KC < 8) ? KC : 8;
+    __shared__ double sh[kPxSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    const int lb = logical_block(a.nblk);
+    const int it = ld_flag(&a.S->it);
+    const bool first = (it == 0);
+    T* pnew = a.sb[it & 1];
+    const T* pold = a.sb[(it & 1) ^ 1];
+    const int d = a.d, L = d / V;
+    const int ci = a.blk_seg[lb] * d + ((int)threadIdx.x % L) * V;
+    T beta[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) beta[u] = (T)a.cs.beta[ci + u];
+    const int* gg = a.geo + 8 * lb;
+    const int W = gg[1], H = gg[2], r0g = gg[0];
+    double acc[1][V] = {};
+    auto p_of = [&](const VT& z, const VT& po) {
+        VT p;
+#pragma unroll
+        for (int u = 0; u < V; ++u) p.v[u] = first ? z.v[u] : fma_t(beta[u], po.v[u], z.v[u]);
+        return p;
+    };
+    px_walk<V>(a, lb, [&](int i, size_t e, int c0) {
+        const int il = i - r0g, py = il / W, px = il - py * W;
+        VT zero;
+#pragma unroll
+        for (int u = 0; u < V; ++u) zero.v[u] = T(0);
+        const VT pi = p_of(ld_lanes<T, V>(a.zl + e), first ? zero : ld_lanes<T, V>(pold + e));
+        VT accA = zero;
+#pragma unroll
+        for (int k0 = 0; k0 < KC; k0 += G) {
+            T ww[G];
+            VT pj[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const size_t ej = (size_t)px_nb<KC>(i, py, px, W, H, k0 + k) * d + c0;
+                ww[k] = a.sw[(size_t)(k0 + k) * a.n + i];
+                pj[k] = p_of(ld_lanes<T, V>(a.zl + ej), first ? zero : ld_lanes<T, V>(pold + ej));
+            }
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const T w2 = mul_t(ww[k], ww[k]);
+#pragma unroll
+                for (int u = 0; u < V; ++u) accA.v[u] = fma_t(w2, pj[k].v[u], accA.v[u]);
+            }
+        }
+        const T dA = a.diagA[i];
+        VT qi;
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            qi.v[u] = fma_t(dA, pi.v[u], -mul_t(a.c_off, accA.v[u]));
+            acc[0][u] += (double)pi.v[u] * (double)qi.v[u];
+        }
+        st_lanes<T, V>(pnew + e, pi);
+        st_lanes<T, V>(a.wb[0] + e, qi);
+    });
+    const int qo[1] = {0};
+    block_partials_px<1, V>(acc, qo, sh, d, a.part, a.nblk, lb);
+    if (last_of_launch(a, 1, sh)) fin_la(a, sh, grouped_fin(a));
+}
+
+template <typename T, int KC, int V>
+__global__ void __launch_bounds__(kBlock) k_pl_c(KA<T> a, int upd) {
+    using VT = Lanes<T, V>;
+    constexpr int HS = KC / 2;
+    if (ld_flag(&a.S->done)) return;
+    const int lb = logical_block(a.nblk);
+    const int it = upd ? ld_flag(&a.S->it) : 0;
+    const T* r = a.rb[it & 1];
+    T* rn = a.rb[(it & 1) ^ 1];
+    const T* p = a.sb[it & 1];
+    const T* q = a.wb[0];
+    const int d = a.d, L = d / V;
+    const int ci = a.blk_seg[lb] * d + ((int)threadIdx.x % L) * V;
+    T alpha[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) alpha[u] = upd ? (T)a.cs.alpha[ci + u] : T(0);
+    const int* gg = a.geo + 8 * lb;
+    const int W = gg[1], H = gg[2], r0g = gg[0];
+    // isq r' of element e of pixel j (r' = r - alpha q after the update)
+    auto sr_of = [&](int j, size_t ej) {
+        VT rv = ld_lanes<T, V>(r + ej);
+        if (upd) {
+            const VT qv = ld_lanes<T, V>(q + ej);
+#pragma unroll
+            for (int u = 0; u < V; ++u) rv.v[u] = fma_t(-alpha[u], qv.v[u], rv.v[u]);
+        }
+        return rv;
+    };
+    px_walk<V>(a, lb, [&](int i, size_t e, int c0) {
+        const int il = i - r0g, py = il / W, px = il - py * W;
+        const VT ri = sr_of(i, e);
+        if (upd) {
+            const VT pv = ld_lanes<T, V>(p + e);
+            VT xv = ld_lanes<T, V>(a.x + e);
+#pragma unroll
+            for (int u = 0; u < V; ++u) xv.v[u] = fma_t(alpha[u], pv.v[u], xv.v[u]);
+            st_lanes<T, V>(a.x + e, xv);
+            st_lanes<T, V>(rn + e, ri);
+        }
+        const T gd = a.gdiag[i], si = a.isq[i];
+        VT y;
+#pragma unroll
+        for (int u = 0; u < V; ++u) y.v[u] = mul_t(gd, mul_t(si, ri.v[u]));
+        T gv[HS], sj[HS];
+        VT rj[HS];
+#pragma unroll
+        for (int k = 0; k < HS; ++k) {
+            const int j = px_nb<KC>(i, py, px, W, H, k);
+            gv[k] = a.gval[(size_t)k * a.n + i];
+            sj[k] = a.isq[j];
+            rj[k] = sr_of(j, (size_t)j * d + c0);
+        }
+#pragma unroll
+        for (int k = 0; k < HS; ++k) {
+#pragma unroll
+            for (int u = 0; u < V; ++u) y.v[u] = fma_t(gv[k], mul_t(sj[k], rj[k].v[u]), y.v[u]);
+        }
+        st_lanes<T, V>(a.y1 + e, y);
+    });
+}
+
+template <typename T, int KC, int V>
+__global__ void __launch_bounds__(kBlock) k_pl_d(KA<T> a, int initial) {
+    using VT = Lanes<T, V>;
+    constexpr int HS = KC / 2;
+    __shared__ double sh[kPxSmemDoubles];
+    if (ld_flag(&a.S->done)) return;
+    const int lb = logical_block(a.nblk);
+    const int it = initial ? 0 : ld_flag(&a.S->it);
+    const T* rr = initial ? a.rb[0] : a.rb[(it & 1) ^ 1];
+    const int d = a.d;
+    const int* gg = a.geo + 8 * lb;
+    const int W = gg[1], H = gg[2], r0g = gg[0];
+    double acc[2][V] = {};
+    px_walk<V>(a, lb, [&](int i, size_t e, int c0) {
+        const int il = i - r0g, py = il / W, px = il - py * W;
+        const T gd = a.gdiag[i];
+        const VT yi = ld_lanes<T, V>(a.y1 + e);
+        VT z;
+#pragma unroll
+        for (int u = 0; u < V; ++u) z.v[u] = mul_t(gd, yi.v[u]);
+        T gv[KC - HS];
+        VT yj[KC - HS];
+#pragma unroll
+        for (int k = HS; k < KC; ++k) {
+            gv[k - HS] = a.gval[(size_t)k * a.n + i];
+            yj[k - HS] = ld_lanes<T, V>(a.y1 + (size_t)px_nb<KC>(i, py, px, W, H, k) * d + c0);
+        }
+#pragma unroll
+        for (int k = 0; k < KC - HS; ++k) {
+#pragma unroll
+            for (int u = 0; u < V; ++u) z.v[u] = fma_t(gv[k], yj[k].v[u], z.v[u]);
+        }
+        const T si = a.isq[i];
+        const VT ri = ld_lanes<T, V>(rr + e);
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            z.v[u] = mul_t(si, z.v[u]);
+            acc[0][u] += (double)ri.v[u] * (double)z.v[u];
+            acc[1][u] += (double)ri.v[u] * (double)ri.v[u];
+        }
+        st_lanes<T, V>(a.zl + e, z);
+    });
+    const int qo[2] = {0, 1};
+    block_partials_px<2, V>(acc, qo, sh, d, a.part, a.nblk, lb);
+    if (last_of_launch(a, 2, sh)) {
+        fin_ld(a, sh, initial != 0, grouped_fin(a));
         if (threadIdx.x == 0 && a.S->done) solve_stats(a);
     }
 }
@@ -4378,14 +4563,23 @@ const void* px_kernel(int ph, int K) {
         case 8: return reinterpret_cast<const void*>(&KN<T, 8, V>);                    \
         case 24: return reinterpret_cast<const void*>(&KN<T, 24, V>);                  \
         default: return reinterpret_cast<const void*>(&KN<T, 0, V>); }
+#define PFE_PXSEL_ST(KN) switch (K) {                                                   \
+        case 4: return reinterpret_cast<const void*>(&KN<T, 4, V>);                    \
+        case 8: return reinterpret_cast<const void*>(&KN<T, 8, V>);                    \
+        case 24: return reinterpret_cast<const void*>(&KN<T, 24, V>);                  \
+        default: return nullptr; }
     switch (ph) {
         case PH_R0: PFE_PXSEL(k_px_res)
         case PH_W0: PFE_PXSEL(k_px_w0)
         case PH_IT: PFE_PXSEL(k_px_gb)
         case PH_GA: return reinterpret_cast<const void*>(&k_px_ga<T, V>);
+        case PH_LA: PFE_PXSEL_ST(k_pl_a)
+        case PH_LC: PFE_PXSEL_ST(k_pl_c)
+        case PH_LD: PFE_PXSEL_ST(k_pl_d)
         default: return nullptr;
     }
 #undef PFE_PXSEL
+#undef PFE_PXSEL_ST
 }
 
 // columns per thread of the per-pixel kernels: 16-byte accesses where d allows
@@ -4434,6 +4628,14 @@ pfe_status launch_phase(pfe_ctx* c, const KA<T>& a, int ph, int mode, int do_r0)
             if (fa && fn) {
                 PFE_CHECK_HIP(hipLaunchKernel(fa, grid, dim3(kBlock), kp1, 0, st));
                 PFE_CHECK_HIP(hipLaunchKernel(fn, grid, dim3(kBlock), kp1, 0, st));
+                return PFE_OK;
+            }
+        } else if (ph == PH_LA || ph == PH_LC || ph == PH_LD) {
+            // factor-preconditioned PCG (pixel grids); PH_LC: mode = update, PH_LD: mode = initial
+            fn = px_kernel_for<T>(ph, KP, a.d);
+            pm = mode;
+            if (fn) {
+                PFE_CHECK_HIP(hipLaunchKernel(fn, grid, dim3(kBlock), ph == PH_LA ? kp1 : kp2, 0, st));
                 return PFE_OK;
             }
         }
@@ -4582,6 +4784,10 @@ pfe_status cg_chunk_graph(pfe_ctx* c, const KA<T>& a, bool learned, const KA<T>*
     for (int k = 0; k < kCgChunk; ++k) {
         if (learned && af) {
             add(kernel_for<T>(PH_FIT, K, true, c->fcg_cpl), p5, af->nblk);
+        } else if (learned && a.pxl) {
+            add(px_kernel_for<T>(PH_LA, a.geo ? K : 0, a.d), p1, a.nblk);
+            add(px_kernel_for<T>(PH_LC, a.geo ? K : 0, a.d), p3, a.nblk);
+            add(px_kernel_for<T>(PH_LD, a.geo ? K : 0, a.d), p2, a.nblk);
         } else if (learned) {
             add(kernel_for<T>(PH_LA, K, st), p1, a.nblk);
             if (al) {
@@ -4658,7 +4864,7 @@ pfe_status pcg_loop_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
 template <typename T>
 pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
     // on strips with a three-radius halo: one pass per iteration
-    if (as.geo && c->pf.nblk > 0 && c->one_pass) {
+    if (as.geo && !as.pxl && c->pf.nblk > 0 && c->one_pass) {
         KA<T> af = make_args<T>(c, c->pf);
         af.x = as.x;       // the iterate and rhs of this solve (a caller's buffers in pfe_pcg)
         af.rhs = as.rhs;
@@ -4681,7 +4887,7 @@ pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
     }
     // on strips the two factor products run as one kernel on strips with a
     // two-radius halo
-    const bool fused = as.geo && c->pl.nblk > 0;
+    const bool fused = as.geo && !as.pxl && c->pl.nblk > 0;
     KA<T> al = as;
     if (fused) {
         al = make_args<T>(c, c->pl);
@@ -4759,9 +4965,13 @@ pfe_status pcg_solve_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as, int res_ph)
 // has one and the context wants it
 inline bool use_strips(const pfe_ctx* c) { return c->want_strips > 0 && c->ps.nblk > 0; }
 
-// pixel launches: Jacobi PCG by the per-row kernels, when the context wants them
+// pixel launches: PCG by the per-row kernels (Jacobi on any layout, the factor
+// preconditioners on pixel grids), when the context wants them
 inline bool use_px(const pfe_ctx* c) {
-    return c->want_px > 0 && c->want_px <= 2 && c->px[c->want_px - 1].nblk > 0 && c->prm.precond == PFE_JACOBI;
+    if (c->want_px <= 0 || c->want_px > 2) return false;
+    const Partition& P = c->px[c->want_px - 1];
+    // the factor preconditioners' pixel kernels exist for pixel grids only
+    return P.nblk > 0 && (c->prm.precond == PFE_JACOBI || P.geo != nullptr);
 }
 
 // arguments of the PCG phases (residual, w0, iterations) for the iterate and
@@ -5683,7 +5893,9 @@ pfe_status pfe_autotune(pfe_ctx* c, int trials, pfe_tune_result* results, int ma
             if (sh.strips && c->strip_slots == 0) continue;
             if (sh.w2 != 1.0 && c->per_cu != 2) continue;
             if (sh.one_pass && (c->prm.precond == PFE_JACOBI || c->fcg_slots == 0)) continue;
-            if (sh.pixel && (c->prm.precond != PFE_JACOBI || c->px[sh.pixel - 1].nblk == 0)) continue;
+            if (sh.pixel && (c->px[sh.pixel - 1].nblk == 0 ||
+                             (c->prm.precond != PFE_JACOBI && c->px[sh.pixel - 1].geo == nullptr)))
+                continue;
             c->one_pass = sh.one_pass;
             c->want_px = sh.pixel;
             c->prm.persistent = sh.persistent;

@@ -193,11 +193,12 @@ def test_pixel_launch_batch_matches_solo_and_strips(fp64, monkeypatch):
 def test_pixel_launch_shape_checks_and_factor_preconditioners(monkeypatch):
     """set_launch_shape rejects two workgroups per CU on a graph too small for
     them and sizes other than 1 and 2; a factor-preconditioned (FSAI) solve on a
-    context that wants pixel launches runs on strips."""
+    pixel grid runs by pixel launches too, and on an edge-list graph it keeps
+    the row chunks."""
     from paper_1612_06496_amd import Solver
     from paper_1612_06496_amd import _lib as L
     monkeypatch.setenv("PFE_PIXEL", "1")
-    banner("pixel launches: shape checks, FSAI on strips")
+    banner("pixel launches: shape checks, factor preconditioners")
     wl = synth.make_workload("voronoi48x40_r2", 0)
     G = gpu_graph(wl)
     S = Solver(G, wl.y0, lam=20.0, r=2.0, n_inner=2, tol=1e-6, persistent=False)
@@ -207,8 +208,19 @@ def test_pixel_launch_shape_checks_and_factor_preconditioners(monkeypatch):
         S.set_launch_shape(persistent=False, pixel=3)
     S.set_fsai()
     info = S.solve(1, info=True)
+    assert info["flags"] & 4
+    S.close()
+    G.close()
+    from paper_1612_06496_amd import Mpnn
+    wle = edge_workload(4)
+    G = gpu_graph(wle)
+    S = Solver(G, wle.y0, lam=20.0, r=2.0, n_inner=2, tol=1e-6, persistent=False)
+    net = Mpnn(None)
+    S.set_learned(net)
+    info = S.solve(1, info=True)
     assert not (info["flags"] & 4)
     S.close()
+    net.close()
     G.close()
 
 
@@ -264,3 +276,80 @@ def test_row_launch_general_graph_pcg_matches_direct_solve(monkeypatch):
     assert np.all(np.abs(iters - it_o) <= 1)
     S.close()
     G.close()
+
+
+FACTOR_CASES = [(8, 4, True, "learned"), (-2, 5, True, "learned"), (4, 3, True, "fsai"), (-2, 16, True, "fsai"),
+                (-2, 16, False, "learned"), (8, 10, False, "fsai")]
+
+
+@pytest.mark.parametrize("stencil,d,fp64,pre", FACTOR_CASES)
+def test_pixel_factor_pcg_matches_strips(stencil, d, fp64, pre, monkeypatch):
+    """Factor-preconditioned PCG (learned G or FSAI) by pixel launches, three
+    per-pixel passes per iteration (p and q = A p; x, r' and y1 = Gt D_A^{-1/2} r';
+    z = D_A^{-1/2} Gt^T y1), against the strip launches on every stencil width
+    and with 1, 2 and 4 columns per thread: the iterate and the iteration
+    counts of the standalone PCG call."""
+    from paper_1612_06496_amd import Mpnn, Solver
+    banner(f"{pre} PCG by pixel launches vs strips: stencil={stencil} d={d} fp64={fp64}")
+    wl = synth.grid_workload("t", 45, 101, 6, 0.05, 3, stencil=stencil, d=d)
+    th = np.random.default_rng(1).normal(0.0, 0.3, size=Mpnn.NPARAMS)
+    th[Mpnn.NPARAMS - 1] = np.log(np.e - 1.0)
+    rhs = np.random.default_rng(2).normal(size=(wl.n, d))
+    tol = 1e-10 if fp64 else 1e-6
+    out = []
+    for pixel in ("1", "0"):
+        monkeypatch.setenv("PFE_PIXEL", pixel)
+        monkeypatch.setenv("PFE_STRIPS", "1")
+        G = gpu_graph(wl)
+        S = Solver(G, wl.y0, lam=20.0, r=1.0, n_inner=2, tol=tol, maxit=5000, fp64=fp64, persistent=False)
+        net = None
+        if pre == "learned":
+            net = Mpnn(th.astype(np.float32))
+            S.set_learned(net)
+        else:
+            S.set_fsai()
+        x, iters, info = S.pcg(rhs, np.zeros_like(rhs))
+        assert bool(info["flags"] & 4) == (pixel == "1")
+        assert info["fallbacks"] == 0
+        out.append((to_np(x), np.asarray(iters), info))
+        S.close()
+        if net is not None:
+            net.close()
+        G.close()
+    e = rel(out[0][0], out[1][0])
+    print(f"rel diff {e:.2e}; iterations {out[0][1].tolist()} vs {out[1][1].tolist()}")
+    assert np.all(np.abs(out[0][1] - out[1][1]) <= (1 if fp64 else 2))
+    assert e <= (1e-9 if fp64 else 1e-4)
+    assert out[0][2]["rel_res_max"] <= tol
+
+
+def test_pixel_factor_pcg_graph_replay_bitwise_and_direct_solve(monkeypatch):
+    """FSAI PCG by pixel launches: replayed from HIP graphs (three nodes per
+    iteration) bitwise equal to host launches, and the solution of the direct
+    solve within the condition-number bound of the stopping rule."""
+    from paper_1612_06496_amd import Solver
+    monkeypatch.setenv("PFE_PIXEL", "1")
+    wl = synth.make_workload("voronoi48x40_r2", 0)
+    banner("FSAI PCG by pixel launches: graph replay, direct solve")
+    g = oracle_graph(wl)
+    lam, r, tol = 40.0, 2.0, 1e-12
+    rhs = np.random.default_rng(5).normal(size=(g.n, wl.y0.shape[1]))
+    res = []
+    for graphs in (True, False):
+        G = gpu_graph(wl)
+        S = Solver(G, wl.y0, lam=lam, r=r, n_inner=2, tol=tol, maxit=5000, fp64=True, persistent=False,
+                   graphs=graphs)
+        S.set_fsai()
+        x, iters, info = S.pcg(rhs, np.zeros_like(rhs))
+        assert info["flags"] & 4
+        res.append((to_np(x), iters, info))
+        S.close()
+        G.close()
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    A = O.system_matrix(g, lam, r)
+    exact = O.DirectSolver(A)(rhs)
+    kappa = O.jacobi_condition_number(A)
+    e = rel(res[0][0], exact)
+    print(f"rel err {e:.2e}, kappa {kappa:.1f}, iterations {res[0][1].max()}")
+    assert res[0][2]["rel_res_max"] <= tol
+    assert e <= kappa * tol * 4
