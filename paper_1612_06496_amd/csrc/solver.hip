@@ -323,6 +323,10 @@ constexpr int kSlotUnroll = KC > 0 ? 4 : 2;
 
 // slots per group of the loops over rows of any length (general CSR layout)
 constexpr int kGenGroup = 4;
+// the per-row kernels' slot groups on general layouts (one thread per row and
+// up to four columns: fewer threads per row, so more slots in flight each; on
+// the 200k k-NN graph 8 ran a SOC iteration in 20.0 ms, 4 in 21.3)
+constexpr int kRowGroup = 8;
 
 template <int KC, int GM>
 constexpr int slot_group() { return KC <= 0 ? 1 : (KC <= GM ? KC : GM); }
@@ -2890,35 +2894,39 @@ __global__ void __launch_bounds__(kBlock) k_eu_px(KA<T> a, int W, int H) {
             st_lanes<T, V>(bwrite + (size_t)sl * d + c0, bn);
             if (a.keep_split) st_lanes<T, V>(a.ds + (size_t)sl * d + c0, dn);
         };
+        // full groups of kRowGroup slots, then the rest one by one (slot order kept;
+        // predicated last groups were slower)
         int k = 0;
-        for (; k + kGenGroup <= cnt; k += kGenGroup) {
-            T ww[kGenGroup];
-            VT yj[kGenGroup], bo[kGenGroup];
+        for (; k + kRowGroup <= cnt; k += kRowGroup) {
+            T ww[kRowGroup];
+            VT yj[kRowGroup], bo[kRowGroup];
 #pragma unroll
-            for (int g = 0; g < kGenGroup; ++g) {
-                const int sl = s0 + (k + g) * st;
-                ww[g] = a.sw[sl];
-                yj[g] = ld_lanes<T, V>(a.Y + (size_t)a.scol[sl] * d + c0);
-                if (a.b_zero) {
+            for (int g = 0; g < kRowGroup; ++g) {
+                {
+                    const int sl = s0 + (k + g) * st;
+                    ww[g] = a.sw[sl];
+                    yj[g] = ld_lanes<T, V>(a.Y + (size_t)a.scol[sl] * d + c0);
+                    if (a.b_zero) {
 #pragma unroll
-                    for (int u = 0; u < V; ++u) bo[g].v[u] = T(0);
-                } else {
-                    bo[g] = ld_lanes<T, V>(bread + (size_t)sl * d + c0);
+                        for (int u = 0; u < V; ++u) bo[g].v[u] = T(0);
+                    } else {
+                        bo[g] = ld_lanes<T, V>(bread + (size_t)sl * d + c0);
+                    }
                 }
             }
 #pragma unroll
-            for (int g = 0; g < kGenGroup; ++g) slot(s0 + (k + g) * st, ww[g], yj[g], bo[g]);
+            for (int g = 0; g < kRowGroup; ++g) slot(s0 + (k + g) * st, ww[g], yj[g], bo[g]);
         }
         for (; k < cnt; ++k) {
             const int sl = s0 + k * st;
-            VT bo;
+            VT b1;
             if (a.b_zero) {
 #pragma unroll
-                for (int u = 0; u < V; ++u) bo.v[u] = T(0);
+                for (int u = 0; u < V; ++u) b1.v[u] = T(0);
             } else {
-                bo = ld_lanes<T, V>(bread + (size_t)sl * d + c0);
+                b1 = ld_lanes<T, V>(bread + (size_t)sl * d + c0);
             }
-            slot(sl, a.sw[sl], ld_lanes<T, V>(a.Y + (size_t)a.scol[sl] * d + c0), bo);
+            slot(sl, a.sw[sl], ld_lanes<T, V>(a.Y + (size_t)a.scol[sl] * d + c0), b1);
         }
     } else {
         int py = 0, px = 0;
@@ -3043,7 +3051,7 @@ __device__ __forceinline__ void block_partials_px(const double (&acc)[NQ][V], co
 
 // sum over the slots k of row i of w_k^2 v_j (slot order), V columns from c0:
 // stencil offsets on pixel grids (KC > 0), the row's slot columns otherwise
-// (ELL or CSR; loads in groups of kGenGroup slots, as in the row-chunk phases)
+// (ELL or CSR; loads in groups of kRowGroup slots, slot order kept)
 template <typename T, int KC, int V>
 __device__ __forceinline__ Lanes<T, V> px_nbsum(const KA<T>& a, const T* v, int i, int c0, int lb) {
     using VT = Lanes<T, V>;
@@ -3077,17 +3085,17 @@ __device__ __forceinline__ Lanes<T, V> px_nbsum(const KA<T>& a, const T* v, int 
         int s0, cnt, st;
         row_slots<0>(a, i, s0, cnt, st);
         int k = 0;
-        for (; k + kGenGroup <= cnt; k += kGenGroup) {
-            T ww[kGenGroup];
-            VT vj[kGenGroup];
+        for (; k + kRowGroup <= cnt; k += kRowGroup) {
+            T ww[kRowGroup];
+            VT vj[kRowGroup];
 #pragma unroll
-            for (int g = 0; g < kGenGroup; ++g) {
+            for (int g = 0; g < kRowGroup; ++g) {
                 const int sl = s0 + (k + g) * st;
                 ww[g] = a.sw[sl];
                 vj[g] = ld_lanes<T, V>(v + (size_t)a.scol[sl] * d + c0);
             }
 #pragma unroll
-            for (int g = 0; g < kGenGroup; ++g) {
+            for (int g = 0; g < kRowGroup; ++g) {
                 const T w2 = mul_t(ww[g], ww[g]);
 #pragma unroll
                 for (int q = 0; q < V; ++q) acc.v[q] = fma_t(w2, vj[g].v[q], acc.v[q]);
@@ -3096,9 +3104,9 @@ __device__ __forceinline__ Lanes<T, V> px_nbsum(const KA<T>& a, const T* v, int 
         for (; k < cnt; ++k) {
             const int sl = s0 + k * st;
             const T w2 = mul_t(a.sw[sl], a.sw[sl]);
-            VT vj = ld_lanes<T, V>(v + (size_t)a.scol[sl] * d + c0);
+            VT vj1 = ld_lanes<T, V>(v + (size_t)a.scol[sl] * d + c0);
 #pragma unroll
-            for (int q = 0; q < V; ++q) acc.v[q] = fma_t(w2, vj.v[q], acc.v[q]);
+            for (int q = 0; q < V; ++q) acc.v[q] = fma_t(w2, vj1.v[q], acc.v[q]);
         }
     }
     return acc;
