@@ -3113,15 +3113,21 @@ __device__ __forceinline__ Lanes<T, V> px_nbsum(const KA<T>& a, const T* v, int 
 }
 
 // the pixels of logical workgroup lb, kBlock / (d / V) per step: f(i, e, c0)
-// for each of this thread's pixels (element e = i d + c0)
+// for each of this thread's pixels (element e = i d + c0).  The workgroups of
+// an XCD band form a team that deals the band's steps out cyclically (chunks
+// first + k stride of one step each), so the band is swept together and the
+// neighbour rows one workgroup gathers were just read by the others of its XCD
 template <int V, typename T, class F>
 __device__ __forceinline__ void px_walk(const KA<T>& a, int lb, F&& f) {
     const int d = a.d, L = d / V, ppb = kBlock / L;
     const int qp = (int)threadIdx.x / L;
     if (qp >= ppb) return;
     const int c0 = ((int)threadIdx.x - qp * L) * V;
-    const int r1 = a.row0[lb + 1];
-    for (int i = a.row0[lb] + qp; i < r1; i += ppb) f(i, (size_t)i * d + c0, c0);
+    const int first = a.bit[3 * lb], end = a.bit[3 * lb + 1], stride = a.bit[3 * lb + 2];
+    for (int base = first; base < end; base += stride) {
+        const int i = base + qp;
+        if (i < end) f(i, (size_t)i * d + c0, c0);
+    }
 }
 
 // residual r0 = rhs - A x (PH_E0: rhs = r/2 D^{1/2} (P - B), stored when
@@ -5679,7 +5685,9 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
             want_px = (int)std::min<int64_t>(want_px, steps);
             if (want_px >= kNumXcd) want_px -= want_px % kNumXcd;   // whole XCD groups where there are enough
             if (k == 1 && want_px <= c->px[0].nblk) break;          // no second size
-            s = make_partition(seg_rows, std::max(1, want_px), ppb, 1, c->px[k]);
+            int team_px = 64;   // the whole XCD band sweeps together (team_iteration caps at the band)
+            if (const char* ev = getenv("PFE_PX_TEAM")) team_px = std::max(1, atoi(ev));   // launch-shape experiments
+            s = make_partition(seg_rows, std::max(1, want_px), ppb, team_px, c->px[k]);
             if (s == PFE_OK && px_grid) s = set_px_geo(c, c->px[k]);
         }
     }
