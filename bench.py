@@ -67,11 +67,11 @@ def algorithmic_bytes(n, E, d, esz, cg_iters, solves, n_inner, n_outer, pupdate=
     return cg_iters * cg_iter + n_outer * per_outer_fixed
 
 
-# committed rocprofv3 traffic summaries of the persistent kernel, per workload
 # committed rocprofv3 FETCH_SIZE / WRITE_SIZE records: (workload, launch) ->
-# file; persistent records count one k_soc launch, strip records one SOC
-# iteration of the one-launch-per-phase path on image strips
-TRAFFIC_FILES = {("voronoi481x321_8nbr", "persistent"): "k_soc_voronoi481x321_traffic.json"}
+# file; persistent records count one k_soc launch, per-row records one SOC
+# iteration of the one-launch-per-phase path (all its kernels)
+TRAFFIC_FILES = {("voronoi481x321_8nbr", "persistent"): "k_soc_voronoi481x321_traffic.json",
+                 ("voronoi1024_r2", "per-row"): "per_row_voronoi1024_r2_traffic.json"}
 
 
 def measured_traffic(workload, launch):
