@@ -2929,59 +2929,89 @@ __global__ void __launch_bounds__(kBlock) k_eu_px(KA<T> a, int W, int H) {
             slot(sl, a.sw[sl], ld_lanes<T, V>(a.Y + (size_t)a.scol[sl] * d + c0), b1);
         }
     } else {
+        // FP32: slots are visited in pairs, own slot m (the edge to an earlier
+        // pixel, whose b this pixel stores) beside slot KC-1-m (the edge to a
+        // later pixel, whose b that pixel stores at its slot m).  A pixel and
+        // its later neighbour then read the shared b at the same point of their
+        // loops, which keeps the second read in L2.  The sum over the slots
+        // keeps the slot order: the later-pixel slots' weight and d - b are
+        // held and added after the own slots.  FP64 (twice the registers per
+        // value) visits the slots in order.
+        constexpr bool kPair = sizeof(T) == 4;
+        constexpr int GP = G / 2;                 // pairs whose loads are issued together
+        static_assert(!kPair || KH % GP == 0, "pair groups must tile the own slots");
+        auto slot_of = [&](int g, int h) {
+            return kPair ? ((h < GP) ? g * GP + h : KC - 1 - (g * GP + h - GP)) : g * G + h;
+        };
         int py = 0, px = 0;
         if constexpr (GEO) {
             py = i / W;
             px = i - py * W;
         }
+        T mw[KH];
+        VT mdb[KH];
     #pragma unroll
-        for (int k0 = 0; k0 < KC; k0 += G) {
+        for (int g = 0; g < KC / G; ++g) {
             int jj[G];
             T ww[G];
             VT yj[G], bo[G];
             size_t ss[G];
     #pragma unroll
-            for (int k = 0; k < G; ++k) {
-                const int kk = k0 + k;
+            for (int h = 0; h < G; ++h) {
+                const int kk = slot_of(g, h);
                 const size_t sl = (size_t)kk * a.n + i;
                 if constexpr (GEO) {
                     const int yy = py + S::dy(kk), xx = px + S::dx(kk);
-                    jj[k] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? i + S::dy(kk) * W + S::dx(kk) : i;
+                    jj[h] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? i + S::dy(kk) * W + S::dx(kk) : i;
                 } else {
-                    jj[k] = a.scol[sl];
+                    jj[h] = a.scol[sl];
                 }
-                ww[k] = a.sw[sl];
-                ss[k] = (kk < KH) ? sl : (size_t)(KC - 1 - kk) * a.n + jj[k];
+                ww[h] = a.sw[sl];
+                ss[h] = (kk < KH) ? sl : (size_t)(KC - 1 - kk) * a.n + jj[h];
                 if (a.b_zero) {
     #pragma unroll
-                    for (int u = 0; u < V; ++u) bo[k].v[u] = T(0);
+                    for (int u = 0; u < V; ++u) bo[h].v[u] = T(0);
                 } else {
-                    bo[k] = ld_lanes<T, V>(bread + ss[k] * d + c0);
+                    bo[h] = ld_lanes<T, V>(bread + ss[h] * d + c0);
                     if (kk >= KH) {
     #pragma unroll
-                        for (int u = 0; u < V; ++u) bo[k].v[u] = -bo[k].v[u];
+                        for (int u = 0; u < V; ++u) bo[h].v[u] = -bo[h].v[u];
                     }
                 }
             }
     #pragma unroll
-            for (int k = 0; k < G; ++k) yj[k] = ld_lanes<T, V>(a.Y + (size_t)jj[k] * d + c0);
+            for (int h = 0; h < G; ++h) yj[h] = ld_lanes<T, V>(a.Y + (size_t)jj[h] * d + c0);
     #pragma unroll
-            for (int k = 0; k < G; ++k) {
-                const int kk = k0 + k;
-                VT bn, dn;
+            for (int h = 0; h < G; ++h) {
+                const int kk = slot_of(g, h);
+                VT bn, dn, db;
     #pragma unroll
                 for (int u = 0; u < V; ++u) {
-                    const T tv = fma_t(ww[k], yi.v[u] - yj[k].v[u], bo[k].v[u]);
+                    const T tv = fma_t(ww[h], yi.v[u] - yj[h].v[u], bo[h].v[u]);
                     const T dv = shrink(tv, a.gamma);
                     const T b1 = tv - dv;
                     bn.v[u] = b1;
                     dn.v[u] = dv;
-                    acc.v[u] = fma_t(ww[k], dv - b1, acc.v[u]);
+                    db.v[u] = dv - b1;
+                }
+                if (!kPair || kk < KH) {
+    #pragma unroll
+                    for (int u = 0; u < V; ++u) acc.v[u] = fma_t(ww[h], db.v[u], acc.v[u]);
+                } else {
+                    mw[kk - KH] = ww[h];
+                    mdb[kk - KH] = db;
                 }
                 if (kk < KH) {
-                    st_lanes<T, V>(bwrite + ss[k] * d + c0, bn);
-                    if (a.keep_split) st_lanes<T, V>(a.ds + ss[k] * d + c0, dn);
+                    st_lanes<T, V>(bwrite + ss[h] * d + c0, bn);
+                    if (a.keep_split) st_lanes<T, V>(a.ds + ss[h] * d + c0, dn);
                 }
+            }
+        }
+        if constexpr (kPair) {
+    #pragma unroll
+            for (int m = 0; m < KH; ++m) {
+    #pragma unroll
+                for (int u = 0; u < V; ++u) acc.v[u] = fma_t(mw[m], mdb[m].v[u], acc.v[u]);
             }
         }
     }
