@@ -5097,11 +5097,12 @@ pfe_status launch_eu_px_k(pfe_ctx* c, const KA<T>& a, dim3 grid, bool geo, int W
     }
 }
 
-// columns per thread: 16-byte accesses where d allows (4 FP32 or 2 FP64 columns), else one
+// columns per thread as in the per-row passes: the widest access of up to 16
+// bytes that d allows
 template <typename T>
 pfe_status launch_eu_px(pfe_ctx* c, const KA<T>& a) {
     const int d = (int)c->d;
-    const int V = (sizeof(T) == 4) ? ((d % 4 == 0) ? 4 : 1) : ((d % 2 == 0) ? 2 : 1);
+    const int V = px_cols<T>(d);
     const int ppb = kBlock / (d / V);
     const dim3 grid((unsigned)((c->n + ppb - 1) / ppb));
     // one image: neighbours from the stencil offsets; batches read the slot columns
@@ -5111,9 +5112,8 @@ pfe_status launch_eu_px(pfe_ctx* c, const KA<T>& a) {
     const int W = geo ? g->seg_W[0] : 0, H = geo ? g->seg_H[0] : 0;
     if constexpr (sizeof(T) == 4) {
         if (V == 4) return launch_eu_px_k<T, 4>(c, a, grid, geo, W, H);
-    } else {
-        if (V == 2) return launch_eu_px_k<T, 2>(c, a, grid, geo, W, H);
     }
+    if (V == 2) return launch_eu_px_k<T, 2>(c, a, grid, geo, W, H);
     return launch_eu_px_k<T, 1>(c, a, grid, geo, W, H);
 }
 
