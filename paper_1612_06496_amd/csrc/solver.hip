@@ -2847,6 +2847,117 @@ __device__ __forceinline__ Lanes<T, V> ld_lanes(const T* p) { return *reinterpre
 template <typename T, int V>
 __device__ __forceinline__ void st_lanes(T* p, const Lanes<T, V>& x) { *reinterpret_cast<Lanes<T, V>*>(p) = x; }
 
+// The stencil slots of the edge update for pixel i at (py, px) of a W x H
+// image (GEO; otherwise the slot columns): b once per undirected edge (own
+// slots kk < KC/2 stored by this pixel, the others read negated from the later
+// neighbour), Eqs. 9-10 per slot, acc += w (d - b) in slot order.  With AX the
+// same loop also sums w^2 y_j over the slots for A y, and both sums run in the
+// visiting order (nothing is held: the registers go to the caller's residual).
+template <typename T, int KC, int V, bool GEO, bool AX>
+__device__ __forceinline__ void eu_stencil_slots(const KA<T>& a, int i, int c0, int py, int px, int W, int H,
+                                                 const T* bread, T* bwrite, const Lanes<T, V>& yi,
+                                                 Lanes<T, V>& acc, Lanes<T, V>& accA) {
+    using VT = Lanes<T, V>;
+    using S = Sten<KC>;
+    constexpr int KH = KC / 2;
+    constexpr int G = (KC < 8) ? KC : 8;   // slots whose loads are issued together
+    const int d = a.d;
+    // FP32: slots are visited in pairs, own slot m (the edge to an earlier
+    // pixel, whose b this pixel stores) beside slot KC-1-m (the edge to a
+    // later pixel, whose b that pixel stores at its slot m).  A pixel and
+    // its later neighbour then read the shared b at the same point of their
+    // loops, which keeps the second read in L2.  The sum over the slots
+    // keeps the slot order: the later-pixel slots' weight and d - b are
+    // held and added after the own slots.  FP64 (twice the registers per
+    // value) visits the slots in order.
+    constexpr bool kPair = sizeof(T) == 4;
+    constexpr bool kHold = kPair && !AX;      // later-pixel slots held for the slot-order sum
+    constexpr int GP = G / 2;                 // pairs whose loads are issued together
+    static_assert(!kPair || KH % GP == 0, "pair groups must tile the own slots");
+    auto slot_of = [&](int g, int h) {
+        return kPair ? ((h < GP) ? g * GP + h : KC - 1 - (g * GP + h - GP)) : g * G + h;
+    };
+    T mw[KH];
+    VT mdb[KH];
+    auto group = [&](int g) {
+        int jj[G];
+        T ww[G];
+        VT yj[G], bo[G];
+        size_t ss[G];
+#pragma unroll
+        for (int h = 0; h < G; ++h) {
+            const int kk = slot_of(g, h);
+            const size_t sl = (size_t)kk * a.n + i;
+            if constexpr (GEO) {
+                const int yy = py + S::dy(kk), xx = px + S::dx(kk);
+                jj[h] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? i + S::dy(kk) * W + S::dx(kk) : i;
+            } else {
+                jj[h] = a.scol[sl];
+            }
+            ww[h] = a.sw[sl];
+            ss[h] = (kk < KH) ? sl : (size_t)(KC - 1 - kk) * a.n + jj[h];
+            if (a.b_zero) {
+#pragma unroll
+                for (int u = 0; u < V; ++u) bo[h].v[u] = T(0);
+            } else {
+                bo[h] = ld_lanes<T, V>(bread + ss[h] * d + c0);
+                if (kk >= KH) {
+#pragma unroll
+                    for (int u = 0; u < V; ++u) bo[h].v[u] = -bo[h].v[u];
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < G; ++h) yj[h] = ld_lanes<T, V>(a.Y + (size_t)jj[h] * d + c0);
+#pragma unroll
+        for (int h = 0; h < G; ++h) {
+            const int kk = slot_of(g, h);
+            VT bn, dn, db;
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                const T tv = fma_t(ww[h], yi.v[u] - yj[h].v[u], bo[h].v[u]);
+                const T dv = shrink(tv, a.gamma);
+                const T b1 = tv - dv;
+                bn.v[u] = b1;
+                dn.v[u] = dv;
+                db.v[u] = dv - b1;
+            }
+            if constexpr (AX) {
+                const T w2 = mul_t(ww[h], ww[h]);
+#pragma unroll
+                for (int u = 0; u < V; ++u) accA.v[u] = fma_t(w2, yj[h].v[u], accA.v[u]);
+            }
+            if (!kHold || kk < KH) {
+#pragma unroll
+                for (int u = 0; u < V; ++u) acc.v[u] = fma_t(ww[h], db.v[u], acc.v[u]);
+            } else {
+                mw[kk - KH] = ww[h];
+                mdb[kk - KH] = db;
+            }
+            if (kk < KH) {
+                st_lanes<T, V>(bwrite + ss[h] * d + c0, bn);
+                if (a.keep_split) st_lanes<T, V>(a.ds + ss[h] * d + c0, dn);
+            }
+        }
+    };
+    if constexpr (AX) {
+        // one group at a time (the caller's residual needs the registers that
+        // unrolling the groups would take)
+#pragma unroll 1
+        for (int g = 0; g < KC / G; ++g) group(g);
+    } else {
+#pragma unroll
+        for (int g = 0; g < KC / G; ++g) group(g);
+    }
+    if constexpr (kHold) {
+#pragma unroll
+        for (int m = 0; m < KH; ++m) {
+#pragma unroll
+            for (int u = 0; u < V; ++u) acc.v[u] = fma_t(mw[m], mdb[m].v[u], acc.v[u]);
+        }
+    }
+}
+
 // Edge update, one thread per row (the
 // PH_EU arithmetic without r0, element by element and in the same slot order):
 // one thread per pixel and V consecutive columns, no LDS, one workgroup per
@@ -2860,9 +2971,6 @@ __device__ __forceinline__ void st_lanes(T* p, const Lanes<T, V>& x) { *reinterp
 template <typename T, int KC, int V, bool GEO>
 __global__ void __launch_bounds__(kBlock) k_eu_px(KA<T> a, int W, int H) {
     using VT = Lanes<T, V>;
-    using S = Sten<KC>;
-    constexpr int KH = KC / 2;
-    constexpr int G = (KC < 8) ? (KC > 0 ? KC : 1) : 8;   // slots whose loads are issued together
     const int d = a.d, L = d / V, ppb = kBlock / L;
     const int q = threadIdx.x / L;
     const int64_t i64 = (int64_t)blockIdx.x * ppb + q;
@@ -2929,91 +3037,13 @@ __global__ void __launch_bounds__(kBlock) k_eu_px(KA<T> a, int W, int H) {
             slot(sl, a.sw[sl], ld_lanes<T, V>(a.Y + (size_t)a.scol[sl] * d + c0), b1);
         }
     } else {
-        // FP32: slots are visited in pairs, own slot m (the edge to an earlier
-        // pixel, whose b this pixel stores) beside slot KC-1-m (the edge to a
-        // later pixel, whose b that pixel stores at its slot m).  A pixel and
-        // its later neighbour then read the shared b at the same point of their
-        // loops, which keeps the second read in L2.  The sum over the slots
-        // keeps the slot order: the later-pixel slots' weight and d - b are
-        // held and added after the own slots.  FP64 (twice the registers per
-        // value) visits the slots in order.
-        constexpr bool kPair = sizeof(T) == 4;
-        constexpr int GP = G / 2;                 // pairs whose loads are issued together
-        static_assert(!kPair || KH % GP == 0, "pair groups must tile the own slots");
-        auto slot_of = [&](int g, int h) {
-            return kPair ? ((h < GP) ? g * GP + h : KC - 1 - (g * GP + h - GP)) : g * G + h;
-        };
         int py = 0, px = 0;
         if constexpr (GEO) {
             py = i / W;
             px = i - py * W;
         }
-        T mw[KH];
-        VT mdb[KH];
-    #pragma unroll
-        for (int g = 0; g < KC / G; ++g) {
-            int jj[G];
-            T ww[G];
-            VT yj[G], bo[G];
-            size_t ss[G];
-    #pragma unroll
-            for (int h = 0; h < G; ++h) {
-                const int kk = slot_of(g, h);
-                const size_t sl = (size_t)kk * a.n + i;
-                if constexpr (GEO) {
-                    const int yy = py + S::dy(kk), xx = px + S::dx(kk);
-                    jj[h] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? i + S::dy(kk) * W + S::dx(kk) : i;
-                } else {
-                    jj[h] = a.scol[sl];
-                }
-                ww[h] = a.sw[sl];
-                ss[h] = (kk < KH) ? sl : (size_t)(KC - 1 - kk) * a.n + jj[h];
-                if (a.b_zero) {
-    #pragma unroll
-                    for (int u = 0; u < V; ++u) bo[h].v[u] = T(0);
-                } else {
-                    bo[h] = ld_lanes<T, V>(bread + ss[h] * d + c0);
-                    if (kk >= KH) {
-    #pragma unroll
-                        for (int u = 0; u < V; ++u) bo[h].v[u] = -bo[h].v[u];
-                    }
-                }
-            }
-    #pragma unroll
-            for (int h = 0; h < G; ++h) yj[h] = ld_lanes<T, V>(a.Y + (size_t)jj[h] * d + c0);
-    #pragma unroll
-            for (int h = 0; h < G; ++h) {
-                const int kk = slot_of(g, h);
-                VT bn, dn, db;
-    #pragma unroll
-                for (int u = 0; u < V; ++u) {
-                    const T tv = fma_t(ww[h], yi.v[u] - yj[h].v[u], bo[h].v[u]);
-                    const T dv = shrink(tv, a.gamma);
-                    const T b1 = tv - dv;
-                    bn.v[u] = b1;
-                    dn.v[u] = dv;
-                    db.v[u] = dv - b1;
-                }
-                if (!kPair || kk < KH) {
-    #pragma unroll
-                    for (int u = 0; u < V; ++u) acc.v[u] = fma_t(ww[h], db.v[u], acc.v[u]);
-                } else {
-                    mw[kk - KH] = ww[h];
-                    mdb[kk - KH] = db;
-                }
-                if (kk < KH) {
-                    st_lanes<T, V>(bwrite + ss[h] * d + c0, bn);
-                    if (a.keep_split) st_lanes<T, V>(a.ds + ss[h] * d + c0, dn);
-                }
-            }
-        }
-        if constexpr (kPair) {
-    #pragma unroll
-            for (int m = 0; m < KH; ++m) {
-    #pragma unroll
-                for (int u = 0; u < V; ++u) acc.v[u] = fma_t(mw[m], mdb[m].v[u], acc.v[u]);
-            }
-        }
+        VT unused;
+        eu_stencil_slots<T, KC, V, GEO, false>(a, i, c0, py, px, W, H, bread, bwrite, yi, acc, unused);
     }
     const T sq = a.sqrtD[i];
     VT pv = ld_lanes<T, V>(a.P + e);
@@ -3200,6 +3230,55 @@ __global__ void __launch_bounds__(kBlock) k_px_res(KA<T> a, int mode) {
     });
     const int qo[2] = {0, 1};
     block_partials_px<2, V>(acc, qo, sh, a.d, a.part, a.nblk, lb);
+    if (last_of_launch(a, 2, sh)) fin_res(a, sh, grouped_fin(a));
+}
+
+// The edge update of inner step l fused with the residual of solve l + 1 on
+// pixel-stencil images (per-row partition): Eqs. 9-10 per slot and the next
+// right-hand side as in k_eu_px, then r0 = rhs - A x for the iterate that solve
+// starts from, x = Y, out of the Y values the edge update has gathered (the sum
+// of w^2 y_j in the slots' visiting order: the slot order in FP64, pairs of
+// slots in FP32, as is then the sum forming the right-hand side), and
+// u0 = r0 / diag(A); partials of rhs.rhs and r0.r0 and the
+// finaliser as in k_px_res.  The right-hand side is not stored: the solve
+// reads only r0.
+template <typename T, int KC, int V>
+__global__ void __launch_bounds__(kBlock) k_eur_px(KA<T> a) {
+    using VT = Lanes<T, V>;
+    __shared__ double sh[kPxSmemDoubles];
+    const int lb = logical_block(a.nblk);
+    const T* bread = a.bsb[a.bpar & 1];
+    T* bwrite = a.bsb[(a.bpar & 1) ^ 1];
+    const int* gg = a.geo + 8 * lb;   // the workgroup's image: first row, width, height
+    const int row0 = gg[0], W = gg[1], H = gg[2];
+    double acc2[2][V] = {};
+    px_walk<V>(a, lb, [&](int i, size_t e, int c0) {
+        const int il = i - row0, py = il / W, px = il - py * W;
+        const VT yi = ld_lanes<T, V>(a.Y + e);
+        VT acc, accA;
+#pragma unroll
+        for (int u = 0; u < V; ++u) acc.v[u] = accA.v[u] = T(0);
+        eu_stencil_slots<T, KC, V, true, true>(a, i, c0, py, px, W, H, bread, bwrite, yi, acc, accA);
+        const T sq = a.sqrtD[i], dA = a.diagA[i], inv = a.invdiag[i];
+        const VT pv = ld_lanes<T, V>(a.P + e);
+        const VT bv = ld_lanes<T, V>(a.B + e);
+        VT rv, uv;
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            const T split = mul_t(a.half_r, mul_t(sq, pv.v[u] - bv.v[u]));
+            const T rhs = fma_t(a.c_off, acc.v[u], split);
+            const T ax = fma_t(dA, yi.v[u], -mul_t(a.c_off, accA.v[u]));
+            const T r = rhs - ax;
+            rv.v[u] = r;
+            uv.v[u] = mul_t(inv, r);
+            acc2[0][u] += (double)rhs * (double)rhs;
+            acc2[1][u] += (double)r * (double)r;
+        }
+        st_lanes<T, V>(a.rb[0] + e, rv);
+        st_lanes<T, V>(a.zl + e, uv);
+    });
+    const int qo[2] = {0, 1};
+    block_partials_px<2, V>(acc2, qo, sh, a.d, a.part, a.nblk, lb);
     if (last_of_launch(a, 2, sh)) fin_res(a, sh, grouped_fin(a));
 }
 
@@ -4289,6 +4368,7 @@ struct pfe_ctx {
     int one_pass = 0;        // factor preconditioners on strips: one pass per CG iteration (0: two)
     int eu_px = 1;           // pixel stencils with b once per edge: the edge update by the per-pixel
                              // kernel (0: by the strip or row-chunk phase kernel)
+    int eur_px = 1;          // per-row Jacobi PCG: edge updates that also form the next solve's residual
     int want_strips = 2;     // one launch per phase: residual, w0 and CG kernels on image strips sized
                              // for this many waves of co-resident strip workgroups (0: row chunks)
     int strip_slots = 0;     // co-resident strip workgroups on the device (0: no strip kernel)
@@ -4322,6 +4402,7 @@ struct pfe_ctx {
     int* colint = nullptr;
     int cache_np = 0;        // persistent kernel: LDS row cache chunks (0: no cache)
     int launched_coop = 0;   // the last advance ran the persistent kernel
+    int fused_eur = 0;       // the last advance fused edge updates with the next residual
     // persistent launch shape
     std::vector<int64_t> seg_rows;
     int per_cu = 0;          // co-resident workgroups per CU
@@ -4979,9 +5060,10 @@ pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
 // restored and the same solve is redone with Jacobi from the same start;
 // fallbacks counts such solves, and the status reported is the redo's.
 template <typename T>
-pfe_status pcg_solve_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as, int res_ph) {
+pfe_status pcg_solve_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as, int res_ph, bool r0_ready = false) {
     if (c->prm.precond == PFE_JACOBI) {
-        PFE_TRY(launch_phase(c, as, res_ph, 0, 1));
+        // r0_ready: the previous edge update formed r0, u0 and the CG state (k_eur_px)
+        if (!r0_ready) PFE_TRY(launch_phase(c, as, res_ph, 0, 1));
         return pcg_loop_mk(c, a, as);
     }
     const size_t bytes = (size_t)c->n * c->d * sizeof(T);
@@ -5117,21 +5199,64 @@ pfe_status launch_eu_px(pfe_ctx* c, const KA<T>& a) {
     return launch_eu_px_k<T, 1>(c, a, grid, geo, W, H);
 }
 
-// inner iteration l of a Split-Bregman run (l = 0: b = d = 0), one launch per phase
+// the edge update fused with the next solve's residual (k_eur_px): Jacobi PCG by
+// per-row launches on pixel-stencil images, warm starts (the iterate is Y)
 template <typename T>
-pfe_status inner_at(pfe_ctx* c, int l) {
+bool eur_px_ok(const pfe_ctx* c, const KA<T>& as) {
+    const int K = c->g->ell_K;
+    return c->eur_px && c->prm.precond == PFE_JACOBI && as.pxl && as.geo != nullptr && eu_px_ok(c) && c->g->stencil &&
+           (K == 4 || K == 8 || K == 24) && !c->prm.cold_start && as.x == as.Y;
+}
+
+template <typename T, int V>
+pfe_status launch_eur_px_v(pfe_ctx* c, const KA<T>& f) {
+    const dim3 grid(f.nblk);
+    switch (c->g->ell_K) {
+        case 4: hipLaunchKernelGGL((k_eur_px<T, 4, V>), grid, dim3(kBlock), 0, c->stream, f); break;
+        case 8: hipLaunchKernelGGL((k_eur_px<T, 8, V>), grid, dim3(kBlock), 0, c->stream, f); break;
+        case 24: hipLaunchKernelGGL((k_eur_px<T, 24, V>), grid, dim3(kBlock), 0, c->stream, f); break;
+        default: set_error("the fused edge update needs a stencil of 4, 8 or 24 slots"); return PFE_E_STATE;
+    }
+    PFE_CHECK_HIP(hipGetLastError());
+    c->fused_eur = 1;
+    return PFE_OK;
+}
+
+template <typename T>
+pfe_status launch_eur_px(pfe_ctx* c, const KA<T>& f) {
+    const int V = px_cols<T>((int)c->d);
+    if constexpr (sizeof(T) == 4) {
+        if (V == 4) return launch_eur_px_v<T, 4>(c, f);
+    }
+    if (V == 2) return launch_eur_px_v<T, 2>(c, f);
+    return launch_eur_px_v<T, 1>(c, f);
+}
+
+// inner iteration l of a Split-Bregman run (l = 0: b = d = 0), one launch per
+// phase.  next: inner iteration l + 1 follows in the same call, so its residual
+// may be formed by this edge update (*fused is then set); r0_ready: the previous
+// inner iteration's edge update formed this solve's residual.
+template <typename T>
+pfe_status inner_at(pfe_ctx* c, int l, bool next = false, bool r0_ready = false, bool* fused = nullptr) {
     KA<T> a = make_args<T>(c, c->pm);
     const KA<T> as = pcg_args<T>(c, a);
     // cold start: the solve begins from Y = 0 (the right-hand side does not
     // depend on Y; the previous edge update has already consumed it)
     if (c->prm.cold_start) PFE_CHECK_HIP(hipMemsetAsync(c->Y, 0, (size_t)c->n * c->d * sizeof(T), c->stream));
-    PFE_TRY(pcg_solve_mk(c, a, as, (l == 0) ? PH_E0 : PH_R0));
+    PFE_TRY(pcg_solve_mk(c, a, as, (l == 0) ? PH_E0 : PH_R0, r0_ready && l > 0));
     // edge update of this inner step and rhs of the next one (on strips when
     // the slot data are loaded one image row ahead, widths up to 8)
     KA<T> b = (as.geo && !as.pxl && c->g->ell_K <= 8) ? as : a;
     b.store_rhs = 1;
     b.b_zero = (l == 0);
     b.bpar = l & 1;
+    if (next && fused && eur_px_ok(c, as)) {
+        KA<T> f = as;
+        f.b_zero = b.b_zero;
+        f.bpar = b.bpar;
+        *fused = true;
+        return launch_eur_px(c, f);
+    }
     if (eu_px_ok(c)) return launch_eu_px(c, b);
     PFE_TRY(launch_phase(c, b, PH_EU, 0, 0));
     return PFE_OK;
@@ -5158,7 +5283,15 @@ pfe_status ortho_mk(pfe_ctx* c, int mode) {
 
 template <typename T>
 pfe_status outer_mk(pfe_ctx* c) {
-    while (c->inner < c->prm.n_inner) PFE_TRY(inner_mk<T>(c));
+    // the remaining inner iterations run back to back: each edge update but the
+    // last may form the next solve's residual
+    bool r0 = false;
+    while (c->inner < c->prm.n_inner) {
+        bool fused = false;
+        PFE_TRY(inner_at<T>(c, c->inner, c->inner + 1 < c->prm.n_inner, r0, &fused));
+        r0 = fused;
+        c->inner += 1;
+    }
     PFE_TRY(ortho_mk<T>(c, 0));
     c->inner = 0;
     return PFE_OK;
@@ -5211,7 +5344,12 @@ template <typename T>
 pfe_status split_bregman_run(pfe_ctx* c, int n_iter) {
     if (c->prm.persistent && c->pc.nblk > 0 && c->prm.precond == PFE_JACOBI && !c->prm.cold_start)
         return launch_soc<T>(c, n_iter, 1, 0);
-    for (int l = 0; l < n_iter; ++l) PFE_TRY(inner_at<T>(c, l));
+    bool r0 = false;
+    for (int l = 0; l < n_iter; ++l) {
+        bool fused = false;
+        PFE_TRY(inner_at<T>(c, l, l + 1 < n_iter, r0, &fused));
+        r0 = fused;
+    }
     return PFE_OK;
 }
 
@@ -5231,7 +5369,8 @@ pfe_status read_info(pfe_ctx* c, pfe_step_info* info) {
         info->workgroups = c->launched_coop ? c->pc.nblk : 0;
         const bool px = !c->launched_coop && use_px(c);
         info->flags = ((c->launched_coop && c->cache_np > 0) ? 1 : 0) |
-                      ((!c->launched_coop && !px && use_strips(c)) ? 2 : 0) | (px ? 4 : 0);
+                      ((!c->launched_coop && !px && use_strips(c)) ? 2 : 0) | (px ? 4 : 0) |
+                      (c->fused_eur ? 8 : 0);
     }
     if (h.status != 0) {
         set_error("%s", pfe_status_string((pfe_status)h.status));
@@ -5671,6 +5810,7 @@ pfe_status pfe_init(pfe_graph* g, const pfe_params* p, const void* Y0, hipStream
     if (const char* ev = getenv("PFE_STRIPS")) c->want_strips = std::max(0, atoi(ev));   // launch-shape experiments
     if (const char* ev = getenv("PFE_ONE_PASS")) c->one_pass = atoi(ev) != 0;
     if (const char* ev = getenv("PFE_EU_PX")) c->eu_px = atoi(ev) != 0;     // launch-shape experiments
+    if (const char* ev = getenv("PFE_EUR_PX")) c->eur_px = atoi(ev) != 0;   // launch-shape experiments
     if (s == PFE_OK) {
         // strip partition: built first for the most waves any later shape asks
         // for (it has the most workgroups), then for the wanted count
@@ -5838,6 +5978,7 @@ pfe_status pfe_set_penalties(pfe_ctx* c, double lambda, double r) {
 pfe_status pfe_step(pfe_ctx* c, int granularity, pfe_step_info* info) {
     if (!c) { set_error("null context"); return PFE_E_ARG; }
     c->launched_coop = 0;
+    c->fused_eur = 0;
     if (info) PFE_TRY(reset_stats(c));
     pfe_status s;
     const bool f64 = c->prm.dtype == PFE_FP64;
@@ -5861,6 +6002,7 @@ pfe_status pfe_step(pfe_ctx* c, int granularity, pfe_step_info* info) {
 pfe_status pfe_solve(pfe_ctx* c, int n_outer, pfe_step_info* info) {
     if (!c || n_outer < 0) { set_error("pfe_solve: bad argument"); return PFE_E_ARG; }
     c->launched_coop = 0;
+    c->fused_eur = 0;
     if (info) PFE_TRY(reset_stats(c));
     const bool f64 = c->prm.dtype == PFE_FP64;
     if (c->prm.persistent && c->pc.nblk > 0 && n_outer > 0 && c->prm.precond == PFE_JACOBI && !c->prm.cold_start) {
@@ -5876,6 +6018,7 @@ pfe_status pfe_split_bregman(pfe_ctx* c, int n_iter, pfe_step_info* info) {
     if (!c || n_iter < 0) { set_error("pfe_split_bregman: bad argument"); return PFE_E_ARG; }
     if (c->inner != 0) { set_error("pfe_split_bregman: call between SOC iterations (inner index 0)"); return PFE_E_STATE; }
     c->launched_coop = 0;
+    c->fused_eur = 0;
     if (info) PFE_TRY(reset_stats(c));
     if (n_iter > 0) PFE_TRY(c->prm.dtype == PFE_FP64 ? split_bregman_run<double>(c, n_iter) : split_bregman_run<float>(c, n_iter));
     if (info) return read_info(c, info);

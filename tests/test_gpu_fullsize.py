@@ -87,6 +87,33 @@ def test_window1024_soc_iteration_on_strips_vs_oracle(window_case, waves):
 
 
 @pytest.mark.timeout(900)
+def test_window1024_soc_iteration_per_row_vs_oracle(window_case):
+    """The launch shape the benchmark times on this graph: Jacobi PCG by per-row
+    kernels (one workgroup per CU), the SOC iteration in one call, so that the
+    first inner step's edge update also forms the second solve's residual.  Y
+    and P against the oracle by Frobenius norm and element-wise, B relative to
+    its norm."""
+    from paper_1612_06496_amd import Solver
+    wl, g, Y0, c, (Y1, P1, B1, _) = window_case
+    banner("1024x1024 window graph, d = 16, per-row launches: one SOC iteration vs oracle")
+    G = gpu_graph(wl)
+    S = Solver(G, Y0.astype(np.float32), lam=c, r=c, n_inner=N_INNER, tol=1e-6, maxit=1000, init_ortho=False,
+               persistent=False, graphs=True)
+    S.set_launch_shape(persistent=False, pixel=1)
+    info = S.solve(1, info=True)
+    assert info["flags"] & 4 and info["flags"] & 8, info
+    got = {k: to_np(S.get(k)) for k in ("Y", "P", "B")}
+    errs = {k: (rel(got[k], ref), maxrel(got[k], ref)) for k, ref in (("Y", Y1), ("P", P1), ("B", B1))}
+    print("errors (Frobenius, element-wise):", {k: f"{a:.2e}, {m:.2e}" for k, (a, m) in errs.items()},
+          f"CG iterations {info['cg_iters_total']}")
+    for name in ("Y", "P"):
+        assert errs[name][0] <= 2e-5 and errs[name][1] <= 1e-4, name
+    assert errs["B"][0] <= 1e-3
+    S.close()
+    G.close()
+
+
+@pytest.mark.timeout(900)
 def test_window1024_learned_factor_vs_oracle(window_case):
     from paper_1612_06496_amd import Mpnn, Solver
     wl, g, Y0, c, _ = window_case

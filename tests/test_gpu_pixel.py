@@ -65,6 +65,7 @@ def test_pixel_launch_matches_strips_and_row_chunks(case, fp64, monkeypatch):
     banner(f"pixel launch vs strips / row chunks {case[0]} fp64={fp64}")
     ip, px = run(wl, monkeypatch, True, fp64)
     assert ip["flags"] & 4, "the pixel kernels did not run"
+    assert ip["flags"] & 8, "the edge updates did not form the next residual"
     bound = 1e-10 if fp64 else 1e-5
     for strips in (1, 0):
         io, other = run(wl, monkeypatch, False, fp64, strips=strips)
@@ -92,6 +93,56 @@ def test_pixel_launch_outer_step_matches_oracle(monkeypatch):
     e = rel(got["P"], ref.P)
     print(f"P rel err vs oracle {e:.2e}")
     assert e <= 1e-8
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+@pytest.mark.parametrize("name", ["voronoi48x40_r2", "voronoi96x80_8nbr", "voronoi64_4nbr", "ragged37x41_8"])
+def test_fused_edge_update_residual_matches_separate_kernels(name, fp64, monkeypatch):
+    """An SOC iteration run in one call (each edge update but the last also
+    forms the next solve's residual r0 = rhs - A Y, u0 = r0 / diag(A) and the
+    CG start: k_eur_px) against the same iteration one inner step per call (edge
+    update, then the residual kernel of the next solve): bitwise equal in FP64,
+    where the fused kernel sums the slots in the residual kernel's order; in
+    FP32 (slots visited in pairs) Y, P within 1e-5 (B relative to P) and CG
+    iterations within 2."""
+    from paper_1612_06496_amd import Solver
+    wl = case_workload(next(c for c in CASES if c[0] == name))
+    banner(f"fused edge update + residual vs separate kernels: {name} fp64={fp64}")
+    monkeypatch.setenv("PFE_PIXEL", "1")
+    monkeypatch.setenv("PFE_STRIPS", "1")
+    G = gpu_graph(wl)
+    res = []
+    for fused in (True, False):
+        S = Solver(G, wl.y0, lam=30.0, r=3.0, n_inner=4, tol=1e-10 if fp64 else 1e-6, maxit=3000, fp64=fp64,
+                   persistent=False)
+        S.solve(1)                     # a first SOC iteration, so that P, B and b are not trivial
+        if fused:
+            info = S.solve(1, info=True)
+        else:
+            iters = 0
+            for _ in range(4):
+                step = S.step("inner", info=True)
+                assert not step["flags"] & 8
+                iters += step["cg_iters_total"]
+            info = S.step("outer", info=True)
+            info["cg_iters_total"] += iters
+            assert not info["flags"] & 8
+        res.append((info, {k: to_np(S.get(k)) for k in ("Y", "P", "B")}))
+        S.close()
+    G.close()
+    (i1, o1), (i2, o2) = res
+    assert i1["flags"] & 8 and i1["flags"] & 4
+    print("CG iterations fused / separate:", i1["cg_iters_total"], i2["cg_iters_total"])
+    if fp64:
+        assert i1["cg_iters_total"] == i2["cg_iters_total"]
+        for k in o1:
+            assert np.array_equal(o1[k], o2[k]), k
+    else:
+        assert abs(i1["cg_iters_total"] - i2["cg_iters_total"]) <= 2
+        for k in ("Y", "P"):
+            assert rel(o1[k], o2[k]) <= 1e-5, k
+        # B = Z - P is a small difference of O(1) quantities: relative to P
+        assert np.linalg.norm(o1["B"] - o2["B"]) / np.linalg.norm(o2["P"]) <= 1e-5
 
 
 def test_pixel_launch_graph_replay_bitwise_and_deterministic(monkeypatch):
