@@ -166,8 +166,9 @@ typedef struct {
     int32_t flags;           /* bit 0: persistent launch with the rows' slot data held in LDS;
                                 bit 1: one launch per phase on image strips;
                                 bit 2: Jacobi PCG by pixel launches (pfe_tune_result.pixel);
-                                bit 3: in those, edge updates that also formed the next
-                                solve's residual (inner iterations run in one call) */
+                                bit 3: edge updates that also formed the next solve's
+                                residual (Jacobi PCG by pixel launches or on strips,
+                                inner iterations run in one call) */
 } pfe_step_info;
 
 /* Monitors of the current state (Eq. 1, Eq. 2). */

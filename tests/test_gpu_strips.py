@@ -230,6 +230,8 @@ def test_one_pass_factor_pcg_matches_two_pass(stencil, d, fp64):
 def run_eu(wl_or_graph, y0, monkeypatch, eu_px, fp64, keep_split, inner_steps):
     from paper_1612_06496_amd import Solver
     monkeypatch.setenv("PFE_EU_PX", "1" if eu_px else "0")
+    # the edge update alone (not fused with the next residual, which has its own test)
+    monkeypatch.setenv("PFE_EUR_PX", "0")
     monkeypatch.setenv("PFE_STRIPS", "1")
     S = Solver(wl_or_graph, y0, lam=30.0, r=3.0, n_inner=3, tol=1e-10 if fp64 else 1e-6, maxit=3000, fp64=fp64,
                persistent=False, keep_split=keep_split)
