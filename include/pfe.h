@@ -167,8 +167,8 @@ typedef struct {
                                 bit 1: one launch per phase on image strips;
                                 bit 2: Jacobi PCG by pixel launches (pfe_tune_result.pixel);
                                 bit 3: edge updates that also formed the next solve's
-                                residual (Jacobi PCG by pixel launches or on strips,
-                                inner iterations run in one call) */
+                                residual (PCG by pixel launches or on strips of a pixel
+                                grid, inner iterations run in one call) */
 } pfe_step_info;
 
 /* Monitors of the current state (Eq. 1, Eq. 2). */

@@ -3240,8 +3240,9 @@ __global__ void __launch_bounds__(kBlock) k_px_res(KA<T> a, int mode) {
 // of w^2 y_j in the slots' visiting order: the slot order in FP64, pairs of
 // slots in FP32, as is then the sum forming the right-hand side), and
 // u0 = r0 / diag(A); partials of rhs.rhs and r0.r0 and the
-// finaliser as in k_px_res.  The right-hand side is not stored: the solve
-// reads only r0.
+// finaliser as in k_px_res.  The right-hand side is stored only with
+// store_rhs (factor-preconditioned solves, whose Jacobi fallback forms r0 from
+// it again); a Jacobi solve reads only r0.
 template <typename T, int KC, int V>
 __global__ void __launch_bounds__(kBlock) k_eur_px(KA<T> a) {
     using VT = Lanes<T, V>;
@@ -3262,18 +3263,20 @@ __global__ void __launch_bounds__(kBlock) k_eur_px(KA<T> a) {
         const T sq = a.sqrtD[i], dA = a.diagA[i], inv = a.invdiag[i];
         const VT pv = ld_lanes<T, V>(a.P + e);
         const VT bv = ld_lanes<T, V>(a.B + e);
-        VT rv, uv;
+        VT hv, rv, uv;
 #pragma unroll
         for (int u = 0; u < V; ++u) {
             const T split = mul_t(a.half_r, mul_t(sq, pv.v[u] - bv.v[u]));
             const T rhs = fma_t(a.c_off, acc.v[u], split);
             const T ax = fma_t(dA, yi.v[u], -mul_t(a.c_off, accA.v[u]));
             const T r = rhs - ax;
+            hv.v[u] = rhs;
             rv.v[u] = r;
             uv.v[u] = mul_t(inv, r);
             acc2[0][u] += (double)rhs * (double)rhs;
             acc2[1][u] += (double)r * (double)r;
         }
+        if (a.store_rhs) st_lanes<T, V>(a.rhs + e, hv);
         st_lanes<T, V>(a.rb[0] + e, rv);
         st_lanes<T, V>(a.zl + e, uv);
     });
@@ -5061,8 +5064,8 @@ pfe_status pcg_loop_learned_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as) {
 // fallbacks counts such solves, and the status reported is the redo's.
 template <typename T>
 pfe_status pcg_solve_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as, int res_ph, bool r0_ready = false) {
+    // r0_ready: the previous edge update formed r0, u0 and the CG state (k_eur_px)
     if (c->prm.precond == PFE_JACOBI) {
-        // r0_ready: the previous edge update formed r0, u0 and the CG state (k_eur_px)
         if (!r0_ready) PFE_TRY(launch_phase(c, as, res_ph, 0, 1));
         return pcg_loop_mk(c, a, as);
     }
@@ -5070,7 +5073,7 @@ pfe_status pcg_solve_mk(pfe_ctx* c, const KA<T>& a, const KA<T>& as, int res_ph,
     if (!c->xbak) PFE_CHECK_HIP(dev_alloc(&c->xbak, (size_t)c->n * c->d * 8));
     PFE_CHECK_HIP(hipMemcpyAsync(c->xbak, a.x, bytes, hipMemcpyDeviceToDevice, c->stream));
     hipLaunchKernelGGL(k_status_save, dim3(1), dim3(64), 0, c->stream, c->S);
-    PFE_TRY(launch_phase(c, as, res_ph, 0, 1));
+    if (!r0_ready) PFE_TRY(launch_phase(c, as, res_ph, 0, 1));
     PFE_TRY(pcg_loop_learned_mk(c, a, as));
     int st = 0;
     PFE_CHECK_HIP(hipMemcpyAsync(&st, &c->S->status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -5199,8 +5202,8 @@ pfe_status launch_eu_px(pfe_ctx* c, const KA<T>& a) {
     return launch_eu_px_k<T, 1>(c, a, grid, geo, W, H);
 }
 
-// the edge update fused with the next solve's residual (k_eur_px): Jacobi PCG
-// by per-row launches or on strips of pixel-stencil images, warm starts (the
+// the edge update fused with the next solve's residual (k_eur_px): PCG by
+// per-row launches or on strips of pixel-stencil images, warm starts (the
 // iterate is Y).  f: the kernel's arguments on a per-row partition (the
 // solve's own with per-row launches; with strips, whose w0 kernel reads r0
 // alone, the partition of two workgroups per CU).  False when the shape does
@@ -5208,7 +5211,7 @@ pfe_status launch_eu_px(pfe_ctx* c, const KA<T>& a) {
 template <typename T>
 bool eur_px_args(pfe_ctx* c, const KA<T>& a, const KA<T>& as, KA<T>& f) {
     const int K = c->g->ell_K;
-    if (!c->eur_px || c->prm.precond != PFE_JACOBI || c->prm.cold_start || !eu_px_ok(c) || !c->g->stencil ||
+    if (!c->eur_px || c->prm.cold_start || !eu_px_ok(c) || !c->g->stencil ||
         !(K == 4 || K == 8 || K == 24) || a.x != a.Y)
         return false;
     if (as.pxl) {
@@ -5272,6 +5275,8 @@ pfe_status inner_at(pfe_ctx* c, int l, bool next = false, bool r0_ready = false,
     if (next && fused && eur_px_args(c, a, as, f)) {
         f.b_zero = b.b_zero;
         f.bpar = b.bpar;
+        // the factor path's Jacobi fallback forms r0 again from the stored rhs
+        f.store_rhs = c->prm.precond != PFE_JACOBI;
         *fused = true;
         return launch_eur_px(c, f);
     }

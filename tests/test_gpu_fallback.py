@@ -76,6 +76,28 @@ def test_failed_factor_solve_is_redone_with_jacobi(case):
         assert np.array_equal(a, b), (which, rel(a, b))
 
 
+def test_factor_solve_after_fused_residual_is_redone_with_jacobi():
+    """An SOC iteration in one call, so that the second solve starts from the
+    residual the first edge update formed (which then also stores the
+    right-hand side): with a factor whose PCG breaks down, both solves are redone
+    with Jacobi (the second from the stored right-hand side), and the state
+    follows the Jacobi context's (FP32; that context's second solve starts from
+    the fused kernel's residual, which rounds differently)."""
+    banner("Jacobi fallback after a fused edge update and residual")
+    wl = synth.grid_workload("t", 40, 48, 6, 0.05, 3, stencil=8, d=4)
+    _, S_l = make(wl, 100, zero_factor_params())
+    _, S_j = make(wl, 100, None)
+    info_l = S_l.solve(1, info=True)
+    info_j = S_j.solve(1, info=True)
+    print(f"fallbacks {info_l['fallbacks']}, status {info_l['status']}, flags {info_l['flags']} / {info_j['flags']}")
+    assert info_l["flags"] & 8 and info_j["flags"] & 8
+    assert info_l["fallbacks"] == 2 and info_l["status"] == 0 and info_j["fallbacks"] == 0
+    for which in ("Y", "P"):
+        a = S_l.get(which).cpu().numpy()
+        b = S_j.get(which).cpu().numpy()
+        assert rel(a, b) <= 1e-5, (which, rel(a, b))
+
+
 def test_pcg_entry_point_falls_back_and_reports_jacobi_counts():
     banner("Jacobi fallback: pfe_pcg")
     wl = synth.grid_workload("t", 40, 48, 6, 0.05, 3, stencil=8, d=4)

@@ -95,10 +95,11 @@ def test_pixel_launch_outer_step_matches_oracle(monkeypatch):
     assert e <= 1e-8
 
 
+@pytest.mark.parametrize("precond", ["jacobi", "fsai"])
 @pytest.mark.parametrize("pixel", [1, 0])
 @pytest.mark.parametrize("fp64", [True, False])
 @pytest.mark.parametrize("name", ["voronoi48x40_r2", "voronoi96x80_8nbr", "voronoi64_4nbr", "ragged37x41_8"])
-def test_fused_edge_update_residual_matches_separate_kernels(name, fp64, pixel, monkeypatch):
+def test_fused_edge_update_residual_matches_separate_kernels(name, fp64, pixel, precond, monkeypatch):
     """An SOC iteration run in one call (each edge update but the last also
     forms the next solve's residual r0 = rhs - A Y, u0 = r0 / diag(A) and the
     CG start: k_eur_px) against the same iteration one inner step per call (edge
@@ -108,10 +109,11 @@ def test_fused_edge_update_residual_matches_separate_kernels(name, fp64, pixel, 
     slots in the residual kernel's order; strips in FP64 within 1e-12 (the
     residual norms are summed over other workgroups) and CG iterations within
     1; in FP32 (slots visited in pairs) Y, P within 1e-5 (B relative to P) and
-    CG iterations within 2."""
+    CG iterations within 2.  Jacobi PCG, and the FSAI factor (whose fused edge
+    updates also store the right-hand side for the Jacobi fallback)."""
     from paper_1612_06496_amd import Solver
     wl = case_workload(next(c for c in CASES if c[0] == name))
-    banner(f"fused edge update + residual vs separate kernels: {name} fp64={fp64} pixel={pixel}")
+    banner(f"fused edge update + residual vs separate kernels: {name} fp64={fp64} pixel={pixel} {precond}")
     monkeypatch.setenv("PFE_PIXEL", str(pixel))
     monkeypatch.setenv("PFE_STRIPS", "1")
     G = gpu_graph(wl)
@@ -119,6 +121,8 @@ def test_fused_edge_update_residual_matches_separate_kernels(name, fp64, pixel, 
     for fused in (True, False):
         S = Solver(G, wl.y0, lam=30.0, r=3.0, n_inner=4, tol=1e-10 if fp64 else 1e-6, maxit=3000, fp64=fp64,
                    persistent=False)
+        if precond == "fsai":
+            S.set_fsai()
         S.solve(1)                     # a first SOC iteration, so that P, B and b are not trivial
         if fused:
             info = S.solve(1, info=True)
