@@ -2958,6 +2958,72 @@ __device__ __forceinline__ void eu_stencil_slots(const KA<T>& a, int i, int c0, 
     }
 }
 
+// The slots of row i of the edge update on general layouts (ELL or CSR rows):
+// b and d per slot, updated in place, Eqs. 9-10 per slot, acc += w (d - b) in
+// slot order.  With AX the same loop also sums w^2 y_j in slot order (the
+// residual kernel's order) for A y.
+template <typename T, int V, bool AX>
+__device__ __forceinline__ void eu_row_slots(const KA<T>& a, int i, int c0, const T* bread, T* bwrite,
+                                             const Lanes<T, V>& yi, Lanes<T, V>& acc, Lanes<T, V>& accA) {
+    using VT = Lanes<T, V>;
+    const int d = a.d;
+    int s0, cnt, st;
+    row_slots<0>(a, i, s0, cnt, st);
+    auto slot = [&](int sl, T w, const VT& yj, const VT& bo) {
+        VT bn, dn;
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            const T tv = fma_t(w, yi.v[u] - yj.v[u], bo.v[u]);
+            const T dv = shrink(tv, a.gamma);
+            const T b1 = tv - dv;
+            bn.v[u] = b1;
+            dn.v[u] = dv;
+            acc.v[u] = fma_t(w, dv - b1, acc.v[u]);
+        }
+        st_lanes<T, V>(bwrite + (size_t)sl * d + c0, bn);
+        if (a.keep_split) st_lanes<T, V>(a.ds + (size_t)sl * d + c0, dn);
+        if constexpr (AX) {
+            const T w2 = mul_t(w, w);
+#pragma unroll
+            for (int u = 0; u < V; ++u) accA.v[u] = fma_t(w2, yj.v[u], accA.v[u]);
+        }
+    };
+    // full groups of kRowGroup slots, then the rest one by one (slot order kept;
+    // predicated last groups were slower)
+    int k = 0;
+    for (; k + kRowGroup <= cnt; k += kRowGroup) {
+        T ww[kRowGroup];
+        VT yj[kRowGroup], bo[kRowGroup];
+#pragma unroll
+        for (int g = 0; g < kRowGroup; ++g) {
+            {
+                const int sl = s0 + (k + g) * st;
+                ww[g] = a.sw[sl];
+                yj[g] = ld_lanes<T, V>(a.Y + (size_t)a.scol[sl] * d + c0);
+                if (a.b_zero) {
+#pragma unroll
+                    for (int u = 0; u < V; ++u) bo[g].v[u] = T(0);
+                } else {
+                    bo[g] = ld_lanes<T, V>(bread + (size_t)sl * d + c0);
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < kRowGroup; ++g) slot(s0 + (k + g) * st, ww[g], yj[g], bo[g]);
+    }
+    for (; k < cnt; ++k) {
+        const int sl = s0 + k * st;
+        VT b1;
+        if (a.b_zero) {
+#pragma unroll
+            for (int u = 0; u < V; ++u) b1.v[u] = T(0);
+        } else {
+            b1 = ld_lanes<T, V>(bread + (size_t)sl * d + c0);
+        }
+        slot(sl, a.sw[sl], ld_lanes<T, V>(a.Y + (size_t)a.scol[sl] * d + c0), b1);
+    }
+}
+
 // Edge update, one thread per row (the
 // PH_EU arithmetic without r0, element by element and in the same slot order):
 // one thread per pixel and V consecutive columns, no LDS, one workgroup per
@@ -2986,64 +3052,16 @@ __global__ void __launch_bounds__(kBlock) k_eu_px(KA<T> a, int W, int H) {
     for (int u = 0; u < V; ++u) acc.v[u] = T(0);
     if constexpr (KC == 0) {
         // general layouts: the row's slots (ELL or CSR), b and d per slot, updated in place
-        int s0, cnt, st;
-        row_slots<0>(a, i, s0, cnt, st);
-        auto slot = [&](int sl, T w, const VT& yj, const VT& bo) {
-            VT bn, dn;
-#pragma unroll
-            for (int u = 0; u < V; ++u) {
-                const T tv = fma_t(w, yi.v[u] - yj.v[u], bo.v[u]);
-                const T dv = shrink(tv, a.gamma);
-                const T b1 = tv - dv;
-                bn.v[u] = b1;
-                dn.v[u] = dv;
-                acc.v[u] = fma_t(w, dv - b1, acc.v[u]);
-            }
-            st_lanes<T, V>(bwrite + (size_t)sl * d + c0, bn);
-            if (a.keep_split) st_lanes<T, V>(a.ds + (size_t)sl * d + c0, dn);
-        };
-        // full groups of kRowGroup slots, then the rest one by one (slot order kept;
-        // predicated last groups were slower)
-        int k = 0;
-        for (; k + kRowGroup <= cnt; k += kRowGroup) {
-            T ww[kRowGroup];
-            VT yj[kRowGroup], bo[kRowGroup];
-#pragma unroll
-            for (int g = 0; g < kRowGroup; ++g) {
-                {
-                    const int sl = s0 + (k + g) * st;
-                    ww[g] = a.sw[sl];
-                    yj[g] = ld_lanes<T, V>(a.Y + (size_t)a.scol[sl] * d + c0);
-                    if (a.b_zero) {
-#pragma unroll
-                        for (int u = 0; u < V; ++u) bo[g].v[u] = T(0);
-                    } else {
-                        bo[g] = ld_lanes<T, V>(bread + (size_t)sl * d + c0);
-                    }
-                }
-            }
-#pragma unroll
-            for (int g = 0; g < kRowGroup; ++g) slot(s0 + (k + g) * st, ww[g], yj[g], bo[g]);
-        }
-        for (; k < cnt; ++k) {
-            const int sl = s0 + k * st;
-            VT b1;
-            if (a.b_zero) {
-#pragma unroll
-                for (int u = 0; u < V; ++u) b1.v[u] = T(0);
-            } else {
-                b1 = ld_lanes<T, V>(bread + (size_t)sl * d + c0);
-            }
-            slot(sl, a.sw[sl], ld_lanes<T, V>(a.Y + (size_t)a.scol[sl] * d + c0), b1);
-        }
+        VT no_ax;
+        eu_row_slots<T, V, false>(a, i, c0, bread, bwrite, yi, acc, no_ax);
     } else {
         int py = 0, px = 0;
         if constexpr (GEO) {
             py = i / W;
             px = i - py * W;
         }
-        VT unused;
-        eu_stencil_slots<T, KC, V, GEO, false>(a, i, c0, py, px, W, H, bread, bwrite, yi, acc, unused);
+        VT no_ax;
+        eu_stencil_slots<T, KC, V, GEO, false>(a, i, c0, py, px, W, H, bread, bwrite, yi, acc, no_ax);
     }
     const T sq = a.sqrtD[i];
     VT pv = ld_lanes<T, V>(a.P + e);
@@ -3234,11 +3252,13 @@ __global__ void __launch_bounds__(kBlock) k_px_res(KA<T> a, int mode) {
 }
 
 // The edge update of inner step l fused with the residual of solve l + 1 on
-// pixel-stencil images (per-row partition): Eqs. 9-10 per slot and the next
+// pixel-stencil images or general layouts (KC = 0; per-row partition): Eqs.
+// 9-10 per slot and the next
 // right-hand side as in k_eu_px, then r0 = rhs - A x for the iterate that solve
 // starts from, x = Y, out of the Y values the edge update has gathered (the sum
-// of w^2 y_j in the slots' visiting order: the slot order in FP64, pairs of
-// slots in FP32, as is then the sum forming the right-hand side), and
+// of w^2 y_j in the slots' visiting order: the slot order in FP64 and on
+// general layouts, pairs of slots in FP32 on stencils, as is then the sum
+// forming the right-hand side), and
 // u0 = r0 / diag(A); partials of rhs.rhs and r0.r0 and the
 // finaliser as in k_px_res.  The right-hand side is stored only with
 // store_rhs (factor-preconditioned solves, whose Jacobi fallback forms r0 from
@@ -3250,16 +3270,25 @@ __global__ void __launch_bounds__(kBlock) k_eur_px(KA<T> a) {
     const int lb = logical_block(a.nblk);
     const T* bread = a.bsb[a.bpar & 1];
     T* bwrite = a.bsb[(a.bpar & 1) ^ 1];
-    const int* gg = a.geo + 8 * lb;   // the workgroup's image: first row, width, height
-    const int row0 = gg[0], W = gg[1], H = gg[2];
+    int row0 = 0, W = 0, H = 0;
+    if constexpr (KC > 0) {
+        const int* gg = a.geo + 8 * lb;   // the workgroup's image: first row, width, height
+        row0 = gg[0];
+        W = gg[1];
+        H = gg[2];
+    }
     double acc2[2][V] = {};
     px_walk<V>(a, lb, [&](int i, size_t e, int c0) {
-        const int il = i - row0, py = il / W, px = il - py * W;
         const VT yi = ld_lanes<T, V>(a.Y + e);
         VT acc, accA;
 #pragma unroll
         for (int u = 0; u < V; ++u) acc.v[u] = accA.v[u] = T(0);
-        eu_stencil_slots<T, KC, V, true, true>(a, i, c0, py, px, W, H, bread, bwrite, yi, acc, accA);
+        if constexpr (KC > 0) {
+            const int il = i - row0, py = il / W, px = il - py * W;
+            eu_stencil_slots<T, KC, V, true, true>(a, i, c0, py, px, W, H, bread, bwrite, yi, acc, accA);
+        } else {
+            eu_row_slots<T, V, true>(a, i, c0, bread, bwrite, yi, acc, accA);
+        }
         const T sq = a.sqrtD[i], dA = a.diagA[i], inv = a.invdiag[i];
         const VT pv = ld_lanes<T, V>(a.P + e);
         const VT bv = ld_lanes<T, V>(a.B + e);
@@ -5203,20 +5232,20 @@ pfe_status launch_eu_px(pfe_ctx* c, const KA<T>& a) {
 }
 
 // the edge update fused with the next solve's residual (k_eur_px): PCG by
-// per-row launches or on strips of pixel-stencil images, warm starts (the
-// iterate is Y).  f: the kernel's arguments on a per-row partition (the
+// per-row launches (pixel stencils or general layouts) or on strips of
+// pixel-stencil images, warm starts (the iterate is Y).  f: the kernel's arguments on a per-row partition (the
 // solve's own with per-row launches; with strips, whose w0 kernel reads r0
 // alone, the partition of two workgroups per CU).  False when the shape does
 // not allow it.
 template <typename T>
 bool eur_px_args(pfe_ctx* c, const KA<T>& a, const KA<T>& as, KA<T>& f) {
     const int K = c->g->ell_K;
-    if (!c->eur_px || c->prm.cold_start || !eu_px_ok(c) || !c->g->stencil ||
-        !(K == 4 || K == 8 || K == 24) || a.x != a.Y)
+    const bool sten = c->g->stencil;
+    if (!c->eur_px || c->prm.cold_start || !eu_px_ok(c) || (sten && !(K == 4 || K == 8 || K == 24)) || a.x != a.Y)
         return false;
     if (as.pxl) {
         f = as;
-    } else if (use_strips(c) && as.geo != nullptr && c->px[0].nblk > 0) {
+    } else if (sten && use_strips(c) && as.geo != nullptr && c->px[0].nblk > 0) {
         // two workgroups per CU where built (64-image batch, d = 10: 58.1 ms per
         // SOC iteration against 60.2 with one, and 60.2 unfused)
         f = make_args<T>(c, c->px[c->px[1].nblk > 0 ? 1 : 0]);
@@ -5226,17 +5255,18 @@ bool eur_px_args(pfe_ctx* c, const KA<T>& a, const KA<T>& as, KA<T>& f) {
     } else {
         return false;
     }
-    return f.geo != nullptr;
+    return !sten || f.geo != nullptr;   // stencils take the workgroups' image geometry
 }
 
 template <typename T, int V>
 pfe_status launch_eur_px_v(pfe_ctx* c, const KA<T>& f) {
     const dim3 grid(f.nblk);
-    switch (c->g->ell_K) {
+    switch (c->g->stencil ? c->g->ell_K : 0) {
+        case 0: hipLaunchKernelGGL((k_eur_px<T, 0, V>), grid, dim3(kBlock), 0, c->stream, f); break;
         case 4: hipLaunchKernelGGL((k_eur_px<T, 4, V>), grid, dim3(kBlock), 0, c->stream, f); break;
         case 8: hipLaunchKernelGGL((k_eur_px<T, 8, V>), grid, dim3(kBlock), 0, c->stream, f); break;
         case 24: hipLaunchKernelGGL((k_eur_px<T, 24, V>), grid, dim3(kBlock), 0, c->stream, f); break;
-        default: set_error("the fused edge update needs a stencil of 4, 8 or 24 slots"); return PFE_E_STATE;
+        default: set_error("the fused edge update needs a stencil of 4, 8 or 24 slots or a general layout"); return PFE_E_STATE;
     }
     PFE_CHECK_HIP(hipGetLastError());
     c->fused_eur = 1;

@@ -157,6 +157,39 @@ def test_fused_edge_update_residual_matches_separate_kernels(name, fp64, pixel, 
         assert np.linalg.norm(o1["B"] - o2["B"]) / np.linalg.norm(o2["P"]) <= 1e-5
 
 
+@pytest.mark.parametrize("fp64", [True, False])
+@pytest.mark.parametrize("d,n", [(4, 5000), (5, 5000), (4, 900)])
+def test_fused_edge_update_residual_general_graph_bitwise(d, n, fp64, monkeypatch):
+    """Per-row launches on an edge-list graph (general slot layout, b per slot):
+    an SOC iteration in one call (each edge update but the last also forms the
+    next residual, summing w^2 y_j in the residual kernel's slot order) equals,
+    bitwise in FP32 and FP64, the same iteration one inner step per call."""
+    from paper_1612_06496_amd import Solver
+    wl = edge_workload(d, n)
+    banner(f"fused edge update + residual, edge-list graph d={d} n={n} fp64={fp64}")
+    monkeypatch.setenv("PFE_PIXEL", "1")
+    G = gpu_graph(wl)
+    res = []
+    for fused in (True, False):
+        S = Solver(G, wl.y0, lam=30.0, r=3.0, n_inner=3, tol=1e-10 if fp64 else 1e-6, maxit=3000, fp64=fp64,
+                   persistent=False)
+        S.solve(1)
+        if fused:
+            info = S.solve(1, info=True)
+        else:
+            iters = sum(S.step("inner", info=True)["cg_iters_total"] for _ in range(3))
+            info = S.step("outer", info=True)
+            info["cg_iters_total"] += iters
+        res.append((info, {k: to_np(S.get(k)) for k in ("Y", "P", "B")}))
+        S.close()
+    G.close()
+    (i1, o1), (i2, o2) = res
+    assert i1["flags"] & 4 and i1["flags"] & 8 and not i2["flags"] & 8
+    assert i1["cg_iters_total"] == i2["cg_iters_total"]
+    for k in o1:
+        assert np.array_equal(o1[k], o2[k]), k
+
+
 def test_pixel_launch_graph_replay_bitwise_and_deterministic(monkeypatch):
     """CG iterations replayed from HIP graphs (two nodes per iteration) give
     bitwise the host-launched ones, and a rerun gives bitwise the same state."""
