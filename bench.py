@@ -68,10 +68,11 @@ def algorithmic_bytes(n, E, d, esz, cg_iters, solves, n_inner, n_outer, pupdate=
 
 
 # committed rocprofv3 FETCH_SIZE / WRITE_SIZE records: (workload, launch) ->
-# file; persistent records count one k_soc launch, per-row records one SOC
-# iteration of the one-launch-per-phase path (all its kernels)
+# file; persistent records count one k_soc launch, per-row and strip records one
+# SOC iteration of the one-launch-per-phase path (all its kernels)
 TRAFFIC_FILES = {("voronoi481x321_8nbr", "persistent"): "k_soc_voronoi481x321_traffic.json",
-                 ("voronoi1024_r2", "per-row"): "per_row_voronoi1024_r2_traffic.json"}
+                 ("voronoi1024_r2", "per-row"): "per_row_voronoi1024_r2_traffic.json",
+                 ("voronoi_batch64_8nbr", "strips"): "strips_voronoi_batch64_traffic.json"}
 
 
 def measured_traffic(workload, launch):
