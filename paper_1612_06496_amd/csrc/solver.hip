@@ -3251,18 +3251,17 @@ __global__ void __launch_bounds__(kBlock) k_px_res(KA<T> a, int mode) {
     if (last_of_launch(a, 2, sh)) fin_res(a, sh, grouped_fin(a));
 }
 
-// The edge update of inner step l fused with the residual of solve l + 1 on
-// pixel-stencil images or general layouts (KC = 0; per-row partition): Eqs.
-// 9-10 per slot and the next
-// right-hand side as in k_eu_px, then r0 = rhs - A x for the iterate that solve
-// starts from, x = Y, out of the Y values the edge update has gathered (the sum
-// of w^2 y_j in the slots' visiting order: the slot order in FP64 and on
-// general layouts, pairs of slots in FP32 on stencils, as is then the sum
-// forming the right-hand side), and
-// u0 = r0 / diag(A); partials of rhs.rhs and r0.r0 and the
-// finaliser as in k_px_res.  The right-hand side is stored only with
-// store_rhs (factor-preconditioned solves, whose Jacobi fallback forms r0 from
-// it again); a Jacobi solve reads only r0.
+// The edge update of inner step l fused with the residual of solve l + 1, on
+// pixel-stencil images or general layouts (KC = 0), per-row partition: Eqs.
+// 9-10 per slot and the next right-hand side as in k_eu_px; then r0 = rhs - A x
+// for the iterate that solve starts from (x = Y), out of the Y values the edge
+// update has gathered, and u0 = r0 / diag(A); partials of rhs.rhs and r0.r0 and
+// the finaliser as in k_px_res.  A x sums w^2 y_j in the slots' visiting order:
+// the slot order in FP64 and on general layouts (r0 then equals k_px_res's
+// bitwise), pairs of slots in FP32 on stencils (as does the right-hand side's
+// sum here).  The right-hand side is stored only with store_rhs
+// (factor-preconditioned solves, whose Jacobi fallback forms r0 from it
+// again); a Jacobi solve reads only r0.
 template <typename T, int KC, int V>
 __global__ void __launch_bounds__(kBlock) k_eur_px(KA<T> a) {
     using VT = Lanes<T, V>;
