@@ -88,20 +88,26 @@ __global__ void k_prep(View v, float* __restrict__ at, float* __restrict__ x) {
     x[i * 4 + 3] = (float)deg / (float)max(1, v.deg_max);
 }
 
-// out_i = sum_s (-At_s) in_j  (F features per vertex)
+// out_i = sum_s (-At_s) in_j  (F features per vertex): F / 4 threads per
+// vertex, each summing four consecutive features (one slot load and one
+// 16-byte gather per slot), every feature in slot order
 template <int F>
 __global__ void k_agg(View v, const float* __restrict__ at, const float* __restrict__ in, float* __restrict__ out) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= v.n * F) return;
-    int i = e / F, f = e - i * F;
+    static_assert(F % 4 == 0, "four features per thread");
+    constexpr int L = F / 4;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= v.n * L) return;
+    const int i = e / L, f0 = (e - i * L) * 4;
     int s0, cnt, st;
     slots(v, i, s0, cnt, st);
-    float acc = 0.f;
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int k = 0; k < cnt; ++k) {
-        int s = s0 + k * st;
-        acc = fmaf(-at[s], in[v.scol[s] * F + f], acc);
+        const int s = s0 + k * st;
+        const float w = -at[s];
+        const f4 x = *reinterpret_cast<const f4*>(in + (size_t)v.scol[s] * F + f0);
+        for (int t = 0; t < 4; ++t) acc[t] = fmaf(w, x[t], acc[t]);
     }
-    out[e] = acc;
+    *reinterpret_cast<f4*>(out + (size_t)i * F + f0) = acc;
 }
 
 // MFMA tile: D[m][o] += sum_k A[m][k] B[k][o] for a 16x16x16 bf16 block.  Lane l
@@ -537,10 +543,10 @@ View make_view(const NetGraph& g) {
 pfe_status forward(pfe_mpnn* w, const View& v, int64_t ns, hipStream_t st) {
     const int n = v.n;
     hipLaunchKernelGGL(k_prep, dim3(nblk(n)), dim3(kTB), 0, st, v, w->at, w->x);
-    hipLaunchKernelGGL(k_agg<4>, dim3(nblk((int64_t)n * 4)), dim3(kTB), 0, st, v, w->at, w->x, w->agg1);
+    hipLaunchKernelGGL(k_agg<4>, dim3(nblk((int64_t)n)), dim3(kTB), 0, st, v, w->at, w->x, w->agg1);
     const unsigned gd = (unsigned)(((n + 15) / 16 + 3) / 4);
     hipLaunchKernelGGL(k_dense<1>, dim3(gd), dim3(kTB), 0, st, n, w->theta, w->x, w->agg1, w->pre1, w->h1);
-    hipLaunchKernelGGL(k_agg<kH>, dim3(nblk((int64_t)n * kH)), dim3(kTB), 0, st, v, w->at, w->h1, w->agg2);
+    hipLaunchKernelGGL(k_agg<kH>, dim3(nblk((int64_t)n * (kH / 4))), dim3(kTB), 0, st, v, w->at, w->h1, w->agg2);
     hipLaunchKernelGGL(k_dense<2>, dim3(gd), dim3(kTB), 0, st, n, w->theta, w->h1, w->agg2, w->pre2, w->h2);
     hipLaunchKernelGGL(k_dense<3>, dim3(gd), dim3(kTB), 0, st, n, w->theta, w->h2, (const float*)nullptr, w->uvz,
                        (float*)nullptr);
@@ -602,7 +608,7 @@ pfe_status mpnn_train_step(pfe_mpnn* w, const NetGraph& g, const void* samples, 
     hipLaunchKernelGGL(k_out_bwd, dim3(nblk(n)), dim3(kTB), 0, st, v, w->theta, w->at, w->dgval, w->dgdiag, w->uvz,
                        w->pre2, w->duvz, w->dpre2);
     hipLaunchKernelGGL(k_l2_bwd, dim3(nblk((int64_t)n * kH)), dim3(kTB), 0, st, n, w->theta, w->dpre2, w->dh1, w->dagg2);
-    hipLaunchKernelGGL(k_agg<kH>, dim3(nblk((int64_t)n * kH)), dim3(kTB), 0, st, v, w->at, w->dagg2, w->tbuf);
+    hipLaunchKernelGGL(k_agg<kH>, dim3(nblk((int64_t)n * (kH / 4))), dim3(kTB), 0, st, v, w->at, w->dagg2, w->tbuf);
     hipLaunchKernelGGL(k_l1_mask, dim3(nblk((int64_t)n * kH)), dim3(kTB), 0, st, n, w->dh1, w->tbuf, w->pre1, w->dpre1);
     WG wg{n, w->x, w->agg1, w->h1, w->agg2, w->h2, w->dpre1, w->dpre2, w->duvz};
     hipLaunchKernelGGL(k_wgrad, dim3(kRedBlocks), dim3(kTB), 0, st, wg, w->part);
