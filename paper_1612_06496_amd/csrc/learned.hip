@@ -90,18 +90,33 @@ __global__ void k_prep(View v, float* __restrict__ at, float* __restrict__ x) {
 
 // out_i = sum_s (-At_s) in_j  (F features per vertex): F / 4 threads per
 // vertex, each summing four consecutive features (one slot load and one
-// 16-byte gather per slot), every feature in slot order
+// 16-byte gather per slot, issued for eight slots at a time), every feature in
+// slot order
 template <int F>
 __global__ void k_agg(View v, const float* __restrict__ at, const float* __restrict__ in, float* __restrict__ out) {
     static_assert(F % 4 == 0, "four features per thread");
-    constexpr int L = F / 4;
+    constexpr int L = F / 4, G = 8;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= v.n * L) return;
     const int i = e / L, f0 = (e - i * L) * 4;
     int s0, cnt, st;
     slots(v, i, s0, cnt, st);
     f4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < cnt; ++k) {
+    int k = 0;
+    for (; k + G <= cnt; k += G) {
+        float w[G];
+        f4 x[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int s = s0 + (k + g) * st;
+            w[g] = -at[s];
+            x[g] = *reinterpret_cast<const f4*>(in + (size_t)v.scol[s] * F + f0);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            for (int t = 0; t < 4; ++t) acc[t] = fmaf(w[g], x[g][t], acc[t]);
+    }
+    for (; k < cnt; ++k) {
         const int s = s0 + k * st;
         const float w = -at[s];
         const f4 x = *reinterpret_cast<const f4*>(in + (size_t)v.scol[s] * F + f0);
@@ -307,21 +322,33 @@ __global__ void k_dfactor(View v, int kc, const float* __restrict__ rho, const f
                           float* __restrict__ dgval, float* __restrict__ dgdiag) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= v.n) return;
+    // sum over the kc sample columns (in column order) of dy1_lo rho_hi + y1_lo dy2_hi,
+    // four columns per 16-byte load when kc allows
+    auto pair = [&](int lo, int hi) {
+        const float* a = dy1 + (size_t)lo * kc;
+        const float* b = rho + (size_t)hi * kc;
+        const float* c = y1 + (size_t)lo * kc;
+        const float* d = dy2 + (size_t)hi * kc;
+        float acc = 0.f;
+        if ((kc & 3) == 0) {
+            for (int q = 0; q < kc; q += 4) {
+                const f4 av = *reinterpret_cast<const f4*>(a + q), bv = *reinterpret_cast<const f4*>(b + q);
+                const f4 cv = *reinterpret_cast<const f4*>(c + q), dv = *reinterpret_cast<const f4*>(d + q);
+                for (int t = 0; t < 4; ++t) acc += av[t] * bv[t] + cv[t] * dv[t];
+            }
+        } else {
+            for (int q = 0; q < kc; ++q) acc += a[q] * b[q] + c[q] * d[q];
+        }
+        return acc;
+    };
     int s0, cnt, st;
     slots(v, i, s0, cnt, st);
     for (int k = 0; k < cnt; ++k) {
         int s = s0 + k * st;
         int j = v.scol[s];
-        int lo = max(i, j), hi = min(i, j);
-        float acc = 0.f;
-        if (j != i)
-            for (int c = 0; c < kc; ++c)
-                acc += dy1[lo * kc + c] * rho[hi * kc + c] + y1[lo * kc + c] * dy2[hi * kc + c];
-        dgval[s] = acc;
+        dgval[s] = (j != i) ? pair(max(i, j), min(i, j)) : 0.f;
     }
-    float acc = 0.f;
-    for (int c = 0; c < kc; ++c) acc += dy1[i * kc + c] * rho[i * kc + c] + y1[i * kc + c] * dy2[i * kc + c];
-    dgdiag[i] = acc;
+    dgdiag[i] = pair(i, i);
 }
 
 // output layer backward: dU, dV, dZ per vertex and dpre2

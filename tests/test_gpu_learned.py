@@ -92,13 +92,17 @@ def test_learned_pcg_matches_oracle():
     assert np.all(np.abs(it - it_o) <= 2)
 
 
-def test_gradient_matches_oracle_autograd():
+@pytest.mark.parametrize("cols", [6, 8])
+def test_gradient_matches_oracle_autograd(cols):
+    """The training gradient against the oracle's autograd, with a sample
+    count that takes the factor gradient's scalar path (6) and its 16-byte path
+    (8)."""
     from paper_1612_06496_amd import Mpnn
-    banner("learned gradient vs oracle")
+    banner(f"learned gradient vs oracle, {cols} sample columns")
     wl, g, G, S, SS = setup(H=24, W=28)
     th = random_params(6, scale=0.2)
     net = Mpnn(th)
-    R = np.random.default_rng(7).normal(size=(g.n, 6))
+    R = np.random.default_rng(7).normal(size=(g.n, cols))
     loss_gpu = net.train_step(S, R, lr=0.0)
     grad_gpu = net.grad.astype(np.float64)
     rho = R / np.sqrt(SS.dA)[:, None]
